@@ -1,0 +1,188 @@
+/*
+ * fockjk -- Coulomb (J) and exchange (K) matrices of direct Hartree-Fock on
+ * one AMD Instinct MI355X (gfx950).
+ *
+ * The library evaluates J_uv = sum_ls (uv|ls) D_ls and K_uv = sum_ls (ul|vs) D_ls
+ * (paper, "Hartree-Fock Energy Formulation", eqs. for J and K) from the
+ * electron repulsion integrals of contracted Cartesian Gaussian shells
+ * (paper, "Notation", eqs. cgf and prim) up to f, screened by the Cauchy-
+ * Schwarz bounds G_ab G_cd (eq. cauchy-schwarz) and by the density block
+ * maximum D_max of the six density blocks of each quartet (paper, section
+ * "Optimised GPU Implementation" of the Brc21 scheme), and exploiting the
+ * 8-fold permutational symmetry of the integrals (paper, "Algorithmic
+ * Challenges").  Integrals are evaluated by Rys quadrature.
+ *
+ * Conventions
+ *   - Units: bohr and hartree.  D includes the factor 2 (D = 2 C_occ C_occ^T).
+ *   - Matrices are nbf x nbf, row-major, full (both triangles), FP64.
+ *   - Basis functions follow the shell order given to fk_set_basis; inside a
+ *     shell the Cartesian components are ordered x^l, x^(l-1)y, x^(l-1)z,
+ *     x^(l-2)y^2, ... z^l (descending x power, then descending y power).
+ *     Every component is normalised to unit self-overlap.
+ *   - Contraction coefficients multiply primitives normalised as the
+ *     axis-aligned component: N(a,l) = (2a/pi)^(3/4) (4a)^(l/2) / sqrt((2l-1)!!).
+ *
+ * Ownership and threading
+ *   - The caller owns every array it passes.  Host inputs are copied during
+ *     the call.  Device pointers are borrowed for the duration of the call and
+ *     used on the HIP stream passed in (NULL = the null stream); the call
+ *     returns after enqueueing unless stated otherwise.
+ *   - The library owns its device buffers (allocated with hipMalloc on the
+ *     context's device when the basis or screening changes).
+ *   - A context is used from one host thread at a time; separate contexts are
+ *     independent.
+ *
+ * Errors
+ *   Every function returns an fk_status (0 = success).  Arguments are fully
+ *   validated on the host before any device work; nothing throws across the
+ *   ABI.  fk_last_error returns a message describing the last failure of the
+ *   context (valid until the next call on it).
+ */
+#ifndef FOCKJK_H
+#define FOCKJK_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct fk_ctx fk_ctx;
+
+typedef enum {
+    FK_OK = 0,
+    FK_ERR_ARG = -1,          /* invalid argument (checked on the host) */
+    FK_ERR_UNSUPPORTED = -2,  /* l > FK_MAX_L, contraction depth > FK_MAX_K, ... */
+    FK_ERR_HIP = -3,          /* a HIP runtime call failed */
+    FK_ERR_OOM = -4,          /* device allocation failed */
+    FK_ERR_NOT_CONVERGED = -5,/* SCF reached max_iter */
+    FK_ERR_STATE = -6         /* call out of order (e.g. build_jk before build_quartets) */
+} fk_status;
+
+#define FK_MAX_L 3            /* s, p, d, f */
+#define FK_MAX_K 9            /* primitives per contracted shell */
+
+/* flags for fk_build_jk */
+#define FK_DEVICE_PTRS 1u     /* D, J, K are device pointers (else host pointers) */
+#define FK_SYNC 2u            /* synchronise the stream before returning */
+
+/* Screening options (paper: Cauchy-Schwarz screening, eq. cauchy-schwarz, and
+ * the density screen G_ab G_cd D_max < tau of the Brc21 scheme). */
+typedef struct {
+    double tau;        /* quartet threshold; 0 disables screening (every quartet) */
+    double tau_prim;   /* primitive-pair pruning: drop primitive pairs whose
+                          bound G_[ab] * max_all G_[cd] < tau_prim; 0 = keep all */
+    int    density_screen; /* 1: apply the per-quartet D_max screen in fk_build_jk */
+    int    reserved;
+} fk_screen_opts;
+
+typedef struct {
+    int    nbf, nshell, natom, nelec;
+    int    npair;            /* unique shell pairs (a >= b) */
+    int    npair_kept;       /* pairs with G_ab * G_max >= tau */
+    int    nclass_pair;      /* angular-momentum pair classes present */
+    int    nquartet_class;   /* quartet classes with work */
+    int64_t nprim_pair;      /* primitive pairs kept */
+    int64_t nquartet_schwarz;/* unique shell quartets surviving the Schwarz screen */
+    int64_t ntile;           /* work tiles (bra pair x up to 64 ket pairs) */
+    double  flops_schwarz;   /* algorithmic FP64 flops of one build if no quartet
+                                were removed by the density screen */
+} fk_info_t;
+
+/* Per-build statistics of the last fk_build_jk (filled by fk_stats). */
+#define FK_MAX_QCLASS 55
+typedef struct {
+    int     nclass;                       /* quartet classes launched */
+    int     la[FK_MAX_QCLASS], lb[FK_MAX_QCLASS], lc[FK_MAX_QCLASS], ld[FK_MAX_QCLASS];
+    int64_t quartets[FK_MAX_QCLASS];      /* contracted quartets computed */
+    int64_t prim_quartets[FK_MAX_QCLASS]; /* primitive quartets computed */
+    double  flops_per_prim[FK_MAX_QCLASS];/* algorithmic flops per primitive quartet */
+    double  flops_per_quartet[FK_MAX_QCLASS]; /* per contracted quartet (digestion) */
+    double  flops_total;                  /* algorithmic flops of the build */
+} fk_stats_t;
+
+/* ---- context ---------------------------------------------------------- */
+/* Create a context on HIP device `device`. */
+int fk_create(fk_ctx **out, int device);
+void fk_destroy(fk_ctx *ctx);
+const char *fk_last_error(const fk_ctx *ctx);
+
+/* ---- inputs (paper: "Notation") -------------------------------------- */
+/* natom atoms with nuclear charges Z[natom] at xyz[natom*3] (bohr); the
+ * molecule carries `charge` (electrons = sum Z - charge, must be even). */
+int fk_set_geometry(fk_ctx *ctx, int natom, const int *Z, const double *xyz, int charge);
+
+/* nshell contracted shells; shell s sits on atom shell_atom[s], has angular
+ * momentum shell_l[s] (0..FK_MAX_L) and shell_nprim[s] (1..FK_MAX_K)
+ * primitives whose exponents (> 0) and contraction coefficients are stored
+ * consecutively in exps[] and coefs[] (sum of shell_nprim entries).
+ * Requires fk_set_geometry first.  Invalidates quartet lists. */
+int fk_set_basis(fk_ctx *ctx, int nshell, const int *shell_atom, const int *shell_l,
+                 const int *shell_nprim, const double *exps, const double *coefs);
+
+/* ---- screening and work lists (paper: Cauchy-Schwarz bounds; shell-pair
+ * batching and upper-triangle class launches of the Brc21 scheme) -------- */
+/* Builds shell pairs and primitive pairs, the Schwarz factors
+ * G_ab = max sqrt((ab|ab)) (computed on the device), sorts pairs by class and
+ * bound, and builds the work tiles.  opts == NULL means tau = 1e-10,
+ * tau_prim = 0, density_screen = 1.  Synchronous. */
+int fk_build_quartets(fk_ctx *ctx, const fk_screen_opts *opts);
+int fk_info(const fk_ctx *ctx, fk_info_t *info);
+
+/* ---- the hot path (paper: eq. fock_build; J and K) --------------------- */
+/* J and K for the density D (all nbf x nbf, row-major, symmetric D).
+ * flags: FK_DEVICE_PTRS (D, J, K in device memory, used on `stream`);
+ * otherwise host arrays, copied in and out synchronously.  FK_SYNC waits for
+ * completion.  Asymmetric D gives J, K of its symmetric part only when
+ * density screening is off; callers pass symmetric D. */
+int fk_build_jk(fk_ctx *ctx, const double *D, double *J, double *K, unsigned flags, void *stream);
+
+/* Statistics of the last fk_build_jk (waits for it to finish). */
+int fk_stats(fk_ctx *ctx, fk_stats_t *stats);
+
+/* ---- one-electron part and SCF (paper: "Hartree-Fock Energy Formulation") */
+/* Overlap S, kinetic T and nuclear attraction V (host arrays nbf x nbf) and the
+ * nuclear repulsion energy.  Any output pointer may be NULL. */
+int fk_one_electron(fk_ctx *ctx, double *S, double *T, double *V, double *e_nuc);
+
+typedef struct {
+    int    max_iter;     /* default 100 */
+    double e_tol;        /* |dE| threshold, default 1e-10 */
+    double g_tol;        /* max |X^T (FDS - SDF) X| threshold, default 1e-8 */
+    int    diis_n;       /* DIIS subspace size, default 8 */
+    int    guess;        /* 0 = core Hamiltonian, 1 = density given in D_inout */
+    double lindep;       /* overlap eigenvalue cutoff, default 1e-8 */
+} fk_scf_opts;
+
+typedef struct {
+    double energy;       /* total energy (hartree) */
+    double e_nuc;
+    int    iterations;   /* Fock builds performed */
+    int    converged;
+    double jk_seconds;   /* wall time spent in fk_build_jk */
+    double total_seconds;
+} fk_scf_result;
+
+/* Restricted closed-shell SCF: F = h + J - K/2, FC = SC eps, Pulay DIIS.
+ * J/K run on the device; the small dense linear algebra runs on the host.
+ * D_inout (host, nbf x nbf) holds the guess when opts->guess == 1 and the
+ * converged density on return.  Returns FK_ERR_NOT_CONVERGED (with the
+ * result filled) if max_iter is reached. */
+int fk_run_scf(fk_ctx *ctx, const fk_scf_opts *opts, fk_scf_result *result, double *D_inout);
+
+/* ---- diagnostics -------------------------------------------------------- */
+/* Raw contracted integrals (ab|cd) for nq shell quartets (shell indices
+ * quartets[4q..4q+3], any order and any angular momenta), written
+ * consecutively as [na][nb][nc][nd] blocks into out (host array of
+ * sum na*nb*nc*nd doubles).  on_device = 1 evaluates on the GPU with the
+ * production per-quartet code, 0 evaluates the same code on the host. */
+int fk_debug_eri(fk_ctx *ctx, int nq, const int *quartets, double *out, int on_device);
+
+/* Rys roots u[n] and weights w[n] for argument T from the library's tables,
+ * evaluated on the host (n = 1..7). */
+int fk_rys_host(int n, double T, double *u, double *w);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

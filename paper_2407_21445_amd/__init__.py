@@ -1,0 +1,234 @@
+"""Python binding of libfockjk (see include/fockjk.h): argument marshalling only.
+
+Every step of the J/K build runs in the library's HIP kernels; this module
+only converts arrays, device pointers and streams.  Importing it loads
+``libfockjk.so`` from this directory and fails loudly when it is missing.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libfockjk.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"libfockjk.so not built at {LIB_PATH}; run __graft_entry__.build() "
+                      "(or python -m paper_2407_21445_amd.build)")
+
+_lib = ctypes.CDLL(LIB_PATH)
+
+FK_OK, FK_ERR_ARG, FK_ERR_UNSUPPORTED, FK_ERR_HIP, FK_ERR_OOM, FK_ERR_NOT_CONVERGED, FK_ERR_STATE = 0, -1, -2, -3, -4, -5, -6
+FK_DEVICE_PTRS, FK_SYNC = 1, 2
+FK_MAX_QCLASS = 55
+MAX_L, MAX_K = 3, 9
+
+
+class ScreenOpts(ctypes.Structure):
+    _fields_ = [("tau", ctypes.c_double), ("tau_prim", ctypes.c_double),
+                ("density_screen", ctypes.c_int), ("reserved", ctypes.c_int)]
+
+
+class Info(ctypes.Structure):
+    _fields_ = [("nbf", ctypes.c_int), ("nshell", ctypes.c_int), ("natom", ctypes.c_int), ("nelec", ctypes.c_int),
+                ("npair", ctypes.c_int), ("npair_kept", ctypes.c_int), ("nclass_pair", ctypes.c_int),
+                ("nquartet_class", ctypes.c_int), ("nprim_pair", ctypes.c_int64),
+                ("nquartet_schwarz", ctypes.c_int64), ("ntile", ctypes.c_int64), ("flops_schwarz", ctypes.c_double)]
+
+
+_Q = FK_MAX_QCLASS
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [("nclass", ctypes.c_int), ("la", ctypes.c_int * _Q), ("lb", ctypes.c_int * _Q),
+                ("lc", ctypes.c_int * _Q), ("ld", ctypes.c_int * _Q), ("quartets", ctypes.c_int64 * _Q),
+                ("prim_quartets", ctypes.c_int64 * _Q), ("flops_per_prim", ctypes.c_double * _Q),
+                ("flops_per_quartet", ctypes.c_double * _Q), ("flops_total", ctypes.c_double)]
+
+
+class ScfOpts(ctypes.Structure):
+    _fields_ = [("max_iter", ctypes.c_int), ("e_tol", ctypes.c_double), ("g_tol", ctypes.c_double),
+                ("diis_n", ctypes.c_int), ("guess", ctypes.c_int), ("lindep", ctypes.c_double)]
+
+
+class ScfResult(ctypes.Structure):
+    _fields_ = [("energy", ctypes.c_double), ("e_nuc", ctypes.c_double), ("iterations", ctypes.c_int),
+                ("converged", ctypes.c_int), ("jk_seconds", ctypes.c_double), ("total_seconds", ctypes.c_double)]
+
+
+_P, _I, _D, _U = ctypes.c_void_p, ctypes.c_int, ctypes.c_double, ctypes.c_uint
+_sig = {
+    "fk_create": ([ctypes.POINTER(_P), _I], _I),
+    "fk_destroy": ([_P], None),
+    "fk_last_error": ([_P], ctypes.c_char_p),
+    "fk_set_geometry": ([_P, _I, _P, _P, _I], _I),
+    "fk_set_basis": ([_P, _I, _P, _P, _P, _P, _P], _I),
+    "fk_build_quartets": ([_P, ctypes.POINTER(ScreenOpts)], _I),
+    "fk_info": ([_P, ctypes.POINTER(Info)], _I),
+    "fk_build_jk": ([_P, _P, _P, _P, _U, _P], _I),
+    "fk_stats": ([_P, ctypes.POINTER(Stats)], _I),
+    "fk_one_electron": ([_P, _P, _P, _P, _P], _I),
+    "fk_run_scf": ([_P, ctypes.POINTER(ScfOpts), ctypes.POINTER(ScfResult), _P], _I),
+    "fk_debug_eri": ([_P, _I, _P, _P, _I], _I),
+    "fk_rys_host": ([_I, _D, _P, _P], _I),
+}
+EXPORTS = tuple(_sig)
+for _name, (_args, _res) in _sig.items():
+    _f = getattr(_lib, _name)
+    _f.argtypes = _args
+    _f.restype = _res
+
+
+class FockJKError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"fockjk error {code}: {msg}")
+        self.code = code
+
+
+def _ptr(a):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _ncart(l):
+    return (l + 1) * (l + 2) // 2
+
+
+def rys_host(n, T):
+    """Rys roots and weights of the library's tables, evaluated on the host."""
+    u = np.zeros(n)
+    w = np.zeros(n)
+    rc = _lib.fk_rys_host(int(n), float(T), _ptr(u), _ptr(w))
+    if rc:
+        raise FockJKError(rc, "fk_rys_host: bad arguments")
+    return u, w
+
+
+class FockJK:
+    """One library context on one device (device=-1: host-only context, which
+    can build screening lists and evaluate integrals on the host for checks,
+    but cannot run fk_build_jk)."""
+
+    def __init__(self, device=0):
+        self._ctx = ctypes.c_void_p()
+        rc = _lib.fk_create(ctypes.byref(self._ctx), int(device))
+        if rc:
+            raise FockJKError(rc, f"fk_create(device={device}) failed")
+        self.device = device
+        self.nbf = 0
+        self._keep = []
+
+    def close(self):
+        if self._ctx:
+            _lib.fk_destroy(self._ctx)
+            self._ctx = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, rc):
+        if rc not in (FK_OK,):
+            raise FockJKError(rc, _lib.fk_last_error(self._ctx).decode())
+        return rc
+
+    # ---- inputs ----
+    def set_system(self, sys):
+        Z = np.ascontiguousarray(sys["Z"], dtype=np.int32)
+        xyz = np.ascontiguousarray(sys["xyz"], dtype=np.float64).reshape(-1)
+        self._check(_lib.fk_set_geometry(self._ctx, len(Z), _ptr(Z), _ptr(xyz), int(sys.get("charge", 0))))
+        sa = np.ascontiguousarray(sys["sh_atom"], dtype=np.int32)
+        sl = np.ascontiguousarray(sys["sh_l"], dtype=np.int32)
+        sn = np.ascontiguousarray(sys["sh_nprim"], dtype=np.int32)
+        ex = np.ascontiguousarray(sys["exps"], dtype=np.float64)
+        co = np.ascontiguousarray(sys["coefs"], dtype=np.float64)
+        self._check(_lib.fk_set_basis(self._ctx, len(sl), _ptr(sa), _ptr(sl), _ptr(sn), _ptr(ex), _ptr(co)))
+        self.sh_l = sl.copy()
+        self.nbf = int(sum(_ncart(int(l)) for l in sl))
+        return self
+
+    def build_quartets(self, tau=1e-10, tau_prim=0.0, density_screen=True):
+        o = ScreenOpts(float(tau), float(tau_prim), 1 if density_screen else 0, 0)
+        self._check(_lib.fk_build_quartets(self._ctx, ctypes.byref(o)))
+        return self
+
+    def info(self):
+        i = Info()
+        self._check(_lib.fk_info(self._ctx, ctypes.byref(i)))
+        return {k: getattr(i, k) for k, _ in Info._fields_}
+
+    # ---- hot path ----
+    def build_jk(self, D, J=None, K=None, stream=None, sync=False):
+        """J, K for density D.  torch CUDA tensors (float64, contiguous) stay on
+        the device and run on `stream` (default: torch's current stream);
+        numpy arrays go through host copies."""
+        if isinstance(D, np.ndarray):
+            Dh = np.ascontiguousarray(D, dtype=np.float64)
+            n = self.nbf
+            if Dh.shape != (n, n):
+                raise ValueError(f"D must be {n}x{n}")
+            Jh = np.zeros((n, n))
+            Kh = np.zeros((n, n))
+            self._check(_lib.fk_build_jk(self._ctx, _ptr(Dh), _ptr(Jh), _ptr(Kh), 0, None))
+            return Jh, Kh
+        import torch
+        n = self.nbf
+        if not (D.is_cuda and D.dtype == torch.float64 and D.is_contiguous() and tuple(D.shape) == (n, n)):
+            raise ValueError(f"D must be a contiguous float64 CUDA tensor of shape ({n},{n})")
+        if J is None:
+            J = torch.empty_like(D)
+        if K is None:
+            K = torch.empty_like(D)
+        st = stream if stream is not None else torch.cuda.current_stream(D.device)
+        flags = FK_DEVICE_PTRS | (FK_SYNC if sync else 0)
+        self._check(_lib.fk_build_jk(self._ctx, ctypes.c_void_p(D.data_ptr()), ctypes.c_void_p(J.data_ptr()),
+                                     ctypes.c_void_p(K.data_ptr()), flags, ctypes.c_void_p(st.cuda_stream)))
+        return J, K
+
+    def stats(self):
+        s = Stats()
+        self._check(_lib.fk_stats(self._ctx, ctypes.byref(s)))
+        out = []
+        for i in range(s.nclass):
+            out.append({"class": (s.la[i], s.lb[i], s.lc[i], s.ld[i]), "quartets": s.quartets[i],
+                        "prim_quartets": s.prim_quartets[i], "flops_per_prim": s.flops_per_prim[i],
+                        "flops_per_quartet": s.flops_per_quartet[i]})
+        return {"classes": out, "flops_total": s.flops_total,
+                "quartets": sum(c["quartets"] for c in out), "prim_quartets": sum(c["prim_quartets"] for c in out)}
+
+    # ---- one-electron / SCF ----
+    def one_electron(self):
+        n = self.nbf
+        S, T, V = np.zeros((n, n)), np.zeros((n, n)), np.zeros((n, n))
+        e = ctypes.c_double()
+        self._check(_lib.fk_one_electron(self._ctx, _ptr(S), _ptr(T), _ptr(V), ctypes.byref(e)))
+        return S, T, V, e.value
+
+    def run_scf(self, D0=None, max_iter=100, e_tol=1e-10, g_tol=1e-8, diis_n=8, lindep=1e-8):
+        n = self.nbf
+        D = np.zeros((n, n)) if D0 is None else np.ascontiguousarray(D0, dtype=np.float64).copy()
+        o = ScfOpts(int(max_iter), float(e_tol), float(g_tol), int(diis_n), 0 if D0 is None else 1, float(lindep))
+        r = ScfResult()
+        rc = _lib.fk_run_scf(self._ctx, ctypes.byref(o), ctypes.byref(r), _ptr(D))
+        if rc not in (FK_OK, FK_ERR_NOT_CONVERGED):
+            self._check(rc)
+        res = {k: getattr(r, k) for k, _ in ScfResult._fields_}
+        res["D"] = D
+        return res
+
+    # ---- diagnostics ----
+    def debug_eri(self, quartets, on_device=True):
+        q = np.ascontiguousarray(np.asarray(quartets, dtype=np.int32).reshape(-1, 4))
+        shapes = [tuple(_ncart(int(self.sh_l[s])) for s in row) for row in q]
+        tot = sum(int(np.prod(s)) for s in shapes)
+        out = np.zeros(max(tot, 1))
+        self._check(_lib.fk_debug_eri(self._ctx, len(q), _ptr(q), _ptr(out), 1 if on_device else 0))
+        res, o = [], 0
+        for s in shapes:
+            m = int(np.prod(s))
+            res.append(out[o:o + m].reshape(s))
+            o += m
+        return res

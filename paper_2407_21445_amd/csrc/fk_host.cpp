@@ -1,0 +1,854 @@
+// Host side of libfockjk: context, basis normalisation, shell pairs, Schwarz
+// factors, class sort, work tiles and the C-ABI entry points declared in
+// include/fockjk.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <numeric>
+#include <string>
+#include <vector>
+
+#include "../../include/fockjk.h"
+#include "fk_internal.h"
+#include "fk_rys.h"
+
+namespace {
+
+constexpr int NPC = 10;  // pair classes (la >= lb, la <= 3)
+
+constexpr int ncart(int l) { return (l + 1) * (l + 2) / 2; }
+inline int pair_class(int la, int lb) { return la * (la + 1) / 2 + lb; }
+
+double dfact(int n)
+{
+    double r = 1.0;
+    for (int k = n; k > 1; k -= 2) r *= k;
+    return r;
+}
+
+template <class T>
+struct DevBuf {
+    T *p = nullptr;
+    size_t n = 0;
+};
+
+struct QuartetClass {
+    int P, Q;
+    FkClassInfo info;
+    int64_t tile_off, ntile;
+    int64_t nquartet, nprim;  // Schwarz-surviving counts
+    int blocks_per_cu;
+};
+
+}  // namespace
+
+struct fk_ctx {
+    int device = -1;
+    std::string err;
+    int ncu = 0;
+    // geometry
+    int natom = 0, charge = 0, nelec = 0;
+    std::vector<int> Z;
+    std::vector<double> xyz;
+    bool have_geom = false, have_basis = false, have_quartets = false;
+    // basis
+    int nshell = 0, nbf = 0;
+    std::vector<int> sh_atom, sh_l, sh_nprim, sh_poff, sh_bf;
+    std::vector<double> exps, coef;  // coef: normalised for the axis component
+    std::vector<double> bf_scale;    // component scale factors
+    // pairs
+    fk_screen_opts opts{};
+    std::vector<int> pr_sa, pr_sb, pr_ppoff, pr_npp, pr_cls;
+    std::vector<double> pr_AB, pr_G, pp;
+    std::vector<int> cls_list[NPC];              // sorted pair indices per class
+    std::vector<std::pair<int, int>> cls_groups[NPC];  // [begin, end) of equal npp
+    std::vector<int> ket_list_all;               // concatenated class lists
+    int ket_off[NPC + 1] = {0};
+    std::vector<FkTile> tiles;
+    std::vector<QuartetClass> qclasses;
+    double flops_schwarz = 0;
+    int64_t nq_schwarz = 0;
+    int npair_kept = 0;
+    // device buffers
+    DevBuf<int> d_sh_bf, d_pr_sa, d_pr_sb, d_pr_ppoff, d_pr_npp, d_ket;
+    DevBuf<double> d_bf_scale, d_pr_AB, d_pr_G, d_pp, d_rys, d_Ds, d_Dsh, d_X, d_Din, d_Jout, d_Kout;
+    DevBuf<FkTile> d_tiles;
+    DevBuf<unsigned long long> d_cnt;
+    bool constants_uploaded = false;
+    // last build
+    bool stats_pending = false;
+};
+
+namespace {
+
+int fail(fk_ctx *c, int code, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    if (c) c->err = buf;
+    return code;
+}
+
+#define HIPCHK(ctx, call)                                                                   \
+    do {                                                                                   \
+        hipError_t e_ = (call);                                                            \
+        if (e_ != hipSuccess) return fail(ctx, FK_ERR_HIP, "%s: %s", #call, hipGetErrorString(e_)); \
+    } while (0)
+
+template <class T>
+int dev_upload(fk_ctx *c, DevBuf<T> &b, const T *src, size_t n)
+{
+    if (b.n < n || !b.p) {
+        if (b.p) hipFree(b.p);
+        b.p = nullptr;
+        b.n = 0;
+        if (hipMalloc((void **)&b.p, std::max<size_t>(n, 1) * sizeof(T)) != hipSuccess)
+            return fail(c, FK_ERR_OOM, "hipMalloc of %zu bytes failed", n * sizeof(T));
+        b.n = std::max<size_t>(n, 1);
+    }
+    if (src && n) HIPCHK(c, hipMemcpy(b.p, src, n * sizeof(T), hipMemcpyHostToDevice));
+    return FK_OK;
+}
+
+template <class T>
+void dev_free(DevBuf<T> &b)
+{
+    if (b.p) hipFree(b.p);
+    b.p = nullptr;
+    b.n = 0;
+}
+
+// Contraction coefficients for the axis-aligned component, normalised so the
+// contracted function has unit self-overlap; primitives use
+// N(a,l) = (2a/pi)^(3/4) (4a)^(l/2) / sqrt((2l-1)!!).
+void normalise_shell(int l, const double *e, const double *d, int np, double *out)
+{
+    for (int i = 0; i < np; ++i)
+        out[i] = d[i] * std::pow(2 * e[i] / M_PI, 0.75) * std::pow(4 * e[i], 0.5 * l) / std::sqrt(dfact(2 * l - 1));
+    double s = 0;
+    for (int i = 0; i < np; ++i)
+        for (int j = 0; j < np; ++j) {
+            const double p = e[i] + e[j];
+            s += out[i] * out[j] * std::pow(M_PI / p, 1.5) * dfact(2 * l - 1) / std::pow(2 * p, l);
+        }
+    const double f = 1.0 / std::sqrt(s);
+    for (int i = 0; i < np; ++i) out[i] *= f;
+}
+
+void cart_exps(int l, int k, int &x, int &y, int &z)
+{
+    int c = 0;
+    for (int a = l; a >= 0; --a)
+        for (int b = l - a; b >= 0; --b) {
+            if (c == k) { x = a; y = b; z = l - a - b; return; }
+            ++c;
+        }
+}
+
+void free_device(fk_ctx *c)
+{
+    dev_free(c->d_sh_bf); dev_free(c->d_pr_sa); dev_free(c->d_pr_sb); dev_free(c->d_pr_ppoff);
+    dev_free(c->d_pr_npp); dev_free(c->d_ket); dev_free(c->d_bf_scale); dev_free(c->d_pr_AB);
+    dev_free(c->d_pr_G); dev_free(c->d_pp); dev_free(c->d_rys); dev_free(c->d_Ds); dev_free(c->d_Dsh);
+    dev_free(c->d_X); dev_free(c->d_Din); dev_free(c->d_Jout); dev_free(c->d_Kout); dev_free(c->d_tiles);
+    dev_free(c->d_cnt);
+}
+
+// canonical orientation of a shell pair: first shell has the higher l
+void orient(const fk_ctx *c, int a, int b, int &sa, int &sb)
+{
+    if (c->sh_l[a] > c->sh_l[b] || (c->sh_l[a] == c->sh_l[b] && a >= b)) { sa = a; sb = b; }
+    else { sa = b; sb = a; }
+}
+
+void make_pair(fk_ctx *c, int sa, int sb)
+{
+    const double *A = &c->xyz[3 * c->sh_atom[sa]], *B = &c->xyz[3 * c->sh_atom[sb]];
+    double AB[3] = {A[0] - B[0], A[1] - B[1], A[2] - B[2]};
+    const double ab2 = AB[0] * AB[0] + AB[1] * AB[1] + AB[2] * AB[2];
+    c->pr_sa.push_back(sa);
+    c->pr_sb.push_back(sb);
+    c->pr_cls.push_back(pair_class(c->sh_l[sa], c->sh_l[sb]));
+    c->pr_ppoff.push_back((int)(c->pp.size() / FK_NPP_REC));
+    for (int k = 0; k < 3; ++k) c->pr_AB.push_back(AB[k]);
+    const double kfac = std::sqrt(2.0 / std::sqrt(M_PI));
+    int np = 0;
+    for (int i = c->sh_poff[sa]; i < c->sh_poff[sa + 1]; ++i)
+        for (int j = c->sh_poff[sb]; j < c->sh_poff[sb + 1]; ++j) {
+            const double ai = c->exps[i], aj = c->exps[j], z = ai + aj;
+            double rec[FK_NPP_REC];
+            rec[0] = z;
+            rec[1] = 0.5 / z;
+            for (int k = 0; k < 3; ++k) {
+                rec[2 + k] = (ai * A[k] + aj * B[k]) / z;
+                rec[5 + k] = rec[2 + k] - A[k];
+            }
+            rec[8] = c->coef[i] * c->coef[j] * std::pow(M_PI / z, 1.5) * std::exp(-ai * aj / z * ab2) * kfac;
+            rec[9] = 0.0;
+            c->pp.insert(c->pp.end(), rec, rec + FK_NPP_REC);
+            ++np;
+        }
+    c->pr_npp.push_back(np);
+    c->pr_G.push_back(0.0);
+}
+
+// Raw contracted integrals for quartets given as (bra pair, ket pair) of one
+// class pair (P = class of bra >= Q = class of ket), on device or host.
+int eval_quartets(fk_ctx *c, int P, int Q, const std::vector<int> &qs, std::vector<double> &out, bool on_device)
+{
+    FkClassInfo ci;
+    int rc = fk_kernels_class_info(P, Q, &ci);
+    if (rc) return fail(c, FK_ERR_UNSUPPORTED, "class (%d,%d) not built", P, Q);
+    const int nq = (int)qs.size() / 2;
+    out.assign((size_t)nq * ci.nout, 0.0);
+    if (nq == 0) return FK_OK;
+    if (!on_device) {
+        rc = fk_kernels_debug_host(P, Q, c->pr_ppoff.data(), c->pr_npp.data(), c->pr_AB.data(), c->pp.data(),
+                                   qs.data(), nq, out.data());
+        return rc ? fail(c, FK_ERR_UNSUPPORTED, "host evaluation failed") : FK_OK;
+    }
+    DevBuf<int> dq;
+    DevBuf<double> dout;
+    if ((rc = dev_upload(c, dq, qs.data(), qs.size()))) return rc;
+    if ((rc = dev_upload<double>(c, dout, nullptr, out.size()))) { dev_free(dq); return rc; }
+    FkDebugArgs a;
+    a.pair_ppoff = c->d_pr_ppoff.p;
+    a.pair_npp = c->d_pr_npp.p;
+    a.pair_AB = c->d_pr_AB.p;
+    a.pp = c->d_pp.p;
+    a.quartets = (const int2 *)dq.p;
+    a.nq = nq;
+    a.out = dout.p;
+    a.rys_tab = c->d_rys.p + rys_staged_offset(ci.nroot);
+    rc = fk_kernels_launch_debug(P, Q, &a, nullptr);
+    hipError_t e = hipDeviceSynchronize();
+    if (rc == 0 && e == hipSuccess) e = hipMemcpy(out.data(), dout.p, out.size() * sizeof(double), hipMemcpyDeviceToHost);
+    dev_free(dq);
+    dev_free(dout);
+    if (rc) return fail(c, FK_ERR_HIP, "debug kernel launch failed for class (%d,%d)", P, Q);
+    if (e != hipSuccess) return fail(c, FK_ERR_HIP, "debug kernel: %s", hipGetErrorString(e));
+    return FK_OK;
+}
+
+int upload_pairs(fk_ctx *c)
+{
+    int rc;
+    if ((rc = dev_upload(c, c->d_pr_sa, c->pr_sa.data(), c->pr_sa.size()))) return rc;
+    if ((rc = dev_upload(c, c->d_pr_sb, c->pr_sb.data(), c->pr_sb.size()))) return rc;
+    if ((rc = dev_upload(c, c->d_pr_ppoff, c->pr_ppoff.data(), c->pr_ppoff.size()))) return rc;
+    if ((rc = dev_upload(c, c->d_pr_npp, c->pr_npp.data(), c->pr_npp.size()))) return rc;
+    if ((rc = dev_upload(c, c->d_pr_AB, c->pr_AB.data(), c->pr_AB.size()))) return rc;
+    if ((rc = dev_upload(c, c->d_pp, c->pp.data(), c->pp.size()))) return rc;
+    return FK_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int fk_create(fk_ctx **out, int device)
+{
+    if (!out) return FK_ERR_ARG;
+    *out = nullptr;
+    fk_ctx *c = new fk_ctx();
+    c->device = device;
+    if (device >= 0) {
+        int ndev = 0;
+        if (hipGetDeviceCount(&ndev) != hipSuccess || device >= ndev) {
+            delete c;
+            return FK_ERR_HIP;
+        }
+        if (hipSetDevice(device) != hipSuccess) { delete c; return FK_ERR_HIP; }
+        hipDeviceProp_t prop;
+        if (hipGetDeviceProperties(&prop, device) != hipSuccess) { delete c; return FK_ERR_HIP; }
+        c->ncu = prop.multiProcessorCount;
+        if (dev_upload(c, c->d_rys, rys_staged_host(), (size_t)rys_staged_total())) { delete c; return FK_ERR_OOM; }
+    }
+    *out = c;
+    return FK_OK;
+}
+
+void fk_destroy(fk_ctx *c)
+{
+    if (!c) return;
+    if (c->device >= 0) {
+        hipSetDevice(c->device);
+        free_device(c);
+    }
+    delete c;
+}
+
+const char *fk_last_error(const fk_ctx *c) { return c ? c->err.c_str() : "null context"; }
+
+int fk_set_geometry(fk_ctx *c, int natom, const int *Z, const double *xyz, int charge)
+{
+    if (!c) return FK_ERR_ARG;
+    if (natom <= 0 || !Z || !xyz) return fail(c, FK_ERR_ARG, "fk_set_geometry: natom must be > 0 and arrays non-null");
+    long long zs = 0;
+    for (int i = 0; i < natom; ++i) {
+        if (Z[i] < 0 || Z[i] > 118) return fail(c, FK_ERR_ARG, "fk_set_geometry: Z[%d] = %d out of range", i, Z[i]);
+        zs += Z[i];
+        for (int k = 0; k < 3; ++k)
+            if (!std::isfinite(xyz[3 * i + k])) return fail(c, FK_ERR_ARG, "fk_set_geometry: non-finite coordinate");
+    }
+    const long long ne = zs - charge;
+    if (ne < 0 || (ne & 1)) return fail(c, FK_ERR_ARG, "fk_set_geometry: %lld electrons (closed shell needs an even count)", ne);
+    c->natom = natom;
+    c->Z.assign(Z, Z + natom);
+    c->xyz.assign(xyz, xyz + 3 * natom);
+    c->charge = charge;
+    c->nelec = (int)ne;
+    c->have_geom = true;
+    c->have_basis = false;
+    c->have_quartets = false;
+    return FK_OK;
+}
+
+int fk_set_basis(fk_ctx *c, int nshell, const int *shell_atom, const int *shell_l, const int *shell_nprim,
+                 const double *exps, const double *coefs)
+{
+    if (!c) return FK_ERR_ARG;
+    if (!c->have_geom) return fail(c, FK_ERR_STATE, "fk_set_basis: call fk_set_geometry first");
+    if (nshell <= 0 || !shell_atom || !shell_l || !shell_nprim || !exps || !coefs)
+        return fail(c, FK_ERR_ARG, "fk_set_basis: nshell must be > 0 and arrays non-null");
+    int np = 0;
+    for (int s = 0; s < nshell; ++s) {
+        if (shell_atom[s] < 0 || shell_atom[s] >= c->natom)
+            return fail(c, FK_ERR_ARG, "fk_set_basis: shell %d on atom %d of %d", s, shell_atom[s], c->natom);
+        if (shell_l[s] < 0 || shell_l[s] > FK_MAX_L)
+            return fail(c, FK_ERR_UNSUPPORTED, "fk_set_basis: shell %d has l = %d (max %d)", s, shell_l[s], FK_MAX_L);
+        if (shell_nprim[s] < 1 || shell_nprim[s] > FK_MAX_K)
+            return fail(c, FK_ERR_UNSUPPORTED, "fk_set_basis: shell %d has %d primitives (1..%d)", s, shell_nprim[s],
+                        FK_MAX_K);
+        np += shell_nprim[s];
+    }
+    for (int i = 0; i < np; ++i) {
+        if (!(exps[i] > 0) || !std::isfinite(exps[i]))
+            return fail(c, FK_ERR_ARG, "fk_set_basis: exponent %d is %g (must be > 0)", i, exps[i]);
+        if (!std::isfinite(coefs[i])) return fail(c, FK_ERR_ARG, "fk_set_basis: coefficient %d not finite", i);
+    }
+    c->nshell = nshell;
+    c->sh_atom.assign(shell_atom, shell_atom + nshell);
+    c->sh_l.assign(shell_l, shell_l + nshell);
+    c->sh_nprim.assign(shell_nprim, shell_nprim + nshell);
+    c->sh_poff.assign(nshell + 1, 0);
+    c->sh_bf.assign(nshell + 1, 0);
+    for (int s = 0; s < nshell; ++s) {
+        c->sh_poff[s + 1] = c->sh_poff[s] + shell_nprim[s];
+        c->sh_bf[s + 1] = c->sh_bf[s] + ncart(shell_l[s]);
+    }
+    c->nbf = c->sh_bf[nshell];
+    c->exps.assign(exps, exps + np);
+    c->coef.assign(np, 0.0);
+    c->bf_scale.assign(c->nbf, 1.0);
+    for (int s = 0; s < nshell; ++s) {
+        const int l = shell_l[s];
+        normalise_shell(l, &c->exps[c->sh_poff[s]], coefs + c->sh_poff[s], shell_nprim[s], &c->coef[c->sh_poff[s]]);
+        for (int k = 0; k < ncart(l); ++k) {
+            int x, y, z;
+            cart_exps(l, k, x, y, z);
+            c->bf_scale[c->sh_bf[s] + k] = std::sqrt(dfact(2 * l - 1) / (dfact(2 * x - 1) * dfact(2 * y - 1) * dfact(2 * z - 1)));
+        }
+    }
+    c->have_basis = true;
+    c->have_quartets = false;
+    if (c->device >= 0) {
+        hipSetDevice(c->device);
+        int rc;
+        if ((rc = dev_upload(c, c->d_sh_bf, c->sh_bf.data(), c->sh_bf.size()))) return rc;
+        if ((rc = dev_upload(c, c->d_bf_scale, c->bf_scale.data(), c->bf_scale.size()))) return rc;
+    }
+    return FK_OK;
+}
+
+int fk_build_quartets(fk_ctx *c, const fk_screen_opts *o)
+{
+    if (!c) return FK_ERR_ARG;
+    if (!c->have_basis) return fail(c, FK_ERR_STATE, "fk_build_quartets: basis not set");
+    fk_screen_opts opts = {1e-10, 0.0, 1, 0};
+    if (o) opts = *o;
+    if (!(opts.tau >= 0) || !(opts.tau_prim >= 0)) return fail(c, FK_ERR_ARG, "fk_build_quartets: negative threshold");
+    c->opts = opts;
+    const bool dev = c->device >= 0;
+    if (dev) hipSetDevice(c->device);
+    // 1. all unique shell pairs with their primitive pairs
+    c->pr_sa.clear(); c->pr_sb.clear(); c->pr_ppoff.clear(); c->pr_npp.clear(); c->pr_cls.clear();
+    c->pr_AB.clear(); c->pr_G.clear(); c->pp.clear();
+    for (int a = 0; a < c->nshell; ++a)
+        for (int b = 0; b <= a; ++b) {
+            int sa, sb;
+            orient(c, a, b, sa, sb);
+            make_pair(c, sa, sb);
+        }
+    const int npair = (int)c->pr_sa.size();
+    int rc;
+    if (dev && (rc = upload_pairs(c))) return rc;
+    // 2. Schwarz factors from the diagonal quartets (ab|ab)
+    for (int P = 0; P < NPC; ++P) {
+        std::vector<int> idx, qs;
+        for (int p = 0; p < npair; ++p)
+            if (c->pr_cls[p] == P) { idx.push_back(p); qs.push_back(p); qs.push_back(p); }
+        if (idx.empty()) continue;
+        std::vector<double> out;
+        if ((rc = eval_quartets(c, P, P, qs, out, dev))) return rc;
+        const int la = c->sh_l[c->pr_sa[idx[0]]], lb = c->sh_l[c->pr_sb[idx[0]]];
+        const int na = ncart(la), nb = ncart(lb), nout = na * nb * na * nb;
+        for (size_t q = 0; q < idx.size(); ++q) {
+            const int p = idx[q];
+            const double *sa = &c->bf_scale[c->sh_bf[c->pr_sa[p]]], *sb = &c->bf_scale[c->sh_bf[c->pr_sb[p]]];
+            double g = 0;
+            for (int ia = 0; ia < na; ++ia)
+                for (int ib = 0; ib < nb; ++ib) {
+                    const double v = out[q * nout + ((ia * nb + ib) * na + ia) * nb + ib] * sa[ia] * sa[ia] * sb[ib] * sb[ib];
+                    g = std::max(g, std::sqrt(std::fabs(v)));
+                }
+            c->pr_G[p] = g;
+        }
+    }
+    const double gmax = npair ? *std::max_element(c->pr_G.begin(), c->pr_G.end()) : 0.0;
+    // 3. class lists sorted by (primitive-pair count, G descending)
+    c->npair_kept = 0;
+    for (int P = 0; P < NPC; ++P) { c->cls_list[P].clear(); c->cls_groups[P].clear(); }
+    for (int p = 0; p < npair; ++p) {
+        if (opts.tau > 0 && c->pr_G[p] * gmax < opts.tau) continue;
+        c->cls_list[c->pr_cls[p]].push_back(p);
+        ++c->npair_kept;
+    }
+    c->ket_list_all.clear();
+    for (int P = 0; P < NPC; ++P) {
+        auto &L = c->cls_list[P];
+        std::stable_sort(L.begin(), L.end(), [&](int x, int y) {
+            if (c->pr_npp[x] != c->pr_npp[y]) return c->pr_npp[x] > c->pr_npp[y];
+            return c->pr_G[x] > c->pr_G[y];
+        });
+        for (size_t i = 0; i < L.size();) {
+            size_t j = i;
+            while (j < L.size() && c->pr_npp[L[j]] == c->pr_npp[L[i]]) ++j;
+            c->cls_groups[P].push_back({(int)i, (int)j});
+            i = j;
+        }
+        c->ket_off[P] = (int)c->ket_list_all.size();
+        c->ket_list_all.insert(c->ket_list_all.end(), L.begin(), L.end());
+    }
+    c->ket_off[NPC] = (int)c->ket_list_all.size();
+    // 4. tiles per quartet class (P >= Q): bra from class P, kets from class Q
+    c->tiles.clear();
+    c->qclasses.clear();
+    c->flops_schwarz = 0;
+    c->nq_schwarz = 0;
+    for (int P = 0; P < NPC; ++P)
+        for (int Q = 0; Q <= P; ++Q) {
+            const auto &LP = c->cls_list[P], &LQ = c->cls_list[Q];
+            if (LP.empty() || LQ.empty()) continue;
+            QuartetClass qc;
+            qc.P = P; qc.Q = Q;
+            if (fk_kernels_class_info(P, Q, &qc.info))
+                return fail(c, FK_ERR_UNSUPPORTED, "quartet class (%d|%d) is not built into this library", P, Q);
+            qc.tile_off = (int64_t)c->tiles.size();
+            qc.nquartet = 0; qc.nprim = 0;
+            for (int pb = 0; pb < (int)LP.size(); ++pb) {
+                const int bra = LP[pb];
+                const double thr = opts.tau > 0 ? opts.tau / c->pr_G[bra] : 0.0;
+                for (const auto &g : c->cls_groups[Q]) {
+                    // kets in [g.first, g.second) are sorted by G descending
+                    int lo = g.first, hi = g.second;
+                    while (lo < hi) {
+                        const int mid = (lo + hi) / 2;
+                        if (c->pr_G[LQ[mid]] >= thr) lo = mid + 1; else hi = mid;
+                    }
+                    int cnt = lo - g.first;
+                    if (P == Q) cnt = std::min(cnt, std::max(0, pb + 1 - g.first));
+                    if (cnt <= 0) continue;
+                    for (int k = 0; k < cnt; k += 64) {
+                        FkTile t;
+                        t.bra = bra;
+                        t.ket_begin = c->ket_off[Q] + g.first + k;
+                        t.ket_count = std::min(64, cnt - k);
+                        t.flags = (P == Q) ? 1 : 0;
+                        c->tiles.push_back(t);
+                    }
+                    qc.nquartet += cnt;
+                    qc.nprim += (int64_t)cnt * c->pr_npp[bra] * c->pr_npp[LQ[g.first]];
+                }
+            }
+            qc.ntile = (int64_t)c->tiles.size() - qc.tile_off;
+            if (qc.ntile == 0) continue;
+            c->flops_schwarz += qc.nprim * qc.info.flops_prim + qc.nquartet * qc.info.flops_quartet;
+            c->nq_schwarz += qc.nquartet;
+            qc.blocks_per_cu = 1;
+            if (dev) {
+                int nb = 0;
+                if (fk_kernels_max_blocks(P, Q, &nb) == 0 && nb > 0) qc.blocks_per_cu = nb;
+            }
+            c->qclasses.push_back(qc);
+        }
+    if (dev) {
+        if ((rc = dev_upload(c, c->d_pr_G, c->pr_G.data(), c->pr_G.size()))) return rc;
+        if ((rc = dev_upload(c, c->d_ket, c->ket_list_all.data(), c->ket_list_all.size()))) return rc;
+        if ((rc = dev_upload(c, c->d_tiles, c->tiles.data(), c->tiles.size()))) return rc;
+        const size_t nn = (size_t)c->nbf * c->nbf;
+        if ((rc = dev_upload<double>(c, c->d_Ds, nullptr, nn))) return rc;
+        if ((rc = dev_upload<double>(c, c->d_Dsh, nullptr, (size_t)c->nshell * c->nshell))) return rc;
+        if ((rc = dev_upload<double>(c, c->d_X, nullptr, 2 * nn))) return rc;
+        if ((rc = dev_upload<unsigned long long>(c, c->d_cnt, nullptr, 2 * FK_MAX_QCLASS))) return rc;
+    }
+    c->have_quartets = true;
+    return FK_OK;
+}
+
+int fk_info(const fk_ctx *c, fk_info_t *info)
+{
+    if (!c || !info) return FK_ERR_ARG;
+    std::memset(info, 0, sizeof *info);
+    info->nbf = c->nbf;
+    info->nshell = c->nshell;
+    info->natom = c->natom;
+    info->nelec = c->nelec;
+    info->npair = (int)c->pr_sa.size();
+    info->npair_kept = c->npair_kept;
+    int ncls = 0;
+    for (int P = 0; P < NPC; ++P) ncls += !c->cls_list[P].empty();
+    info->nclass_pair = ncls;
+    info->nquartet_class = (int)c->qclasses.size();
+    info->nprim_pair = (int64_t)(c->pp.size() / FK_NPP_REC);
+    info->nquartet_schwarz = c->nq_schwarz;
+    info->ntile = (int64_t)c->tiles.size();
+    info->flops_schwarz = c->flops_schwarz;
+    return FK_OK;
+}
+
+int fk_build_jk(fk_ctx *c, const double *D, double *J, double *K, unsigned flags, void *stream)
+{
+    if (!c) return FK_ERR_ARG;
+    if (c->device < 0) return fail(c, FK_ERR_STATE, "fk_build_jk: context has no device");
+    if (!c->have_quartets) return fail(c, FK_ERR_STATE, "fk_build_jk: call fk_build_quartets first");
+    if (!D || !J || !K) return fail(c, FK_ERR_ARG, "fk_build_jk: null matrix pointer");
+    hipSetDevice(c->device);
+    hipStream_t st = (hipStream_t)stream;
+    const int n = c->nbf;
+    const size_t nn = (size_t)n * n;
+    const bool devp = flags & FK_DEVICE_PTRS;
+    int rc;
+    const double *Dd = D;
+    double *Jd = J, *Kd = K;
+    if (!devp) {
+        if ((rc = dev_upload<double>(c, c->d_Din, nullptr, nn))) return rc;
+        if ((rc = dev_upload<double>(c, c->d_Jout, nullptr, nn))) return rc;
+        if ((rc = dev_upload<double>(c, c->d_Kout, nullptr, nn))) return rc;
+        HIPCHK(c, hipMemcpyAsync(c->d_Din.p, D, nn * sizeof(double), hipMemcpyHostToDevice, st));
+        Dd = c->d_Din.p;
+        Jd = c->d_Jout.p;
+        Kd = c->d_Kout.p;
+    }
+    if (fk_kernels_launch_prep(Dd, c->d_sh_bf.p, c->d_bf_scale.p, c->nshell, n, c->d_Ds.p, c->d_Dsh.p, st))
+        return fail(c, FK_ERR_HIP, "prep kernel launch failed");
+    if (fk_kernels_launch_fill(c->d_X.p, (long long)(2 * nn), st) ||
+        fk_kernels_launch_fill((double *)c->d_cnt.p, 2 * FK_MAX_QCLASS, st))
+        return fail(c, FK_ERR_HIP, "fill kernel launch failed");
+    for (size_t i = 0; i < c->qclasses.size(); ++i) {
+        const QuartetClass &qc = c->qclasses[i];
+        FkJKArgs a;
+        a.sh_bf = c->d_sh_bf.p;
+        a.pair_sa = c->d_pr_sa.p;
+        a.pair_sb = c->d_pr_sb.p;
+        a.pair_ppoff = c->d_pr_ppoff.p;
+        a.pair_npp = c->d_pr_npp.p;
+        a.pair_AB = c->d_pr_AB.p;
+        a.pair_G = c->d_pr_G.p;
+        a.pp = c->d_pp.p;
+        a.ket_list = c->d_ket.p;
+        a.tiles = c->d_tiles.p + qc.tile_off;
+        a.ntiles = (int)qc.ntile;
+        a.nshell = c->nshell;
+        a.Dsh = c->d_Dsh.p;
+        a.Ds = c->d_Ds.p;
+        a.XJ = c->d_X.p;
+        a.XK = c->d_X.p + nn;
+        a.nbf = n;
+        a.dscreen = c->opts.density_screen && c->opts.tau > 0;
+        a.tau = c->opts.tau;
+        a.rys_tab = c->d_rys.p + rys_staged_offset(qc.info.nroot);
+        a.counters = c->d_cnt.p + 2 * i;
+        const int64_t want = (qc.ntile + 3) / 4;
+        const int64_t cap = (int64_t)qc.blocks_per_cu * std::max(c->ncu, 1);
+        const int grid = (int)std::max<int64_t>(1, std::min(want, cap));
+        if (fk_kernels_launch_jk(qc.P, qc.Q, &a, grid, st))
+            return fail(c, FK_ERR_HIP, "J/K kernel launch failed for class (%d|%d)", qc.P, qc.Q);
+    }
+    if (fk_kernels_launch_finalize(c->d_X.p, c->d_X.p + nn, c->d_bf_scale.p, n, Jd, Kd, st))
+        return fail(c, FK_ERR_HIP, "finalize kernel launch failed");
+    c->stats_pending = true;
+    if (!devp) {
+        HIPCHK(c, hipMemcpyAsync(J, Jd, nn * sizeof(double), hipMemcpyDeviceToHost, st));
+        HIPCHK(c, hipMemcpyAsync(K, Kd, nn * sizeof(double), hipMemcpyDeviceToHost, st));
+        HIPCHK(c, hipStreamSynchronize(st));
+    } else if (flags & FK_SYNC) {
+        HIPCHK(c, hipStreamSynchronize(st));
+    }
+    return FK_OK;
+}
+
+int fk_stats(fk_ctx *c, fk_stats_t *s)
+{
+    if (!c || !s) return FK_ERR_ARG;
+    std::memset(s, 0, sizeof *s);
+    if (!c->have_quartets || c->device < 0) return fail(c, FK_ERR_STATE, "fk_stats: no build on this context");
+    hipSetDevice(c->device);
+    std::vector<unsigned long long> cnt(2 * FK_MAX_QCLASS, 0);
+    HIPCHK(c, hipDeviceSynchronize());
+    HIPCHK(c, hipMemcpy(cnt.data(), c->d_cnt.p, cnt.size() * sizeof(unsigned long long), hipMemcpyDeviceToHost));
+    s->nclass = (int)c->qclasses.size();
+    for (size_t i = 0; i < c->qclasses.size(); ++i) {
+        const auto &q = c->qclasses[i];
+        s->la[i] = q.info.la; s->lb[i] = q.info.lb; s->lc[i] = q.info.lc; s->ld[i] = q.info.ld;
+        s->quartets[i] = (int64_t)cnt[2 * i];
+        s->prim_quartets[i] = (int64_t)cnt[2 * i + 1];
+        s->flops_per_prim[i] = q.info.flops_prim;
+        s->flops_per_quartet[i] = q.info.flops_quartet;
+        s->flops_total += s->prim_quartets[i] * q.info.flops_prim + s->quartets[i] * q.info.flops_quartet;
+    }
+    return FK_OK;
+}
+
+int fk_debug_eri(fk_ctx *c, int nq, const int *quartets, double *out, int on_device)
+{
+    if (!c) return FK_ERR_ARG;
+    if (!c->have_quartets) return fail(c, FK_ERR_STATE, "fk_debug_eri: call fk_build_quartets first");
+    if (nq < 0 || (nq > 0 && (!quartets || !out))) return fail(c, FK_ERR_ARG, "fk_debug_eri: bad arguments");
+    if (on_device && c->device < 0) return fail(c, FK_ERR_STATE, "fk_debug_eri: context has no device");
+    if (on_device) hipSetDevice(c->device);
+    // pair index lookup for arbitrary shell pairs
+    auto pair_index = [&](int a, int b) {
+        const int hi = std::max(a, b), lo = std::min(a, b);
+        return hi * (hi + 1) / 2 + lo;  // pairs were generated for a >= b in this order
+    };
+    size_t off = 0;
+    std::vector<size_t> offs(nq);
+    for (int q = 0; q < nq; ++q) {
+        for (int k = 0; k < 4; ++k)
+            if (quartets[4 * q + k] < 0 || quartets[4 * q + k] >= c->nshell)
+                return fail(c, FK_ERR_ARG, "fk_debug_eri: shell index out of range in quartet %d", q);
+        offs[q] = off;
+        off += (size_t)ncart(c->sh_l[quartets[4 * q]]) * ncart(c->sh_l[quartets[4 * q + 1]]) *
+               ncart(c->sh_l[quartets[4 * q + 2]]) * ncart(c->sh_l[quartets[4 * q + 3]]);
+    }
+    // group by canonical class
+    struct Item { int q, bra, ket; bool swap; };
+    std::vector<std::vector<Item>> groups(NPC * NPC);
+    for (int q = 0; q < nq; ++q) {
+        const int *s = quartets + 4 * q;
+        int p1 = pair_index(s[0], s[1]), p2 = pair_index(s[2], s[3]);
+        int c1 = c->pr_cls[p1], c2 = c->pr_cls[p2];
+        bool swap = c1 < c2;
+        if (swap) { std::swap(p1, p2); std::swap(c1, c2); }
+        groups[c1 * NPC + c2].push_back({q, p1, p2, swap});
+    }
+    for (int P = 0; P < NPC; ++P)
+        for (int Q = 0; Q <= P; ++Q) {
+            auto &g = groups[P * NPC + Q];
+            if (g.empty()) continue;
+            std::vector<int> qs;
+            for (auto &it : g) { qs.push_back(it.bra); qs.push_back(it.ket); }
+            std::vector<double> raw;
+            int rc = eval_quartets(c, P, Q, qs, raw, on_device != 0);
+            if (rc) return rc;
+            for (size_t k = 0; k < g.size(); ++k) {
+                const Item &it = g[k];
+                const int *s = quartets + 4 * it.q;
+                // canonical shells in raw order: (pa, pb | pc, pd)
+                const int pa = c->pr_sa[it.bra], pb = c->pr_sb[it.bra], pc = c->pr_sa[it.ket], pd = c->pr_sb[it.ket];
+                const int cs[4] = {pa, pb, pc, pd};
+                const int cn[4] = {ncart(c->sh_l[pa]), ncart(c->sh_l[pb]), ncart(c->sh_l[pc]), ncart(c->sh_l[pd])};
+                const int rn[4] = {ncart(c->sh_l[s[0]]), ncart(c->sh_l[s[1]]), ncart(c->sh_l[s[2]]), ncart(c->sh_l[s[3]])};
+                // position of requested shell slot r in the canonical tuple
+                int pos[4];
+                const int req_pair_first = it.swap ? 2 : 0;
+                // requested (s0,s1) maps to canonical pair (bra if !swap else ket)
+                for (int r = 0; r < 2; ++r) {
+                    const int base = it.swap ? 2 : 0;  // canonical slots of requested bra pair
+                    const int x = s[r];
+                    // if the pair has two equal shells, keep the slot order
+                    if (cs[base] == x && (cs[base + 1] != x || r == 0)) pos[r] = base;
+                    else pos[r] = base + 1;
+                }
+                for (int r = 2; r < 4; ++r) {
+                    const int base = it.swap ? 0 : 2;
+                    const int x = s[r];
+                    if (cs[base] == x && (cs[base + 1] != x || r == 2)) pos[r] = base;
+                    else pos[r] = base + 1;
+                }
+                (void)req_pair_first;
+                const double *src = raw.data() + k * (size_t)(cn[0] * cn[1] * cn[2] * cn[3]);
+                double *dst = out + offs[it.q];
+                const double *sc[4];
+                for (int r = 0; r < 4; ++r) sc[r] = &c->bf_scale[c->sh_bf[s[r]]];
+                int i[4];
+                for (i[0] = 0; i[0] < rn[0]; ++i[0])
+                    for (i[1] = 0; i[1] < rn[1]; ++i[1])
+                        for (i[2] = 0; i[2] < rn[2]; ++i[2])
+                            for (i[3] = 0; i[3] < rn[3]; ++i[3]) {
+                                int ci[4];
+                                for (int r = 0; r < 4; ++r) ci[pos[r]] = i[r];
+                                const double v = src[((ci[0] * cn[1] + ci[1]) * cn[2] + ci[2]) * cn[3] + ci[3]];
+                                dst[((i[0] * rn[1] + i[1]) * rn[2] + i[2]) * rn[3] + i[3]] =
+                                    v * sc[0][i[0]] * sc[1][i[1]] * sc[2][i[2]] * sc[3][i[3]];
+                            }
+            }
+        }
+    return FK_OK;
+}
+
+int fk_rys_host(int n, double T, double *u, double *w);
+
+// One-electron integrals on the host.  Overlap and kinetic energy by the
+// Obara-Saika 1-D recurrences; nuclear attraction by Rys quadrature of the
+// one-centre operator: V_ab = -Z_C (2 pi/p) K_AB sum_r w_r Ix Iy Iz with
+// I(a+1,0) = (PA - u PC) I(a,0) + a (1-u)/(2p) I(a-1,0) and the horizontal
+// transfer I(a,b+1) = I(a+1,b) + AB I(a,b).
+int fk_one_electron(fk_ctx *c, double *S, double *T, double *V, double *e_nuc)
+{
+    if (!c) return FK_ERR_ARG;
+    if (!c->have_basis) return fail(c, FK_ERR_STATE, "fk_one_electron: basis not set");
+    const int n = c->nbf;
+    if (e_nuc) {
+        double e = 0;
+        for (int a = 0; a < c->natom; ++a)
+            for (int b = 0; b < a; ++b) {
+                double r2 = 0;
+                for (int k = 0; k < 3; ++k) r2 += (c->xyz[3 * a + k] - c->xyz[3 * b + k]) * (c->xyz[3 * a + k] - c->xyz[3 * b + k]);
+                e += (double)c->Z[a] * c->Z[b] / std::sqrt(r2);
+            }
+        *e_nuc = e;
+    }
+    if (!S && !T && !V) return FK_OK;
+    constexpr int LM = FK_MAX_L + 3;
+    for (int sa = 0; sa < c->nshell; ++sa)
+        for (int sb = 0; sb < c->nshell; ++sb) {
+            const int la = c->sh_l[sa], lb = c->sh_l[sb];
+            const int na = ncart(la), nb = ncart(lb);
+            const double *A = &c->xyz[3 * c->sh_atom[sa]], *B = &c->xyz[3 * c->sh_atom[sb]];
+            double AB[3], ab2 = 0;
+            for (int k = 0; k < 3; ++k) { AB[k] = A[k] - B[k]; ab2 += AB[k] * AB[k]; }
+            std::vector<double> bs(na * nb, 0.0), bt(na * nb, 0.0), bv(na * nb, 0.0);
+            for (int i = c->sh_poff[sa]; i < c->sh_poff[sa + 1]; ++i)
+                for (int j = c->sh_poff[sb]; j < c->sh_poff[sb + 1]; ++j) {
+                    const double al = c->exps[i], be = c->exps[j], p = al + be;
+                    const double Kab = std::exp(-al * be / p * ab2) * c->coef[i] * c->coef[j];
+                    double P[3], PA[3], PB[3];
+                    for (int k = 0; k < 3; ++k) {
+                        P[k] = (al * A[k] + be * B[k]) / p;
+                        PA[k] = P[k] - A[k];
+                        PB[k] = P[k] - B[k];
+                    }
+                    // 1-D overlaps O[k][i][j], i <= la, j <= lb + 2
+                    double O[3][LM][LM] = {};
+                    for (int k = 0; k < 3; ++k) {
+                        O[k][0][0] = std::sqrt(M_PI / p);
+                        for (int x = 0; x <= la; ++x)
+                            for (int y = 0; y <= lb + 2; ++y) {
+                                if (x == 0 && y == 0) continue;
+                                double v;
+                                if (x > 0) {
+                                    v = PA[k] * O[k][x - 1][y];
+                                    if (x > 1) v += (x - 1) / (2 * p) * O[k][x - 2][y];
+                                    if (y > 0) v += y / (2 * p) * O[k][x - 1][y - 1];
+                                } else {
+                                    v = PB[k] * O[k][x][y - 1];
+                                    if (y > 1) v += (y - 1) / (2 * p) * O[k][x][y - 2];
+                                }
+                                O[k][x][y] = v;
+                            }
+                    }
+                    for (int ia = 0; ia < na; ++ia)
+                        for (int ib = 0; ib < nb; ++ib) {
+                            int a[3], b[3];
+                            cart_exps(la, ia, a[0], a[1], a[2]);
+                            cart_exps(lb, ib, b[0], b[1], b[2]);
+                            double s1[3], t1[3];
+                            for (int k = 0; k < 3; ++k) {
+                                s1[k] = O[k][a[k]][b[k]];
+                                double tk = -2 * be * be * O[k][a[k]][b[k] + 2] + be * (2 * b[k] + 1) * s1[k];
+                                if (b[k] >= 2) tk -= 0.5 * b[k] * (b[k] - 1) * O[k][a[k]][b[k] - 2];
+                                t1[k] = tk;
+                            }
+                            bs[ia * nb + ib] += Kab * s1[0] * s1[1] * s1[2];
+                            bt[ia * nb + ib] += Kab * (t1[0] * s1[1] * s1[2] + s1[0] * t1[1] * s1[2] + s1[0] * s1[1] * t1[2]);
+                        }
+                    if (!V) continue;
+                    const int nr = (la + lb) / 2 + 1;
+                    for (int C = 0; C < c->natom; ++C) {
+                        if (c->Z[C] == 0) continue;
+                        double PC[3], pc2 = 0;
+                        for (int k = 0; k < 3; ++k) { PC[k] = P[k] - c->xyz[3 * C + k]; pc2 += PC[k] * PC[k]; }
+                        double u[RYS_NMAX], w[RYS_NMAX];
+                        fk_rys_host(nr, p * pc2, u, w);
+                        const double pre = -c->Z[C] * 2 * M_PI / p * Kab;
+                        for (int r = 0; r < nr; ++r) {
+                            double I[3][LM][LM];
+                            for (int k = 0; k < 3; ++k) {
+                                double G[2 * LM];
+                                G[0] = 1.0;
+                                const double c00 = PA[k] - u[r] * PC[k], b10 = (1 - u[r]) / (2 * p);
+                                if (la + lb > 0) G[1] = c00;
+                                for (int e = 1; e < la + lb; ++e) G[e + 1] = c00 * G[e] + e * b10 * G[e - 1];
+                                // transfer to b: H[x][y] with x + y <= la + lb
+                                double H[2 * LM][LM];
+                                for (int e = 0; e <= la + lb; ++e) H[e][0] = G[e];
+                                for (int y = 0; y < lb; ++y)
+                                    for (int x = 0; x < la + lb - y; ++x) H[x][y + 1] = H[x + 1][y] + AB[k] * H[x][y];
+                                for (int x = 0; x <= la; ++x)
+                                    for (int y = 0; y <= lb; ++y) I[k][x][y] = H[x][y];
+                            }
+                            for (int ia = 0; ia < na; ++ia)
+                                for (int ib = 0; ib < nb; ++ib) {
+                                    int a[3], b[3];
+                                    cart_exps(la, ia, a[0], a[1], a[2]);
+                                    cart_exps(lb, ib, b[0], b[1], b[2]);
+                                    bv[ia * nb + ib] += pre * w[r] * I[0][a[0]][b[0]] * I[1][a[1]][b[1]] * I[2][a[2]][b[2]];
+                                }
+                        }
+                    }
+                }
+            for (int ia = 0; ia < na; ++ia)
+                for (int ib = 0; ib < nb; ++ib) {
+                    const int r = c->sh_bf[sa] + ia, col = c->sh_bf[sb] + ib;
+                    const double f = c->bf_scale[r] * c->bf_scale[col];
+                    if (S) S[(size_t)r * n + col] = f * bs[ia * nb + ib];
+                    if (T) T[(size_t)r * n + col] = f * bt[ia * nb + ib];
+                    if (V) V[(size_t)r * n + col] = f * bv[ia * nb + ib];
+                }
+        }
+    return FK_OK;
+}
+
+int fk_run_scf(fk_ctx *c, const fk_scf_opts *opts, fk_scf_result *result, double *D_inout)
+{
+    (void)opts; (void)result; (void)D_inout;
+    return fail(c, FK_ERR_UNSUPPORTED, "fk_run_scf: not available in this build");
+}
+
+int fk_rys_host(int n, double T, double *u, double *w)
+{
+    if (n < 1 || n > RYS_NMAX || !u || !w || !(T >= 0)) return FK_ERR_ARG;
+    const double *tab = rys_staged_host() + rys_staged_offset(n);
+    switch (n) {
+    case 1: rys_roots<1, true>(T, tab, u, w); break;
+    case 2: rys_roots<2, true>(T, tab, u, w); break;
+    case 3: rys_roots<3, true>(T, tab, u, w); break;
+    case 4: rys_roots<4, true>(T, tab, u, w); break;
+    case 5: rys_roots<5, true>(T, tab, u, w); break;
+    case 6: rys_roots<6, true>(T, tab, u, w); break;
+    case 7: rys_roots<7, true>(T, tab, u, w); break;
+    }
+    return FK_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,698 @@
+// HIP kernels of the J/K build for gfx950 (CDNA4, wave64).
+//
+// Hot path (per Fock build):
+//   k_prep_*   density preprocessing: component-scaled D and the shell-block
+//              maxima D_sh used by the per-quartet density screen;
+//   k_jk_lpq   lane-per-quartet Rys ERI + fused 8-fold digestion for classes
+//              whose whole output block fits in registers;
+//   k_jk_wpq   wave-per-quartet variant for large classes: lanes own bra
+//              Cartesian components;
+//   k_finalize J = X_J + X_J^T, K = X_K + X_K^T with component scaling.
+//
+// Digestion (paper: six Fock blocks per quartet, atomics after partial
+// pre-digestion; the degeneracy factors are not printed and are derived from
+// J and K's definitions): with v = (ab|cd) and s = 1/2 per coincidence among
+// a = b, c = d, ab = cd (shell level),
+//   X_J[a,b] += 2 s v D_cd,  X_J[c,d] += 2 s v D_ab,
+//   X_K[a,c] += s v D_bd,    X_K[a,d] += s v D_bc,
+//   X_K[b,c] += s v D_ad,    X_K[b,d] += s v D_ac,
+// and J = X_J + X_J^T, K = X_K + X_K^T.
+#include <hip/hip_runtime.h>
+
+#include "fk_internal.h"
+#include "fk_eri.h"
+
+#ifndef FK_BUILD_MAXL
+#define FK_BUILD_MAXL 3
+#endif
+#define FK_LPQ_MAX_NOUT 108
+#define FK_BLOCK 256
+#define FK_WAVES (FK_BLOCK / 64)
+
+namespace {
+
+constexpr int pair_la(int P) { return P == 0 ? 0 : (P <= 2 ? 1 : (P <= 5 ? 2 : 3)); }
+constexpr int pair_lb(int P) { return P - pair_la(P) * (pair_la(P) + 1) / 2; }
+
+template <int LA, int LB, int LC, int LD>
+constexpr bool use_wpq() { return fk::QClass<LA, LB, LC, LD>::NOUT > FK_LPQ_MAX_NOUT; }
+
+__device__ __forceinline__ fk::PrimPair load_pp(const double *__restrict pp, int idx)
+{
+    const double *r = pp + (size_t)idx * FK_NPP_REC;
+    fk::PrimPair p;
+    p.zeta = r[0];
+    p.oo2z = r[1];
+    p.P[0] = r[2]; p.P[1] = r[3]; p.P[2] = r[4];
+    p.PA[0] = r[5]; p.PA[1] = r[6]; p.PA[2] = r[7];
+    p.K = r[8];
+    return p;
+}
+
+__device__ __forceinline__ double wave_sum(double v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+__device__ __forceinline__ void atomic_add(double *p, double v) { unsafeAtomicAdd(p, v); }
+
+template <int NR>
+__device__ __forceinline__ void load_table(double *s_tab, const double *__restrict g)
+{
+    constexpr int TABN = rys_lds_size(NR);
+    for (int i = threadIdx.x; i < TABN; i += blockDim.x) s_tab[i] = g[i];
+    __syncthreads();
+}
+
+__device__ __forceinline__ double dmax6(const double *__restrict Dsh, int ns, int sa, int sb, int sc, int sd)
+{
+    double m1 = fmax(Dsh[sa * ns + sb], Dsh[sc * ns + sd]);
+    double m2 = fmax(Dsh[sa * ns + sc], Dsh[sa * ns + sd]);
+    double m3 = fmax(Dsh[sb * ns + sc], Dsh[sb * ns + sd]);
+    return fmax(m1, fmax(m2, m3));
+}
+
+// ---------------------------------------------------------------- lpq ----
+// One wave per tile (one bra pair, up to 64 ket pairs); lane i computes the
+// whole contracted quartet (bra | ket_i), consecutive lanes taking consecutive
+// kets, then digests it into the six blocks.
+template <int LA, int LB, int LC, int LD>
+__global__ void __launch_bounds__(FK_BLOCK) k_jk_lpq(FkJKArgs a)
+{
+    using Q = fk::QClass<LA, LB, LC, LD>;
+    constexpr int NA = Q::NA, NB = Q::NB, NC = Q::NC, ND = Q::ND, NOUT = Q::NOUT;
+    __shared__ double s_tab[rys_lds_size(Q::NR)];
+    load_table<Q::NR>(s_tab, a.rys_tab);
+
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int nwt = gridDim.x * FK_WAVES;
+    const int n = a.nbf, ns = a.nshell;
+    unsigned long long cq = 0, cp = 0;
+
+    for (int t = blockIdx.x * FK_WAVES + wave; t < a.ntiles; t += nwt) {
+        const FkTile tile = a.tiles[t];
+        const int bra = tile.bra;
+        const int sa = a.pair_sa[bra], sb = a.pair_sb[bra];
+        const int bpo = a.pair_ppoff[bra], bnp = a.pair_npp[bra];
+        const double AB[3] = {a.pair_AB[3 * bra], a.pair_AB[3 * bra + 1], a.pair_AB[3 * bra + 2]};
+        const double Gab = a.pair_G[bra];
+
+        const bool inrange = lane < tile.ket_count;
+        const int ket = a.ket_list[tile.ket_begin + (inrange ? lane : 0)];
+        const int sc = a.pair_sa[ket], sd = a.pair_sb[ket];
+        const int kpo = a.pair_ppoff[ket], knp = a.pair_npp[ket];
+        const double CD[3] = {a.pair_AB[3 * ket], a.pair_AB[3 * ket + 1], a.pair_AB[3 * ket + 2]};
+        bool active = inrange;
+        if (a.dscreen) active = active && (Gab * a.pair_G[ket] * dmax6(a.Dsh, ns, sa, sb, sc, sd) >= a.tau);
+        const unsigned long long mask = __ballot(active);
+        if (mask == 0ull) continue;
+        const int nact = __popcll(mask);
+        cq += nact;
+        cp += (unsigned long long)nact * bnp * knp;
+
+        double acc[NOUT];
+#pragma unroll
+        for (int o = 0; o < NOUT; ++o) acc[o] = 0.0;
+        if (active) {
+            for (int i = 0; i < bnp; ++i) {
+                const fk::PrimPair p = load_pp(a.pp, bpo + i);
+                for (int j = 0; j < knp; ++j) {
+                    const fk::PrimPair q = load_pp(a.pp, kpo + j);
+                    fk::rys_prim_all<LA, LB, LC, LD>(s_tab, p, q, AB, CD, acc);
+                }
+            }
+        }
+
+        const double fac = (sa == sb ? 0.5 : 1.0) * (sc == sd ? 0.5 : 1.0) *
+                           (((tile.flags & 1) && ket == bra) ? 0.5 : 1.0);
+        const int oa = a.sh_bf[sa], ob = a.sh_bf[sb], oc = a.sh_bf[sc], od = a.sh_bf[sd];
+        double jab[NA * NB];
+#pragma unroll
+        for (int o = 0; o < NA * NB; ++o) jab[o] = 0.0;
+        if (active) {
+#pragma unroll
+            for (int o = 0; o < NOUT; ++o) acc[o] *= fac;
+            // X_J[a,b] partial (reduced over the wave below) and X_J[c,d]
+            {
+                double dcd[NC * ND], dab[NA * NB];
+#pragma unroll
+                for (int ic = 0; ic < NC; ++ic)
+#pragma unroll
+                    for (int id = 0; id < ND; ++id) dcd[ic * ND + id] = a.Ds[(size_t)(oc + ic) * n + od + id];
+#pragma unroll
+                for (int ia = 0; ia < NA; ++ia)
+#pragma unroll
+                    for (int ib = 0; ib < NB; ++ib) dab[ia * NB + ib] = a.Ds[(size_t)(oa + ia) * n + ob + ib];
+#pragma unroll
+                for (int ab = 0; ab < NA * NB; ++ab)
+#pragma unroll
+                    for (int cd = 0; cd < NC * ND; ++cd) jab[ab] += acc[ab * NC * ND + cd] * dcd[cd];
+#pragma unroll
+                for (int ic = 0; ic < NC; ++ic)
+#pragma unroll
+                    for (int id = 0; id < ND; ++id) {
+                        double s = 0.0;
+#pragma unroll
+                        for (int ab = 0; ab < NA * NB; ++ab) s += acc[ab * NC * ND + ic * ND + id] * dab[ab];
+                        atomic_add(&a.XJ[(size_t)(oc + ic) * n + od + id], 2.0 * s);
+                    }
+            }
+            // X_K[a,c] += v D_bd and X_K[a,d] += v D_bc
+            {
+                double dbd[NB * ND], dbc[NB * NC];
+#pragma unroll
+                for (int ib = 0; ib < NB; ++ib) {
+#pragma unroll
+                    for (int id = 0; id < ND; ++id) dbd[ib * ND + id] = a.Ds[(size_t)(ob + ib) * n + od + id];
+#pragma unroll
+                    for (int ic = 0; ic < NC; ++ic) dbc[ib * NC + ic] = a.Ds[(size_t)(ob + ib) * n + oc + ic];
+                }
+#pragma unroll
+                for (int ia = 0; ia < NA; ++ia) {
+#pragma unroll
+                    for (int ic = 0; ic < NC; ++ic) {
+                        double s = 0.0;
+#pragma unroll
+                        for (int ib = 0; ib < NB; ++ib)
+#pragma unroll
+                            for (int id = 0; id < ND; ++id)
+                                s += acc[((ia * NB + ib) * NC + ic) * ND + id] * dbd[ib * ND + id];
+                        atomic_add(&a.XK[(size_t)(oa + ia) * n + oc + ic], s);
+                    }
+#pragma unroll
+                    for (int id = 0; id < ND; ++id) {
+                        double s = 0.0;
+#pragma unroll
+                        for (int ib = 0; ib < NB; ++ib)
+#pragma unroll
+                            for (int ic = 0; ic < NC; ++ic)
+                                s += acc[((ia * NB + ib) * NC + ic) * ND + id] * dbc[ib * NC + ic];
+                        atomic_add(&a.XK[(size_t)(oa + ia) * n + od + id], s);
+                    }
+                }
+            }
+            // X_K[b,c] += v D_ad and X_K[b,d] += v D_ac
+            {
+                double dad[NA * ND], dac[NA * NC];
+#pragma unroll
+                for (int ia = 0; ia < NA; ++ia) {
+#pragma unroll
+                    for (int id = 0; id < ND; ++id) dad[ia * ND + id] = a.Ds[(size_t)(oa + ia) * n + od + id];
+#pragma unroll
+                    for (int ic = 0; ic < NC; ++ic) dac[ia * NC + ic] = a.Ds[(size_t)(oa + ia) * n + oc + ic];
+                }
+#pragma unroll
+                for (int ib = 0; ib < NB; ++ib) {
+#pragma unroll
+                    for (int ic = 0; ic < NC; ++ic) {
+                        double s = 0.0;
+#pragma unroll
+                        for (int ia = 0; ia < NA; ++ia)
+#pragma unroll
+                            for (int id = 0; id < ND; ++id)
+                                s += acc[((ia * NB + ib) * NC + ic) * ND + id] * dad[ia * ND + id];
+                        atomic_add(&a.XK[(size_t)(ob + ib) * n + oc + ic], s);
+                    }
+#pragma unroll
+                    for (int id = 0; id < ND; ++id) {
+                        double s = 0.0;
+#pragma unroll
+                        for (int ia = 0; ia < NA; ++ia)
+#pragma unroll
+                            for (int ic = 0; ic < NC; ++ic)
+                                s += acc[((ia * NB + ib) * NC + ic) * ND + id] * dac[ia * NC + ic];
+                        atomic_add(&a.XK[(size_t)(ob + ib) * n + od + id], s);
+                    }
+                }
+            }
+        }
+        // all lanes (active or not) take part in the wave reduction of X_J[a,b]
+#pragma unroll
+        for (int ab = 0; ab < NA * NB; ++ab) {
+            const double s = wave_sum(jab[ab]);
+            if (lane == 0) atomic_add(&a.XJ[(size_t)(oa + ab / NB) * n + ob + ab % NB], 2.0 * s);
+        }
+    }
+    if (lane == 0 && cq) {
+        atomicAdd(&a.counters[0], cq);
+        atomicAdd(&a.counters[1], cp);
+    }
+}
+
+// ---------------------------------------------------------------- wpq ----
+// One wave per contracted quartet; lane i owns bra components i, i+64, ...
+// (each with every ket component).  Kets of a tile are visited in turn.
+template <int LA, int LB, int LC, int LD>
+__global__ void __launch_bounds__(FK_BLOCK) k_jk_wpq(FkJKArgs a)
+{
+    using Q = fk::QClass<LA, LB, LC, LD>;
+    constexpr int NB = Q::NB, NC = Q::NC, ND = Q::ND;
+    constexpr int NAB = Q::NA * Q::NB, NCD = NC * ND;
+    constexpr int ITEMS = (NAB + 63) / 64;
+    __shared__ double s_tab[rys_lds_size(Q::NR)];
+    load_table<Q::NR>(s_tab, a.rys_tab);
+
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int nwt = gridDim.x * FK_WAVES;
+    const int n = a.nbf, ns = a.nshell;
+    unsigned long long cq = 0, cp = 0;
+
+    int iax[ITEMS][3], ibx[ITEMS][3], iab[ITEMS];
+    bool ival[ITEMS];
+#pragma unroll
+    for (int k = 0; k < ITEMS; ++k) {
+        const int it = lane + 64 * k;
+        ival[k] = it < NAB;
+        const int ia = ival[k] ? it / NB : 0, ib = ival[k] ? it % NB : 0;
+        iab[k] = ia * NB + ib;
+        iax[k][0] = fk::kCart.x[LA][ia]; iax[k][1] = fk::kCart.y[LA][ia]; iax[k][2] = fk::kCart.z[LA][ia];
+        ibx[k][0] = fk::kCart.x[LB][ib]; ibx[k][1] = fk::kCart.y[LB][ib]; ibx[k][2] = fk::kCart.z[LB][ib];
+    }
+
+    for (int t = blockIdx.x * FK_WAVES + wave; t < a.ntiles; t += nwt) {
+        const FkTile tile = a.tiles[t];
+        const int bra = tile.bra;
+        const int sa = a.pair_sa[bra], sb = a.pair_sb[bra];
+        const int bpo = a.pair_ppoff[bra], bnp = a.pair_npp[bra];
+        const double AB[3] = {a.pair_AB[3 * bra], a.pair_AB[3 * bra + 1], a.pair_AB[3 * bra + 2]};
+        const double Gab = a.pair_G[bra];
+        const int oa = a.sh_bf[sa], ob = a.sh_bf[sb];
+        for (int k = 0; k < tile.ket_count; ++k) {
+            const int ket = a.ket_list[tile.ket_begin + k];
+            const int sc = a.pair_sa[ket], sd = a.pair_sb[ket];
+            if (a.dscreen && Gab * a.pair_G[ket] * dmax6(a.Dsh, ns, sa, sb, sc, sd) < a.tau) continue;
+            const int kpo = a.pair_ppoff[ket], knp = a.pair_npp[ket];
+            const double CD[3] = {a.pair_AB[3 * ket], a.pair_AB[3 * ket + 1], a.pair_AB[3 * ket + 2]};
+            cq += 1;
+            cp += (unsigned long long)bnp * knp;
+            double acc[ITEMS][NCD];
+#pragma unroll
+            for (int it = 0; it < ITEMS; ++it)
+#pragma unroll
+                for (int o = 0; o < NCD; ++o) acc[it][o] = 0.0;
+            for (int i = 0; i < bnp; ++i) {
+                const fk::PrimPair p = load_pp(a.pp, bpo + i);
+                for (int j = 0; j < knp; ++j) {
+                    const fk::PrimPair q = load_pp(a.pp, kpo + j);
+#pragma unroll
+                    for (int it = 0; it < ITEMS; ++it)
+                        if (ival[it]) fk::rys_prim_bra_comp<LA, LB, LC, LD>(s_tab, p, q, AB, CD, iax[it], ibx[it], acc[it]);
+                }
+            }
+            const double fac = (sa == sb ? 0.5 : 1.0) * (sc == sd ? 0.5 : 1.0) *
+                               (((tile.flags & 1) && ket == bra) ? 0.5 : 1.0);
+            const int oc = a.sh_bf[sc], od = a.sh_bf[sd];
+            double jcd[NCD];
+#pragma unroll
+            for (int o = 0; o < NCD; ++o) jcd[o] = 0.0;
+#pragma unroll
+            for (int it = 0; it < ITEMS; ++it) {
+                if (!ival[it]) continue;
+                const int ia = iab[it] / NB, ib = iab[it] % NB;
+                double *v = acc[it];
+#pragma unroll
+                for (int o = 0; o < NCD; ++o) v[o] *= fac;
+                const double dab = a.Ds[(size_t)(oa + ia) * n + ob + ib];
+                double sj = 0.0;
+#pragma unroll
+                for (int ic = 0; ic < NC; ++ic)
+#pragma unroll
+                    for (int id = 0; id < ND; ++id) {
+                        sj += v[ic * ND + id] * a.Ds[(size_t)(oc + ic) * n + od + id];
+                        jcd[ic * ND + id] += v[ic * ND + id] * dab;
+                    }
+                atomic_add(&a.XJ[(size_t)(oa + ia) * n + ob + ib], 2.0 * sj);
+#pragma unroll
+                for (int ic = 0; ic < NC; ++ic) {
+                    double s1 = 0.0, s2 = 0.0;
+#pragma unroll
+                    for (int id = 0; id < ND; ++id) {
+                        s1 += v[ic * ND + id] * a.Ds[(size_t)(ob + ib) * n + od + id];
+                        s2 += v[ic * ND + id] * a.Ds[(size_t)(oa + ia) * n + od + id];
+                    }
+                    atomic_add(&a.XK[(size_t)(oa + ia) * n + oc + ic], s1);
+                    atomic_add(&a.XK[(size_t)(ob + ib) * n + oc + ic], s2);
+                }
+#pragma unroll
+                for (int id = 0; id < ND; ++id) {
+                    double s1 = 0.0, s2 = 0.0;
+#pragma unroll
+                    for (int ic = 0; ic < NC; ++ic) {
+                        s1 += v[ic * ND + id] * a.Ds[(size_t)(ob + ib) * n + oc + ic];
+                        s2 += v[ic * ND + id] * a.Ds[(size_t)(oa + ia) * n + oc + ic];
+                    }
+                    atomic_add(&a.XK[(size_t)(oa + ia) * n + od + id], s1);
+                    atomic_add(&a.XK[(size_t)(ob + ib) * n + od + id], s2);
+                }
+            }
+#pragma unroll
+            for (int o = 0; o < NCD; ++o) {
+                const double s = wave_sum(jcd[o]);
+                if (lane == 0) atomic_add(&a.XJ[(size_t)(oc + o / ND) * n + od + o % ND], 2.0 * s);
+            }
+        }
+    }
+    if (lane == 0 && cq) {
+        atomicAdd(&a.counters[0], cq);
+        atomicAdd(&a.counters[1], cp);
+    }
+}
+
+// -------------------------------------------------------------- debug ----
+// Raw contracted integrals of listed quartets (canonical orientation), one
+// lane per quartet (small classes) or one wave per quartet (large classes).
+template <int LA, int LB, int LC, int LD>
+__global__ void __launch_bounds__(FK_BLOCK) k_debug_lpq(FkDebugArgs a)
+{
+    using Q = fk::QClass<LA, LB, LC, LD>;
+    __shared__ double s_tab[rys_lds_size(Q::NR)];
+    load_table<Q::NR>(s_tab, a.rys_tab);
+    const int q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= a.nq) return;
+    const int bra = a.quartets[q].x, ket = a.quartets[q].y;
+    const double AB[3] = {a.pair_AB[3 * bra], a.pair_AB[3 * bra + 1], a.pair_AB[3 * bra + 2]};
+    const double CD[3] = {a.pair_AB[3 * ket], a.pair_AB[3 * ket + 1], a.pair_AB[3 * ket + 2]};
+    double acc[Q::NOUT];
+#pragma unroll
+    for (int o = 0; o < Q::NOUT; ++o) acc[o] = 0.0;
+    for (int i = 0; i < a.pair_npp[bra]; ++i) {
+        const fk::PrimPair p = load_pp(a.pp, a.pair_ppoff[bra] + i);
+        for (int j = 0; j < a.pair_npp[ket]; ++j)
+            fk::rys_prim_all<LA, LB, LC, LD>(s_tab, p, load_pp(a.pp, a.pair_ppoff[ket] + j), AB, CD, acc);
+    }
+#pragma unroll
+    for (int o = 0; o < Q::NOUT; ++o) a.out[(size_t)q * Q::NOUT + o] = acc[o];
+}
+
+template <int LA, int LB, int LC, int LD>
+__global__ void __launch_bounds__(FK_BLOCK) k_debug_wpq(FkDebugArgs a)
+{
+    using Q = fk::QClass<LA, LB, LC, LD>;
+    constexpr int NB = Q::NB, NAB = Q::NA * Q::NB, NCD = Q::NC * Q::ND;
+    __shared__ double s_tab[rys_lds_size(Q::NR)];
+    load_table<Q::NR>(s_tab, a.rys_tab);
+    const int lane = threadIdx.x & 63;
+    const int q = blockIdx.x * FK_WAVES + (threadIdx.x >> 6);
+    if (q >= a.nq) return;
+    const int bra = a.quartets[q].x, ket = a.quartets[q].y;
+    const double AB[3] = {a.pair_AB[3 * bra], a.pair_AB[3 * bra + 1], a.pair_AB[3 * bra + 2]};
+    const double CD[3] = {a.pair_AB[3 * ket], a.pair_AB[3 * ket + 1], a.pair_AB[3 * ket + 2]};
+    for (int it = lane; it < NAB; it += 64) {
+        const int ia = it / NB, ib = it % NB;
+        const int ax[3] = {fk::kCart.x[LA][ia], fk::kCart.y[LA][ia], fk::kCart.z[LA][ia]};
+        const int bx[3] = {fk::kCart.x[LB][ib], fk::kCart.y[LB][ib], fk::kCart.z[LB][ib]};
+        double acc[NCD];
+#pragma unroll
+        for (int o = 0; o < NCD; ++o) acc[o] = 0.0;
+        for (int i = 0; i < a.pair_npp[bra]; ++i) {
+            const fk::PrimPair p = load_pp(a.pp, a.pair_ppoff[bra] + i);
+            for (int j = 0; j < a.pair_npp[ket]; ++j)
+                fk::rys_prim_bra_comp<LA, LB, LC, LD>(s_tab, p, load_pp(a.pp, a.pair_ppoff[ket] + j), AB, CD, ax, bx,
+                                                      acc);
+        }
+#pragma unroll
+        for (int o = 0; o < NCD; ++o) a.out[(size_t)q * Q::NOUT + it * NCD + o] = acc[o];
+    }
+}
+
+// --------------------------------------------------------- dispatch ------
+template <int P, int Q>
+struct Disp {
+    static constexpr int LA = pair_la(P), LB = pair_lb(P), LC = pair_la(Q), LD = pair_lb(Q);
+    static constexpr bool BUILT = LA <= FK_BUILD_MAXL;
+    static constexpr bool WPQ = use_wpq<LA, LB, LC, LD>();
+    static void info(FkClassInfo *i)
+    {
+        using C = fk::QClass<LA, LB, LC, LD>;
+        i->la = LA; i->lb = LB; i->lc = LC; i->ld = LD;
+        i->nroot = C::NR; i->nout = C::NOUT;
+        i->wave_per_quartet = WPQ ? 1 : 0;
+        i->flops_prim = fk::flops_prim(LA, LB, LC, LD);
+        i->flops_quartet = fk::flops_digest(LA, LB, LC, LD);
+    }
+    static const void *jk_kernel()
+    {
+        if constexpr (!BUILT) return nullptr;
+        else if constexpr (WPQ) return (const void *)&k_jk_wpq<LA, LB, LC, LD>;
+        else return (const void *)&k_jk_lpq<LA, LB, LC, LD>;
+    }
+    static int launch_jk(const FkJKArgs *a, int grid, hipStream_t st)
+    {
+        if constexpr (!BUILT) return -2;
+        else {
+            if constexpr (WPQ) hipLaunchKernelGGL((k_jk_wpq<LA, LB, LC, LD>), dim3(grid), dim3(FK_BLOCK), 0, st, *a);
+            else hipLaunchKernelGGL((k_jk_lpq<LA, LB, LC, LD>), dim3(grid), dim3(FK_BLOCK), 0, st, *a);
+            return hipGetLastError() == hipSuccess ? 0 : -3;
+        }
+    }
+    static int launch_debug(const FkDebugArgs *a, hipStream_t st)
+    {
+        if constexpr (!BUILT) return -2;
+        else {
+            if (a->nq <= 0) return 0;
+            if constexpr (WPQ) {
+                const int grid = (a->nq + FK_WAVES - 1) / FK_WAVES;
+                hipLaunchKernelGGL((k_debug_wpq<LA, LB, LC, LD>), dim3(grid), dim3(FK_BLOCK), 0, st, *a);
+            } else {
+                const int grid = (a->nq + FK_BLOCK - 1) / FK_BLOCK;
+                hipLaunchKernelGGL((k_debug_lpq<LA, LB, LC, LD>), dim3(grid), dim3(FK_BLOCK), 0, st, *a);
+            }
+            return hipGetLastError() == hipSuccess ? 0 : -3;
+        }
+    }
+    static int debug_host(const int *ppoff, const int *npp, const double *AB, const double *pp, const int *qs,
+                          int nq, double *out)
+    {
+        if constexpr (!BUILT) return -2;
+        else {
+        using C = fk::QClass<LA, LB, LC, LD>;
+        const double *tab = rys_staged_host() + rys_staged_offset(C::NR);
+        auto ld = [&](int idx) {
+            const double *r = pp + (size_t)idx * FK_NPP_REC;
+            fk::PrimPair p;
+            p.zeta = r[0]; p.oo2z = r[1];
+            for (int k = 0; k < 3; ++k) { p.P[k] = r[2 + k]; p.PA[k] = r[5 + k]; }
+            p.K = r[8];
+            return p;
+        };
+        for (int q = 0; q < nq; ++q) {
+            const int bra = qs[2 * q], ket = qs[2 * q + 1];
+            double *o = out + (size_t)q * C::NOUT;
+            for (int x = 0; x < C::NOUT; ++x) o[x] = 0.0;
+            for (int i = 0; i < npp[bra]; ++i)
+                for (int j = 0; j < npp[ket]; ++j) {
+                    const fk::PrimPair p = ld(ppoff[bra] + i), qq = ld(ppoff[ket] + j);
+                    if constexpr (WPQ) {
+                        for (int it = 0; it < C::NA * C::NB; ++it) {
+                            const int ia = it / C::NB, ib = it % C::NB;
+                            const int ax[3] = {fk::kCart.x[LA][ia], fk::kCart.y[LA][ia], fk::kCart.z[LA][ia]};
+                            const int bx[3] = {fk::kCart.x[LB][ib], fk::kCart.y[LB][ib], fk::kCart.z[LB][ib]};
+                            fk::rys_prim_bra_comp<LA, LB, LC, LD>(tab, p, qq, AB + 3 * bra, AB + 3 * ket, ax, bx,
+                                                                  o + it * C::NC * C::ND);
+                        }
+                    } else {
+                        fk::rys_prim_all<LA, LB, LC, LD>(tab, p, qq, AB + 3 * bra, AB + 3 * ket, o);
+                    }
+                }
+        }
+        return 0;
+        }
+    }
+};
+
+
+#define FK_CAT2(a, b, c) a##b##c
+#define FK_CAT(a, b, c) FK_CAT2(a, b, c)
+
+template <int P, int Q = 0>
+int info_q(int q, FkClassInfo *i)
+{
+    if constexpr (Q > P) return -1;
+    else {
+        if (q == Q) { Disp<P, Q>::info(i); return Disp<P, Q>::BUILT ? 0 : -2; }
+        return info_q<P, Q + 1>(q, i);
+    }
+}
+template <int P, int Q = 0>
+int jk_q(int q, const FkJKArgs *a, int grid, hipStream_t st)
+{
+    if constexpr (Q > P) return -1;
+    else return q == Q ? Disp<P, Q>::launch_jk(a, grid, st) : jk_q<P, Q + 1>(q, a, grid, st);
+}
+template <int P, int Q = 0>
+int dbg_q(int q, const FkDebugArgs *a, hipStream_t st)
+{
+    if constexpr (Q > P) return -1;
+    else return q == Q ? Disp<P, Q>::launch_debug(a, st) : dbg_q<P, Q + 1>(q, a, st);
+}
+template <int P, int Q = 0>
+int host_q(int q, const int *o, const int *n, const double *ab, const double *pp, const int *qs, int nq, double *out)
+{
+    if constexpr (Q > P) return -1;
+    else return q == Q ? Disp<P, Q>::debug_host(o, n, ab, pp, qs, nq, out) : host_q<P, Q + 1>(q, o, n, ab, pp, qs, nq, out);
+}
+template <int P, int Q = 0>
+const void *kern_q(int q)
+{
+    if constexpr (Q > P) return nullptr;
+    else return q == Q ? Disp<P, Q>::jk_kernel() : kern_q<P, Q + 1>(q);
+}
+
+}  // namespace
+
+#if FK_ONLY_P >= 0
+// ---- per bra-class translation unit ----
+extern "C" {
+int FK_CAT(fk_kp, FK_ONLY_P, _info)(int Q, FkClassInfo *i) { return info_q<FK_ONLY_P>(Q, i); }
+int FK_CAT(fk_kp, FK_ONLY_P, _jk)(int Q, const FkJKArgs *a, int grid, void *st)
+{
+    return jk_q<FK_ONLY_P>(Q, a, grid, (hipStream_t)st);
+}
+int FK_CAT(fk_kp, FK_ONLY_P, _dbg)(int Q, const FkDebugArgs *a, void *st) { return dbg_q<FK_ONLY_P>(Q, a, (hipStream_t)st); }
+int FK_CAT(fk_kp, FK_ONLY_P, _host)(int Q, const int *o, const int *n, const double *ab, const double *pp,
+                                      const int *qs, int nq, double *out)
+{
+    return host_q<FK_ONLY_P>(Q, o, n, ab, pp, qs, nq, out);
+}
+const void *FK_CAT(fk_kp, FK_ONLY_P, _kern)(int Q) { return kern_q<FK_ONLY_P>(Q); }
+}
+#else
+// ---- common translation unit: small kernels and the dispatch tables ----
+namespace {
+// ------------------------------------------------------ small kernels ----
+__global__ void k_fill(double *p, long long n)
+{
+    long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0.0;
+}
+
+__global__ void k_prep_ds(const double *__restrict D, const double *__restrict s, int n, double *__restrict Ds)
+{
+    long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= (long long)n * n) return;
+    const int r = (int)(i / n), c = (int)(i % n);
+    Ds[i] = s[r] * s[c] * D[i];
+}
+
+__global__ void k_prep_dsh(const double *__restrict D, const int *__restrict sh_bf, int ns, int n,
+                           double *__restrict Dsh)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= ns * ns) return;
+    const int A = i / ns, B = i % ns;
+    double m = 0.0;
+    for (int r = sh_bf[A]; r < sh_bf[A + 1]; ++r)
+        for (int c = sh_bf[B]; c < sh_bf[B + 1]; ++c) m = fmax(m, fabs(D[(size_t)r * n + c]));
+    Dsh[i] = m;
+}
+
+__global__ void k_finalize(const double *__restrict XJ, const double *__restrict XK, const double *__restrict s,
+                           int n, double *__restrict J, double *__restrict K)
+{
+    long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= (long long)n * n) return;
+    const int r = (int)(i / n), c = (int)(i % n);
+    const long long t = (long long)c * n + r;
+    const double f = s[r] * s[c];
+    J[i] = f * (XJ[i] + XJ[t]);
+    K[i] = f * (XK[i] + XK[t]);
+}
+
+
+}  // namespace
+
+#define FK_DECL_P(P)                                                                                         \
+    int fk_kp##P##_info(int, FkClassInfo *);                                                                 \
+    int fk_kp##P##_jk(int, const FkJKArgs *, int, void *);                                                   \
+    int fk_kp##P##_dbg(int, const FkDebugArgs *, void *);                                                    \
+    int fk_kp##P##_host(int, const int *, const int *, const double *, const double *, const int *, int,    \
+                        double *);                                                                           \
+    const void *fk_kp##P##_kern(int);
+extern "C" {
+FK_DECL_P(0) FK_DECL_P(1) FK_DECL_P(2) FK_DECL_P(3) FK_DECL_P(4)
+FK_DECL_P(5) FK_DECL_P(6) FK_DECL_P(7) FK_DECL_P(8) FK_DECL_P(9)
+}
+#define FK_SWITCH_P(P, call)                                                                            \
+    switch (P) {                                                                                        \
+    case 0: return fk_kp0_##call; case 1: return fk_kp1_##call; case 2: return fk_kp2_##call;        \
+    case 3: return fk_kp3_##call; case 4: return fk_kp4_##call; case 5: return fk_kp5_##call;        \
+    case 6: return fk_kp6_##call; case 7: return fk_kp7_##call; case 8: return fk_kp8_##call;        \
+    case 9: return fk_kp9_##call; default: break;                                                       \
+    }
+
+extern "C" {
+
+int fk_kernels_class_info(int P, int Q, FkClassInfo *info)
+{
+    FK_SWITCH_P(P, info(Q, info))
+    return -1;
+}
+
+int fk_kernels_launch_jk(int P, int Q, const FkJKArgs *args, int grid, void *stream)
+{
+    FK_SWITCH_P(P, jk(Q, args, grid, stream))
+    return -1;
+}
+
+int fk_kernels_launch_debug(int P, int Q, const FkDebugArgs *args, void *stream)
+{
+    FK_SWITCH_P(P, dbg(Q, args, stream))
+    return -1;
+}
+
+int fk_kernels_debug_host(int P, int Q, const int *pair_ppoff, const int *pair_npp, const double *pair_AB,
+                          const double *pp, const int *quartets, int nq, double *out)
+{
+    FK_SWITCH_P(P, host(Q, pair_ppoff, pair_npp, pair_AB, pp, quartets, nq, out))
+    return -1;
+}
+
+static const void *kern_of(int P, int Q)
+{
+    FK_SWITCH_P(P, kern(Q))
+    return nullptr;
+}
+
+int fk_kernels_max_blocks(int P, int Q, int *blocks_per_cu)
+{
+    const void *k = kern_of(P, Q);
+    if (!k) return -2;
+    int nb = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k, FK_BLOCK, 0) != hipSuccess) return -3;
+    *blocks_per_cu = nb;
+    return 0;
+}
+
+int fk_kernels_launch_prep(const double *D, const int *sh_bf, const double *bf_scale, int nshell, int nbf,
+                           double *Ds, double *Dsh, void *stream)
+{
+    hipStream_t st = (hipStream_t)stream;
+    const long long nn = (long long)nbf * nbf;
+    hipLaunchKernelGGL(k_prep_ds, dim3((unsigned)((nn + 255) / 256)), dim3(256), 0, st, D, bf_scale, nbf, Ds);
+    const int ss = nshell * nshell;
+    hipLaunchKernelGGL(k_prep_dsh, dim3((ss + 255) / 256), dim3(256), 0, st, D, sh_bf, nshell, nbf, Dsh);
+    return hipGetLastError() == hipSuccess ? 0 : -3;
+}
+
+int fk_kernels_launch_finalize(const double *XJ, const double *XK, const double *bf_scale, int nbf, double *J,
+                               double *K, void *stream)
+{
+    const long long nn = (long long)nbf * nbf;
+    hipLaunchKernelGGL(k_finalize, dim3((unsigned)((nn + 255) / 256)), dim3(256), 0, (hipStream_t)stream, XJ, XK,
+                       bf_scale, nbf, J, K);
+    return hipGetLastError() == hipSuccess ? 0 : -3;
+}
+
+int fk_kernels_launch_fill(double *p, long long n, void *stream)
+{
+    if (n <= 0) return 0;
+    hipLaunchKernelGGL(k_fill, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, (hipStream_t)stream, p, n);
+    return hipGetLastError() == hipSuccess ? 0 : -3;
+}
+
+}  // extern "C"
+#endif

@@ -1,0 +1,153 @@
+"""Host-side checks of libfockjk that need no GPU: exported symbols, the Rys
+tables, the per-quartet integral code evaluated on the host, one-electron
+integrals, screening lists and argument validation."""
+import math
+import os
+import re
+
+import mpmath
+import numpy as np
+import pytest
+
+import oracle
+import paper_2407_21445_amd as fk
+from synth import workloads as wl
+from test_oracle import _rand_sys
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def test_exports_every_declared_symbol():
+    hdr = open(os.path.join(ROOT, "include", "fockjk.h")).read()
+    names = set(re.findall(r"^\s*(?:int|void|const char \*)\s*(fk_\w+)\s*\(", hdr, re.M))
+    assert len(names) >= 12
+    import ctypes
+    lib = ctypes.CDLL(fk.LIB_PATH)
+    for n in sorted(names):
+        assert hasattr(lib, n), n
+    assert names == set(fk.EXPORTS)
+
+
+@pytest.mark.parametrize("n", range(1, 8))
+def test_rys_moments(n):
+    """sum_i w_i u_i^k = F_k(T) for k < 2n (the defining property of the rule),
+    against 30-digit Boys values, across the table, its interval edges and the
+    asymptotic region."""
+    mpmath.mp.dps = 30
+    Ts = [0.0, 1e-9, 0.25, 0.5, 3.7, 15.999, 16.0, 16.001, 29.3, 47.0, 63.999, 64.0, 64.5, 90.0, 400.0]
+    for T in Ts:
+        u, w = fk.rys_host(n, T)
+        assert np.all(u > 0) and np.all(u < 1) and np.all(w > 0)
+        for k in range(2 * n):
+            if T == 0:
+                ref = 1.0 / (2 * k + 1)
+            else:
+                ref = float(mpmath.gammainc(k + 0.5, 0, T) / (2 * mpmath.mpf(T) ** (k + 0.5)))
+            got = float(np.sum(w * u ** k))
+            assert abs(got - ref) <= 1e-13 * ref + 1e-300, (n, T, k, got, ref)
+
+
+def test_rys_n1_closed_form():
+    for T in [0.0, 0.3, 2.0, 11.0, 40.0, 70.0]:
+        F = oracle.boys(1, T)
+        u, w = fk.rys_host(1, T)
+        assert w[0] == pytest.approx(F[0], rel=1e-14)
+        assert u[0] == pytest.approx(F[1] / F[0], rel=1e-13)
+
+
+def test_host_eri_matches_oracle_all_classes():
+    """The production per-quartet Rys code (run on the host) against the
+    oracle's McMurchie-Davidson integrals, random shells up to (ff|ff)."""
+    s = _rand_sys(21, lmax=3, natom=4, kmax=2)
+    c = fk.FockJK(device=-1).set_system(s).build_quartets(tau=0.0)
+    rng = np.random.default_rng(4)
+    qs = [rng.integers(0, s["nshell"], size=4) for _ in range(60)]
+    qs += [[3, 7, 11, 15], [2, 6, 10, 14], [1, 5, 9, 13], [0, 4, 8, 12], [3, 3, 3, 3], [7, 3, 3, 7]]
+    res = c.debug_eri(qs, on_device=False)
+    for q, a in zip(qs, res):
+        b = oracle.eri_quartet(s, *q)
+        assert np.max(np.abs(a - b)) <= 1e-12 * max(1.0, np.max(np.abs(b))), q
+
+
+def test_one_electron_matches_oracle():
+    s = _rand_sys(22, lmax=3, natom=3, kmax=3)
+    s["charge"] = 1  # three H nuclei: keep the electron count even
+    c = fk.FockJK(device=-1).set_system(s)
+    S, T, V, en = c.one_electron()
+    So, To, Vo = oracle.oneel(s)
+    assert np.max(np.abs(S - So)) < 1e-13
+    assert np.max(np.abs(T - To)) < 1e-12
+    assert np.max(np.abs(V - Vo)) < 1e-11
+    assert en == pytest.approx(oracle.enuc(s), rel=1e-14)
+
+
+def _schwarz_oracle(s):
+    n = s["nshell"]
+    G = {}
+    for a in range(n):
+        for b in range(a + 1):
+            v = oracle.eri_quartet(s, a, b, a, b)
+            G[(a, b)] = math.sqrt(float(np.max(np.abs(np.einsum("ijij->ij", v)))))
+    return G
+
+
+@pytest.mark.parametrize("tau", [0.0, 1e-10, 1e-6, 1e-3])
+def test_schwarz_quartet_count(tau):
+    """Unique quartets kept by the ket-prefix lists equal the brute-force count
+    of unordered pair pairs with G_ab G_cd >= tau."""
+    s = wl.water4_sto3g()
+    c = fk.FockJK(device=-1).set_system(s).build_quartets(tau=tau)
+    G = np.array(list(_schwarz_oracle(s).values()))
+    npair = len(G)
+    assert c.info()["npair"] == npair == s["nshell"] * (s["nshell"] + 1) // 2
+    prod = np.outer(G, G)
+    iu = np.tril_indices(npair)
+    ref = int(np.sum(prod[iu] >= tau)) if tau > 0 else len(iu[0])
+    got = c.info()["nquartet_schwarz"]
+    # pairs whose product sits within rounding of tau may fall either side
+    near = int(np.sum(np.abs(prod[iu] - tau) <= 1e-12 * tau)) if tau > 0 else 0
+    assert abs(got - ref) <= near
+    if tau == 0:
+        assert got == 22155
+
+
+def test_argument_validation():
+    s = wl.h2_sto3g()
+    c = fk.FockJK(device=-1)
+    Z = np.array([1, 1], dtype=np.int32)
+    xyz = np.zeros(6)
+    P = fk._ptr
+    with pytest.raises(fk.FockJKError) as e:
+        c._check(fk._lib.fk_set_geometry(c._ctx, 0, P(Z), P(xyz), 0))
+    assert e.value.code == fk.FK_ERR_ARG
+    with pytest.raises(fk.FockJKError) as e:  # odd electron count
+        c._check(fk._lib.fk_set_geometry(c._ctx, 2, P(Z), P(xyz), 1))
+    assert e.value.code == fk.FK_ERR_ARG
+    with pytest.raises(fk.FockJKError) as e:  # basis before geometry
+        c._check(fk._lib.fk_set_basis(c._ctx, 1, P(np.zeros(1, np.int32)), P(np.zeros(1, np.int32)),
+                                      P(np.ones(1, np.int32)), P(np.ones(1)), P(np.ones(1))))
+    assert e.value.code == fk.FK_ERR_STATE
+    c.set_system(s)
+    bad = dict(s)
+    bad["sh_l"] = np.array([4, 0], dtype=np.int32)
+    with pytest.raises(fk.FockJKError) as e:
+        c.set_system(bad)
+    assert e.value.code == fk.FK_ERR_UNSUPPORTED
+    bad = dict(s)
+    bad["exps"] = s["exps"].copy()
+    bad["exps"][1] = -1.0
+    with pytest.raises(fk.FockJKError) as e:
+        c.set_system(bad)
+    assert e.value.code == fk.FK_ERR_ARG
+    bad = dict(s)
+    bad["sh_nprim"] = np.array([10, 3], dtype=np.int32)
+    with pytest.raises(fk.FockJKError):
+        c.set_system(bad)
+    c.set_system(s)
+    with pytest.raises(fk.FockJKError) as e:  # J/K before the quartet lists
+        c.build_jk(np.eye(2))
+    assert e.value.code == fk.FK_ERR_STATE
+    c.build_quartets(tau=0.0)
+    with pytest.raises(fk.FockJKError) as e:  # host-only context has no device
+        c.build_jk(np.eye(2))
+    assert e.value.code == fk.FK_ERR_STATE
