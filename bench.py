@@ -1,0 +1,160 @@
+#!/usr/bin/env python
+"""J+K Fock-build throughput on one MI355X.
+
+A step is one full pass of the J/K hot path for one density: density
+preprocessing (scaled D, shell-block maxima), every quartet-class Rys ERI +
+digestion kernel, and the symmetrisation into J and K, on resident device
+buffers.  Workload (default): all-trans C20H42 with 0.02 A seeded jitter in the
+6-31G*-type basis (384 Cartesian functions, s/p/d), Schwarz threshold 1e-10
+with the per-quartet density screen, at the core-Hamiltonian guess density.
+
+Prints one JSON line (see the fields below).  --gpus above 1 is refused: the
+build runs on one GPU.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, HERE)
+
+METRIC = "J+K Fock builds/s & ERI quartets/s, FP64 vs mixed @1e-6 Eh; SCF iters"
+PEAK_FP64_VALU = 78.6  # TFLOP/s, MI355X dense FP64 vector
+
+
+def _workload(name):
+    from synth import workloads as wl
+    if name == "c20h42":
+        return wl.c20h42_631gs(), "C20H42 all-trans (0.02 A jitter), 6-31G*-type, 384 Cartesian bf, tau=1e-10"
+    if name == "water4":
+        return wl.water4_sto3g(), "(H2O)4 STO-3G-type, 28 bf, tau=1e-10"
+    if name == "water64":
+        return wl.water64_ccpvdz(), "(H2O)64 1.0 g/cm3, cc-pVDZ-type, 1600 Cartesian bf, tau=1e-10"
+    raise SystemExit(f"unknown workload {name}")
+
+
+def _core_density(S, h, nocc):
+    w, U = np.linalg.eigh(S)
+    keep = w > 1e-8
+    X = U[:, keep] / np.sqrt(w[keep])
+    e, Cp = np.linalg.eigh(X.T @ h @ X)
+    C = X @ Cp[:, :nocc]
+    return 2.0 * C @ C.T
+
+
+def cpu_baseline(sys_, D, target_s=15.0):
+    """The oracle (test infrastructure) timed on host cores over a bounded
+    sample of the same workload: whole shell blocks J[A,B] by literal sums
+    (every (AB|CD) over all C, D), scaled to one full unscreened oracle build
+    (one evaluation per unique shell quartet)."""
+    import oracle
+    nthreads = min(16, os.cpu_count() or 1)
+    ns = sys_["nshell"]
+    rng = np.random.default_rng(99)
+    done_q, t_used, nblk = 0, 0.0, 0
+    while t_used < target_s and nblk < 4096:
+        a, b = (int(x) for x in rng.integers(0, ns, size=2))
+        t0 = time.perf_counter()
+        oracle.jk_blocks(sys_, D, [(a, b)], [], nthreads=nthreads)
+        t_used += time.perf_counter() - t0
+        done_q += ns * ns
+        nblk += 1
+    npair = ns * (ns + 1) // 2
+    unique_q = npair * (npair + 1) // 2
+    per_q = t_used / done_q
+    est_build_s = per_q * unique_q
+    return {"value": 1.0 / est_build_s, "unit": "builds/s", "cores": nthreads, "kind": "oracle",
+            "sample": f"{nblk} random J shell blocks ({done_q} shell quartets, {t_used:.1f} s) scaled to one "
+                      f"unscreened build of {unique_q} unique shell quartets",
+            "quartets_per_s": 1.0 / per_q, "est_build_s": est_build_s}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="c20h42")
+    ap.add_argument("--tau", type=float, default=1e-10)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported", file=sys.stderr)
+        return 2
+    import torch
+    import paper_2407_21445_amd as fk
+
+    sys_, desc = _workload(args.workload)
+    ctx = fk.FockJK(0).set_system(sys_).build_quartets(tau=args.tau)
+    info = ctx.info()
+    S, T, V, _ = ctx.one_electron()
+    D = _core_density(S, T + V, sys_["nelec"] // 2)
+    dev = torch.device("cuda:0")
+    Dd = torch.tensor(D, dtype=torch.float64, device=dev)
+    J = torch.empty_like(Dd)
+    K = torch.empty_like(Dd)
+    stream = torch.cuda.current_stream(dev)
+
+    for _ in range(args.warmup):
+        ctx.build_jk(Dd, J, K, stream=stream)
+    torch.cuda.synchronize()
+    st = ctx.stats()
+
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    w0 = time.perf_counter()
+    e0.record(stream)
+    for _ in range(args.steps):
+        ctx.build_jk(Dd, J, K, stream=stream)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - w0
+    ms = e0.elapsed_time(e1) / args.steps
+
+    # per-class kernel times (HIP events around each class launch on the same stream)
+    reps = 3
+    acc = None
+    for _ in range(reps):
+        ctx.build_jk(Dd, J, K, stream=stream, time_classes=True)
+        s2 = ctx.stats()
+        t = np.array([c["ms"] for c in s2["classes"]])
+        acc = t if acc is None else acc + t
+    cls_ms = acc / reps
+    i = int(np.argmax(cls_ms))
+    c = s2["classes"][i]
+    cflops = c["prim_quartets"] * c["flops_per_prim"] + c["quartets"] * c["flops_per_quartet"]
+    achieved = cflops / (cls_ms[i] * 1e-3) / 1e12
+    lname = "spdf"
+    cname = "({}{}|{}{})".format(*(lname[x] for x in c["class"]))
+    out = {
+        "metric": METRIC, "value": 1000.0 / ms, "unit": "builds/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": desc, "nbf": info["nbf"], "nshell": info["nshell"], "tau": args.tau,
+                   "density": "core-Hamiltonian guess", "precision": "fp64"},
+        "quartets_per_s": st["quartets"] / (ms * 1e-3),
+        "prim_quartets_per_s": st["prim_quartets"] / (ms * 1e-3),
+        "quartets_per_build": st["quartets"], "schwarz_quartets": info["nquartet_schwarz"],
+        "flops_per_build": st["flops_total"], "tflops_build": st["flops_total"] / (ms * 1e-3) / 1e12,
+        "wall_s_timed": wall,
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP64_VALU, "unit": "TFLOP/s",
+                     "frac": achieved / PEAK_FP64_VALU, "traffic": None,
+                     "kernel": f"J/K class {cname}", "kernel_ms": float(cls_ms[i]),
+                     "class_share": float(cls_ms[i] / cls_ms.sum())},
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(sys_, D, args.cpu_seconds)
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -65,6 +65,7 @@ typedef enum {
 /* flags for fk_build_jk */
 #define FK_DEVICE_PTRS 1u     /* D, J, K are device pointers (else host pointers) */
 #define FK_SYNC 2u            /* synchronise the stream before returning */
+#define FK_TIME_CLASSES 4u    /* record HIP events around each class kernel (read by fk_stats) */
 
 /* Screening options (paper: Cauchy-Schwarz screening, eq. cauchy-schwarz, and
  * the density screen G_ab G_cd D_max < tau of the Brc21 scheme). */
@@ -99,6 +100,7 @@ typedef struct {
     double  flops_per_prim[FK_MAX_QCLASS];/* algorithmic flops per primitive quartet */
     double  flops_per_quartet[FK_MAX_QCLASS]; /* per contracted quartet (digestion) */
     double  flops_total;                  /* algorithmic flops of the build */
+    double  class_ms[FK_MAX_QCLASS];      /* kernel time per class (FK_TIME_CLASSES builds), else 0 */
 } fk_stats_t;
 
 /* ---- context ---------------------------------------------------------- */

@@ -21,7 +21,7 @@ if not os.path.exists(LIB_PATH):
 _lib = ctypes.CDLL(LIB_PATH)
 
 FK_OK, FK_ERR_ARG, FK_ERR_UNSUPPORTED, FK_ERR_HIP, FK_ERR_OOM, FK_ERR_NOT_CONVERGED, FK_ERR_STATE = 0, -1, -2, -3, -4, -5, -6
-FK_DEVICE_PTRS, FK_SYNC = 1, 2
+FK_DEVICE_PTRS, FK_SYNC, FK_TIME_CLASSES = 1, 2, 4
 FK_MAX_QCLASS = 55
 MAX_L, MAX_K = 3, 9
 
@@ -45,7 +45,8 @@ class Stats(ctypes.Structure):
     _fields_ = [("nclass", ctypes.c_int), ("la", ctypes.c_int * _Q), ("lb", ctypes.c_int * _Q),
                 ("lc", ctypes.c_int * _Q), ("ld", ctypes.c_int * _Q), ("quartets", ctypes.c_int64 * _Q),
                 ("prim_quartets", ctypes.c_int64 * _Q), ("flops_per_prim", ctypes.c_double * _Q),
-                ("flops_per_quartet", ctypes.c_double * _Q), ("flops_total", ctypes.c_double)]
+                ("flops_per_quartet", ctypes.c_double * _Q), ("flops_total", ctypes.c_double),
+                ("class_ms", ctypes.c_double * _Q)]
 
 
 class ScfOpts(ctypes.Structure):
@@ -161,7 +162,7 @@ class FockJK:
         return {k: getattr(i, k) for k, _ in Info._fields_}
 
     # ---- hot path ----
-    def build_jk(self, D, J=None, K=None, stream=None, sync=False):
+    def build_jk(self, D, J=None, K=None, stream=None, sync=False, time_classes=False):
         """J, K for density D.  torch CUDA tensors (float64, contiguous) stay on
         the device and run on `stream` (default: torch's current stream);
         numpy arrays go through host copies."""
@@ -183,7 +184,7 @@ class FockJK:
         if K is None:
             K = torch.empty_like(D)
         st = stream if stream is not None else torch.cuda.current_stream(D.device)
-        flags = FK_DEVICE_PTRS | (FK_SYNC if sync else 0)
+        flags = FK_DEVICE_PTRS | (FK_SYNC if sync else 0) | (FK_TIME_CLASSES if time_classes else 0)
         self._check(_lib.fk_build_jk(self._ctx, ctypes.c_void_p(D.data_ptr()), ctypes.c_void_p(J.data_ptr()),
                                      ctypes.c_void_p(K.data_ptr()), flags, ctypes.c_void_p(st.cuda_stream)))
         return J, K
@@ -195,7 +196,7 @@ class FockJK:
         for i in range(s.nclass):
             out.append({"class": (s.la[i], s.lb[i], s.lc[i], s.ld[i]), "quartets": s.quartets[i],
                         "prim_quartets": s.prim_quartets[i], "flops_per_prim": s.flops_per_prim[i],
-                        "flops_per_quartet": s.flops_per_quartet[i]})
+                        "flops_per_quartet": s.flops_per_quartet[i], "ms": s.class_ms[i]})
         return {"classes": out, "flops_total": s.flops_total,
                 "quartets": sum(c["quartets"] for c in out), "prim_quartets": sum(c["prim_quartets"] for c in out)}
 

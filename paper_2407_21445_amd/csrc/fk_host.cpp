@@ -79,9 +79,10 @@ struct fk_ctx {
     DevBuf<double> d_bf_scale, d_pr_AB, d_pr_G, d_pp, d_rys, d_Ds, d_Dsh, d_X, d_Din, d_Jout, d_Kout;
     DevBuf<FkTile> d_tiles;
     DevBuf<unsigned long long> d_cnt;
-    bool constants_uploaded = false;
     // last build
     bool stats_pending = false;
+    bool timed = false;
+    std::vector<hipEvent_t> ev;  // 2 per quartet class
 };
 
 namespace {
@@ -282,6 +283,7 @@ void fk_destroy(fk_ctx *c)
     if (c->device >= 0) {
         hipSetDevice(c->device);
         free_device(c);
+        for (auto e : c->ev) (void)hipEventDestroy(e);
     }
     delete c;
 }
@@ -553,8 +555,16 @@ int fk_build_jk(fk_ctx *c, const double *D, double *J, double *K, unsigned flags
     if (fk_kernels_launch_fill(c->d_X.p, (long long)(2 * nn), st) ||
         fk_kernels_launch_fill((double *)c->d_cnt.p, 2 * FK_MAX_QCLASS, st))
         return fail(c, FK_ERR_HIP, "fill kernel launch failed");
+    c->timed = (flags & FK_TIME_CLASSES) != 0;
+    if (c->timed)
+        while (c->ev.size() < 2 * c->qclasses.size()) {
+            hipEvent_t e;
+            HIPCHK(c, hipEventCreate(&e));
+            c->ev.push_back(e);
+        }
     for (size_t i = 0; i < c->qclasses.size(); ++i) {
         const QuartetClass &qc = c->qclasses[i];
+        if (c->timed) HIPCHK(c, hipEventRecord(c->ev[2 * i], st));
         FkJKArgs a;
         a.sh_bf = c->d_sh_bf.p;
         a.pair_sa = c->d_pr_sa.p;
@@ -582,6 +592,7 @@ int fk_build_jk(fk_ctx *c, const double *D, double *J, double *K, unsigned flags
         const int grid = (int)std::max<int64_t>(1, std::min(want, cap));
         if (fk_kernels_launch_jk(qc.P, qc.Q, &a, grid, st))
             return fail(c, FK_ERR_HIP, "J/K kernel launch failed for class (%d|%d)", qc.P, qc.Q);
+        if (c->timed) HIPCHK(c, hipEventRecord(c->ev[2 * i + 1], st));
     }
     if (fk_kernels_launch_finalize(c->d_X.p, c->d_X.p + nn, c->d_bf_scale.p, n, Jd, Kd, st))
         return fail(c, FK_ERR_HIP, "finalize kernel launch failed");
@@ -614,6 +625,10 @@ int fk_stats(fk_ctx *c, fk_stats_t *s)
         s->flops_per_prim[i] = q.info.flops_prim;
         s->flops_per_quartet[i] = q.info.flops_quartet;
         s->flops_total += s->prim_quartets[i] * q.info.flops_prim + s->quartets[i] * q.info.flops_quartet;
+        if (c->timed && 2 * i + 1 < c->ev.size()) {
+            float ms = 0;
+            if (hipEventElapsedTime(&ms, c->ev[2 * i], c->ev[2 * i + 1]) == hipSuccess) s->class_ms[i] = ms;
+        }
     }
     return FK_OK;
 }
