@@ -31,7 +31,7 @@ PEAK_FP64_VALU = 78.6  # TFLOP/s, MI355X dense FP64 vector
 def _workload(name):
     from synth import workloads as wl
     if name == "c20h42":
-        return wl.c20h42_631gs(), "C20H42 all-trans (0.02 A jitter), 6-31G*-type, 384 Cartesian bf, tau=1e-10"
+        return wl.c20h42_631gs(), "C20H42 all-trans (0.02 A jitter), 6-31G*-type, 384 Cartesian bf"
     if name == "water4":
         return wl.water4_sto3g(), "(H2O)4 STO-3G-type, 28 bf, tau=1e-10"
     if name == "water64":
@@ -82,8 +82,10 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="c20h42")
     ap.add_argument("--tau", type=float, default=1e-10)
+    ap.add_argument("--tau-prim", type=float, default=1e-12, help="primitive-pair pruning threshold")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--classes", action="store_true", help="print the per-class kernel table to stderr")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported", file=sys.stderr)
@@ -92,7 +94,7 @@ def main():
     import paper_2407_21445_amd as fk
 
     sys_, desc = _workload(args.workload)
-    ctx = fk.FockJK(0).set_system(sys_).build_quartets(tau=args.tau)
+    ctx = fk.FockJK(0).set_system(sys_).build_quartets(tau=args.tau, tau_prim=args.tau_prim)
     info = ctx.info()
     S, T, V, _ = ctx.one_electron()
     D = _core_density(S, T + V, sys_["nelec"] // 2)
@@ -130,6 +132,16 @@ def main():
     cls_ms = acc / reps
     i = int(np.argmax(cls_ms))
     c = s2["classes"][i]
+    if args.classes:
+        print(f"{'class':>10} {'ms':>8} {'share':>6} {'quartets':>11} {'prims':>13} {'GFLOP':>9} {'TFLOP/s':>8} {'frac':>6}",
+              file=sys.stderr)
+        for k in np.argsort(-cls_ms):
+            cc = s2["classes"][k]
+            f = cc["prim_quartets"] * cc["flops_per_prim"] + cc["quartets"] * cc["flops_per_quartet"]
+            tf = f / (cls_ms[k] * 1e-3) / 1e12 if cls_ms[k] > 0 else 0.0
+            nm = "({}{}|{}{})".format(*("spdf"[x] for x in cc["class"]))
+            print(f"{nm:>10} {cls_ms[k]:8.3f} {cls_ms[k] / cls_ms.sum():6.3f} {cc['quartets']:11d} "
+                  f"{cc['prim_quartets']:13d} {f / 1e9:9.2f} {tf:8.3f} {tf / PEAK_FP64_VALU:6.3f}", file=sys.stderr)
     cflops = c["prim_quartets"] * c["flops_per_prim"] + c["quartets"] * c["flops_per_quartet"]
     achieved = cflops / (cls_ms[i] * 1e-3) / 1e12
     lname = "spdf"
@@ -139,6 +151,7 @@ def main():
         "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f64", "data": "synthetic",
         "config": {"workload": desc, "nbf": info["nbf"], "nshell": info["nshell"], "tau": args.tau,
+                   "tau_prim": args.tau_prim,
                    "density": "core-Hamiltonian guess", "precision": "fp64"},
         "quartets_per_s": st["quartets"] / (ms * 1e-3),
         "prim_quartets_per_s": st["prim_quartets"] / (ms * 1e-3),

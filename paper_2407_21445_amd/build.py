@@ -14,6 +14,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libfockjk.so")
+INCLUDE = os.path.join(os.path.dirname(HERE), "include")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 
@@ -33,7 +34,7 @@ def _run(cmd):
 def build(maxl: int = 3, jobs: int | None = None, verbose: bool = False, extra=()) -> str:
     os.makedirs(BUILD, exist_ok=True)
     jobs = jobs or min(16, os.cpu_count() or 4)
-    defs = [f"-DFK_BUILD_MAXL={maxl}"] + list(extra)
+    defs = [f"-DFK_BUILD_MAXL={maxl}", f"-I{INCLUDE}"] + list(extra)
     units = []
     # the kernel file is compiled once per bra pair class (FK_ONLY_P selects it)
     for P in range(10):

@@ -135,17 +135,44 @@ struct QuartetSetup {
     double PQ[3];
 };
 
+// 1/x and sqrt(x) for x > 0: on the device the hardware approximations refined
+// by two Newton steps each (cheaper than the IEEE sequences, same accuracy
+// class); on the host the library functions.
+FK_HD double fk_rcp(double x)
+{
+#if defined(__HIP_DEVICE_COMPILE__)
+    double r = __builtin_amdgcn_rcp(x);
+    r = fma(fma(-x, r, 1.0), r, r);
+    r = fma(fma(-x, r, 1.0), r, r);
+    return r;
+#else
+    return 1.0 / x;
+#endif
+}
+
+FK_HD double fk_sqrt(double x)
+{
+#if defined(__HIP_DEVICE_COMPILE__)
+    double y = __builtin_amdgcn_rsq(x);
+    y = fma(0.5 * y, fma(-x * y, y, 1.0), y);
+    y = fma(0.5 * y, fma(-x * y, y, 1.0), y);
+    return x * y;
+#else
+    return sqrt(x);
+#endif
+}
+
 FK_HD QuartetSetup quartet_setup(const PrimPair &p, const PrimPair &q)
 {
     QuartetSetup s;
     double zpe = p.zeta + q.zeta;
-    s.inv = 1.0 / zpe;
+    s.inv = fk_rcp(zpe);
     double rho = p.zeta * q.zeta * s.inv;
     s.PQ[0] = p.P[0] - q.P[0];
     s.PQ[1] = p.P[1] - q.P[1];
     s.PQ[2] = p.P[2] - q.P[2];
     s.T = rho * (s.PQ[0] * s.PQ[0] + s.PQ[1] * s.PQ[1] + s.PQ[2] * s.PQ[2]);
-    s.pref = p.K * q.K * sqrt(rho);
+    s.pref = p.K * q.K * fk_sqrt(rho);
     s.ez = q.zeta * s.inv;
     s.zz = p.zeta * s.inv;
     return s;
@@ -288,6 +315,126 @@ FK_HD void rys_prim_bra_comp(const double *__restrict tab, const PrimPair &p, co
                 acc[ic * Q::ND + id] += I[0][kCart.x[LC][ic]][kCart.x[LD][id]]
                                       * I[1][kCart.y[LC][ic]][kCart.y[LD][id]]
                                       * I[2][kCart.z[LC][ic]][kCart.z[LD][id]];
+    }
+}
+
+// Team form: the lane owns bra component a (exponents a[3], run-time) and,
+// for MODE 1, every b component (NB*NC*ND outputs), for MODE 2 the single b
+// component b[3] (NC*ND outputs).  The 2-D recurrences are evaluated per lane;
+// the bra transfer uses the closed form I(a,b) = sum_j C(b,j) AB^(b-j) G(a+j).
+template <int LA, int LB, int LC, int LD, int MODE>
+FK_HD void rys_prim_team(const double *__restrict tab, const PrimPair &p, const PrimPair &q, const double AB[3],
+                         const double CD[3], const int a[3], const int b[3], double *__restrict acc)
+{
+    using Q = QClass<LA, LB, LC, LD>;
+    constexpr int LAB = Q::LAB, LCD = Q::LCD;
+    constexpr int NBL = (MODE == 1) ? Q::NB : 1;
+    QuartetSetup s = quartet_setup(p, q);
+    double u[Q::NR], w[Q::NR];
+    rys_roots<Q::NR, (Q::L > 0)>(s.T, tab, u, w);
+#pragma unroll
+    for (int r = 0; r < Q::NR; ++r) {
+        const double ur = (Q::L > 0) ? u[r] : 0.0;
+        const double B00 = 0.5 * s.inv * ur;
+        const double B10 = p.oo2z * (1.0 - s.ez * ur);
+        const double B01 = q.oo2z * (1.0 - s.zz * ur);
+        double I[3][NBL][LC + 1][LD + 1];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            const double C00 = p.PA[k] - s.ez * s.PQ[k] * ur;
+            const double C00p = q.PA[k] + s.zz * s.PQ[k] * ur;
+            double G[LAB + 1][LCD + 1];
+            G[0][0] = (k == 2) ? w[r] * s.pref : 1.0;
+            if constexpr (LAB > 0) {
+                G[1][0] = C00 * G[0][0];
+#pragma unroll
+                for (int e = 1; e < LAB; ++e) G[e + 1][0] = C00 * G[e][0] + (double)e * B10 * G[e - 1][0];
+            }
+            if constexpr (LCD > 0) {
+                G[0][1] = C00p * G[0][0];
+#pragma unroll
+                for (int e = 1; e <= LAB; ++e) G[e][1] = C00p * G[e][0] + (double)e * B00 * G[e - 1][0];
+#pragma unroll
+                for (int f = 1; f < LCD; ++f) {
+                    G[0][f + 1] = C00p * G[0][f] + (double)f * B01 * G[0][f - 1];
+#pragma unroll
+                    for (int e = 1; e <= LAB; ++e)
+                        G[e][f + 1] = C00p * G[e][f] + (double)f * B01 * G[e][f - 1] + (double)e * B00 * G[e - 1][f];
+                }
+            }
+            // rows a_k .. a_k + LB of G for this lane's run-time a_k
+            const int ak = a[k];
+            double Gs[LB + 1][LCD + 1];
+#pragma unroll
+            for (int j = 0; j <= LB; ++j)
+#pragma unroll
+                for (int f = 0; f <= LCD; ++f) {
+                    double v = G[j][f];
+#pragma unroll
+                    for (int e = 1; e <= LA; ++e) v = (ak == e) ? G[e + j][f] : v;
+                    Gs[j][f] = v;
+                }
+            double abp[LB + 1];
+            abp[0] = 1.0;
+#pragma unroll
+            for (int j = 1; j <= LB; ++j) abp[j] = abp[j - 1] * AB[k];
+#pragma unroll
+            for (int ib = 0; ib < NBL; ++ib) {
+                double h[LCD + 1];
+                if constexpr (MODE == 1) {
+                    constexpr int dummy = 0;
+                    (void)dummy;
+                    // b exponent of component ib along axis k is a compile-time constant
+                    const int bk = (k == 0) ? kCart.x[LB][ib] : (k == 1 ? kCart.y[LB][ib] : kCart.z[LB][ib]);
+#pragma unroll
+                    for (int f = 0; f <= LCD; ++f) {
+                        double v = 0.0;
+#pragma unroll
+                        for (int j = 0; j <= LB; ++j)
+                            if (j <= bk) v += binom(bk, j) * abp[bk - j] * Gs[j][f];
+                        h[f] = v;
+                    }
+                } else {
+                    const int bk = b[k];
+                    double cf[LB + 1];
+#pragma unroll
+                    for (int j = 0; j <= LB; ++j) {
+                        double c = 0.0;
+#pragma unroll
+                        for (int bb = 0; bb <= LB; ++bb)
+                            if (j <= bb) c = (bk == bb) ? binom(bb, j) * abp[bb - j] : c;
+                        cf[j] = c;
+                    }
+#pragma unroll
+                    for (int f = 0; f <= LCD; ++f) {
+                        double v = 0.0;
+#pragma unroll
+                        for (int j = 0; j <= LB; ++j) v += cf[j] * Gs[j][f];
+                        h[f] = v;
+                    }
+                }
+                double Kt[LCD + 1][LD + 1];
+#pragma unroll
+                for (int c = 0; c <= LCD; ++c) Kt[c][0] = h[c];
+#pragma unroll
+                for (int d = 0; d < LD; ++d)
+#pragma unroll
+                    for (int c = 0; c < LCD - d; ++c) Kt[c][d + 1] = Kt[c + 1][d] + CD[k] * Kt[c][d];
+#pragma unroll
+                for (int c = 0; c <= LC; ++c)
+#pragma unroll
+                    for (int d = 0; d <= LD; ++d) I[k][ib][c][d] = Kt[c][d];
+            }
+        }
+#pragma unroll
+        for (int ib = 0; ib < NBL; ++ib)
+#pragma unroll
+            for (int ic = 0; ic < Q::NC; ++ic)
+#pragma unroll
+                for (int id = 0; id < Q::ND; ++id)
+                    acc[(ib * Q::NC + ic) * Q::ND + id] += I[0][ib][kCart.x[LC][ic]][kCart.x[LD][id]]
+                                                         * I[1][ib][kCart.y[LC][ic]][kCart.y[LD][id]]
+                                                         * I[2][ib][kCart.z[LC][ic]][kCart.z[LD][id]];
     }
 }
 

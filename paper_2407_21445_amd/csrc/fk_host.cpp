@@ -13,7 +13,7 @@
 #include <string>
 #include <vector>
 
-#include "../../include/fockjk.h"
+#include "fockjk.h"
 #include "fk_internal.h"
 #include "fk_rys.h"
 
@@ -43,6 +43,7 @@ struct QuartetClass {
     int64_t tile_off, ntile;
     int64_t nquartet, nprim;  // Schwarz-surviving counts
     int blocks_per_cu;
+    int bra_slot;             // doubles per wave of staged bra primitive records
 };
 
 }  // namespace
@@ -69,16 +70,23 @@ struct fk_ctx {
     std::vector<std::pair<int, int>> cls_groups[NPC];  // [begin, end) of equal npp
     std::vector<int> ket_list_all;               // concatenated class lists
     int ket_off[NPC + 1] = {0};
+    std::vector<int> lst_sa, lst_sb;
+    std::vector<double> lst_CD, lst_G, ppT;
+    std::vector<FkGroup> groups;
+    std::vector<int> cls_group0;                 // first global group of each class
     std::vector<FkTile> tiles;
     std::vector<QuartetClass> qclasses;
     double flops_schwarz = 0;
     int64_t nq_schwarz = 0;
     int npair_kept = 0;
     // device buffers
-    DevBuf<int> d_sh_bf, d_pr_sa, d_pr_sb, d_pr_ppoff, d_pr_npp, d_ket;
+    DevBuf<int> d_sh_bf, d_pr_sa, d_pr_sb, d_pr_ppoff, d_pr_npp, d_ket, d_lst_sa, d_lst_sb;
     DevBuf<double> d_bf_scale, d_pr_AB, d_pr_G, d_pp, d_rys, d_Ds, d_Dsh, d_X, d_Din, d_Jout, d_Kout;
+    DevBuf<double> d_lst_CD, d_lst_G, d_ppT;
+    DevBuf<FkGroup> d_groups;
     DevBuf<FkTile> d_tiles;
     DevBuf<unsigned long long> d_cnt;
+    DevBuf<unsigned int> d_tilectr;
     // last build
     bool stats_pending = false;
     bool timed = false;
@@ -160,7 +168,8 @@ void free_device(fk_ctx *c)
     dev_free(c->d_pr_npp); dev_free(c->d_ket); dev_free(c->d_bf_scale); dev_free(c->d_pr_AB);
     dev_free(c->d_pr_G); dev_free(c->d_pp); dev_free(c->d_rys); dev_free(c->d_Ds); dev_free(c->d_Dsh);
     dev_free(c->d_X); dev_free(c->d_Din); dev_free(c->d_Jout); dev_free(c->d_Kout); dev_free(c->d_tiles);
-    dev_free(c->d_cnt);
+    dev_free(c->d_cnt); dev_free(c->d_tilectr); dev_free(c->d_lst_sa); dev_free(c->d_lst_sb); dev_free(c->d_lst_CD);
+    dev_free(c->d_lst_G); dev_free(c->d_ppT); dev_free(c->d_groups);
 }
 
 // canonical orientation of a shell pair: first shell has the higher l
@@ -203,7 +212,17 @@ void make_pair(fk_ctx *c, int sa, int sb)
 
 // Raw contracted integrals for quartets given as (bra pair, ket pair) of one
 // class pair (P = class of bra >= Q = class of ket), on device or host.
-int eval_quartets(fk_ctx *c, int P, int Q, const std::vector<int> &qs, std::vector<double> &out, bool on_device)
+// A pair table as read by the integral code: primitive offsets/counts and
+// A - B per pair, primitive records in c->pp.
+struct PairTab {
+    const int *ppoff, *npp;
+    const double *AB;
+    const int *d_ppoff, *d_npp;  // device copies (device evaluation only)
+    const double *d_AB;
+};
+
+int eval_quartets_tab(fk_ctx *c, const PairTab &t, int P, int Q, const std::vector<int> &qs,
+                      std::vector<double> &out, bool on_device)
 {
     FkClassInfo ci;
     int rc = fk_kernels_class_info(P, Q, &ci);
@@ -212,8 +231,7 @@ int eval_quartets(fk_ctx *c, int P, int Q, const std::vector<int> &qs, std::vect
     out.assign((size_t)nq * ci.nout, 0.0);
     if (nq == 0) return FK_OK;
     if (!on_device) {
-        rc = fk_kernels_debug_host(P, Q, c->pr_ppoff.data(), c->pr_npp.data(), c->pr_AB.data(), c->pp.data(),
-                                   qs.data(), nq, out.data());
+        rc = fk_kernels_debug_host(P, Q, t.ppoff, t.npp, t.AB, c->pp.data(), qs.data(), nq, out.data());
         return rc ? fail(c, FK_ERR_UNSUPPORTED, "host evaluation failed") : FK_OK;
     }
     DevBuf<int> dq;
@@ -221,9 +239,9 @@ int eval_quartets(fk_ctx *c, int P, int Q, const std::vector<int> &qs, std::vect
     if ((rc = dev_upload(c, dq, qs.data(), qs.size()))) return rc;
     if ((rc = dev_upload<double>(c, dout, nullptr, out.size()))) { dev_free(dq); return rc; }
     FkDebugArgs a;
-    a.pair_ppoff = c->d_pr_ppoff.p;
-    a.pair_npp = c->d_pr_npp.p;
-    a.pair_AB = c->d_pr_AB.p;
+    a.pair_ppoff = t.d_ppoff;
+    a.pair_npp = t.d_npp;
+    a.pair_AB = t.d_AB;
     a.pp = c->d_pp.p;
     a.quartets = (const int2 *)dq.p;
     a.nq = nq;
@@ -236,6 +254,148 @@ int eval_quartets(fk_ctx *c, int P, int Q, const std::vector<int> &qs, std::vect
     dev_free(dout);
     if (rc) return fail(c, FK_ERR_HIP, "debug kernel launch failed for class (%d,%d)", P, Q);
     if (e != hipSuccess) return fail(c, FK_ERR_HIP, "debug kernel: %s", hipGetErrorString(e));
+    return FK_OK;
+}
+
+int eval_quartets(fk_ctx *c, int P, int Q, const std::vector<int> &qs, std::vector<double> &out, bool on_device)
+{
+    PairTab t{c->pr_ppoff.data(), c->pr_npp.data(), c->pr_AB.data(), c->d_pr_ppoff.p, c->d_pr_npp.p, c->d_pr_AB.p};
+    return eval_quartets_tab(c, t, P, Q, qs, out, on_device);
+}
+
+// Largest Cartesian diagonal of (ab|ab) over the components, true normalisation.
+double diag_max(const fk_ctx *c, const double *v, int sa, int sb)
+{
+    const int na = ncart(c->sh_l[sa]), nb = ncart(c->sh_l[sb]);
+    const double *fa = &c->bf_scale[c->sh_bf[sa]], *fb = &c->bf_scale[c->sh_bf[sb]];
+    double g = 0;
+    for (int ia = 0; ia < na; ++ia)
+        for (int ib = 0; ib < nb; ++ib) {
+            const double x = v[((ia * nb + ib) * na + ia) * nb + ib] * fa[ia] * fa[ia] * fb[ib] * fb[ib];
+            g = std::max(g, std::sqrt(std::fabs(x)));
+        }
+    return g;
+}
+
+// Primitive Cauchy-Schwarz factors G_[ab] (eq. cauchy-schwarz2) of every
+// primitive pair, from the diagonal primitive quartets [ab|ab] evaluated by the
+// same integral code, stored in field 9 of the primitive records.
+int prim_schwarz(fk_ctx *c, bool dev)
+{
+    const int np = (int)(c->pp.size() / FK_NPP_REC);
+    const int npair = (int)c->pr_sa.size();
+    std::vector<int> owner(np), one(np, 1), self(np);
+    std::vector<double> ab(3 * (size_t)np);
+    for (int p = 0; p < npair; ++p)
+        for (int j = 0; j < c->pr_npp[p]; ++j) {
+            const int k = c->pr_ppoff[p] + j;
+            owner[k] = p;
+            for (int x = 0; x < 3; ++x) ab[3 * k + x] = c->pr_AB[3 * p + x];
+        }
+    std::iota(self.begin(), self.end(), 0);
+    DevBuf<int> d_self, d_one;
+    DevBuf<double> d_ab;
+    int rc;
+    if (dev) {
+        if ((rc = dev_upload(c, d_self, self.data(), self.size())) || (rc = dev_upload(c, d_one, one.data(), one.size())) ||
+            (rc = dev_upload(c, d_ab, ab.data(), ab.size()))) {
+            dev_free(d_self); dev_free(d_one); dev_free(d_ab);
+            return rc;
+        }
+    }
+    PairTab t{self.data(), one.data(), ab.data(), d_self.p, d_one.p, d_ab.p};
+    rc = FK_OK;
+    for (int P = 0; P < NPC && rc == FK_OK; ++P) {
+        std::vector<int> qs, ks;
+        for (int k = 0; k < np; ++k)
+            if (c->pr_cls[owner[k]] == P) { qs.push_back(k); qs.push_back(k); ks.push_back(k); }
+        if (ks.empty()) continue;
+        std::vector<double> out;
+        if ((rc = eval_quartets_tab(c, t, P, P, qs, out, dev))) break;
+        const size_t nout = out.size() / ks.size();
+        for (size_t q = 0; q < ks.size(); ++q) {
+            const int p = owner[ks[q]];
+            const double g = diag_max(c, out.data() + q * nout, c->pr_sa[p], c->pr_sb[p]);
+            if (!std::isfinite(g)) { rc = fail(c, FK_ERR_ARG, "non-finite primitive Schwarz factor"); break; }
+            c->pp[(size_t)ks[q] * FK_NPP_REC + 9] = g;
+        }
+    }
+    dev_free(d_self); dev_free(d_one); dev_free(d_ab);
+    return rc;
+}
+
+// Orders each pair's primitive pairs by G_[ab] (largest first) and, when
+// tau_prim > 0, deletes those with G_[ab] * max G_[cd] < tau_prim: every
+// primitive quartet they belong to is then bounded by tau_prim times the
+// density.  The largest primitive pair of a shell pair is always kept.
+void prune_primitives(fk_ctx *c, double tau_prim)
+{
+    const int npair = (int)c->pr_sa.size();
+    double gmax = 0;
+    for (size_t k = 0; k < c->pp.size() / FK_NPP_REC; ++k) gmax = std::max(gmax, c->pp[k * FK_NPP_REC + 9]);
+    std::vector<double> npp_new;
+    npp_new.reserve(c->pp.size());
+    for (int p = 0; p < npair; ++p) {
+        std::vector<int> idx(c->pr_npp[p]);
+        std::iota(idx.begin(), idx.end(), c->pr_ppoff[p]);
+        std::stable_sort(idx.begin(), idx.end(), [&](int x, int y) {
+            return c->pp[(size_t)x * FK_NPP_REC + 9] > c->pp[(size_t)y * FK_NPP_REC + 9];
+        });
+        const int off = (int)(npp_new.size() / FK_NPP_REC);
+        int kept = 0;
+        for (size_t r = 0; r < idx.size(); ++r) {
+            const double g = c->pp[(size_t)idx[r] * FK_NPP_REC + 9];
+            if (r > 0 && tau_prim > 0 && g * gmax < tau_prim) break;
+            npp_new.insert(npp_new.end(), c->pp.begin() + (size_t)idx[r] * FK_NPP_REC,
+                           c->pp.begin() + (size_t)(idx[r] + 1) * FK_NPP_REC);
+            ++kept;
+        }
+        c->pr_ppoff[p] = off;
+        c->pr_npp[p] = kept;
+    }
+    c->pp.swap(npp_new);
+}
+
+// Every index a J/K kernel dereferences, checked on the host before upload:
+// tiles -> pairs, groups and list positions; groups -> transposed records;
+// pairs -> shells and primitive records; shells -> basis-function offsets.
+int validate_lists(fk_ctx *c)
+{
+    const int npair = (int)c->pr_sa.size();
+    const long long npp_tot = (long long)(c->pp.size() / FK_NPP_REC);
+    const int nl = (int)c->ket_list_all.size();
+    for (int p = 0; p < npair; ++p) {
+        if (c->pr_sa[p] < 0 || c->pr_sa[p] >= c->nshell || c->pr_sb[p] < 0 || c->pr_sb[p] >= c->nshell ||
+            c->pr_ppoff[p] < 0 || c->pr_npp[p] < 1 || c->pr_npp[p] > FK_MAX_K * FK_MAX_K ||
+            (long long)c->pr_ppoff[p] + c->pr_npp[p] > npp_tot || !std::isfinite(c->pr_G[p]) || c->pr_G[p] < 0)
+            return fail(c, FK_ERR_STATE, "internal: shell pair %d is inconsistent", p);
+    }
+    for (int q = 0; q < nl; ++q)
+        if (c->ket_list_all[q] < 0 || c->ket_list_all[q] >= npair)
+            return fail(c, FK_ERR_STATE, "internal: list position %d holds pair %d", q, c->ket_list_all[q]);
+    for (size_t g = 0; g < c->groups.size(); ++g) {
+        const FkGroup &G = c->groups[g];
+        if (G.begin < 0 || G.len < 1 || G.begin + G.len > nl || G.npp < 1 ||
+            G.base < 0 || G.base + (long long)G.npp * FK_NFLD * G.len > (long long)c->ppT.size())
+            return fail(c, FK_ERR_STATE, "internal: group %zu is inconsistent", g);
+        for (int r = 0; r < G.len; ++r)
+            if (c->pr_npp[c->ket_list_all[G.begin + r]] != G.npp)
+                return fail(c, FK_ERR_STATE, "internal: group %zu mixes primitive counts", g);
+    }
+    for (const QuartetClass &qc : c->qclasses) {
+        for (int64_t t = qc.tile_off; t < qc.tile_off + qc.ntile; ++t) {
+            const FkTile &T = c->tiles[t];
+            const int gid = T.grp & ~FK_TILE_SAME;
+            if (T.bra < 0 || T.bra >= npair || gid < 0 || gid >= (int)c->groups.size() || T.ket_count < 1 ||
+                T.ket_count > 64 || c->pr_npp[T.bra] * FK_NFLD > qc.bra_slot)
+                return fail(c, FK_ERR_STATE, "internal: tile %lld is inconsistent", (long long)t);
+            const FkGroup &G = c->groups[gid];
+            if (T.ket_begin < G.begin || T.ket_begin + T.ket_count > G.begin + G.len)
+                return fail(c, FK_ERR_STATE, "internal: tile %lld leaves its group", (long long)t);
+        }
+    }
+    for (int s = 0; s <= c->nshell; ++s)
+        if (c->sh_bf[s] < 0 || c->sh_bf[s] > c->nbf) return fail(c, FK_ERR_STATE, "internal: shell offsets");
     return FK_OK;
 }
 
@@ -393,7 +553,11 @@ int fk_build_quartets(fk_ctx *c, const fk_screen_opts *o)
     const int npair = (int)c->pr_sa.size();
     int rc;
     if (dev && (rc = upload_pairs(c))) return rc;
-    // 2. Schwarz factors from the diagonal quartets (ab|ab)
+    // 2a. primitive Schwarz factors, primitive order and pruning
+    if ((rc = prim_schwarz(c, dev))) return rc;
+    prune_primitives(c, opts.tau_prim);
+    if (dev && (rc = upload_pairs(c))) return rc;
+    // 2b. Schwarz factors from the diagonal quartets (ab|ab)
     for (int P = 0; P < NPC; ++P) {
         std::vector<int> idx, qs;
         for (int p = 0; p < npair; ++p)
@@ -412,6 +576,7 @@ int fk_build_quartets(fk_ctx *c, const fk_screen_opts *o)
                     const double v = out[q * nout + ((ia * nb + ib) * na + ia) * nb + ib] * sa[ia] * sa[ia] * sb[ib] * sb[ib];
                     g = std::max(g, std::sqrt(std::fabs(v)));
                 }
+            if (!std::isfinite(g)) return fail(c, FK_ERR_ARG, "non-finite Schwarz factor for shell pair %d", p);
             c->pr_G[p] = g;
         }
     }
@@ -441,6 +606,42 @@ int fk_build_quartets(fk_ctx *c, const fk_screen_opts *o)
         c->ket_list_all.insert(c->ket_list_all.end(), L.begin(), L.end());
     }
     c->ket_off[NPC] = (int)c->ket_list_all.size();
+    {
+        const size_t nl = c->ket_list_all.size();
+        c->lst_sa.assign(nl, 0); c->lst_sb.assign(nl, 0);
+        c->lst_CD.assign(3 * std::max<size_t>(nl, 1), 0.0); c->lst_G.assign(nl, 0.0);
+        for (size_t q = 0; q < nl; ++q) {
+            const int p = c->ket_list_all[q];
+            c->lst_sa[q] = c->pr_sa[p];
+            c->lst_sb[q] = c->pr_sb[p];
+            for (int k = 0; k < 3; ++k) c->lst_CD[k * nl + q] = c->pr_AB[3 * p + k];
+            c->lst_G[q] = c->pr_G[p];
+        }
+        c->groups.clear();
+        c->cls_group0.assign(NPC + 1, 0);
+        c->ppT.clear();
+        for (int P = 0; P < NPC; ++P) {
+            c->cls_group0[P] = (int)c->groups.size();
+            for (const auto &g : c->cls_groups[P]) {
+                FkGroup G;
+                G.begin = c->ket_off[P] + g.first;
+                G.len = g.second - g.first;
+                G.npp = c->pr_npp[c->cls_list[P][g.first]];
+                G.pad = 0;
+                G.base = (long long)c->ppT.size();
+                c->ppT.resize(c->ppT.size() + (size_t)G.npp * FK_NFLD * G.len);
+                for (int r = 0; r < G.len; ++r) {
+                    const int p = c->ket_list_all[G.begin + r];
+                    for (int j = 0; j < G.npp; ++j)
+                        for (int f = 0; f < FK_NFLD; ++f)
+                            c->ppT[G.base + ((size_t)j * FK_NFLD + f) * G.len + r] =
+                                c->pp[((size_t)c->pr_ppoff[p] + j) * FK_NPP_REC + f];
+                }
+                c->groups.push_back(G);
+            }
+        }
+        c->cls_group0[NPC] = (int)c->groups.size();
+    }
     // 4. tiles per quartet class (P >= Q): bra from class P, kets from class Q
     c->tiles.clear();
     c->qclasses.clear();
@@ -456,10 +657,18 @@ int fk_build_quartets(fk_ctx *c, const fk_screen_opts *o)
                 return fail(c, FK_ERR_UNSUPPORTED, "quartet class (%d|%d) is not built into this library", P, Q);
             qc.tile_off = (int64_t)c->tiles.size();
             qc.nquartet = 0; qc.nprim = 0;
+            // kets per tile: a full wave of kets for lane-per-quartet kernels, two
+            // rounds of teams for team kernels, two kets for wave-per-quartet
+            const int ts = std::max(1, qc.info.team_size);
+            const int tile_kets = qc.info.wave_per_quartet == 0 ? 64 : std::max(1, 2 * (64 / ts));
+            int max_bra_npp = 1;
+            for (int p : LP) max_bra_npp = std::max(max_bra_npp, c->pr_npp[p]);
+            qc.bra_slot = max_bra_npp * FK_NFLD;
             for (int pb = 0; pb < (int)LP.size(); ++pb) {
                 const int bra = LP[pb];
                 const double thr = opts.tau > 0 ? opts.tau / c->pr_G[bra] : 0.0;
-                for (const auto &g : c->cls_groups[Q]) {
+                for (size_t gi = 0; gi < c->cls_groups[Q].size(); ++gi) {
+                    const auto &g = c->cls_groups[Q][gi];
                     // kets in [g.first, g.second) are sorted by G descending
                     int lo = g.first, hi = g.second;
                     while (lo < hi) {
@@ -469,12 +678,12 @@ int fk_build_quartets(fk_ctx *c, const fk_screen_opts *o)
                     int cnt = lo - g.first;
                     if (P == Q) cnt = std::min(cnt, std::max(0, pb + 1 - g.first));
                     if (cnt <= 0) continue;
-                    for (int k = 0; k < cnt; k += 64) {
+                    for (int k = 0; k < cnt; k += tile_kets) {
                         FkTile t;
                         t.bra = bra;
                         t.ket_begin = c->ket_off[Q] + g.first + k;
-                        t.ket_count = std::min(64, cnt - k);
-                        t.flags = (P == Q) ? 1 : 0;
+                        t.ket_count = std::min(tile_kets, cnt - k);
+                        t.grp = (c->cls_group0[Q] + (int)gi) | ((P == Q) ? FK_TILE_SAME : 0);
                         c->tiles.push_back(t);
                     }
                     qc.nquartet += cnt;
@@ -483,24 +692,42 @@ int fk_build_quartets(fk_ctx *c, const fk_screen_opts *o)
             }
             qc.ntile = (int64_t)c->tiles.size() - qc.tile_off;
             if (qc.ntile == 0) continue;
+            // most expensive tiles first (bra primitives x ket primitives x kets)
+            {
+                auto cost = [&](const FkTile &t) {
+                    const FkGroup &gg = c->groups[t.grp & ~FK_TILE_SAME];
+                    return (int64_t)c->pr_npp[t.bra] * gg.npp * t.ket_count;
+                };
+                std::stable_sort(c->tiles.begin() + qc.tile_off, c->tiles.end(),
+                                 [&](const FkTile &x, const FkTile &y) { return cost(x) > cost(y); });
+            }
             c->flops_schwarz += qc.nprim * qc.info.flops_prim + qc.nquartet * qc.info.flops_quartet;
             c->nq_schwarz += qc.nquartet;
             qc.blocks_per_cu = 1;
             if (dev) {
                 int nb = 0;
-                if (fk_kernels_max_blocks(P, Q, &nb) == 0 && nb > 0) qc.blocks_per_cu = nb;
+                const int lds = fk_kernels_jk_lds_bytes(P, Q, qc.bra_slot);
+                if (fk_kernels_max_blocks(P, Q, lds, &nb) == 0 && nb > 0) qc.blocks_per_cu = nb;
             }
             c->qclasses.push_back(qc);
         }
+    if ((rc = validate_lists(c))) return rc;
     if (dev) {
         if ((rc = dev_upload(c, c->d_pr_G, c->pr_G.data(), c->pr_G.size()))) return rc;
         if ((rc = dev_upload(c, c->d_ket, c->ket_list_all.data(), c->ket_list_all.size()))) return rc;
+        if ((rc = dev_upload(c, c->d_lst_sa, c->lst_sa.data(), c->lst_sa.size()))) return rc;
+        if ((rc = dev_upload(c, c->d_lst_sb, c->lst_sb.data(), c->lst_sb.size()))) return rc;
+        if ((rc = dev_upload(c, c->d_lst_CD, c->lst_CD.data(), c->lst_CD.size()))) return rc;
+        if ((rc = dev_upload(c, c->d_lst_G, c->lst_G.data(), c->lst_G.size()))) return rc;
+        if ((rc = dev_upload(c, c->d_ppT, c->ppT.data(), c->ppT.size()))) return rc;
+        if ((rc = dev_upload(c, c->d_groups, c->groups.data(), c->groups.size()))) return rc;
         if ((rc = dev_upload(c, c->d_tiles, c->tiles.data(), c->tiles.size()))) return rc;
         const size_t nn = (size_t)c->nbf * c->nbf;
         if ((rc = dev_upload<double>(c, c->d_Ds, nullptr, nn))) return rc;
         if ((rc = dev_upload<double>(c, c->d_Dsh, nullptr, (size_t)c->nshell * c->nshell))) return rc;
         if ((rc = dev_upload<double>(c, c->d_X, nullptr, 2 * nn))) return rc;
         if ((rc = dev_upload<unsigned long long>(c, c->d_cnt, nullptr, 2 * FK_MAX_QCLASS))) return rc;
+        if ((rc = dev_upload<unsigned int>(c, c->d_tilectr, nullptr, 2 * FK_MAX_QCLASS))) return rc;
     }
     c->have_quartets = true;
     return FK_OK;
@@ -553,7 +780,8 @@ int fk_build_jk(fk_ctx *c, const double *D, double *J, double *K, unsigned flags
     if (fk_kernels_launch_prep(Dd, c->d_sh_bf.p, c->d_bf_scale.p, c->nshell, n, c->d_Ds.p, c->d_Dsh.p, st))
         return fail(c, FK_ERR_HIP, "prep kernel launch failed");
     if (fk_kernels_launch_fill(c->d_X.p, (long long)(2 * nn), st) ||
-        fk_kernels_launch_fill((double *)c->d_cnt.p, 2 * FK_MAX_QCLASS, st))
+        fk_kernels_launch_fill((double *)c->d_cnt.p, 2 * FK_MAX_QCLASS, st) ||
+        fk_kernels_launch_fill((double *)c->d_tilectr.p, FK_MAX_QCLASS, st))
         return fail(c, FK_ERR_HIP, "fill kernel launch failed");
     c->timed = (flags & FK_TIME_CLASSES) != 0;
     if (c->timed)
@@ -575,6 +803,13 @@ int fk_build_jk(fk_ctx *c, const double *D, double *J, double *K, unsigned flags
         a.pair_G = c->d_pr_G.p;
         a.pp = c->d_pp.p;
         a.ket_list = c->d_ket.p;
+        a.lst_sa = c->d_lst_sa.p;
+        a.lst_sb = c->d_lst_sb.p;
+        a.lst_CD = c->d_lst_CD.p;
+        a.lst_G = c->d_lst_G.p;
+        a.nlist = (int)c->ket_list_all.size();
+        a.groups = c->d_groups.p;
+        a.ppT = c->d_ppT.p;
         a.tiles = c->d_tiles.p + qc.tile_off;
         a.ntiles = (int)qc.ntile;
         a.nshell = c->nshell;
@@ -587,8 +822,12 @@ int fk_build_jk(fk_ctx *c, const double *D, double *J, double *K, unsigned flags
         a.tau = c->opts.tau;
         a.rys_tab = c->d_rys.p + rys_staged_offset(qc.info.nroot);
         a.counters = c->d_cnt.p + 2 * i;
+        a.bra_slot = qc.bra_slot;
+        a.tile_next = c->d_tilectr.p + i;
+        // Enough workgroups for the hardware to fill every CU to its register and
+        // LDS limit; the persistent loop covers the rest.
         const int64_t want = (qc.ntile + 3) / 4;
-        const int64_t cap = (int64_t)qc.blocks_per_cu * std::max(c->ncu, 1);
+        const int64_t cap = (int64_t)std::max(8, qc.blocks_per_cu) * std::max(c->ncu, 1);
         const int grid = (int)std::max<int64_t>(1, std::min(want, cap));
         if (fk_kernels_launch_jk(qc.P, qc.Q, &a, grid, st))
             return fail(c, FK_ERR_HIP, "J/K kernel launch failed for class (%d|%d)", qc.P, qc.Q);

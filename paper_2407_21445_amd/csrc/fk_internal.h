@@ -8,13 +8,27 @@
 // Primitive-pair record layout (FK_NPP_REC doubles):
 //   0 zeta, 1 1/(2 zeta), 2-4 P, 5-7 P - A, 8 K (see fk::PrimPair), 9 G_[ab].
 
+#define FK_NFLD 9  // fields of a transposed primitive-pair record (no G)
+
 // Work tile: one bra shell pair and up to 64 consecutive ket shell pairs of one
-// ket class (all with the same number of primitive pairs).
+// ket class, all from one primitive-count group.
 struct FkTile {
-    int bra;        // shell-pair index
-    int ket_begin;  // index into the ket class's sorted pair list
+    int bra;        // shell-pair index of the bra
+    int ket_begin;  // position in the concatenated sorted pair lists
     int ket_count;  // 1..64
-    int flags;      // bit 0: bra and ket from the same class
+    int grp;        // primitive-count group of the kets; bit 30: bra and ket from the same class
+};
+#define FK_TILE_SAME (1 << 30)
+
+// A run of equal primitive-pair count inside one class's sorted pair list.
+// Its primitive records are stored transposed, [j][field][position in run],
+// so that lanes holding consecutive kets read consecutive addresses.
+struct FkGroup {
+    int begin;      // first list position
+    int len;        // number of pairs
+    int npp;        // primitive pairs per pair
+    int pad;
+    long long base; // offset of the run's records in the transposed array
 };
 
 struct FkJKArgs {
@@ -26,7 +40,13 @@ struct FkJKArgs {
     const double *pair_AB;   // [npair * 3] A - B
     const double *pair_G;    // [npair] Schwarz factor
     const double *pp;        // [nprimpair * FK_NPP_REC]
-    const int *ket_list;     // sorted pair indices of the ket class
+    const int *ket_list;     // sorted pair indices (all classes, concatenated)
+    const int *lst_sa, *lst_sb;   // shells of the pair at each list position
+    const double *lst_CD;    // [3][nlist] A - B of the pair at each list position
+    const double *lst_G;     // Schwarz factor at each list position
+    int nlist;
+    const FkGroup *groups;
+    const double *ppT;       // transposed primitive records of every group
     const FkTile *tiles;
     int ntiles;
     int nshell;
@@ -39,6 +59,8 @@ struct FkJKArgs {
     double tau;
     const double *rys_tab;   // staged Rys segment (table + Gauss-Hermite) of this class's root count
     unsigned long long *counters;  // [2]: contracted quartets, primitive quartets
+    int bra_slot;            // doubles per wave for the staged bra primitive records
+    unsigned int *tile_next; // work counter: waves claim tiles in order (zeroed before the launch)
 };
 
 // Quartet list for the debug/Schwarz kernels (canonical orientation).
@@ -55,7 +77,8 @@ struct FkDebugArgs {
 // Per-class launch entry points (defined in fk_kernels.hip).
 struct FkClassInfo {
     int la, lb, lc, ld, nroot, nout;
-    int wave_per_quartet;    // 1: wave-per-quartet kernel, 0: lane-per-quartet
+    int wave_per_quartet;    // kernel kind: 0 lane, 1 team over a, 2 team over (a,b), 3 wave per quartet
+    int team_size;           // lanes per quartet
     double flops_prim, flops_quartet;
 };
 
@@ -63,7 +86,8 @@ extern "C" {
 int fk_kernels_class_info(int P, int Q, FkClassInfo *info);
 int fk_kernels_launch_jk(int P, int Q, const FkJKArgs *args, int grid, void *stream);
 int fk_kernels_launch_debug(int P, int Q, const FkDebugArgs *args, void *stream);
-int fk_kernels_max_blocks(int P, int Q, int *blocks_per_cu);
+int fk_kernels_max_blocks(int P, int Q, int dyn_lds_bytes, int *blocks_per_cu);
+int fk_kernels_jk_lds_bytes(int P, int Q, int bra_slot);
 int fk_kernels_launch_prep(const double *D, const int *sh_bf, const double *bf_scale, int nshell, int nbf,
                            double *Ds, double *Dsh, void *stream);
 int fk_kernels_launch_finalize(const double *XJ, const double *XK, const double *bf_scale, int nbf,

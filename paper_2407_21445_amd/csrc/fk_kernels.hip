@@ -34,8 +34,17 @@ namespace {
 constexpr int pair_la(int P) { return P == 0 ? 0 : (P <= 2 ? 1 : (P <= 5 ? 2 : 3)); }
 constexpr int pair_lb(int P) { return P - pair_la(P) * (pair_la(P) + 1) / 2; }
 
+// Kernel kind per class: 0 lane per quartet, 1 team over bra a components,
+// 2 team over bra (a, b) component pairs, 3 wave per quartet.
 template <int LA, int LB, int LC, int LD>
-constexpr bool use_wpq() { return fk::QClass<LA, LB, LC, LD>::NOUT > FK_LPQ_MAX_NOUT; }
+constexpr int kernel_kind()
+{
+    using Q = fk::QClass<LA, LB, LC, LD>;
+    if (Q::NOUT <= FK_LPQ_MAX_NOUT) return 0;
+    if (Q::NB * Q::NC * Q::ND <= FK_LPQ_MAX_NOUT) return 1;
+    if (Q::NA * Q::NB <= 64 && Q::NC * Q::ND <= FK_LPQ_MAX_NOUT) return 2;
+    return 3;
+}
 
 __device__ __forceinline__ fk::PrimPair load_pp(const double *__restrict pp, int idx)
 {
@@ -74,60 +83,161 @@ __device__ __forceinline__ double dmax6(const double *__restrict Dsh, int ns, in
     return fmax(m1, fmax(m2, m3));
 }
 
+// Ket pair data at a list position (consecutive lanes: consecutive positions).
+struct KetInfo {
+    int sc, sd;
+    double CD[3], G;
+};
+__device__ __forceinline__ KetInfo load_ket(const FkJKArgs &a, int pos)
+{
+    KetInfo k;
+    k.sc = a.lst_sa[pos];
+    k.sd = a.lst_sb[pos];
+    k.CD[0] = a.lst_CD[pos];
+    k.CD[1] = a.lst_CD[a.nlist + pos];
+    k.CD[2] = a.lst_CD[2 * a.nlist + pos];
+    k.G = a.lst_G[pos];
+    return k;
+}
+
+// Primitive pair j of the ket at position r of a group (transposed records).
+__device__ __forceinline__ fk::PrimPair load_ket_pp(const double *__restrict ppT, const FkGroup &g, int j, int r)
+{
+    const double *q = ppT + g.base + (size_t)j * FK_NFLD * g.len + r;
+    const int L = g.len;
+    fk::PrimPair p;
+    p.zeta = q[0];
+    p.oo2z = q[L];
+    p.P[0] = q[2 * L]; p.P[1] = q[3 * L]; p.P[2] = q[4 * L];
+    p.PA[0] = q[5 * L]; p.PA[1] = q[6 * L]; p.PA[2] = q[7 * L];
+    p.K = q[8 * L];
+    return p;
+}
+
+struct BraInfo {
+    int sa, sb, ppo, npp;
+    double AB[3], G;
+};
+__device__ __forceinline__ BraInfo load_bra(const FkJKArgs &a, int bra)
+{
+    BraInfo b;
+    b.sa = a.pair_sa[bra];
+    b.sb = a.pair_sb[bra];
+    b.ppo = a.pair_ppoff[bra];
+    b.npp = a.pair_npp[bra];
+    b.AB[0] = a.pair_AB[3 * bra];
+    b.AB[1] = a.pair_AB[3 * bra + 1];
+    b.AB[2] = a.pair_AB[3 * bra + 2];
+    b.G = a.pair_G[bra];
+    return b;
+}
+
+// The bra's primitive records are staged in a per-wave LDS slot once per tile
+// (wave-uniform data read inside the innermost loop).
+
+__device__ __forceinline__ void wave_sync_lds()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+__device__ __forceinline__ void stage_bra(double *s, const double *__restrict pp, int ppo, int npp, int lane)
+{
+    wave_sync_lds();
+    for (int x = lane; x < npp * FK_NFLD; x += 64) {
+        const int i = x / FK_NFLD, f = x - i * FK_NFLD;
+        s[x] = pp[(size_t)(ppo + i) * FK_NPP_REC + f];
+    }
+    wave_sync_lds();
+}
+
+__device__ __forceinline__ fk::PrimPair lds_pp(const double *s, int i)
+{
+    const double *r = s + i * FK_NFLD;
+    fk::PrimPair p;
+    p.zeta = r[0];
+    p.oo2z = r[1];
+    p.P[0] = r[2]; p.P[1] = r[3]; p.P[2] = r[4];
+    p.PA[0] = r[5]; p.PA[1] = r[6]; p.PA[2] = r[7];
+    p.K = r[8];
+    return p;
+}
+
+// position of the n-th set bit of m (n = 0 is the lowest), or -1
+__device__ __forceinline__ int nth_bit(unsigned long long m, int n)
+{
+    for (int k = 0; k < n && m; ++k) m &= m - 1;
+    return m ? __ffsll((long long)m) - 1 : -1;
+}
+
+// Next tile for this wave: tiles are sorted by decreasing estimated cost and
+// claimed one at a time, so long tiles start first and short ones fill in.
+__device__ __forceinline__ int claim_tile(unsigned int *ctr, int lane)
+{
+    unsigned int t = 0;
+    if (lane == 0) t = atomicAdd(ctr, 1u);
+    return __builtin_amdgcn_readfirstlane((int)__shfl((int)t, 0, 64));
+}
+
 // ---------------------------------------------------------------- lpq ----
 // One wave per tile (one bra pair, up to 64 ket pairs); lane i computes the
 // whole contracted quartet (bra | ket_i), consecutive lanes taking consecutive
-// kets, then digests it into the six blocks.
+// kets, then digests it into the six blocks.  Ket primitives are the outer
+// loop (one coalesced load per primitive pair), bra primitives the inner loop
+// (wave-uniform, scalar loads).
 template <int LA, int LB, int LC, int LD>
 __global__ void __launch_bounds__(FK_BLOCK) k_jk_lpq(FkJKArgs a)
 {
     using Q = fk::QClass<LA, LB, LC, LD>;
     constexpr int NA = Q::NA, NB = Q::NB, NC = Q::NC, ND = Q::ND, NOUT = Q::NOUT;
-    __shared__ double s_tab[rys_lds_size(Q::NR)];
+    extern __shared__ double s_dyn[];
+    double *s_tab = s_dyn;
     load_table<Q::NR>(s_tab, a.rys_tab);
 
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    double *s_bra = s_dyn + rys_lds_size(Q::NR) + wave * a.bra_slot;
     const int nwt = gridDim.x * FK_WAVES;
     const int n = a.nbf, ns = a.nshell;
     unsigned long long cq = 0, cp = 0;
 
-    for (int t = blockIdx.x * FK_WAVES + wave; t < a.ntiles; t += nwt) {
+    for (int t = claim_tile(a.tile_next, lane); t < a.ntiles; t = claim_tile(a.tile_next, lane)) {
         const FkTile tile = a.tiles[t];
         const int bra = tile.bra;
-        const int sa = a.pair_sa[bra], sb = a.pair_sb[bra];
-        const int bpo = a.pair_ppoff[bra], bnp = a.pair_npp[bra];
-        const double AB[3] = {a.pair_AB[3 * bra], a.pair_AB[3 * bra + 1], a.pair_AB[3 * bra + 2]};
-        const double Gab = a.pair_G[bra];
-
+        const bool same = (tile.grp & FK_TILE_SAME) != 0;
+        const FkGroup g = a.groups[tile.grp & ~FK_TILE_SAME];
+        const BraInfo B = load_bra(a, bra);
         const bool inrange = lane < tile.ket_count;
-        const int ket = a.ket_list[tile.ket_begin + (inrange ? lane : 0)];
-        const int sc = a.pair_sa[ket], sd = a.pair_sb[ket];
-        const int kpo = a.pair_ppoff[ket], knp = a.pair_npp[ket];
-        const double CD[3] = {a.pair_AB[3 * ket], a.pair_AB[3 * ket + 1], a.pair_AB[3 * ket + 2]};
+        const int pos = tile.ket_begin + (inrange ? lane : 0);
+        const int r = pos - g.begin;
+        const KetInfo Kt = load_ket(a, pos);
+        const int sa = B.sa, sb = B.sb, sc = Kt.sc, sd = Kt.sd;
         bool active = inrange;
-        if (a.dscreen) active = active && (Gab * a.pair_G[ket] * dmax6(a.Dsh, ns, sa, sb, sc, sd) >= a.tau);
+        if (a.dscreen) active = active && (B.G * Kt.G * dmax6(a.Dsh, ns, sa, sb, sc, sd) >= a.tau);
         const unsigned long long mask = __ballot(active);
         if (mask == 0ull) continue;
         const int nact = __popcll(mask);
         cq += nact;
-        cp += (unsigned long long)nact * bnp * knp;
+        cp += (unsigned long long)nact * B.npp * g.npp;
 
+        stage_bra(s_bra, a.pp, B.ppo, B.npp, lane);
         double acc[NOUT];
 #pragma unroll
         for (int o = 0; o < NOUT; ++o) acc[o] = 0.0;
         if (active) {
-            for (int i = 0; i < bnp; ++i) {
-                const fk::PrimPair p = load_pp(a.pp, bpo + i);
-                for (int j = 0; j < knp; ++j) {
-                    const fk::PrimPair q = load_pp(a.pp, kpo + j);
-                    fk::rys_prim_all<LA, LB, LC, LD>(s_tab, p, q, AB, CD, acc);
-                }
+            fk::PrimPair qn = load_ket_pp(a.ppT, g, 0, r);
+            for (int j = 0; j < g.npp; ++j) {
+                const fk::PrimPair q = qn;
+                if (j + 1 < g.npp) qn = load_ket_pp(a.ppT, g, j + 1, r);
+#pragma unroll 2
+                for (int i = 0; i < B.npp; ++i)
+                    fk::rys_prim_all<LA, LB, LC, LD>(s_tab, lds_pp(s_bra, i), q, B.AB, Kt.CD, acc);
             }
         }
 
-        const double fac = (sa == sb ? 0.5 : 1.0) * (sc == sd ? 0.5 : 1.0) *
-                           (((tile.flags & 1) && ket == bra) ? 0.5 : 1.0);
+        const bool diag = same && a.ket_list[pos] == bra;
+        const double fac = (sa == sb ? 0.5 : 1.0) * (sc == sd ? 0.5 : 1.0) * (diag ? 0.5 : 1.0);
         const int oa = a.sh_bf[sa], ob = a.sh_bf[sb], oc = a.sh_bf[sc], od = a.sh_bf[sd];
         double jab[NA * NB];
 #pragma unroll
@@ -242,9 +352,141 @@ __global__ void __launch_bounds__(FK_BLOCK) k_jk_lpq(FkJKArgs a)
     }
 }
 
+// ---------------------------------------------------------------- tpq ----
+// Team per quartet: a team of TS lanes computes one contracted quartet, lane
+// `comp` of the team owning bra component a (MODE 1, TS = NA, all b) or the
+// bra component pair (a, b) (MODE 2, TS = NA NB); a wave holds 64/TS teams,
+// which take consecutive kets of the tile.
+template <int LA, int LB, int LC, int LD, int MODE>
+__global__ void __launch_bounds__(FK_BLOCK) k_jk_tpq(FkJKArgs a)
+{
+    using Q = fk::QClass<LA, LB, LC, LD>;
+    constexpr int NA = Q::NA, NB = Q::NB, NC = Q::NC, ND = Q::ND;
+    constexpr int TS = (MODE == 1) ? NA : NA * NB;
+    constexpr int QPW = 64 / TS;
+    constexpr int NBL = (MODE == 1) ? NB : 1;
+    constexpr int NOL = NBL * NC * ND;
+    static_assert(QPW >= 1, "team larger than a wave");
+    extern __shared__ double s_dyn[];
+    double *s_tab = s_dyn;
+    load_table<Q::NR>(s_tab, a.rys_tab);
+
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    double *s_bra = s_dyn + rys_lds_size(Q::NR) + wave * a.bra_slot;
+    const int nwt = gridDim.x * FK_WAVES;
+    const int n = a.nbf, ns = a.nshell;
+    const int slot = lane / TS, comp = lane % TS;
+    const bool lane_ok = slot < QPW;
+    const int ia = (MODE == 1) ? comp : comp / NB;
+    const int ib0 = (MODE == 1) ? 0 : comp % NB;
+    const int ax[3] = {fk::kCart.x[LA][ia], fk::kCart.y[LA][ia], fk::kCart.z[LA][ia]};
+    const int bx[3] = {fk::kCart.x[LB][ib0], fk::kCart.y[LB][ib0], fk::kCart.z[LB][ib0]};
+    unsigned long long cq = 0, cp = 0;
+
+    for (int t = claim_tile(a.tile_next, lane); t < a.ntiles; t = claim_tile(a.tile_next, lane)) {
+        const FkTile tile = a.tiles[t];
+        const int bra = tile.bra;
+        const bool same = (tile.grp & FK_TILE_SAME) != 0;
+        const FkGroup g = a.groups[tile.grp & ~FK_TILE_SAME];
+        const BraInfo B = load_bra(a, bra);
+        const int sa = B.sa, sb = B.sb;
+        const int oa = a.sh_bf[sa], ob = a.sh_bf[sb];
+        // screen the tile's kets one per lane, then visit only the survivors
+        unsigned long long live;
+        {
+            const bool in = lane < tile.ket_count;
+            const KetInfo K0 = load_ket(a, tile.ket_begin + (in ? lane : 0));
+            bool ok = in;
+            if (a.dscreen) ok = ok && (B.G * K0.G * dmax6(a.Dsh, ns, sa, sb, K0.sc, K0.sd) >= a.tau);
+            live = __ballot(ok);
+        }
+        if (live == 0ull) continue;
+        stage_bra(s_bra, a.pp, B.ppo, B.npp, lane);
+        while (live) {
+            const int kk = lane_ok ? nth_bit(live, slot) : -1;
+#pragma unroll 1
+            for (int x = 0; x < QPW && live; ++x) live &= live - 1;
+            const bool active = kk >= 0;
+            const int pos = tile.ket_begin + (active ? kk : 0);
+            const int r = pos - g.begin;
+            const KetInfo Kt = load_ket(a, pos);
+            const int sc = Kt.sc, sd = Kt.sd;
+            const int nact = __popcll(__ballot(active)) / TS;
+            cq += nact;
+            cp += (unsigned long long)nact * B.npp * g.npp;
+            if (!active) continue;
+            double acc[NOL];
+#pragma unroll
+            for (int o = 0; o < NOL; ++o) acc[o] = 0.0;
+            fk::PrimPair qn = load_ket_pp(a.ppT, g, 0, r);
+            for (int j = 0; j < g.npp; ++j) {
+                const fk::PrimPair q = qn;
+                if (j + 1 < g.npp) qn = load_ket_pp(a.ppT, g, j + 1, r);
+                for (int i = 0; i < B.npp; ++i)
+                    fk::rys_prim_team<LA, LB, LC, LD, MODE>(s_tab, lds_pp(s_bra, i), q, B.AB, Kt.CD, ax, bx, acc);
+            }
+            const bool diag = same && a.ket_list[pos] == bra;
+            const double fac = (sa == sb ? 0.5 : 1.0) * (sc == sd ? 0.5 : 1.0) * (diag ? 0.5 : 1.0);
+            const int oc = a.sh_bf[sc], od = a.sh_bf[sd];
+            const size_t ra = (size_t)(oa + ia) * n;
+            double kac[NC], kad[ND], jcd[NC * ND];
+#pragma unroll
+            for (int ic = 0; ic < NC; ++ic) kac[ic] = 0.0;
+#pragma unroll
+            for (int id = 0; id < ND; ++id) kad[id] = 0.0;
+#pragma unroll
+            for (int o = 0; o < NC * ND; ++o) jcd[o] = 0.0;
+#pragma unroll
+            for (int jb = 0; jb < NBL; ++jb) {
+                const int ib = (MODE == 1) ? jb : ib0;
+                const size_t rb = (size_t)(ob + ib) * n;
+                const double dab = a.Ds[ra + ob + ib];
+                double sj = 0.0;
+#pragma unroll
+                for (int ic = 0; ic < NC; ++ic) {
+                    double kbc = 0.0;
+#pragma unroll
+                    for (int id = 0; id < ND; ++id) {
+                        const double v = fac * acc[(jb * NC + ic) * ND + id];
+                        sj += v * a.Ds[(size_t)(oc + ic) * n + od + id];
+                        jcd[ic * ND + id] += v * dab;
+                        kac[ic] += v * a.Ds[rb + od + id];
+                        kad[id] += v * a.Ds[rb + oc + ic];
+                        kbc += v * a.Ds[ra + od + id];
+                    }
+                    atomic_add(&a.XK[rb + oc + ic], kbc);
+                }
+#pragma unroll
+                for (int id = 0; id < ND; ++id) {
+                    double kbd = 0.0;
+#pragma unroll
+                    for (int ic = 0; ic < NC; ++ic) kbd += fac * acc[(jb * NC + ic) * ND + id] * a.Ds[ra + oc + ic];
+                    atomic_add(&a.XK[rb + od + id], kbd);
+                }
+                atomic_add(&a.XJ[ra + ob + ib], 2.0 * sj);
+            }
+#pragma unroll
+            for (int ic = 0; ic < NC; ++ic) atomic_add(&a.XK[ra + oc + ic], kac[ic]);
+#pragma unroll
+            for (int id = 0; id < ND; ++id) atomic_add(&a.XK[ra + od + id], kad[id]);
+#pragma unroll
+            for (int ic = 0; ic < NC; ++ic)
+#pragma unroll
+                for (int id = 0; id < ND; ++id)
+                    atomic_add(&a.XJ[(size_t)(oc + ic) * n + od + id], 2.0 * jcd[ic * ND + id]);
+        }
+    }
+    if (lane == 0 && cq) {
+        atomicAdd(&a.counters[0], cq);
+        atomicAdd(&a.counters[1], cp);
+    }
+}
+
 // ---------------------------------------------------------------- wpq ----
-// One wave per contracted quartet; lane i owns bra components i, i+64, ...
-// (each with every ket component).  Kets of a tile are visited in turn.
+// One wave per contracted quartet; lane i owns bra component pairs i, i+64,
+// ... (each with every ket component).  Used when a bra component pair block
+// exceeds a wave (f-f bras).
 template <int LA, int LB, int LC, int LD>
 __global__ void __launch_bounds__(FK_BLOCK) k_jk_wpq(FkJKArgs a)
 {
@@ -252,11 +494,13 @@ __global__ void __launch_bounds__(FK_BLOCK) k_jk_wpq(FkJKArgs a)
     constexpr int NB = Q::NB, NC = Q::NC, ND = Q::ND;
     constexpr int NAB = Q::NA * Q::NB, NCD = NC * ND;
     constexpr int ITEMS = (NAB + 63) / 64;
-    __shared__ double s_tab[rys_lds_size(Q::NR)];
+    extern __shared__ double s_dyn[];
+    double *s_tab = s_dyn;
     load_table<Q::NR>(s_tab, a.rys_tab);
 
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    double *s_bra = s_dyn + rys_lds_size(Q::NR) + wave * a.bra_slot;
     const int nwt = gridDim.x * FK_WAVES;
     const int n = a.nbf, ns = a.nshell;
     unsigned long long cq = 0, cp = 0;
@@ -273,38 +517,49 @@ __global__ void __launch_bounds__(FK_BLOCK) k_jk_wpq(FkJKArgs a)
         ibx[k][0] = fk::kCart.x[LB][ib]; ibx[k][1] = fk::kCart.y[LB][ib]; ibx[k][2] = fk::kCart.z[LB][ib];
     }
 
-    for (int t = blockIdx.x * FK_WAVES + wave; t < a.ntiles; t += nwt) {
+    for (int t = claim_tile(a.tile_next, lane); t < a.ntiles; t = claim_tile(a.tile_next, lane)) {
         const FkTile tile = a.tiles[t];
         const int bra = tile.bra;
-        const int sa = a.pair_sa[bra], sb = a.pair_sb[bra];
-        const int bpo = a.pair_ppoff[bra], bnp = a.pair_npp[bra];
-        const double AB[3] = {a.pair_AB[3 * bra], a.pair_AB[3 * bra + 1], a.pair_AB[3 * bra + 2]};
-        const double Gab = a.pair_G[bra];
+        const bool same = (tile.grp & FK_TILE_SAME) != 0;
+        const FkGroup g = a.groups[tile.grp & ~FK_TILE_SAME];
+        const BraInfo B = load_bra(a, bra);
+        const int sa = B.sa, sb = B.sb;
         const int oa = a.sh_bf[sa], ob = a.sh_bf[sb];
-        for (int k = 0; k < tile.ket_count; ++k) {
-            const int ket = a.ket_list[tile.ket_begin + k];
-            const int sc = a.pair_sa[ket], sd = a.pair_sb[ket];
-            if (a.dscreen && Gab * a.pair_G[ket] * dmax6(a.Dsh, ns, sa, sb, sc, sd) < a.tau) continue;
-            const int kpo = a.pair_ppoff[ket], knp = a.pair_npp[ket];
-            const double CD[3] = {a.pair_AB[3 * ket], a.pair_AB[3 * ket + 1], a.pair_AB[3 * ket + 2]};
+        unsigned long long live;
+        {
+            const bool in = lane < tile.ket_count;
+            const KetInfo K0 = load_ket(a, tile.ket_begin + (in ? lane : 0));
+            bool ok = in;
+            if (a.dscreen) ok = ok && (B.G * K0.G * dmax6(a.Dsh, ns, sa, sb, K0.sc, K0.sd) >= a.tau);
+            live = __ballot(ok);
+        }
+        if (live == 0ull) continue;
+        stage_bra(s_bra, a.pp, B.ppo, B.npp, lane);
+        while (live) {
+            const int k = __ffsll((long long)live) - 1;
+            live &= live - 1;
+            const int pos = tile.ket_begin + k;
+            const KetInfo Kt = load_ket(a, pos);
+            const int sc = Kt.sc, sd = Kt.sd;
+            const int r = pos - g.begin;
             cq += 1;
-            cp += (unsigned long long)bnp * knp;
+            cp += (unsigned long long)B.npp * g.npp;
             double acc[ITEMS][NCD];
 #pragma unroll
             for (int it = 0; it < ITEMS; ++it)
 #pragma unroll
                 for (int o = 0; o < NCD; ++o) acc[it][o] = 0.0;
-            for (int i = 0; i < bnp; ++i) {
-                const fk::PrimPair p = load_pp(a.pp, bpo + i);
-                for (int j = 0; j < knp; ++j) {
-                    const fk::PrimPair q = load_pp(a.pp, kpo + j);
+            for (int j = 0; j < g.npp; ++j) {
+                const fk::PrimPair q = load_ket_pp(a.ppT, g, j, r);
+                for (int i = 0; i < B.npp; ++i) {
+                    const fk::PrimPair p = lds_pp(s_bra, i);
 #pragma unroll
                     for (int it = 0; it < ITEMS; ++it)
-                        if (ival[it]) fk::rys_prim_bra_comp<LA, LB, LC, LD>(s_tab, p, q, AB, CD, iax[it], ibx[it], acc[it]);
+                        if (ival[it]) fk::rys_prim_bra_comp<LA, LB, LC, LD>(s_tab, p, q, B.AB, Kt.CD, iax[it], ibx[it], acc[it]);
                 }
             }
-            const double fac = (sa == sb ? 0.5 : 1.0) * (sc == sd ? 0.5 : 1.0) *
-                               (((tile.flags & 1) && ket == bra) ? 0.5 : 1.0);
+            const bool diag = same && a.ket_list[pos] == bra;
+            const double fac = (sa == sb ? 0.5 : 1.0) * (sc == sd ? 0.5 : 1.0) * (diag ? 0.5 : 1.0);
             const int oc = a.sh_bf[sc], od = a.sh_bf[sd];
             double jcd[NCD];
 #pragma unroll
@@ -419,33 +674,91 @@ __global__ void __launch_bounds__(FK_BLOCK) k_debug_wpq(FkDebugArgs a)
     }
 }
 
+template <int LA, int LB, int LC, int LD, int MODE>
+__global__ void __launch_bounds__(FK_BLOCK) k_debug_tpq(FkDebugArgs a)
+{
+    using Q = fk::QClass<LA, LB, LC, LD>;
+    constexpr int NB = Q::NB, NC = Q::NC, ND = Q::ND;
+    constexpr int TS = (MODE == 1) ? Q::NA : Q::NA * Q::NB;
+    constexpr int QPW = 64 / TS;
+    constexpr int NBL = (MODE == 1) ? NB : 1;
+    __shared__ double s_tab[rys_lds_size(Q::NR)];
+    load_table<Q::NR>(s_tab, a.rys_tab);
+    const int lane = threadIdx.x & 63;
+    const int slot = lane / TS, comp = lane % TS;
+    const int q = (blockIdx.x * FK_WAVES + (threadIdx.x >> 6)) * QPW + slot;
+    if (slot >= QPW || q >= a.nq) return;
+    const int ia = (MODE == 1) ? comp : comp / NB;
+    const int ib0 = (MODE == 1) ? 0 : comp % NB;
+    const int ax[3] = {fk::kCart.x[LA][ia], fk::kCart.y[LA][ia], fk::kCart.z[LA][ia]};
+    const int bx[3] = {fk::kCart.x[LB][ib0], fk::kCart.y[LB][ib0], fk::kCart.z[LB][ib0]};
+    const int bra = a.quartets[q].x, ket = a.quartets[q].y;
+    const double AB[3] = {a.pair_AB[3 * bra], a.pair_AB[3 * bra + 1], a.pair_AB[3 * bra + 2]};
+    const double CD[3] = {a.pair_AB[3 * ket], a.pair_AB[3 * ket + 1], a.pair_AB[3 * ket + 2]};
+    double acc[NBL * NC * ND];
+#pragma unroll
+    for (int o = 0; o < NBL * NC * ND; ++o) acc[o] = 0.0;
+    for (int i = 0; i < a.pair_npp[bra]; ++i) {
+        const fk::PrimPair p = load_pp(a.pp, a.pair_ppoff[bra] + i);
+        for (int j = 0; j < a.pair_npp[ket]; ++j)
+            fk::rys_prim_team<LA, LB, LC, LD, MODE>(s_tab, p, load_pp(a.pp, a.pair_ppoff[ket] + j), AB, CD, ax, bx, acc);
+    }
+#pragma unroll
+    for (int jb = 0; jb < NBL; ++jb) {
+        const int ib = (MODE == 1) ? jb : ib0;
+#pragma unroll
+        for (int o = 0; o < NC * ND; ++o)
+            a.out[(size_t)q * Q::NOUT + (ia * NB + ib) * NC * ND + o] = acc[jb * NC * ND + o];
+    }
+}
+
 // --------------------------------------------------------- dispatch ------
 template <int P, int Q>
 struct Disp {
     static constexpr int LA = pair_la(P), LB = pair_lb(P), LC = pair_la(Q), LD = pair_lb(Q);
     static constexpr bool BUILT = LA <= FK_BUILD_MAXL;
-    static constexpr bool WPQ = use_wpq<LA, LB, LC, LD>();
+    static constexpr int KIND = kernel_kind<LA, LB, LC, LD>();
+    static constexpr bool WPQ = KIND == 3;
     static void info(FkClassInfo *i)
     {
         using C = fk::QClass<LA, LB, LC, LD>;
         i->la = LA; i->lb = LB; i->lc = LC; i->ld = LD;
         i->nroot = C::NR; i->nout = C::NOUT;
-        i->wave_per_quartet = WPQ ? 1 : 0;
+        i->wave_per_quartet = KIND;
+        i->team_size = KIND == 0 ? 1 : (KIND == 1 ? C::NA : (KIND == 2 ? C::NA * C::NB : 64));
         i->flops_prim = fk::flops_prim(LA, LB, LC, LD);
         i->flops_quartet = fk::flops_digest(LA, LB, LC, LD);
     }
     static const void *jk_kernel()
     {
         if constexpr (!BUILT) return nullptr;
-        else if constexpr (WPQ) return (const void *)&k_jk_wpq<LA, LB, LC, LD>;
-        else return (const void *)&k_jk_lpq<LA, LB, LC, LD>;
+        else if constexpr (KIND == 0) return (const void *)&k_jk_lpq<LA, LB, LC, LD>;
+        else if constexpr (KIND == 1) return (const void *)&k_jk_tpq<LA, LB, LC, LD, 1>;
+        else if constexpr (KIND == 2) return (const void *)&k_jk_tpq<LA, LB, LC, LD, 2>;
+        else return (const void *)&k_jk_wpq<LA, LB, LC, LD>;
+    }
+    static int lds_bytes(int bra_slot)
+    {
+        using C = fk::QClass<LA, LB, LC, LD>;
+        return (int)sizeof(double) * (rys_lds_size(C::NR) + FK_WAVES * bra_slot);
     }
     static int launch_jk(const FkJKArgs *a, int grid, hipStream_t st)
     {
         if constexpr (!BUILT) return -2;
         else {
-            if constexpr (WPQ) hipLaunchKernelGGL((k_jk_wpq<LA, LB, LC, LD>), dim3(grid), dim3(FK_BLOCK), 0, st, *a);
-            else hipLaunchKernelGGL((k_jk_lpq<LA, LB, LC, LD>), dim3(grid), dim3(FK_BLOCK), 0, st, *a);
+            const int lds = lds_bytes(a->bra_slot);
+            const void *k = jk_kernel();
+            static int raised = 0;
+            if (lds > 65536 && lds > raised) {
+                if (hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, lds) != hipSuccess) return -3;
+                raised = lds;
+            }
+            if constexpr (KIND == 0) hipLaunchKernelGGL((k_jk_lpq<LA, LB, LC, LD>), dim3(grid), dim3(FK_BLOCK), lds, st, *a);
+            else if constexpr (KIND == 1)
+                hipLaunchKernelGGL((k_jk_tpq<LA, LB, LC, LD, 1>), dim3(grid), dim3(FK_BLOCK), lds, st, *a);
+            else if constexpr (KIND == 2)
+                hipLaunchKernelGGL((k_jk_tpq<LA, LB, LC, LD, 2>), dim3(grid), dim3(FK_BLOCK), lds, st, *a);
+            else hipLaunchKernelGGL((k_jk_wpq<LA, LB, LC, LD>), dim3(grid), dim3(FK_BLOCK), lds, st, *a);
             return hipGetLastError() == hipSuccess ? 0 : -3;
         }
     }
@@ -454,9 +767,15 @@ struct Disp {
         if constexpr (!BUILT) return -2;
         else {
             if (a->nq <= 0) return 0;
-            if constexpr (WPQ) {
+            if constexpr (KIND == 3) {
                 const int grid = (a->nq + FK_WAVES - 1) / FK_WAVES;
                 hipLaunchKernelGGL((k_debug_wpq<LA, LB, LC, LD>), dim3(grid), dim3(FK_BLOCK), 0, st, *a);
+            } else if constexpr (KIND == 1 || KIND == 2) {
+                using C = fk::QClass<LA, LB, LC, LD>;
+                constexpr int TS = (KIND == 1) ? C::NA : C::NA * C::NB;
+                constexpr int QPB = (64 / TS) * FK_WAVES;
+                const int grid = (a->nq + QPB - 1) / QPB;
+                hipLaunchKernelGGL((k_debug_tpq<LA, LB, LC, LD, KIND>), dim3(grid), dim3(FK_BLOCK), 0, st, *a);
             } else {
                 const int grid = (a->nq + FK_BLOCK - 1) / FK_BLOCK;
                 hipLaunchKernelGGL((k_debug_lpq<LA, LB, LC, LD>), dim3(grid), dim3(FK_BLOCK), 0, st, *a);
@@ -486,7 +805,23 @@ struct Disp {
             for (int i = 0; i < npp[bra]; ++i)
                 for (int j = 0; j < npp[ket]; ++j) {
                     const fk::PrimPair p = ld(ppoff[bra] + i), qq = ld(ppoff[ket] + j);
-                    if constexpr (WPQ) {
+                    if constexpr (KIND == 1 || KIND == 2) {
+                        constexpr int TS = (KIND == 1) ? C::NA : C::NA * C::NB;
+                        constexpr int NBL = (KIND == 1) ? C::NB : 1;
+                        for (int comp = 0; comp < TS; ++comp) {
+                            const int ia = (KIND == 1) ? comp : comp / C::NB;
+                            const int ib0 = (KIND == 1) ? 0 : comp % C::NB;
+                            const int ax[3] = {fk::kCart.x[LA][ia], fk::kCart.y[LA][ia], fk::kCart.z[LA][ia]};
+                            const int bx[3] = {fk::kCart.x[LB][ib0], fk::kCart.y[LB][ib0], fk::kCart.z[LB][ib0]};
+                            double tmp[NBL * C::NC * C::ND] = {};
+                            fk::rys_prim_team<LA, LB, LC, LD, KIND>(tab, p, qq, AB + 3 * bra, AB + 3 * ket, ax, bx, tmp);
+                            for (int jb = 0; jb < NBL; ++jb) {
+                                const int ib = (KIND == 1) ? jb : ib0;
+                                for (int x = 0; x < C::NC * C::ND; ++x)
+                                    o[(ia * C::NB + ib) * C::NC * C::ND + x] += tmp[jb * C::NC * C::ND + x];
+                            }
+                        }
+                    } else if constexpr (WPQ) {
                         for (int it = 0; it < C::NA * C::NB; ++it) {
                             const int ia = it / C::NB, ib = it % C::NB;
                             const int ax[3] = {fk::kCart.x[LA][ia], fk::kCart.y[LA][ia], fk::kCart.z[LA][ia]};
@@ -536,6 +871,12 @@ int host_q(int q, const int *o, const int *n, const double *ab, const double *pp
     else return q == Q ? Disp<P, Q>::debug_host(o, n, ab, pp, qs, nq, out) : host_q<P, Q + 1>(q, o, n, ab, pp, qs, nq, out);
 }
 template <int P, int Q = 0>
+int lds_q(int q, int slot)
+{
+    if constexpr (Q > P) return -1;
+    else return q == Q ? Disp<P, Q>::lds_bytes(slot) : lds_q<P, Q + 1>(q, slot);
+}
+template <int P, int Q = 0>
 const void *kern_q(int q)
 {
     if constexpr (Q > P) return nullptr;
@@ -559,6 +900,7 @@ int FK_CAT(fk_kp, FK_ONLY_P, _host)(int Q, const int *o, const int *n, const dou
     return host_q<FK_ONLY_P>(Q, o, n, ab, pp, qs, nq, out);
 }
 const void *FK_CAT(fk_kp, FK_ONLY_P, _kern)(int Q) { return kern_q<FK_ONLY_P>(Q); }
+int FK_CAT(fk_kp, FK_ONLY_P, _lds)(int Q, int slot) { return lds_q<FK_ONLY_P>(Q, slot); }
 }
 #else
 // ---- common translation unit: small kernels and the dispatch tables ----
@@ -611,7 +953,8 @@ __global__ void k_finalize(const double *__restrict XJ, const double *__restrict
     int fk_kp##P##_dbg(int, const FkDebugArgs *, void *);                                                    \
     int fk_kp##P##_host(int, const int *, const int *, const double *, const double *, const int *, int,    \
                         double *);                                                                           \
-    const void *fk_kp##P##_kern(int);
+    const void *fk_kp##P##_kern(int);                                                                        \
+    int fk_kp##P##_lds(int, int);
 extern "C" {
 FK_DECL_P(0) FK_DECL_P(1) FK_DECL_P(2) FK_DECL_P(3) FK_DECL_P(4)
 FK_DECL_P(5) FK_DECL_P(6) FK_DECL_P(7) FK_DECL_P(8) FK_DECL_P(9)
@@ -657,12 +1000,21 @@ static const void *kern_of(int P, int Q)
     return nullptr;
 }
 
-int fk_kernels_max_blocks(int P, int Q, int *blocks_per_cu)
+int fk_kernels_jk_lds_bytes(int P, int Q, int bra_slot)
+{
+    FK_SWITCH_P(P, lds(Q, bra_slot))
+    return -1;
+}
+
+int fk_kernels_max_blocks(int P, int Q, int dyn_lds_bytes, int *blocks_per_cu)
 {
     const void *k = kern_of(P, Q);
     if (!k) return -2;
     int nb = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k, FK_BLOCK, 0) != hipSuccess) return -3;
+    if (dyn_lds_bytes > 65536 &&
+        hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, dyn_lds_bytes) != hipSuccess)
+        return -3;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k, FK_BLOCK, dyn_lds_bytes) != hipSuccess) return -3;
     *blocks_per_cu = nb;
     return 0;
 }

@@ -38,18 +38,18 @@ FK_HD void rys_roots_from(double T, const double *__restrict tab, const double *
                           const double *__restrict gw, double *u, double *w)
 {
     constexpr int NF = 2 * N;
-    // table path, evaluated at T clamped into the table's range; the region
-    // of T fixes the interval width (finer at small T)
+    // table path, evaluated at T clamped into the table's range.  Region k =
+    // floor(T/16) (k <= 3) has interval width 2^(k-1) and starts at interval
+    // 64 - 2^(6-k).
     const double Tc = T < RYS_TMAX ? T : 0.0;
-    static_assert(RYS_NREG == 4, "region selection below assumes four regions");
-    double t0 = RYS_REG0_T0, ih = RYS_REG0_INVH;
-    int base = RYS_REG0_BASE;
-    if (Tc >= RYS_REG1_T0) { t0 = RYS_REG1_T0; ih = RYS_REG1_INVH; base = RYS_REG1_BASE; }
-    if (Tc >= RYS_REG2_T0) { t0 = RYS_REG2_T0; ih = RYS_REG2_INVH; base = RYS_REG2_BASE; }
-    if (Tc >= RYS_REG3_T0) { t0 = RYS_REG3_T0; ih = RYS_REG3_INVH; base = RYS_REG3_BASE; }
-    const double y = (Tc - t0) * ih;
+    static_assert(RYS_NREG == 4 && RYS_REG1_T0 == 16.0 && RYS_REG1_INVH == 1.0 && RYS_REG3_BASE == 56,
+                  "closed-form region selection assumes the generated four-region layout");
+    int k = (int)(Tc * (1.0 / 16.0));
+    k = k < 3 ? k : 3;
+    const double ih = (double)(2 >> k) + (k == 3 ? 0.25 : 0.0) + (k == 2 ? 0.5 : 0.0);
+    const double y = (Tc - 16.0 * k) * ih;
     const int j = (int)y;
-    const int iv = base + j;
+    const int iv = 64 - (64 >> k) + j;
     const double x = 2.0 * (y - j) - 1.0;
     const double *c = tab + iv * ((RYS_DEG + 1) * NF);
 #pragma unroll

@@ -123,13 +123,14 @@ def _blocks(s, seed, n=6):
     return pairs
 
 
-@pytest.mark.parametrize("tau", [0.0, 1e-10])
-def test_jk_c20h42_sampled_blocks(fk, torch, c2, tau):
+@pytest.mark.parametrize("tau,tau_prim", [(0.0, 0.0), (1e-10, 0.0), (1e-10, 1e-12)])
+def test_jk_c20h42_sampled_blocks(fk, torch, c2, tau, tau_prim):
     """C20H42 6-31G*-type (384 functions), full size, core-Hamiltonian density,
-    in the configuration the benchmark times (tau = 1e-10, density screen);
-    sampled shell blocks of J and K against the oracle's literal sums."""
+    unscreened and in the configuration the benchmark times (tau = 1e-10 with
+    the density screen, primitive pairs pruned at 1e-12); sampled shell blocks
+    of J and K against the oracle's literal (unscreened) sums."""
     s, D = c2
-    J, K, c = _gpu_jk(fk, torch, s, D, tau=tau)
+    J, K, c = _gpu_jk(fk, torch, s, D, tau=tau, tau_prim=tau_prim)
     assert np.allclose(J, J.T, atol=1e-13) and np.allclose(K, K.T, atol=1e-13)
     off = oracle.bf_offsets(s)
     jp = _blocks(s, 1)
