@@ -180,6 +180,12 @@ int fk_run_scf(fk_ctx *ctx, const fk_scf_opts *opts, fk_scf_result *result, doub
  * production per-quartet code, 0 evaluates the same code on the host. */
 int fk_debug_eri(fk_ctx *ctx, int nq, const int *quartets, double *out, int on_device);
 
+/* Host-side check of every address the J/K kernels will form for the current
+ * quartet lists (list positions, primitive records, LDS slots, density and
+ * Fock indices).  FK_OK, or FK_ERR_STATE with the first violation in
+ * fk_last_error.  Intended for tests and diagnostics. */
+int fk_check_indices(fk_ctx *ctx);
+
 /* Rys roots u[n] and weights w[n] for argument T from the library's tables,
  * evaluated on the host (n = 1..7). */
 int fk_rys_host(int n, double T, double *u, double *w);

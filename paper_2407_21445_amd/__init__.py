@@ -74,6 +74,7 @@ _sig = {
     "fk_run_scf": ([_P, ctypes.POINTER(ScfOpts), ctypes.POINTER(ScfResult), _P], _I),
     "fk_debug_eri": ([_P, _I, _P, _P, _I], _I),
     "fk_rys_host": ([_I, _D, _P, _P], _I),
+    "fk_check_indices": ([_P], _I),
 }
 EXPORTS = tuple(_sig)
 for _name, (_args, _res) in _sig.items():
@@ -221,6 +222,8 @@ class FockJK:
         return res
 
     # ---- diagnostics ----
+    def check_indices(self):
+        self._check(_lib.fk_check_indices(self._ctx))
     def debug_eri(self, quartets, on_device=True):
         q = np.ascontiguousarray(np.asarray(quartets, dtype=np.int32).reshape(-1, 4))
         shapes = [tuple(_ncart(int(self.sh_l[s])) for s in row) for row in q]

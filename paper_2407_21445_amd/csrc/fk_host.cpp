@@ -962,6 +962,61 @@ int fk_debug_eri(fk_ctx *c, int nq, const int *quartets, double *out, int on_dev
 
 int fk_rys_host(int n, double T, double *u, double *w);
 
+// Walks every tile the J/K kernels will visit and checks each address they
+// form (list positions, transposed and bra primitive records, LDS slot,
+// density, shell-block maxima and Fock accumulators) against its array.
+// Returns FK_OK or FK_ERR_STATE with the first violation in fk_last_error.
+int fk_check_indices(fk_ctx *c)
+{
+    if (!c) return FK_ERR_ARG;
+    if (!c->have_quartets) return fail(c, FK_ERR_STATE, "fk_check_indices: no quartet lists");
+    const long long n = c->nbf, ns = c->nshell, nl = (long long)c->ket_list_all.size();
+    const long long npair = (long long)c->pr_sa.size(), nppr = (long long)(c->pp.size() / FK_NPP_REC);
+    const long long nT = (long long)c->ppT.size();
+    for (size_t qi = 0; qi < c->qclasses.size(); ++qi) {
+        const QuartetClass &qc = c->qclasses[qi];
+        const int NA = ncart(qc.info.la), NB = ncart(qc.info.lb), NC = ncart(qc.info.lc), ND = ncart(qc.info.ld);
+        for (int64_t t = qc.tile_off; t < qc.tile_off + qc.ntile; ++t) {
+            const FkTile &T = c->tiles[t];
+            const long long gid = T.grp & ~FK_TILE_SAME;
+            if (T.bra < 0 || T.bra >= npair || gid < 0 || gid >= (long long)c->groups.size())
+                return fail(c, FK_ERR_STATE, "class %zu tile %lld: bra/group out of range", qi, (long long)t);
+            const FkGroup &g = c->groups[gid];
+            const int sa = c->pr_sa[T.bra], sb = c->pr_sb[T.bra];
+            const long long ppo = c->pr_ppoff[T.bra], bnp = c->pr_npp[T.bra];
+            if (ppo < 0 || ppo + bnp > nppr) return fail(c, FK_ERR_STATE, "tile %lld: bra records", (long long)t);
+            if (bnp * FK_NFLD > qc.bra_slot) return fail(c, FK_ERR_STATE, "tile %lld: LDS bra slot", (long long)t);
+            const long long oa = c->sh_bf[sa], ob = c->sh_bf[sb];
+            if (oa + NA > n || ob + NB > n || ncart(c->sh_l[sa]) != NA || ncart(c->sh_l[sb]) != NB)
+                return fail(c, FK_ERR_STATE, "tile %lld: bra shells do not match the class", (long long)t);
+            if (T.ket_count < 1 || T.ket_count > 64)
+                return fail(c, FK_ERR_STATE, "tile %lld: ket count %d", (long long)t, T.ket_count);
+            for (int k = 0; k < 64; ++k) {
+                // every lane reads position ket_begin + (lane < count ? lane : 0)
+                const long long pos = T.ket_begin + (k < T.ket_count ? k : 0);
+                if (pos < 0 || pos >= nl) return fail(c, FK_ERR_STATE, "tile %lld lane %d: position %lld", (long long)t, k, pos);
+                const long long r = pos - g.begin;
+                if (r < 0 || r >= g.len) return fail(c, FK_ERR_STATE, "tile %lld lane %d: outside its group", (long long)t, k);
+                const long long kp = c->ket_list_all[pos];
+                if (kp < 0 || kp >= npair) return fail(c, FK_ERR_STATE, "tile %lld lane %d: ket pair", (long long)t, k);
+                const int sc = c->lst_sa[pos], sd = c->lst_sb[pos];
+                if (sc != c->pr_sa[kp] || sd != c->pr_sb[kp])
+                    return fail(c, FK_ERR_STATE, "tile %lld lane %d: list data disagree with the pair", (long long)t, k);
+                if (ncart(c->sh_l[sc]) != NC || ncart(c->sh_l[sd]) != ND || c->pr_npp[kp] != g.npp)
+                    return fail(c, FK_ERR_STATE, "tile %lld lane %d: ket does not match class/group", (long long)t, k);
+                const long long last = g.base + ((long long)(g.npp - 1) * FK_NFLD + FK_NFLD - 1) * g.len + r;
+                if (g.base < 0 || last >= nT) return fail(c, FK_ERR_STATE, "tile %lld lane %d: ket records", (long long)t, k);
+                const long long oc = c->sh_bf[sc], od = c->sh_bf[sd];
+                if (oc + NC > n || od + ND > n) return fail(c, FK_ERR_STATE, "tile %lld lane %d: ket functions", (long long)t, k);
+                const long long dsh[6] = {sa * ns + sb, sc * ns + sd, sa * ns + sc, sa * ns + sd, sb * ns + sc, sb * ns + sd};
+                for (long long x : dsh)
+                    if (x < 0 || x >= ns * ns) return fail(c, FK_ERR_STATE, "tile %lld lane %d: shell block", (long long)t, k);
+            }
+        }
+    }
+    return FK_OK;
+}
+
 // One-electron integrals on the host.  Overlap and kinetic energy by the
 // Obara-Saika 1-D recurrences; nuclear attraction by Rys quadrature of the
 // one-centre operator: V_ab = -Z_C (2 pi/p) K_AB sum_r w_r Ix Iy Iz with

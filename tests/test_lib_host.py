@@ -151,3 +151,23 @@ def test_argument_validation():
     with pytest.raises(fk.FockJKError) as e:  # host-only context has no device
         c.build_jk(np.eye(2))
     assert e.value.code == fk.FK_ERR_STATE
+
+
+@pytest.mark.parametrize("name,tau,tau_prim", [
+    ("spdf", 0.0, 0.0), ("water4", 1e-10, 1e-12),
+    ("c20h42", 0.0, 0.0), ("c20h42", 1e-10, 0.0), ("c20h42", 1e-10, 1e-12)])
+def test_kernel_indices_in_bounds(name, tau, tau_prim):
+    """Every address the J/K kernels form from the tile, list, group and pair
+    tables (positions, transposed ket records, bra records and their LDS slot,
+    density, shell-block maxima, Fock accumulators) lies inside its array, for
+    the test systems and the full-size benchmark configurations."""
+    if name == "spdf":
+        s = _rand_sys(33, lmax=3, natom=3, kmax=2)
+        s["charge"] = 1
+    elif name == "water4":
+        s = wl.water4_sto3g()
+    else:
+        s = wl.c20h42_631gs()
+    c = fk.FockJK(device=-1).set_system(s).build_quartets(tau=tau, tau_prim=tau_prim)
+    c.check_indices()
+    assert c.info()["ntile"] > 0
