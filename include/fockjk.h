@@ -36,7 +36,8 @@
  *   Every function returns an fk_status (0 = success).  Arguments are fully
  *   validated on the host before any device work; nothing throws across the
  *   ABI.  fk_last_error returns a message describing the last failure of the
- *   context (valid until the next call on it).
+ *   context (valid until the next call on it); fk_last_error(NULL) describes
+ *   the last failed fk_create on the calling thread.
  */
 #ifndef FOCKJK_H
 #define FOCKJK_H

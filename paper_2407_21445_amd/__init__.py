@@ -18,6 +18,15 @@ if not os.path.exists(LIB_PATH):
     raise ImportError(f"libfockjk.so not built at {LIB_PATH}; run __graft_entry__.build() "
                       "(or python -m paper_2407_21445_amd.build)")
 
+# One HIP runtime per process.  PyTorch ships its own copy of the runtime
+# (linked by its unversioned name); loading the library first would pull in the
+# system copy as well, and two runtimes in one process do not share the device.
+# Importing torch first makes the library bind to the copy torch has loaded.
+try:
+    import torch as _torch  # noqa: F401
+except ImportError:  # host-only use (tables, validation) without PyTorch
+    _torch = None
+
 _lib = ctypes.CDLL(LIB_PATH)
 
 FK_OK, FK_ERR_ARG, FK_ERR_UNSUPPORTED, FK_ERR_HIP, FK_ERR_OOM, FK_ERR_NOT_CONVERGED, FK_ERR_STATE = 0, -1, -2, -3, -4, -5, -6
@@ -116,7 +125,7 @@ class FockJK:
         self._ctx = ctypes.c_void_p()
         rc = _lib.fk_create(ctypes.byref(self._ctx), int(device))
         if rc:
-            raise FockJKError(rc, f"fk_create(device={device}) failed")
+            raise FockJKError(rc, f"fk_create(device={device}) failed: " + _lib.fk_last_error(None).decode())
         self.device = device
         self.nbf = 0
         self._keep = []

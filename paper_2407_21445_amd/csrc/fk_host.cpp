@@ -415,23 +415,39 @@ int upload_pairs(fk_ctx *c)
 
 extern "C" {
 
+// failure message of the last fk_create on this thread (there is no context yet)
+static thread_local std::string g_create_err;
+
 int fk_create(fk_ctx **out, int device)
 {
     if (!out) return FK_ERR_ARG;
     *out = nullptr;
+    g_create_err.clear();
     fk_ctx *c = new fk_ctx();
     c->device = device;
     if (device >= 0) {
         int ndev = 0;
-        if (hipGetDeviceCount(&ndev) != hipSuccess || device >= ndev) {
+        hipError_t e = hipGetDeviceCount(&ndev);
+        if (e == hipSuccess && device >= ndev) {
+            g_create_err = "fk_create: device " + std::to_string(device) + " of " + std::to_string(ndev);
+            delete c;
+            return FK_ERR_ARG;
+        }
+        const char *what = "hipGetDeviceCount";
+        if (e == hipSuccess) { what = "hipSetDevice"; e = hipSetDevice(device); }
+        hipDeviceProp_t prop;
+        if (e == hipSuccess) { what = "hipGetDeviceProperties"; e = hipGetDeviceProperties(&prop, device); }
+        if (e != hipSuccess) {
+            g_create_err = std::string("fk_create: ") + what + ": " + hipGetErrorString(e);
             delete c;
             return FK_ERR_HIP;
         }
-        if (hipSetDevice(device) != hipSuccess) { delete c; return FK_ERR_HIP; }
-        hipDeviceProp_t prop;
-        if (hipGetDeviceProperties(&prop, device) != hipSuccess) { delete c; return FK_ERR_HIP; }
         c->ncu = prop.multiProcessorCount;
-        if (dev_upload(c, c->d_rys, rys_staged_host(), (size_t)rys_staged_total())) { delete c; return FK_ERR_OOM; }
+        if (dev_upload(c, c->d_rys, rys_staged_host(), (size_t)rys_staged_total())) {
+            g_create_err = c->err;
+            delete c;
+            return FK_ERR_OOM;
+        }
     }
     *out = c;
     return FK_OK;
@@ -448,7 +464,7 @@ void fk_destroy(fk_ctx *c)
     delete c;
 }
 
-const char *fk_last_error(const fk_ctx *c) { return c ? c->err.c_str() : "null context"; }
+const char *fk_last_error(const fk_ctx *c) { return c ? c->err.c_str() : g_create_err.c_str(); }
 
 int fk_set_geometry(fk_ctx *c, int natom, const int *Z, const double *xyz, int charge)
 {
