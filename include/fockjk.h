@@ -91,7 +91,9 @@ typedef struct {
                                 were removed by the density screen */
 } fk_info_t;
 
-/* Per-build statistics of the last fk_build_jk (filled by fk_stats). */
+/* Per-build statistics of the last fk_build_jk (filled by fk_stats).  On a
+ * context without a device, or before the first build, only the host-side
+ * fields (class, tiles, prim_slots, flops per unit) are filled. */
 #define FK_MAX_QCLASS 55
 typedef struct {
     int     nclass;                       /* quartet classes launched */
@@ -102,6 +104,13 @@ typedef struct {
     double  flops_per_quartet[FK_MAX_QCLASS]; /* per contracted quartet (digestion) */
     double  flops_total;                  /* algorithmic flops of the build */
     double  class_ms[FK_MAX_QCLASS];      /* kernel time per class (FK_TIME_CLASSES builds), else 0 */
+    int64_t tiles[FK_MAX_QCLASS];         /* work tiles of the class */
+    int     team_size[FK_MAX_QCLASS];     /* lanes computing one quartet (1, a team, or 64) */
+    int64_t prim_slots[FK_MAX_QCLASS];    /* lane x primitive-quartet slots the waves step
+                                             through if no quartet fails the density screen:
+                                             per tile, rounds x 64 lanes x bra x ket primitive
+                                             pairs.  prim_quartets * team_size / prim_slots is
+                                             the lane utilisation of the primitive loops */
 } fk_stats_t;
 
 /* ---- context ---------------------------------------------------------- */

@@ -55,7 +55,8 @@ class Stats(ctypes.Structure):
                 ("lc", ctypes.c_int * _Q), ("ld", ctypes.c_int * _Q), ("quartets", ctypes.c_int64 * _Q),
                 ("prim_quartets", ctypes.c_int64 * _Q), ("flops_per_prim", ctypes.c_double * _Q),
                 ("flops_per_quartet", ctypes.c_double * _Q), ("flops_total", ctypes.c_double),
-                ("class_ms", ctypes.c_double * _Q)]
+                ("class_ms", ctypes.c_double * _Q), ("tiles", ctypes.c_int64 * _Q),
+                ("team_size", ctypes.c_int * _Q), ("prim_slots", ctypes.c_int64 * _Q)]
 
 
 class ScfOpts(ctypes.Structure):
@@ -206,7 +207,9 @@ class FockJK:
         for i in range(s.nclass):
             out.append({"class": (s.la[i], s.lb[i], s.lc[i], s.ld[i]), "quartets": s.quartets[i],
                         "prim_quartets": s.prim_quartets[i], "flops_per_prim": s.flops_per_prim[i],
-                        "flops_per_quartet": s.flops_per_quartet[i], "ms": s.class_ms[i]})
+                        "flops_per_quartet": s.flops_per_quartet[i], "ms": s.class_ms[i],
+                        "tiles": s.tiles[i], "team_size": s.team_size[i],
+                        "prim_slots": s.prim_slots[i]})
         return {"classes": out, "flops_total": s.flops_total,
                 "quartets": sum(c["quartets"] for c in out), "prim_quartets": sum(c["prim_quartets"] for c in out)}
 

@@ -42,6 +42,7 @@ struct QuartetClass {
     FkClassInfo info;
     int64_t tile_off, ntile;
     int64_t nquartet, nprim;  // Schwarz-surviving counts
+    int64_t prim_slots;       // primitive-quartet slots the waves step through
     int blocks_per_cu;
     int bra_slot;             // doubles per wave of staged bra primitive records
 };
@@ -672,7 +673,7 @@ int fk_build_quartets(fk_ctx *c, const fk_screen_opts *o)
             if (fk_kernels_class_info(P, Q, &qc.info))
                 return fail(c, FK_ERR_UNSUPPORTED, "quartet class (%d|%d) is not built into this library", P, Q);
             qc.tile_off = (int64_t)c->tiles.size();
-            qc.nquartet = 0; qc.nprim = 0;
+            qc.nquartet = 0; qc.nprim = 0; qc.prim_slots = 0;
             // kets per tile: a full wave of kets for lane-per-quartet kernels, two
             // rounds of teams for team kernels, two kets for wave-per-quartet
             const int ts = std::max(1, qc.info.team_size);
@@ -701,6 +702,11 @@ int fk_build_quartets(fk_ctx *c, const fk_screen_opts *o)
                         t.ket_count = std::min(tile_kets, cnt - k);
                         t.grp = (c->cls_group0[Q] + (int)gi) | ((P == Q) ? FK_TILE_SAME : 0);
                         c->tiles.push_back(t);
+                        // lane slots of the tile's primitive loops: rounds of
+                        // (quartets per wave) kets, 64 lanes each
+                        const int qpw = qc.info.wave_per_quartet == 0 ? 64 : (qc.info.wave_per_quartet == 3 ? 1 : 64 / ts);
+                        const int64_t rounds = (t.ket_count + qpw - 1) / qpw;
+                        qc.prim_slots += rounds * 64 * c->pr_npp[bra] * c->pr_npp[LQ[g.first]];
                     }
                     qc.nquartet += cnt;
                     qc.nprim += (int64_t)cnt * c->pr_npp[bra] * c->pr_npp[LQ[g.first]];
@@ -746,6 +752,7 @@ int fk_build_quartets(fk_ctx *c, const fk_screen_opts *o)
         if ((rc = dev_upload<unsigned int>(c, c->d_tilectr, nullptr, 2 * FK_MAX_QCLASS))) return rc;
     }
     c->have_quartets = true;
+    c->stats_pending = false;
     return FK_OK;
 }
 
@@ -866,11 +873,13 @@ int fk_stats(fk_ctx *c, fk_stats_t *s)
 {
     if (!c || !s) return FK_ERR_ARG;
     std::memset(s, 0, sizeof *s);
-    if (!c->have_quartets || c->device < 0) return fail(c, FK_ERR_STATE, "fk_stats: no build on this context");
-    hipSetDevice(c->device);
+    if (!c->have_quartets) return fail(c, FK_ERR_STATE, "fk_stats: call fk_build_quartets first");
     std::vector<unsigned long long> cnt(2 * FK_MAX_QCLASS, 0);
-    HIPCHK(c, hipDeviceSynchronize());
-    HIPCHK(c, hipMemcpy(cnt.data(), c->d_cnt.p, cnt.size() * sizeof(unsigned long long), hipMemcpyDeviceToHost));
+    if (c->device >= 0 && c->stats_pending) {
+        hipSetDevice(c->device);
+        HIPCHK(c, hipDeviceSynchronize());
+        HIPCHK(c, hipMemcpy(cnt.data(), c->d_cnt.p, cnt.size() * sizeof(unsigned long long), hipMemcpyDeviceToHost));
+    }
     s->nclass = (int)c->qclasses.size();
     for (size_t i = 0; i < c->qclasses.size(); ++i) {
         const auto &q = c->qclasses[i];
@@ -879,6 +888,9 @@ int fk_stats(fk_ctx *c, fk_stats_t *s)
         s->prim_quartets[i] = (int64_t)cnt[2 * i + 1];
         s->flops_per_prim[i] = q.info.flops_prim;
         s->flops_per_quartet[i] = q.info.flops_quartet;
+        s->tiles[i] = q.ntile;
+        s->team_size[i] = q.info.wave_per_quartet == 3 ? 64 : std::max(1, q.info.team_size);
+        s->prim_slots[i] = q.prim_slots;
         s->flops_total += s->prim_quartets[i] * q.info.flops_prim + s->quartets[i] * q.info.flops_quartet;
         if (c->timed && 2 * i + 1 < c->ev.size()) {
             float ms = 0;
