@@ -86,6 +86,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--classes", action="store_true", help="print the per-class kernel table to stderr")
+    ap.add_argument("--no-scf", action="store_true", help="skip the SCF run reported beside the build rate")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported", file=sys.stderr)
@@ -163,6 +164,12 @@ def main():
                      "kernel": f"J/K class {cname}", "kernel_ms": float(cls_ms[i]),
                      "class_share": float(cls_ms[i] / cls_ms.sum())},
     }
+    if not args.no_scf:
+        # SCF from the core-Hamiltonian guess on the same quartet lists (outside
+        # the timed region): iterations to |dE| < 1e-10, max|error| < 1e-8
+        r = ctx.run_scf()
+        out["scf"] = {"iterations": r["iterations"], "converged": bool(r["converged"]), "energy": r["energy"],
+                      "seconds": r["total_seconds"], "jk_seconds": r["jk_seconds"], "guess": "core Hamiltonian"}
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(sys_, D, args.cpu_seconds)
     print(json.dumps(out), flush=True)

@@ -160,26 +160,38 @@ int fk_one_electron(fk_ctx *ctx, double *S, double *T, double *V, double *e_nuc)
 typedef struct {
     int    max_iter;     /* default 100 */
     double e_tol;        /* |dE| threshold, default 1e-10 */
-    double g_tol;        /* max |X^T (FDS - SDF) X| threshold, default 1e-8 */
-    int    diis_n;       /* DIIS subspace size, default 8 */
+    double g_tol;        /* max |X (FDS - SDF) X| threshold, default 1e-8 */
+    int    diis_n;       /* DIIS subspace size (0 or 1: no DIIS), default 8, at most 32 */
     int    guess;        /* 0 = core Hamiltonian, 1 = density given in D_inout */
-    double lindep;       /* overlap eigenvalue cutoff, default 1e-8 */
+    double lindep;       /* required accuracy of the orthogonaliser: max |Z S Z - I|
+                            with Z = S^(-1/2) from the Newton-Schulz iteration;
+                            fails with FK_ERR_ARG for an overlap matrix too
+                            ill-conditioned to reach it.  Default 1e-8 */
 } fk_scf_opts;
 
 typedef struct {
-    double energy;       /* total energy (hartree) */
+    double energy;       /* total energy (hartree) of the last density */
     double e_nuc;
     int    iterations;   /* Fock builds performed */
     int    converged;
     double jk_seconds;   /* wall time spent in fk_build_jk */
     double total_seconds;
+    double error;        /* max |X (FDS - SDF) X| at the last iteration */
+    double delta_e;      /* energy change of the last iteration */
 } fk_scf_result;
 
-/* Restricted closed-shell SCF: F = h + J - K/2, FC = SC eps, Pulay DIIS.
- * J/K run on the device; the small dense linear algebra runs on the host.
- * D_inout (host, nbf x nbf) holds the guess when opts->guess == 1 and the
- * converged density on return.  Returns FK_ERR_NOT_CONVERGED (with the
- * result filled) if max_iter is reached. */
+/* Restricted closed-shell SCF (paper: "Hartree-Fock Energy Formulation"):
+ * F = h + J - K/2 with J, K from fk_build_jk on the quartet lists of the last
+ * fk_build_quartets; E = (D.h + D.F)/2 + E_nuc; Pulay DIIS on the commutator
+ * X (FDS - SDF) X.  Every per-iteration matrix step runs on the device: the
+ * orthogonaliser X = S^(-1/2) comes from a Newton-Schulz iteration, and the
+ * density D = 2 X P X from trace-correcting purification of X F X (P the
+ * projector onto the nelec/2 lowest states), so no eigensolver is used; the
+ * host solves the small DIIS system.  Converged when |dE| < e_tol and the
+ * error < g_tol.  D_inout (host, nbf x nbf, row-major) holds the guess when
+ * opts->guess == 1 and the final density on return.  opts may be NULL
+ * (defaults).  Returns FK_ERR_NOT_CONVERGED (with the result filled) if
+ * max_iter is reached, or if the purification finds no gap. */
 int fk_run_scf(fk_ctx *ctx, const fk_scf_opts *opts, fk_scf_result *result, double *D_inout);
 
 /* ---- diagnostics -------------------------------------------------------- */

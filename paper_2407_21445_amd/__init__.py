@@ -66,7 +66,8 @@ class ScfOpts(ctypes.Structure):
 
 class ScfResult(ctypes.Structure):
     _fields_ = [("energy", ctypes.c_double), ("e_nuc", ctypes.c_double), ("iterations", ctypes.c_int),
-                ("converged", ctypes.c_int), ("jk_seconds", ctypes.c_double), ("total_seconds", ctypes.c_double)]
+                ("converged", ctypes.c_int), ("jk_seconds", ctypes.c_double), ("total_seconds", ctypes.c_double),
+                ("error", ctypes.c_double), ("delta_e", ctypes.c_double)]
 
 
 _P, _I, _D, _U = ctypes.c_void_p, ctypes.c_int, ctypes.c_double, ctypes.c_uint

@@ -1166,10 +1166,284 @@ int fk_one_electron(fk_ctx *c, double *S, double *T, double *V, double *e_nuc)
     return FK_OK;
 }
 
+// ---------------------------------------------------------------- SCF ----
+// Restricted closed-shell SCF around the device J/K build.  Every per-iteration
+// matrix operation is a device kernel (fk_scf.hip): F = h + J - K/2, the
+// energy, F' = X F X, the DIIS commutator F'D' - D'F' and its inner products,
+// the DIIS combination, the purification that turns F' into the density and
+// D = X D' X.  The host solves the (m+1) x (m+1) DIIS system and decides
+// convergence from scalars read back each step.
+namespace {
+
+struct ScfWork {
+    fk_ctx *c = nullptr;
+    hipStream_t st = nullptr;
+    int n = 0;
+    DevBuf<double> h, X, Xi, D, Do, J, K, F, Fo, G, E, T1, T2, T3, part, scal;
+    std::vector<DevBuf<double>> ringF, ringE;
+    ~ScfWork()
+    {
+        for (auto *b : {&h, &X, &Xi, &D, &Do, &J, &K, &F, &Fo, &G, &E, &T1, &T2, &T3, &part, &scal}) dev_free(*b);
+        for (auto &b : ringF) dev_free(b);
+        for (auto &b : ringE) dev_free(b);
+    }
+};
+
+#define SCFCHK(w, call)                                                                          \
+    do {                                                                                        \
+        if ((call) != 0) return fail((w).c, FK_ERR_HIP, "fk_run_scf: kernel launch failed: %s", #call); \
+    } while (0)
+
+// reduction `op` of x (and y) into a host scalar (op 3 returns two values)
+int scf_reduce(ScfWork &w, const double *x, const double *y, int op, double *out)
+{
+    SCFCHK(w, fk_scf_reduce(x, y, w.n, op, w.part.p, w.scal.p, 0, w.st));
+    HIPCHK(w.c, hipMemcpyAsync(out, w.scal.p, (op == 3 ? 2 : 1) * sizeof(double), hipMemcpyDeviceToHost, w.st));
+    HIPCHK(w.c, hipStreamSynchronize(w.st));
+    return FK_OK;
+}
+
+// A <- swap helper for device buffers
+inline void swapbuf(DevBuf<double> &a, DevBuf<double> &b) { std::swap(a, b); }
+
+// Orthogonaliser X = S^(-1/2) and S^(1/2) by the coupled Newton-Schulz
+// iteration on S / c, c an upper bound of the spectrum (Gershgorin).
+int scf_orthogonaliser(ScfWork &w, double tol)
+{
+    const int n = w.n;
+    double gb[2];
+    int rc;
+    // T3 holds S on entry
+    if ((rc = scf_reduce(w, w.T3.p, nullptr, 3, gb))) return rc;
+    const double cs = gb[1];
+    if (!(cs > 0)) return fail(w.c, FK_ERR_ARG, "fk_run_scf: overlap matrix has no positive bound");
+    SCFCHK(w, fk_scf_lincomb(w.Xi.p, w.T3.p, nullptr, nullptr, n, 1.0 / cs, 0, 0, 0, w.st));  // Y
+    SCFCHK(w, fk_scf_lincomb(w.X.p, w.T3.p, nullptr, nullptr, n, 0.0, 0, 0, 1.0, w.st));       // Z = I
+    double prev = 1e300, err = 1e300;
+    for (int it = 0; it < 200; ++it) {
+        SCFCHK(w, fk_scf_gemm(w.X.p, w.Xi.p, w.T1.p, n, 1.0, 0.0, w.st));                      // ZY
+        SCFCHK(w, fk_scf_lincomb(w.T2.p, w.T1.p, nullptr, nullptr, n, 1.0, 0, 0, -1.0, w.st));  // ZY - I
+        if ((rc = scf_reduce(w, w.T2.p, nullptr, 1, &err))) return rc;
+        if (err < tol * 1e-3 || (err < 1e-9 && err > 0.5 * prev)) break;  // converged or at the rounding floor
+        prev = err;
+        SCFCHK(w, fk_scf_lincomb(w.T2.p, w.T1.p, nullptr, nullptr, n, -0.5, 0, 0, 1.5, w.st));  // T = (3I - ZY)/2
+        SCFCHK(w, fk_scf_gemm(w.Xi.p, w.T2.p, w.T1.p, n, 1.0, 0.0, w.st));                     // Y T
+        SCFCHK(w, fk_scf_gemm(w.T2.p, w.X.p, w.G.p, n, 1.0, 0.0, w.st));                       // T Z
+        swapbuf(w.Xi, w.T1);
+        swapbuf(w.X, w.G);
+    }
+    if (!(err < tol)) return fail(w.c, FK_ERR_ARG, "fk_run_scf: S^(-1/2) did not converge (max|ZY - I| = %.3g); overlap too ill-conditioned", err);
+    SCFCHK(w, fk_scf_lincomb(w.X.p, w.X.p, nullptr, nullptr, n, 1.0 / std::sqrt(cs), 0, 0, 0, w.st));
+    SCFCHK(w, fk_scf_lincomb(w.Xi.p, w.Xi.p, nullptr, nullptr, n, std::sqrt(cs), 0, 0, 0, w.st));
+    return FK_OK;
+}
+
+// Orthonormal density D' = 2 P, P the projector onto the nocc lowest states of
+// the symmetric matrix in w.Fo (trace-correcting purification); result in w.Do.
+int scf_purify(ScfWork &w, int nocc, int *steps)
+{
+    const int n = w.n;
+    double gb[2];
+    int rc;
+    if ((rc = scf_reduce(w, w.Fo.p, nullptr, 3, gb))) return rc;
+    const double lo = gb[0], hi = gb[1];
+    if (!(hi > lo)) return fail(w.c, FK_ERR_ARG, "fk_run_scf: degenerate Fock spectrum bounds");
+    // P0 = (hi I - F') / (hi - lo): occupied (low) states near 1
+    SCFCHK(w, fk_scf_lincomb(w.T1.p, w.Fo.p, nullptr, nullptr, n, -1.0 / (hi - lo), 0, 0, hi / (hi - lo), w.st));
+    int extra = -1, it = 0;
+    for (; it < 300; ++it) {
+        SCFCHK(w, fk_scf_gemm(w.T1.p, w.T1.p, w.T2.p, n, 1.0, 0.0, w.st));
+        double t1, t2;
+        if ((rc = scf_reduce(w, w.T1.p, nullptr, 2, &t1))) return rc;
+        if ((rc = scf_reduce(w, w.T2.p, nullptr, 2, &t2))) return rc;
+        const double idem = t1 - t2;  // sum of x(1 - x) over the eigenvalues
+        if (extra < 0 && std::fabs(idem) < 1e-11) extra = 2;  // quadratic convergence: two more steps
+        if (extra == 0) break;
+        if (extra > 0) --extra;
+        if (std::fabs(t2 - nocc) < std::fabs(2 * t1 - t2 - nocc)) {
+            swapbuf(w.T1, w.T2);                                                                  // P <- P^2
+        } else {
+            SCFCHK(w, fk_scf_lincomb(w.T1.p, w.T1.p, w.T2.p, nullptr, n, 2.0, -1.0, 0, 0, w.st)); // P <- 2P - P^2
+        }
+    }
+    if (extra != 0) return fail(w.c, FK_ERR_NOT_CONVERGED, "fk_run_scf: purification did not converge (no gap?)");
+    if (steps) *steps = it;
+    SCFCHK(w, fk_scf_lincomb(w.Do.p, w.T1.p, nullptr, nullptr, n, 2.0, 0, 0, 0, w.st));
+    return FK_OK;
+}
+
+// Solves the Pulay system [B 1; 1 0] [c; l] = [0; 1] for m vectors (Gaussian
+// elimination with partial pivoting).  Returns false if singular.
+bool diis_solve(const std::vector<double> &B, int m, std::vector<double> &coef)
+{
+    const int k = m + 1;
+    std::vector<double> A((size_t)k * (k + 1), 0.0);
+    for (int i = 0; i < m; ++i) {
+        for (int j = 0; j < m; ++j) A[i * (k + 1) + j] = B[(size_t)i * m + j];
+        A[i * (k + 1) + m] = 1.0;
+        A[m * (k + 1) + i] = 1.0;
+    }
+    A[m * (k + 1) + k] = 1.0;  // right-hand side of the constraint row
+    // scale the error block so that pivoting compares like with like
+    double bmax = 0;
+    for (int i = 0; i < m; ++i) bmax = std::max(bmax, std::fabs(B[(size_t)i * m + i]));
+    if (!(bmax > 0)) return false;
+    for (int i = 0; i < m; ++i)
+        for (int j = 0; j < m; ++j) A[i * (k + 1) + j] /= bmax;
+    for (int col = 0; col < k; ++col) {
+        int piv = col;
+        for (int r = col + 1; r < k; ++r)
+            if (std::fabs(A[r * (k + 1) + col]) > std::fabs(A[piv * (k + 1) + col])) piv = r;
+        if (std::fabs(A[piv * (k + 1) + col]) < 1e-300) return false;
+        if (piv != col)
+            for (int j = 0; j <= k; ++j) std::swap(A[col * (k + 1) + j], A[piv * (k + 1) + j]);
+        for (int r = 0; r < k; ++r) {
+            if (r == col) continue;
+            const double f = A[r * (k + 1) + col] / A[col * (k + 1) + col];
+            for (int j = col; j <= k; ++j) A[r * (k + 1) + j] -= f * A[col * (k + 1) + j];
+        }
+    }
+    coef.assign(m, 0.0);
+    for (int i = 0; i < m; ++i) coef[i] = A[i * (k + 1) + k] / A[i * (k + 1) + i];
+    for (double v : coef)
+        if (!std::isfinite(v)) return false;
+    return true;
+}
+
+}  // namespace
+
 int fk_run_scf(fk_ctx *c, const fk_scf_opts *opts, fk_scf_result *result, double *D_inout)
 {
-    (void)opts; (void)result; (void)D_inout;
-    return fail(c, FK_ERR_UNSUPPORTED, "fk_run_scf: not available in this build");
+    if (!c) return FK_ERR_ARG;
+    if (!result || !D_inout) return fail(c, FK_ERR_ARG, "fk_run_scf: null result or density pointer");
+    std::memset(result, 0, sizeof *result);
+    if (c->device < 0) return fail(c, FK_ERR_STATE, "fk_run_scf: context has no device");
+    if (!c->have_quartets) return fail(c, FK_ERR_STATE, "fk_run_scf: call fk_build_quartets first");
+    fk_scf_opts o = {100, 1e-10, 1e-8, 8, 0, 1e-8};
+    if (opts) o = *opts;
+    if (o.max_iter < 1 || o.diis_n < 0 || o.diis_n > 32 || !(o.e_tol > 0) || !(o.g_tol > 0) || !(o.lindep > 0) ||
+        (o.guess != 0 && o.guess != 1))
+        return fail(c, FK_ERR_ARG, "fk_run_scf: invalid options");
+    if (c->nelec % 2 != 0 || c->nelec <= 0) return fail(c, FK_ERR_ARG, "fk_run_scf: closed shell needs an even, positive electron count");
+    const int n = c->nbf, nocc = c->nelec / 2;
+    if (nocc > n) return fail(c, FK_ERR_ARG, "fk_run_scf: more occupied orbitals than basis functions");
+    const auto t_start = std::chrono::steady_clock::now();
+    hipSetDevice(c->device);
+    const size_t nn = (size_t)n * n;
+    // one-electron part on the host, once per geometry
+    std::vector<double> S(nn), T(nn), V(nn), h(nn);
+    double enuc = 0;
+    int rc;
+    if ((rc = fk_one_electron(c, S.data(), T.data(), V.data(), &enuc))) return rc;
+    for (size_t i = 0; i < nn; ++i) h[i] = T[i] + V[i];
+    result->e_nuc = enuc;
+
+    ScfWork w;
+    w.c = c;
+    w.n = n;
+    w.st = nullptr;
+    for (auto *b : {&w.h, &w.X, &w.Xi, &w.D, &w.Do, &w.J, &w.K, &w.F, &w.Fo, &w.G, &w.E, &w.T1, &w.T2, &w.T3})
+        if ((rc = dev_upload<double>(c, *b, nullptr, nn))) return rc;
+    if ((rc = dev_upload<double>(c, w.part, nullptr, (size_t)fk_scf_reduce_scratch() + 2))) return rc;
+    if ((rc = dev_upload<double>(c, w.scal, nullptr, 4))) return rc;
+    w.ringF.resize(std::max(o.diis_n, 1));
+    w.ringE.resize(std::max(o.diis_n, 1));
+    if (o.diis_n > 0)
+        for (int k = 0; k < o.diis_n; ++k)
+            if ((rc = dev_upload<double>(c, w.ringF[k], nullptr, nn)) || (rc = dev_upload<double>(c, w.ringE[k], nullptr, nn)))
+                return rc;
+    if ((rc = dev_upload(c, w.h, h.data(), nn))) return rc;
+    if ((rc = dev_upload(c, w.T3, S.data(), nn))) return rc;
+    if ((rc = scf_orthogonaliser(w, o.lindep))) return rc;
+
+    // initial orthonormal density
+    if (o.guess == 0) {
+        SCFCHK(w, fk_scf_gemm(w.X.p, w.h.p, w.T3.p, n, 1.0, 0.0, w.st));
+        SCFCHK(w, fk_scf_gemm(w.T3.p, w.X.p, w.Fo.p, n, 1.0, 0.0, w.st));
+        if ((rc = scf_purify(w, nocc, nullptr))) return rc;
+    } else {
+        if ((rc = dev_upload(c, w.D, D_inout, nn))) return rc;
+        SCFCHK(w, fk_scf_gemm(w.Xi.p, w.D.p, w.T3.p, n, 1.0, 0.0, w.st));
+        SCFCHK(w, fk_scf_gemm(w.T3.p, w.Xi.p, w.Do.p, n, 1.0, 0.0, w.st));
+    }
+    // D = X D' X
+    SCFCHK(w, fk_scf_gemm(w.X.p, w.Do.p, w.T3.p, n, 1.0, 0.0, w.st));
+    SCFCHK(w, fk_scf_gemm(w.T3.p, w.X.p, w.D.p, n, 1.0, 0.0, w.st));
+
+    std::vector<double> B;  // DIIS inner products, row-major m x m over ring slots
+    const int dn = std::max(o.diis_n, 1);
+    B.assign((size_t)dn * dn, 0.0);
+    std::vector<int> slot_age;  // ring slots in insertion order
+    double e_prev = 0, e_cur = 0, err = 0, jk_s = 0;
+    bool converged = false;
+    int it = 0;
+    for (; it < o.max_iter; ++it) {
+        const auto t0 = std::chrono::steady_clock::now();
+        if ((rc = fk_build_jk(c, w.D.p, w.J.p, w.K.p, FK_DEVICE_PTRS | FK_SYNC, w.st))) return rc;
+        jk_s += std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+        // F = h + J - K/2 and E = (D.h + D.F)/2 + E_nuc
+        SCFCHK(w, fk_scf_lincomb(w.F.p, w.h.p, w.J.p, w.K.p, n, 1.0, 1.0, -0.5, 0, w.st));
+        double dh, df;
+        if ((rc = scf_reduce(w, w.D.p, w.h.p, 0, &dh)) || (rc = scf_reduce(w, w.D.p, w.F.p, 0, &df))) return rc;
+        e_prev = e_cur;
+        e_cur = 0.5 * (dh + df) + enuc;
+        // F' = X F X and the commutator e = F'D' - D'F'
+        SCFCHK(w, fk_scf_gemm(w.X.p, w.F.p, w.T3.p, n, 1.0, 0.0, w.st));
+        SCFCHK(w, fk_scf_gemm(w.T3.p, w.X.p, w.Fo.p, n, 1.0, 0.0, w.st));
+        SCFCHK(w, fk_scf_gemm(w.Fo.p, w.Do.p, w.G.p, n, 1.0, 0.0, w.st));
+        SCFCHK(w, fk_scf_antisym(w.E.p, w.G.p, n, w.st));
+        if ((rc = scf_reduce(w, w.E.p, nullptr, 1, &err))) return rc;
+        if (!std::isfinite(e_cur) || !std::isfinite(err))
+            return fail(c, FK_ERR_NOT_CONVERGED, "fk_run_scf: non-finite energy or error at iteration %d", it + 1);
+        if (it > 0 && std::fabs(e_cur - e_prev) < o.e_tol && err < o.g_tol) {
+            converged = true;
+            ++it;
+            break;
+        }
+        // DIIS extrapolation of F'
+        if (o.diis_n > 1) {
+            int k;
+            if ((int)slot_age.size() < o.diis_n) {
+                k = (int)slot_age.size();
+            } else {
+                k = slot_age.front();
+                slot_age.erase(slot_age.begin());
+            }
+            slot_age.push_back(k);
+            HIPCHK(c, hipMemcpyAsync(w.ringF[k].p, w.Fo.p, nn * sizeof(double), hipMemcpyDeviceToDevice, w.st));
+            HIPCHK(c, hipMemcpyAsync(w.ringE[k].p, w.E.p, nn * sizeof(double), hipMemcpyDeviceToDevice, w.st));
+            for (int j : slot_age) {
+                double v;
+                if ((rc = scf_reduce(w, w.ringE[k].p, w.ringE[j].p, 0, &v))) return rc;
+                B[(size_t)k * dn + j] = B[(size_t)j * dn + k] = v;
+            }
+            const int m = (int)slot_age.size();
+            if (m >= 2) {
+                std::vector<double> Bm((size_t)m * m), coef;
+                for (int i = 0; i < m; ++i)
+                    for (int j = 0; j < m; ++j) Bm[(size_t)i * m + j] = B[(size_t)slot_age[i] * dn + slot_age[j]];
+                if (diis_solve(Bm, m, coef)) {
+                    SCFCHK(w, fk_scf_lincomb(w.Fo.p, w.ringF[slot_age[0]].p, nullptr, nullptr, n, coef[0], 0, 0, 0, w.st));
+                    for (int i = 1; i < m; ++i)
+                        SCFCHK(w, fk_scf_lincomb(w.Fo.p, w.Fo.p, w.ringF[slot_age[i]].p, nullptr, n, 1.0, coef[i], 0, 0, w.st));
+                }
+            }
+        }
+        // new density: D' from F', D = X D' X
+        if ((rc = scf_purify(w, nocc, nullptr))) return rc;
+        SCFCHK(w, fk_scf_gemm(w.X.p, w.Do.p, w.T3.p, n, 1.0, 0.0, w.st));
+        SCFCHK(w, fk_scf_gemm(w.T3.p, w.X.p, w.D.p, n, 1.0, 0.0, w.st));
+    }
+    HIPCHK(c, hipMemcpy(D_inout, w.D.p, nn * sizeof(double), hipMemcpyDeviceToHost));
+    result->energy = e_cur;
+    result->iterations = it;
+    result->converged = converged ? 1 : 0;
+    result->error = err;
+    result->delta_e = e_cur - e_prev;
+    result->jk_seconds = jk_s;
+    result->total_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start).count();
+    if (!converged) return fail(c, FK_ERR_NOT_CONVERGED, "fk_run_scf: not converged in %d iterations", o.max_iter);
+    return FK_OK;
 }
 
 int fk_rys_host(int n, double T, double *u, double *w)

@@ -95,4 +95,12 @@ int fk_kernels_launch_finalize(const double *XJ, const double *XK, const double 
 int fk_kernels_launch_fill(double *p, long long n, void *stream);
 int fk_kernels_debug_host(int P, int Q, const int *pair_ppoff, const int *pair_npp, const double *pair_AB,
                           const double *pp, const int *quartets, int nq, double *out);
+// dense SCF kernels (fk_scf.hip); n x n row-major FP64 device matrices
+int fk_scf_gemm(const double *A, const double *B, double *C, int n, double alpha, double beta, void *stream);
+int fk_scf_lincomb(double *out, const double *x, const double *y, const double *z, int n, double a, double b,
+                   double c, double d, void *stream);
+int fk_scf_antisym(double *e, const double *G, int n, void *stream);
+int fk_scf_reduce(const double *x, const double *y, int n, int op, double *part, double *out, int slot,
+                  void *stream);
+int fk_scf_reduce_scratch();
 }

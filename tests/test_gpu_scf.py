@@ -1,0 +1,85 @@
+"""GPU parity of the SCF step (fk_run_scf) against the CPU oracle's SCF
+(run with -m gpu).
+
+The oracle diagonalises F in a canonical orthogonal basis with numpy and uses
+its own literal J/K; the library purifies X F X on the device with its own
+Rys J/K.  Converged total energies must agree within 1e-8 Eh (criterion of
+the workload definition; both stop at |dE| < 1e-10 and max|error| < 1e-8).
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle.scf import run_scf
+from synth import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+@pytest.fixture(scope="module")
+def fk():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a visible GPU"
+    import paper_2407_21445_amd as m
+    return m
+
+
+def _gpu_scf(fk, s, tau=0.0, **kw):
+    c = fk.FockJK(0).set_system(s).build_quartets(tau=tau)
+    return c.run_scf(**kw), c
+
+
+def test_scf_h2_textbook(fk):
+    """H2 / STO-3G at R = 1.4 bohr: the textbook total energy."""
+    with open(os.path.join(HERE, "golden", "h2_sto3g_szabo_ostlund.json")) as f:
+        gold = json.load(f)
+    s = wl.h2_sto3g()
+    r, _ = _gpu_scf(fk, s)
+    assert r["converged"]
+    assert abs(r["energy"] - gold["E_total"]) <= gold["E_tol"]
+    assert abs(r["energy"] - run_scf(s)["E"]) <= 1e-8
+
+
+@pytest.mark.parametrize("name", ["water4_sto3g", "c2h6_631gs"])
+def test_scf_energy_matches_oracle(fk, name):
+    s = wl.water4_sto3g() if name == "water4_sto3g" else wl.alkane_sys(2, "6-31gs-type")
+    r, _ = _gpu_scf(fk, s)
+    ref = run_scf(s)
+    assert r["converged"] and ref["converged"]
+    assert abs(r["energy"] - ref["E"]) <= 1e-8, (r["energy"], ref["E"])
+    assert abs(r["e_nuc"] - oracle.enuc(s)) <= 1e-10
+    # the density: trace, idempotency in the S metric, agreement with the oracle
+    S = oracle.oneel(s)[0]
+    D = r["D"]
+    assert abs(np.trace(D @ S) - s["nelec"]) <= 1e-9
+    DS = D @ S
+    assert np.max(np.abs(DS @ DS - 2 * DS)) <= 1e-8
+    assert np.max(np.abs(D - ref["D"])) <= 1e-5
+
+
+def test_scf_screened_and_restarted(fk):
+    """tau = 1e-10 changes the converged energy by far less than 1e-8 Eh; a
+    restart from the converged density converges at once to the same energy."""
+    s = wl.water4_sto3g()
+    ref = run_scf(s)
+    r, c = _gpu_scf(fk, s, tau=1e-10)
+    assert r["converged"] and abs(r["energy"] - ref["E"]) <= 1e-8
+    r2 = c.run_scf(D0=r["D"])
+    assert r2["converged"] and r2["iterations"] <= 3
+    assert abs(r2["energy"] - r["energy"]) <= 1e-9
+
+
+def test_scf_errors(fk):
+    s = wl.water4_sto3g()
+    c = fk.FockJK(0).set_system(s)
+    with pytest.raises(fk.FockJKError) as e:  # before the quartet lists
+        c.run_scf()
+    assert e.value.code == fk.FK_ERR_STATE
+    c.build_quartets(tau=0.0)
+    r = c.run_scf(max_iter=2)
+    assert not r["converged"] and r["iterations"] == 2

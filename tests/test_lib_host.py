@@ -171,3 +171,11 @@ def test_kernel_indices_in_bounds(name, tau, tau_prim):
     c = fk.FockJK(device=-1).set_system(s).build_quartets(tau=tau, tau_prim=tau_prim)
     c.check_indices()
     assert c.info()["ntile"] > 0
+
+
+def test_scf_needs_device():
+    s = wl.water4_sto3g()
+    c = fk.FockJK(device=-1).set_system(s).build_quartets(tau=0.0)
+    with pytest.raises(fk.FockJKError) as e:
+        c.run_scf()
+    assert e.value.code == fk.FK_ERR_STATE
