@@ -75,7 +75,10 @@ typedef struct {
     double tau_prim;   /* primitive-pair pruning: drop primitive pairs whose
                           bound G_[ab] * max_all G_[cd] < tau_prim; 0 = keep all */
     int    density_screen; /* 1: apply the per-quartet D_max screen in fk_build_jk */
-    int    reserved;
+    int    bra_block;  /* bras sharing their first shell that one work tile
+                          pairs with the same kets (1..32; 0 = default 8).
+                          Contributions to K[a, c], K[a, d] and J[c, d] are
+                          summed over the block before they reach memory */
 } fk_screen_opts;
 
 typedef struct {

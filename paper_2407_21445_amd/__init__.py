@@ -37,7 +37,7 @@ MAX_L, MAX_K = 3, 9
 
 class ScreenOpts(ctypes.Structure):
     _fields_ = [("tau", ctypes.c_double), ("tau_prim", ctypes.c_double),
-                ("density_screen", ctypes.c_int), ("reserved", ctypes.c_int)]
+                ("density_screen", ctypes.c_int), ("bra_block", ctypes.c_int)]
 
 
 class Info(ctypes.Structure):
@@ -163,8 +163,8 @@ class FockJK:
         self.nbf = int(sum(_ncart(int(l)) for l in sl))
         return self
 
-    def build_quartets(self, tau=1e-10, tau_prim=0.0, density_screen=True):
-        o = ScreenOpts(float(tau), float(tau_prim), 1 if density_screen else 0, 0)
+    def build_quartets(self, tau=1e-10, tau_prim=0.0, density_screen=True, bra_block=0):
+        o = ScreenOpts(float(tau), float(tau_prim), 1 if density_screen else 0, int(bra_block))
         self._check(_lib.fk_build_quartets(self._ctx, ctypes.byref(o)))
         return self
 

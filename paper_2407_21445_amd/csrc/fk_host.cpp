@@ -76,6 +76,9 @@ struct fk_ctx {
     std::vector<FkGroup> groups;
     std::vector<int> cls_group0;                 // first global group of each class
     std::vector<FkTile> tiles;
+    std::vector<FkBraBlock> blocks;
+    std::vector<int> blk_bra, blk_pos;
+    std::vector<int64_t> blk_nppsum;             // sum of the bras' primitive-pair counts
     std::vector<QuartetClass> qclasses;
     double flops_schwarz = 0;
     int64_t nq_schwarz = 0;
@@ -86,8 +89,9 @@ struct fk_ctx {
     DevBuf<double> d_lst_CD, d_lst_G, d_ppT;
     DevBuf<FkGroup> d_groups;
     DevBuf<FkTile> d_tiles;
+    DevBuf<FkBraBlock> d_blocks;
+    DevBuf<int> d_blk_bra, d_blk_pos;
     DevBuf<unsigned long long> d_cnt;
-    DevBuf<unsigned int> d_tilectr;
     // last build
     bool stats_pending = false;
     bool timed = false;
@@ -169,7 +173,7 @@ void free_device(fk_ctx *c)
     dev_free(c->d_pr_npp); dev_free(c->d_ket); dev_free(c->d_bf_scale); dev_free(c->d_pr_AB);
     dev_free(c->d_pr_G); dev_free(c->d_pp); dev_free(c->d_rys); dev_free(c->d_Ds); dev_free(c->d_Dsh);
     dev_free(c->d_X); dev_free(c->d_Din); dev_free(c->d_Jout); dev_free(c->d_Kout); dev_free(c->d_tiles);
-    dev_free(c->d_cnt); dev_free(c->d_tilectr); dev_free(c->d_lst_sa); dev_free(c->d_lst_sb); dev_free(c->d_lst_CD);
+    dev_free(c->d_cnt); dev_free(c->d_blocks); dev_free(c->d_blk_bra); dev_free(c->d_blk_pos); dev_free(c->d_lst_sa); dev_free(c->d_lst_sb); dev_free(c->d_lst_CD);
     dev_free(c->d_lst_G); dev_free(c->d_ppT); dev_free(c->d_groups);
 }
 
@@ -383,13 +387,29 @@ int validate_lists(fk_ctx *c)
             if (c->pr_npp[c->ket_list_all[G.begin + r]] != G.npp)
                 return fail(c, FK_ERR_STATE, "internal: group %zu mixes primitive counts", g);
     }
+    if (c->blk_pos.size() != c->blk_bra.size()) return fail(c, FK_ERR_STATE, "internal: bra block arrays differ in size");
+    for (size_t b = 0; b < c->blocks.size(); ++b) {
+        const FkBraBlock &B = c->blocks[b];
+        if (B.first < 0 || B.count < 1 || B.count > FK_MAX_BRA_BLOCK || (size_t)B.first + B.count > c->blk_bra.size())
+            return fail(c, FK_ERR_STATE, "internal: bra block %zu is inconsistent", b);
+        for (int j = 0; j < B.count; ++j) {
+            const int p = c->blk_bra[B.first + j], q = c->blk_pos[B.first + j];
+            if (p < 0 || p >= npair || q < 0 || q >= nl || c->ket_list_all[q] != p ||
+                c->pr_sa[p] != c->pr_sa[c->blk_bra[B.first]] || c->pr_cls[p] != c->pr_cls[c->blk_bra[B.first]])
+                return fail(c, FK_ERR_STATE, "internal: bra block %zu member %d is inconsistent", b, j);
+        }
+    }
     for (const QuartetClass &qc : c->qclasses) {
         for (int64_t t = qc.tile_off; t < qc.tile_off + qc.ntile; ++t) {
             const FkTile &T = c->tiles[t];
             const int gid = T.grp & ~FK_TILE_SAME;
-            if (T.bra < 0 || T.bra >= npair || gid < 0 || gid >= (int)c->groups.size() || T.ket_count < 1 ||
-                T.ket_count > 64 || c->pr_npp[T.bra] * FK_NFLD > qc.bra_slot)
+            if (T.blk < 0 || T.blk >= (int)c->blocks.size() || gid < 0 || gid >= (int)c->groups.size() ||
+                T.ket_count < 1 || T.ket_count > 64)
                 return fail(c, FK_ERR_STATE, "internal: tile %lld is inconsistent", (long long)t);
+            const FkBraBlock &B = c->blocks[T.blk];
+            for (int j = 0; j < B.count; ++j)
+                if (c->pr_npp[c->blk_bra[B.first + j]] * FK_NFLD > qc.bra_slot || c->pr_cls[c->blk_bra[B.first + j]] != qc.P)
+                    return fail(c, FK_ERR_STATE, "internal: tile %lld bra %d does not fit its class", (long long)t, j);
             const FkGroup &G = c->groups[gid];
             if (T.ket_begin < G.begin || T.ket_begin + T.ket_count > G.begin + G.len)
                 return fail(c, FK_ERR_STATE, "internal: tile %lld leaves its group", (long long)t);
@@ -555,6 +575,8 @@ int fk_build_quartets(fk_ctx *c, const fk_screen_opts *o)
     fk_screen_opts opts = {1e-10, 0.0, 1, 0};
     if (o) opts = *o;
     if (!(opts.tau >= 0) || !(opts.tau_prim >= 0)) return fail(c, FK_ERR_ARG, "fk_build_quartets: negative threshold");
+    if (opts.bra_block < 0 || opts.bra_block > FK_MAX_BRA_BLOCK)
+        return fail(c, FK_ERR_ARG, "fk_build_quartets: bra_block must be 0..%d", FK_MAX_BRA_BLOCK);
     c->opts = opts;
     const bool dev = c->device >= 0;
     if (dev) hipSetDevice(c->device);
@@ -659,8 +681,13 @@ int fk_build_quartets(fk_ctx *c, const fk_screen_opts *o)
         }
         c->cls_group0[NPC] = (int)c->groups.size();
     }
-    // 4. tiles per quartet class (P >= Q): bra from class P, kets from class Q
+    // 4. tiles per quartet class (P >= Q): bra blocks from class P, kets from class Q
+    const int bra_block = opts.bra_block > 0 ? std::min(opts.bra_block, FK_MAX_BRA_BLOCK) : 8;
     c->tiles.clear();
+    c->blocks.clear();
+    c->blk_bra.clear();
+    c->blk_pos.clear();
+    c->blk_nppsum.clear();
     c->qclasses.clear();
     c->flops_schwarz = 0;
     c->nq_schwarz = 0;
@@ -681,36 +708,63 @@ int fk_build_quartets(fk_ctx *c, const fk_screen_opts *o)
             int max_bra_npp = 1;
             for (int p : LP) max_bra_npp = std::max(max_bra_npp, c->pr_npp[p]);
             qc.bra_slot = max_bra_npp * FK_NFLD;
-            for (int pb = 0; pb < (int)LP.size(); ++pb) {
-                const int bra = LP[pb];
-                const double thr = opts.tau > 0 ? opts.tau / c->pr_G[bra] : 0.0;
+            // bra blocks: the class's pairs ordered by (first shell, G descending),
+            // cut into runs of at most bmax pairs with the same first shell
+            const int bmax = std::max(1, std::min(bra_block, qc.info.bra_block));
+            std::vector<int> ord(LP.size());
+            std::iota(ord.begin(), ord.end(), 0);
+            std::stable_sort(ord.begin(), ord.end(), [&](int x, int y) {
+                if (c->pr_sa[LP[x]] != c->pr_sa[LP[y]]) return c->pr_sa[LP[x]] < c->pr_sa[LP[y]];
+                return c->pr_G[LP[x]] > c->pr_G[LP[y]];
+            });
+            for (size_t i0 = 0; i0 < ord.size();) {
+                size_t i1 = i0;
+                const int sa0 = c->pr_sa[LP[ord[i0]]];
+                while (i1 < ord.size() && (int)(i1 - i0) < bmax && c->pr_sa[LP[ord[i1]]] == sa0) ++i1;
+                const int blk = (int)c->blocks.size();
+                c->blocks.push_back(FkBraBlock{(int)c->blk_bra.size(), (int)(i1 - i0)});
+                int64_t nppsum = 0;
+                for (size_t x = i0; x < i1; ++x) {
+                    c->blk_bra.push_back(LP[ord[x]]);
+                    c->blk_pos.push_back(c->ket_off[P] + ord[x]);
+                    nppsum += c->pr_npp[LP[ord[x]]];
+                }
+                c->blk_nppsum.push_back(nppsum);
                 for (size_t gi = 0; gi < c->cls_groups[Q].size(); ++gi) {
                     const auto &g = c->cls_groups[Q][gi];
-                    // kets in [g.first, g.second) are sorted by G descending
-                    int lo = g.first, hi = g.second;
-                    while (lo < hi) {
-                        const int mid = (lo + hi) / 2;
-                        if (c->pr_G[LQ[mid]] >= thr) lo = mid + 1; else hi = mid;
+                    const int gnpp = c->pr_npp[LQ[g.first]];
+                    int cmax = 0;
+                    for (size_t x = i0; x < i1; ++x) {
+                        const int pb = ord[x], bra = LP[pb];
+                        const double thr = opts.tau > 0 ? opts.tau / c->pr_G[bra] : 0.0;
+                        // kets in [g.first, g.second) are sorted by G descending
+                        int lo = g.first, hi = g.second;
+                        while (lo < hi) {
+                            const int mid = (lo + hi) / 2;
+                            if (c->pr_G[LQ[mid]] >= thr) lo = mid + 1; else hi = mid;
+                        }
+                        int cnt = lo - g.first;
+                        if (P == Q) cnt = std::min(cnt, std::max(0, pb + 1 - g.first));
+                        if (cnt <= 0) continue;
+                        cmax = std::max(cmax, cnt);
+                        qc.nquartet += cnt;
+                        qc.nprim += (int64_t)cnt * c->pr_npp[bra] * gnpp;
                     }
-                    int cnt = lo - g.first;
-                    if (P == Q) cnt = std::min(cnt, std::max(0, pb + 1 - g.first));
-                    if (cnt <= 0) continue;
-                    for (int k = 0; k < cnt; k += tile_kets) {
+                    for (int k = 0; k < cmax; k += tile_kets) {
                         FkTile t;
-                        t.bra = bra;
+                        t.blk = blk;
                         t.ket_begin = c->ket_off[Q] + g.first + k;
-                        t.ket_count = std::min(tile_kets, cnt - k);
+                        t.ket_count = std::min(tile_kets, cmax - k);
                         t.grp = (c->cls_group0[Q] + (int)gi) | ((P == Q) ? FK_TILE_SAME : 0);
                         c->tiles.push_back(t);
                         // lane slots of the tile's primitive loops: rounds of
-                        // (quartets per wave) kets, 64 lanes each
+                        // (quartets per wave) kets, 64 lanes each, for every bra
                         const int qpw = qc.info.wave_per_quartet == 0 ? 64 : (qc.info.wave_per_quartet == 3 ? 1 : 64 / ts);
                         const int64_t rounds = (t.ket_count + qpw - 1) / qpw;
-                        qc.prim_slots += rounds * 64 * c->pr_npp[bra] * c->pr_npp[LQ[g.first]];
+                        qc.prim_slots += rounds * 64 * nppsum * gnpp;
                     }
-                    qc.nquartet += cnt;
-                    qc.nprim += (int64_t)cnt * c->pr_npp[bra] * c->pr_npp[LQ[g.first]];
                 }
+                i0 = i1;
             }
             qc.ntile = (int64_t)c->tiles.size() - qc.tile_off;
             if (qc.ntile == 0) continue;
@@ -718,7 +772,7 @@ int fk_build_quartets(fk_ctx *c, const fk_screen_opts *o)
             {
                 auto cost = [&](const FkTile &t) {
                     const FkGroup &gg = c->groups[t.grp & ~FK_TILE_SAME];
-                    return (int64_t)c->pr_npp[t.bra] * gg.npp * t.ket_count;
+                    return c->blk_nppsum[t.blk] * gg.npp * t.ket_count;
                 };
                 std::stable_sort(c->tiles.begin() + qc.tile_off, c->tiles.end(),
                                  [&](const FkTile &x, const FkTile &y) { return cost(x) > cost(y); });
@@ -749,7 +803,9 @@ int fk_build_quartets(fk_ctx *c, const fk_screen_opts *o)
         if ((rc = dev_upload<double>(c, c->d_Dsh, nullptr, (size_t)c->nshell * c->nshell))) return rc;
         if ((rc = dev_upload<double>(c, c->d_X, nullptr, 2 * nn))) return rc;
         if ((rc = dev_upload<unsigned long long>(c, c->d_cnt, nullptr, 2 * FK_MAX_QCLASS))) return rc;
-        if ((rc = dev_upload<unsigned int>(c, c->d_tilectr, nullptr, 2 * FK_MAX_QCLASS))) return rc;
+        if ((rc = dev_upload(c, c->d_blocks, c->blocks.data(), c->blocks.size()))) return rc;
+        if ((rc = dev_upload(c, c->d_blk_bra, c->blk_bra.data(), c->blk_bra.size()))) return rc;
+        if ((rc = dev_upload(c, c->d_blk_pos, c->blk_pos.data(), c->blk_pos.size()))) return rc;
     }
     c->have_quartets = true;
     c->stats_pending = false;
@@ -803,8 +859,7 @@ int fk_build_jk(fk_ctx *c, const double *D, double *J, double *K, unsigned flags
     if (fk_kernels_launch_prep(Dd, c->d_sh_bf.p, c->d_bf_scale.p, c->nshell, n, c->d_Ds.p, c->d_Dsh.p, st))
         return fail(c, FK_ERR_HIP, "prep kernel launch failed");
     if (fk_kernels_launch_fill(c->d_X.p, (long long)(2 * nn), st) ||
-        fk_kernels_launch_fill((double *)c->d_cnt.p, 2 * FK_MAX_QCLASS, st) ||
-        fk_kernels_launch_fill((double *)c->d_tilectr.p, FK_MAX_QCLASS, st))
+        fk_kernels_launch_fill((double *)c->d_cnt.p, 2 * FK_MAX_QCLASS, st))
         return fail(c, FK_ERR_HIP, "fill kernel launch failed");
     c->timed = (flags & FK_TIME_CLASSES) != 0;
     if (c->timed)
@@ -846,7 +901,9 @@ int fk_build_jk(fk_ctx *c, const double *D, double *J, double *K, unsigned flags
         a.rys_tab = c->d_rys.p + rys_staged_offset(qc.info.nroot);
         a.counters = c->d_cnt.p + 2 * i;
         a.bra_slot = qc.bra_slot;
-        a.tile_next = c->d_tilectr.p + i;
+        a.blocks = c->d_blocks.p;
+        a.blk_bra = c->d_blk_bra.p;
+        a.blk_pos = c->d_blk_pos.p;
         // Enough workgroups for the hardware to fill every CU to its register and
         // LDS limit; the persistent loop covers the rest.
         const int64_t want = (qc.ntile + 3) / 4;
@@ -1007,16 +1064,24 @@ int fk_check_indices(fk_ctx *c)
         for (int64_t t = qc.tile_off; t < qc.tile_off + qc.ntile; ++t) {
             const FkTile &T = c->tiles[t];
             const long long gid = T.grp & ~FK_TILE_SAME;
-            if (T.bra < 0 || T.bra >= npair || gid < 0 || gid >= (long long)c->groups.size())
-                return fail(c, FK_ERR_STATE, "class %zu tile %lld: bra/group out of range", qi, (long long)t);
+            if (T.blk < 0 || T.blk >= (long long)c->blocks.size() || gid < 0 || gid >= (long long)c->groups.size())
+                return fail(c, FK_ERR_STATE, "class %zu tile %lld: block/group out of range", qi, (long long)t);
             const FkGroup &g = c->groups[gid];
-            const int sa = c->pr_sa[T.bra], sb = c->pr_sb[T.bra];
-            const long long ppo = c->pr_ppoff[T.bra], bnp = c->pr_npp[T.bra];
+            const FkBraBlock &BB = c->blocks[T.blk];
+            if (BB.first < 0 || BB.count < 1 || BB.count > FK_MAX_BRA_BLOCK || (size_t)BB.first + BB.count > c->blk_bra.size())
+                return fail(c, FK_ERR_STATE, "tile %lld: bra block range", (long long)t);
+          for (int jb = 0; jb < BB.count; ++jb) {
+            const long long bra = c->blk_bra[BB.first + jb], bpos = c->blk_pos[BB.first + jb];
+            if (bra < 0 || bra >= npair || bpos < 0 || bpos >= nl) return fail(c, FK_ERR_STATE, "tile %lld: bra %d index", (long long)t, jb);
+            const int sa = c->pr_sa[bra], sb = c->pr_sb[bra];
+            const long long ppo = c->pr_ppoff[bra], bnp = c->pr_npp[bra];
             if (ppo < 0 || ppo + bnp > nppr) return fail(c, FK_ERR_STATE, "tile %lld: bra records", (long long)t);
             if (bnp * FK_NFLD > qc.bra_slot) return fail(c, FK_ERR_STATE, "tile %lld: LDS bra slot", (long long)t);
             const long long oa = c->sh_bf[sa], ob = c->sh_bf[sb];
             if (oa + NA > n || ob + NB > n || ncart(c->sh_l[sa]) != NA || ncart(c->sh_l[sb]) != NB)
                 return fail(c, FK_ERR_STATE, "tile %lld: bra shells do not match the class", (long long)t);
+            if (sa != c->pr_sa[c->blk_bra[BB.first]])
+                return fail(c, FK_ERR_STATE, "tile %lld: bra block members differ in their first shell", (long long)t);
             if (T.ket_count < 1 || T.ket_count > 64)
                 return fail(c, FK_ERR_STATE, "tile %lld: ket count %d", (long long)t, T.ket_count);
             for (int k = 0; k < 64; ++k) {
@@ -1040,6 +1105,7 @@ int fk_check_indices(fk_ctx *c)
                 for (long long x : dsh)
                     if (x < 0 || x >= ns * ns) return fail(c, FK_ERR_STATE, "tile %lld lane %d: shell block", (long long)t, k);
             }
+          }
         }
     }
     return FK_OK;

@@ -10,15 +10,26 @@
 
 #define FK_NFLD 9  // fields of a transposed primitive-pair record (no G)
 
-// Work tile: one bra shell pair and up to 64 consecutive ket shell pairs of one
-// ket class, all from one primitive-count group.
+// Work tile: a block of bra shell pairs that share their first shell, and up to
+// 64 consecutive ket shell pairs of one ket class, all from one
+// primitive-count group.  Every (bra, ket) combination of the tile is a
+// candidate quartet; the kernels apply the Schwarz, same-class and density
+// tests per combination.
 struct FkTile {
-    int bra;        // shell-pair index of the bra
+    int blk;        // bra block (index into FkJKArgs::blocks)
     int ket_begin;  // position in the concatenated sorted pair lists
     int ket_count;  // 1..64
     int grp;        // primitive-count group of the kets; bit 30: bra and ket from the same class
 };
 #define FK_TILE_SAME (1 << 30)
+
+// Bra block: blk_bra[first .. first + count) are shell-pair indices with the
+// same first shell; blk_pos holds their positions in the sorted pair lists.
+struct FkBraBlock {
+    int first;
+    int count;
+};
+#define FK_MAX_BRA_BLOCK 32
 
 // A run of equal primitive-pair count inside one class's sorted pair list.
 // Its primitive records are stored transposed, [j][field][position in run],
@@ -30,6 +41,11 @@ struct FkGroup {
     int pad;
     long long base; // offset of the run's records in the transposed array
 };
+
+// Declaration of a kernel's dynamically sized LDS block (as doubles).
+#ifndef FK_DYN_LDS
+#define FK_DYN_LDS(name) extern __shared__ double name[]
+#endif
 
 struct FkJKArgs {
     const int *sh_bf;        // [nshell + 1] first basis function of each shell
@@ -49,6 +65,9 @@ struct FkJKArgs {
     const double *ppT;       // transposed primitive records of every group
     const FkTile *tiles;
     int ntiles;
+    const FkBraBlock *blocks;
+    const int *blk_bra;      // shell-pair index of each bra of each block
+    const int *blk_pos;      // its position in the sorted pair lists
     int nshell;
     const double *Dsh;       // [nshell * nshell] max |D| per shell block
     const double *Ds;        // [nbf * nbf] component-scaled density
@@ -60,7 +79,6 @@ struct FkJKArgs {
     const double *rys_tab;   // staged Rys segment (table + Gauss-Hermite) of this class's root count
     unsigned long long *counters;  // [2]: contracted quartets, primitive quartets
     int bra_slot;            // doubles per wave for the staged bra primitive records
-    unsigned int *tile_next; // work counter: waves claim tiles in order (zeroed before the launch)
 };
 
 // Quartet list for the debug/Schwarz kernels (canonical orientation).
@@ -79,6 +97,7 @@ struct FkClassInfo {
     int la, lb, lc, ld, nroot, nout;
     int wave_per_quartet;    // kernel kind: 0 lane, 1 team over a, 2 team over (a,b), 3 wave per quartet
     int team_size;           // lanes per quartet
+    int bra_block;           // largest bra block the class kernel takes per tile
     double flops_prim, flops_quartet;
 };
 

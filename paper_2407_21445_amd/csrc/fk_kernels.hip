@@ -25,7 +25,10 @@
 #ifndef FK_BUILD_MAXL
 #define FK_BUILD_MAXL 3
 #endif
-#define FK_LPQ_MAX_NOUT 108
+#define FK_LPQ_MAX_NOUT 54
+// lane-per-quartet classes up to this many integrals sum K[a,c], K[a,d] and
+// J[c,d] over a block of bras in registers; larger ones take one bra per tile
+#define FK_LPQ_BLOCK_NOUT 54
 #define FK_BLOCK 256
 #define FK_WAVES (FK_BLOCK / 64)
 
@@ -171,27 +174,24 @@ __device__ __forceinline__ int nth_bit(unsigned long long m, int n)
     return m ? __ffsll((long long)m) - 1 : -1;
 }
 
-// Next tile for this wave: tiles are sorted by decreasing estimated cost and
-// claimed one at a time, so long tiles start first and short ones fill in.
-__device__ __forceinline__ int claim_tile(unsigned int *ctr, int lane)
-{
-    unsigned int t = 0;
-    if (lane == 0) t = atomicAdd(ctr, 1u);
-    return __builtin_amdgcn_readfirstlane((int)__shfl((int)t, 0, 64));
-}
 
 // ---------------------------------------------------------------- lpq ----
-// One wave per tile (one bra pair, up to 64 ket pairs); lane i computes the
-// whole contracted quartet (bra | ket_i), consecutive lanes taking consecutive
-// kets, then digests it into the six blocks.  Ket primitives are the outer
-// loop (one coalesced load per primitive pair), bra primitives the inner loop
-// (wave-uniform, scalar loads).
+// One wave per tile: a block of bras (a, b_j) sharing the first shell a, and up
+// to 64 kets.  Lane i holds ket i and computes the contracted quartets
+// (a b_j | c_i d_i) for every bra of the block in turn: ket primitives outer
+// (one coalesced load per primitive), bra primitives inner (LDS broadcast).
+// Digestion: X_J[a, b_j] is reduced over the wave per bra; X_K[b_j, c],
+// X_K[b_j, d] go to memory per bra; X_K[a, c], X_K[a, d] and X_J[c, d] do not
+// depend on b_j and are summed in registers over the whole block first.
 template <int LA, int LB, int LC, int LD>
 __global__ void __launch_bounds__(FK_BLOCK) k_jk_lpq(FkJKArgs a)
 {
     using Q = fk::QClass<LA, LB, LC, LD>;
     constexpr int NA = Q::NA, NB = Q::NB, NC = Q::NC, ND = Q::ND, NOUT = Q::NOUT;
-    extern __shared__ double s_dyn[];
+    // block sums in registers (small classes); otherwise tiles hold one bra
+    // and those blocks go to memory per bra
+    constexpr bool BLK = NOUT <= FK_LPQ_BLOCK_NOUT;
+    FK_DYN_LDS(s_dyn);
     double *s_tab = s_dyn;
     load_table<Q::NR>(s_tab, a.rys_tab);
 
@@ -202,118 +202,140 @@ __global__ void __launch_bounds__(FK_BLOCK) k_jk_lpq(FkJKArgs a)
     const int n = a.nbf, ns = a.nshell;
     unsigned long long cq = 0, cp = 0;
 
-    for (int t = claim_tile(a.tile_next, lane); t < a.ntiles; t = claim_tile(a.tile_next, lane)) {
+    for (int t = blockIdx.x * FK_WAVES + wave; t < a.ntiles; t += nwt) {
         const FkTile tile = a.tiles[t];
-        const int bra = tile.bra;
         const bool same = (tile.grp & FK_TILE_SAME) != 0;
         const FkGroup g = a.groups[tile.grp & ~FK_TILE_SAME];
-        const BraInfo B = load_bra(a, bra);
+        const FkBraBlock blk = a.blocks[tile.blk];
         const bool inrange = lane < tile.ket_count;
         const int pos = tile.ket_begin + (inrange ? lane : 0);
         const int r = pos - g.begin;
         const KetInfo Kt = load_ket(a, pos);
-        const int sa = B.sa, sb = B.sb, sc = Kt.sc, sd = Kt.sd;
-        bool active = inrange;
-        if (a.dscreen) active = active && (B.G * Kt.G * dmax6(a.Dsh, ns, sa, sb, sc, sd) >= a.tau);
-        const unsigned long long mask = __ballot(active);
-        if (mask == 0ull) continue;
-        const int nact = __popcll(mask);
-        cq += nact;
-        cp += (unsigned long long)nact * B.npp * g.npp;
-
-        stage_bra(s_bra, a.pp, B.ppo, B.npp, lane);
-        double acc[NOUT];
+        const int sc = Kt.sc, sd = Kt.sd;
+        const int oc = a.sh_bf[sc], od = a.sh_bf[sd];
+        const int sa = a.pair_sa[a.blk_bra[blk.first]];
+        const int oa = a.sh_bf[sa];
+        // D_cd is used with every bra of the block
+        double dcd[NC * ND];
 #pragma unroll
-        for (int o = 0; o < NOUT; ++o) acc[o] = 0.0;
-        if (active) {
-            fk::PrimPair qn = load_ket_pp(a.ppT, g, 0, r);
-            for (int j = 0; j < g.npp; ++j) {
-                const fk::PrimPair q = qn;
-                if (j + 1 < g.npp) qn = load_ket_pp(a.ppT, g, j + 1, r);
+        for (int ic = 0; ic < NC; ++ic)
+#pragma unroll
+            for (int id = 0; id < ND; ++id) dcd[ic * ND + id] = a.Ds[(size_t)(oc + ic) * n + od + id];
+        // block sums: X_K[a, c], X_K[a, d], X_J[c, d]
+        double kac[NA * NC], kad[NA * ND], jcd[NC * ND];
+#pragma unroll
+        for (int o = 0; o < NA * NC; ++o) kac[o] = 0.0;
+#pragma unroll
+        for (int o = 0; o < NA * ND; ++o) kad[o] = 0.0;
+#pragma unroll
+        for (int o = 0; o < NC * ND; ++o) jcd[o] = 0.0;
+        bool any = false;
+
+        for (int jb = 0; jb < blk.count; ++jb) {
+            const int bra = a.blk_bra[blk.first + jb];
+            const int bpos = a.blk_pos[blk.first + jb];
+            const BraInfo B = load_bra(a, bra);
+            const int sb = B.sb;
+            // Schwarz bound, same-class triangle (ket position <= bra position)
+            // and density screen for this (bra, ket)
+            bool active = inrange && (!same || pos <= bpos) && (a.tau <= 0 || B.G * Kt.G >= a.tau);
+            if (a.dscreen) active = active && (B.G * Kt.G * dmax6(a.Dsh, ns, sa, sb, sc, sd) >= a.tau);
+            const unsigned long long mask = __ballot(active);
+            if (mask == 0ull) continue;
+            const int nact = __popcll(mask);
+            cq += nact;
+            cp += (unsigned long long)nact * B.npp * g.npp;
+
+            stage_bra(s_bra, a.pp, B.ppo, B.npp, lane);
+            double acc[NOUT];
+#pragma unroll
+            for (int o = 0; o < NOUT; ++o) acc[o] = 0.0;
+            if (active) {
+                fk::PrimPair qn = load_ket_pp(a.ppT, g, 0, r);
+                for (int j = 0; j < g.npp; ++j) {
+                    const fk::PrimPair q = qn;
+                    if (j + 1 < g.npp) qn = load_ket_pp(a.ppT, g, j + 1, r);
 #pragma unroll 2
-                for (int i = 0; i < B.npp; ++i)
-                    fk::rys_prim_all<LA, LB, LC, LD>(s_tab, lds_pp(s_bra, i), q, B.AB, Kt.CD, acc);
+                    for (int i = 0; i < B.npp; ++i)
+                        fk::rys_prim_all<LA, LB, LC, LD>(s_tab, lds_pp(s_bra, i), q, B.AB, Kt.CD, acc);
+                }
             }
-        }
-
-        const bool diag = same && a.ket_list[pos] == bra;
-        const double fac = (sa == sb ? 0.5 : 1.0) * (sc == sd ? 0.5 : 1.0) * (diag ? 0.5 : 1.0);
-        const int oa = a.sh_bf[sa], ob = a.sh_bf[sb], oc = a.sh_bf[sc], od = a.sh_bf[sd];
-        double jab[NA * NB];
+            const bool diag = same && pos == bpos;
+            const double fac = (sa == sb ? 0.5 : 1.0) * (sc == sd ? 0.5 : 1.0) * (diag ? 0.5 : 1.0);
+            const int ob = a.sh_bf[sb];
+            double jab[NA * NB];
 #pragma unroll
-        for (int o = 0; o < NA * NB; ++o) jab[o] = 0.0;
-        if (active) {
+            for (int o = 0; o < NA * NB; ++o) jab[o] = 0.0;
+            if (active) {
+                any = true;
 #pragma unroll
-            for (int o = 0; o < NOUT; ++o) acc[o] *= fac;
-            // X_J[a,b] partial (reduced over the wave below) and X_J[c,d]
-            {
-                double dcd[NC * ND], dab[NA * NB];
-#pragma unroll
-                for (int ic = 0; ic < NC; ++ic)
-#pragma unroll
-                    for (int id = 0; id < ND; ++id) dcd[ic * ND + id] = a.Ds[(size_t)(oc + ic) * n + od + id];
-#pragma unroll
-                for (int ia = 0; ia < NA; ++ia)
-#pragma unroll
-                    for (int ib = 0; ib < NB; ++ib) dab[ia * NB + ib] = a.Ds[(size_t)(oa + ia) * n + ob + ib];
-#pragma unroll
-                for (int ab = 0; ab < NA * NB; ++ab)
-#pragma unroll
-                    for (int cd = 0; cd < NC * ND; ++cd) jab[ab] += acc[ab * NC * ND + cd] * dcd[cd];
-#pragma unroll
-                for (int ic = 0; ic < NC; ++ic)
-#pragma unroll
-                    for (int id = 0; id < ND; ++id) {
-                        double s = 0.0;
-#pragma unroll
-                        for (int ab = 0; ab < NA * NB; ++ab) s += acc[ab * NC * ND + ic * ND + id] * dab[ab];
-                        atomic_add(&a.XJ[(size_t)(oc + ic) * n + od + id], 2.0 * s);
-                    }
-            }
-            // X_K[a,c] += v D_bd and X_K[a,d] += v D_bc
-            {
-                double dbd[NB * ND], dbc[NB * NC];
+                for (int o = 0; o < NOUT; ++o) acc[o] *= fac;
+                double dab[NA * NB], dbc[NB * NC], dbd[NB * ND];
 #pragma unroll
                 for (int ib = 0; ib < NB; ++ib) {
 #pragma unroll
-                    for (int id = 0; id < ND; ++id) dbd[ib * ND + id] = a.Ds[(size_t)(ob + ib) * n + od + id];
+                    for (int ia = 0; ia < NA; ++ia) dab[ia * NB + ib] = a.Ds[(size_t)(oa + ia) * n + ob + ib];
 #pragma unroll
                     for (int ic = 0; ic < NC; ++ic) dbc[ib * NC + ic] = a.Ds[(size_t)(ob + ib) * n + oc + ic];
+#pragma unroll
+                    for (int id = 0; id < ND; ++id) dbd[ib * ND + id] = a.Ds[(size_t)(ob + ib) * n + od + id];
                 }
+                // X_J[a, b] partial (reduced over the wave below); X_J[c, d] block sum
 #pragma unroll
-                for (int ia = 0; ia < NA; ++ia) {
+                for (int ab = 0; ab < NA * NB; ++ab)
 #pragma unroll
-                    for (int ic = 0; ic < NC; ++ic) {
-                        double s = 0.0;
-#pragma unroll
-                        for (int ib = 0; ib < NB; ++ib)
-#pragma unroll
-                            for (int id = 0; id < ND; ++id)
-                                s += acc[((ia * NB + ib) * NC + ic) * ND + id] * dbd[ib * ND + id];
-                        atomic_add(&a.XK[(size_t)(oa + ia) * n + oc + ic], s);
+                    for (int cd = 0; cd < NC * ND; ++cd) {
+                        jab[ab] += acc[ab * NC * ND + cd] * dcd[cd];
+                        if constexpr (BLK) jcd[cd] += acc[ab * NC * ND + cd] * dab[ab];
                     }
+                if constexpr (BLK) {
+                    // X_K[a, c] += v D_bd and X_K[a, d] += v D_bc (block sums)
 #pragma unroll
-                    for (int id = 0; id < ND; ++id) {
-                        double s = 0.0;
+                    for (int ia = 0; ia < NA; ++ia)
 #pragma unroll
                         for (int ib = 0; ib < NB; ++ib)
 #pragma unroll
                             for (int ic = 0; ic < NC; ++ic)
-                                s += acc[((ia * NB + ib) * NC + ic) * ND + id] * dbc[ib * NC + ic];
-                        atomic_add(&a.XK[(size_t)(oa + ia) * n + od + id], s);
+#pragma unroll
+                                for (int id = 0; id < ND; ++id) {
+                                    const double v = acc[((ia * NB + ib) * NC + ic) * ND + id];
+                                    kac[ia * NC + ic] += v * dbd[ib * ND + id];
+                                    kad[ia * ND + id] += v * dbc[ib * NC + ic];
+                                }
+                } else {
+                    // one bra per tile: X_J[c, d], X_K[a, c], X_K[a, d] straight to memory
+#pragma unroll
+                    for (int cd = 0; cd < NC * ND; ++cd) {
+                        double s = 0.0;
+#pragma unroll
+                        for (int ab = 0; ab < NA * NB; ++ab) s += acc[ab * NC * ND + cd] * dab[ab];
+                        atomic_add(&a.XJ[(size_t)(oc + cd / ND) * n + od + cd % ND], 2.0 * s);
+                    }
+#pragma unroll
+                    for (int ia = 0; ia < NA; ++ia) {
+#pragma unroll
+                        for (int ic = 0; ic < NC; ++ic) {
+                            double s = 0.0;
+#pragma unroll
+                            for (int ib = 0; ib < NB; ++ib)
+#pragma unroll
+                                for (int id = 0; id < ND; ++id)
+                                    s += acc[((ia * NB + ib) * NC + ic) * ND + id] * dbd[ib * ND + id];
+                            atomic_add(&a.XK[(size_t)(oa + ia) * n + oc + ic], s);
+                        }
+#pragma unroll
+                        for (int id = 0; id < ND; ++id) {
+                            double s = 0.0;
+#pragma unroll
+                            for (int ib = 0; ib < NB; ++ib)
+#pragma unroll
+                                for (int ic = 0; ic < NC; ++ic)
+                                    s += acc[((ia * NB + ib) * NC + ic) * ND + id] * dbc[ib * NC + ic];
+                            atomic_add(&a.XK[(size_t)(oa + ia) * n + od + id], s);
+                        }
                     }
                 }
-            }
-            // X_K[b,c] += v D_ad and X_K[b,d] += v D_ac
-            {
-                double dad[NA * ND], dac[NA * NC];
-#pragma unroll
-                for (int ia = 0; ia < NA; ++ia) {
-#pragma unroll
-                    for (int id = 0; id < ND; ++id) dad[ia * ND + id] = a.Ds[(size_t)(oa + ia) * n + od + id];
-#pragma unroll
-                    for (int ic = 0; ic < NC; ++ic) dac[ia * NC + ic] = a.Ds[(size_t)(oa + ia) * n + oc + ic];
-                }
+                // X_K[b, c] += v D_ad and X_K[b, d] += v D_ac (per bra)
 #pragma unroll
                 for (int ib = 0; ib < NB; ++ib) {
 #pragma unroll
@@ -323,7 +345,7 @@ __global__ void __launch_bounds__(FK_BLOCK) k_jk_lpq(FkJKArgs a)
                         for (int ia = 0; ia < NA; ++ia)
 #pragma unroll
                             for (int id = 0; id < ND; ++id)
-                                s += acc[((ia * NB + ib) * NC + ic) * ND + id] * dad[ia * ND + id];
+                                s += acc[((ia * NB + ib) * NC + ic) * ND + id] * a.Ds[(size_t)(oa + ia) * n + od + id];
                         atomic_add(&a.XK[(size_t)(ob + ib) * n + oc + ic], s);
                     }
 #pragma unroll
@@ -333,17 +355,31 @@ __global__ void __launch_bounds__(FK_BLOCK) k_jk_lpq(FkJKArgs a)
                         for (int ia = 0; ia < NA; ++ia)
 #pragma unroll
                             for (int ic = 0; ic < NC; ++ic)
-                                s += acc[((ia * NB + ib) * NC + ic) * ND + id] * dac[ia * NC + ic];
+                                s += acc[((ia * NB + ib) * NC + ic) * ND + id] * a.Ds[(size_t)(oa + ia) * n + oc + ic];
                         atomic_add(&a.XK[(size_t)(ob + ib) * n + od + id], s);
                     }
                 }
             }
-        }
-        // all lanes (active or not) take part in the wave reduction of X_J[a,b]
+            // all lanes (active or not) take part in the wave reduction of X_J[a, b]
 #pragma unroll
-        for (int ab = 0; ab < NA * NB; ++ab) {
-            const double s = wave_sum(jab[ab]);
-            if (lane == 0) atomic_add(&a.XJ[(size_t)(oa + ab / NB) * n + ob + ab % NB], 2.0 * s);
+            for (int ab = 0; ab < NA * NB; ++ab) {
+                const double s = wave_sum(jab[ab]);
+                if (lane == 0) atomic_add(&a.XJ[(size_t)(oa + ab / NB) * n + ob + ab % NB], 2.0 * s);
+            }
+        }
+        if (BLK && any) {
+#pragma unroll
+            for (int ia = 0; ia < NA; ++ia) {
+#pragma unroll
+                for (int ic = 0; ic < NC; ++ic) atomic_add(&a.XK[(size_t)(oa + ia) * n + oc + ic], kac[ia * NC + ic]);
+#pragma unroll
+                for (int id = 0; id < ND; ++id) atomic_add(&a.XK[(size_t)(oa + ia) * n + od + id], kad[ia * ND + id]);
+            }
+#pragma unroll
+            for (int ic = 0; ic < NC; ++ic)
+#pragma unroll
+                for (int id = 0; id < ND; ++id)
+                    atomic_add(&a.XJ[(size_t)(oc + ic) * n + od + id], 2.0 * jcd[ic * ND + id]);
         }
     }
     if (lane == 0 && cq) {
@@ -356,24 +392,46 @@ __global__ void __launch_bounds__(FK_BLOCK) k_jk_lpq(FkJKArgs a)
 // Team per quartet: a team of TS lanes computes one contracted quartet, lane
 // `comp` of the team owning bra component a (MODE 1, TS = NA, all b) or the
 // bra component pair (a, b) (MODE 2, TS = NA NB); a wave holds 64/TS teams,
-// which take consecutive kets of the tile.
+// which take consecutive kets of the tile.  A tile holds a block of bras that
+// share their first shell a; each team keeps its ket for every bra of the
+// block.  Sums that span the lanes of a team (X_K[b, c], X_K[b, d] per bra and
+// X_J[c, d] per block) or the whole wave (X_J[a, b] per bra, over all kets of
+// the tile) are formed with LDS atomics and reach memory once; X_K[a, c] and
+// X_K[a, d] stay in the lane's registers over the block.
+#define FK_TEAM_MAX_BLOCK 8
+
+template <int LA, int LB, int LC, int LD, int MODE>
+struct TeamShape {
+    using Q = fk::QClass<LA, LB, LC, LD>;
+    static constexpr int TS = (MODE == 1) ? Q::NA : Q::NA * Q::NB;
+    static constexpr int QPW = 64 / TS;
+    static constexpr int NVB = Q::NB * (Q::NC + Q::ND);   // team sums per bra
+    static constexpr int NV = NVB > Q::NC * Q::ND ? NVB : Q::NC * Q::ND;
+    // per-wave LDS for the reductions (doubles), after the staged bra records
+    static constexpr int RED = QPW * NV + FK_TEAM_MAX_BLOCK * Q::NA * Q::NB;
+};
+
+__device__ __forceinline__ void lds_add(double *p, double v) { unsafeAtomicAdd(p, v); }
+
 template <int LA, int LB, int LC, int LD, int MODE>
 __global__ void __launch_bounds__(FK_BLOCK) k_jk_tpq(FkJKArgs a)
 {
     using Q = fk::QClass<LA, LB, LC, LD>;
+    using TSh = TeamShape<LA, LB, LC, LD, MODE>;
     constexpr int NA = Q::NA, NB = Q::NB, NC = Q::NC, ND = Q::ND;
-    constexpr int TS = (MODE == 1) ? NA : NA * NB;
-    constexpr int QPW = 64 / TS;
+    constexpr int TS = TSh::TS, QPW = TSh::QPW, NV = TSh::NV;
     constexpr int NBL = (MODE == 1) ? NB : 1;
     constexpr int NOL = NBL * NC * ND;
     static_assert(QPW >= 1, "team larger than a wave");
-    extern __shared__ double s_dyn[];
+    FK_DYN_LDS(s_dyn);
     double *s_tab = s_dyn;
     load_table<Q::NR>(s_tab, a.rys_tab);
 
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    double *s_bra = s_dyn + rys_lds_size(Q::NR) + wave * a.bra_slot;
+    double *s_bra = s_dyn + rys_lds_size(Q::NR) + wave * (a.bra_slot + TSh::RED);
+    double *s_team = s_bra + a.bra_slot;     // [QPW][NV] team sums
+    double *s_jab = s_team + QPW * NV;       // [block bra][NA * NB] wave sums of X_J[a, b]
     const int nwt = gridDim.x * FK_WAVES;
     const int n = a.nbf, ns = a.nshell;
     const int slot = lane / TS, comp = lane % TS;
@@ -382,54 +440,28 @@ __global__ void __launch_bounds__(FK_BLOCK) k_jk_tpq(FkJKArgs a)
     const int ib0 = (MODE == 1) ? 0 : comp % NB;
     const int ax[3] = {fk::kCart.x[LA][ia], fk::kCart.y[LA][ia], fk::kCart.z[LA][ia]};
     const int bx[3] = {fk::kCart.x[LB][ib0], fk::kCart.y[LB][ib0], fk::kCart.z[LB][ib0]};
+    double *tsum = s_team + (lane_ok ? slot : 0) * NV;
     unsigned long long cq = 0, cp = 0;
 
-    for (int t = claim_tile(a.tile_next, lane); t < a.ntiles; t = claim_tile(a.tile_next, lane)) {
+    for (int t = blockIdx.x * FK_WAVES + wave; t < a.ntiles; t += nwt) {
         const FkTile tile = a.tiles[t];
-        const int bra = tile.bra;
         const bool same = (tile.grp & FK_TILE_SAME) != 0;
         const FkGroup g = a.groups[tile.grp & ~FK_TILE_SAME];
-        const BraInfo B = load_bra(a, bra);
-        const int sa = B.sa, sb = B.sb;
-        const int oa = a.sh_bf[sa], ob = a.sh_bf[sb];
-        // screen the tile's kets one per lane, then visit only the survivors
-        unsigned long long live;
-        {
-            const bool in = lane < tile.ket_count;
-            const KetInfo K0 = load_ket(a, tile.ket_begin + (in ? lane : 0));
-            bool ok = in;
-            if (a.dscreen) ok = ok && (B.G * K0.G * dmax6(a.Dsh, ns, sa, sb, K0.sc, K0.sd) >= a.tau);
-            live = __ballot(ok);
-        }
-        if (live == 0ull) continue;
-        stage_bra(s_bra, a.pp, B.ppo, B.npp, lane);
-        while (live) {
-            const int kk = lane_ok ? nth_bit(live, slot) : -1;
-#pragma unroll 1
-            for (int x = 0; x < QPW && live; ++x) live &= live - 1;
-            const bool active = kk >= 0;
-            const int pos = tile.ket_begin + (active ? kk : 0);
+        const FkBraBlock blk = a.blocks[tile.blk];
+        const int sa = a.pair_sa[a.blk_bra[blk.first]];
+        const int oa = a.sh_bf[sa];
+        const size_t ra = (size_t)(oa + ia) * n;
+        wave_sync_lds();
+        for (int x = lane; x < blk.count * NA * NB; x += 64) s_jab[x] = 0.0;
+
+        // rounds of QPW kets, one per team
+        for (int k0 = 0; k0 < tile.ket_count; k0 += QPW) {
+            const bool tin = lane_ok && k0 + slot < tile.ket_count;
+            const int pos = tile.ket_begin + (tin ? k0 + slot : 0);
             const int r = pos - g.begin;
             const KetInfo Kt = load_ket(a, pos);
             const int sc = Kt.sc, sd = Kt.sd;
-            const int nact = __popcll(__ballot(active)) / TS;
-            cq += nact;
-            cp += (unsigned long long)nact * B.npp * g.npp;
-            if (!active) continue;
-            double acc[NOL];
-#pragma unroll
-            for (int o = 0; o < NOL; ++o) acc[o] = 0.0;
-            fk::PrimPair qn = load_ket_pp(a.ppT, g, 0, r);
-            for (int j = 0; j < g.npp; ++j) {
-                const fk::PrimPair q = qn;
-                if (j + 1 < g.npp) qn = load_ket_pp(a.ppT, g, j + 1, r);
-                for (int i = 0; i < B.npp; ++i)
-                    fk::rys_prim_team<LA, LB, LC, LD, MODE>(s_tab, lds_pp(s_bra, i), q, B.AB, Kt.CD, ax, bx, acc);
-            }
-            const bool diag = same && a.ket_list[pos] == bra;
-            const double fac = (sa == sb ? 0.5 : 1.0) * (sc == sd ? 0.5 : 1.0) * (diag ? 0.5 : 1.0);
             const int oc = a.sh_bf[sc], od = a.sh_bf[sd];
-            const size_t ra = (size_t)(oa + ia) * n;
             double kac[NC], kad[ND], jcd[NC * ND];
 #pragma unroll
             for (int ic = 0; ic < NC; ++ic) kac[ic] = 0.0;
@@ -437,44 +469,107 @@ __global__ void __launch_bounds__(FK_BLOCK) k_jk_tpq(FkJKArgs a)
             for (int id = 0; id < ND; ++id) kad[id] = 0.0;
 #pragma unroll
             for (int o = 0; o < NC * ND; ++o) jcd[o] = 0.0;
+            bool any = false;
+
+            for (int jb = 0; jb < blk.count; ++jb) {
+                const int bra = a.blk_bra[blk.first + jb];
+                const int bpos = a.blk_pos[blk.first + jb];
+                const BraInfo B = load_bra(a, bra);
+                const int sb = B.sb;
+                bool active = tin && (!same || pos <= bpos) && (a.tau <= 0 || B.G * Kt.G >= a.tau);
+                if (a.dscreen) active = active && (B.G * Kt.G * dmax6(a.Dsh, ns, sa, sb, sc, sd) >= a.tau);
+                const unsigned long long mask = __ballot(active);
+                if (mask == 0ull) continue;
+                const int nact = __popcll(mask) / TS;
+                cq += nact;
+                cp += (unsigned long long)nact * B.npp * g.npp;
+                stage_bra(s_bra, a.pp, B.ppo, B.npp, lane);
+                double acc[NOL];
 #pragma unroll
-            for (int jb = 0; jb < NBL; ++jb) {
-                const int ib = (MODE == 1) ? jb : ib0;
-                const size_t rb = (size_t)(ob + ib) * n;
-                const double dab = a.Ds[ra + ob + ib];
-                double sj = 0.0;
-#pragma unroll
-                for (int ic = 0; ic < NC; ++ic) {
-                    double kbc = 0.0;
-#pragma unroll
-                    for (int id = 0; id < ND; ++id) {
-                        const double v = fac * acc[(jb * NC + ic) * ND + id];
-                        sj += v * a.Ds[(size_t)(oc + ic) * n + od + id];
-                        jcd[ic * ND + id] += v * dab;
-                        kac[ic] += v * a.Ds[rb + od + id];
-                        kad[id] += v * a.Ds[rb + oc + ic];
-                        kbc += v * a.Ds[ra + od + id];
+                for (int o = 0; o < NOL; ++o) acc[o] = 0.0;
+                if (active) {
+                    fk::PrimPair qn = load_ket_pp(a.ppT, g, 0, r);
+                    for (int j = 0; j < g.npp; ++j) {
+                        const fk::PrimPair q = qn;
+                        if (j + 1 < g.npp) qn = load_ket_pp(a.ppT, g, j + 1, r);
+                        for (int i = 0; i < B.npp; ++i)
+                            fk::rys_prim_team<LA, LB, LC, LD, MODE>(s_tab, lds_pp(s_bra, i), q, B.AB, Kt.CD, ax, bx, acc);
                     }
-                    atomic_add(&a.XK[rb + oc + ic], kbc);
                 }
+                const bool diag = same && pos == bpos;
+                const double fac = (sa == sb ? 0.5 : 1.0) * (sc == sd ? 0.5 : 1.0) * (diag ? 0.5 : 1.0);
+                const int ob = a.sh_bf[sb];
+                // team sums of X_K[b, c] and X_K[b, d] for this bra
+                if (lane_ok)
+                    for (int v = comp; v < NV; v += TS) tsum[v] = 0.0;
+                wave_sync_lds();
+                if (active) {
+                    any = true;
 #pragma unroll
-                for (int id = 0; id < ND; ++id) {
-                    double kbd = 0.0;
+                    for (int jj = 0; jj < NBL; ++jj) {
+                        const int ib = (MODE == 1) ? jj : ib0;
+                        const size_t rb = (size_t)(ob + ib) * n;
+                        const double dab = a.Ds[ra + ob + ib];
+                        double sj = 0.0;
 #pragma unroll
-                    for (int ic = 0; ic < NC; ++ic) kbd += fac * acc[(jb * NC + ic) * ND + id] * a.Ds[ra + oc + ic];
-                    atomic_add(&a.XK[rb + od + id], kbd);
+                        for (int ic = 0; ic < NC; ++ic) {
+                            double kbc = 0.0;
+#pragma unroll
+                            for (int id = 0; id < ND; ++id) {
+                                const double v = fac * acc[(jj * NC + ic) * ND + id];
+                                sj += v * a.Ds[(size_t)(oc + ic) * n + od + id];
+                                jcd[ic * ND + id] += v * dab;
+                                kac[ic] += v * a.Ds[rb + od + id];
+                                kad[id] += v * a.Ds[rb + oc + ic];
+                                kbc += v * a.Ds[ra + od + id];
+                            }
+                            lds_add(&tsum[ib * NC + ic], kbc);
+                        }
+#pragma unroll
+                        for (int id = 0; id < ND; ++id) {
+                            double kbd = 0.0;
+#pragma unroll
+                            for (int ic = 0; ic < NC; ++ic) kbd += fac * acc[(jj * NC + ic) * ND + id] * a.Ds[ra + oc + ic];
+                            lds_add(&tsum[NB * NC + ib * ND + id], kbd);
+                        }
+                        lds_add(&s_jab[jb * NA * NB + ia * NB + ib], sj);
+                    }
                 }
-                atomic_add(&a.XJ[ra + ob + ib], 2.0 * sj);
+                wave_sync_lds();
+                if (active)
+                    for (int v = comp; v < TSh::NVB; v += TS) {
+                        size_t dst;
+                        if (v < NB * NC) dst = (size_t)(ob + v / NC) * n + oc + v % NC;
+                        else dst = (size_t)(ob + (v - NB * NC) / ND) * n + od + (v - NB * NC) % ND;
+                        atomic_add(&a.XK[dst], tsum[v]);
+                    }
+                wave_sync_lds();
             }
+            // end of the block for this round's kets: X_K[a, c], X_K[a, d] from
+            // the lanes, X_J[c, d] as a team sum
+            if (lane_ok)
+                for (int v = comp; v < NV; v += TS) tsum[v] = 0.0;
+            wave_sync_lds();
+            if (any) {
 #pragma unroll
-            for (int ic = 0; ic < NC; ++ic) atomic_add(&a.XK[ra + oc + ic], kac[ic]);
+                for (int ic = 0; ic < NC; ++ic) atomic_add(&a.XK[ra + oc + ic], kac[ic]);
 #pragma unroll
-            for (int id = 0; id < ND; ++id) atomic_add(&a.XK[ra + od + id], kad[id]);
+                for (int id = 0; id < ND; ++id) atomic_add(&a.XK[ra + od + id], kad[id]);
 #pragma unroll
-            for (int ic = 0; ic < NC; ++ic)
-#pragma unroll
-                for (int id = 0; id < ND; ++id)
-                    atomic_add(&a.XJ[(size_t)(oc + ic) * n + od + id], 2.0 * jcd[ic * ND + id]);
+                for (int o = 0; o < NC * ND; ++o) lds_add(&tsum[o], jcd[o]);
+            }
+            wave_sync_lds();
+            if (any)
+                for (int v = comp; v < NC * ND; v += TS)
+                    atomic_add(&a.XJ[(size_t)(oc + v / ND) * n + od + v % ND], 2.0 * tsum[v]);
+            wave_sync_lds();
+        }
+        // X_J[a, b] of every bra of the block, summed over the tile's kets
+        for (int x = lane; x < blk.count * NA * NB; x += 64) {
+            const int jb = x / (NA * NB), ab = x % (NA * NB);
+            const int ob = a.sh_bf[a.pair_sb[a.blk_bra[blk.first + jb]]];
+            const double v = s_jab[x];
+            if (v != 0.0) atomic_add(&a.XJ[(size_t)(oa + ab / NB) * n + ob + ab % NB], 2.0 * v);
         }
     }
     if (lane == 0 && cq) {
@@ -494,7 +589,7 @@ __global__ void __launch_bounds__(FK_BLOCK) k_jk_wpq(FkJKArgs a)
     constexpr int NB = Q::NB, NC = Q::NC, ND = Q::ND;
     constexpr int NAB = Q::NA * Q::NB, NCD = NC * ND;
     constexpr int ITEMS = (NAB + 63) / 64;
-    extern __shared__ double s_dyn[];
+    FK_DYN_LDS(s_dyn);
     double *s_tab = s_dyn;
     load_table<Q::NR>(s_tab, a.rys_tab);
 
@@ -517,9 +612,11 @@ __global__ void __launch_bounds__(FK_BLOCK) k_jk_wpq(FkJKArgs a)
         ibx[k][0] = fk::kCart.x[LB][ib]; ibx[k][1] = fk::kCart.y[LB][ib]; ibx[k][2] = fk::kCart.z[LB][ib];
     }
 
-    for (int t = claim_tile(a.tile_next, lane); t < a.ntiles; t = claim_tile(a.tile_next, lane)) {
+    for (int t = blockIdx.x * FK_WAVES + wave; t < a.ntiles; t += nwt) {
         const FkTile tile = a.tiles[t];
-        const int bra = tile.bra;
+        // team and wave kernels get blocks of one bra: the tile's kets are
+        // exactly that bra's Schwarz prefix (and same-class triangle)
+        const int bra = a.blk_bra[a.blocks[tile.blk].first];
         const bool same = (tile.grp & FK_TILE_SAME) != 0;
         const FkGroup g = a.groups[tile.grp & ~FK_TILE_SAME];
         const BraInfo B = load_bra(a, bra);
@@ -725,6 +822,9 @@ struct Disp {
         i->la = LA; i->lb = LB; i->lc = LC; i->ld = LD;
         i->nroot = C::NR; i->nout = C::NOUT;
         i->wave_per_quartet = KIND;
+        // largest bra block the kernel takes (1: one bra per tile)
+        i->bra_block = (KIND == 0 && C::NOUT <= FK_LPQ_BLOCK_NOUT) ? FK_MAX_BRA_BLOCK
+                       : ((KIND == 1 || KIND == 2) ? FK_TEAM_MAX_BLOCK : 1);
         i->team_size = KIND == 0 ? 1 : (KIND == 1 ? C::NA : (KIND == 2 ? C::NA * C::NB : 64));
         i->flops_prim = fk::flops_prim(LA, LB, LC, LD);
         i->flops_quartet = fk::flops_digest(LA, LB, LC, LD);
@@ -740,7 +840,9 @@ struct Disp {
     static int lds_bytes(int bra_slot)
     {
         using C = fk::QClass<LA, LB, LC, LD>;
-        return (int)sizeof(double) * (rys_lds_size(C::NR) + FK_WAVES * bra_slot);
+        int extra = 0;
+        if constexpr (KIND == 1 || KIND == 2) extra = TeamShape<LA, LB, LC, LD, KIND>::RED;
+        return (int)sizeof(double) * (rys_lds_size(C::NR) + FK_WAVES * (bra_slot + extra));
     }
     static int launch_jk(const FkJKArgs *a, int grid, hipStream_t st)
     {
