@@ -26,6 +26,7 @@ sys.path.insert(0, HERE)
 
 METRIC = "J+K Fock builds/s & ERI quartets/s, FP64 vs mixed @1e-6 Eh; SCF iters"
 PEAK_FP64_VALU = 78.6  # TFLOP/s, MI355X dense FP64 vector
+PEAK_FP32_VALU = 157.3  # TFLOP/s, MI355X dense FP32 vector
 
 
 def _workload(name):
@@ -87,6 +88,8 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--classes", action="store_true", help="print the per-class kernel table to stderr")
     ap.add_argument("--no-scf", action="store_true", help="skip the SCF run reported beside the build rate")
+    ap.add_argument("--tau-fp32", type=float, default=0.0,
+                    help="precision split: FP32 recurrences for quartets with G_ab G_cd * 2 below this (0: FP64)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported", file=sys.stderr)
@@ -95,7 +98,7 @@ def main():
     import paper_2407_21445_amd as fk
 
     sys_, desc = _workload(args.workload)
-    ctx = fk.FockJK(0).set_system(sys_).build_quartets(tau=args.tau, tau_prim=args.tau_prim)
+    ctx = fk.FockJK(0).set_system(sys_).build_quartets(tau=args.tau, tau_prim=args.tau_prim, tau_fp32=args.tau_fp32)
     info = ctx.info()
     S, T, V, _ = ctx.one_electron()
     D = _core_density(S, T + V, sys_["nelec"] // 2)
@@ -145,29 +148,58 @@ def main():
                   f"{cc['prim_quartets']:13d} {f / 1e9:9.2f} {tf:8.3f} {tf / PEAK_FP64_VALU:6.3f}", file=sys.stderr)
     cflops = c["prim_quartets"] * c["flops_per_prim"] + c["quartets"] * c["flops_per_quartet"]
     achieved = cflops / (cls_ms[i] * 1e-3) / 1e12
+    peak = PEAK_FP32_VALU if c["precision"] == 32 else PEAK_FP64_VALU
     lname = "spdf"
     cname = "({}{}|{}{})".format(*(lname[x] for x in c["class"]))
     out = {
         "metric": METRIC, "value": 1000.0 / ms, "unit": "builds/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
-        "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "vs_baseline": None, "dtype": "f64" if args.tau_fp32 <= 0 else "f64+f32", "data": "synthetic",
         "config": {"workload": desc, "nbf": info["nbf"], "nshell": info["nshell"], "tau": args.tau,
                    "tau_prim": args.tau_prim,
-                   "density": "core-Hamiltonian guess", "precision": "fp64"},
+                   "density": "core-Hamiltonian guess",
+                   "precision": "fp64" if args.tau_fp32 <= 0 else f"mixed (FP32 below tau_fp32={args.tau_fp32:g})"},
         "quartets_per_s": st["quartets"] / (ms * 1e-3),
         "prim_quartets_per_s": st["prim_quartets"] / (ms * 1e-3),
         "quartets_per_build": st["quartets"], "schwarz_quartets": info["nquartet_schwarz"],
         "flops_per_build": st["flops_total"], "tflops_build": st["flops_total"] / (ms * 1e-3) / 1e12,
         "wall_s_timed": wall,
-        "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP64_VALU, "unit": "TFLOP/s",
-                     "frac": achieved / PEAK_FP64_VALU, "traffic": None,
-                     "kernel": f"J/K class {cname}", "kernel_ms": float(cls_ms[i]),
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
+                     "frac": achieved / peak, "traffic": None,
+                     "kernel": f"J/K class {cname}" + (" (FP32 part)" if c["precision"] == 32 else ""),
+                     "kernel_ms": float(cls_ms[i]),
                      "class_share": float(cls_ms[i] / cls_ms.sum())},
     }
+    if args.tau_fp32 > 0:
+        # the same build in FP64 only: J/K and one-build energy differences
+        ref = fk.FockJK(0).set_system(sys_).build_quartets(tau=args.tau, tau_prim=args.tau_prim)
+        J64, K64 = ref.build_jk(Dd, sync=True)
+        torch.cuda.synchronize()
+        for _ in range(2):
+            ref.build_jk(Dd, J64, K64, stream=stream)
+        r0 = torch.cuda.Event(enable_timing=True)
+        r1 = torch.cuda.Event(enable_timing=True)
+        r0.record(stream)
+        for _ in range(args.steps):
+            ref.build_jk(Dd, J64, K64, stream=stream)
+        r1.record(stream)
+        torch.cuda.synchronize()
+        ms64 = r0.elapsed_time(r1) / args.steps
+        dJ = (J - J64).cpu().numpy()
+        dK = (K - K64).cpu().numpy()
+        n32 = sum(x["quartets"] for x in st["classes"] if x["precision"] == 32)
+        out["mixed"] = {"tau_fp32": args.tau_fp32, "fp32_quartet_fraction": n32 / max(1, st["quartets"]),
+                        "fp64_builds_per_s": 1000.0 / ms64, "speedup": ms64 / ms,
+                        "max_abs_dJ": float(np.max(np.abs(dJ))), "max_abs_dK": float(np.max(np.abs(dK))),
+                        "dE_one_build": float(0.5 * np.sum(D * dJ) - 0.25 * np.sum(D * dK))}
     if not args.no_scf:
         # SCF from the core-Hamiltonian guess on the same quartet lists (outside
         # the timed region): iterations to |dE| < 1e-10, max|error| < 1e-8
         r = ctx.run_scf()
+        if args.tau_fp32 > 0:
+            r64 = ref.run_scf()
+            out["mixed"]["scf_energy_fp64"] = r64["energy"]
+            out["mixed"]["scf_energy_diff"] = r["energy"] - r64["energy"]
         out["scf"] = {"iterations": r["iterations"], "converged": bool(r["converged"]), "energy": r["energy"],
                       "seconds": r["total_seconds"], "jk_seconds": r["jk_seconds"], "guess": "core Hamiltonian"}
     if not args.no_cpu_baseline:

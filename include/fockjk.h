@@ -79,6 +79,10 @@ typedef struct {
                           pairs with the same kets (1..32; 0 = default 8).
                           Contributions to K[a, c], K[a, d] and J[c, d] are
                           summed over the block before they reach memory */
+    double tau_fp32;   /* precision split: quartets with G_ab G_cd * 2 < tau_fp32
+                          (2 bounds |D| of a closed-shell density) evaluate their
+                          recurrences in FP32; set-up, roots, weights,
+                          digestion and all accumulation stay FP64.  0 = FP64 only */
 } fk_screen_opts;
 
 typedef struct {
@@ -97,7 +101,7 @@ typedef struct {
 /* Per-build statistics of the last fk_build_jk (filled by fk_stats).  On a
  * context without a device, or before the first build, only the host-side
  * fields (class, tiles, prim_slots, flops per unit) are filled. */
-#define FK_MAX_QCLASS 55
+#define FK_MAX_QCLASS 110  /* 55 classes, each with an FP64 and an FP32 launch */
 typedef struct {
     int     nclass;                       /* quartet classes launched */
     int     la[FK_MAX_QCLASS], lb[FK_MAX_QCLASS], lc[FK_MAX_QCLASS], ld[FK_MAX_QCLASS];
@@ -109,6 +113,7 @@ typedef struct {
     double  class_ms[FK_MAX_QCLASS];      /* kernel time per class (FK_TIME_CLASSES builds), else 0 */
     int64_t tiles[FK_MAX_QCLASS];         /* work tiles of the class */
     int     team_size[FK_MAX_QCLASS];     /* lanes computing one quartet (1, a team, or 64) */
+    int     precision[FK_MAX_QCLASS];     /* 64: FP64 launch, 32: FP32 launch of the split */
     int64_t prim_slots[FK_MAX_QCLASS];    /* lane x primitive-quartet slots the waves step
                                              through if no quartet fails the density screen:
                                              per tile, rounds x 64 lanes x bra x ket primitive

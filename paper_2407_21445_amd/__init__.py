@@ -31,13 +31,13 @@ _lib = ctypes.CDLL(LIB_PATH)
 
 FK_OK, FK_ERR_ARG, FK_ERR_UNSUPPORTED, FK_ERR_HIP, FK_ERR_OOM, FK_ERR_NOT_CONVERGED, FK_ERR_STATE = 0, -1, -2, -3, -4, -5, -6
 FK_DEVICE_PTRS, FK_SYNC, FK_TIME_CLASSES = 1, 2, 4
-FK_MAX_QCLASS = 55
+FK_MAX_QCLASS = 110
 MAX_L, MAX_K = 3, 9
 
 
 class ScreenOpts(ctypes.Structure):
     _fields_ = [("tau", ctypes.c_double), ("tau_prim", ctypes.c_double),
-                ("density_screen", ctypes.c_int), ("bra_block", ctypes.c_int)]
+                ("density_screen", ctypes.c_int), ("bra_block", ctypes.c_int), ("tau_fp32", ctypes.c_double)]
 
 
 class Info(ctypes.Structure):
@@ -56,7 +56,7 @@ class Stats(ctypes.Structure):
                 ("prim_quartets", ctypes.c_int64 * _Q), ("flops_per_prim", ctypes.c_double * _Q),
                 ("flops_per_quartet", ctypes.c_double * _Q), ("flops_total", ctypes.c_double),
                 ("class_ms", ctypes.c_double * _Q), ("tiles", ctypes.c_int64 * _Q),
-                ("team_size", ctypes.c_int * _Q), ("prim_slots", ctypes.c_int64 * _Q)]
+                ("team_size", ctypes.c_int * _Q), ("precision", ctypes.c_int * _Q), ("prim_slots", ctypes.c_int64 * _Q)]
 
 
 class ScfOpts(ctypes.Structure):
@@ -163,8 +163,8 @@ class FockJK:
         self.nbf = int(sum(_ncart(int(l)) for l in sl))
         return self
 
-    def build_quartets(self, tau=1e-10, tau_prim=0.0, density_screen=True, bra_block=0):
-        o = ScreenOpts(float(tau), float(tau_prim), 1 if density_screen else 0, int(bra_block))
+    def build_quartets(self, tau=1e-10, tau_prim=0.0, density_screen=True, bra_block=0, tau_fp32=0.0):
+        o = ScreenOpts(float(tau), float(tau_prim), 1 if density_screen else 0, int(bra_block), float(tau_fp32))
         self._check(_lib.fk_build_quartets(self._ctx, ctypes.byref(o)))
         return self
 
@@ -209,7 +209,7 @@ class FockJK:
             out.append({"class": (s.la[i], s.lb[i], s.lc[i], s.ld[i]), "quartets": s.quartets[i],
                         "prim_quartets": s.prim_quartets[i], "flops_per_prim": s.flops_per_prim[i],
                         "flops_per_quartet": s.flops_per_quartet[i], "ms": s.class_ms[i],
-                        "tiles": s.tiles[i], "team_size": s.team_size[i],
+                        "tiles": s.tiles[i], "team_size": s.team_size[i], "precision": s.precision[i],
                         "prim_slots": s.prim_slots[i]})
         return {"classes": out, "flops_total": s.flops_total,
                 "quartets": sum(c["quartets"] for c in out), "prim_quartets": sum(c["prim_quartets"] for c in out)}

@@ -73,33 +73,32 @@ struct PrimPair {
 
 // 2-D recurrences of one axis for one root followed by both horizontal
 // recurrences; I[a][b][c][d] for a <= LA, b <= LB, c <= LC, d <= LD.
-template <int LA, int LB, int LC, int LD>
-FK_HD void vrr_hrr_axis(double C00, double C00p, double B00, double B10, double B01,
-                        double AB, double CD, double g00,
-                        double (&I)[LA + 1][LB + 1][LC + 1][LD + 1])
+template <int LA, int LB, int LC, int LD, typename R = double>
+FK_HD void vrr_hrr_axis(R C00, R C00p, R B00, R B10, R B01, R AB, R CD, R g00,
+                        R (&I)[LA + 1][LB + 1][LC + 1][LD + 1])
 {
     constexpr int LAB = LA + LB, LCD = LC + LD;
-    double G[LAB + 1][LCD + 1];
+    R G[LAB + 1][LCD + 1];
     G[0][0] = g00;
     if constexpr (LAB > 0) {
         G[1][0] = C00 * g00;
 #pragma unroll
-        for (int e = 1; e < LAB; ++e) G[e + 1][0] = C00 * G[e][0] + (double)e * B10 * G[e - 1][0];
+        for (int e = 1; e < LAB; ++e) G[e + 1][0] = C00 * G[e][0] + (R)e * B10 * G[e - 1][0];
     }
     if constexpr (LCD > 0) {
         G[0][1] = C00p * g00;
 #pragma unroll
-        for (int e = 1; e <= LAB; ++e) G[e][1] = C00p * G[e][0] + (double)e * B00 * G[e - 1][0];
+        for (int e = 1; e <= LAB; ++e) G[e][1] = C00p * G[e][0] + (R)e * B00 * G[e - 1][0];
 #pragma unroll
         for (int f = 1; f < LCD; ++f) {
-            G[0][f + 1] = C00p * G[0][f] + (double)f * B01 * G[0][f - 1];
+            G[0][f + 1] = C00p * G[0][f] + (R)f * B01 * G[0][f - 1];
 #pragma unroll
             for (int e = 1; e <= LAB; ++e)
-                G[e][f + 1] = C00p * G[e][f] + (double)f * B01 * G[e][f - 1] + (double)e * B00 * G[e - 1][f];
+                G[e][f + 1] = C00p * G[e][f] + (R)f * B01 * G[e][f - 1] + (R)e * B00 * G[e - 1][f];
         }
     }
     // bra HRR: H[a][b][f], valid for a <= LAB - b
-    double H[LAB + 1][LB + 1][LCD + 1];
+    R H[LAB + 1][LB + 1][LCD + 1];
 #pragma unroll
     for (int e = 0; e <= LAB; ++e)
 #pragma unroll
@@ -115,7 +114,7 @@ FK_HD void vrr_hrr_axis(double C00, double C00p, double B00, double B10, double 
     for (int a = 0; a <= LA; ++a)
 #pragma unroll
         for (int b = 0; b <= LB; ++b) {
-            double Kt[LCD + 1][LD + 1];
+            R Kt[LCD + 1][LD + 1];
 #pragma unroll
             for (int c = 0; c <= LCD; ++c) Kt[c][0] = H[a][b][c];
 #pragma unroll
@@ -179,32 +178,44 @@ FK_HD QuartetSetup quartet_setup(const PrimPair &p, const PrimPair &q)
 }
 
 // Adds the primitive quartet [ab|cd] to acc[NA][NB][NC][ND] (all components).
-template <int LA, int LB, int LC, int LD>
+// Adds the primitive quartet [ab|cd] to acc[NA][NB][NC][ND] (all components).
+// The set-up (T, prefactor) and the roots and weights are FP64; the 2-D
+// recurrences, transfers and products run in R (double, or float for the
+// quartets the precision split assigns to FP32).
+template <int LA, int LB, int LC, int LD, typename R = double>
 FK_HD void rys_prim_all(const double *__restrict tab, const PrimPair &p, const PrimPair &q,
-                        const double AB[3], const double CD[3], double *__restrict acc)
+                        const double AB[3], const double CD[3], R *__restrict acc)
 {
     using Q = QClass<LA, LB, LC, LD>;
     QuartetSetup s = quartet_setup(p, q);
     double u[Q::NR], w[Q::NR];
     rys_roots<Q::NR, (Q::L > 0)>(s.T, tab, u, w);
     if constexpr (Q::L == 0) {
-        acc[0] += w[0] * s.pref;
+        acc[0] += (R)(w[0] * s.pref);
         return;
     } else {
-        double ezPQ[3], zzPQ[3];
+        R ezPQ[3], zzPQ[3], PA[3], QC[3], ab[3], cd[3];
 #pragma unroll
-        for (int k = 0; k < 3; ++k) { ezPQ[k] = s.ez * s.PQ[k]; zzPQ[k] = s.zz * s.PQ[k]; }
+        for (int k = 0; k < 3; ++k) {
+            ezPQ[k] = (R)(s.ez * s.PQ[k]);
+            zzPQ[k] = (R)(s.zz * s.PQ[k]);
+            PA[k] = (R)p.PA[k];
+            QC[k] = (R)q.PA[k];
+            ab[k] = (R)AB[k];
+            cd[k] = (R)CD[k];
+        }
+        const R hinv = (R)(0.5 * s.inv), ez = (R)s.ez, zz = (R)s.zz, po = (R)p.oo2z, qo = (R)q.oo2z;
 #pragma unroll
         for (int r = 0; r < Q::NR; ++r) {
-            const double ur = u[r];
-            const double B00 = 0.5 * s.inv * ur;
-            const double B10 = p.oo2z * (1.0 - s.ez * ur);
-            const double B01 = q.oo2z * (1.0 - s.zz * ur);
-            double I[3][LA + 1][LB + 1][LC + 1][LD + 1];
+            const R ur = (R)u[r];
+            const R B00 = hinv * ur;
+            const R B10 = po * ((R)1 - ez * ur);
+            const R B01 = qo * ((R)1 - zz * ur);
+            R I[3][LA + 1][LB + 1][LC + 1][LD + 1];
 #pragma unroll
             for (int k = 0; k < 3; ++k)
-                vrr_hrr_axis<LA, LB, LC, LD>(p.PA[k] - ezPQ[k] * ur, q.PA[k] + zzPQ[k] * ur, B00, B10, B01,
-                                             AB[k], CD[k], k == 2 ? w[r] * s.pref : 1.0, I[k]);
+                vrr_hrr_axis<LA, LB, LC, LD, R>(PA[k] - ezPQ[k] * ur, QC[k] + zzPQ[k] * ur, B00, B10, B01, ab[k], cd[k],
+                                                k == 2 ? (R)(w[r] * s.pref) : (R)1, I[k]);
 #pragma unroll
             for (int ia = 0; ia < Q::NA; ++ia)
 #pragma unroll
@@ -322,9 +333,9 @@ FK_HD void rys_prim_bra_comp(const double *__restrict tab, const PrimPair &p, co
 // for MODE 1, every b component (NB*NC*ND outputs), for MODE 2 the single b
 // component b[3] (NC*ND outputs).  The 2-D recurrences are evaluated per lane;
 // the bra transfer uses the closed form I(a,b) = sum_j C(b,j) AB^(b-j) G(a+j).
-template <int LA, int LB, int LC, int LD, int MODE>
+template <int LA, int LB, int LC, int LD, int MODE, typename R = double>
 FK_HD void rys_prim_team(const double *__restrict tab, const PrimPair &p, const PrimPair &q, const double AB[3],
-                         const double CD[3], const int a[3], const int b[3], double *__restrict acc)
+                         const double CD[3], const int a[3], const int b[3], R *__restrict acc)
 {
     using Q = QClass<LA, LB, LC, LD>;
     constexpr int LAB = Q::LAB, LCD = Q::LCD;
@@ -334,53 +345,53 @@ FK_HD void rys_prim_team(const double *__restrict tab, const PrimPair &p, const 
     rys_roots<Q::NR, (Q::L > 0)>(s.T, tab, u, w);
 #pragma unroll
     for (int r = 0; r < Q::NR; ++r) {
-        const double ur = (Q::L > 0) ? u[r] : 0.0;
-        const double B00 = 0.5 * s.inv * ur;
-        const double B10 = p.oo2z * (1.0 - s.ez * ur);
-        const double B01 = q.oo2z * (1.0 - s.zz * ur);
-        double I[3][NBL][LC + 1][LD + 1];
+        const R ur = (Q::L > 0) ? (R)u[r] : (R)0;
+        const R B00 = (R)(0.5 * s.inv) * ur;
+        const R B10 = (R)p.oo2z * ((R)1 - (R)s.ez * ur);
+        const R B01 = (R)q.oo2z * ((R)1 - (R)s.zz * ur);
+        R I[3][NBL][LC + 1][LD + 1];
 #pragma unroll
         for (int k = 0; k < 3; ++k) {
-            const double C00 = p.PA[k] - s.ez * s.PQ[k] * ur;
-            const double C00p = q.PA[k] + s.zz * s.PQ[k] * ur;
-            double G[LAB + 1][LCD + 1];
-            G[0][0] = (k == 2) ? w[r] * s.pref : 1.0;
+            const R C00 = (R)p.PA[k] - (R)(s.ez * s.PQ[k]) * ur;
+            const R C00p = (R)q.PA[k] + (R)(s.zz * s.PQ[k]) * ur;
+            R G[LAB + 1][LCD + 1];
+            G[0][0] = (k == 2) ? (R)(w[r] * s.pref) : (R)1;
             if constexpr (LAB > 0) {
                 G[1][0] = C00 * G[0][0];
 #pragma unroll
-                for (int e = 1; e < LAB; ++e) G[e + 1][0] = C00 * G[e][0] + (double)e * B10 * G[e - 1][0];
+                for (int e = 1; e < LAB; ++e) G[e + 1][0] = C00 * G[e][0] + (R)e * B10 * G[e - 1][0];
             }
             if constexpr (LCD > 0) {
                 G[0][1] = C00p * G[0][0];
 #pragma unroll
-                for (int e = 1; e <= LAB; ++e) G[e][1] = C00p * G[e][0] + (double)e * B00 * G[e - 1][0];
+                for (int e = 1; e <= LAB; ++e) G[e][1] = C00p * G[e][0] + (R)e * B00 * G[e - 1][0];
 #pragma unroll
                 for (int f = 1; f < LCD; ++f) {
-                    G[0][f + 1] = C00p * G[0][f] + (double)f * B01 * G[0][f - 1];
+                    G[0][f + 1] = C00p * G[0][f] + (R)f * B01 * G[0][f - 1];
 #pragma unroll
                     for (int e = 1; e <= LAB; ++e)
-                        G[e][f + 1] = C00p * G[e][f] + (double)f * B01 * G[e][f - 1] + (double)e * B00 * G[e - 1][f];
+                        G[e][f + 1] = C00p * G[e][f] + (R)f * B01 * G[e][f - 1] + (R)e * B00 * G[e - 1][f];
                 }
             }
             // rows a_k .. a_k + LB of G for this lane's run-time a_k
             const int ak = a[k];
-            double Gs[LB + 1][LCD + 1];
+            R Gs[LB + 1][LCD + 1];
 #pragma unroll
             for (int j = 0; j <= LB; ++j)
 #pragma unroll
                 for (int f = 0; f <= LCD; ++f) {
-                    double v = G[j][f];
+                    R v = G[j][f];
 #pragma unroll
                     for (int e = 1; e <= LA; ++e) v = (ak == e) ? G[e + j][f] : v;
                     Gs[j][f] = v;
                 }
-            double abp[LB + 1];
-            abp[0] = 1.0;
+            R abp[LB + 1];
+            abp[0] = (R)1;
 #pragma unroll
-            for (int j = 1; j <= LB; ++j) abp[j] = abp[j - 1] * AB[k];
+            for (int j = 1; j <= LB; ++j) abp[j] = abp[j - 1] * (R)AB[k];
 #pragma unroll
             for (int ib = 0; ib < NBL; ++ib) {
-                double h[LCD + 1];
+                R h[LCD + 1];
                 if constexpr (MODE == 1) {
                     constexpr int dummy = 0;
                     (void)dummy;
@@ -388,38 +399,38 @@ FK_HD void rys_prim_team(const double *__restrict tab, const PrimPair &p, const 
                     const int bk = (k == 0) ? kCart.x[LB][ib] : (k == 1 ? kCart.y[LB][ib] : kCart.z[LB][ib]);
 #pragma unroll
                     for (int f = 0; f <= LCD; ++f) {
-                        double v = 0.0;
+                        R v = (R)0;
 #pragma unroll
                         for (int j = 0; j <= LB; ++j)
-                            if (j <= bk) v += binom(bk, j) * abp[bk - j] * Gs[j][f];
+                            if (j <= bk) v += (R)binom(bk, j) * abp[bk - j] * Gs[j][f];
                         h[f] = v;
                     }
                 } else {
                     const int bk = b[k];
-                    double cf[LB + 1];
+                    R cf[LB + 1];
 #pragma unroll
                     for (int j = 0; j <= LB; ++j) {
-                        double c = 0.0;
+                        R c = (R)0;
 #pragma unroll
                         for (int bb = 0; bb <= LB; ++bb)
-                            if (j <= bb) c = (bk == bb) ? binom(bb, j) * abp[bb - j] : c;
+                            if (j <= bb) c = (bk == bb) ? (R)binom(bb, j) * abp[bb - j] : c;
                         cf[j] = c;
                     }
 #pragma unroll
                     for (int f = 0; f <= LCD; ++f) {
-                        double v = 0.0;
+                        R v = (R)0;
 #pragma unroll
                         for (int j = 0; j <= LB; ++j) v += cf[j] * Gs[j][f];
                         h[f] = v;
                     }
                 }
-                double Kt[LCD + 1][LD + 1];
+                R Kt[LCD + 1][LD + 1];
 #pragma unroll
                 for (int c = 0; c <= LCD; ++c) Kt[c][0] = h[c];
 #pragma unroll
                 for (int d = 0; d < LD; ++d)
 #pragma unroll
-                    for (int c = 0; c < LCD - d; ++c) Kt[c][d + 1] = Kt[c + 1][d] + CD[k] * Kt[c][d];
+                    for (int c = 0; c < LCD - d; ++c) Kt[c][d + 1] = Kt[c + 1][d] + (R)CD[k] * Kt[c][d];
 #pragma unroll
                 for (int c = 0; c <= LC; ++c)
 #pragma unroll

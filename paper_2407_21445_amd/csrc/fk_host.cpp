@@ -45,6 +45,7 @@ struct QuartetClass {
     int64_t prim_slots;       // primitive-quartet slots the waves step through
     int blocks_per_cu;
     int bra_slot;             // doubles per wave of staged bra primitive records
+    int prec;                 // 0: FP64 launch, 1: FP32 launch of the precision split
 };
 
 }  // namespace
@@ -572,9 +573,10 @@ int fk_build_quartets(fk_ctx *c, const fk_screen_opts *o)
 {
     if (!c) return FK_ERR_ARG;
     if (!c->have_basis) return fail(c, FK_ERR_STATE, "fk_build_quartets: basis not set");
-    fk_screen_opts opts = {1e-10, 0.0, 1, 0};
+    fk_screen_opts opts = {1e-10, 0.0, 1, 0, 0.0};
     if (o) opts = *o;
     if (!(opts.tau >= 0) || !(opts.tau_prim >= 0)) return fail(c, FK_ERR_ARG, "fk_build_quartets: negative threshold");
+    if (!(opts.tau_fp32 >= 0)) return fail(c, FK_ERR_ARG, "fk_build_quartets: negative tau_fp32");
     if (opts.bra_block < 0 || opts.bra_block > FK_MAX_BRA_BLOCK)
         return fail(c, FK_ERR_ARG, "fk_build_quartets: bra_block must be 0..%d", FK_MAX_BRA_BLOCK);
     c->opts = opts;
@@ -683,6 +685,8 @@ int fk_build_quartets(fk_ctx *c, const fk_screen_opts *o)
     }
     // 4. tiles per quartet class (P >= Q): bra blocks from class P, kets from class Q
     const int bra_block = opts.bra_block > 0 ? std::min(opts.bra_block, FK_MAX_BRA_BLOCK) : 8;
+    // precision split threshold on G_ab G_cd (|D| <= 2 for a closed-shell density)
+    const double tau_hi = opts.tau_fp32 > 0 ? 0.5 * opts.tau_fp32 : 0.0;
     c->tiles.clear();
     c->blocks.clear();
     c->blk_bra.clear();
@@ -699,15 +703,22 @@ int fk_build_quartets(fk_ctx *c, const fk_screen_opts *o)
             qc.P = P; qc.Q = Q;
             if (fk_kernels_class_info(P, Q, &qc.info))
                 return fail(c, FK_ERR_UNSUPPORTED, "quartet class (%d|%d) is not built into this library", P, Q);
-            qc.tile_off = (int64_t)c->tiles.size();
-            qc.nquartet = 0; qc.nprim = 0; qc.prim_slots = 0;
+            // precision split (FP32 recurrences below tau_hi), not for f-f bra kernels
+            const bool split = tau_hi > 0 && qc.info.wave_per_quartet != 3;
             // kets per tile: a full wave of kets for lane-per-quartet kernels, two
             // rounds of teams for team kernels, two kets for wave-per-quartet
             const int ts = std::max(1, qc.info.team_size);
             const int tile_kets = qc.info.wave_per_quartet == 0 ? 64 : std::max(1, 2 * (64 / ts));
+            const int qpw = qc.info.wave_per_quartet == 0 ? 64 : (qc.info.wave_per_quartet == 3 ? 1 : 64 / ts);
             int max_bra_npp = 1;
             for (int p : LP) max_bra_npp = std::max(max_bra_npp, c->pr_npp[p]);
             qc.bra_slot = max_bra_npp * FK_NFLD;
+            QuartetClass qp[2] = {qc, qc};
+            std::vector<FkTile> tl[2];
+            for (int k = 0; k < 2; ++k) {
+                qp[k].prec = k;
+                qp[k].nquartet = 0; qp[k].nprim = 0; qp[k].prim_slots = 0;
+            }
             // bra blocks: the class's pairs ordered by (first shell, G descending),
             // cut into runs of at most bmax pairs with the same first shell
             const int bmax = std::max(1, std::min(bra_block, qc.info.bra_block));
@@ -717,6 +728,16 @@ int fk_build_quartets(fk_ctx *c, const fk_screen_opts *o)
                 if (c->pr_sa[LP[x]] != c->pr_sa[LP[y]]) return c->pr_sa[LP[x]] < c->pr_sa[LP[y]];
                 return c->pr_G[LP[x]] > c->pr_G[LP[y]];
             });
+            // length of the prefix of [first, last) (G descending) with G_bra G_ket >= thr:
+            // the same product the kernels test
+            auto prefix = [&](int first, int last, double gb, double thr) {
+                int lo = first, hi = last;
+                while (lo < hi) {
+                    const int mid = (lo + hi) / 2;
+                    if (gb * c->pr_G[LQ[mid]] >= thr) lo = mid + 1; else hi = mid;
+                }
+                return lo - first;
+            };
             for (size_t i0 = 0; i0 < ord.size();) {
                 size_t i1 = i0;
                 const int sa0 = c->pr_sa[LP[ord[i0]]];
@@ -733,59 +754,66 @@ int fk_build_quartets(fk_ctx *c, const fk_screen_opts *o)
                 for (size_t gi = 0; gi < c->cls_groups[Q].size(); ++gi) {
                     const auto &g = c->cls_groups[Q][gi];
                     const int gnpp = c->pr_npp[LQ[g.first]];
-                    int cmax = 0;
+                    // ket ranges [lo, hi) of the group for the FP64 and FP32 launches
+                    int hi64 = 0, lo32 = g.second - g.first, hi32 = 0;
                     for (size_t x = i0; x < i1; ++x) {
                         const int pb = ord[x], bra = LP[pb];
-                        const double thr = opts.tau > 0 ? opts.tau / c->pr_G[bra] : 0.0;
-                        // kets in [g.first, g.second) are sorted by G descending
-                        int lo = g.first, hi = g.second;
-                        while (lo < hi) {
-                            const int mid = (lo + hi) / 2;
-                            if (c->pr_G[LQ[mid]] >= thr) lo = mid + 1; else hi = mid;
-                        }
-                        int cnt = lo - g.first;
+                        const double gb = c->pr_G[bra];
+                        int cnt = opts.tau > 0 ? prefix(g.first, g.second, gb, opts.tau) : g.second - g.first;
                         if (P == Q) cnt = std::min(cnt, std::max(0, pb + 1 - g.first));
                         if (cnt <= 0) continue;
-                        cmax = std::max(cmax, cnt);
-                        qc.nquartet += cnt;
-                        qc.nprim += (int64_t)cnt * c->pr_npp[bra] * gnpp;
+                        const int c64 = split ? std::min(cnt, prefix(g.first, g.second, gb, tau_hi)) : cnt;
+                        hi64 = std::max(hi64, c64);
+                        if (c64 < cnt) {
+                            lo32 = std::min(lo32, c64);
+                            hi32 = std::max(hi32, cnt);
+                        }
+                        qp[0].nquartet += c64;
+                        qp[0].nprim += (int64_t)c64 * c->pr_npp[bra] * gnpp;
+                        qp[1].nquartet += cnt - c64;
+                        qp[1].nprim += (int64_t)(cnt - c64) * c->pr_npp[bra] * gnpp;
                     }
-                    for (int k = 0; k < cmax; k += tile_kets) {
-                        FkTile t;
-                        t.blk = blk;
-                        t.ket_begin = c->ket_off[Q] + g.first + k;
-                        t.ket_count = std::min(tile_kets, cmax - k);
-                        t.grp = (c->cls_group0[Q] + (int)gi) | ((P == Q) ? FK_TILE_SAME : 0);
-                        c->tiles.push_back(t);
-                        // lane slots of the tile's primitive loops: rounds of
-                        // (quartets per wave) kets, 64 lanes each, for every bra
-                        const int qpw = qc.info.wave_per_quartet == 0 ? 64 : (qc.info.wave_per_quartet == 3 ? 1 : 64 / ts);
-                        const int64_t rounds = (t.ket_count + qpw - 1) / qpw;
-                        qc.prim_slots += rounds * 64 * nppsum * gnpp;
-                    }
+                    const int rng[2][2] = {{0, hi64}, {lo32, hi32}};
+                    for (int k = 0; k < 2; ++k)
+                        for (int kk = rng[k][0]; kk < rng[k][1]; kk += tile_kets) {
+                            FkTile t;
+                            t.blk = blk;
+                            t.ket_begin = c->ket_off[Q] + g.first + kk;
+                            t.ket_count = std::min(tile_kets, rng[k][1] - kk);
+                            t.grp = (c->cls_group0[Q] + (int)gi) | ((P == Q) ? FK_TILE_SAME : 0);
+                            tl[k].push_back(t);
+                            // lane slots of the tile's primitive loops: rounds of
+                            // (quartets per wave) kets, 64 lanes each, for every bra
+                            const int64_t rounds = (t.ket_count + qpw - 1) / qpw;
+                            qp[k].prim_slots += rounds * 64 * nppsum * gnpp;
+                        }
                 }
                 i0 = i1;
             }
-            qc.ntile = (int64_t)c->tiles.size() - qc.tile_off;
-            if (qc.ntile == 0) continue;
-            // most expensive tiles first (bra primitives x ket primitives x kets)
-            {
+            for (int k = 0; k < 2; ++k) {
+                if (tl[k].empty()) continue;
+                QuartetClass &q = qp[k];
+                // most expensive tiles first (bra primitives x ket primitives x kets)
                 auto cost = [&](const FkTile &t) {
                     const FkGroup &gg = c->groups[t.grp & ~FK_TILE_SAME];
                     return c->blk_nppsum[t.blk] * gg.npp * t.ket_count;
                 };
-                std::stable_sort(c->tiles.begin() + qc.tile_off, c->tiles.end(),
-                                 [&](const FkTile &x, const FkTile &y) { return cost(x) > cost(y); });
+                std::stable_sort(tl[k].begin(), tl[k].end(), [&](const FkTile &x, const FkTile &y) { return cost(x) > cost(y); });
+                q.tile_off = (int64_t)c->tiles.size();
+                q.ntile = (int64_t)tl[k].size();
+                c->tiles.insert(c->tiles.end(), tl[k].begin(), tl[k].end());
+                c->flops_schwarz += q.nprim * q.info.flops_prim + q.nquartet * q.info.flops_quartet;
+                c->nq_schwarz += q.nquartet;
+                q.blocks_per_cu = 1;
+                if (dev) {
+                    int nb = 0;
+                    const int lds = fk_kernels_jk_lds_bytes(P, Q, q.bra_slot);
+                    if (fk_kernels_max_blocks(P, Q, lds, &nb) == 0 && nb > 0) q.blocks_per_cu = nb;
+                }
+                if ((int)c->qclasses.size() >= FK_MAX_QCLASS)
+                    return fail(c, FK_ERR_STATE, "internal: more class launches than FK_MAX_QCLASS");
+                c->qclasses.push_back(q);
             }
-            c->flops_schwarz += qc.nprim * qc.info.flops_prim + qc.nquartet * qc.info.flops_quartet;
-            c->nq_schwarz += qc.nquartet;
-            qc.blocks_per_cu = 1;
-            if (dev) {
-                int nb = 0;
-                const int lds = fk_kernels_jk_lds_bytes(P, Q, qc.bra_slot);
-                if (fk_kernels_max_blocks(P, Q, lds, &nb) == 0 && nb > 0) qc.blocks_per_cu = nb;
-            }
-            c->qclasses.push_back(qc);
         }
     if ((rc = validate_lists(c))) return rc;
     if (dev) {
@@ -901,6 +929,8 @@ int fk_build_jk(fk_ctx *c, const double *D, double *J, double *K, unsigned flags
         a.rys_tab = c->d_rys.p + rys_staged_offset(qc.info.nroot);
         a.counters = c->d_cnt.p + 2 * i;
         a.bra_slot = qc.bra_slot;
+        a.prec = qc.prec;
+        a.tau_hi = c->opts.tau_fp32 > 0 ? 0.5 * c->opts.tau_fp32 : 0.0;
         a.blocks = c->d_blocks.p;
         a.blk_bra = c->d_blk_bra.p;
         a.blk_pos = c->d_blk_pos.p;
@@ -947,6 +977,7 @@ int fk_stats(fk_ctx *c, fk_stats_t *s)
         s->flops_per_quartet[i] = q.info.flops_quartet;
         s->tiles[i] = q.ntile;
         s->team_size[i] = q.info.wave_per_quartet == 3 ? 64 : std::max(1, q.info.team_size);
+        s->precision[i] = q.prec ? 32 : 64;
         s->prim_slots[i] = q.prim_slots;
         s->flops_total += s->prim_quartets[i] * q.info.flops_prim + s->quartets[i] * q.info.flops_quartet;
         if (c->timed && 2 * i + 1 < c->ev.size()) {

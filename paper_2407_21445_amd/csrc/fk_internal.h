@@ -79,6 +79,9 @@ struct FkJKArgs {
     const double *rys_tab;   // staged Rys segment (table + Gauss-Hermite) of this class's root count
     unsigned long long *counters;  // [2]: contracted quartets, primitive quartets
     int bra_slot;            // doubles per wave for the staged bra primitive records
+    int prec;                // 0: FP64 kernel, 1: FP32 kernel of the precision split
+    double tau_hi;           // precision split: the FP64 kernel takes quartets with
+                             // G_ab G_cd >= tau_hi, the FP32 kernel the others (0: no split)
 };
 
 // Quartet list for the debug/Schwarz kernels (canonical orientation).

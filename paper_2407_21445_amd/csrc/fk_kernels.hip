@@ -25,7 +25,7 @@
 #ifndef FK_BUILD_MAXL
 #define FK_BUILD_MAXL 3
 #endif
-#define FK_LPQ_MAX_NOUT 54
+#define FK_LPQ_MAX_NOUT 81
 // lane-per-quartet classes up to this many integrals sum K[a,c], K[a,d] and
 // J[c,d] over a block of bras in registers; larger ones take one bra per tile
 #define FK_LPQ_BLOCK_NOUT 54
@@ -59,6 +59,15 @@ __device__ __forceinline__ fk::PrimPair load_pp(const double *__restrict pp, int
     p.PA[0] = r[5]; p.PA[1] = r[6]; p.PA[2] = r[7];
     p.K = r[8];
     return p;
+}
+
+// Precision split: the FP64 kernel takes quartets with Schwarz product at or
+// above tau_hi (all of them when tau_hi <= 0), the FP32 kernel the rest.
+template <typename R>
+__device__ __forceinline__ bool prec_side(double gg, double tau_hi)
+{
+    if constexpr (sizeof(R) == sizeof(double)) return tau_hi <= 0 || gg >= tau_hi;
+    else return gg < tau_hi;
 }
 
 __device__ __forceinline__ double wave_sum(double v)
@@ -183,7 +192,7 @@ __device__ __forceinline__ int nth_bit(unsigned long long m, int n)
 // Digestion: X_J[a, b_j] is reduced over the wave per bra; X_K[b_j, c],
 // X_K[b_j, d] go to memory per bra; X_K[a, c], X_K[a, d] and X_J[c, d] do not
 // depend on b_j and are summed in registers over the whole block first.
-template <int LA, int LB, int LC, int LD>
+template <int LA, int LB, int LC, int LD, typename R = double>
 __global__ void __launch_bounds__(FK_BLOCK) k_jk_lpq(FkJKArgs a)
 {
     using Q = fk::QClass<LA, LB, LC, LD>;
@@ -216,11 +225,13 @@ __global__ void __launch_bounds__(FK_BLOCK) k_jk_lpq(FkJKArgs a)
         const int sa = a.pair_sa[a.blk_bra[blk.first]];
         const int oa = a.sh_bf[sa];
         // D_cd is used with every bra of the block
-        double dcd[NC * ND];
+        double dcd[BLK ? NC * ND : 1];
+        if constexpr (BLK) {
 #pragma unroll
-        for (int ic = 0; ic < NC; ++ic)
+            for (int ic = 0; ic < NC; ++ic)
 #pragma unroll
-            for (int id = 0; id < ND; ++id) dcd[ic * ND + id] = a.Ds[(size_t)(oc + ic) * n + od + id];
+                for (int id = 0; id < ND; ++id) dcd[ic * ND + id] = a.Ds[(size_t)(oc + ic) * n + od + id];
+        }
         // block sums: X_K[a, c], X_K[a, d], X_J[c, d]
         double kac[NA * NC], kad[NA * ND], jcd[NC * ND];
 #pragma unroll
@@ -238,7 +249,8 @@ __global__ void __launch_bounds__(FK_BLOCK) k_jk_lpq(FkJKArgs a)
             const int sb = B.sb;
             // Schwarz bound, same-class triangle (ket position <= bra position)
             // and density screen for this (bra, ket)
-            bool active = inrange && (!same || pos <= bpos) && (a.tau <= 0 || B.G * Kt.G >= a.tau);
+            bool active = inrange && (!same || pos <= bpos) && (a.tau <= 0 || B.G * Kt.G >= a.tau) &&
+                          prec_side<R>(B.G * Kt.G, a.tau_hi);
             if (a.dscreen) active = active && (B.G * Kt.G * dmax6(a.Dsh, ns, sa, sb, sc, sd) >= a.tau);
             const unsigned long long mask = __ballot(active);
             if (mask == 0ull) continue;
@@ -247,9 +259,9 @@ __global__ void __launch_bounds__(FK_BLOCK) k_jk_lpq(FkJKArgs a)
             cp += (unsigned long long)nact * B.npp * g.npp;
 
             stage_bra(s_bra, a.pp, B.ppo, B.npp, lane);
-            double acc[NOUT];
+            R acc[NOUT];
 #pragma unroll
-            for (int o = 0; o < NOUT; ++o) acc[o] = 0.0;
+            for (int o = 0; o < NOUT; ++o) acc[o] = (R)0;
             if (active) {
                 fk::PrimPair qn = load_ket_pp(a.ppT, g, 0, r);
                 for (int j = 0; j < g.npp; ++j) {
@@ -257,7 +269,7 @@ __global__ void __launch_bounds__(FK_BLOCK) k_jk_lpq(FkJKArgs a)
                     if (j + 1 < g.npp) qn = load_ket_pp(a.ppT, g, j + 1, r);
 #pragma unroll 2
                     for (int i = 0; i < B.npp; ++i)
-                        fk::rys_prim_all<LA, LB, LC, LD>(s_tab, lds_pp(s_bra, i), q, B.AB, Kt.CD, acc);
+                        fk::rys_prim_all<LA, LB, LC, LD, R>(s_tab, lds_pp(s_bra, i), q, B.AB, Kt.CD, acc);
                 }
             }
             const bool diag = same && pos == bpos;
@@ -266,10 +278,10 @@ __global__ void __launch_bounds__(FK_BLOCK) k_jk_lpq(FkJKArgs a)
             double jab[NA * NB];
 #pragma unroll
             for (int o = 0; o < NA * NB; ++o) jab[o] = 0.0;
-            if (active) {
+            if (active && BLK) {
                 any = true;
 #pragma unroll
-                for (int o = 0; o < NOUT; ++o) acc[o] *= fac;
+                for (int o = 0; o < NOUT; ++o) acc[o] *= (R)fac;
                 double dab[NA * NB], dbc[NB * NC], dbd[NB * ND];
 #pragma unroll
                 for (int ib = 0; ib < NB; ++ib) {
@@ -285,57 +297,88 @@ __global__ void __launch_bounds__(FK_BLOCK) k_jk_lpq(FkJKArgs a)
                 for (int ab = 0; ab < NA * NB; ++ab)
 #pragma unroll
                     for (int cd = 0; cd < NC * ND; ++cd) {
-                        jab[ab] += acc[ab * NC * ND + cd] * dcd[cd];
-                        if constexpr (BLK) jcd[cd] += acc[ab * NC * ND + cd] * dab[ab];
+                        jab[ab] += acc[ab * NC * ND + cd] * dcd[BLK ? cd : 0];
+                        jcd[cd] += acc[ab * NC * ND + cd] * dab[ab];
                     }
-                if constexpr (BLK) {
-                    // X_K[a, c] += v D_bd and X_K[a, d] += v D_bc (block sums)
+                // X_K[a, c] += v D_bd and X_K[a, d] += v D_bc (block sums)
 #pragma unroll
-                    for (int ia = 0; ia < NA; ++ia)
+                for (int ia = 0; ia < NA; ++ia)
+#pragma unroll
+                    for (int ib = 0; ib < NB; ++ib)
+#pragma unroll
+                        for (int ic = 0; ic < NC; ++ic)
+#pragma unroll
+                            for (int id = 0; id < ND; ++id) {
+                                const double v = acc[((ia * NB + ib) * NC + ic) * ND + id];
+                                kac[ia * NC + ic] += v * dbd[ib * ND + id];
+                                kad[ia * ND + id] += v * dbc[ib * NC + ic];
+                            }
+                // X_K[b, c] += v D_ad and X_K[b, d] += v D_ac (per bra)
+#pragma unroll
+                for (int ib = 0; ib < NB; ++ib) {
+#pragma unroll
+                    for (int ic = 0; ic < NC; ++ic) {
+                        double s = 0.0;
+#pragma unroll
+                        for (int ia = 0; ia < NA; ++ia)
+#pragma unroll
+                            for (int id = 0; id < ND; ++id)
+                                s += acc[((ia * NB + ib) * NC + ic) * ND + id] * a.Ds[(size_t)(oa + ia) * n + od + id];
+                        atomic_add(&a.XK[(size_t)(ob + ib) * n + oc + ic], s);
+                    }
+#pragma unroll
+                    for (int id = 0; id < ND; ++id) {
+                        double s = 0.0;
+#pragma unroll
+                        for (int ia = 0; ia < NA; ++ia)
+#pragma unroll
+                            for (int ic = 0; ic < NC; ++ic)
+                                s += acc[((ia * NB + ib) * NC + ic) * ND + id] * a.Ds[(size_t)(oa + ia) * n + oc + ic];
+                        atomic_add(&a.XK[(size_t)(ob + ib) * n + od + id], s);
+                    }
+                }
+            }
+            if (active && !BLK) {
+                // one bra per tile: the six blocks straight to memory, density
+                // elements loaded where they are used (register pressure)
+#pragma unroll
+                for (int o = 0; o < NOUT; ++o) acc[o] *= (R)fac;
+#pragma unroll
+                for (int ab = 0; ab < NA * NB; ++ab)
+#pragma unroll
+                    for (int cd = 0; cd < NC * ND; ++cd)
+                        jab[ab] += acc[ab * NC * ND + cd] * a.Ds[(size_t)(oc + cd / ND) * n + od + cd % ND];
+#pragma unroll
+                for (int cd = 0; cd < NC * ND; ++cd) {
+                    double s = 0.0;
+#pragma unroll
+                    for (int ab = 0; ab < NA * NB; ++ab)
+                        s += acc[ab * NC * ND + cd] * a.Ds[(size_t)(oa + ab / NB) * n + ob + ab % NB];
+                    atomic_add(&a.XJ[(size_t)(oc + cd / ND) * n + od + cd % ND], 2.0 * s);
+                }
+#pragma unroll
+                for (int ia = 0; ia < NA; ++ia) {
+#pragma unroll
+                    for (int ic = 0; ic < NC; ++ic) {
+                        double s = 0.0;
+#pragma unroll
+                        for (int ib = 0; ib < NB; ++ib)
+#pragma unroll
+                            for (int id = 0; id < ND; ++id)
+                                s += acc[((ia * NB + ib) * NC + ic) * ND + id] * a.Ds[(size_t)(ob + ib) * n + od + id];
+                        atomic_add(&a.XK[(size_t)(oa + ia) * n + oc + ic], s);
+                    }
+#pragma unroll
+                    for (int id = 0; id < ND; ++id) {
+                        double s = 0.0;
 #pragma unroll
                         for (int ib = 0; ib < NB; ++ib)
 #pragma unroll
                             for (int ic = 0; ic < NC; ++ic)
-#pragma unroll
-                                for (int id = 0; id < ND; ++id) {
-                                    const double v = acc[((ia * NB + ib) * NC + ic) * ND + id];
-                                    kac[ia * NC + ic] += v * dbd[ib * ND + id];
-                                    kad[ia * ND + id] += v * dbc[ib * NC + ic];
-                                }
-                } else {
-                    // one bra per tile: X_J[c, d], X_K[a, c], X_K[a, d] straight to memory
-#pragma unroll
-                    for (int cd = 0; cd < NC * ND; ++cd) {
-                        double s = 0.0;
-#pragma unroll
-                        for (int ab = 0; ab < NA * NB; ++ab) s += acc[ab * NC * ND + cd] * dab[ab];
-                        atomic_add(&a.XJ[(size_t)(oc + cd / ND) * n + od + cd % ND], 2.0 * s);
-                    }
-#pragma unroll
-                    for (int ia = 0; ia < NA; ++ia) {
-#pragma unroll
-                        for (int ic = 0; ic < NC; ++ic) {
-                            double s = 0.0;
-#pragma unroll
-                            for (int ib = 0; ib < NB; ++ib)
-#pragma unroll
-                                for (int id = 0; id < ND; ++id)
-                                    s += acc[((ia * NB + ib) * NC + ic) * ND + id] * dbd[ib * ND + id];
-                            atomic_add(&a.XK[(size_t)(oa + ia) * n + oc + ic], s);
-                        }
-#pragma unroll
-                        for (int id = 0; id < ND; ++id) {
-                            double s = 0.0;
-#pragma unroll
-                            for (int ib = 0; ib < NB; ++ib)
-#pragma unroll
-                                for (int ic = 0; ic < NC; ++ic)
-                                    s += acc[((ia * NB + ib) * NC + ic) * ND + id] * dbc[ib * NC + ic];
-                            atomic_add(&a.XK[(size_t)(oa + ia) * n + od + id], s);
-                        }
+                                s += acc[((ia * NB + ib) * NC + ic) * ND + id] * a.Ds[(size_t)(ob + ib) * n + oc + ic];
+                        atomic_add(&a.XK[(size_t)(oa + ia) * n + od + id], s);
                     }
                 }
-                // X_K[b, c] += v D_ad and X_K[b, d] += v D_ac (per bra)
 #pragma unroll
                 for (int ib = 0; ib < NB; ++ib) {
 #pragma unroll
@@ -413,7 +456,7 @@ struct TeamShape {
 
 __device__ __forceinline__ void lds_add(double *p, double v) { unsafeAtomicAdd(p, v); }
 
-template <int LA, int LB, int LC, int LD, int MODE>
+template <int LA, int LB, int LC, int LD, int MODE, typename R = double>
 __global__ void __launch_bounds__(FK_BLOCK) k_jk_tpq(FkJKArgs a)
 {
     using Q = fk::QClass<LA, LB, LC, LD>;
@@ -476,7 +519,8 @@ __global__ void __launch_bounds__(FK_BLOCK) k_jk_tpq(FkJKArgs a)
                 const int bpos = a.blk_pos[blk.first + jb];
                 const BraInfo B = load_bra(a, bra);
                 const int sb = B.sb;
-                bool active = tin && (!same || pos <= bpos) && (a.tau <= 0 || B.G * Kt.G >= a.tau);
+                bool active = tin && (!same || pos <= bpos) && (a.tau <= 0 || B.G * Kt.G >= a.tau) &&
+                              prec_side<R>(B.G * Kt.G, a.tau_hi);
                 if (a.dscreen) active = active && (B.G * Kt.G * dmax6(a.Dsh, ns, sa, sb, sc, sd) >= a.tau);
                 const unsigned long long mask = __ballot(active);
                 if (mask == 0ull) continue;
@@ -484,16 +528,16 @@ __global__ void __launch_bounds__(FK_BLOCK) k_jk_tpq(FkJKArgs a)
                 cq += nact;
                 cp += (unsigned long long)nact * B.npp * g.npp;
                 stage_bra(s_bra, a.pp, B.ppo, B.npp, lane);
-                double acc[NOL];
+                R acc[NOL];
 #pragma unroll
-                for (int o = 0; o < NOL; ++o) acc[o] = 0.0;
+                for (int o = 0; o < NOL; ++o) acc[o] = (R)0;
                 if (active) {
                     fk::PrimPair qn = load_ket_pp(a.ppT, g, 0, r);
                     for (int j = 0; j < g.npp; ++j) {
                         const fk::PrimPair q = qn;
                         if (j + 1 < g.npp) qn = load_ket_pp(a.ppT, g, j + 1, r);
                         for (int i = 0; i < B.npp; ++i)
-                            fk::rys_prim_team<LA, LB, LC, LD, MODE>(s_tab, lds_pp(s_bra, i), q, B.AB, Kt.CD, ax, bx, acc);
+                            fk::rys_prim_team<LA, LB, LC, LD, MODE, R>(s_tab, lds_pp(s_bra, i), q, B.AB, Kt.CD, ax, bx, acc);
                     }
                 }
                 const bool diag = same && pos == bpos;
@@ -829,12 +873,14 @@ struct Disp {
         i->flops_prim = fk::flops_prim(LA, LB, LC, LD);
         i->flops_quartet = fk::flops_digest(LA, LB, LC, LD);
     }
-    static const void *jk_kernel()
+    static const void *jk_kernel(bool low = false)
     {
         if constexpr (!BUILT) return nullptr;
-        else if constexpr (KIND == 0) return (const void *)&k_jk_lpq<LA, LB, LC, LD>;
-        else if constexpr (KIND == 1) return (const void *)&k_jk_tpq<LA, LB, LC, LD, 1>;
-        else if constexpr (KIND == 2) return (const void *)&k_jk_tpq<LA, LB, LC, LD, 2>;
+        else if constexpr (KIND == 0)
+            return low ? (const void *)&k_jk_lpq<LA, LB, LC, LD, float> : (const void *)&k_jk_lpq<LA, LB, LC, LD, double>;
+        else if constexpr (KIND == 1 || KIND == 2)
+            return low ? (const void *)&k_jk_tpq<LA, LB, LC, LD, KIND, float>
+                       : (const void *)&k_jk_tpq<LA, LB, LC, LD, KIND, double>;
         else return (const void *)&k_jk_wpq<LA, LB, LC, LD>;
     }
     static int lds_bytes(int bra_slot)
@@ -849,18 +895,23 @@ struct Disp {
         if constexpr (!BUILT) return -2;
         else {
             const int lds = lds_bytes(a->bra_slot);
-            const void *k = jk_kernel();
-            static int raised = 0;
-            if (lds > 65536 && lds > raised) {
+            const bool low = a->prec == 1;
+            if (low && KIND == 3) return -2;  // f-f bras: FP64 only
+            const void *k = jk_kernel(low);
+            static int raised[2] = {0, 0};
+            if (lds > 65536 && lds > raised[low]) {
                 if (hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, lds) != hipSuccess) return -3;
-                raised = lds;
+                raised[low] = lds;
             }
-            if constexpr (KIND == 0) hipLaunchKernelGGL((k_jk_lpq<LA, LB, LC, LD>), dim3(grid), dim3(FK_BLOCK), lds, st, *a);
-            else if constexpr (KIND == 1)
-                hipLaunchKernelGGL((k_jk_tpq<LA, LB, LC, LD, 1>), dim3(grid), dim3(FK_BLOCK), lds, st, *a);
-            else if constexpr (KIND == 2)
-                hipLaunchKernelGGL((k_jk_tpq<LA, LB, LC, LD, 2>), dim3(grid), dim3(FK_BLOCK), lds, st, *a);
-            else hipLaunchKernelGGL((k_jk_wpq<LA, LB, LC, LD>), dim3(grid), dim3(FK_BLOCK), lds, st, *a);
+            if constexpr (KIND == 0) {
+                if (low) hipLaunchKernelGGL((k_jk_lpq<LA, LB, LC, LD, float>), dim3(grid), dim3(FK_BLOCK), lds, st, *a);
+                else hipLaunchKernelGGL((k_jk_lpq<LA, LB, LC, LD, double>), dim3(grid), dim3(FK_BLOCK), lds, st, *a);
+            } else if constexpr (KIND == 1 || KIND == 2) {
+                if (low) hipLaunchKernelGGL((k_jk_tpq<LA, LB, LC, LD, KIND, float>), dim3(grid), dim3(FK_BLOCK), lds, st, *a);
+                else hipLaunchKernelGGL((k_jk_tpq<LA, LB, LC, LD, KIND, double>), dim3(grid), dim3(FK_BLOCK), lds, st, *a);
+            } else {
+                hipLaunchKernelGGL((k_jk_wpq<LA, LB, LC, LD>), dim3(grid), dim3(FK_BLOCK), lds, st, *a);
+            }
             return hipGetLastError() == hipSuccess ? 0 : -3;
         }
     }

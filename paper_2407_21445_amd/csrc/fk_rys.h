@@ -29,6 +29,20 @@ struct GHConst {
     double y2[28], w[28];
 };
 
+// 1/sqrt(x) for x > 0: on the device the hardware estimate refined by two
+// Newton steps y <- y (3 - x y^2)/2 (each doubles the correct bits).
+FK_HD double rys_rsqrt(double x)
+{
+#if defined(__HIP_DEVICE_COMPILE__)
+    double y = __builtin_amdgcn_rsq(x);
+    y = y * fma(-0.5 * x * y, y, 1.5);
+    y = y * fma(-0.5 * x * y, y, 1.5);
+    return y;
+#else
+    return 1.0 / sqrt(x);
+#endif
+}
+
 // Evaluate the n-point rule at T.  `tab` points at the n-point segment of the
 // table ([interval][coefficient][function]); gy2/gw at the n-point
 // Gauss-Hermite data (y_i^2 and h_i).  NEED_U = false evaluates the weights
@@ -67,8 +81,8 @@ FK_HD void rys_roots_from(double T, const double *__restrict tab, const double *
     }
     // half-range Gauss-Hermite rule beyond the table
     if (T >= RYS_TMAX) {
-        const double rT = 1.0 / T;
-        const double sT = sqrt(rT);
+        const double sT = rys_rsqrt(T);
+        const double rT = sT * sT;
 #pragma unroll
         for (int i = 0; i < N; ++i) {
             if constexpr (NEED_U) u[i] = gy2[i] * rT;

@@ -170,3 +170,43 @@ def test_edge_cases(fk, torch):
     # host-pointer path equals the device-pointer path
     Jh, Kh = c.build_jk(D)
     assert np.max(np.abs(Jh - J1.cpu().numpy())) < 1e-12
+
+
+@pytest.mark.parametrize("tau_fp32", [1e-5, 1e-3])
+def test_precision_split_water4(fk, torch, tau_fp32):
+    """Quartets below the split run their recurrences in FP32: every quartet
+    is still computed exactly once (FP64 + FP32 counts = the unscreened
+    count) and J, K and the energy functional stay within the split's error
+    bound of the oracle (per quartet |(ab|cd)| < tau_fp32/2 with FP32 relative
+    error; pinned here at 1e-8 in J/K and 1e-8 Eh for tau_fp32 = 1e-3)."""
+    s = wl.water4_sto3g()
+    D = _core_D(s)
+    J, K, c = _gpu_jk(fk, torch, s, D, tau=0.0, tau_fp32=tau_fp32)
+    Jo, Ko = oracle.jk(s, D)
+    st = c.stats()
+    n32 = sum(x["quartets"] for x in st["classes"] if x["precision"] == 32)
+    n64 = sum(x["quartets"] for x in st["classes"] if x["precision"] == 64)
+    assert n32 > 0 and n32 + n64 == 22155
+    assert np.max(np.abs(J - Jo)) <= 1e-8 and np.max(np.abs(K - Ko)) <= 1e-8
+    dE = 0.5 * np.sum(D * (J - Jo)) - 0.25 * np.sum(D * (K - Ko))
+    assert abs(dE) <= 1e-8
+
+
+def test_precision_split_c20h42(fk, torch, c2):
+    """The benchmark configuration with the split at tau_fp32 = 1e-5: sampled
+    blocks against the oracle and the one-build energy functional against the
+    all-FP64 build (the mixed-precision gate is 1e-6 Eh)."""
+    s, D = c2
+    J, K, c = _gpu_jk(fk, torch, s, D, tau=1e-10, tau_prim=1e-12, tau_fp32=1e-5)
+    J64, K64, _ = _gpu_jk(fk, torch, s, D, tau=1e-10, tau_prim=1e-12)
+    st = c.stats()
+    assert sum(x["quartets"] for x in st["classes"] if x["precision"] == 32) > 0
+    dE = 0.5 * np.sum(D * (J - J64)) - 0.25 * np.sum(D * (K - K64))
+    assert abs(dE) <= 1e-6
+    assert np.max(np.abs(J - J64)) <= 1e-7 and np.max(np.abs(K - K64)) <= 1e-7
+    off = oracle.bf_offsets(s)
+    jp = _blocks(s, 3, n=4)
+    Jb, Kb = oracle.jk_blocks(s, D, jp, jp)
+    for (a, b), bj, bk in zip(jp, Jb, Kb):
+        assert np.max(np.abs(J[off[a]:off[a + 1], off[b]:off[b + 1]] - bj)) <= 1e-7
+        assert np.max(np.abs(K[off[a]:off[a + 1], off[b]:off[b + 1]] - bk)) <= 1e-7

@@ -83,3 +83,14 @@ def test_scf_errors(fk):
     c.build_quartets(tau=0.0)
     r = c.run_scf(max_iter=2)
     assert not r["converged"] and r["iterations"] == 2
+
+
+def test_scf_mixed_precision_gate(fk):
+    """SCF with the FP32 split at tau_fp32 = 1e-5 converges to the FP64 SCF
+    energy within the 1e-6 Eh gate (C2H6, 6-31G*-type)."""
+    s = wl.alkane_sys(2, "6-31gs-type")
+    r64, _ = _gpu_scf(fk, s, tau=1e-10)
+    c = fk.FockJK(0).set_system(s).build_quartets(tau=1e-10, tau_fp32=1e-5)
+    r32 = c.run_scf()
+    assert r64["converged"] and r32["converged"]
+    assert abs(r32["energy"] - r64["energy"]) <= 1e-6

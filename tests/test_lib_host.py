@@ -179,3 +179,19 @@ def test_scf_needs_device():
     with pytest.raises(fk.FockJKError) as e:
         c.run_scf()
     assert e.value.code == fk.FK_ERR_STATE
+
+
+@pytest.mark.parametrize("tau_fp32", [1e-5, 1e-3])
+def test_precision_split_lists(tau_fp32):
+    """The FP64 and FP32 launches partition the Schwarz quartets: the total
+    unique quartet count is unchanged, both precisions get work, and every
+    kernel address stays in bounds."""
+    s = wl.water4_sto3g()
+    ref = fk.FockJK(device=-1).set_system(s).build_quartets(tau=0.0)
+    c = fk.FockJK(device=-1).set_system(s).build_quartets(tau=0.0, tau_fp32=tau_fp32)
+    assert c.info()["nquartet_schwarz"] == ref.info()["nquartet_schwarz"] == 22155
+    prec = [x["precision"] for x in c.stats()["classes"]]
+    assert 32 in prec and 64 in prec and len(prec) > len(ref.stats()["classes"])
+    c.check_indices()
+    with pytest.raises(fk.FockJKError):
+        fk.FockJK(device=-1).set_system(s).build_quartets(tau=0.0, tau_fp32=-1.0)
