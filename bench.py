@@ -29,12 +29,42 @@ PEAK_FP64_VALU = 78.6  # TFLOP/s, MI355X dense FP64 vector
 PEAK_FP32_VALU = 157.3  # TFLOP/s, MI355X dense FP32 vector
 
 
+def _kernel_source_hash():
+    """Hash of the kernel sources: a committed counter measurement applies
+    only to the kernels it was taken on."""
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("fk_kernels.hip", "fk_eri.h", "fk_rys.h", "fk_internal.h"):
+        with open(os.path.join(HERE, "paper_2407_21445_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def _traffic(kernel_name, workload):
+    """HBM bytes per launch of the named kernel from profiles/roofline_traffic.json
+    (rocprofv3 FETCH_SIZE and WRITE_SIZE, each scaled by the same counter on a
+    plain copy of known size), or None when absent or taken on other kernels."""
+    path = os.path.join(HERE, "profiles", "roofline_traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        t = json.load(f)
+    if t.get("source_sha256") != _kernel_source_hash() or t.get("workload") != workload:
+        return None
+    for k in t.get("kernels", []):
+        if k["kernel"] == kernel_name:
+            return k["fetch_bytes_per_launch"] * t["copy_scale_fetch"] + k["write_bytes_per_launch"] * t["copy_scale_write"]
+    return None
+
+
 def _workload(name):
     from synth import workloads as wl
     if name == "c20h42":
         return wl.c20h42_631gs(), "C20H42 all-trans (0.02 A jitter), 6-31G*-type, 384 Cartesian bf"
     if name == "water4":
         return wl.water4_sto3g(), "(H2O)4 STO-3G-type, 28 bf, tau=1e-10"
+    if name == "c4":
+        raise SystemExit("c4 is a batch workload (bench_batch)")
     if name == "water64":
         return wl.water64_ccpvdz(), "(H2O)64 1.0 g/cm3, cc-pVDZ-type, 1600 Cartesian bf, tau=1e-10"
     raise SystemExit(f"unknown workload {name}")
@@ -76,6 +106,68 @@ def cpu_baseline(sys_, D, target_s=15.0):
             "quartets_per_s": 1.0 / per_q, "est_build_s": est_build_s}
 
 
+def bench_batch(args, torch, fk):
+    """Batched builds: the first --nmol molecules of the seeded 256-molecule
+    organic set (tzvp-type basis, s to f) in one context, every class launch
+    covering all molecules; eager builds and replays of the build captured in
+    a HIP graph are timed with HIP events."""
+    from synth import workloads as wl
+    b = wl.organic_batch(args.nmol)
+    ctx = fk.FockJK(0).set_system(b).set_molecules(b["atom_mol"])
+    ctx.build_quartets(tau=args.tau, tau_prim=args.tau_prim, tau_fp32=args.tau_fp32)
+    info = ctx.info()
+    Ds = []
+    for m in b["mols"]:
+        h = fk.FockJK(-1).set_system(m)
+        S, T, V, _ = h.one_electron()
+        Ds.append(_core_density(S, T + V, m["nelec"] // 2).ravel())
+    dev = torch.device("cuda:0")
+    Dd = torch.tensor(np.concatenate(Ds), dtype=torch.float64, device=dev)
+    J = torch.empty_like(Dd)
+    K = torch.empty_like(Dd)
+    stream = torch.cuda.current_stream(dev)
+    for _ in range(args.warmup):
+        ctx.build_jk(Dd, J, K, stream=stream)
+    torch.cuda.synchronize()
+    st = ctx.stats()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(args.steps):
+        ctx.build_jk(Dd, J, K, stream=stream)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / args.steps
+    # the same build captured once in a HIP graph, replayed
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        ctx.build_jk(Dd, J, K)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    for _ in range(args.steps):
+        g.replay()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms_graph = e0.elapsed_time(e1) / args.steps
+    nbf = [m["nbf"] for m in b["mols"]]
+    out = {
+        "metric": METRIC, "value": 1000.0 / ms, "unit": "batch builds/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64" if args.tau_fp32 <= 0 else "f64+f32", "data": "synthetic",
+        "config": {"workload": f"organic batch, first {args.nmol} of 256 seeded molecules (3-30 C/N/O + H), "
+                               f"tzvp-type basis (s-f), one launch per class for all molecules",
+                   "nmol": args.nmol, "nbf_total": int(sum(nbf)), "nbf_min": int(min(nbf)), "nbf_max": int(max(nbf)),
+                   "tau": args.tau, "tau_prim": args.tau_prim, "density": "core-Hamiltonian guess per molecule"},
+        "molecule_builds_per_s": args.nmol * 1000.0 / ms,
+        "graph_ms_per_step": ms_graph,
+        "quartets_per_s": st["quartets"] / (ms * 1e-3),
+        "quartets_per_build": st["quartets"], "schwarz_quartets": info["nquartet_schwarz"],
+        "tflops_build": st["flops_total"] / (ms * 1e-3) / 1e12,
+    }
+    print(json.dumps(out), flush=True)
+    return 0
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -88,6 +180,9 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--classes", action="store_true", help="print the per-class kernel table to stderr")
     ap.add_argument("--no-scf", action="store_true", help="skip the SCF run reported beside the build rate")
+    ap.add_argument("--nmol", type=int, default=8, help="molecules of the organic batch (--workload c4)")
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="MB",
+                    help="only run a plain device copy of MB megabytes 5 times (calibrates HBM byte counters)")
     ap.add_argument("--tau-fp32", type=float, default=0.0,
                     help="precision split: FP32 recurrences for quartets with G_ab G_cd * 2 below this (0: FP64)")
     args = ap.parse_args()
@@ -97,6 +192,16 @@ def main():
     import torch
     import paper_2407_21445_amd as fk
 
+    if args.copy_probe > 0:
+        x = torch.ones(args.copy_probe * (1 << 20) // 8, dtype=torch.float64, device="cuda:0")
+        y = torch.empty_like(x)
+        for _ in range(5):
+            y.copy_(x)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_bytes": x.numel() * 8}), flush=True)
+        return 0
+    if args.workload == "c4":
+        return bench_batch(args, torch, fk)
     sys_, desc = _workload(args.workload)
     ctx = fk.FockJK(0).set_system(sys_).build_quartets(tau=args.tau, tau_prim=args.tau_prim, tau_fp32=args.tau_fp32)
     info = ctx.info()
@@ -165,7 +270,7 @@ def main():
         "flops_per_build": st["flops_total"], "tflops_build": st["flops_total"] / (ms * 1e-3) / 1e12,
         "wall_s_timed": wall,
         "roofline": {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
-                     "frac": achieved / peak, "traffic": None,
+                     "frac": achieved / peak, "traffic": _traffic(f"J/K class {cname}", args.workload),
                      "kernel": f"J/K class {cname}" + (" (FP32 part)" if c["precision"] == 32 else ""),
                      "kernel_ms": float(cls_ms[i]),
                      "class_share": float(cls_ms[i] / cls_ms.sum())},

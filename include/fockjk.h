@@ -96,6 +96,9 @@ typedef struct {
     int64_t ntile;           /* work tiles (bra pair x up to 64 ket pairs) */
     double  flops_schwarz;   /* algorithmic FP64 flops of one build if no quartet
                                 were removed by the density screen */
+    int     nmol;            /* molecules in the context (1 unless fk_set_molecules) */
+    int     reserved;
+    int64_t nmat;            /* elements of D, J, K: sum over molecules of nbf_m^2 */
 } fk_info_t;
 
 /* Per-build statistics of the last fk_build_jk (filled by fk_stats).  On a
@@ -139,6 +142,22 @@ int fk_set_geometry(fk_ctx *ctx, int natom, const int *Z, const double *xyz, int
  * Requires fk_set_geometry first.  Invalidates quartet lists. */
 int fk_set_basis(fk_ctx *ctx, int nshell, const int *shell_atom, const int *shell_l,
                  const int *shell_nprim, const double *exps, const double *coefs);
+
+/* Batch of independent molecules in one context: atom a belongs to molecule
+ * atom_mol[a] (0..nmol-1, non-decreasing over the atoms, so that each
+ * molecule's atoms, shells and functions are contiguous).  Call after
+ * fk_set_geometry (before or after fk_set_basis; it invalidates the quartet
+ * lists).  Shell pairs and quartets never span two molecules; one
+ * fk_build_jk then runs every molecule's quartets in the same class launches.
+ * D, J and K become the concatenation of the molecules' nbf_m x nbf_m
+ * row-major blocks (fk_molecule_layout gives the sizes and offsets).
+ * fk_one_electron, fk_run_scf and fk_debug_eri return FK_ERR_UNSUPPORTED
+ * for a batch (one context per molecule for those). */
+int fk_set_molecules(fk_ctx *ctx, int nmol, const int *atom_mol);
+
+/* nbf[m] and offset[m] (m = 0..nmol; offset[nmol] = total elements) of each
+ * molecule's block of D, J, K.  Arrays of nmol and nmol + 1 entries. */
+int fk_molecule_layout(const fk_ctx *ctx, int *nbf, int64_t *offset);
 
 /* ---- screening and work lists (paper: Cauchy-Schwarz bounds; shell-pair
  * batching and upper-triangle class launches of the Brc21 scheme) -------- */

@@ -44,7 +44,8 @@ class Info(ctypes.Structure):
     _fields_ = [("nbf", ctypes.c_int), ("nshell", ctypes.c_int), ("natom", ctypes.c_int), ("nelec", ctypes.c_int),
                 ("npair", ctypes.c_int), ("npair_kept", ctypes.c_int), ("nclass_pair", ctypes.c_int),
                 ("nquartet_class", ctypes.c_int), ("nprim_pair", ctypes.c_int64),
-                ("nquartet_schwarz", ctypes.c_int64), ("ntile", ctypes.c_int64), ("flops_schwarz", ctypes.c_double)]
+                ("nquartet_schwarz", ctypes.c_int64), ("ntile", ctypes.c_int64), ("flops_schwarz", ctypes.c_double),
+                ("nmol", ctypes.c_int), ("reserved", ctypes.c_int), ("nmat", ctypes.c_int64)]
 
 
 _Q = FK_MAX_QCLASS
@@ -86,6 +87,8 @@ _sig = {
     "fk_debug_eri": ([_P, _I, _P, _P, _I], _I),
     "fk_rys_host": ([_I, _D, _P, _P], _I),
     "fk_check_indices": ([_P], _I),
+    "fk_set_molecules": ([_P, _I, _P], _I),
+    "fk_molecule_layout": ([_P, _P, _P], _I),
 }
 EXPORTS = tuple(_sig)
 for _name, (_args, _res) in _sig.items():
@@ -163,6 +166,22 @@ class FockJK:
         self.nbf = int(sum(_ncart(int(l)) for l in sl))
         return self
 
+    def set_molecules(self, atom_mol):
+        """Splits the atoms into independent molecules (batch); atom_mol is
+        non-decreasing.  D, J, K are then flat concatenations of the
+        molecules' nbf_m x nbf_m blocks (see molecule_layout)."""
+        am = np.ascontiguousarray(atom_mol, dtype=np.int32)
+        self._check(_lib.fk_set_molecules(self._ctx, int(am.max()) + 1, _ptr(am)))
+        return self
+
+    def molecule_layout(self):
+        """(nbf per molecule, offsets of the blocks (nmol + 1 entries))."""
+        nmol = self.info()["nmol"]
+        nbf = np.zeros(nmol, dtype=np.int32)
+        off = np.zeros(nmol + 1, dtype=np.int64)
+        self._check(_lib.fk_molecule_layout(self._ctx, _ptr(nbf), _ptr(off)))
+        return nbf, off
+
     def build_quartets(self, tau=1e-10, tau_prim=0.0, density_screen=True, bra_block=0, tau_fp32=0.0):
         o = ScreenOpts(float(tau), float(tau_prim), 1 if density_screen else 0, int(bra_block), float(tau_fp32))
         self._check(_lib.fk_build_quartets(self._ctx, ctypes.byref(o)))
@@ -178,19 +197,18 @@ class FockJK:
         """J, K for density D.  torch CUDA tensors (float64, contiguous) stay on
         the device and run on `stream` (default: torch's current stream);
         numpy arrays go through host copies."""
+        nmat = self.info()["nmat"]
         if isinstance(D, np.ndarray):
             Dh = np.ascontiguousarray(D, dtype=np.float64)
-            n = self.nbf
-            if Dh.shape != (n, n):
-                raise ValueError(f"D must be {n}x{n}")
-            Jh = np.zeros((n, n))
-            Kh = np.zeros((n, n))
+            if Dh.size != nmat:
+                raise ValueError(f"D must hold {nmat} elements (nbf x nbf, or the concatenated blocks of a batch)")
+            Jh = np.zeros(Dh.shape)
+            Kh = np.zeros(Dh.shape)
             self._check(_lib.fk_build_jk(self._ctx, _ptr(Dh), _ptr(Jh), _ptr(Kh), 0, None))
             return Jh, Kh
         import torch
-        n = self.nbf
-        if not (D.is_cuda and D.dtype == torch.float64 and D.is_contiguous() and tuple(D.shape) == (n, n)):
-            raise ValueError(f"D must be a contiguous float64 CUDA tensor of shape ({n},{n})")
+        if not (D.is_cuda and D.dtype == torch.float64 and D.is_contiguous() and D.numel() == nmat):
+            raise ValueError(f"D must be a contiguous float64 CUDA tensor of {nmat} elements")
         if J is None:
             J = torch.empty_like(D)
         if K is None:

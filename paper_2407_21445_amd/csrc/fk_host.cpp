@@ -61,7 +61,15 @@ struct fk_ctx {
     bool have_geom = false, have_basis = false, have_quartets = false;
     // basis
     int nshell = 0, nbf = 0;
-    std::vector<int> sh_atom, sh_l, sh_nprim, sh_poff, sh_bf;
+    std::vector<int> sh_atom, sh_l, sh_nprim, sh_poff, sh_bf;   // sh_bf: flat offsets over all molecules
+    // molecules of a batch (one molecule unless fk_set_molecules split the atoms):
+    // shells, functions and matrix blocks are numbered within each molecule
+    int nmol = 1;
+    std::vector<int> atom_mol;                   // molecule of each atom
+    std::vector<int> sh_mol, sh_loc, sh_lbf, sh_lend;  // per shell: molecule, local index, local first/end function
+    std::vector<int> mol_sh0, mol_nsh, mol_bf0, mol_nbf;
+    std::vector<long long> mol_base, mol_shbase;  // [nmol + 1] offsets of the nbf^2 and nshell^2 blocks
+    std::vector<int> pr_sa_loc, pr_sb_loc, lst_sa_loc, lst_sb_loc;
     std::vector<double> exps, coef;  // coef: normalised for the axis component
     std::vector<double> bf_scale;    // component scale factors
     // pairs
@@ -86,6 +94,8 @@ struct fk_ctx {
     int npair_kept = 0;
     // device buffers
     DevBuf<int> d_sh_bf, d_pr_sa, d_pr_sb, d_pr_ppoff, d_pr_npp, d_ket, d_lst_sa, d_lst_sb;
+    DevBuf<int> d_sh_lend, d_mol_sh0, d_mol_nsh, d_mol_bf0, d_mol_nbf;
+    DevBuf<long long> d_mol_base, d_mol_shbase;
     DevBuf<double> d_bf_scale, d_pr_AB, d_pr_G, d_pp, d_rys, d_Ds, d_Dsh, d_X, d_Din, d_Jout, d_Kout;
     DevBuf<double> d_lst_CD, d_lst_G, d_ppT;
     DevBuf<FkGroup> d_groups;
@@ -170,6 +180,8 @@ void cart_exps(int l, int k, int &x, int &y, int &z)
 
 void free_device(fk_ctx *c)
 {
+    dev_free(c->d_sh_lend); dev_free(c->d_mol_sh0); dev_free(c->d_mol_nsh); dev_free(c->d_mol_bf0);
+    dev_free(c->d_mol_nbf); dev_free(c->d_mol_base); dev_free(c->d_mol_shbase);
     dev_free(c->d_sh_bf); dev_free(c->d_pr_sa); dev_free(c->d_pr_sb); dev_free(c->d_pr_ppoff);
     dev_free(c->d_pr_npp); dev_free(c->d_ket); dev_free(c->d_bf_scale); dev_free(c->d_pr_AB);
     dev_free(c->d_pr_G); dev_free(c->d_pp); dev_free(c->d_rys); dev_free(c->d_Ds); dev_free(c->d_Dsh);
@@ -421,11 +433,63 @@ int validate_lists(fk_ctx *c)
     return FK_OK;
 }
 
+// Per-molecule numbering of shells and functions and the offsets of each
+// molecule's matrix blocks in the concatenated D, J, K and shell-maximum arrays.
+int layout_molecules(fk_ctx *c)
+{
+    const int ns = c->nshell;
+    if ((int)c->atom_mol.size() != c->natom) c->atom_mol.assign(c->natom, 0);
+    c->nmol = 1;
+    for (int m : c->atom_mol) c->nmol = std::max(c->nmol, m + 1);
+    const int nm = c->nmol;
+    c->sh_mol.assign(ns, 0); c->sh_loc.assign(ns, 0); c->sh_lbf.assign(ns, 0); c->sh_lend.assign(ns, 0);
+    c->mol_sh0.assign(nm, -1); c->mol_nsh.assign(nm, 0); c->mol_bf0.assign(nm, 0); c->mol_nbf.assign(nm, 0);
+    for (int s = 0; s < ns; ++s) {
+        const int m = c->atom_mol[c->sh_atom[s]];
+        if (s > 0 && m < c->sh_mol[s - 1])
+            return fail(c, FK_ERR_ARG, "fk_set_molecules: shells of a molecule must be contiguous (atoms in molecule order)");
+        c->sh_mol[s] = m;
+        if (c->mol_sh0[m] < 0) { c->mol_sh0[m] = s; c->mol_bf0[m] = c->sh_bf[s]; }
+        c->sh_loc[s] = s - c->mol_sh0[m];
+        c->sh_lbf[s] = c->sh_bf[s] - c->mol_bf0[m];
+        c->sh_lend[s] = c->sh_bf[s + 1] - c->mol_bf0[m];
+        c->mol_nsh[m] += 1;
+        c->mol_nbf[m] += ncart(c->sh_l[s]);
+    }
+    c->mol_base.assign(nm + 1, 0);
+    c->mol_shbase.assign(nm + 1, 0);
+    for (int m = 0; m < nm; ++m) {
+        if (c->mol_nsh[m] == 0) return fail(c, FK_ERR_ARG, "fk_set_molecules: molecule %d has no shells", m);
+        c->mol_base[m + 1] = c->mol_base[m] + (long long)c->mol_nbf[m] * c->mol_nbf[m];
+        c->mol_shbase[m + 1] = c->mol_shbase[m] + (long long)c->mol_nsh[m] * c->mol_nsh[m];
+    }
+    if (c->device >= 0) {
+        int rc;
+        if ((rc = dev_upload(c, c->d_sh_bf, c->sh_lbf.data(), c->sh_lbf.size())) ||
+            (rc = dev_upload(c, c->d_sh_lend, c->sh_lend.data(), c->sh_lend.size())) ||
+            (rc = dev_upload(c, c->d_mol_sh0, c->mol_sh0.data(), c->mol_sh0.size())) ||
+            (rc = dev_upload(c, c->d_mol_nsh, c->mol_nsh.data(), c->mol_nsh.size())) ||
+            (rc = dev_upload(c, c->d_mol_bf0, c->mol_bf0.data(), c->mol_bf0.size())) ||
+            (rc = dev_upload(c, c->d_mol_nbf, c->mol_nbf.data(), c->mol_nbf.size())) ||
+            (rc = dev_upload(c, c->d_mol_base, c->mol_base.data(), c->mol_base.size())) ||
+            (rc = dev_upload(c, c->d_mol_shbase, c->mol_shbase.data(), c->mol_shbase.size())))
+            return rc;
+    }
+    return FK_OK;
+}
+
 int upload_pairs(fk_ctx *c)
 {
     int rc;
-    if ((rc = dev_upload(c, c->d_pr_sa, c->pr_sa.data(), c->pr_sa.size()))) return rc;
-    if ((rc = dev_upload(c, c->d_pr_sb, c->pr_sb.data(), c->pr_sb.size()))) return rc;
+    // the kernels see shells by their index within the molecule
+    c->pr_sa_loc.resize(c->pr_sa.size());
+    c->pr_sb_loc.resize(c->pr_sb.size());
+    for (size_t p = 0; p < c->pr_sa.size(); ++p) {
+        c->pr_sa_loc[p] = c->sh_loc[c->pr_sa[p]];
+        c->pr_sb_loc[p] = c->sh_loc[c->pr_sb[p]];
+    }
+    if ((rc = dev_upload(c, c->d_pr_sa, c->pr_sa_loc.data(), c->pr_sa_loc.size()))) return rc;
+    if ((rc = dev_upload(c, c->d_pr_sb, c->pr_sb_loc.data(), c->pr_sb_loc.size()))) return rc;
     if ((rc = dev_upload(c, c->d_pr_ppoff, c->pr_ppoff.data(), c->pr_ppoff.size()))) return rc;
     if ((rc = dev_upload(c, c->d_pr_npp, c->pr_npp.data(), c->pr_npp.size()))) return rc;
     if ((rc = dev_upload(c, c->d_pr_AB, c->pr_AB.data(), c->pr_AB.size()))) return rc;
@@ -506,6 +570,7 @@ int fk_set_geometry(fk_ctx *c, int natom, const int *Z, const double *xyz, int c
     c->xyz.assign(xyz, xyz + 3 * natom);
     c->charge = charge;
     c->nelec = (int)ne;
+    c->atom_mol.assign(natom, 0);
     c->have_geom = true;
     c->have_basis = false;
     c->have_quartets = false;
@@ -560,11 +625,32 @@ int fk_set_basis(fk_ctx *c, int nshell, const int *shell_atom, const int *shell_
     }
     c->have_basis = true;
     c->have_quartets = false;
+    int rc;
     if (c->device >= 0) {
         hipSetDevice(c->device);
-        int rc;
-        if ((rc = dev_upload(c, c->d_sh_bf, c->sh_bf.data(), c->sh_bf.size()))) return rc;
         if ((rc = dev_upload(c, c->d_bf_scale, c->bf_scale.data(), c->bf_scale.size()))) return rc;
+    }
+    if ((rc = layout_molecules(c))) { c->have_basis = false; return rc; }
+    return FK_OK;
+}
+
+int fk_set_molecules(fk_ctx *c, int nmol, const int *atom_mol)
+{
+    if (!c) return FK_ERR_ARG;
+    if (!c->have_geom) return fail(c, FK_ERR_STATE, "fk_set_molecules: geometry not set");
+    if (nmol < 1 || !atom_mol) return fail(c, FK_ERR_ARG, "fk_set_molecules: nmol must be >= 1 and atom_mol non-null");
+    for (int a = 0; a < c->natom; ++a) {
+        if (atom_mol[a] < 0 || atom_mol[a] >= nmol || (a > 0 && atom_mol[a] < atom_mol[a - 1]))
+            return fail(c, FK_ERR_ARG, "fk_set_molecules: atom %d: molecule indices must be 0..nmol-1, non-decreasing", a);
+    }
+    for (int m = 0; m < nmol; ++m)
+        if (std::find(atom_mol, atom_mol + c->natom, m) == atom_mol + c->natom)
+            return fail(c, FK_ERR_ARG, "fk_set_molecules: molecule %d has no atoms", m);
+    c->atom_mol.assign(atom_mol, atom_mol + c->natom);
+    c->have_quartets = false;
+    if (c->have_basis) {
+        int rc;
+        if ((rc = layout_molecules(c))) { c->have_basis = false; return rc; }
     }
     return FK_OK;
 }
@@ -587,6 +673,7 @@ int fk_build_quartets(fk_ctx *c, const fk_screen_opts *o)
     c->pr_AB.clear(); c->pr_G.clear(); c->pp.clear();
     for (int a = 0; a < c->nshell; ++a)
         for (int b = 0; b <= a; ++b) {
+            if (c->sh_mol[a] != c->sh_mol[b]) continue;  // molecules of a batch do not interact
             int sa, sb;
             orient(c, a, b, sa, sb);
             make_pair(c, sa, sb);
@@ -634,12 +721,16 @@ int fk_build_quartets(fk_ctx *c, const fk_screen_opts *o)
     for (int P = 0; P < NPC; ++P) {
         auto &L = c->cls_list[P];
         std::stable_sort(L.begin(), L.end(), [&](int x, int y) {
+            const int mx = c->sh_mol[c->pr_sa[x]], my = c->sh_mol[c->pr_sa[y]];
+            if (mx != my) return mx < my;
             if (c->pr_npp[x] != c->pr_npp[y]) return c->pr_npp[x] > c->pr_npp[y];
             return c->pr_G[x] > c->pr_G[y];
         });
+        // groups: runs of one molecule and one primitive-pair count
         for (size_t i = 0; i < L.size();) {
             size_t j = i;
-            while (j < L.size() && c->pr_npp[L[j]] == c->pr_npp[L[i]]) ++j;
+            const int mi = c->sh_mol[c->pr_sa[L[i]]];
+            while (j < L.size() && c->pr_npp[L[j]] == c->pr_npp[L[i]] && c->sh_mol[c->pr_sa[L[j]]] == mi) ++j;
             c->cls_groups[P].push_back({(int)i, (int)j});
             i = j;
         }
@@ -650,11 +741,14 @@ int fk_build_quartets(fk_ctx *c, const fk_screen_opts *o)
     {
         const size_t nl = c->ket_list_all.size();
         c->lst_sa.assign(nl, 0); c->lst_sb.assign(nl, 0);
+        c->lst_sa_loc.assign(nl, 0); c->lst_sb_loc.assign(nl, 0);
         c->lst_CD.assign(3 * std::max<size_t>(nl, 1), 0.0); c->lst_G.assign(nl, 0.0);
         for (size_t q = 0; q < nl; ++q) {
             const int p = c->ket_list_all[q];
             c->lst_sa[q] = c->pr_sa[p];
             c->lst_sb[q] = c->pr_sb[p];
+            c->lst_sa_loc[q] = c->sh_loc[c->pr_sa[p]];
+            c->lst_sb_loc[q] = c->sh_loc[c->pr_sb[p]];
             for (int k = 0; k < 3; ++k) c->lst_CD[k * nl + q] = c->pr_AB[3 * p + k];
             c->lst_G[q] = c->pr_G[p];
         }
@@ -668,7 +762,7 @@ int fk_build_quartets(fk_ctx *c, const fk_screen_opts *o)
                 G.begin = c->ket_off[P] + g.first;
                 G.len = g.second - g.first;
                 G.npp = c->pr_npp[c->cls_list[P][g.first]];
-                G.pad = 0;
+                G.mol = c->sh_mol[c->pr_sa[c->cls_list[P][g.first]]];
                 G.base = (long long)c->ppT.size();
                 c->ppT.resize(c->ppT.size() + (size_t)G.npp * FK_NFLD * G.len);
                 for (int r = 0; r < G.len; ++r) {
@@ -751,8 +845,10 @@ int fk_build_quartets(fk_ctx *c, const fk_screen_opts *o)
                     nppsum += c->pr_npp[LP[ord[x]]];
                 }
                 c->blk_nppsum.push_back(nppsum);
+                const int bmol = c->sh_mol[sa0];
                 for (size_t gi = 0; gi < c->cls_groups[Q].size(); ++gi) {
                     const auto &g = c->cls_groups[Q][gi];
+                    if (c->sh_mol[c->pr_sa[LQ[g.first]]] != bmol) continue;  // kets of the bra's molecule only
                     const int gnpp = c->pr_npp[LQ[g.first]];
                     // ket ranges [lo, hi) of the group for the FP64 and FP32 launches
                     int hi64 = 0, lo32 = g.second - g.first, hi32 = 0;
@@ -819,17 +915,17 @@ int fk_build_quartets(fk_ctx *c, const fk_screen_opts *o)
     if (dev) {
         if ((rc = dev_upload(c, c->d_pr_G, c->pr_G.data(), c->pr_G.size()))) return rc;
         if ((rc = dev_upload(c, c->d_ket, c->ket_list_all.data(), c->ket_list_all.size()))) return rc;
-        if ((rc = dev_upload(c, c->d_lst_sa, c->lst_sa.data(), c->lst_sa.size()))) return rc;
-        if ((rc = dev_upload(c, c->d_lst_sb, c->lst_sb.data(), c->lst_sb.size()))) return rc;
+        if ((rc = dev_upload(c, c->d_lst_sa, c->lst_sa_loc.data(), c->lst_sa_loc.size()))) return rc;
+        if ((rc = dev_upload(c, c->d_lst_sb, c->lst_sb_loc.data(), c->lst_sb_loc.size()))) return rc;
         if ((rc = dev_upload(c, c->d_lst_CD, c->lst_CD.data(), c->lst_CD.size()))) return rc;
         if ((rc = dev_upload(c, c->d_lst_G, c->lst_G.data(), c->lst_G.size()))) return rc;
         if ((rc = dev_upload(c, c->d_ppT, c->ppT.data(), c->ppT.size()))) return rc;
         if ((rc = dev_upload(c, c->d_groups, c->groups.data(), c->groups.size()))) return rc;
         if ((rc = dev_upload(c, c->d_tiles, c->tiles.data(), c->tiles.size()))) return rc;
-        const size_t nn = (size_t)c->nbf * c->nbf;
+        const size_t nn = (size_t)c->mol_base[c->nmol];
         if ((rc = dev_upload<double>(c, c->d_Ds, nullptr, nn))) return rc;
-        if ((rc = dev_upload<double>(c, c->d_Dsh, nullptr, (size_t)c->nshell * c->nshell))) return rc;
-        if ((rc = dev_upload<double>(c, c->d_X, nullptr, 2 * nn))) return rc;
+        if ((rc = dev_upload<double>(c, c->d_Dsh, nullptr, (size_t)c->mol_shbase[c->nmol]))) return rc;
+        if ((rc = dev_upload<double>(c, c->d_X, nullptr, 2 * nn * FK_XCD_COPIES))) return rc;
         if ((rc = dev_upload<unsigned long long>(c, c->d_cnt, nullptr, 2 * FK_MAX_QCLASS))) return rc;
         if ((rc = dev_upload(c, c->d_blocks, c->blocks.data(), c->blocks.size()))) return rc;
         if ((rc = dev_upload(c, c->d_blk_bra, c->blk_bra.data(), c->blk_bra.size()))) return rc;
@@ -858,6 +954,17 @@ int fk_info(const fk_ctx *c, fk_info_t *info)
     info->nquartet_schwarz = c->nq_schwarz;
     info->ntile = (int64_t)c->tiles.size();
     info->flops_schwarz = c->flops_schwarz;
+    info->nmol = c->nmol;
+    info->nmat = c->mol_base.empty() ? 0 : c->mol_base[c->nmol];
+    return FK_OK;
+}
+
+int fk_molecule_layout(const fk_ctx *c, int *nbf, int64_t *offset)
+{
+    if (!c || !nbf || !offset) return FK_ERR_ARG;
+    if (!c->have_basis) return FK_ERR_STATE;
+    for (int m = 0; m < c->nmol; ++m) nbf[m] = c->mol_nbf[m];
+    for (int m = 0; m <= c->nmol; ++m) offset[m] = c->mol_base[m];
     return FK_OK;
 }
 
@@ -869,8 +976,12 @@ int fk_build_jk(fk_ctx *c, const double *D, double *J, double *K, unsigned flags
     if (!D || !J || !K) return fail(c, FK_ERR_ARG, "fk_build_jk: null matrix pointer");
     hipSetDevice(c->device);
     hipStream_t st = (hipStream_t)stream;
-    const int n = c->nbf;
-    const size_t nn = (size_t)n * n;
+    // one nbf_m^2 block per molecule, concatenated
+    const size_t nn = (size_t)c->mol_base[c->nmol];
+    FkMolArgs ma;
+    ma.sh_lbf = c->d_sh_bf.p; ma.sh_lend = c->d_sh_lend.p; ma.mol_sh0 = c->d_mol_sh0.p; ma.mol_nsh = c->d_mol_nsh.p;
+    ma.mol_nbf = c->d_mol_nbf.p; ma.mol_bf0 = c->d_mol_bf0.p; ma.mol_base = c->d_mol_base.p;
+    ma.mol_shbase = c->d_mol_shbase.p; ma.nmol = c->nmol; ma.nmat = (long long)nn; ma.nshmat = c->mol_shbase[c->nmol];
     const bool devp = flags & FK_DEVICE_PTRS;
     int rc;
     const double *Dd = D;
@@ -884,9 +995,9 @@ int fk_build_jk(fk_ctx *c, const double *D, double *J, double *K, unsigned flags
         Jd = c->d_Jout.p;
         Kd = c->d_Kout.p;
     }
-    if (fk_kernels_launch_prep(Dd, c->d_sh_bf.p, c->d_bf_scale.p, c->nshell, n, c->d_Ds.p, c->d_Dsh.p, st))
+    if (fk_kernels_launch_prep(Dd, c->d_bf_scale.p, &ma, c->d_Ds.p, c->d_Dsh.p, st))
         return fail(c, FK_ERR_HIP, "prep kernel launch failed");
-    if (fk_kernels_launch_fill(c->d_X.p, (long long)(2 * nn), st) ||
+    if (fk_kernels_launch_fill(c->d_X.p, (long long)(2 * nn * FK_XCD_COPIES), st) ||
         fk_kernels_launch_fill((double *)c->d_cnt.p, 2 * FK_MAX_QCLASS, st))
         return fail(c, FK_ERR_HIP, "fill kernel launch failed");
     c->timed = (flags & FK_TIME_CLASSES) != 0;
@@ -901,6 +1012,11 @@ int fk_build_jk(fk_ctx *c, const double *D, double *J, double *K, unsigned flags
         if (c->timed) HIPCHK(c, hipEventRecord(c->ev[2 * i], st));
         FkJKArgs a;
         a.sh_bf = c->d_sh_bf.p;
+        a.mol_sh0 = c->d_mol_sh0.p;
+        a.mol_nbf = c->d_mol_nbf.p;
+        a.mol_nsh = c->d_mol_nsh.p;
+        a.mol_base = c->d_mol_base.p;
+        a.mol_shbase = c->d_mol_shbase.p;
         a.pair_sa = c->d_pr_sa.p;
         a.pair_sb = c->d_pr_sb.p;
         a.pair_ppoff = c->d_pr_ppoff.p;
@@ -918,12 +1034,11 @@ int fk_build_jk(fk_ctx *c, const double *D, double *J, double *K, unsigned flags
         a.ppT = c->d_ppT.p;
         a.tiles = c->d_tiles.p + qc.tile_off;
         a.ntiles = (int)qc.ntile;
-        a.nshell = c->nshell;
         a.Dsh = c->d_Dsh.p;
         a.Ds = c->d_Ds.p;
         a.XJ = c->d_X.p;
         a.XK = c->d_X.p + nn;
-        a.nbf = n;
+        a.xcopy = (long long)(2 * nn);
         a.dscreen = c->opts.density_screen && c->opts.tau > 0;
         a.tau = c->opts.tau;
         a.rys_tab = c->d_rys.p + rys_staged_offset(qc.info.nroot);
@@ -943,7 +1058,7 @@ int fk_build_jk(fk_ctx *c, const double *D, double *J, double *K, unsigned flags
             return fail(c, FK_ERR_HIP, "J/K kernel launch failed for class (%d|%d)", qc.P, qc.Q);
         if (c->timed) HIPCHK(c, hipEventRecord(c->ev[2 * i + 1], st));
     }
-    if (fk_kernels_launch_finalize(c->d_X.p, c->d_X.p + nn, c->d_bf_scale.p, n, Jd, Kd, st))
+    if (fk_kernels_launch_finalize(c->d_X.p, c->d_X.p + nn, (long long)(2 * nn), c->d_bf_scale.p, &ma, Jd, Kd, st))
         return fail(c, FK_ERR_HIP, "finalize kernel launch failed");
     c->stats_pending = true;
     if (!devp) {
@@ -991,6 +1106,7 @@ int fk_stats(fk_ctx *c, fk_stats_t *s)
 int fk_debug_eri(fk_ctx *c, int nq, const int *quartets, double *out, int on_device)
 {
     if (!c) return FK_ERR_ARG;
+    if (c->nmol > 1) return fail(c, FK_ERR_UNSUPPORTED, "fk_debug_eri: not available for a batch of molecules");
     if (!c->have_quartets) return fail(c, FK_ERR_STATE, "fk_debug_eri: call fk_build_quartets first");
     if (nq < 0 || (nq > 0 && (!quartets || !out))) return fail(c, FK_ERR_ARG, "fk_debug_eri: bad arguments");
     if (on_device && c->device < 0) return fail(c, FK_ERR_STATE, "fk_debug_eri: context has no device");
@@ -1086,7 +1202,7 @@ int fk_check_indices(fk_ctx *c)
 {
     if (!c) return FK_ERR_ARG;
     if (!c->have_quartets) return fail(c, FK_ERR_STATE, "fk_check_indices: no quartet lists");
-    const long long n = c->nbf, ns = c->nshell, nl = (long long)c->ket_list_all.size();
+    const long long nl = (long long)c->ket_list_all.size();
     const long long npair = (long long)c->pr_sa.size(), nppr = (long long)(c->pp.size() / FK_NPP_REC);
     const long long nT = (long long)c->ppT.size();
     for (size_t qi = 0; qi < c->qclasses.size(); ++qi) {
@@ -1099,19 +1215,25 @@ int fk_check_indices(fk_ctx *c)
                 return fail(c, FK_ERR_STATE, "class %zu tile %lld: block/group out of range", qi, (long long)t);
             const FkGroup &g = c->groups[gid];
             const FkBraBlock &BB = c->blocks[T.blk];
+            // the kernels address the tile's molecule: its nbf_m^2 and nshell_m^2 blocks
+            if (g.mol < 0 || g.mol >= c->nmol) return fail(c, FK_ERR_STATE, "tile %lld: molecule out of range", (long long)t);
+            const long long n = c->mol_nbf[g.mol], ns = c->mol_nsh[g.mol];
             if (BB.first < 0 || BB.count < 1 || BB.count > FK_MAX_BRA_BLOCK || (size_t)BB.first + BB.count > c->blk_bra.size())
                 return fail(c, FK_ERR_STATE, "tile %lld: bra block range", (long long)t);
           for (int jb = 0; jb < BB.count; ++jb) {
             const long long bra = c->blk_bra[BB.first + jb], bpos = c->blk_pos[BB.first + jb];
             if (bra < 0 || bra >= npair || bpos < 0 || bpos >= nl) return fail(c, FK_ERR_STATE, "tile %lld: bra %d index", (long long)t, jb);
-            const int sa = c->pr_sa[bra], sb = c->pr_sb[bra];
+            const int gsa = c->pr_sa[bra], gsb = c->pr_sb[bra];
+            if (c->sh_mol[gsa] != g.mol || c->sh_mol[gsb] != g.mol)
+                return fail(c, FK_ERR_STATE, "tile %lld: bra outside the tile's molecule", (long long)t);
+            const int sa = c->sh_loc[gsa], sb = c->sh_loc[gsb];
             const long long ppo = c->pr_ppoff[bra], bnp = c->pr_npp[bra];
             if (ppo < 0 || ppo + bnp > nppr) return fail(c, FK_ERR_STATE, "tile %lld: bra records", (long long)t);
             if (bnp * FK_NFLD > qc.bra_slot) return fail(c, FK_ERR_STATE, "tile %lld: LDS bra slot", (long long)t);
-            const long long oa = c->sh_bf[sa], ob = c->sh_bf[sb];
-            if (oa + NA > n || ob + NB > n || ncart(c->sh_l[sa]) != NA || ncart(c->sh_l[sb]) != NB)
+            const long long oa = c->sh_lbf[gsa], ob = c->sh_lbf[gsb];
+            if (oa + NA > n || ob + NB > n || ncart(c->sh_l[gsa]) != NA || ncart(c->sh_l[gsb]) != NB)
                 return fail(c, FK_ERR_STATE, "tile %lld: bra shells do not match the class", (long long)t);
-            if (sa != c->pr_sa[c->blk_bra[BB.first]])
+            if (gsa != c->pr_sa[c->blk_bra[BB.first]])
                 return fail(c, FK_ERR_STATE, "tile %lld: bra block members differ in their first shell", (long long)t);
             if (T.ket_count < 1 || T.ket_count > 64)
                 return fail(c, FK_ERR_STATE, "tile %lld: ket count %d", (long long)t, T.ket_count);
@@ -1123,14 +1245,18 @@ int fk_check_indices(fk_ctx *c)
                 if (r < 0 || r >= g.len) return fail(c, FK_ERR_STATE, "tile %lld lane %d: outside its group", (long long)t, k);
                 const long long kp = c->ket_list_all[pos];
                 if (kp < 0 || kp >= npair) return fail(c, FK_ERR_STATE, "tile %lld lane %d: ket pair", (long long)t, k);
-                const int sc = c->lst_sa[pos], sd = c->lst_sb[pos];
-                if (sc != c->pr_sa[kp] || sd != c->pr_sb[kp])
+                const int gsc = c->lst_sa[pos], gsd = c->lst_sb[pos];
+                if (gsc != c->pr_sa[kp] || gsd != c->pr_sb[kp] || c->lst_sa_loc[pos] != c->sh_loc[gsc] ||
+                    c->lst_sb_loc[pos] != c->sh_loc[gsd])
                     return fail(c, FK_ERR_STATE, "tile %lld lane %d: list data disagree with the pair", (long long)t, k);
-                if (ncart(c->sh_l[sc]) != NC || ncart(c->sh_l[sd]) != ND || c->pr_npp[kp] != g.npp)
+                if (c->sh_mol[gsc] != g.mol || c->sh_mol[gsd] != g.mol)
+                    return fail(c, FK_ERR_STATE, "tile %lld lane %d: ket outside the tile's molecule", (long long)t, k);
+                const int sc = c->sh_loc[gsc], sd = c->sh_loc[gsd];
+                if (ncart(c->sh_l[gsc]) != NC || ncart(c->sh_l[gsd]) != ND || c->pr_npp[kp] != g.npp)
                     return fail(c, FK_ERR_STATE, "tile %lld lane %d: ket does not match class/group", (long long)t, k);
                 const long long last = g.base + ((long long)(g.npp - 1) * FK_NFLD + FK_NFLD - 1) * g.len + r;
                 if (g.base < 0 || last >= nT) return fail(c, FK_ERR_STATE, "tile %lld lane %d: ket records", (long long)t, k);
-                const long long oc = c->sh_bf[sc], od = c->sh_bf[sd];
+                const long long oc = c->sh_lbf[gsc], od = c->sh_lbf[gsd];
                 if (oc + NC > n || od + ND > n) return fail(c, FK_ERR_STATE, "tile %lld lane %d: ket functions", (long long)t, k);
                 const long long dsh[6] = {sa * ns + sb, sc * ns + sd, sa * ns + sc, sa * ns + sd, sb * ns + sc, sb * ns + sd};
                 for (long long x : dsh)
@@ -1150,6 +1276,7 @@ int fk_check_indices(fk_ctx *c)
 int fk_one_electron(fk_ctx *c, double *S, double *T, double *V, double *e_nuc)
 {
     if (!c) return FK_ERR_ARG;
+    if (c->nmol > 1) return fail(c, FK_ERR_UNSUPPORTED, "fk_one_electron: not available for a batch of molecules");
     if (!c->have_basis) return fail(c, FK_ERR_STATE, "fk_one_electron: basis not set");
     const int n = c->nbf;
     if (e_nuc) {
@@ -1416,6 +1543,7 @@ int fk_run_scf(fk_ctx *c, const fk_scf_opts *opts, fk_scf_result *result, double
     std::memset(result, 0, sizeof *result);
     if (c->device < 0) return fail(c, FK_ERR_STATE, "fk_run_scf: context has no device");
     if (!c->have_quartets) return fail(c, FK_ERR_STATE, "fk_run_scf: call fk_build_quartets first");
+    if (c->nmol > 1) return fail(c, FK_ERR_UNSUPPORTED, "fk_run_scf: one molecule per context (batches: one context each)");
     fk_scf_opts o = {100, 1e-10, 1e-8, 8, 0, 1e-8};
     if (opts) o = *opts;
     if (o.max_iter < 1 || o.diis_n < 0 || o.diis_n > 32 || !(o.e_tol > 0) || !(o.g_tol > 0) || !(o.lindep > 0) ||

@@ -38,7 +38,7 @@ struct FkGroup {
     int begin;      // first list position
     int len;        // number of pairs
     int npp;        // primitive pairs per pair
-    int pad;
+    int mol;        // molecule of the run's pairs (0 unless the context holds a batch)
     long long base; // offset of the run's records in the transposed array
 };
 
@@ -48,16 +48,23 @@ struct FkGroup {
 #endif
 
 struct FkJKArgs {
-    const int *sh_bf;        // [nshell + 1] first basis function of each shell
-    const int *pair_sa;      // [npair] first shell (higher l)
-    const int *pair_sb;      // [npair] second shell
+    // Shells are numbered within their molecule: a kernel offsets these arrays
+    // by the tile's molecule (FkGroup::mol).
+    const int *sh_bf;        // [nshell] first basis function of each shell, within its molecule
+    const int *mol_sh0;      // [nmol] first shell of each molecule
+    const int *mol_nbf;      // [nmol] functions per molecule
+    const int *mol_nsh;      // [nmol] shells per molecule
+    const long long *mol_base;    // [nmol + 1] offset of each molecule's nbf^2 block in Ds, XJ, XK
+    const long long *mol_shbase;  // [nmol + 1] offset of each molecule's nshell^2 block in Dsh
+    const int *pair_sa;      // [npair] first shell (higher l), index within the molecule
+    const int *pair_sb;      // [npair] second shell, index within the molecule
     const int *pair_ppoff;   // [npair] first primitive pair
     const int *pair_npp;     // [npair] number of primitive pairs
     const double *pair_AB;   // [npair * 3] A - B
     const double *pair_G;    // [npair] Schwarz factor
     const double *pp;        // [nprimpair * FK_NPP_REC]
     const int *ket_list;     // sorted pair indices (all classes, concatenated)
-    const int *lst_sa, *lst_sb;   // shells of the pair at each list position
+    const int *lst_sa, *lst_sb;   // shells (within the molecule) of the pair at each list position
     const double *lst_CD;    // [3][nlist] A - B of the pair at each list position
     const double *lst_G;     // Schwarz factor at each list position
     int nlist;
@@ -68,12 +75,11 @@ struct FkJKArgs {
     const FkBraBlock *blocks;
     const int *blk_bra;      // shell-pair index of each bra of each block
     const int *blk_pos;      // its position in the sorted pair lists
-    int nshell;
-    const double *Dsh;       // [nshell * nshell] max |D| per shell block
-    const double *Ds;        // [nbf * nbf] component-scaled density
-    double *XJ;              // [nbf * nbf] unsymmetrised Coulomb accumulator
-    double *XK;              // [nbf * nbf] unsymmetrised exchange accumulator
-    int nbf;
+    const double *Dsh;       // per molecule [nshell_m * nshell_m] max |D| per shell block
+    const double *Ds;        // per molecule [nbf_m * nbf_m] component-scaled density
+    double *XJ;              // per molecule [nbf_m * nbf_m] unsymmetrised Coulomb accumulator
+    double *XK;              // per molecule [nbf_m * nbf_m] unsymmetrised exchange accumulator
+    long long xcopy;         // distance between the FK_XCD_COPIES copies of (XJ, XK)
     int dscreen;             // apply the density screen
     double tau;
     const double *rys_tab;   // staged Rys segment (table + Gauss-Hermite) of this class's root count
@@ -82,6 +88,22 @@ struct FkJKArgs {
     int prec;                // 0: FP64 kernel, 1: FP32 kernel of the precision split
     double tau_hi;           // precision split: the FP64 kernel takes quartets with
                              // G_ab G_cd >= tau_hi, the FP32 kernel the others (0: no split)
+};
+
+// The accumulators X_J, X_K exist once per XCD (CDNA3/4 parts have 8 XCDs,
+// each with its own L2; workgroups are dispatched to them round-robin).  A
+// workgroup adds into copy blockIdx.x mod FK_XCD_COPIES, so the atomics of one
+// XCD stay on lines its L2 owns; the finalize kernel sums the copies.  Any
+// assignment is correct, the round-robin one keeps the traffic local.
+#define FK_XCD_COPIES 8
+
+// Molecule layout for the density preprocessing and finalize kernels.
+struct FkMolArgs {
+    const int *sh_lbf, *sh_lend;  // [nshell] first and end function of each shell within its molecule
+    const int *mol_sh0, *mol_nsh, *mol_nbf, *mol_bf0;  // [nmol]; mol_bf0: first function in the flat numbering
+    const long long *mol_base, *mol_shbase;           // [nmol + 1]
+    int nmol;
+    long long nmat, nshmat;       // total elements of the nbf^2 and nshell^2 blocks
 };
 
 // Quartet list for the debug/Schwarz kernels (canonical orientation).
@@ -110,10 +132,10 @@ int fk_kernels_launch_jk(int P, int Q, const FkJKArgs *args, int grid, void *str
 int fk_kernels_launch_debug(int P, int Q, const FkDebugArgs *args, void *stream);
 int fk_kernels_max_blocks(int P, int Q, int dyn_lds_bytes, int *blocks_per_cu);
 int fk_kernels_jk_lds_bytes(int P, int Q, int bra_slot);
-int fk_kernels_launch_prep(const double *D, const int *sh_bf, const double *bf_scale, int nshell, int nbf,
-                           double *Ds, double *Dsh, void *stream);
-int fk_kernels_launch_finalize(const double *XJ, const double *XK, const double *bf_scale, int nbf,
-                               double *J, double *K, void *stream);
+int fk_kernels_launch_prep(const double *D, const double *bf_scale, const FkMolArgs *m, double *Ds, double *Dsh,
+                           void *stream);
+int fk_kernels_launch_finalize(const double *XJ, const double *XK, long long xcopy, const double *bf_scale,
+                               const FkMolArgs *m, double *J, double *K, void *stream);
 int fk_kernels_launch_fill(double *p, long long n, void *stream);
 int fk_kernels_debug_host(int P, int Q, const int *pair_ppoff, const int *pair_npp, const double *pair_AB,
                           const double *pp, const int *quartets, int nq, double *out);

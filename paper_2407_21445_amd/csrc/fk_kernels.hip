@@ -208,29 +208,37 @@ __global__ void __launch_bounds__(FK_BLOCK) k_jk_lpq(FkJKArgs a)
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     double *s_bra = s_dyn + rys_lds_size(Q::NR) + wave * a.bra_slot;
     const int nwt = gridDim.x * FK_WAVES;
-    const int n = a.nbf, ns = a.nshell;
     unsigned long long cq = 0, cp = 0;
 
     for (int t = blockIdx.x * FK_WAVES + wave; t < a.ntiles; t += nwt) {
         const FkTile tile = a.tiles[t];
         const bool same = (tile.grp & FK_TILE_SAME) != 0;
         const FkGroup g = a.groups[tile.grp & ~FK_TILE_SAME];
+        // the tile's molecule: its blocks of D, D_sh, X_J, X_K and shells
+        const int mol = g.mol;
+        const int n = a.mol_nbf[mol], ns = a.mol_nsh[mol];
+        const int *__restrict shbf = a.sh_bf + a.mol_sh0[mol];
+        const double *__restrict Ds = a.Ds + a.mol_base[mol];
+        const double *__restrict Dsh = a.Dsh + a.mol_shbase[mol];
+        const long long xoff = (long long)(blockIdx.x % FK_XCD_COPIES) * a.xcopy + a.mol_base[mol];
+        double *XJ = a.XJ + xoff;
+        double *XK = a.XK + xoff;
         const FkBraBlock blk = a.blocks[tile.blk];
         const bool inrange = lane < tile.ket_count;
         const int pos = tile.ket_begin + (inrange ? lane : 0);
         const int r = pos - g.begin;
         const KetInfo Kt = load_ket(a, pos);
         const int sc = Kt.sc, sd = Kt.sd;
-        const int oc = a.sh_bf[sc], od = a.sh_bf[sd];
+        const int oc = shbf[sc], od = shbf[sd];
         const int sa = a.pair_sa[a.blk_bra[blk.first]];
-        const int oa = a.sh_bf[sa];
+        const int oa = shbf[sa];
         // D_cd is used with every bra of the block
         double dcd[BLK ? NC * ND : 1];
         if constexpr (BLK) {
 #pragma unroll
             for (int ic = 0; ic < NC; ++ic)
 #pragma unroll
-                for (int id = 0; id < ND; ++id) dcd[ic * ND + id] = a.Ds[(size_t)(oc + ic) * n + od + id];
+                for (int id = 0; id < ND; ++id) dcd[ic * ND + id] = Ds[(size_t)(oc + ic) * n + od + id];
         }
         // block sums: X_K[a, c], X_K[a, d], X_J[c, d]
         double kac[NA * NC], kad[NA * ND], jcd[NC * ND];
@@ -251,7 +259,7 @@ __global__ void __launch_bounds__(FK_BLOCK) k_jk_lpq(FkJKArgs a)
             // and density screen for this (bra, ket)
             bool active = inrange && (!same || pos <= bpos) && (a.tau <= 0 || B.G * Kt.G >= a.tau) &&
                           prec_side<R>(B.G * Kt.G, a.tau_hi);
-            if (a.dscreen) active = active && (B.G * Kt.G * dmax6(a.Dsh, ns, sa, sb, sc, sd) >= a.tau);
+            if (a.dscreen) active = active && (B.G * Kt.G * dmax6(Dsh, ns, sa, sb, sc, sd) >= a.tau);
             const unsigned long long mask = __ballot(active);
             if (mask == 0ull) continue;
             const int nact = __popcll(mask);
@@ -274,7 +282,7 @@ __global__ void __launch_bounds__(FK_BLOCK) k_jk_lpq(FkJKArgs a)
             }
             const bool diag = same && pos == bpos;
             const double fac = (sa == sb ? 0.5 : 1.0) * (sc == sd ? 0.5 : 1.0) * (diag ? 0.5 : 1.0);
-            const int ob = a.sh_bf[sb];
+            const int ob = shbf[sb];
             double jab[NA * NB];
 #pragma unroll
             for (int o = 0; o < NA * NB; ++o) jab[o] = 0.0;
@@ -286,11 +294,11 @@ __global__ void __launch_bounds__(FK_BLOCK) k_jk_lpq(FkJKArgs a)
 #pragma unroll
                 for (int ib = 0; ib < NB; ++ib) {
 #pragma unroll
-                    for (int ia = 0; ia < NA; ++ia) dab[ia * NB + ib] = a.Ds[(size_t)(oa + ia) * n + ob + ib];
+                    for (int ia = 0; ia < NA; ++ia) dab[ia * NB + ib] = Ds[(size_t)(oa + ia) * n + ob + ib];
 #pragma unroll
-                    for (int ic = 0; ic < NC; ++ic) dbc[ib * NC + ic] = a.Ds[(size_t)(ob + ib) * n + oc + ic];
+                    for (int ic = 0; ic < NC; ++ic) dbc[ib * NC + ic] = Ds[(size_t)(ob + ib) * n + oc + ic];
 #pragma unroll
-                    for (int id = 0; id < ND; ++id) dbd[ib * ND + id] = a.Ds[(size_t)(ob + ib) * n + od + id];
+                    for (int id = 0; id < ND; ++id) dbd[ib * ND + id] = Ds[(size_t)(ob + ib) * n + od + id];
                 }
                 // X_J[a, b] partial (reduced over the wave below); X_J[c, d] block sum
 #pragma unroll
@@ -323,8 +331,8 @@ __global__ void __launch_bounds__(FK_BLOCK) k_jk_lpq(FkJKArgs a)
                         for (int ia = 0; ia < NA; ++ia)
 #pragma unroll
                             for (int id = 0; id < ND; ++id)
-                                s += acc[((ia * NB + ib) * NC + ic) * ND + id] * a.Ds[(size_t)(oa + ia) * n + od + id];
-                        atomic_add(&a.XK[(size_t)(ob + ib) * n + oc + ic], s);
+                                s += acc[((ia * NB + ib) * NC + ic) * ND + id] * Ds[(size_t)(oa + ia) * n + od + id];
+                        atomic_add(&XK[(size_t)(ob + ib) * n + oc + ic], s);
                     }
 #pragma unroll
                     for (int id = 0; id < ND; ++id) {
@@ -333,8 +341,8 @@ __global__ void __launch_bounds__(FK_BLOCK) k_jk_lpq(FkJKArgs a)
                         for (int ia = 0; ia < NA; ++ia)
 #pragma unroll
                             for (int ic = 0; ic < NC; ++ic)
-                                s += acc[((ia * NB + ib) * NC + ic) * ND + id] * a.Ds[(size_t)(oa + ia) * n + oc + ic];
-                        atomic_add(&a.XK[(size_t)(ob + ib) * n + od + id], s);
+                                s += acc[((ia * NB + ib) * NC + ic) * ND + id] * Ds[(size_t)(oa + ia) * n + oc + ic];
+                        atomic_add(&XK[(size_t)(ob + ib) * n + od + id], s);
                     }
                 }
             }
@@ -347,14 +355,14 @@ __global__ void __launch_bounds__(FK_BLOCK) k_jk_lpq(FkJKArgs a)
                 for (int ab = 0; ab < NA * NB; ++ab)
 #pragma unroll
                     for (int cd = 0; cd < NC * ND; ++cd)
-                        jab[ab] += acc[ab * NC * ND + cd] * a.Ds[(size_t)(oc + cd / ND) * n + od + cd % ND];
+                        jab[ab] += acc[ab * NC * ND + cd] * Ds[(size_t)(oc + cd / ND) * n + od + cd % ND];
 #pragma unroll
                 for (int cd = 0; cd < NC * ND; ++cd) {
                     double s = 0.0;
 #pragma unroll
                     for (int ab = 0; ab < NA * NB; ++ab)
-                        s += acc[ab * NC * ND + cd] * a.Ds[(size_t)(oa + ab / NB) * n + ob + ab % NB];
-                    atomic_add(&a.XJ[(size_t)(oc + cd / ND) * n + od + cd % ND], 2.0 * s);
+                        s += acc[ab * NC * ND + cd] * Ds[(size_t)(oa + ab / NB) * n + ob + ab % NB];
+                    atomic_add(&XJ[(size_t)(oc + cd / ND) * n + od + cd % ND], 2.0 * s);
                 }
 #pragma unroll
                 for (int ia = 0; ia < NA; ++ia) {
@@ -365,8 +373,8 @@ __global__ void __launch_bounds__(FK_BLOCK) k_jk_lpq(FkJKArgs a)
                         for (int ib = 0; ib < NB; ++ib)
 #pragma unroll
                             for (int id = 0; id < ND; ++id)
-                                s += acc[((ia * NB + ib) * NC + ic) * ND + id] * a.Ds[(size_t)(ob + ib) * n + od + id];
-                        atomic_add(&a.XK[(size_t)(oa + ia) * n + oc + ic], s);
+                                s += acc[((ia * NB + ib) * NC + ic) * ND + id] * Ds[(size_t)(ob + ib) * n + od + id];
+                        atomic_add(&XK[(size_t)(oa + ia) * n + oc + ic], s);
                     }
 #pragma unroll
                     for (int id = 0; id < ND; ++id) {
@@ -375,8 +383,8 @@ __global__ void __launch_bounds__(FK_BLOCK) k_jk_lpq(FkJKArgs a)
                         for (int ib = 0; ib < NB; ++ib)
 #pragma unroll
                             for (int ic = 0; ic < NC; ++ic)
-                                s += acc[((ia * NB + ib) * NC + ic) * ND + id] * a.Ds[(size_t)(ob + ib) * n + oc + ic];
-                        atomic_add(&a.XK[(size_t)(oa + ia) * n + od + id], s);
+                                s += acc[((ia * NB + ib) * NC + ic) * ND + id] * Ds[(size_t)(ob + ib) * n + oc + ic];
+                        atomic_add(&XK[(size_t)(oa + ia) * n + od + id], s);
                     }
                 }
 #pragma unroll
@@ -388,8 +396,8 @@ __global__ void __launch_bounds__(FK_BLOCK) k_jk_lpq(FkJKArgs a)
                         for (int ia = 0; ia < NA; ++ia)
 #pragma unroll
                             for (int id = 0; id < ND; ++id)
-                                s += acc[((ia * NB + ib) * NC + ic) * ND + id] * a.Ds[(size_t)(oa + ia) * n + od + id];
-                        atomic_add(&a.XK[(size_t)(ob + ib) * n + oc + ic], s);
+                                s += acc[((ia * NB + ib) * NC + ic) * ND + id] * Ds[(size_t)(oa + ia) * n + od + id];
+                        atomic_add(&XK[(size_t)(ob + ib) * n + oc + ic], s);
                     }
 #pragma unroll
                     for (int id = 0; id < ND; ++id) {
@@ -398,8 +406,8 @@ __global__ void __launch_bounds__(FK_BLOCK) k_jk_lpq(FkJKArgs a)
                         for (int ia = 0; ia < NA; ++ia)
 #pragma unroll
                             for (int ic = 0; ic < NC; ++ic)
-                                s += acc[((ia * NB + ib) * NC + ic) * ND + id] * a.Ds[(size_t)(oa + ia) * n + oc + ic];
-                        atomic_add(&a.XK[(size_t)(ob + ib) * n + od + id], s);
+                                s += acc[((ia * NB + ib) * NC + ic) * ND + id] * Ds[(size_t)(oa + ia) * n + oc + ic];
+                        atomic_add(&XK[(size_t)(ob + ib) * n + od + id], s);
                     }
                 }
             }
@@ -407,22 +415,22 @@ __global__ void __launch_bounds__(FK_BLOCK) k_jk_lpq(FkJKArgs a)
 #pragma unroll
             for (int ab = 0; ab < NA * NB; ++ab) {
                 const double s = wave_sum(jab[ab]);
-                if (lane == 0) atomic_add(&a.XJ[(size_t)(oa + ab / NB) * n + ob + ab % NB], 2.0 * s);
+                if (lane == 0) atomic_add(&XJ[(size_t)(oa + ab / NB) * n + ob + ab % NB], 2.0 * s);
             }
         }
         if (BLK && any) {
 #pragma unroll
             for (int ia = 0; ia < NA; ++ia) {
 #pragma unroll
-                for (int ic = 0; ic < NC; ++ic) atomic_add(&a.XK[(size_t)(oa + ia) * n + oc + ic], kac[ia * NC + ic]);
+                for (int ic = 0; ic < NC; ++ic) atomic_add(&XK[(size_t)(oa + ia) * n + oc + ic], kac[ia * NC + ic]);
 #pragma unroll
-                for (int id = 0; id < ND; ++id) atomic_add(&a.XK[(size_t)(oa + ia) * n + od + id], kad[ia * ND + id]);
+                for (int id = 0; id < ND; ++id) atomic_add(&XK[(size_t)(oa + ia) * n + od + id], kad[ia * ND + id]);
             }
 #pragma unroll
             for (int ic = 0; ic < NC; ++ic)
 #pragma unroll
                 for (int id = 0; id < ND; ++id)
-                    atomic_add(&a.XJ[(size_t)(oc + ic) * n + od + id], 2.0 * jcd[ic * ND + id]);
+                    atomic_add(&XJ[(size_t)(oc + ic) * n + od + id], 2.0 * jcd[ic * ND + id]);
         }
     }
     if (lane == 0 && cq) {
@@ -476,7 +484,6 @@ __global__ void __launch_bounds__(FK_BLOCK) k_jk_tpq(FkJKArgs a)
     double *s_team = s_bra + a.bra_slot;     // [QPW][NV] team sums
     double *s_jab = s_team + QPW * NV;       // [block bra][NA * NB] wave sums of X_J[a, b]
     const int nwt = gridDim.x * FK_WAVES;
-    const int n = a.nbf, ns = a.nshell;
     const int slot = lane / TS, comp = lane % TS;
     const bool lane_ok = slot < QPW;
     const int ia = (MODE == 1) ? comp : comp / NB;
@@ -490,9 +497,18 @@ __global__ void __launch_bounds__(FK_BLOCK) k_jk_tpq(FkJKArgs a)
         const FkTile tile = a.tiles[t];
         const bool same = (tile.grp & FK_TILE_SAME) != 0;
         const FkGroup g = a.groups[tile.grp & ~FK_TILE_SAME];
+        // the tile's molecule: its blocks of D, D_sh, X_J, X_K and shells
+        const int mol = g.mol;
+        const int n = a.mol_nbf[mol], ns = a.mol_nsh[mol];
+        const int *__restrict shbf = a.sh_bf + a.mol_sh0[mol];
+        const double *__restrict Ds = a.Ds + a.mol_base[mol];
+        const double *__restrict Dsh = a.Dsh + a.mol_shbase[mol];
+        const long long xoff = (long long)(blockIdx.x % FK_XCD_COPIES) * a.xcopy + a.mol_base[mol];
+        double *XJ = a.XJ + xoff;
+        double *XK = a.XK + xoff;
         const FkBraBlock blk = a.blocks[tile.blk];
         const int sa = a.pair_sa[a.blk_bra[blk.first]];
-        const int oa = a.sh_bf[sa];
+        const int oa = shbf[sa];
         const size_t ra = (size_t)(oa + ia) * n;
         wave_sync_lds();
         for (int x = lane; x < blk.count * NA * NB; x += 64) s_jab[x] = 0.0;
@@ -504,7 +520,7 @@ __global__ void __launch_bounds__(FK_BLOCK) k_jk_tpq(FkJKArgs a)
             const int r = pos - g.begin;
             const KetInfo Kt = load_ket(a, pos);
             const int sc = Kt.sc, sd = Kt.sd;
-            const int oc = a.sh_bf[sc], od = a.sh_bf[sd];
+            const int oc = shbf[sc], od = shbf[sd];
             double kac[NC], kad[ND], jcd[NC * ND];
 #pragma unroll
             for (int ic = 0; ic < NC; ++ic) kac[ic] = 0.0;
@@ -521,7 +537,7 @@ __global__ void __launch_bounds__(FK_BLOCK) k_jk_tpq(FkJKArgs a)
                 const int sb = B.sb;
                 bool active = tin && (!same || pos <= bpos) && (a.tau <= 0 || B.G * Kt.G >= a.tau) &&
                               prec_side<R>(B.G * Kt.G, a.tau_hi);
-                if (a.dscreen) active = active && (B.G * Kt.G * dmax6(a.Dsh, ns, sa, sb, sc, sd) >= a.tau);
+                if (a.dscreen) active = active && (B.G * Kt.G * dmax6(Dsh, ns, sa, sb, sc, sd) >= a.tau);
                 const unsigned long long mask = __ballot(active);
                 if (mask == 0ull) continue;
                 const int nact = __popcll(mask) / TS;
@@ -542,7 +558,7 @@ __global__ void __launch_bounds__(FK_BLOCK) k_jk_tpq(FkJKArgs a)
                 }
                 const bool diag = same && pos == bpos;
                 const double fac = (sa == sb ? 0.5 : 1.0) * (sc == sd ? 0.5 : 1.0) * (diag ? 0.5 : 1.0);
-                const int ob = a.sh_bf[sb];
+                const int ob = shbf[sb];
                 // team sums of X_K[b, c] and X_K[b, d] for this bra
                 if (lane_ok)
                     for (int v = comp; v < NV; v += TS) tsum[v] = 0.0;
@@ -553,7 +569,7 @@ __global__ void __launch_bounds__(FK_BLOCK) k_jk_tpq(FkJKArgs a)
                     for (int jj = 0; jj < NBL; ++jj) {
                         const int ib = (MODE == 1) ? jj : ib0;
                         const size_t rb = (size_t)(ob + ib) * n;
-                        const double dab = a.Ds[ra + ob + ib];
+                        const double dab = Ds[ra + ob + ib];
                         double sj = 0.0;
 #pragma unroll
                         for (int ic = 0; ic < NC; ++ic) {
@@ -561,11 +577,11 @@ __global__ void __launch_bounds__(FK_BLOCK) k_jk_tpq(FkJKArgs a)
 #pragma unroll
                             for (int id = 0; id < ND; ++id) {
                                 const double v = fac * acc[(jj * NC + ic) * ND + id];
-                                sj += v * a.Ds[(size_t)(oc + ic) * n + od + id];
+                                sj += v * Ds[(size_t)(oc + ic) * n + od + id];
                                 jcd[ic * ND + id] += v * dab;
-                                kac[ic] += v * a.Ds[rb + od + id];
-                                kad[id] += v * a.Ds[rb + oc + ic];
-                                kbc += v * a.Ds[ra + od + id];
+                                kac[ic] += v * Ds[rb + od + id];
+                                kad[id] += v * Ds[rb + oc + ic];
+                                kbc += v * Ds[ra + od + id];
                             }
                             lds_add(&tsum[ib * NC + ic], kbc);
                         }
@@ -573,7 +589,7 @@ __global__ void __launch_bounds__(FK_BLOCK) k_jk_tpq(FkJKArgs a)
                         for (int id = 0; id < ND; ++id) {
                             double kbd = 0.0;
 #pragma unroll
-                            for (int ic = 0; ic < NC; ++ic) kbd += fac * acc[(jj * NC + ic) * ND + id] * a.Ds[ra + oc + ic];
+                            for (int ic = 0; ic < NC; ++ic) kbd += fac * acc[(jj * NC + ic) * ND + id] * Ds[ra + oc + ic];
                             lds_add(&tsum[NB * NC + ib * ND + id], kbd);
                         }
                         lds_add(&s_jab[jb * NA * NB + ia * NB + ib], sj);
@@ -585,7 +601,7 @@ __global__ void __launch_bounds__(FK_BLOCK) k_jk_tpq(FkJKArgs a)
                         size_t dst;
                         if (v < NB * NC) dst = (size_t)(ob + v / NC) * n + oc + v % NC;
                         else dst = (size_t)(ob + (v - NB * NC) / ND) * n + od + (v - NB * NC) % ND;
-                        atomic_add(&a.XK[dst], tsum[v]);
+                        atomic_add(&XK[dst], tsum[v]);
                     }
                 wave_sync_lds();
             }
@@ -596,24 +612,24 @@ __global__ void __launch_bounds__(FK_BLOCK) k_jk_tpq(FkJKArgs a)
             wave_sync_lds();
             if (any) {
 #pragma unroll
-                for (int ic = 0; ic < NC; ++ic) atomic_add(&a.XK[ra + oc + ic], kac[ic]);
+                for (int ic = 0; ic < NC; ++ic) atomic_add(&XK[ra + oc + ic], kac[ic]);
 #pragma unroll
-                for (int id = 0; id < ND; ++id) atomic_add(&a.XK[ra + od + id], kad[id]);
+                for (int id = 0; id < ND; ++id) atomic_add(&XK[ra + od + id], kad[id]);
 #pragma unroll
                 for (int o = 0; o < NC * ND; ++o) lds_add(&tsum[o], jcd[o]);
             }
             wave_sync_lds();
             if (any)
                 for (int v = comp; v < NC * ND; v += TS)
-                    atomic_add(&a.XJ[(size_t)(oc + v / ND) * n + od + v % ND], 2.0 * tsum[v]);
+                    atomic_add(&XJ[(size_t)(oc + v / ND) * n + od + v % ND], 2.0 * tsum[v]);
             wave_sync_lds();
         }
         // X_J[a, b] of every bra of the block, summed over the tile's kets
         for (int x = lane; x < blk.count * NA * NB; x += 64) {
             const int jb = x / (NA * NB), ab = x % (NA * NB);
-            const int ob = a.sh_bf[a.pair_sb[a.blk_bra[blk.first + jb]]];
+            const int ob = shbf[a.pair_sb[a.blk_bra[blk.first + jb]]];
             const double v = s_jab[x];
-            if (v != 0.0) atomic_add(&a.XJ[(size_t)(oa + ab / NB) * n + ob + ab % NB], 2.0 * v);
+            if (v != 0.0) atomic_add(&XJ[(size_t)(oa + ab / NB) * n + ob + ab % NB], 2.0 * v);
         }
     }
     if (lane == 0 && cq) {
@@ -641,7 +657,6 @@ __global__ void __launch_bounds__(FK_BLOCK) k_jk_wpq(FkJKArgs a)
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     double *s_bra = s_dyn + rys_lds_size(Q::NR) + wave * a.bra_slot;
     const int nwt = gridDim.x * FK_WAVES;
-    const int n = a.nbf, ns = a.nshell;
     unsigned long long cq = 0, cp = 0;
 
     int iax[ITEMS][3], ibx[ITEMS][3], iab[ITEMS];
@@ -663,15 +678,24 @@ __global__ void __launch_bounds__(FK_BLOCK) k_jk_wpq(FkJKArgs a)
         const int bra = a.blk_bra[a.blocks[tile.blk].first];
         const bool same = (tile.grp & FK_TILE_SAME) != 0;
         const FkGroup g = a.groups[tile.grp & ~FK_TILE_SAME];
+        // the tile's molecule: its blocks of D, D_sh, X_J, X_K and shells
+        const int mol = g.mol;
+        const int n = a.mol_nbf[mol], ns = a.mol_nsh[mol];
+        const int *__restrict shbf = a.sh_bf + a.mol_sh0[mol];
+        const double *__restrict Ds = a.Ds + a.mol_base[mol];
+        const double *__restrict Dsh = a.Dsh + a.mol_shbase[mol];
+        const long long xoff = (long long)(blockIdx.x % FK_XCD_COPIES) * a.xcopy + a.mol_base[mol];
+        double *XJ = a.XJ + xoff;
+        double *XK = a.XK + xoff;
         const BraInfo B = load_bra(a, bra);
         const int sa = B.sa, sb = B.sb;
-        const int oa = a.sh_bf[sa], ob = a.sh_bf[sb];
+        const int oa = shbf[sa], ob = shbf[sb];
         unsigned long long live;
         {
             const bool in = lane < tile.ket_count;
             const KetInfo K0 = load_ket(a, tile.ket_begin + (in ? lane : 0));
             bool ok = in;
-            if (a.dscreen) ok = ok && (B.G * K0.G * dmax6(a.Dsh, ns, sa, sb, K0.sc, K0.sd) >= a.tau);
+            if (a.dscreen) ok = ok && (B.G * K0.G * dmax6(Dsh, ns, sa, sb, K0.sc, K0.sd) >= a.tau);
             live = __ballot(ok);
         }
         if (live == 0ull) continue;
@@ -701,7 +725,7 @@ __global__ void __launch_bounds__(FK_BLOCK) k_jk_wpq(FkJKArgs a)
             }
             const bool diag = same && a.ket_list[pos] == bra;
             const double fac = (sa == sb ? 0.5 : 1.0) * (sc == sd ? 0.5 : 1.0) * (diag ? 0.5 : 1.0);
-            const int oc = a.sh_bf[sc], od = a.sh_bf[sd];
+            const int oc = shbf[sc], od = shbf[sd];
             double jcd[NCD];
 #pragma unroll
             for (int o = 0; o < NCD; ++o) jcd[o] = 0.0;
@@ -712,43 +736,43 @@ __global__ void __launch_bounds__(FK_BLOCK) k_jk_wpq(FkJKArgs a)
                 double *v = acc[it];
 #pragma unroll
                 for (int o = 0; o < NCD; ++o) v[o] *= fac;
-                const double dab = a.Ds[(size_t)(oa + ia) * n + ob + ib];
+                const double dab = Ds[(size_t)(oa + ia) * n + ob + ib];
                 double sj = 0.0;
 #pragma unroll
                 for (int ic = 0; ic < NC; ++ic)
 #pragma unroll
                     for (int id = 0; id < ND; ++id) {
-                        sj += v[ic * ND + id] * a.Ds[(size_t)(oc + ic) * n + od + id];
+                        sj += v[ic * ND + id] * Ds[(size_t)(oc + ic) * n + od + id];
                         jcd[ic * ND + id] += v[ic * ND + id] * dab;
                     }
-                atomic_add(&a.XJ[(size_t)(oa + ia) * n + ob + ib], 2.0 * sj);
+                atomic_add(&XJ[(size_t)(oa + ia) * n + ob + ib], 2.0 * sj);
 #pragma unroll
                 for (int ic = 0; ic < NC; ++ic) {
                     double s1 = 0.0, s2 = 0.0;
 #pragma unroll
                     for (int id = 0; id < ND; ++id) {
-                        s1 += v[ic * ND + id] * a.Ds[(size_t)(ob + ib) * n + od + id];
-                        s2 += v[ic * ND + id] * a.Ds[(size_t)(oa + ia) * n + od + id];
+                        s1 += v[ic * ND + id] * Ds[(size_t)(ob + ib) * n + od + id];
+                        s2 += v[ic * ND + id] * Ds[(size_t)(oa + ia) * n + od + id];
                     }
-                    atomic_add(&a.XK[(size_t)(oa + ia) * n + oc + ic], s1);
-                    atomic_add(&a.XK[(size_t)(ob + ib) * n + oc + ic], s2);
+                    atomic_add(&XK[(size_t)(oa + ia) * n + oc + ic], s1);
+                    atomic_add(&XK[(size_t)(ob + ib) * n + oc + ic], s2);
                 }
 #pragma unroll
                 for (int id = 0; id < ND; ++id) {
                     double s1 = 0.0, s2 = 0.0;
 #pragma unroll
                     for (int ic = 0; ic < NC; ++ic) {
-                        s1 += v[ic * ND + id] * a.Ds[(size_t)(ob + ib) * n + oc + ic];
-                        s2 += v[ic * ND + id] * a.Ds[(size_t)(oa + ia) * n + oc + ic];
+                        s1 += v[ic * ND + id] * Ds[(size_t)(ob + ib) * n + oc + ic];
+                        s2 += v[ic * ND + id] * Ds[(size_t)(oa + ia) * n + oc + ic];
                     }
-                    atomic_add(&a.XK[(size_t)(oa + ia) * n + od + id], s1);
-                    atomic_add(&a.XK[(size_t)(ob + ib) * n + od + id], s2);
+                    atomic_add(&XK[(size_t)(oa + ia) * n + od + id], s1);
+                    atomic_add(&XK[(size_t)(ob + ib) * n + od + id], s2);
                 }
             }
 #pragma unroll
             for (int o = 0; o < NCD; ++o) {
                 const double s = wave_sum(jcd[o]);
-                if (lane == 0) atomic_add(&a.XJ[(size_t)(oc + o / ND) * n + od + o % ND], 2.0 * s);
+                if (lane == 0) atomic_add(&XJ[(size_t)(oc + o / ND) * n + od + o % ND], 2.0 * s);
             }
         }
     }
@@ -1065,36 +1089,66 @@ __global__ void k_fill(double *p, long long n)
     if (i < n) p[i] = 0.0;
 }
 
-__global__ void k_prep_ds(const double *__restrict D, const double *__restrict s, int n, double *__restrict Ds)
+// molecule m with base[m] <= i < base[m + 1] (base has nmol + 1 entries)
+__device__ __forceinline__ int find_mol(const long long *__restrict base, int nmol, long long i)
 {
-    long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= (long long)n * n) return;
-    const int r = (int)(i / n), c = (int)(i % n);
-    Ds[i] = s[r] * s[c] * D[i];
+    int lo = 0, hi = nmol;
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (base[mid] <= i) lo = mid; else hi = mid;
+    }
+    return lo;
 }
 
-__global__ void k_prep_dsh(const double *__restrict D, const int *__restrict sh_bf, int ns, int n,
-                           double *__restrict Dsh)
+// Ds = s_r s_c D over every molecule's block
+__global__ void k_prep_ds(const double *__restrict D, const double *__restrict s, FkMolArgs m, double *__restrict Ds)
 {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= ns * ns) return;
-    const int A = i / ns, B = i % ns;
-    double m = 0.0;
-    for (int r = sh_bf[A]; r < sh_bf[A + 1]; ++r)
-        for (int c = sh_bf[B]; c < sh_bf[B + 1]; ++c) m = fmax(m, fabs(D[(size_t)r * n + c]));
-    Dsh[i] = m;
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= m.nmat) return;
+    const int k = find_mol(m.mol_base, m.nmol, i);
+    const long long loc = i - m.mol_base[k];
+    const int n = m.mol_nbf[k], f0 = m.mol_bf0[k];
+    const int r = (int)(loc / n), c = (int)(loc % n);
+    Ds[i] = s[f0 + r] * s[f0 + c] * D[i];
 }
 
-__global__ void k_finalize(const double *__restrict XJ, const double *__restrict XK, const double *__restrict s,
-                           int n, double *__restrict J, double *__restrict K)
+// D_sh[A, B] = max |D| over the shell block, per molecule
+__global__ void k_prep_dsh(const double *__restrict D, FkMolArgs m, double *__restrict Dsh)
 {
-    long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= (long long)n * n) return;
-    const int r = (int)(i / n), c = (int)(i % n);
-    const long long t = (long long)c * n + r;
-    const double f = s[r] * s[c];
-    J[i] = f * (XJ[i] + XJ[t]);
-    K[i] = f * (XK[i] + XK[t]);
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= m.nshmat) return;
+    const int k = find_mol(m.mol_shbase, m.nmol, i);
+    const long long loc = i - m.mol_shbase[k];
+    const int ns = m.mol_nsh[k], n = m.mol_nbf[k];
+    const int A = m.mol_sh0[k] + (int)(loc / ns), B = m.mol_sh0[k] + (int)(loc % ns);
+    const double *Dm = D + m.mol_base[k];
+    double v = 0.0;
+    for (int r = m.sh_lbf[A]; r < m.sh_lend[A]; ++r)
+        for (int c = m.sh_lbf[B]; c < m.sh_lend[B]; ++c) v = fmax(v, fabs(Dm[(size_t)r * n + c]));
+    Dsh[i] = v;
+}
+
+// J = s_r s_c (X_J + X_J^T), K likewise, within each molecule's block
+__global__ void k_finalize(const double *__restrict XJ, const double *__restrict XK, long long xcopy,
+                           const double *__restrict s, FkMolArgs m, double *__restrict J, double *__restrict K)
+{
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= m.nmat) return;
+    const int k = find_mol(m.mol_base, m.nmol, i);
+    const long long loc = i - m.mol_base[k];
+    const int n = m.mol_nbf[k], f0 = m.mol_bf0[k];
+    const int r = (int)(loc / n), c = (int)(loc % n);
+    const long long t = m.mol_base[k] + (long long)c * n + r;
+    const double f = s[f0 + r] * s[f0 + c];
+    double sj = 0.0, sk = 0.0;
+#pragma unroll
+    for (int x = 0; x < FK_XCD_COPIES; ++x) {
+        const long long o = (long long)x * xcopy;
+        sj += XJ[o + i] + XJ[o + t];
+        sk += XK[o + i] + XK[o + t];
+    }
+    J[i] = f * sj;
+    K[i] = f * sk;
 }
 
 
@@ -1172,23 +1226,23 @@ int fk_kernels_max_blocks(int P, int Q, int dyn_lds_bytes, int *blocks_per_cu)
     return 0;
 }
 
-int fk_kernels_launch_prep(const double *D, const int *sh_bf, const double *bf_scale, int nshell, int nbf,
-                           double *Ds, double *Dsh, void *stream)
+int fk_kernels_launch_prep(const double *D, const double *bf_scale, const FkMolArgs *m, double *Ds, double *Dsh,
+                           void *stream)
 {
     hipStream_t st = (hipStream_t)stream;
-    const long long nn = (long long)nbf * nbf;
-    hipLaunchKernelGGL(k_prep_ds, dim3((unsigned)((nn + 255) / 256)), dim3(256), 0, st, D, bf_scale, nbf, Ds);
-    const int ss = nshell * nshell;
-    hipLaunchKernelGGL(k_prep_dsh, dim3((ss + 255) / 256), dim3(256), 0, st, D, sh_bf, nshell, nbf, Dsh);
+    if (m->nmat > 0)
+        hipLaunchKernelGGL(k_prep_ds, dim3((unsigned)((m->nmat + 255) / 256)), dim3(256), 0, st, D, bf_scale, *m, Ds);
+    if (m->nshmat > 0)
+        hipLaunchKernelGGL(k_prep_dsh, dim3((unsigned)((m->nshmat + 255) / 256)), dim3(256), 0, st, D, *m, Dsh);
     return hipGetLastError() == hipSuccess ? 0 : -3;
 }
 
-int fk_kernels_launch_finalize(const double *XJ, const double *XK, const double *bf_scale, int nbf, double *J,
-                               double *K, void *stream)
+int fk_kernels_launch_finalize(const double *XJ, const double *XK, long long xcopy, const double *bf_scale,
+                               const FkMolArgs *m, double *J, double *K, void *stream)
 {
-    const long long nn = (long long)nbf * nbf;
-    hipLaunchKernelGGL(k_finalize, dim3((unsigned)((nn + 255) / 256)), dim3(256), 0, (hipStream_t)stream, XJ, XK,
-                       bf_scale, nbf, J, K);
+    if (m->nmat > 0)
+        hipLaunchKernelGGL(k_finalize, dim3((unsigned)((m->nmat + 255) / 256)), dim3(256), 0, (hipStream_t)stream, XJ,
+                           XK, xcopy, bf_scale, *m, J, K);
     return hipGetLastError() == hipSuccess ? 0 : -3;
 }
 

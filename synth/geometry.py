@@ -13,6 +13,12 @@ these stand in for its linear and globular benchmark systems):
   sphere, O by random sequential addition (min O-O 2.5 A), random orientation,
   min intermolecular atom-atom 1.2 A.
 * ``h2(R)``: the hydrogen molecule at bond length R bohr.
+* ``organic(seed)``: a random closed-shell organic molecule: 3-30 heavy atoms
+  (C/N/O with probabilities 0.7/0.15/0.15 under their valences 4/3/2) on a
+  random branched tree, with probability 0.4 a planar 5- or 6-membered carbon
+  ring first; heavy-heavy bonds U(1.30, 1.55) A, X-H U(1.00, 1.10) A; every
+  free valence capped with H; placements rejected if a non-bonded pair comes
+  closer than 1.7 A (heavy) or 1.2 A (involving H).
 
 Holds none of the method's arithmetic.
 """
@@ -141,6 +147,87 @@ def alkane(n: int, seed: int, jitter=0.02, rcc=1.54, rch=1.09):
     xyz = np.concatenate([C, np.array(H)])
     xyz = xyz + rng.uniform(-jitter, jitter, size=xyz.shape)
     return _mol([6] * n + [1] * len(H), xyz, name=f"C{n}H{2*n+2}")
+
+
+def _free_direction(rng, pos, center, bonded, tries=200):
+    """Unit vector from `center` that keeps the new atom away from the bonded
+    neighbours' directions (best of random candidates)."""
+    best, score = None, -1e9
+    dirs = [(pos[j] - center) / np.linalg.norm(pos[j] - center) for j in bonded]
+    for _ in range(tries):
+        d = _unit(rng)
+        s_ = min((-(d @ u) for u in dirs), default=1.0)
+        if s_ > score:
+            best, score = d, s_
+    return best
+
+
+def organic(seed: int, hmin=3, hmax=30):
+    rng = np.random.default_rng(seed)
+    valence = {6: 4, 7: 3, 8: 2}
+    for _attempt in range(200):
+        nh = int(rng.integers(hmin, hmax + 1))
+        Z, pos, nbrs = [], [], []
+        if rng.random() < 0.4 and nh >= 6:
+            ring = 6 if rng.random() < 0.5 else 5
+            r = 1.40 / (2 * math.sin(math.pi / ring))
+            for k in range(ring):
+                a = 2 * math.pi * k / ring
+                Z.append(6)
+                pos.append(np.array([r * math.cos(a), r * math.sin(a), 0.0]))
+                nbrs.append([(k - 1) % ring, (k + 1) % ring])
+        else:
+            Z.append(6)
+            pos.append(np.zeros(3))
+            nbrs.append([])
+        ok = True
+        while len(Z) < nh and ok:
+            el = int(rng.choice([6, 7, 8], p=[0.7, 0.15, 0.15]))
+            free = [i for i in range(len(Z)) if len(nbrs[i]) < valence[Z[i]] - (1 if len(Z) < nh - 1 else 0)]
+            if not free:
+                free = [i for i in range(len(Z)) if len(nbrs[i]) < valence[Z[i]]]
+            if not free:
+                ok = False
+                break
+            placed = False
+            for _t in range(30):
+                i = int(rng.choice(free))
+                d = _free_direction(rng, pos, pos[i], nbrs[i])
+                p_new = pos[i] + rng.uniform(1.30, 1.55) * d
+                if all(np.linalg.norm(p_new - pos[j]) >= 1.7 for j in range(len(Z)) if j != i):
+                    Z.append(el)
+                    pos.append(p_new)
+                    nbrs.append([i])
+                    nbrs[i].append(len(Z) - 1)
+                    placed = True
+                    break
+            if not placed:
+                ok = False
+        if not ok:
+            continue
+        heavy = len(Z)
+        H = []
+        for i in range(heavy):
+            for _ in range(valence[Z[i]] - len(nbrs[i])):
+                placed = False
+                for _t in range(60):
+                    d = _free_direction(rng, pos + H, pos[i], nbrs[i], tries=60)
+                    p_new = pos[i] + rng.uniform(1.00, 1.10) * d
+                    # H keeps 1.2 A from every atom other than its own
+                    if all(np.linalg.norm(p_new - q) >= 1.2 for j, q in enumerate(pos + H) if j != i):
+                        H.append(p_new)
+                        nbrs[i].append(len(pos) + len(H) - 1)
+                        placed = True
+                        break
+                if not placed:
+                    break
+            else:
+                continue
+            break
+        else:
+            xyz = np.array(pos + H)
+            return _mol(Z + [1] * len(H), xyz, name=f"org{seed}-h{heavy}")
+    raise RuntimeError("organic: no valid molecule after 200 attempts")
 
 
 def h2(R=1.4):

@@ -5,6 +5,10 @@ plain arrays that both the oracle and the library consume.
 * ``c20h42_631gs``  -- all-trans C20H42 with 0.02 A jitter, 6-31G*-type
   (384 Cartesian functions, s, p and d).
 * ``water64_ccpvdz`` -- 64 waters at 1.0 g/cm^3, cc-pVDZ-type (1600 functions).
+* ``batch(systems)`` -- several systems as one batch (atoms, shells and
+  primitives concatenated; ``atom_mol`` maps atoms to molecules).
+* ``organic_batch(n)`` -- n random organic molecules in the def2-TZVP-like
+  ``tzvp-type`` basis (s to f), the 256-molecule batched workload.
 * small test systems (H2, short alkanes, water dimers) in any basis.
 """
 from __future__ import annotations
@@ -87,3 +91,31 @@ def random_density(sys, seed):
     nocc = max(1, sys["nelec"] // 2)
     C = rng.normal(scale=0.3, size=(n, nocc))
     return 2.0 * C @ C.T
+
+
+def batch(systems):
+    """Concatenates systems into one batch: the flattened arrays of all
+    molecules plus ``atom_mol`` (molecule of each atom) and ``mols`` (the
+    input systems, for per-molecule checks)."""
+    natoms = np.cumsum([0] + [len(x["Z"]) for x in systems])
+    out = {
+        "name": f"batch of {len(systems)}",
+        "Z": np.concatenate([x["Z"] for x in systems]).astype(np.int32),
+        "xyz": np.concatenate([x["xyz"] for x in systems]),
+        "charge": int(sum(x["charge"] for x in systems)),
+        "nelec": int(sum(x["nelec"] for x in systems)),
+        "sh_atom": np.concatenate([x["sh_atom"] + natoms[i] for i, x in enumerate(systems)]).astype(np.int32),
+        "sh_l": np.concatenate([x["sh_l"] for x in systems]).astype(np.int32),
+        "sh_nprim": np.concatenate([x["sh_nprim"] for x in systems]).astype(np.int32),
+        "exps": np.concatenate([x["exps"] for x in systems]),
+        "coefs": np.concatenate([x["coefs"] for x in systems]),
+        "nbf": int(sum(x["nbf"] for x in systems)),
+        "nshell": int(sum(x["nshell"] for x in systems)),
+        "atom_mol": np.concatenate([np.full(len(x["Z"]), i, dtype=np.int32) for i, x in enumerate(systems)]),
+        "mols": list(systems),
+    }
+    return out
+
+
+def organic_batch(n=256, basis_name="tzvp-type", seed=SEED + 40):
+    return batch([make_system(_geom.organic(seed + i), basis_name) for i in range(n)])

@@ -210,3 +210,65 @@ def test_precision_split_c20h42(fk, torch, c2):
     for (a, b), bj, bk in zip(jp, Jb, Kb):
         assert np.max(np.abs(J[off[a]:off[a + 1], off[b]:off[b + 1]] - bj)) <= 1e-7
         assert np.max(np.abs(K[off[a]:off[a + 1], off[b]:off[b + 1]] - bk)) <= 1e-7
+
+
+def _small_batch():
+    spdf = _rand_sys(33, lmax=3, natom=3, kmax=2)
+    spdf["charge"] = 1
+    spdf["nelec"] -= 1
+    return wl.batch([wl.water4_sto3g(), wl.h2_sto3g(), wl.alkane_sys(2, "6-31gs-type"), spdf])
+
+
+@pytest.mark.parametrize("tau", [0.0, 1e-10])
+def test_batch_equals_single_molecules(fk, torch, tau):
+    """One batched build (all molecules in the same class launches) gives
+    each molecule the J and K of its own build and of the oracle."""
+    b = _small_batch()
+    Ds = [_rand_D(m["nbf"], 40 + i) for i, m in enumerate(b["mols"])]
+    c = fk.FockJK(0).set_system(b).set_molecules(b["atom_mol"]).build_quartets(tau=tau)
+    nbf, off = c.molecule_layout()
+    Dd = torch.tensor(np.concatenate([d.ravel() for d in Ds]), dtype=torch.float64, device="cuda")
+    J, K = c.build_jk(Dd, sync=True)
+    J, K = J.cpu().numpy(), K.cpu().numpy()
+    for i, (m, d) in enumerate(zip(b["mols"], Ds)):
+        n = m["nbf"]
+        Jb, Kb = J[off[i]:off[i + 1]].reshape(n, n), K[off[i]:off[i + 1]].reshape(n, n)
+        Js, Ks, _ = _gpu_jk(fk, torch, m, d, tau=tau)
+        assert np.max(np.abs(Jb - Js)) <= 1e-12 and np.max(np.abs(Kb - Ks)) <= 1e-12, i
+        if tau == 0:
+            Jo, Ko = oracle.jk(m, d)
+            scale = max(1.0, float(np.max(np.abs(Jo))))
+            assert np.max(np.abs(Jb - Jo)) <= 1e-10 * scale and np.max(np.abs(Kb - Ko)) <= 1e-10 * scale, i
+
+
+def test_build_in_hip_graph(fk, torch):
+    """A J/K build captured in a HIP graph (no host synchronisation, no
+    memset inside) and replayed several times, with eager work and
+    synchronisation between replays, equals the eager build every time."""
+    b = _small_batch()
+    c = fk.FockJK(0).set_system(b).set_molecules(b["atom_mol"]).build_quartets(tau=1e-10)
+    nmat = c.info()["nmat"]
+    Dd = torch.tensor(np.concatenate([_rand_D(m["nbf"], 60 + i).ravel() for i, m in enumerate(b["mols"])]),
+                      dtype=torch.float64, device="cuda")
+    J0, K0 = c.build_jk(Dd, sync=True)
+    J0, K0 = J0.clone(), K0.clone()
+    J = torch.zeros(nmat, dtype=torch.float64, device="cuda")
+    K = torch.zeros_like(J)
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        c.build_jk(Dd, J, K)  # warm-up on the capture stream
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        c.build_jk(Dd, J, K)
+    for rep in range(3):
+        J.fill_(0.0)
+        K.fill_(0.0)
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        assert torch.max(torch.abs(J - J0)).item() <= 1e-12, rep
+        assert torch.max(torch.abs(K - K0)).item() <= 1e-12, rep
+        c.build_jk(Dd, sync=True)  # eager work between replays

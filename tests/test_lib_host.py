@@ -195,3 +195,39 @@ def test_precision_split_lists(tau_fp32):
     c.check_indices()
     with pytest.raises(fk.FockJKError):
         fk.FockJK(device=-1).set_system(s).build_quartets(tau=0.0, tau_fp32=-1.0)
+
+
+def _small_batch():
+    spdf = _rand_sys(33, lmax=3, natom=3, kmax=2)
+    spdf["charge"] = 1
+    spdf["nelec"] -= 1
+    return wl.batch([wl.water4_sto3g(), wl.h2_sto3g(), wl.alkane_sys(2, "6-31gs-type"), spdf])
+
+
+@pytest.mark.parametrize("tau", [0.0, 1e-10])
+def test_batch_lists(tau):
+    """A batch holds each molecule's own quartets and nothing across
+    molecules: unique quartet count = sum of the separate counts; the block
+    layout follows the molecules' sizes; every kernel address stays inside
+    its molecule's blocks."""
+    b = _small_batch()
+    c = fk.FockJK(device=-1).set_system(b).set_molecules(b["atom_mol"]).build_quartets(tau=tau)
+    sep = sum(fk.FockJK(device=-1).set_system(m).build_quartets(tau=tau).info()["nquartet_schwarz"] for m in b["mols"])
+    assert c.info()["nquartet_schwarz"] == sep
+    nbf, off = c.molecule_layout()
+    assert list(nbf) == [m["nbf"] for m in b["mols"]]
+    assert off[-1] == c.info()["nmat"] == sum(m["nbf"] ** 2 for m in b["mols"])
+    c.check_indices()
+
+
+def test_batch_validation():
+    b = _small_batch()
+    c = fk.FockJK(device=-1).set_system(b)
+    bad = b["atom_mol"].copy()
+    bad[0], bad[-1] = bad[-1], bad[0]  # not non-decreasing
+    with pytest.raises(fk.FockJKError):
+        c.set_molecules(bad)
+    c.set_molecules(b["atom_mol"]).build_quartets(tau=0.0)
+    with pytest.raises(fk.FockJKError) as e:
+        c.one_electron()
+    assert e.value.code == fk.FK_ERR_UNSUPPORTED
