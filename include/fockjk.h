@@ -189,7 +189,12 @@ typedef struct {
     double e_tol;        /* |dE| threshold, default 1e-10 */
     double g_tol;        /* max |X (FDS - SDF) X| threshold, default 1e-8 */
     int    diis_n;       /* DIIS subspace size (0 or 1: no DIIS), default 8, at most 32 */
-    int    guess;        /* 0 = core Hamiltonian, 1 = density given in D_inout */
+    int    guess;        /* 0 = core Hamiltonian, 1 = density given in D_inout,
+                            2 = superposition of atomic densities (fk_sad_density),
+                            3 = learned (the model of fk_set_guess_model; falls
+                                back to 2, then 0, if the model is missing, an
+                                element is not covered, the prediction is not
+                                finite or its purification fails) */
     double lindep;       /* required accuracy of the orthogonaliser: max |Z S Z - I|
                             with Z = S^(-1/2) from the Newton-Schulz iteration;
                             fails with FK_ERR_ARG for an overlap matrix too
@@ -205,6 +210,8 @@ typedef struct {
     double total_seconds;
     double error;        /* max |X (FDS - SDF) X| at the last iteration */
     double delta_e;      /* energy change of the last iteration */
+    int    guess_used;   /* the guess the run started from (see fk_scf_opts.guess) */
+    double guess_seconds;/* wall time of the initial density */
 } fk_scf_result;
 
 /* Restricted closed-shell SCF (paper: "Hartree-Fock Energy Formulation"):
@@ -217,9 +224,105 @@ typedef struct {
  * host solves the small DIIS system.  Converged when |dE| < e_tol and the
  * error < g_tol.  D_inout (host, nbf x nbf, row-major) holds the guess when
  * opts->guess == 1 and the final density on return.  opts may be NULL
- * (defaults).  Returns FK_ERR_NOT_CONVERGED (with the result filled) if
- * max_iter is reached, or if the purification finds no gap. */
+ * (defaults).  max_iter = 0 returns the initial density in D_inout and
+ * performs no Fock build.  Returns FK_ERR_NOT_CONVERGED (with the result
+ * filled) if max_iter is reached, or if the purification finds no gap. */
 int fk_run_scf(fk_ctx *ctx, const fk_scf_opts *opts, fk_scf_result *result, double *D_inout);
+
+/* ---- initial densities (an extension: the paper's SCF starts from a
+ * conventional guess and has no learned part) ---------------------------- */
+
+/* Superposition of atomic densities: for each element, the atom alone (its
+ * shells, Z electrons) in a fractional-occupation SCF (F = h + J - K/2,
+ * D = sum n_i c_i c_i^T, aufbau over levels of orbitals within 1e-4 hartree,
+ * a partly filled level sharing its electrons equally, damped iteration
+ * from the core guess until max |dD| < 1e-10); the molecule's density is
+ * block diagonal over its atoms.  Host computation; D_out is a host
+ * nbf x nbf array.  Works on a context without a device. */
+int fk_sad_density(fk_ctx *ctx, double *D_out);
+
+/* Learned guess.  Atom pairs: every atom with itself and every pair closer
+ * than FK_GUESS_RCUT, in row-major order over (i <= j); the pair's first atom
+ * is the one of higher Z (lower index on ties).  Features of a pair
+ * (FK_GUESS_NFEAT floats): one-hot of the first atom's element over
+ * (H, C, N, O), one-hot of the second's, then FK_GUESS_NRBF Gaussians
+ * exp(-g (R - mu_k)^2), mu_k = k RCUT / (NRBF - 1), g = ((NRBF - 1) / RCUT)^2.
+ * Output of a pair: the block D[first's functions][second's functions] in the
+ * bond frame (e_z from the first atom to the second; e_x from the lab axis
+ * least aligned with e_z; the lab frame for an atom with itself), row-major,
+ * padded to FK_GUESS_NB x FK_GUESS_NB. */
+#define FK_GUESS_NB 15
+#define FK_GUESS_NOUT (FK_GUESS_NB * FK_GUESS_NB)
+#define FK_GUESS_NRBF 24
+#define FK_GUESS_NFEAT (8 + FK_GUESS_NRBF)
+#define FK_GUESS_RCUT 8.0      /* bohr */
+#define FK_MLP_MAX_LAYERS 4
+
+/* Multilayer perceptron: y = L_{n-1}(s(... s(L_0(x)))), L_k(x) = x W_k + b_k,
+ * s(z) = z / (1 + exp(-z)) (SiLU).  W_k is dims[k] x dims[k+1] row-major,
+ * b_k has dims[k+1] entries, FP32.  The pointers are host or device pointers
+ * as each function states; the caller owns them. */
+typedef struct {
+    int    nlayer;                        /* 1..FK_MLP_MAX_LAYERS */
+    int    dims[FK_MLP_MAX_LAYERS + 1];   /* each 1..4096 */
+    float *W[FK_MLP_MAX_LAYERS];
+    float *b[FK_MLP_MAX_LAYERS];
+} fk_mlp;
+
+/* Pairs of the current geometry: *npair always; features [npair][NFEAT] and
+ * shape[npair] = (functions of the first atom << 8) | functions of the
+ * second, if non-NULL (host arrays).  FK_ERR_UNSUPPORTED if an atom is not
+ * H, C, N or O or has more than FK_GUESS_NB functions. */
+int fk_guess_pairs(fk_ctx *ctx, int *npair, float *features, int *shape);
+
+/* Training targets: the pair blocks of density D (host nbf x nbf) in the
+ * bond frame, averaged over 8 rotations about the bond (an atom with itself:
+ * over the 60 rotations of the icosahedron, i.e. spherically), as
+ * Y[npair][FK_GUESS_NOUT] (host), zero-padded. */
+int fk_guess_targets(fk_ctx *ctx, const double *D, float *Y);
+
+/* Copies a network (host pointers; dims[0] = FK_GUESS_NFEAT, last dims =
+ * FK_GUESS_NOUT) to the context's device; used by fk_guess_predict and by
+ * fk_run_scf with guess = 3.  NULL removes it. */
+int fk_set_guess_model(fk_ctx *ctx, const fk_mlp *host_model);
+
+/* The network's prediction assembled into an nbf x nbf density before
+ * purification (host D_out): each pair's block rotated back with the
+ * Cartesian transforms of its atoms' shells and written to both triangles;
+ * an atom's own block symmetrised; pairs beyond the cutoff zero. */
+int fk_guess_predict(fk_ctx *ctx, double *D_out);
+
+/* ---- network primitives on the device (training and inference) ----------
+ * Device pointers, FP32, on `stream`; these return FK_ERR_ARG for invalid
+ * sizes and FK_ERR_HIP for a failed launch and need no context. */
+
+/* Floats of workspace fk_mlp_forward needs for n rows (activations kept for
+ * the backward pass). */
+int64_t fk_mlp_work_floats(const fk_mlp *m, int n);
+
+/* Y[n][dims[nlayer]] from X[n][dims[0]]; work as sized above. */
+int fk_mlp_forward(const fk_mlp *m, const float *X, int n, float *Y, float *work, void *stream);
+
+/* Gradients of a loss whose gradient in Y is dY (overwritten as scratch),
+ * after fk_mlp_forward on the same X and work: grad->W[k], grad->b[k]
+ * (device buffers of the weights' sizes) receive dL/dW_k, dL/db_k. */
+int fk_mlp_backward(const fk_mlp *m, const float *X, int n, float *work, float *dY, const fk_mlp *grad, void *stream);
+
+/* Masked mean squared error over rows of FK_GUESS_NB x FK_GUESS_NB blocks:
+ * entries (i, j) with i < shape[r] >> 8 and j < shape[r] & 255 count.
+ * loss[0] (device double) = sum (Y - T)^2 / count; dY = 2 (Y - T) / count
+ * on those entries, 0 elsewhere.  count = sum over rows of the two sizes'
+ * product (given by the caller).  part: fk_mlp_mse_scratch() doubles. */
+int fk_mlp_block_mse(const float *Y, const float *T, const int *shape, int n, double count, float *dY, double *part,
+                     double *loss, void *stream);
+int fk_mlp_mse_scratch(void);
+
+/* One Adam step (Kingma and Ba 2015) on every weight and bias:
+ * m1 = b1 m1 + (1 - b1) g, m2 = b2 m2 + (1 - b2) g^2,
+ * w -= lr (m1 / (1 - b1^step)) / (sqrt(m2 / (1 - b2^step)) + eps).
+ * grad, m1, m2 have the model's shapes (device); step >= 1. */
+int fk_mlp_adam(const fk_mlp *m, const fk_mlp *grad, const fk_mlp *m1, const fk_mlp *m2, int step, float lr, float b1,
+                float b2, float eps, void *stream);
 
 /* ---- diagnostics -------------------------------------------------------- */
 /* Raw contracted integrals (ab|cd) for nq shell quartets (shell indices

@@ -68,7 +68,18 @@ class ScfOpts(ctypes.Structure):
 class ScfResult(ctypes.Structure):
     _fields_ = [("energy", ctypes.c_double), ("e_nuc", ctypes.c_double), ("iterations", ctypes.c_int),
                 ("converged", ctypes.c_int), ("jk_seconds", ctypes.c_double), ("total_seconds", ctypes.c_double),
-                ("error", ctypes.c_double), ("delta_e", ctypes.c_double)]
+                ("error", ctypes.c_double), ("delta_e", ctypes.c_double), ("guess_used", ctypes.c_int),
+                ("guess_seconds", ctypes.c_double)]
+
+
+GUESS_CORE, GUESS_GIVEN, GUESS_SAD, GUESS_LEARNED = 0, 1, 2, 3
+GUESS_NB, GUESS_NOUT, GUESS_NRBF, GUESS_NFEAT, GUESS_RCUT = 15, 225, 24, 32, 8.0
+MLP_MAX_LAYERS = 4
+
+
+class Mlp(ctypes.Structure):
+    _fields_ = [("nlayer", ctypes.c_int), ("dims", ctypes.c_int * (MLP_MAX_LAYERS + 1)),
+                ("W", ctypes.c_void_p * MLP_MAX_LAYERS), ("b", ctypes.c_void_p * MLP_MAX_LAYERS)]
 
 
 _P, _I, _D, _U = ctypes.c_void_p, ctypes.c_int, ctypes.c_double, ctypes.c_uint
@@ -89,6 +100,18 @@ _sig = {
     "fk_check_indices": ([_P], _I),
     "fk_set_molecules": ([_P, _I, _P], _I),
     "fk_molecule_layout": ([_P, _P, _P], _I),
+    "fk_sad_density": ([_P, _P], _I),
+    "fk_guess_pairs": ([_P, _P, _P, _P], _I),
+    "fk_guess_targets": ([_P, _P, _P], _I),
+    "fk_set_guess_model": ([_P, ctypes.POINTER(Mlp)], _I),
+    "fk_guess_predict": ([_P, _P], _I),
+    "fk_mlp_work_floats": ([ctypes.POINTER(Mlp), _I], ctypes.c_int64),
+    "fk_mlp_forward": ([ctypes.POINTER(Mlp), _P, _I, _P, _P, _P], _I),
+    "fk_mlp_backward": ([ctypes.POINTER(Mlp), _P, _I, _P, _P, ctypes.POINTER(Mlp), _P], _I),
+    "fk_mlp_block_mse": ([_P, _P, _P, _I, _D, _P, _P, _P, _P], _I),
+    "fk_mlp_mse_scratch": ([], _I),
+    "fk_mlp_adam": ([ctypes.POINTER(Mlp), ctypes.POINTER(Mlp), ctypes.POINTER(Mlp), ctypes.POINTER(Mlp), _I,
+                     ctypes.c_float, ctypes.c_float, ctypes.c_float, ctypes.c_float, _P], _I),
 }
 EXPORTS = tuple(_sig)
 for _name, (_args, _res) in _sig.items():
@@ -240,10 +263,15 @@ class FockJK:
         self._check(_lib.fk_one_electron(self._ctx, _ptr(S), _ptr(T), _ptr(V), ctypes.byref(e)))
         return S, T, V, e.value
 
-    def run_scf(self, D0=None, max_iter=100, e_tol=1e-10, g_tol=1e-8, diis_n=8, lindep=1e-8):
+    def run_scf(self, D0=None, max_iter=100, e_tol=1e-10, g_tol=1e-8, diis_n=8, lindep=1e-8, guess=None):
+        """guess: GUESS_CORE (default without D0), GUESS_GIVEN (default with
+        D0), GUESS_SAD or GUESS_LEARNED; max_iter=0 returns the initial
+        density only."""
         n = self.nbf
         D = np.zeros((n, n)) if D0 is None else np.ascontiguousarray(D0, dtype=np.float64).copy()
-        o = ScfOpts(int(max_iter), float(e_tol), float(g_tol), int(diis_n), 0 if D0 is None else 1, float(lindep))
+        if guess is None:
+            guess = GUESS_CORE if D0 is None else GUESS_GIVEN
+        o = ScfOpts(int(max_iter), float(e_tol), float(g_tol), int(diis_n), int(guess), float(lindep))
         r = ScfResult()
         rc = _lib.fk_run_scf(self._ctx, ctypes.byref(o), ctypes.byref(r), _ptr(D))
         if rc not in (FK_OK, FK_ERR_NOT_CONVERGED):
@@ -251,6 +279,45 @@ class FockJK:
         res = {k: getattr(r, k) for k, _ in ScfResult._fields_}
         res["D"] = D
         return res
+
+    # ---- initial guesses ----
+    def sad_density(self):
+        D = np.zeros((self.nbf, self.nbf))
+        self._check(_lib.fk_sad_density(self._ctx, _ptr(D)))
+        return D
+
+    def guess_pairs(self):
+        """(features [npair, GUESS_NFEAT] float32, shape codes [npair] int32)."""
+        n = ctypes.c_int()
+        self._check(_lib.fk_guess_pairs(self._ctx, ctypes.byref(n), None, None))
+        X = np.zeros((n.value, GUESS_NFEAT), dtype=np.float32)
+        sh = np.zeros(n.value, dtype=np.int32)
+        self._check(_lib.fk_guess_pairs(self._ctx, ctypes.byref(n), _ptr(X), _ptr(sh)))
+        return X, sh
+
+    def guess_targets(self, D):
+        n = ctypes.c_int()
+        self._check(_lib.fk_guess_pairs(self._ctx, ctypes.byref(n), None, None))
+        Y = np.zeros((n.value, GUESS_NOUT), dtype=np.float32)
+        Dc = np.ascontiguousarray(D, dtype=np.float64)
+        self._check(_lib.fk_guess_targets(self._ctx, _ptr(Dc), _ptr(Y)))
+        return Y
+
+    def set_guess_model(self, Ws, bs):
+        """Ws[k]: (dims[k], dims[k+1]) arrays, bs[k]: (dims[k+1],); None removes."""
+        if Ws is None:
+            self._check(_lib.fk_set_guess_model(self._ctx, None))
+            return self
+        Wc = [np.ascontiguousarray(W, dtype=np.float32) for W in Ws]
+        bc = [np.ascontiguousarray(b, dtype=np.float32) for b in bs]
+        m = mlp_struct([W.shape[0] for W in Wc] + [Wc[-1].shape[1]], [_ptr(W) for W in Wc], [_ptr(b) for b in bc])
+        self._check(_lib.fk_set_guess_model(self._ctx, ctypes.byref(m)))
+        return self
+
+    def guess_predict(self):
+        D = np.zeros((self.nbf, self.nbf))
+        self._check(_lib.fk_guess_predict(self._ctx, _ptr(D)))
+        return D
 
     # ---- diagnostics ----
     def check_indices(self):
@@ -267,3 +334,71 @@ class FockJK:
             res.append(out[o:o + m].reshape(s))
             o += m
         return res
+
+
+# ---- network primitives on device tensors (training and inference) ----------
+def mlp_struct(dims, Wptrs, bptrs):
+    m = Mlp()
+    m.nlayer = len(dims) - 1
+    for k, d in enumerate(dims):
+        m.dims[k] = int(d)
+    for k in range(m.nlayer):
+        m.W[k] = Wptrs[k]
+        m.b[k] = bptrs[k]
+    return m
+
+
+def _dev(t):
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _stream():
+    return ctypes.c_void_p(_torch.cuda.current_stream().cuda_stream)
+
+
+def _mlp_dev(Ws, bs):
+    return mlp_struct([W.shape[0] for W in Ws] + [Ws[-1].shape[1]], [_dev(W) for W in Ws], [_dev(b) for b in bs])
+
+
+def _rc(rc, what):
+    if rc:
+        raise FockJKError(rc, what + " failed")
+
+
+def mlp_work(Ws, n):
+    """Device workspace (float32 tensor) for mlp_forward on n rows."""
+    m = mlp_struct([W.shape[0] for W in Ws] + [Ws[-1].shape[1]], [None] * len(Ws), [None] * len(Ws))
+    k = _lib.fk_mlp_work_floats(ctypes.byref(m), int(n))
+    return _torch.empty(max(int(k), 1), dtype=_torch.float32, device=Ws[0].device)
+
+
+def mlp_forward(Ws, bs, X, work):
+    """Y = network(X) on the device (float32 CUDA tensors, contiguous)."""
+    m = _mlp_dev(Ws, bs)
+    Y = _torch.empty((X.shape[0], Ws[-1].shape[1]), dtype=_torch.float32, device=X.device)
+    _rc(_lib.fk_mlp_forward(ctypes.byref(m), _dev(X), int(X.shape[0]), _dev(Y), _dev(work), _stream()),
+        "fk_mlp_forward")
+    return Y
+
+
+def mlp_backward(Ws, bs, X, work, dY, gWs, gbs):
+    """Fills gWs, gbs with the gradients; dY is overwritten."""
+    m, g = _mlp_dev(Ws, bs), _mlp_dev(gWs, gbs)
+    _rc(_lib.fk_mlp_backward(ctypes.byref(m), _dev(X), int(X.shape[0]), _dev(work), _dev(dY), ctypes.byref(g),
+                             _stream()), "fk_mlp_backward")
+
+
+def block_mse(Y, T, shape, count, dY, part, loss):
+    _rc(_lib.fk_mlp_block_mse(_dev(Y), _dev(T), _dev(shape), int(Y.shape[0]), float(count), _dev(dY), _dev(part),
+                              _dev(loss), _stream()), "fk_mlp_block_mse")
+
+
+def mse_scratch(device):
+    return _torch.empty(_lib.fk_mlp_mse_scratch(), dtype=_torch.float64, device=device)
+
+
+def mlp_adam(Ws, bs, gWs, gbs, m1W, m1b, m2W, m2b, step, lr, b1=0.9, b2=0.999, eps=1e-8):
+    m, g = _mlp_dev(Ws, bs), _mlp_dev(gWs, gbs)
+    a, v = _mlp_dev(m1W, m1b), _mlp_dev(m2W, m2b)
+    _rc(_lib.fk_mlp_adam(ctypes.byref(m), ctypes.byref(g), ctypes.byref(a), ctypes.byref(v), int(step), float(lr),
+                         float(b1), float(b2), float(eps), _stream()), "fk_mlp_adam")

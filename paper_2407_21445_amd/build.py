@@ -43,6 +43,7 @@ def build(maxl: int = 3, jobs: int | None = None, verbose: bool = False, extra=(
     units.append((os.path.join(CSRC, "fk_kernels.hip"), os.path.join(BUILD, "fk_kernels_common.o"),
                   ["-DFK_ONLY_P=-1"]))
     units.append((os.path.join(CSRC, "fk_scf.hip"), os.path.join(BUILD, "fk_scf.o"), []))
+    units.append((os.path.join(CSRC, "fk_guess.hip"), os.path.join(BUILD, "fk_guess.o"), []))
     units.append((os.path.join(CSRC, "fk_host.cpp"), os.path.join(BUILD, "fk_host.o"), ["-x", "hip"]))
     cmds = [[HIPCC] + COMMON + defs + u[2] + ["-c", u[0], "-o", u[1]] for u in units]
     with cf.ThreadPoolExecutor(jobs) as ex:

@@ -4,11 +4,13 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <chrono>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <map>
 #include <numeric>
 #include <string>
 #include <vector>
@@ -107,6 +109,14 @@ struct fk_ctx {
     bool stats_pending = false;
     bool timed = false;
     std::vector<hipEvent_t> ev;  // 2 per quartet class
+    // initial guesses
+    std::vector<double> coef_in;                  // contraction coefficients as given
+    std::map<int, std::vector<double>> sad_cache; // atomic density block per element
+    bool have_model = false;
+    fk_mlp g_model{};                             // device copy of the guess network
+    DevBuf<float> g_W[FK_MLP_MAX_LAYERS], g_b[FK_MLP_MAX_LAYERS], g_X, g_Y, g_work;
+    DevBuf<FkGuessPair> g_pairs;
+    DevBuf<double> g_rot, g_D;
 };
 
 namespace {
@@ -188,6 +198,8 @@ void free_device(fk_ctx *c)
     dev_free(c->d_X); dev_free(c->d_Din); dev_free(c->d_Jout); dev_free(c->d_Kout); dev_free(c->d_tiles);
     dev_free(c->d_cnt); dev_free(c->d_blocks); dev_free(c->d_blk_bra); dev_free(c->d_blk_pos); dev_free(c->d_lst_sa); dev_free(c->d_lst_sb); dev_free(c->d_lst_CD);
     dev_free(c->d_lst_G); dev_free(c->d_ppT); dev_free(c->d_groups);
+    for (int k = 0; k < FK_MLP_MAX_LAYERS; ++k) { dev_free(c->g_W[k]); dev_free(c->g_b[k]); }
+    dev_free(c->g_X); dev_free(c->g_Y); dev_free(c->g_work); dev_free(c->g_pairs); dev_free(c->g_rot); dev_free(c->g_D);
 }
 
 // canonical orientation of a shell pair: first shell has the higher l
@@ -571,6 +583,7 @@ int fk_set_geometry(fk_ctx *c, int natom, const int *Z, const double *xyz, int c
     c->charge = charge;
     c->nelec = (int)ne;
     c->atom_mol.assign(natom, 0);
+    c->sad_cache.clear();
     c->have_geom = true;
     c->have_basis = false;
     c->have_quartets = false;
@@ -612,6 +625,8 @@ int fk_set_basis(fk_ctx *c, int nshell, const int *shell_atom, const int *shell_
     }
     c->nbf = c->sh_bf[nshell];
     c->exps.assign(exps, exps + np);
+    c->coef_in.assign(coefs, coefs + np);
+    c->sad_cache.clear();
     c->coef.assign(np, 0.0);
     c->bf_scale.assign(c->nbf, 1.0);
     for (int s = 0; s < nshell; ++s) {
@@ -1399,6 +1414,8 @@ int fk_one_electron(fk_ctx *c, double *S, double *T, double *V, double *e_nuc)
 // convergence from scalars read back each step.
 namespace {
 
+int guess_predict_device(fk_ctx *c, double *D, hipStream_t st);  // learned guess, defined below
+
 struct ScfWork {
     fk_ctx *c = nullptr;
     hipStream_t st = nullptr;
@@ -1546,8 +1563,8 @@ int fk_run_scf(fk_ctx *c, const fk_scf_opts *opts, fk_scf_result *result, double
     if (c->nmol > 1) return fail(c, FK_ERR_UNSUPPORTED, "fk_run_scf: one molecule per context (batches: one context each)");
     fk_scf_opts o = {100, 1e-10, 1e-8, 8, 0, 1e-8};
     if (opts) o = *opts;
-    if (o.max_iter < 1 || o.diis_n < 0 || o.diis_n > 32 || !(o.e_tol > 0) || !(o.g_tol > 0) || !(o.lindep > 0) ||
-        (o.guess != 0 && o.guess != 1))
+    if (o.max_iter < 0 || o.diis_n < 0 || o.diis_n > 32 || !(o.e_tol > 0) || !(o.g_tol > 0) || !(o.lindep > 0) ||
+        o.guess < 0 || o.guess > 3)
         return fail(c, FK_ERR_ARG, "fk_run_scf: invalid options");
     if (c->nelec % 2 != 0 || c->nelec <= 0) return fail(c, FK_ERR_ARG, "fk_run_scf: closed shell needs an even, positive electron count");
     const int n = c->nbf, nocc = c->nelec / 2;
@@ -1581,12 +1598,41 @@ int fk_run_scf(fk_ctx *c, const fk_scf_opts *opts, fk_scf_result *result, double
     if ((rc = dev_upload(c, w.T3, S.data(), nn))) return rc;
     if ((rc = scf_orthogonaliser(w, o.lindep))) return rc;
 
-    // initial orthonormal density
-    if (o.guess == 0) {
+    // initial orthonormal density D' (w.Do); a learned or SAD guess that
+    // cannot be formed falls back to SAD, then to the core Hamiltonian
+    const auto t_guess = std::chrono::steady_clock::now();
+    int gused = o.guess;
+    if (gused == 3) {
+        rc = guess_predict_device(c, w.D.p, w.st);
+        double ss = 0;
+        if (!rc) rc = scf_reduce(w, w.D.p, w.D.p, 0, &ss);
+        if (!rc && !std::isfinite(ss)) rc = fail(c, FK_ERR_ARG, "learned guess: non-finite prediction");
+        if (!rc) {
+            // projector onto the nocc largest eigenvalues of P' = S^1/2 D S^1/2 / 2:
+            // purification of F' = -P' (its nocc lowest states)
+            SCFCHK(w, fk_scf_gemm(w.Xi.p, w.D.p, w.T3.p, n, 1.0, 0.0, w.st));
+            SCFCHK(w, fk_scf_gemm(w.T3.p, w.Xi.p, w.Fo.p, n, -0.5, 0.0, w.st));
+            rc = scf_purify(w, nocc, nullptr);
+        }
+        if (rc) gused = 2;
+    }
+    if (gused == 2) {
+        std::vector<double> Dsad(nn);
+        rc = fk_sad_density(c, Dsad.data());
+        if (!rc) rc = dev_upload(c, w.D, Dsad.data(), nn);
+        if (rc) {
+            gused = 0;
+        } else {
+            SCFCHK(w, fk_scf_gemm(w.Xi.p, w.D.p, w.T3.p, n, 1.0, 0.0, w.st));
+            SCFCHK(w, fk_scf_gemm(w.T3.p, w.Xi.p, w.Do.p, n, 1.0, 0.0, w.st));
+        }
+    }
+    if (gused != o.guess) c->err.clear();
+    if (gused == 0) {
         SCFCHK(w, fk_scf_gemm(w.X.p, w.h.p, w.T3.p, n, 1.0, 0.0, w.st));
         SCFCHK(w, fk_scf_gemm(w.T3.p, w.X.p, w.Fo.p, n, 1.0, 0.0, w.st));
         if ((rc = scf_purify(w, nocc, nullptr))) return rc;
-    } else {
+    } else if (gused == 1) {
         if ((rc = dev_upload(c, w.D, D_inout, nn))) return rc;
         SCFCHK(w, fk_scf_gemm(w.Xi.p, w.D.p, w.T3.p, n, 1.0, 0.0, w.st));
         SCFCHK(w, fk_scf_gemm(w.T3.p, w.Xi.p, w.Do.p, n, 1.0, 0.0, w.st));
@@ -1594,6 +1640,14 @@ int fk_run_scf(fk_ctx *c, const fk_scf_opts *opts, fk_scf_result *result, double
     // D = X D' X
     SCFCHK(w, fk_scf_gemm(w.X.p, w.Do.p, w.T3.p, n, 1.0, 0.0, w.st));
     SCFCHK(w, fk_scf_gemm(w.T3.p, w.X.p, w.D.p, n, 1.0, 0.0, w.st));
+    HIPCHK(c, hipStreamSynchronize(w.st));
+    result->guess_used = gused;
+    result->guess_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t_guess).count();
+    if (o.max_iter == 0) {
+        HIPCHK(c, hipMemcpy(D_inout, w.D.p, nn * sizeof(double), hipMemcpyDeviceToHost));
+        result->total_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start).count();
+        return FK_OK;
+    }
 
     std::vector<double> B;  // DIIS inner products, row-major m x m over ring slots
     const int dn = std::max(o.diis_n, 1);
@@ -1688,3 +1742,681 @@ int fk_rys_host(int n, double T, double *u, double *w)
 }
 
 }  // extern "C"
+
+// ============================================================ initial guesses
+// Learned initial density and superposition of atomic densities (an
+// extension: the paper's SCF starts from a conventional guess).
+namespace {
+
+// Position of the Cartesian component x^x y^y z^(l-x-y) in the library order.
+inline int cart_index(int l, int x, int y) { return (l - x) * (l - x + 1) / 2 + (l - x - y); }
+
+// T with phi_a(Q r) = sum_b T_ab phi_b(r) for the normalised Cartesian
+// components of momentum l (Q row-major 3 x 3, T row-major ncart x ncart):
+// the component's monomial is a product of l linear forms (Q r)_axis, whose
+// expansion runs over the 3^l choices of one coordinate per factor.
+void cart_rotation(int l, const double *Q, double *T)
+{
+    const int n = ncart(l);
+    for (int i = 0; i < n * n; ++i) T[i] = 0.0;
+    for (int a = 0; a < n; ++a) {
+        int ex, ey, ez;
+        cart_exps(l, a, ex, ey, ez);
+        int axis[3] = {0, 0, 0};
+        for (int f = 0; f < l; ++f) axis[f] = f < ex ? 0 : (f < ex + ey ? 1 : 2);
+        const double na = 1.0 / std::sqrt(dfact(2 * ex - 1) * dfact(2 * ey - 1) * dfact(2 * ez - 1));
+        int total = 1;
+        for (int f = 0; f < l; ++f) total *= 3;
+        for (int code = 0; code < total; ++code) {
+            int cnt[3] = {0, 0, 0}, cc = code;
+            double cf = 1.0;
+            for (int f = 0; f < l; ++f) {
+                const int j = cc % 3;
+                cc /= 3;
+                cf *= Q[axis[f] * 3 + j];
+                ++cnt[j];
+            }
+            const double nb = 1.0 / std::sqrt(dfact(2 * cnt[0] - 1) * dfact(2 * cnt[1] - 1) * dfact(2 * cnt[2] - 1));
+            T[a * n + cart_index(l, cnt[0], cnt[1])] += cf * na / nb;
+        }
+    }
+}
+
+// Block-diagonal rotation over the shells of atom `at` into T (FK_GUESS_NB^2,
+// zero-padded); returns the atom's function count.
+int atom_rotation(const fk_ctx *c, int at, const double *Q, double *T)
+{
+    for (int i = 0; i < FK_GUESS_NB * FK_GUESS_NB; ++i) T[i] = 0.0;
+    int o = 0;
+    double blk[100];
+    for (int s = 0; s < c->nshell; ++s) {
+        if (c->sh_atom[s] != at) continue;
+        const int l = c->sh_l[s], n = ncart(l);
+        cart_rotation(l, Q, blk);
+        for (int i = 0; i < n; ++i)
+            for (int j = 0; j < n; ++j) T[(o + i) * FK_GUESS_NB + o + j] = blk[i * n + j];
+        o += n;
+    }
+    return o;
+}
+
+// Columns e_x, e_y, e_z of the frame of the pair (ra -> rb), row-major.
+void bond_frame(const double *ra, const double *rb, double *Q)
+{
+    double d[3] = {rb[0] - ra[0], rb[1] - ra[1], rb[2] - ra[2]};
+    const double R = std::sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+    if (R == 0.0) {
+        for (int i = 0; i < 9; ++i) Q[i] = (i % 4 == 0) ? 1.0 : 0.0;
+        return;
+    }
+    double ez[3] = {d[0] / R, d[1] / R, d[2] / R};
+    int k = 0;
+    for (int i = 1; i < 3; ++i)
+        if (std::fabs(ez[i]) < std::fabs(ez[k])) k = i;
+    double ex[3] = {0, 0, 0};
+    ex[k] = 1.0;
+    const double p = ez[k];
+    for (int i = 0; i < 3; ++i) ex[i] -= p * ez[i];
+    const double nx = std::sqrt(ex[0] * ex[0] + ex[1] * ex[1] + ex[2] * ex[2]);
+    for (int i = 0; i < 3; ++i) ex[i] /= nx;
+    const double ey[3] = {ez[1] * ex[2] - ez[2] * ex[1], ez[2] * ex[0] - ez[0] * ex[2], ez[0] * ex[1] - ez[1] * ex[0]};
+    for (int i = 0; i < 3; ++i) {
+        Q[i * 3 + 0] = ex[i];
+        Q[i * 3 + 1] = ey[i];
+        Q[i * 3 + 2] = ez[i];
+    }
+}
+
+void transpose3(const double *Q, double *Qt)
+{
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) Qt[j * 3 + i] = Q[i * 3 + j];
+}
+
+// The 60 rotations of an icosahedron from the unit quaternions of the binary
+// icosahedral group (one of each pair +-q): (1,0,0,0) and its coordinate
+// permutations, (+-1/2, +-1/2, +-1/2, +-1/2), and the even permutations of
+// (0, +-1, +-1/phi, +-phi) / 2.
+const std::vector<std::array<double, 9>> &icosahedral_rotations()
+{
+    static const std::vector<std::array<double, 9>> rots = [] {
+        std::vector<std::array<double, 9>> out;
+        const double g = (1.0 + std::sqrt(5.0)) / 2.0;
+        std::vector<std::array<double, 4>> qs;
+        for (int i = 0; i < 4; ++i) {
+            std::array<double, 4> q = {0, 0, 0, 0};
+            q[i] = 1.0;
+            qs.push_back(q);
+        }
+        for (int s = 0; s < 16; ++s)
+            qs.push_back({(s & 1) ? -0.5 : 0.5, (s & 2) ? -0.5 : 0.5, (s & 4) ? -0.5 : 0.5, (s & 8) ? -0.5 : 0.5});
+        const int even[12][4] = {{0, 1, 2, 3}, {0, 2, 3, 1}, {0, 3, 1, 2}, {1, 0, 3, 2}, {1, 2, 0, 3}, {1, 3, 2, 0},
+                                 {2, 0, 1, 3}, {2, 1, 3, 0}, {2, 3, 0, 1}, {3, 0, 2, 1}, {3, 1, 0, 2}, {3, 2, 1, 0}};
+        const double base[4] = {0.0, 0.5, 0.5 / g, 0.5 * g};
+        for (const auto &pm : even)
+            for (int s = 0; s < 8; ++s) {
+                std::array<double, 4> q;
+                for (int k = 0; k < 4; ++k) q[pm[k]] = base[k];
+                q[pm[1]] *= (s & 1) ? -1 : 1;
+                q[pm[2]] *= (s & 2) ? -1 : 1;
+                q[pm[3]] *= (s & 4) ? -1 : 1;
+                qs.push_back(q);
+            }
+        for (const auto &q : qs) {
+            // keep one of +-q: the first non-zero component positive
+            int k = 0;
+            while (q[k] == 0.0) ++k;
+            if (q[k] < 0) continue;
+            const double w = q[0], x = q[1], y = q[2], z = q[3];
+            out.push_back({1 - 2 * (y * y + z * z), 2 * (x * y - w * z), 2 * (x * z + w * y),
+                            2 * (x * y + w * z), 1 - 2 * (x * x + z * z), 2 * (y * z - w * x),
+                            2 * (x * z - w * y), 2 * (y * z + w * x), 1 - 2 * (x * x + y * y)});
+        }
+        return out;
+    }();  // initialised once, thread-safe
+    return rots;
+}
+
+int element_slot(int Z)
+{
+    switch (Z) {
+    case 1: return 0;
+    case 6: return 1;
+    case 7: return 2;
+    case 8: return 3;
+    default: return -1;
+    }
+}
+
+struct GuessPairHost {
+    int a1, a2;
+};
+
+// Atom function ranges; FK_ERR_UNSUPPORTED if an atom's shells are not
+// consecutive or it has more than FK_GUESS_NB functions.
+int atom_ranges(fk_ctx *c, std::vector<int> &f0, std::vector<int> &nf)
+{
+    f0.assign(c->natom, -1);
+    nf.assign(c->natom, 0);
+    for (int s = 0; s < c->nshell; ++s) {
+        const int a = c->sh_atom[s];
+        if (f0[a] < 0) f0[a] = c->sh_bf[s];
+        else if (f0[a] + nf[a] != c->sh_bf[s])
+            return fail(c, FK_ERR_UNSUPPORTED, "initial guess: the shells of atom %d are not consecutive", a);
+        nf[a] += ncart(c->sh_l[s]);
+        if (nf[a] > FK_GUESS_NB)
+            return fail(c, FK_ERR_UNSUPPORTED, "initial guess: atom %d has more than %d functions", a, FK_GUESS_NB);
+    }
+    return FK_OK;
+}
+
+int guess_pair_list(fk_ctx *c, std::vector<GuessPairHost> &pairs)
+{
+    pairs.clear();
+    if (!c->have_basis) return fail(c, FK_ERR_STATE, "initial guess: geometry and basis not set");
+    if (c->nmol > 1) return fail(c, FK_ERR_UNSUPPORTED, "initial guess: one molecule per context");
+    for (int a = 0; a < c->natom; ++a)
+        if (element_slot(c->Z[a]) < 0)
+            return fail(c, FK_ERR_UNSUPPORTED, "learned guess: element Z = %d is not one of H, C, N, O", c->Z[a]);
+    const double rc2 = FK_GUESS_RCUT * FK_GUESS_RCUT;
+    for (int i = 0; i < c->natom; ++i)
+        for (int j = i; j < c->natom; ++j) {
+            if (i != j) {
+                double r2 = 0;
+                for (int k = 0; k < 3; ++k) {
+                    const double d = c->xyz[3 * i + k] - c->xyz[3 * j + k];
+                    r2 += d * d;
+                }
+                if (!(r2 < rc2)) continue;
+            }
+            pairs.push_back(c->Z[j] > c->Z[i] ? GuessPairHost{j, i} : GuessPairHost{i, j});
+        }
+    return FK_OK;
+}
+
+void guess_features(const fk_ctx *c, const GuessPairHost &p, float *x)
+{
+    for (int k = 0; k < FK_GUESS_NFEAT; ++k) x[k] = 0.0f;
+    x[element_slot(c->Z[p.a1])] = 1.0f;
+    x[4 + element_slot(c->Z[p.a2])] = 1.0f;
+    double r2 = 0;
+    for (int k = 0; k < 3; ++k) {
+        const double d = c->xyz[3 * p.a2 + k] - c->xyz[3 * p.a1 + k];
+        r2 += d * d;
+    }
+    const double R = std::sqrt(r2), step = FK_GUESS_RCUT / (FK_GUESS_NRBF - 1);
+    for (int k = 0; k < FK_GUESS_NRBF; ++k) {
+        const double u = (R - k * step) / step;
+        x[8 + k] = (float)std::exp(-u * u);
+    }
+}
+
+// C = A^T B C' helpers on FK_GUESS_NB x FK_GUESS_NB row-major blocks
+void blk_mul(const double *A, bool ta, const double *B, bool tb, double *C)
+{
+    constexpr int W = FK_GUESS_NB;
+    for (int i = 0; i < W; ++i)
+        for (int j = 0; j < W; ++j) {
+            double s = 0;
+            for (int k = 0; k < W; ++k) s += (ta ? A[k * W + i] : A[i * W + k]) * (tb ? B[j * W + k] : B[k * W + j]);
+            C[i * W + j] = s;
+        }
+}
+
+// Cyclic Jacobi eigen-decomposition of a symmetric n x n matrix: A = V diag(w) V^T.
+void jacobi_eigen(int n, std::vector<double> A, std::vector<double> &w, std::vector<double> &V)
+{
+    V.assign((size_t)n * n, 0.0);
+    for (int i = 0; i < n; ++i) V[(size_t)i * n + i] = 1.0;
+    for (int sweep = 0; sweep < 100; ++sweep) {
+        double off = 0, tot = 0;
+        for (int i = 0; i < n; ++i)
+            for (int j = 0; j < n; ++j) {
+                const double v = A[(size_t)i * n + j] * A[(size_t)i * n + j];
+                tot += v;
+                if (i != j) off += v;
+            }
+        if (off <= 1e-30 * tot || off == 0.0) break;
+        for (int p = 0; p < n; ++p)
+            for (int q = p + 1; q < n; ++q) {
+                const double apq = A[(size_t)p * n + q];
+                if (apq == 0.0) continue;
+                const double theta = (A[(size_t)q * n + q] - A[(size_t)p * n + p]) / (2 * apq);
+                const double t = (theta >= 0 ? 1.0 : -1.0) / (std::fabs(theta) + std::sqrt(theta * theta + 1));
+                const double cs = 1 / std::sqrt(t * t + 1), sn = t * cs;
+                for (int k = 0; k < n; ++k) {  // columns p, q
+                    const double akp = A[(size_t)k * n + p], akq = A[(size_t)k * n + q];
+                    A[(size_t)k * n + p] = cs * akp - sn * akq;
+                    A[(size_t)k * n + q] = sn * akp + cs * akq;
+                }
+                for (int k = 0; k < n; ++k) {  // rows p, q
+                    const double apk = A[(size_t)p * n + k], aqk = A[(size_t)q * n + k];
+                    A[(size_t)p * n + k] = cs * apk - sn * aqk;
+                    A[(size_t)q * n + k] = sn * apk + cs * aqk;
+                }
+                for (int k = 0; k < n; ++k) {
+                    const double vkp = V[(size_t)k * n + p], vkq = V[(size_t)k * n + q];
+                    V[(size_t)k * n + p] = cs * vkp - sn * vkq;
+                    V[(size_t)k * n + q] = sn * vkp + cs * vkq;
+                }
+            }
+    }
+    w.resize(n);
+    for (int i = 0; i < n; ++i) w[i] = A[(size_t)i * n + i];
+}
+
+// Fractional-occupation SCF of atom `at` alone (its shells at the origin, Z
+// electrons); result: its nf x nf density block.
+int atomic_density(fk_ctx *c, int at, std::vector<double> &Dat)
+{
+    std::vector<int> shells;
+    for (int s = 0; s < c->nshell; ++s)
+        if (c->sh_atom[s] == at) shells.push_back(s);
+    const int ns = (int)shells.size();
+    std::vector<int> satom(ns, 0), sl(ns), snp(ns);
+    std::vector<double> ex, cf;
+    for (int k = 0; k < ns; ++k) {
+        const int s = shells[k];
+        sl[k] = c->sh_l[s];
+        snp[k] = c->sh_nprim[s];
+        for (int p = c->sh_poff[s]; p < c->sh_poff[s + 1]; ++p) {
+            ex.push_back(c->exps[p]);
+            cf.push_back(c->coef_in[p]);
+        }
+    }
+    const int Z = c->Z[at];
+    const double origin[3] = {0, 0, 0};
+    fk_ctx *t = nullptr;
+    if (fk_create(&t, -1) != FK_OK) return fail(c, FK_ERR_OOM, "SAD: cannot create an atomic context");
+    struct Guard { fk_ctx *t; ~Guard() { fk_destroy(t); } } guard{t};
+    fk_screen_opts so{};
+    // the geometry's own electron count is not used (odd Z gets charge -1 to
+    // pass the closed-shell check); the atom holds Z electrons below
+    if (fk_set_geometry(t, 1, &Z, origin, (Z & 1) ? -1 : 0) || fk_set_basis(t, ns, satom.data(), sl.data(), snp.data(), ex.data(), cf.data()) ||
+        fk_build_quartets(t, &so))
+        return fail(c, FK_ERR_ARG, "SAD: atomic set-up failed: %s", t->err.c_str());
+    const int n = t->nbf;
+    const size_t n2 = (size_t)n * n;
+    std::vector<double> S(n2), T(n2), V(n2), h(n2);
+    if (fk_one_electron(t, S.data(), T.data(), V.data(), nullptr))
+        return fail(c, FK_ERR_ARG, "SAD: atomic one-electron integrals failed: %s", t->err.c_str());
+    for (size_t i = 0; i < n2; ++i) h[i] = T[i] + V[i];
+    // every shell quartet's integrals, scattered into G[i][j][k][l] = (ij|kl)
+    std::vector<int> q;
+    for (int a = 0; a < ns; ++a)
+        for (int b = 0; b < ns; ++b)
+            for (int cc = 0; cc < ns; ++cc)
+                for (int d = 0; d < ns; ++d) q.insert(q.end(), {a, b, cc, d});
+    size_t tot = 0;
+    for (size_t k = 0; k < q.size(); k += 4)
+        tot += (size_t)ncart(sl[q[k]]) * ncart(sl[q[k + 1]]) * ncart(sl[q[k + 2]]) * ncart(sl[q[k + 3]]);
+    std::vector<double> out(tot), G(n2 * n2);
+    if (fk_debug_eri(t, (int)(q.size() / 4), q.data(), out.data(), 0))
+        return fail(c, FK_ERR_ARG, "SAD: atomic integrals failed: %s", t->err.c_str());
+    size_t o = 0;
+    for (size_t k = 0; k < q.size(); k += 4) {
+        const int s0 = q[k], s1 = q[k + 1], s2 = q[k + 2], s3 = q[k + 3];
+        const int n0 = ncart(sl[s0]), n1 = ncart(sl[s1]), n2_ = ncart(sl[s2]), n3 = ncart(sl[s3]);
+        for (int i = 0; i < n0; ++i)
+            for (int j = 0; j < n1; ++j)
+                for (int kk = 0; kk < n2_; ++kk)
+                    for (int l = 0; l < n3; ++l) {
+                        const size_t I = t->sh_bf[s0] + i, J = t->sh_bf[s1] + j, K = t->sh_bf[s2] + kk, L = t->sh_bf[s3] + l;
+                        G[((I * n + J) * n + K) * n + L] = out[o++];
+                    }
+    }
+    // X = S^(-1/2)
+    std::vector<double> w, U;
+    jacobi_eigen(n, S, w, U);
+    std::vector<double> X(n2, 0.0);
+    for (int i = 0; i < n; ++i)
+        for (int j = 0; j < n; ++j) {
+            double s = 0;
+            for (int k = 0; k < n; ++k) s += U[(size_t)i * n + k] * U[(size_t)j * n + k] / std::sqrt(w[k]);
+            X[(size_t)i * n + j] = s;
+        }
+    auto density_of = [&](const std::vector<double> &F, std::vector<double> &D) {
+        std::vector<double> XF(n2, 0.0), Fp(n2, 0.0);
+        for (int i = 0; i < n; ++i)
+            for (int j = 0; j < n; ++j) {
+                double s = 0;
+                for (int k = 0; k < n; ++k) s += X[(size_t)i * n + k] * F[(size_t)k * n + j];
+                XF[(size_t)i * n + j] = s;
+            }
+        for (int i = 0; i < n; ++i)
+            for (int j = 0; j < n; ++j) {
+                double s = 0;
+                for (int k = 0; k < n; ++k) s += XF[(size_t)i * n + k] * X[(size_t)k * n + j];
+                Fp[(size_t)i * n + j] = s;
+            }
+        std::vector<double> e, Cp;
+        jacobi_eigen(n, Fp, e, Cp);
+        std::vector<int> ord(n);
+        for (int i = 0; i < n; ++i) ord[i] = i;
+        std::sort(ord.begin(), ord.end(), [&](int a, int b) { return e[a] < e[b]; });
+        std::vector<double> occ(n, 0.0);
+        double left = Z;
+        for (int i = 0; i < n && left > 0;) {
+            int j = i;
+            while (j < n && e[ord[j]] - e[ord[i]] < 1e-4) ++j;
+            const double each = std::min(2.0, left / (j - i));
+            for (int k = i; k < j; ++k) occ[ord[k]] = each;
+            left -= each * (j - i);
+            i = j;
+        }
+        // C = X C'; D = sum_k occ_k c_k c_k^T
+        std::vector<double> C(n2, 0.0);
+        for (int i = 0; i < n; ++i)
+            for (int k = 0; k < n; ++k) {
+                double s = 0;
+                for (int m = 0; m < n; ++m) s += X[(size_t)i * n + m] * Cp[(size_t)m * n + k];
+                C[(size_t)i * n + k] = s;
+            }
+        D.assign(n2, 0.0);
+        for (int k = 0; k < n; ++k) {
+            if (occ[k] == 0.0) continue;
+            for (int i = 0; i < n; ++i)
+                for (int j = 0; j < n; ++j) D[(size_t)i * n + j] += occ[k] * C[(size_t)i * n + k] * C[(size_t)j * n + k];
+        }
+    };
+    std::vector<double> D, Dn, F(n2);
+    density_of(h, D);
+    for (int it = 0; it < 500; ++it) {
+        for (int i = 0; i < n; ++i)
+            for (int j = 0; j < n; ++j) {
+                double jv = 0, kv = 0;
+                for (int k = 0; k < n; ++k)
+                    for (int l = 0; l < n; ++l) {
+                        jv += G[(((size_t)i * n + j) * n + k) * n + l] * D[(size_t)k * n + l];
+                        kv += G[(((size_t)i * n + k) * n + j) * n + l] * D[(size_t)k * n + l];
+                    }
+                F[(size_t)i * n + j] = h[(size_t)i * n + j] + jv - 0.5 * kv;
+            }
+        density_of(F, Dn);
+        double delta = 0;
+        for (size_t i = 0; i < n2; ++i) delta = std::max(delta, std::fabs(Dn[i] - D[i]));
+        if (delta < 1e-10) {
+            D = Dn;
+            break;
+        }
+        for (size_t i = 0; i < n2; ++i) D[i] = 0.5 * Dn[i] + 0.5 * D[i];
+    }
+    Dat = D;
+    return FK_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int fk_sad_density(fk_ctx *c, double *D_out)
+{
+    if (!c) return FK_ERR_ARG;
+    if (!D_out) return fail(c, FK_ERR_ARG, "fk_sad_density: null output");
+    if (!c->have_basis) return fail(c, FK_ERR_STATE, "fk_sad_density: geometry and basis not set");
+    if (c->nmol > 1) return fail(c, FK_ERR_UNSUPPORTED, "fk_sad_density: one molecule per context");
+    std::vector<int> f0, nf;
+    int rc;
+    if ((rc = atom_ranges(c, f0, nf))) return rc;
+    const int n = c->nbf;
+    std::fill(D_out, D_out + (size_t)n * n, 0.0);
+    for (int a = 0; a < c->natom; ++a) {
+        auto it = c->sad_cache.find(c->Z[a]);
+        if (it == c->sad_cache.end()) {
+            std::vector<double> Dat;
+            if ((rc = atomic_density(c, a, Dat))) return rc;
+            it = c->sad_cache.emplace(c->Z[a], std::move(Dat)).first;
+        }
+        const std::vector<double> &Dat = it->second;
+        const int m = nf[a];
+        if ((int)Dat.size() != m * m) return fail(c, FK_ERR_ARG, "fk_sad_density: atoms of element %d differ in basis", c->Z[a]);
+        for (int i = 0; i < m; ++i)
+            for (int j = 0; j < m; ++j) D_out[(size_t)(f0[a] + i) * n + f0[a] + j] = Dat[(size_t)i * m + j];
+    }
+    return FK_OK;
+}
+
+int fk_guess_pairs(fk_ctx *c, int *npair, float *features, int *shape)
+{
+    if (!c) return FK_ERR_ARG;
+    if (!npair) return fail(c, FK_ERR_ARG, "fk_guess_pairs: null npair");
+    std::vector<GuessPairHost> pairs;
+    std::vector<int> f0, nf;
+    int rc;
+    if ((rc = guess_pair_list(c, pairs)) || (rc = atom_ranges(c, f0, nf))) return rc;
+    *npair = (int)pairs.size();
+    for (size_t p = 0; p < pairs.size(); ++p) {
+        if (features) guess_features(c, pairs[p], features + p * FK_GUESS_NFEAT);
+        if (shape) shape[p] = (nf[pairs[p].a1] << 8) | nf[pairs[p].a2];
+    }
+    return FK_OK;
+}
+
+int fk_guess_targets(fk_ctx *c, const double *D, float *Y)
+{
+    if (!c) return FK_ERR_ARG;
+    if (!D || !Y) return fail(c, FK_ERR_ARG, "fk_guess_targets: null argument");
+    std::vector<GuessPairHost> pairs;
+    std::vector<int> f0, nf;
+    int rc;
+    if ((rc = guess_pair_list(c, pairs)) || (rc = atom_ranges(c, f0, nf))) return rc;
+    constexpr int W = FK_GUESS_NB;
+    const int n = c->nbf;
+    const auto &ico = icosahedral_rotations();
+    std::vector<std::array<double, 9>> zrot(8);
+    for (int k = 0; k < 8; ++k) {
+        const double ph = 2 * M_PI * k / 8, cs = std::cos(ph), sn = std::sin(ph);
+        zrot[k] = {cs, -sn, 0, sn, cs, 0, 0, 0, 1};
+    }
+    double B[W * W], Bb[W * W], T1[W * W], T2[W * W], H[W * W], acc[W * W], Q[9], Gt[9];
+    for (size_t p = 0; p < pairs.size(); ++p) {
+        const int a1 = pairs[p].a1, a2 = pairs[p].a2, n1 = nf[a1], n2 = nf[a2];
+        for (int i = 0; i < W * W; ++i) B[i] = 0.0;
+        for (int i = 0; i < n1; ++i)
+            for (int j = 0; j < n2; ++j) B[i * W + j] = D[(size_t)(f0[a1] + i) * n + f0[a2] + j];
+        // bond frame: D_bond = T(Q)^T D T(Q)
+        bond_frame(&c->xyz[3 * a1], &c->xyz[3 * a2], Q);
+        atom_rotation(c, a1, Q, T1);
+        atom_rotation(c, a2, Q, T2);
+        blk_mul(B, false, T2, false, H);
+        blk_mul(T1, true, H, false, Bb);
+        // average of the bond-frame molecule rotated by G: T(G^T)^T B T(G^T)
+        for (int i = 0; i < W * W; ++i) acc[i] = 0.0;
+        const bool onsite = a1 == a2;
+        const size_t nrot = onsite ? ico.size() : zrot.size();
+        for (size_t r = 0; r < nrot; ++r) {
+            transpose3(onsite ? ico[r].data() : zrot[r].data(), Gt);
+            atom_rotation(c, a1, Gt, T1);
+            atom_rotation(c, a2, Gt, T2);
+            blk_mul(Bb, false, T2, false, H);
+            blk_mul(T1, true, H, false, B);
+            for (int i = 0; i < W * W; ++i) acc[i] += B[i];
+        }
+        float *y = Y + p * FK_GUESS_NOUT;
+        for (int i = 0; i < W; ++i)
+            for (int j = 0; j < W; ++j) y[i * W + j] = (i < n1 && j < n2) ? (float)(acc[i * W + j] / nrot) : 0.0f;
+    }
+    return FK_OK;
+}
+
+int64_t fk_mlp_work_floats(const fk_mlp *m, int n)
+{
+    if (!m || m->nlayer < 1 || m->nlayer > FK_MLP_MAX_LAYERS || n < 0) return -1;
+    int64_t w = 0, hmax = 0;
+    for (int k = 0; k + 1 < m->nlayer; ++k) {
+        w += 2 * (int64_t)n * m->dims[k + 1];
+        hmax = std::max<int64_t>(hmax, m->dims[k + 1]);
+    }
+    return w + 2 * (int64_t)n * hmax;
+}
+
+static int mlp_check(const fk_mlp *m)
+{
+    if (!m || m->nlayer < 1 || m->nlayer > FK_MLP_MAX_LAYERS) return FK_ERR_ARG;
+    for (int k = 0; k <= m->nlayer; ++k)
+        if (m->dims[k] < 1 || m->dims[k] > 4096) return FK_ERR_ARG;
+    for (int k = 0; k < m->nlayer; ++k)
+        if (!m->W[k] || !m->b[k]) return FK_ERR_ARG;
+    return FK_OK;
+}
+
+int fk_mlp_forward(const fk_mlp *m, const float *X, int n, float *Y, float *work, void *stream)
+{
+    if (mlp_check(m) || n < 0 || (n > 0 && (!X || !Y || (m->nlayer > 1 && !work)))) return FK_ERR_ARG;
+    if (n == 0) return FK_OK;
+    const float *in = X;
+    float *wp = work;
+    for (int k = 0; k < m->nlayer; ++k) {
+        const int din = m->dims[k], dout = m->dims[k + 1];
+        if (k + 1 < m->nlayer) {
+            float *Z = wp, *A = wp + (size_t)n * dout;
+            if (fk_guess_mm(0, 0, in, din, m->W[k], dout, Z, A, m->b[k], n, dout, din, stream)) return FK_ERR_HIP;
+            in = A;
+            wp += 2 * (size_t)n * dout;
+        } else {
+            if (fk_guess_mm(0, 0, in, din, m->W[k], dout, Y, nullptr, m->b[k], n, dout, din, stream)) return FK_ERR_HIP;
+        }
+    }
+    return FK_OK;
+}
+
+int fk_mlp_backward(const fk_mlp *m, const float *X, int n, float *work, float *dY, const fk_mlp *grad, void *stream)
+{
+    if (mlp_check(m) || mlp_check(grad) || n < 0 || (n > 0 && (!X || !dY || (m->nlayer > 1 && !work)))) return FK_ERR_ARG;
+    for (int k = 0; k <= m->nlayer; ++k)
+        if (grad->dims[k] != m->dims[k] || grad->nlayer != m->nlayer) return FK_ERR_ARG;
+    if (n == 0) return FK_OK;
+    const int L = m->nlayer;
+    // activations: layer k < L-1 keeps Z_k, A_k at zoff[k]
+    std::vector<size_t> zoff(L, 0);
+    size_t o = 0, hmax = 0;
+    for (int k = 0; k + 1 < L; ++k) {
+        zoff[k] = o;
+        o += 2 * (size_t)n * m->dims[k + 1];
+        hmax = std::max<size_t>(hmax, m->dims[k + 1]);
+    }
+    float *hbuf[2] = {work + o, work + o + (size_t)n * hmax};
+    float *G = dY;
+    for (int k = L - 1; k >= 0; --k) {
+        const int din = m->dims[k], dout = m->dims[k + 1];
+        const float *Ain = k == 0 ? X : work + zoff[k - 1] + (size_t)n * din;
+        if (fk_guess_mm(1, 0, Ain, din, G, dout, grad->W[k], nullptr, nullptr, din, dout, n, stream)) return FK_ERR_HIP;
+        if (fk_guess_colsum(G, n, dout, grad->b[k], stream)) return FK_ERR_HIP;
+        if (k > 0) {
+            float *H = hbuf[k & 1];
+            if (fk_guess_mm(0, 1, G, dout, m->W[k], dout, H, nullptr, nullptr, n, din, dout, stream)) return FK_ERR_HIP;
+            if (fk_guess_silu_back(H, work + zoff[k - 1], (long long)n * din, stream)) return FK_ERR_HIP;
+            G = H;
+        }
+    }
+    return FK_OK;
+}
+
+int fk_mlp_mse_scratch(void) { return fk_guess_mse_parts(); }
+
+int fk_mlp_block_mse(const float *Y, const float *T, const int *shape, int n, double count, float *dY, double *part,
+                     double *loss, void *stream)
+{
+    if (n < 0 || (n > 0 && (!Y || !T || !shape || !dY || !part || !loss)) || !(count > 0)) return FK_ERR_ARG;
+    if (n == 0) return FK_OK;
+    return fk_guess_block_mse(Y, T, shape, n, FK_GUESS_NB, count, dY, part, loss, stream) ? FK_ERR_HIP : FK_OK;
+}
+
+int fk_mlp_adam(const fk_mlp *m, const fk_mlp *grad, const fk_mlp *m1, const fk_mlp *m2, int step, float lr, float b1,
+                float b2, float eps, void *stream)
+{
+    if (mlp_check(m) || mlp_check(grad) || mlp_check(m1) || mlp_check(m2) || step < 1) return FK_ERR_ARG;
+    const float c1 = (float)(1.0 / (1.0 - std::pow((double)b1, step)));
+    const float c2 = (float)(1.0 / (1.0 - std::pow((double)b2, step)));
+    for (int k = 0; k < m->nlayer; ++k) {
+        const long long nw = (long long)m->dims[k] * m->dims[k + 1], nb = m->dims[k + 1];
+        if (fk_guess_adam(m->W[k], grad->W[k], m1->W[k], m2->W[k], nw, lr, b1, b2, eps, c1, c2, stream) ||
+            fk_guess_adam(m->b[k], grad->b[k], m1->b[k], m2->b[k], nb, lr, b1, b2, eps, c1, c2, stream))
+            return FK_ERR_HIP;
+    }
+    return FK_OK;
+}
+
+int fk_set_guess_model(fk_ctx *c, const fk_mlp *hm)
+{
+    if (!c) return FK_ERR_ARG;
+    if (!hm) {
+        c->have_model = false;
+        return FK_OK;
+    }
+    if (c->device < 0) return fail(c, FK_ERR_STATE, "fk_set_guess_model: context has no device");
+    if (mlp_check(hm) || hm->dims[0] != FK_GUESS_NFEAT || hm->dims[hm->nlayer] != FK_GUESS_NOUT)
+        return fail(c, FK_ERR_ARG, "fk_set_guess_model: need 1..%d layers, %d inputs, %d outputs, dims <= 4096",
+                    FK_MLP_MAX_LAYERS, FK_GUESS_NFEAT, FK_GUESS_NOUT);
+    for (int k = 0; k < hm->nlayer; ++k)
+        for (size_t i = 0; i < (size_t)hm->dims[k] * hm->dims[k + 1]; ++i)
+            if (!std::isfinite(hm->W[k][i])) return fail(c, FK_ERR_ARG, "fk_set_guess_model: non-finite weight");
+    hipSetDevice(c->device);
+    c->g_model = *hm;
+    int rc;
+    for (int k = 0; k < hm->nlayer; ++k) {
+        if ((rc = dev_upload<float>(c, c->g_W[k], hm->W[k], (size_t)hm->dims[k] * hm->dims[k + 1])) ||
+            (rc = dev_upload<float>(c, c->g_b[k], hm->b[k], (size_t)hm->dims[k + 1])))
+            return rc;
+        c->g_model.W[k] = c->g_W[k].p;
+        c->g_model.b[k] = c->g_b[k].p;
+    }
+    c->have_model = true;
+    return FK_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+// Predicted (unpurified) density into the device array D (nbf x nbf) on `st`.
+int guess_predict_device(fk_ctx *c, double *D, hipStream_t st)
+{
+    if (!c->have_model) return fail(c, FK_ERR_STATE, "learned guess: no model (fk_set_guess_model)");
+    std::vector<GuessPairHost> pairs;
+    std::vector<int> f0, nf;
+    int rc;
+    if ((rc = guess_pair_list(c, pairs)) || (rc = atom_ranges(c, f0, nf))) return rc;
+    constexpr int W = FK_GUESS_NB;
+    const int np = (int)pairs.size();
+    std::vector<float> X((size_t)np * FK_GUESS_NFEAT);
+    std::vector<FkGuessPair> gp(np);
+    std::vector<double> rot((size_t)np * 2 * W * W);
+    double Q[9], Qt[9];
+    for (int p = 0; p < np; ++p) {
+        const int a1 = pairs[p].a1, a2 = pairs[p].a2;
+        guess_features(c, pairs[p], &X[(size_t)p * FK_GUESS_NFEAT]);
+        gp[p] = FkGuessPair{a1, a2, f0[a1], f0[a2], nf[a1], nf[a2]};
+        // D_lab = T(Q^T)^T B T(Q^T)
+        bond_frame(&c->xyz[3 * a1], &c->xyz[3 * a2], Q);
+        transpose3(Q, Qt);
+        atom_rotation(c, a1, Qt, &rot[(size_t)p * 2 * W * W]);
+        atom_rotation(c, a2, Qt, &rot[(size_t)p * 2 * W * W + W * W]);
+    }
+    const int64_t wf = fk_mlp_work_floats(&c->g_model, np);
+    if ((rc = dev_upload(c, c->g_X, X.data(), X.size())) || (rc = dev_upload<float>(c, c->g_Y, nullptr, (size_t)np * FK_GUESS_NOUT)) ||
+        (rc = dev_upload<float>(c, c->g_work, nullptr, (size_t)std::max<int64_t>(wf, 1))) ||
+        (rc = dev_upload(c, c->g_pairs, gp.data(), gp.size())) || (rc = dev_upload(c, c->g_rot, rot.data(), rot.size())))
+        return rc;
+    if (fk_mlp_forward(&c->g_model, c->g_X.p, np, c->g_Y.p, c->g_work.p, st))
+        return fail(c, FK_ERR_HIP, "learned guess: network launch failed");
+    if (fk_guess_scatter(c->g_Y.p, c->g_pairs.p, c->g_rot.p, np, c->nbf, D, st))
+        return fail(c, FK_ERR_HIP, "learned guess: scatter launch failed");
+    return FK_OK;
+}
+
+}  // namespace
+
+extern "C" int fk_guess_predict(fk_ctx *c, double *D_out)
+{
+    if (!c) return FK_ERR_ARG;
+    if (!D_out) return fail(c, FK_ERR_ARG, "fk_guess_predict: null output");
+    if (c->device < 0) return fail(c, FK_ERR_STATE, "fk_guess_predict: context has no device");
+    hipSetDevice(c->device);
+    const size_t nn = (size_t)c->nbf * c->nbf;
+    int rc;
+    if ((rc = dev_upload<double>(c, c->g_D, nullptr, nn))) return rc;
+    if ((rc = guess_predict_device(c, c->g_D.p, nullptr))) return rc;
+    HIPCHK(c, hipMemcpy(D_out, c->g_D.p, nn * sizeof(double), hipMemcpyDeviceToHost));
+    return FK_OK;
+}

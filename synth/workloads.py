@@ -119,3 +119,27 @@ def batch(systems):
 
 def organic_batch(n=256, basis_name="tzvp-type", seed=SEED + 40):
     return batch([make_system(_geom.organic(seed + i), basis_name) for i in range(n)])
+
+
+# ------------------------------------------------- learned-guess geometry set --
+GUESS_SET_SIZE = 2000
+GUESS_HELD_OUT = 200   # the last 200 indices are never trained on
+
+
+def guess_geometry(i, seed=SEED + 60):
+    """Geometry i of the learned-guess set: even i a linear alkane C4-C16 in
+    a random orientation, odd i a water cluster of 4-32 molecules; every
+    coordinate jittered by up to 0.05 angstrom."""
+    rng = np.random.default_rng(seed + 7919 * i)
+    if i % 2 == 0:
+        n = int(rng.integers(4, 17))
+        mol = _geom.alkane(n, seed + i, jitter=0.05)
+        mol["xyz"] = mol["xyz"] @ _geom._rand_rot(rng).T
+    else:
+        n = int(rng.integers(4, 33))
+        mol = _geom.water_cluster(n, seed + i, jitter=0.05)
+    return mol
+
+
+def guess_system(i, basis_name="6-31gs-type", seed=SEED + 60):
+    return make_system(guess_geometry(i, seed), basis_name)

@@ -1,0 +1,198 @@
+"""GPU tests of the initial guesses (run with -m gpu): the network kernels
+(forward, backward, loss, Adam) against the FP64 oracle, the assembled and
+purified learned guess against the oracle, the SAD and learned guesses inside
+the SCF step, and what the trained network gains over SAD.
+
+Tolerances: the network runs in FP32 (inputs, weights and accumulation), so
+its outputs and gradients are compared relative to their largest magnitude at
+1e-5 (outputs) and 1e-4 (gradients, two FP32 products deep); the purified
+density inherits the prediction's FP32 error divided by the spectral gap at
+the occupied/virtual boundary (about 0.03 here), hence 1e-4.
+"""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import guess as og
+from oracle.scf import run_scf as oracle_scf
+from synth import geometry as geom
+from synth import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as t
+    assert t.cuda.is_available(), "GPU tests need a visible GPU"
+    return t
+
+
+@pytest.fixture(scope="module")
+def fk(torch):
+    import paper_2407_21445_amd as m
+    return m
+
+
+def _rand_mlp(seed, dims, scale=1.0):
+    rng = np.random.default_rng(seed)
+    Ws = [scale * rng.normal(size=(dims[k], dims[k + 1])) / math.sqrt(dims[k]) for k in range(len(dims) - 1)]
+    bs = [0.1 * rng.normal(size=dims[k + 1]) for k in range(len(dims) - 1)]
+    # the library holds FP32 weights; the oracle gets the same rounded values
+    return [W.astype(np.float32) for W in Ws], [b.astype(np.float32) for b in bs]
+
+
+def _to(torch, arrs):
+    return [torch.from_numpy(np.ascontiguousarray(a)).cuda() for a in arrs]
+
+
+@pytest.mark.parametrize("n", [1, 130, 333])
+def test_mlp_forward_backward_match_oracle(fk, torch, n):
+    """n spans a partial tile, two tiles plus a ragged tail, and six tiles."""
+    dims = [32, 64, 48, 225]
+    Ws, bs = _rand_mlp(11, dims)
+    rng = np.random.default_rng(12)
+    X = rng.normal(size=(n, 32)).astype(np.float32)
+    T = rng.normal(size=(n, 225)).astype(np.float32)
+    shp = rng.choice([15 * 256 + 15, 15 * 256 + 2, 2 * 256 + 15, 2 * 256 + 2, 1 * 256 + 1], size=n).astype(np.int32)
+    shapes = [(int(v) >> 8, int(v) & 255) for v in shp]
+    cnt = float(sum(a * b for a, b in shapes))
+    Wd, bd = _to(torch, Ws), _to(torch, bs)
+    Xd, Td, Sd = _to(torch, [X, T, shp])
+    work = fk.mlp_work(Wd, n)
+    Y = fk.mlp_forward(Wd, bd, Xd, work)
+    dY = torch.empty_like(Y)
+    part, loss = fk.mse_scratch(Y.device), torch.zeros(1, dtype=torch.float64, device=Y.device)
+    fk.block_mse(Y, Td, Sd, cnt, dY, part, loss)
+    gW = [torch.zeros_like(W) for W in Wd]
+    gb = [torch.zeros_like(b) for b in bd]
+    fk.mlp_backward(Wd, bd, Xd, work, dY, gW, gb)
+    torch.cuda.synchronize()
+    W64, b64 = [W.astype(float) for W in Ws], [b.astype(float) for b in bs]
+    Yo, pre = og.mlp_forward(W64, b64, X.astype(float))
+    lo, dYo = og.block_mse(Yo, T.astype(float), shapes)
+    dWo, dbo = og.mlp_backward(W64, b64, X.astype(float), pre, dYo)
+    Yg = Y.cpu().numpy()
+    assert np.max(np.abs(Yg - Yo)) <= 1e-5 * np.max(np.abs(Yo))
+    assert float(loss.item()) == pytest.approx(lo, rel=1e-5)
+    for k in range(3):
+        assert np.max(np.abs(gW[k].cpu().numpy() - dWo[k])) <= 1e-4 * np.max(np.abs(dWo[k]))
+        assert np.max(np.abs(gb[k].cpu().numpy() - dbo[k])) <= 1e-4 * np.max(np.abs(dbo[k]))
+
+
+def test_adam_matches_oracle(fk, torch):
+    dims = [32, 40, 225]
+    Ws, bs = _rand_mlp(3, dims)
+    rng = np.random.default_rng(4)
+    gs = [rng.normal(size=W.shape).astype(np.float32) for W in Ws]
+    gbs = [rng.normal(size=b.shape).astype(np.float32) for b in bs]
+    Wd, bd, gWd, gbd = _to(torch, Ws), _to(torch, bs), _to(torch, gs), _to(torch, gbs)
+    m1W, m1b = [torch.zeros_like(W) for W in Wd], [torch.zeros_like(b) for b in bd]
+    m2W, m2b = [torch.zeros_like(W) for W in Wd], [torch.zeros_like(b) for b in bd]
+    for step in (1, 2, 3):
+        fk.mlp_adam(Wd, bd, gWd, gbd, m1W, m1b, m2W, m2b, step, 1e-2)
+    torch.cuda.synchronize()
+    for k in range(2):
+        for got, w0, g in ((Wd[k], Ws[k], gs[k]), (bd[k], bs[k], gbs[k])):
+            W, m, v = w0.astype(float), np.zeros(w0.shape), np.zeros(w0.shape)
+            for step in (1, 2, 3):
+                W, m, v = og.adam(W, g.astype(float), m, v, step, 1e-2)
+            assert np.max(np.abs(got.cpu().numpy() - W)) < 1e-6
+
+
+def _water2():
+    return wl.make_system(geom.water_cluster(2, 8), "6-31gs-type")
+
+
+def test_guess_predict_and_purify_match_oracle(fk):
+    """Random seeded weights: the assembled prediction (network, bond-frame
+    rotation, scatter) and the purified guess against the oracle."""
+    s = _water2()
+    Ws, bs = _rand_mlp(0, [32, 256, 256, 225])
+    c = fk.FockJK(0).set_system(s).build_quartets(tau=1e-10)
+    c.set_guess_model(Ws, bs)
+    D = c.guess_predict()
+    pairs = og.pair_list(s)
+    X = og.features(s, pairs).astype(np.float32).astype(float)
+    Do = og.assemble(s, pairs, og.mlp_forward([W.astype(float) for W in Ws], [b.astype(float) for b in bs], X)[0])
+    assert np.max(np.abs(D - Do)) <= 1e-5 * np.max(np.abs(Do))
+    r = c.run_scf(max_iter=0, guess=fk.GUESS_LEARNED)
+    assert r["guess_used"] == fk.GUESS_LEARNED and r["iterations"] == 0
+    S = oracle.oneel(s)[0]
+    D0o = og.purify(S, Do, s["nelec"] // 2)
+    assert np.max(np.abs(r["D"] - D0o)) < 1e-4
+    assert abs(np.trace(r["D"] @ S) - s["nelec"]) < 1e-8
+    DS = r["D"] @ S
+    assert np.max(np.abs(DS @ DS - 2 * DS)) < 1e-8
+
+
+def test_sad_guess_in_scf(fk):
+    """SCF from SAD reaches the oracle's energy (1e-8 Eh) and starts from the
+    oracle's SAD density."""
+    s = wl.alkane_sys(2, "6-31gs-type")
+    c = fk.FockJK(0).set_system(s).build_quartets(tau=0.0)
+    r0 = c.run_scf(max_iter=0, guess=fk.GUESS_SAD)
+    assert r0["guess_used"] == fk.GUESS_SAD
+    assert np.max(np.abs(r0["D"] - og.sad_density(s))) < 1e-9
+    r = c.run_scf(guess=fk.GUESS_SAD)
+    assert r["converged"] and r["guess_used"] == fk.GUESS_SAD
+    assert abs(r["energy"] - oracle_scf(s)["E"]) <= 1e-8
+
+
+def test_learned_guess_falls_back(fk):
+    """No model: the learned request runs from SAD; an element outside H, C, N,
+    O would do the same (checked on the host)."""
+    s = wl.water4_sto3g()
+    c = fk.FockJK(0).set_system(s).build_quartets(tau=0.0)
+    r = c.run_scf(guess=fk.GUESS_LEARNED)
+    assert r["guess_used"] == fk.GUESS_SAD and r["converged"]
+    assert abs(r["energy"] - oracle_scf(s)["E"]) <= 1e-8
+
+
+def test_training_kernels_reduce_loss(fk, torch):
+    """A few hundred library Adam steps on the pair blocks of two small
+    converged molecules cut the masked loss by an order of magnitude."""
+    from paper_2407_21445_amd import guess_train as gt
+    data = {}
+    for i, s in enumerate([wl.make_system(geom.alkane(4, 1, jitter=0.05), "6-31gs-type"),
+                           wl.make_system(geom.water_cluster(3, 2, jitter=0.05), "6-31gs-type")]):
+        c = fk.FockJK(0).set_system(s).build_quartets(tau=1e-10)
+        r = c.run_scf(guess=fk.GUESS_SAD)
+        assert r["converged"]
+        X, sh = c.guess_pairs()
+        data[i] = (X, sh, c.guess_targets(r["D"]), r["iterations"])
+    data[2] = data[0]  # validation split takes one geometry
+    Ws, bs, hist = gt.train(data, epochs=400, budget_s=60, batch=64, lr=3e-3, val_frac=0.3)
+    first, last = hist[0][1], hist[-1][1]
+    assert last < 0.1 * first, hist[:3] + hist[-3:]
+
+
+MODEL = os.path.join(os.path.dirname(HERE), "paper_2407_21445_amd", "guess_631gs.npz")
+
+
+@pytest.mark.skipif(not os.path.exists(MODEL), reason="no trained guess weights in the package")
+def test_trained_guess_beats_sad_on_held_out(fk):
+    """Held-out geometries of the guess set (never trained on): the learned
+    guess needs fewer SCF iterations than SAD on average and never changes
+    the converged energy by more than 1e-8 Eh."""
+    from paper_2407_21445_amd import guess_train as gt
+    Ws, bs = gt.load_model(MODEL)
+    first = wl.GUESS_SET_SIZE - wl.GUESS_HELD_OUT
+    its_sad, its_nn = [], []
+    for i in range(first, first + 6):
+        s = wl.guess_system(i)
+        c = fk.FockJK(0).set_system(s).build_quartets(tau=1e-10)
+        c.set_guess_model(Ws, bs)
+        r0 = c.run_scf(guess=fk.GUESS_SAD)
+        r1 = c.run_scf(guess=fk.GUESS_LEARNED)
+        assert r0["converged"] and r1["converged"] and r1["guess_used"] == fk.GUESS_LEARNED
+        assert abs(r1["energy"] - r0["energy"]) <= 1e-8
+        its_sad.append(r0["iterations"])
+        its_nn.append(r1["iterations"])
+    assert np.mean(its_nn) < np.mean(its_sad), (its_sad, its_nn)

@@ -19,7 +19,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 def test_exports_every_declared_symbol():
     hdr = open(os.path.join(ROOT, "include", "fockjk.h")).read()
-    names = set(re.findall(r"^\s*(?:int|void|const char \*)\s*(fk_\w+)\s*\(", hdr, re.M))
+    names = set(re.findall(r"^\s*(?:int|int64_t|void|const char \*)\s*(fk_\w+)\s*\(", hdr, re.M))
     assert len(names) >= 12
     import ctypes
     lib = ctypes.CDLL(fk.LIB_PATH)
@@ -231,3 +231,56 @@ def test_batch_validation():
     with pytest.raises(fk.FockJKError) as e:
         c.one_electron()
     assert e.value.code == fk.FK_ERR_UNSUPPORTED
+
+
+# ------------------------------------------------------------ initial guesses
+def _guess_sys(kind):
+    from synth import geometry as geom
+    if kind == "water2":
+        return wl.make_system(geom.water_cluster(2, 8), "6-31gs-type")
+    if kind == "propane":
+        return wl.make_system(geom.alkane(3, 5, jitter=0.05), "6-31gs-type")
+    return wl.make_system(geom.water_cluster(2, 9), "sto-3g")
+
+
+@pytest.mark.parametrize("kind", ["water2", "propane", "water2_sto3g"])
+def test_guess_features_and_targets_match_oracle(kind):
+    """Pair list, features, shapes and bond-frame targets (host) against the
+    oracle on a random density: the same pairs in the same order, features
+    to FP32 rounding, targets to FP32 rounding (the spherical on-site average
+    uses a differently oriented icosahedron on each side, so agreement also
+    shows both are full rotational averages)."""
+    from oracle import guess as og
+    s = _guess_sys(kind)
+    c = fk.FockJK(device=-1).set_system(s)
+    X, sh = c.guess_pairs()
+    pairs = og.pair_list(s)
+    assert len(X) == len(pairs)
+    assert np.max(np.abs(X - og.features(s, pairs))) < 1e-6
+    assert [(int(v) >> 8, int(v) & 255) for v in sh] == og.pair_shape(s, pairs)
+    D = wl.random_density(s, 3)
+    Yo = og.targets(s, D, pairs)
+    assert np.max(np.abs(c.guess_targets(D) - Yo)) <= 1e-6 * max(1.0, np.max(np.abs(Yo)))
+
+
+@pytest.mark.parametrize("kind", ["water2", "propane"])
+def test_sad_density_matches_oracle(kind):
+    from oracle import guess as og
+    s = _guess_sys(kind)
+    c = fk.FockJK(device=-1).set_system(s)
+    assert np.max(np.abs(c.sad_density() - og.sad_density(s))) < 1e-9
+
+
+def test_guess_errors():
+    s = _guess_sys("water2")
+    c = fk.FockJK(device=-1).set_system(s)
+    with pytest.raises(fk.FockJKError) as e:  # weights live on a device
+        c.set_guess_model([np.zeros((32, 225))], [np.zeros(225)])
+    assert e.value.code == fk.FK_ERR_STATE
+    b = _small_batch()
+    cb = fk.FockJK(device=-1).set_system(b).set_molecules(b["atom_mol"])
+    with pytest.raises(fk.FockJKError) as e:
+        cb.guess_pairs()
+    assert e.value.code == fk.FK_ERR_UNSUPPORTED
+    m = fk.mlp_struct([32, 225], [None], [None])
+    assert fk._lib.fk_mlp_forward(fk.ctypes.byref(m), None, 1, None, None, None) == fk.FK_ERR_ARG
