@@ -307,6 +307,20 @@ def main():
             out["mixed"]["scf_energy_diff"] = r["energy"] - r64["energy"]
         out["scf"] = {"iterations": r["iterations"], "converged": bool(r["converged"]), "energy": r["energy"],
                       "seconds": r["total_seconds"], "jk_seconds": r["jk_seconds"], "guess": "core Hamiltonian"}
+        # the same SCF from the SAD guess and from the learned guess (when the
+        # trained network for this basis is present)
+        guesses = {"sad": fk.GUESS_SAD}
+        model = os.path.join(HERE, "paper_2407_21445_amd", "guess_631gs.npz")
+        if sys_["name"].endswith("/6-31gs-type") and os.path.exists(model):
+            from paper_2407_21445_amd.guess_train import load_model
+            ctx.set_guess_model(*load_model(model))
+            guesses["learned"] = fk.GUESS_LEARNED
+        for name, g in guesses.items():
+            rg = ctx.run_scf(guess=g)
+            out["scf"][name] = {"iterations": rg["iterations"], "converged": bool(rg["converged"]),
+                                "seconds": rg["total_seconds"], "guess_seconds": rg["guess_seconds"],
+                                "energy_minus_core_start": rg["energy"] - r["energy"],
+                                "guess_used": {0: "core", 2: "sad", 3: "learned"}.get(rg["guess_used"], "?")}
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(sys_, D, args.cpu_seconds)
     print(json.dumps(out), flush=True)
