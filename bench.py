@@ -313,8 +313,11 @@ def main():
         model = os.path.join(HERE, "paper_2407_21445_amd", "guess_631gs.npz")
         if sys_["name"].endswith("/6-31gs-type") and os.path.exists(model):
             from paper_2407_21445_amd.guess_train import load_model
-            ctx.set_guess_model(*load_model(model))
-            guesses["learned"] = fk.GUESS_LEARNED
+            try:
+                ctx.set_guess_model(*load_model(model))
+                guesses["learned"] = fk.GUESS_LEARNED
+            except fk.FockJKError as e:  # weights of another feature layout
+                print(f"bench.py: learned guess skipped: {e}", file=sys.stderr)
         for name, g in guesses.items():
             rg = ctx.run_scf(guess=g)
             out["scf"][name] = {"iterations": rg["iterations"], "converged": bool(rg["converged"]),

@@ -243,18 +243,30 @@ int fk_sad_density(fk_ctx *ctx, double *D_out);
 
 /* Learned guess.  Atom pairs: every atom with itself and every pair closer
  * than FK_GUESS_RCUT, in row-major order over (i <= j); the pair's first atom
- * is the one of higher Z (lower index on ties).  Features of a pair
- * (FK_GUESS_NFEAT floats): one-hot of the first atom's element over
- * (H, C, N, O), one-hot of the second's, then FK_GUESS_NRBF Gaussians
- * exp(-g (R - mu_k)^2), mu_k = k RCUT / (NRBF - 1), g = ((NRBF - 1) / RCUT)^2.
+ * is the one of higher Z (lower index on ties).
+ * Pair frame (columns e_x, e_y, e_z): for two atoms, e_z from the first to
+ * the second and e_x towards the first atom's nearest neighbour off that axis
+ * (else the second atom's); for an atom with itself, e_z towards its nearest
+ * neighbour and e_x towards the next nearest off-axis one.  "Off-axis": the
+ * direction's component orthogonal to e_z exceeds 0.1 of its length;
+ * neighbours (within FK_GUESS_RCUT) are ordered by distance on a 1e-6 bohr
+ * grid, then index; without a suitable neighbour e_x comes from the lab axis
+ * least aligned with e_z (a lone atom keeps the lab frame).
+ * Features of a pair (FK_GUESS_NFEAT floats): one-hot of the first atom's
+ * element over (H, C, N, O), one-hot of the second's, FK_GUESS_NRBF
+ * Gaussians exp(-g (R - mu_k)^2), mu_k = k RCUT / (NRBF - 1),
+ * g = ((NRBF - 1) / RCUT)^2, then for the first and then the second atom the
+ * moments (1, u_x, u_y, u_z, u_x^2, u_x u_y, u_x u_z, u_y^2, u_y u_z, u_z^2)
+ * of the unit vectors u (pair-frame coordinates) to each other atom within
+ * FK_GUESS_RCUT except the pair's two, weighted by exp(-(r / 3)^2) and
+ * exp(-((r - 5) / 1.5)^2) (r in bohr), summed per element:
+ * [atom][element][weight][moment].
  * Output of a pair: the block D[first's functions][second's functions] in the
- * bond frame (e_z from the first atom to the second; e_x from the lab axis
- * least aligned with e_z; the lab frame for an atom with itself), row-major,
- * padded to FK_GUESS_NB x FK_GUESS_NB. */
+ * pair frame, row-major, padded to FK_GUESS_NB x FK_GUESS_NB. */
 #define FK_GUESS_NB 15
 #define FK_GUESS_NOUT (FK_GUESS_NB * FK_GUESS_NB)
 #define FK_GUESS_NRBF 24
-#define FK_GUESS_NFEAT (8 + FK_GUESS_NRBF)
+#define FK_GUESS_NFEAT (8 + FK_GUESS_NRBF + 160)
 #define FK_GUESS_RCUT 8.0      /* bohr */
 #define FK_MLP_MAX_LAYERS 4
 
@@ -276,9 +288,8 @@ typedef struct {
 int fk_guess_pairs(fk_ctx *ctx, int *npair, float *features, int *shape);
 
 /* Training targets: the pair blocks of density D (host nbf x nbf) in the
- * bond frame, averaged over 8 rotations about the bond (an atom with itself:
- * over the 60 rotations of the icosahedron, i.e. spherically), as
- * Y[npair][FK_GUESS_NOUT] (host), zero-padded. */
+ * pair frames, D_frame = T(Q)^T D_block T(Q) with T the Cartesian rotation
+ * of each atom's shells, as Y[npair][FK_GUESS_NOUT] (host), zero-padded. */
 int fk_guess_targets(fk_ctx *ctx, const double *D, float *Y);
 
 /* Copies a network (host pointers; dims[0] = FK_GUESS_NFEAT, last dims =

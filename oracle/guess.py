@@ -16,15 +16,18 @@ Pieces (each written out from its definition, no blocking or fusion):
   component order and normalisation of the paper's Cartesian Gaussians,
   "Notation").  A density block transforms as D' = T(Q^T)^T D T(Q^T) when the
   molecule is rotated by Q.
-* ``pair_list`` / ``features``: atom pairs within ``R_CUT`` (and every atom
-  with itself), oriented heavier atom first, with element one-hots and
-  Gaussian radial features of the distance.
-* ``targets``: a converged density's pair blocks in each pair's bond frame
-  (z from the first atom to the second), averaged over 8 rotations about the
-  bond (on-site blocks: over the 60 rotations of the icosahedron), padded to
+* ``pair_list`` / ``local_frame`` / ``features``: atom pairs within
+  ``R_CUT`` (and every atom with itself), oriented heavier atom first; each
+  pair's frame is fixed by its own atoms and their nearest neighbours (z
+  along the pair, or towards an atom's nearest neighbour; x towards the
+  nearest neighbour off that axis), so the frame turns with the molecule;
+  features are element one-hots, Gaussian radial features of the distance,
+  and each atom's environment as weighted moments (1, u, u u^T) of its
+  neighbours' directions u in the pair frame, per element and radial shell.
+* ``targets``: a density's pair blocks in each pair's frame, padded to
   15 x 15.
-* ``assemble``: predicted bond-frame blocks rotated back and scattered into
-  an nbf x nbf density (on-site blocks symmetrised).
+* ``assemble``: predicted blocks rotated back to the molecular frame and
+  scattered into an nbf x nbf density (on-site blocks symmetrised).
 * ``purify``: the projection onto an idempotent density with the right
   electron count: D0 = 2 S^-1/2 P S^-1/2, P the projector onto the nelec/2
   largest eigenvalues of S^1/2 D S^1/2 / 2.
@@ -36,7 +39,6 @@ Pieces (each written out from its definition, no blocking or fusion):
 """
 from __future__ import annotations
 
-import itertools
 import math
 
 import numpy as np
@@ -47,7 +49,11 @@ ELEMENTS = (1, 6, 7, 8)          # one-hot order: H, C, N, O
 R_CUT = 8.0                      # bohr
 N_RBF = 24
 NB_PAD = 15                      # functions per atom in the padded block
-N_FEAT = 2 * len(ELEMENTS) + N_RBF
+ENV_SHELLS = ((0.0, 3.0), (5.0, 1.5))   # (centre, width) in bohr of the environment weights
+ENV_MOMENTS = 10                 # 1, u_x, u_y, u_z, u_x^2, u_x u_y, u_x u_z, u_y^2, u_y u_z, u_z^2
+N_ENV = len(ELEMENTS) * len(ENV_SHELLS) * ENV_MOMENTS
+N_FEAT = 2 * len(ELEMENTS) + N_RBF + 2 * N_ENV
+OFF_AXIS = 0.1                   # a reference direction needs |sin| above this
 
 
 # ------------------------------------------------------------ rotations --
@@ -118,53 +124,57 @@ def atom_rotation(sys, atom, Q):
     return T
 
 
-def bond_frame(ra, rb):
-    """Columns e_x, e_y, e_z: e_z from ra to rb; e_x from the lab axis least
-    aligned with e_z (lowest index on ties); Q = I for ra == rb."""
-    d = np.asarray(rb, float) - np.asarray(ra, float)
-    R = np.linalg.norm(d)
-    if R == 0.0:
-        return np.eye(3)
-    ez = d / R
-    k = int(np.argmin(np.abs(ez)))
-    u = np.zeros(3)
-    u[k] = 1.0
-    ex = u - (u @ ez) * ez
+def _frame_from(ez, ref):
+    """Columns e_x, e_y, e_z: e_x along the part of ref orthogonal to e_z, or,
+    without ref, along the lab axis least aligned with e_z (lowest index on
+    ties)."""
+    if ref is None:
+        k = int(np.argmin(np.abs(ez)))
+        ref = np.zeros(3)
+        ref[k] = 1.0
+    ex = ref - (ref @ ez) * ez
     ex /= np.linalg.norm(ex)
-    ey = np.cross(ez, ex)
-    return np.column_stack([ex, ey, ez])
+    return np.column_stack([ex, np.cross(ez, ex), ez])
 
 
-def rot_z(phi):
-    c, s = math.cos(phi), math.sin(phi)
-    return np.array([[c, -s, 0.0], [s, c, 0.0], [0.0, 0.0, 1.0]])
+def _neighbours(xyz, centre, exclude, r_cut=R_CUT):
+    """Atoms within r_cut of atom `centre`, not in `exclude`, by distance on a
+    1e-6 bohr grid, then index (so that distances equal by symmetry order the
+    same way in any orientation)."""
+    d = np.linalg.norm(xyz - xyz[centre], axis=1)
+    ks = [k for k in range(len(xyz)) if k not in exclude and d[k] < r_cut]
+    return sorted(ks, key=lambda k: (math.floor(d[k] * 1e6), k))
 
 
-def icosahedral_rotations():
-    """The 60 rotations of the icosahedron with vertices (0, +-1, +-g) and
-    their cyclic permutations, generated by closure from the 3-fold cyclic
-    permutation of the axes and the 5-fold rotation about (0, 1, g)."""
-    g = (1 + math.sqrt(5)) / 2
-    a = np.array([0.0, 1.0, g]) / math.sqrt(1 + g * g)
-    t = 2 * math.pi / 5
-    K = np.array([[0, -a[2], a[1]], [a[2], 0, -a[0]], [-a[1], a[0], 0]])
-    five = np.eye(3) + math.sin(t) * K + (1 - math.cos(t)) * (K @ K)
-    three = np.array([[0.0, 0.0, 1.0], [1.0, 0.0, 0.0], [0.0, 1.0, 0.0]])
-    group = [np.eye(3)]
-    keys = {tuple(np.round(np.eye(3), 6).ravel())}
-    frontier = [np.eye(3)]
-    while frontier:
-        nxt = []
-        for M in frontier:
-            for G in (five, three):
-                P = G @ M
-                k = tuple(np.round(P, 6).ravel())
-                if k not in keys:
-                    keys.add(k)
-                    group.append(P)
-                    nxt.append(P)
-        frontier = nxt
-    return group
+def _off_axis(xyz, origin, ez, cands):
+    """First candidate whose direction from `origin` is off the e_z axis."""
+    for k in cands:
+        v = xyz[k] - xyz[origin]
+        perp = v - (v @ ez) * ez
+        if np.linalg.norm(perp) > OFF_AXIS * np.linalg.norm(v):
+            return v
+    return None
+
+
+def local_frame(xyz, a, b):
+    """Frame of the pair (a, b), columns e_x, e_y, e_z.  a != b: e_z from a to
+    b; e_x towards the nearest off-axis neighbour of a (else of b).  a == b:
+    e_z towards a's nearest neighbour, e_x towards the next nearest off-axis
+    one.  Missing neighbours: lab axes (a lone atom: the lab frame)."""
+    xyz = np.asarray(xyz, float).reshape(-1, 3)
+    if a != b:
+        ez = xyz[b] - xyz[a]
+        ez = ez / np.linalg.norm(ez)
+        ref = _off_axis(xyz, a, ez, _neighbours(xyz, a, {a, b}))
+        if ref is None:
+            ref = _off_axis(xyz, b, ez, _neighbours(xyz, b, {a, b}))
+        return _frame_from(ez, ref)
+    nb = _neighbours(xyz, a, {a})
+    if not nb:
+        return np.eye(3)
+    ez = xyz[nb[0]] - xyz[a]
+    ez = ez / np.linalg.norm(ez)
+    return _frame_from(ez, _off_axis(xyz, a, ez, nb[1:]))
 
 
 # ---------------------------------------------------------------- pairs --
@@ -187,11 +197,29 @@ def features(sys, pairs, r_cut=R_CUT):
     X = np.zeros((len(pairs), N_FEAT))
     mu = np.arange(N_RBF) * (r_cut / (N_RBF - 1))
     gamma = ((N_RBF - 1) / r_cut) ** 2
+    base = 2 * len(ELEMENTS) + N_RBF
     for p, (a, b) in enumerate(pairs):
         X[p, ELEMENTS.index(int(Z[a]))] = 1.0
         X[p, len(ELEMENTS) + ELEMENTS.index(int(Z[b]))] = 1.0
         R = np.linalg.norm(xyz[b] - xyz[a])
-        X[p, 2 * len(ELEMENTS):] = np.exp(-gamma * (R - mu) ** 2)
+        X[p, 2 * len(ELEMENTS):base] = np.exp(-gamma * (R - mu) ** 2)
+        Q = local_frame(xyz, a, b)
+        for side, atom in enumerate((a, b)):
+            for k in range(len(Z)):
+                if k in (a, b):
+                    continue
+                v = xyz[k] - xyz[atom]
+                r = np.linalg.norm(v)
+                if r >= r_cut:
+                    continue
+                u = Q.T @ (v / r)
+                mom = [1.0, u[0], u[1], u[2], u[0] * u[0], u[0] * u[1], u[0] * u[2], u[1] * u[1], u[1] * u[2],
+                       u[2] * u[2]]
+                e = ELEMENTS.index(int(Z[k]))
+                for sh, (c0, w) in enumerate(ENV_SHELLS):
+                    wt = math.exp(-((r - c0) / w) ** 2)
+                    o = base + side * N_ENV + (e * len(ENV_SHELLS) + sh) * ENV_MOMENTS
+                    X[p, o:o + ENV_MOMENTS] += wt * np.array(mom)
     return X
 
 
@@ -200,22 +228,14 @@ def pair_shape(sys, pairs):
 
 
 def targets(sys, D, pairs):
-    """Bond-frame blocks of D (padded, flattened row-major 15 x 15)."""
+    """Pair blocks of D in each pair's frame (padded, flattened row-major
+    15 x 15): D_frame = T(Q)^T D T(Q), the molecule rotated by Q^T."""
     xyz = np.asarray(sys["xyz"], float).reshape(-1, 3)
     Y = np.zeros((len(pairs), NB_PAD * NB_PAD))
-    ico = icosahedral_rotations()
     for p, (a, b) in enumerate(pairs):
         fa, fb = atom_functions(sys, a), atom_functions(sys, b)
-        Q = bond_frame(xyz[a], xyz[b])
-        blk = D[np.ix_(fa, fb)]
-        # D_bond = T(Q)^T D T(Q) (the molecule rotated by Q^T)
-        blk = atom_rotation(sys, a, Q).T @ blk @ atom_rotation(sys, b, Q)
-        rots = ico if a == b else [rot_z(2 * math.pi * k / 8) for k in range(8)]
-        acc = np.zeros_like(blk)
-        for G in rots:
-            # the bond-frame molecule rotated by G
-            acc += atom_rotation(sys, a, G.T).T @ blk @ atom_rotation(sys, b, G.T)
-        blk = acc / len(rots)
+        Q = local_frame(xyz, a, b)
+        blk = atom_rotation(sys, a, Q).T @ D[np.ix_(fa, fb)] @ atom_rotation(sys, b, Q)
         pad = np.zeros((NB_PAD, NB_PAD))
         pad[:len(fa), :len(fb)] = blk
         Y[p] = pad.ravel()
@@ -223,14 +243,14 @@ def targets(sys, D, pairs):
 
 
 def assemble(sys, pairs, Y):
-    """nbf x nbf density from bond-frame blocks: D_lab = T(Q^T)^T B T(Q^T)."""
+    """nbf x nbf density from pair-frame blocks: D_lab = T(Q^T)^T B T(Q^T)."""
     xyz = np.asarray(sys["xyz"], float).reshape(-1, 3)
     n = sys["nbf"]
     D = np.zeros((n, n))
     for p, (a, b) in enumerate(pairs):
         fa, fb = atom_functions(sys, a), atom_functions(sys, b)
         B = np.asarray(Y[p], float).reshape(NB_PAD, NB_PAD)[:len(fa), :len(fb)]
-        Q = bond_frame(xyz[a], xyz[b])
+        Q = local_frame(xyz, a, b)
         L = atom_rotation(sys, a, Q.T).T @ B @ atom_rotation(sys, b, Q.T)
         if a == b:
             D[np.ix_(fa, fa)] = 0.5 * (L + L.T)

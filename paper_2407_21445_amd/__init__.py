@@ -73,7 +73,7 @@ class ScfResult(ctypes.Structure):
 
 
 GUESS_CORE, GUESS_GIVEN, GUESS_SAD, GUESS_LEARNED = 0, 1, 2, 3
-GUESS_NB, GUESS_NOUT, GUESS_NRBF, GUESS_NFEAT, GUESS_RCUT = 15, 225, 24, 32, 8.0
+GUESS_NB, GUESS_NOUT, GUESS_NRBF, GUESS_NFEAT, GUESS_RCUT = 15, 225, 24, 192, 8.0
 MLP_MAX_LAYERS = 4
 
 

@@ -1800,22 +1800,21 @@ int atom_rotation(const fk_ctx *c, int at, const double *Q, double *T)
     return o;
 }
 
-// Columns e_x, e_y, e_z of the frame of the pair (ra -> rb), row-major.
-void bond_frame(const double *ra, const double *rb, double *Q)
+// Frame with e_z = ez (unit) and e_x along the part of ref orthogonal to e_z,
+// or, for ref == NULL, along the lab axis least aligned with e_z (lowest
+// index on ties); columns e_x, e_y, e_z of Q, row-major.
+void frame_from(const double *ez, const double *ref, double *Q)
 {
-    double d[3] = {rb[0] - ra[0], rb[1] - ra[1], rb[2] - ra[2]};
-    const double R = std::sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
-    if (R == 0.0) {
-        for (int i = 0; i < 9; ++i) Q[i] = (i % 4 == 0) ? 1.0 : 0.0;
-        return;
-    }
-    double ez[3] = {d[0] / R, d[1] / R, d[2] / R};
-    int k = 0;
-    for (int i = 1; i < 3; ++i)
-        if (std::fabs(ez[i]) < std::fabs(ez[k])) k = i;
     double ex[3] = {0, 0, 0};
-    ex[k] = 1.0;
-    const double p = ez[k];
+    if (ref) {
+        for (int i = 0; i < 3; ++i) ex[i] = ref[i];
+    } else {
+        int k = 0;
+        for (int i = 1; i < 3; ++i)
+            if (std::fabs(ez[i]) < std::fabs(ez[k])) k = i;
+        ex[k] = 1.0;
+    }
+    const double p = ex[0] * ez[0] + ex[1] * ez[1] + ex[2] * ez[2];
     for (int i = 0; i < 3; ++i) ex[i] -= p * ez[i];
     const double nx = std::sqrt(ex[0] * ex[0] + ex[1] * ex[1] + ex[2] * ex[2]);
     for (int i = 0; i < 3; ++i) ex[i] /= nx;
@@ -1827,54 +1826,97 @@ void bond_frame(const double *ra, const double *rb, double *Q)
     }
 }
 
+// Atoms within FK_GUESS_RCUT of `centre`, other than e1 and e2, ordered by
+// distance on a 1e-6 bohr grid, then index (atoms at distances equal by
+// symmetry keep one order in any orientation).
+void guess_neighbours(const fk_ctx *c, int centre, int e1, int e2, std::vector<std::pair<long long, int>> &out)
+{
+    out.clear();
+    for (int k = 0; k < c->natom; ++k) {
+        if (k == e1 || k == e2) continue;
+        double r2 = 0;
+        for (int i = 0; i < 3; ++i) {
+            const double d = c->xyz[3 * k + i] - c->xyz[3 * centre + i];
+            r2 += d * d;
+        }
+        const double r = std::sqrt(r2);
+        if (r < FK_GUESS_RCUT) out.push_back({(long long)std::floor(r * 1e6), k});
+    }
+    std::sort(out.begin(), out.end());
+}
+
+// First neighbour (from position `start`) whose direction from `origin` has a
+// component orthogonal to ez above 0.1 of its length; its vector in ref.
+bool guess_off_axis(const fk_ctx *c, int origin, const double *ez, const std::vector<std::pair<long long, int>> &nb,
+                    size_t start, double *ref)
+{
+    for (size_t i = start; i < nb.size(); ++i) {
+        const int k = nb[i].second;
+        double v[3], vv = 0, p = 0;
+        for (int j = 0; j < 3; ++j) {
+            v[j] = c->xyz[3 * k + j] - c->xyz[3 * origin + j];
+            vv += v[j] * v[j];
+            p += v[j] * ez[j];
+        }
+        double pp = 0;
+        for (int j = 0; j < 3; ++j) {
+            const double w = v[j] - p * ez[j];
+            pp += w * w;
+        }
+        if (std::sqrt(pp) > 0.1 * std::sqrt(vv)) {
+            for (int j = 0; j < 3; ++j) ref[j] = v[j];
+            return true;
+        }
+    }
+    return false;
+}
+
+// Frame of the pair (a, b): a != b: e_z from a to b, e_x towards the nearest
+// off-axis neighbour of a (else of b); a == b: e_z towards a's nearest
+// neighbour, e_x towards the next nearest off-axis one; missing neighbours:
+// lab axes (a lone atom: the lab frame).
+void local_frame(const fk_ctx *c, int a, int b, double *Q)
+{
+    std::vector<std::pair<long long, int>> nb;
+    double ez[3], ref[3];
+    if (a != b) {
+        double R = 0;
+        for (int i = 0; i < 3; ++i) {
+            ez[i] = c->xyz[3 * b + i] - c->xyz[3 * a + i];
+            R += ez[i] * ez[i];
+        }
+        R = std::sqrt(R);
+        for (int i = 0; i < 3; ++i) ez[i] /= R;
+        guess_neighbours(c, a, a, b, nb);
+        bool have = guess_off_axis(c, a, ez, nb, 0, ref);
+        if (!have) {
+            guess_neighbours(c, b, a, b, nb);
+            have = guess_off_axis(c, b, ez, nb, 0, ref);
+        }
+        frame_from(ez, have ? ref : nullptr, Q);
+        return;
+    }
+    guess_neighbours(c, a, a, a, nb);
+    if (nb.empty()) {
+        for (int i = 0; i < 9; ++i) Q[i] = (i % 4 == 0) ? 1.0 : 0.0;
+        return;
+    }
+    const int k = nb[0].second;
+    double R = 0;
+    for (int i = 0; i < 3; ++i) {
+        ez[i] = c->xyz[3 * k + i] - c->xyz[3 * a + i];
+        R += ez[i] * ez[i];
+    }
+    R = std::sqrt(R);
+    for (int i = 0; i < 3; ++i) ez[i] /= R;
+    const bool have = guess_off_axis(c, a, ez, nb, 1, ref);
+    frame_from(ez, have ? ref : nullptr, Q);
+}
+
 void transpose3(const double *Q, double *Qt)
 {
     for (int i = 0; i < 3; ++i)
         for (int j = 0; j < 3; ++j) Qt[j * 3 + i] = Q[i * 3 + j];
-}
-
-// The 60 rotations of an icosahedron from the unit quaternions of the binary
-// icosahedral group (one of each pair +-q): (1,0,0,0) and its coordinate
-// permutations, (+-1/2, +-1/2, +-1/2, +-1/2), and the even permutations of
-// (0, +-1, +-1/phi, +-phi) / 2.
-const std::vector<std::array<double, 9>> &icosahedral_rotations()
-{
-    static const std::vector<std::array<double, 9>> rots = [] {
-        std::vector<std::array<double, 9>> out;
-        const double g = (1.0 + std::sqrt(5.0)) / 2.0;
-        std::vector<std::array<double, 4>> qs;
-        for (int i = 0; i < 4; ++i) {
-            std::array<double, 4> q = {0, 0, 0, 0};
-            q[i] = 1.0;
-            qs.push_back(q);
-        }
-        for (int s = 0; s < 16; ++s)
-            qs.push_back({(s & 1) ? -0.5 : 0.5, (s & 2) ? -0.5 : 0.5, (s & 4) ? -0.5 : 0.5, (s & 8) ? -0.5 : 0.5});
-        const int even[12][4] = {{0, 1, 2, 3}, {0, 2, 3, 1}, {0, 3, 1, 2}, {1, 0, 3, 2}, {1, 2, 0, 3}, {1, 3, 2, 0},
-                                 {2, 0, 1, 3}, {2, 1, 3, 0}, {2, 3, 0, 1}, {3, 0, 2, 1}, {3, 1, 0, 2}, {3, 2, 1, 0}};
-        const double base[4] = {0.0, 0.5, 0.5 / g, 0.5 * g};
-        for (const auto &pm : even)
-            for (int s = 0; s < 8; ++s) {
-                std::array<double, 4> q;
-                for (int k = 0; k < 4; ++k) q[pm[k]] = base[k];
-                q[pm[1]] *= (s & 1) ? -1 : 1;
-                q[pm[2]] *= (s & 2) ? -1 : 1;
-                q[pm[3]] *= (s & 4) ? -1 : 1;
-                qs.push_back(q);
-            }
-        for (const auto &q : qs) {
-            // keep one of +-q: the first non-zero component positive
-            int k = 0;
-            while (q[k] == 0.0) ++k;
-            if (q[k] < 0) continue;
-            const double w = q[0], x = q[1], y = q[2], z = q[3];
-            out.push_back({1 - 2 * (y * y + z * z), 2 * (x * y - w * z), 2 * (x * z + w * y),
-                            2 * (x * y + w * z), 1 - 2 * (x * x + z * z), 2 * (y * z - w * x),
-                            2 * (x * z - w * y), 2 * (y * z + w * x), 1 - 2 * (x * x + y * y)});
-        }
-        return out;
-    }();  // initialised once, thread-safe
-    return rots;
 }
 
 int element_slot(int Z)
@@ -1934,7 +1976,16 @@ int guess_pair_list(fk_ctx *c, std::vector<GuessPairHost> &pairs)
     return FK_OK;
 }
 
-void guess_features(const fk_ctx *c, const GuessPairHost &p, float *x)
+// Features of a pair: element one-hots, radial Gaussians of the distance, and
+// for each of the two atoms the moments (1, u, u u^T) of the directions u (in
+// the pair frame Q) to its other neighbours within the cutoff, weighted by
+// two radial shells exp(-((r - c0) / w)^2), per neighbour element.
+constexpr double kEnvShell[2][2] = {{0.0, 3.0}, {5.0, 1.5}};
+constexpr int kEnvMom = 10;
+constexpr int kNEnv = 4 * 2 * kEnvMom;
+static_assert(8 + FK_GUESS_NRBF + 2 * kNEnv == FK_GUESS_NFEAT, "feature layout");
+
+void guess_features(const fk_ctx *c, const GuessPairHost &p, const double *Q, float *x)
 {
     for (int k = 0; k < FK_GUESS_NFEAT; ++k) x[k] = 0.0f;
     x[element_slot(c->Z[p.a1])] = 1.0f;
@@ -1948,6 +1999,33 @@ void guess_features(const fk_ctx *c, const GuessPairHost &p, float *x)
     for (int k = 0; k < FK_GUESS_NRBF; ++k) {
         const double u = (R - k * step) / step;
         x[8 + k] = (float)std::exp(-u * u);
+    }
+    const int base = 8 + FK_GUESS_NRBF;
+    double acc[2][kNEnv];
+    for (int side = 0; side < 2; ++side) {
+        const int at = side ? p.a2 : p.a1;
+        for (int i = 0; i < kNEnv; ++i) acc[side][i] = 0.0;
+        for (int k = 0; k < c->natom; ++k) {
+            if (k == p.a1 || k == p.a2) continue;
+            double v[3], rr = 0;
+            for (int j = 0; j < 3; ++j) {
+                v[j] = c->xyz[3 * k + j] - c->xyz[3 * at + j];
+                rr += v[j] * v[j];
+            }
+            const double r = std::sqrt(rr);
+            if (!(r < FK_GUESS_RCUT)) continue;
+            double u[3];
+            for (int j = 0; j < 3; ++j) u[j] = (Q[0 * 3 + j] * v[0] + Q[1 * 3 + j] * v[1] + Q[2 * 3 + j] * v[2]) / r;
+            const double mom[kEnvMom] = {1.0,         u[0],        u[1],        u[2],        u[0] * u[0],
+                                         u[0] * u[1], u[0] * u[2], u[1] * u[1], u[1] * u[2], u[2] * u[2]};
+            const int e = element_slot(c->Z[k]);
+            for (int sh = 0; sh < 2; ++sh) {
+                const double t = (r - kEnvShell[sh][0]) / kEnvShell[sh][1];
+                const double w = std::exp(-t * t);
+                for (int m = 0; m < kEnvMom; ++m) acc[side][(e * 2 + sh) * kEnvMom + m] += w * mom[m];
+            }
+        }
+        for (int i = 0; i < kNEnv; ++i) x[base + side * kNEnv + i] = (float)acc[side][i];
     }
 }
 
@@ -2185,8 +2263,12 @@ int fk_guess_pairs(fk_ctx *c, int *npair, float *features, int *shape)
     int rc;
     if ((rc = guess_pair_list(c, pairs)) || (rc = atom_ranges(c, f0, nf))) return rc;
     *npair = (int)pairs.size();
+    double Q[9];
     for (size_t p = 0; p < pairs.size(); ++p) {
-        if (features) guess_features(c, pairs[p], features + p * FK_GUESS_NFEAT);
+        if (features) {
+            local_frame(c, pairs[p].a1, pairs[p].a2, Q);
+            guess_features(c, pairs[p], Q, features + p * FK_GUESS_NFEAT);
+        }
         if (shape) shape[p] = (nf[pairs[p].a1] << 8) | nf[pairs[p].a2];
     }
     return FK_OK;
@@ -2202,39 +2284,21 @@ int fk_guess_targets(fk_ctx *c, const double *D, float *Y)
     if ((rc = guess_pair_list(c, pairs)) || (rc = atom_ranges(c, f0, nf))) return rc;
     constexpr int W = FK_GUESS_NB;
     const int n = c->nbf;
-    const auto &ico = icosahedral_rotations();
-    std::vector<std::array<double, 9>> zrot(8);
-    for (int k = 0; k < 8; ++k) {
-        const double ph = 2 * M_PI * k / 8, cs = std::cos(ph), sn = std::sin(ph);
-        zrot[k] = {cs, -sn, 0, sn, cs, 0, 0, 0, 1};
-    }
-    double B[W * W], Bb[W * W], T1[W * W], T2[W * W], H[W * W], acc[W * W], Q[9], Gt[9];
+    double B[W * W], Bb[W * W], T1[W * W], T2[W * W], H[W * W], Q[9];
     for (size_t p = 0; p < pairs.size(); ++p) {
         const int a1 = pairs[p].a1, a2 = pairs[p].a2, n1 = nf[a1], n2 = nf[a2];
         for (int i = 0; i < W * W; ++i) B[i] = 0.0;
         for (int i = 0; i < n1; ++i)
             for (int j = 0; j < n2; ++j) B[i * W + j] = D[(size_t)(f0[a1] + i) * n + f0[a2] + j];
-        // bond frame: D_bond = T(Q)^T D T(Q)
-        bond_frame(&c->xyz[3 * a1], &c->xyz[3 * a2], Q);
+        // pair frame: D_frame = T(Q)^T D T(Q)
+        local_frame(c, a1, a2, Q);
         atom_rotation(c, a1, Q, T1);
         atom_rotation(c, a2, Q, T2);
         blk_mul(B, false, T2, false, H);
         blk_mul(T1, true, H, false, Bb);
-        // average of the bond-frame molecule rotated by G: T(G^T)^T B T(G^T)
-        for (int i = 0; i < W * W; ++i) acc[i] = 0.0;
-        const bool onsite = a1 == a2;
-        const size_t nrot = onsite ? ico.size() : zrot.size();
-        for (size_t r = 0; r < nrot; ++r) {
-            transpose3(onsite ? ico[r].data() : zrot[r].data(), Gt);
-            atom_rotation(c, a1, Gt, T1);
-            atom_rotation(c, a2, Gt, T2);
-            blk_mul(Bb, false, T2, false, H);
-            blk_mul(T1, true, H, false, B);
-            for (int i = 0; i < W * W; ++i) acc[i] += B[i];
-        }
         float *y = Y + p * FK_GUESS_NOUT;
         for (int i = 0; i < W; ++i)
-            for (int j = 0; j < W; ++j) y[i * W + j] = (i < n1 && j < n2) ? (float)(acc[i * W + j] / nrot) : 0.0f;
+            for (int j = 0; j < W; ++j) y[i * W + j] = (i < n1 && j < n2) ? (float)Bb[i * W + j] : 0.0f;
     }
     return FK_OK;
 }
@@ -2385,10 +2449,10 @@ int guess_predict_device(fk_ctx *c, double *D, hipStream_t st)
     double Q[9], Qt[9];
     for (int p = 0; p < np; ++p) {
         const int a1 = pairs[p].a1, a2 = pairs[p].a2;
-        guess_features(c, pairs[p], &X[(size_t)p * FK_GUESS_NFEAT]);
+        local_frame(c, a1, a2, Q);
+        guess_features(c, pairs[p], Q, &X[(size_t)p * FK_GUESS_NFEAT]);
         gp[p] = FkGuessPair{a1, a2, f0[a1], f0[a2], nf[a1], nf[a2]};
         // D_lab = T(Q^T)^T B T(Q^T)
-        bond_frame(&c->xyz[3 * a1], &c->xyz[3 * a2], Q);
         transpose3(Q, Qt);
         atom_rotation(c, a1, Qt, &rot[(size_t)p * 2 * W * W]);
         atom_rotation(c, a2, Qt, &rot[(size_t)p * 2 * W * W + W * W]);

@@ -8,7 +8,7 @@ Training data: the geometries of ``synth.workloads.guess_geometry`` (alkanes
 C4-C16 and water clusters of 4-32 molecules, 6-31G*-type basis) except the
 held-out tail; each is converged by the library's SCF (from the SAD guess),
 and its density is cut into bond-frame pair blocks by ``fk_guess_targets``.
-The network (32 -> 256 -> 256 -> 225, SiLU) is trained with the library's
+The network (192 -> 256 -> 256 -> 225, SiLU) is trained with the library's
 forward, backward, masked-MSE and Adam kernels; PyTorch only holds the device
 arrays and gathers the shuffled minibatch rows.
 
@@ -94,8 +94,16 @@ def train(data, epochs, budget_s, batch=2048, lr=1e-3, seed=2407, val_frac=0.05)
     rng = np.random.default_rng(seed)
     rng.shuffle(keys)
     nval = max(1, int(len(keys) * val_frac))
+    # inputs are standardised on the host with the training set's mean and
+    # spread; the affine map is folded into the first layer afterwards
+    Xall = np.concatenate([data[k][0] for k in keys[nval:]]).astype(np.float64)
+    mu = Xall.mean(axis=0)
+    sd = Xall.std(axis=0)
+    sd[sd < 1e-6] = 1.0
+    del Xall
+
     def stack(ks):
-        X = np.concatenate([data[k][0] for k in ks])
+        X = ((np.concatenate([data[k][0] for k in ks]) - mu) / sd).astype(np.float32)
         S = np.concatenate([data[k][1] for k in ks])
         Y = np.concatenate([data[k][2] for k in ks])
         return (torch.from_numpy(X).to(dev), torch.from_numpy(S).to(dev), torch.from_numpy(Y).to(dev),
@@ -153,7 +161,12 @@ def train(data, epochs, budget_s, batch=2048, lr=1e-3, seed=2407, val_frac=0.05)
         if time.time() - t0 > budget_s:
             break
     torch.cuda.synchronize()
-    return [W.cpu().numpy() for W in Ws], [b.cpu().numpy() for b in bs], hist
+    W = [w.cpu().numpy().astype(np.float64) for w in Ws]
+    b = [v.cpu().numpy().astype(np.float64) for v in bs]
+    # fold the standardisation: ((x - mu) / sd) W0 + b0 = x (W0 / sd) + (b0 - (mu / sd) W0)
+    b[0] = b[0] - (mu / sd) @ W[0]
+    W[0] = W[0] / sd[:, None]
+    return [w.astype(np.float32) for w in W], [v.astype(np.float32) for v in b], hist
 
 
 def cmd_train(a):

@@ -114,7 +114,7 @@ def test_guess_predict_and_purify_match_oracle(fk):
     """Random seeded weights: the assembled prediction (network, bond-frame
     rotation, scatter) and the purified guess against the oracle."""
     s = _water2()
-    Ws, bs = _rand_mlp(0, [32, 256, 256, 225])
+    Ws, bs = _rand_mlp(0, [192, 256, 256, 225])
     c = fk.FockJK(0).set_system(s).build_quartets(tau=1e-10)
     c.set_guess_model(Ws, bs)
     D = c.guess_predict()

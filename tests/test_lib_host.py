@@ -245,11 +245,9 @@ def _guess_sys(kind):
 
 @pytest.mark.parametrize("kind", ["water2", "propane", "water2_sto3g"])
 def test_guess_features_and_targets_match_oracle(kind):
-    """Pair list, features, shapes and bond-frame targets (host) against the
+    """Pair list, features, shapes and pair-frame targets (host) against the
     oracle on a random density: the same pairs in the same order, features
-    to FP32 rounding, targets to FP32 rounding (the spherical on-site average
-    uses a differently oriented icosahedron on each side, so agreement also
-    shows both are full rotational averages)."""
+    and targets to FP32 rounding."""
     from oracle import guess as og
     s = _guess_sys(kind)
     c = fk.FockJK(device=-1).set_system(s)
@@ -275,7 +273,7 @@ def test_guess_errors():
     s = _guess_sys("water2")
     c = fk.FockJK(device=-1).set_system(s)
     with pytest.raises(fk.FockJKError) as e:  # weights live on a device
-        c.set_guess_model([np.zeros((32, 225))], [np.zeros(225)])
+        c.set_guess_model([np.zeros((fk.GUESS_NFEAT, 225))], [np.zeros(225)])
     assert e.value.code == fk.FK_ERR_STATE
     b = _small_batch()
     cb = fk.FockJK(device=-1).set_system(b).set_molecules(b["atom_mol"])

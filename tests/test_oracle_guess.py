@@ -74,56 +74,65 @@ def test_density_transforms_contravariantly():
     assert np.max(np.abs(Tt.T @ D @ Tt - D2)) < 1e-6
 
 
-def test_icosahedral_group():
-    """60 distinct proper rotations, closed under products; averaging over
-    them leaves a d-d block (degree 4 in the rotation) invariant under any
-    rotation, i.e. it is the full rotational average."""
-    G = og.icosahedral_rotations()
-    assert len(G) == 60
-    keys = {tuple(np.round(g, 6).ravel()) for g in G}
-    for g in G:
-        assert np.allclose(g @ g.T, np.eye(3), atol=1e-12) and np.linalg.det(g) > 0
-    for g, h in [(G[7], G[31]), (G[59], G[12])]:
-        assert tuple(np.round(g @ h, 6).ravel()) in keys
-    rng = np.random.default_rng(7)
-    B = rng.normal(size=(6, 6))
-    avg = sum(og.cart_rotation(2, g.T).T @ B @ og.cart_rotation(2, g.T) for g in G) / 60
-    Q = _rot(9)
-    assert np.allclose(og.cart_rotation(2, Q.T).T @ avg @ og.cart_rotation(2, Q.T), avg, atol=1e-12)
+def test_local_frame():
+    """Right-handed orthonormal frames: a pair's e_z along the pair and its
+    nearest off-axis neighbour in the x-z half-plane with x > 0; an atom's
+    own frame points e_z at its nearest neighbour; a lone atom keeps the lab
+    frame."""
+    xyz = np.array([[0.0, 0.0, 0.0], [1.8, 0.2, -0.1], [-0.6, 1.9, 0.3], [0.1, -0.2, 6.0]])
+    for a, b in [(0, 1), (1, 0), (0, 0), (2, 2), (3, 3), (0, 3)]:
+        Q = og.local_frame(xyz, a, b)
+        assert np.allclose(Q.T @ Q, np.eye(3), atol=1e-14) and np.linalg.det(Q) > 0
+    Q = og.local_frame(xyz, 0, 1)
+    assert np.allclose(Q[:, 2], xyz[1] / np.linalg.norm(xyz[1]))
+    v = Q.T @ (xyz[2] - xyz[0])  # atom 2, nearest off-axis neighbour of atom 0
+    assert v[0] > 0 and abs(v[1]) < 1e-14
+    Q = og.local_frame(xyz, 0, 0)
+    assert np.allclose(Q[:, 2], xyz[1] / np.linalg.norm(xyz[1]))
+    v = Q.T @ xyz[2]
+    assert v[0] > 0 and abs(v[1]) < 1e-14
+    assert np.allclose(og.local_frame(xyz[:1], 0, 0), np.eye(3))
 
 
-def test_bond_frame():
-    """Right-handed orthonormal frame with e_z along the bond."""
-    a, b = np.array([0.3, -1.0, 2.0]), np.array([1.1, 0.4, 1.7])
-    Q = og.bond_frame(a, b)
-    assert np.allclose(Q.T @ Q, np.eye(3), atol=1e-14) and np.linalg.det(Q) > 0
-    assert np.allclose(Q[:, 2], (b - a) / np.linalg.norm(b - a))
-    assert np.allclose(og.bond_frame(a, a), np.eye(3))
+def _dimer():
+    return wl.make_system(geom.water_cluster(2, 8), "6-31gs-type")
+
+
+def test_targets_round_trip():
+    """Blocks taken into their frames and assembled back reproduce every pair
+    block of a random symmetric density."""
+    s = _dimer()
+    rng = np.random.default_rng(2)
+    A = rng.normal(size=(s["nbf"], s["nbf"]))
+    D = A + A.T
+    pairs = og.pair_list(s)
+    Da = og.assemble(s, pairs, og.targets(s, D, pairs))
+    for a, b in pairs:
+        fa, fb = og.atom_functions(s, a), og.atom_functions(s, b)
+        assert np.max(np.abs(Da[np.ix_(fa, fb)] - D[np.ix_(fa, fb)])) < 1e-12
+
+
+def test_features_and_targets_turn_with_the_molecule():
+    """Rotating and translating the molecule changes neither the features nor
+    the pair-frame blocks of its SCF density: the frames are built from the
+    atoms, and the blocks transform with T (pinned above by the overlaps)."""
+    mol = geom.water_cluster(2, 8)
+    s = wl.make_system(mol, "6-31gs-type")
+    m2 = _rotated(mol, _rot(21))
+    m2["xyz"] = m2["xyz"] + np.array([0.7, -1.1, 0.4])
+    s2 = wl.make_system(m2, "6-31gs-type")
+    p1, p2 = og.pair_list(s), og.pair_list(s2)
+    assert p1 == p2
+    assert np.max(np.abs(og.features(s, p1) - og.features(s2, p2))) < 1e-12
+    Y1 = og.targets(s, run_scf(s)["D"], p1)
+    Y2 = og.targets(s2, run_scf(s2)["D"], p2)
+    assert np.max(np.abs(Y1 - Y2)) < 1e-6
 
 
 def _co():
     mol = {"Z": np.array([6, 8], dtype=np.int32), "charge": 0, "name": "CO",
            "xyz": np.array([[0.1, 0.2, -0.3], [0.1, 0.2, -0.3]]) + np.array([[0, 0, 0], [1.2, -0.9, 1.5]])}
     return mol
-
-
-def test_targets_round_trip_linear_molecule():
-    """The density of a closed-shell linear molecule is symmetric about its
-    axis, so the bond block survives the azimuthal average and assembly
-    unchanged (a wrong frame, rotation direction or average breaks this);
-    the block is also independent of how the molecule is oriented."""
-    mol = _co()
-    s = wl.make_system(mol, "6-31gs-type")
-    D = run_scf(s)["D"]
-    pairs = og.pair_list(s)
-    assert pairs == [(0, 0), (1, 0), (1, 1)]  # O (Z=8) first in the C-O pair
-    Y = og.targets(s, D, pairs)
-    Da = og.assemble(s, pairs, Y)
-    fC, fO = og.atom_functions(s, 0), og.atom_functions(s, 1)
-    assert np.max(np.abs(Da[np.ix_(fO, fC)] - D[np.ix_(fO, fC)])) < 1e-9
-    s2 = wl.make_system(_rotated(mol, _rot(11)), "6-31gs-type")
-    Y2 = og.targets(s2, run_scf(s2)["D"], og.pair_list(s2))
-    assert np.max(np.abs(Y2 - Y)) < 1e-6
 
 
 def test_features_closed_form():
@@ -139,6 +148,16 @@ def test_features_closed_form():
     assert X[1, 8 + k] == pytest.approx(math.exp(-((R - k * step) / step) ** 2), rel=1e-14)
     assert X[0, 8] == 1.0  # on-site pair: R = 0 at the first centre
     assert og.pair_shape(s, pairs) == [(15, 15), (15, 15), (15, 15)]
+    base = 8 + og.N_RBF
+    # the C-O pair: neither atom has a neighbour besides its partner
+    assert np.all(X[1, base:] == 0)
+    # carbon's own pair: oxygen (slot 3) on the frame's z axis, both shells
+    env = X[0, base:base + og.N_ENV].reshape(len(og.ELEMENTS), len(og.ENV_SHELLS), og.ENV_MOMENTS)
+    for sh, (c0, w) in enumerate(og.ENV_SHELLS):
+        wt = math.exp(-((R - c0) / w) ** 2)
+        assert np.allclose(env[3, sh], wt * np.array([1, 0, 0, 1, 0, 0, 0, 0, 0, 1]), atol=1e-15)
+    assert np.all(env[:3] == 0)
+    assert np.all(X[0, base:base + og.N_ENV] == X[0, base + og.N_ENV:])
 
 
 def test_pair_list_cutoff():
