@@ -14,7 +14,7 @@
 
 #include <algorithm>
 
-#include "fk_internal.h"
+#include "fk_guess.h"
 
 namespace {
 

@@ -17,6 +17,7 @@
 
 #include "fockjk.h"
 #include "fk_internal.h"
+#include "fk_guess.h"
 #include "fk_rys.h"
 
 namespace {
