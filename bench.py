@@ -180,6 +180,7 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--classes", action="store_true", help="print the per-class kernel table to stderr")
     ap.add_argument("--no-scf", action="store_true", help="skip the SCF run reported beside the build rate")
+    ap.add_argument("--autotune", action="store_true", help="tune the per-class kernel schedules before timing")
     ap.add_argument("--nmol", type=int, default=8, help="molecules of the organic batch (--workload c4)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MB",
                     help="only run a plain device copy of MB megabytes 5 times (calibrates HBM byte counters)")
@@ -212,6 +213,18 @@ def main():
     J = torch.empty_like(Dd)
     K = torch.empty_like(Dd)
     stream = torch.cuda.current_stream(dev)
+    tune = None
+    if args.autotune:
+        # schedule tuning before the timed region (lists rebuilt with the choice)
+        t_tune = time.perf_counter()
+        rep = ctx.autotune(Dd, reps=2, stream=stream.cuda_stream)
+        tune = {"seconds": time.perf_counter() - t_tune, "configurations": rep["configurations"],
+                "class_ms_sum_default": rep["build_ms_default"], "class_ms_sum_tuned": rep["build_ms_tuned"],
+                "classes": {f"({r['la']}{r['lb']}|{r['lc']}{r['ld']})/fp{r['precision']}":
+                            [r["bra_block"], r["kets_per_tile"], r["grid_fraction"], round(r["ms_default"], 4),
+                             round(r["ms_tuned"], 4)]
+                            for r in rep["classes"] if r["ms_default"] > 0.1},
+                "fields": "bra_block, kets_per_tile, grid_fraction, ms_default, ms_tuned (classes above 0.1 ms)"}
 
     for _ in range(args.warmup):
         ctx.build_jk(Dd, J, K, stream=stream)
@@ -270,7 +283,7 @@ def main():
         "flops_per_build": st["flops_total"], "tflops_build": st["flops_total"] / (ms * 1e-3) / 1e12,
         "wall_s_timed": wall,
         "roofline": {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
-                     "frac": achieved / peak, "traffic": _traffic(f"J/K class {cname}", args.workload),
+                     "frac": achieved / peak, "traffic": None if tune else _traffic(f"J/K class {cname}", args.workload),
                      "kernel": f"J/K class {cname}" + (" (FP32 part)" if c["precision"] == 32 else ""),
                      "kernel_ms": float(cls_ms[i]),
                      "class_share": float(cls_ms[i] / cls_ms.sum())},
@@ -297,6 +310,8 @@ def main():
                         "fp64_builds_per_s": 1000.0 / ms64, "speedup": ms64 / ms,
                         "max_abs_dJ": float(np.max(np.abs(dJ))), "max_abs_dK": float(np.max(np.abs(dK))),
                         "dE_one_build": float(0.5 * np.sum(D * dJ) - 0.25 * np.sum(D * dK))}
+    if tune:
+        out["autotune"] = tune
     if not args.no_scf:
         # SCF from the core-Hamiltonian guess on the same quartet lists (outside
         # the timed region): iterations to |dE| < 1e-10, max|error| < 1e-8

@@ -179,6 +179,45 @@ int fk_build_jk(fk_ctx *ctx, const double *D, double *J, double *K, unsigned fla
 /* Statistics of the last fk_build_jk (waits for it to finish). */
 int fk_stats(fk_ctx *ctx, fk_stats_t *stats);
 
+/* ---- kernel schedules ---------------------------------------------------
+ * Per quartet class (named by its momenta as fk_stats lists them), the
+ * schedule of its J/K kernel: bra_block = bras sharing their first shell per
+ * work tile (0 = fk_screen_opts.bra_block; capped by the class kernel),
+ * kets_per_tile = 1..64 kets per tile for the team and wave-per-quartet
+ * kernels (0 = two rounds; lane-per-quartet kernels always take 64),
+ * grid_fraction = share (0, 1] of the resident-workgroup grid that is
+ * launched (the persistent loop covers every tile either way).  A schedule
+ * changes the work order only, never the result beyond rounding order.
+ * Takes effect at the next fk_build_quartets; fk_set_geometry, fk_set_basis
+ * and fk_set_molecules clear all schedules. */
+int fk_set_class_schedule(fk_ctx *ctx, int la, int lb, int lc, int ld, int bra_block, int kets_per_tile,
+                          double grid_fraction);
+
+typedef struct {
+    int    nclass;                      /* class launches after tuning (as fk_stats) */
+    int    la[FK_MAX_QCLASS], lb[FK_MAX_QCLASS], lc[FK_MAX_QCLASS], ld[FK_MAX_QCLASS];
+    int    precision[FK_MAX_QCLASS];    /* 64 or 32 */
+    int    bra_block[FK_MAX_QCLASS], kets_per_tile[FK_MAX_QCLASS];
+    double grid_fraction[FK_MAX_QCLASS];
+    double ms_default[FK_MAX_QCLASS];   /* the launch's kernel time before tuning */
+    double ms_tuned[FK_MAX_QCLASS];
+    double build_ms_default, build_ms_tuned;  /* sums over the class launches */
+    int    configurations;              /* list configurations built and timed */
+} fk_tune_report;
+
+/* Autotuner for the schedules above: on the current geometry, basis and
+ * screening options (those of the last fk_build_quartets) and density D
+ * (as in fk_build_jk: FK_DEVICE_PTRS for a device pointer, else host), it
+ * tries one axis at a time for all classes at once -- bra_block 1..32, then
+ * 1, 2, 4, 8 rounds of kets per tile, then grid fractions 1, 1/2, 1/4 --
+ * rebuilding the lists and timing each class launch with HIP events (one
+ * warm-up and `reps` timed builds, the minimum kept), keeps for each class the
+ * candidate more than 2 % faster than its best so far, and leaves the lists
+ * built with the chosen schedules.  report may be NULL.  Runs about
+ * 14 (reps + 1) builds and 14 list builds; allocates three nbf^2 buffers for
+ * its duration. */
+int fk_autotune(fk_ctx *ctx, const double *D, unsigned flags, int reps, void *stream, fk_tune_report *report);
+
 /* ---- one-electron part and SCF (paper: "Hartree-Fock Energy Formulation") */
 /* Overlap S, kinetic T and nuclear attraction V (host arrays nbf x nbf) and the
  * nuclear repulsion energy.  Any output pointer may be NULL. */

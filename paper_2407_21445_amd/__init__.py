@@ -60,6 +60,15 @@ class Stats(ctypes.Structure):
                 ("team_size", ctypes.c_int * _Q), ("precision", ctypes.c_int * _Q), ("prim_slots", ctypes.c_int64 * _Q)]
 
 
+class TuneReport(ctypes.Structure):
+    _fields_ = [("nclass", ctypes.c_int), ("la", ctypes.c_int * _Q), ("lb", ctypes.c_int * _Q),
+                ("lc", ctypes.c_int * _Q), ("ld", ctypes.c_int * _Q), ("precision", ctypes.c_int * _Q),
+                ("bra_block", ctypes.c_int * _Q), ("kets_per_tile", ctypes.c_int * _Q),
+                ("grid_fraction", ctypes.c_double * _Q), ("ms_default", ctypes.c_double * _Q),
+                ("ms_tuned", ctypes.c_double * _Q), ("build_ms_default", ctypes.c_double),
+                ("build_ms_tuned", ctypes.c_double), ("configurations", ctypes.c_int)]
+
+
 class ScfOpts(ctypes.Structure):
     _fields_ = [("max_iter", ctypes.c_int), ("e_tol", ctypes.c_double), ("g_tol", ctypes.c_double),
                 ("diis_n", ctypes.c_int), ("guess", ctypes.c_int), ("lindep", ctypes.c_double)]
@@ -101,6 +110,8 @@ _sig = {
     "fk_set_molecules": ([_P, _I, _P], _I),
     "fk_molecule_layout": ([_P, _P, _P], _I),
     "fk_sad_density": ([_P, _P], _I),
+    "fk_set_class_schedule": ([_P, _I, _I, _I, _I, _I, _I, _D], _I),
+    "fk_autotune": ([_P, _P, _U, _I, _P, ctypes.POINTER(TuneReport)], _I),
     "fk_guess_pairs": ([_P, _P, _P, _P], _I),
     "fk_guess_targets": ([_P, _P, _P], _I),
     "fk_set_guess_model": ([_P, ctypes.POINTER(Mlp)], _I),
@@ -279,6 +290,28 @@ class FockJK:
         res = {k: getattr(r, k) for k, _ in ScfResult._fields_}
         res["D"] = D
         return res
+
+    # ---- kernel schedules ----
+    def set_class_schedule(self, la, lb, lc, ld, bra_block=0, kets_per_tile=0, grid_fraction=1.0):
+        self._check(_lib.fk_set_class_schedule(self._ctx, int(la), int(lb), int(lc), int(ld), int(bra_block),
+                                               int(kets_per_tile), float(grid_fraction)))
+        return self
+
+    def autotune(self, D, reps=2, stream=None):
+        """Tunes the class schedules on density D (numpy or device tensor);
+        returns the report as a dict with a per-launch list."""
+        r = TuneReport()
+        if _torch is not None and isinstance(D, _torch.Tensor):
+            rc = _lib.fk_autotune(self._ctx, ctypes.c_void_p(D.data_ptr()), FK_DEVICE_PTRS, int(reps),
+                                  ctypes.c_void_p(stream) if stream else None, ctypes.byref(r))
+        else:
+            Dc = np.ascontiguousarray(D, dtype=np.float64)
+            rc = _lib.fk_autotune(self._ctx, _ptr(Dc), 0, int(reps), None, ctypes.byref(r))
+        self._check(rc)
+        rows = [{k: getattr(r, k)[i] for k in ("la", "lb", "lc", "ld", "precision", "bra_block", "kets_per_tile",
+                                                 "grid_fraction", "ms_default", "ms_tuned")} for i in range(r.nclass)]
+        return {"classes": rows, "build_ms_default": r.build_ms_default, "build_ms_tuned": r.build_ms_tuned,
+                "configurations": r.configurations}
 
     # ---- initial guesses ----
     def sad_density(self):

@@ -47,6 +47,7 @@ struct QuartetClass {
     int64_t nquartet, nprim;  // Schwarz-surviving counts
     int64_t prim_slots;       // primitive-quartet slots the waves step through
     int blocks_per_cu;
+    double grid_frac = 1.0;   // share of the resident-workgroup grid launched
     int bra_slot;             // doubles per wave of staged bra primitive records
     int prec;                 // 0: FP64 launch, 1: FP32 launch of the precision split
 };
@@ -110,6 +111,9 @@ struct fk_ctx {
     bool stats_pending = false;
     bool timed = false;
     std::vector<hipEvent_t> ev;  // 2 per quartet class
+    // per quartet class schedule (key P * NPC + Q), from fk_set_class_schedule or fk_autotune
+    struct ClassSched { int bb = 0, kt = 0; double gf = 1.0; };
+    std::map<int, ClassSched> sched;
     // initial guesses
     std::vector<double> coef_in;                  // contraction coefficients as given
     std::map<int, std::vector<double>> sad_cache; // atomic density block per element
@@ -585,6 +589,7 @@ int fk_set_geometry(fk_ctx *c, int natom, const int *Z, const double *xyz, int c
     c->nelec = (int)ne;
     c->atom_mol.assign(natom, 0);
     c->sad_cache.clear();
+    c->sched.clear();
     c->have_geom = true;
     c->have_basis = false;
     c->have_quartets = false;
@@ -628,6 +633,7 @@ int fk_set_basis(fk_ctx *c, int nshell, const int *shell_atom, const int *shell_
     c->exps.assign(exps, exps + np);
     c->coef_in.assign(coefs, coefs + np);
     c->sad_cache.clear();
+    c->sched.clear();
     c->coef.assign(np, 0.0);
     c->bf_scale.assign(c->nbf, 1.0);
     for (int s = 0; s < nshell; ++s) {
@@ -663,6 +669,7 @@ int fk_set_molecules(fk_ctx *c, int nmol, const int *atom_mol)
         if (std::find(atom_mol, atom_mol + c->natom, m) == atom_mol + c->natom)
             return fail(c, FK_ERR_ARG, "fk_set_molecules: molecule %d has no atoms", m);
     c->atom_mol.assign(atom_mol, atom_mol + c->natom);
+    c->sched.clear();
     c->have_quartets = false;
     if (c->have_basis) {
         int rc;
@@ -818,7 +825,11 @@ int fk_build_quartets(fk_ctx *c, const fk_screen_opts *o)
             // kets per tile: a full wave of kets for lane-per-quartet kernels, two
             // rounds of teams for team kernels, two kets for wave-per-quartet
             const int ts = std::max(1, qc.info.team_size);
-            const int tile_kets = qc.info.wave_per_quartet == 0 ? 64 : std::max(1, 2 * (64 / ts));
+            const auto sit = c->sched.find(P * NPC + Q);
+            const fk_ctx::ClassSched sch = sit == c->sched.end() ? fk_ctx::ClassSched{} : sit->second;
+            int tile_kets = qc.info.wave_per_quartet == 0 ? 64 : std::max(1, 2 * (64 / ts));
+            if (qc.info.wave_per_quartet != 0 && sch.kt > 0) tile_kets = std::min(64, sch.kt);
+            qc.grid_frac = sch.gf;
             const int qpw = qc.info.wave_per_quartet == 0 ? 64 : (qc.info.wave_per_quartet == 3 ? 1 : 64 / ts);
             int max_bra_npp = 1;
             for (int p : LP) max_bra_npp = std::max(max_bra_npp, c->pr_npp[p]);
@@ -831,7 +842,7 @@ int fk_build_quartets(fk_ctx *c, const fk_screen_opts *o)
             }
             // bra blocks: the class's pairs ordered by (first shell, G descending),
             // cut into runs of at most bmax pairs with the same first shell
-            const int bmax = std::max(1, std::min(bra_block, qc.info.bra_block));
+            const int bmax = std::max(1, std::min(sch.bb > 0 ? std::min(sch.bb, FK_MAX_BRA_BLOCK) : bra_block, qc.info.bra_block));
             std::vector<int> ord(LP.size());
             std::iota(ord.begin(), ord.end(), 0);
             std::stable_sort(ord.begin(), ord.end(), [&](int x, int y) {
@@ -1068,7 +1079,7 @@ int fk_build_jk(fk_ctx *c, const double *D, double *J, double *K, unsigned flags
         // Enough workgroups for the hardware to fill every CU to its register and
         // LDS limit; the persistent loop covers the rest.
         const int64_t want = (qc.ntile + 3) / 4;
-        const int64_t cap = (int64_t)std::max(8, qc.blocks_per_cu) * std::max(c->ncu, 1);
+        const int64_t cap = std::max<int64_t>(1, (int64_t)(qc.grid_frac * std::max(8, qc.blocks_per_cu) * std::max(c->ncu, 1)));
         const int grid = (int)std::max<int64_t>(1, std::min(want, cap));
         if (fk_kernels_launch_jk(qc.P, qc.Q, &a, grid, st))
             return fail(c, FK_ERR_HIP, "J/K kernel launch failed for class (%d|%d)", qc.P, qc.Q);
@@ -1115,6 +1126,132 @@ int fk_stats(fk_ctx *c, fk_stats_t *s)
             float ms = 0;
             if (hipEventElapsedTime(&ms, c->ev[2 * i], c->ev[2 * i + 1]) == hipSuccess) s->class_ms[i] = ms;
         }
+    }
+    return FK_OK;
+}
+
+int fk_set_class_schedule(fk_ctx *c, int la, int lb, int lc, int ld, int bra_block, int kets_per_tile,
+                          double grid_fraction)
+{
+    if (!c) return FK_ERR_ARG;
+    if (la < lb || lc < ld || la > FK_MAX_L || lc > FK_MAX_L || lb < 0 || ld < 0)
+        return fail(c, FK_ERR_ARG, "fk_set_class_schedule: need la >= lb, lc >= ld, l <= %d", FK_MAX_L);
+    int P = pair_class(la, lb), Q = pair_class(lc, ld);
+    if (P < Q) std::swap(P, Q);
+    if (bra_block < 0 || bra_block > FK_MAX_BRA_BLOCK || kets_per_tile < 0 || kets_per_tile > 64 ||
+        !(grid_fraction > 0 && grid_fraction <= 1))
+        return fail(c, FK_ERR_ARG, "fk_set_class_schedule: bra_block 0..%d, kets_per_tile 0..64, grid_fraction (0, 1]",
+                    FK_MAX_BRA_BLOCK);
+    c->sched[P * NPC + Q] = fk_ctx::ClassSched{bra_block, kets_per_tile, grid_fraction};
+    return FK_OK;
+}
+
+int fk_autotune(fk_ctx *c, const double *D, unsigned flags, int reps, void *stream, fk_tune_report *rep)
+{
+    if (!c) return FK_ERR_ARG;
+    if (!D) return fail(c, FK_ERR_ARG, "fk_autotune: null density");
+    if (c->device < 0) return fail(c, FK_ERR_STATE, "fk_autotune: context has no device");
+    if (!c->have_quartets) return fail(c, FK_ERR_STATE, "fk_autotune: call fk_build_quartets first");
+    if (reps < 1 || reps > 100) return fail(c, FK_ERR_ARG, "fk_autotune: reps must be 1..100");
+    if (rep) std::memset(rep, 0, sizeof *rep);
+    hipSetDevice(c->device);
+    hipStream_t st = (hipStream_t)stream;
+    const fk_screen_opts opts = c->opts;
+    int rc;
+    // resident copies of D, J, K for the timed builds
+    DevBuf<double> dD, dJ, dK;
+    struct Free { DevBuf<double> *b[3]; ~Free() { for (auto *x : b) dev_free(*x); } } fr{{&dD, &dJ, &dK}};
+    const size_t nm = c->mol_base.empty() ? (size_t)c->nbf * c->nbf : (size_t)c->mol_base[c->nmol];
+    if ((rc = dev_upload<double>(c, dD, nullptr, nm)) || (rc = dev_upload<double>(c, dJ, nullptr, nm)) ||
+        (rc = dev_upload<double>(c, dK, nullptr, nm)))
+        return rc;
+    HIPCHK(c, hipMemcpy(dD.p, D, nm * sizeof(double), (flags & FK_DEVICE_PTRS) ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice));
+    // times of the class launches (key P * NPC + Q, both precisions summed) for
+    // the current schedules: min over reps of each launch
+    int configs = 0;
+    auto measure = [&](std::map<int, double> &t, std::vector<double> *per_launch) -> int {
+        int r;
+        if ((r = fk_build_quartets(c, &opts))) return r;
+        ++configs;
+        std::vector<double> best(c->qclasses.size(), 1e300);
+        for (int k = 0; k <= reps; ++k) {  // the first build warms up
+            if ((r = fk_build_jk(c, dD.p, dJ.p, dK.p, FK_DEVICE_PTRS | FK_SYNC | FK_TIME_CLASSES, st))) return r;
+            if (k == 0) continue;
+            for (size_t i = 0; i < c->qclasses.size(); ++i) {
+                float ms = 0;
+                if (hipEventElapsedTime(&ms, c->ev[2 * i], c->ev[2 * i + 1]) == hipSuccess) best[i] = std::min(best[i], (double)ms);
+            }
+        }
+        t.clear();
+        for (size_t i = 0; i < c->qclasses.size(); ++i) t[c->qclasses[i].P * NPC + c->qclasses[i].Q] += best[i];
+        if (per_launch) *per_launch = best;
+        return FK_OK;
+    };
+    const std::map<int, fk_ctx::ClassSched> start = c->sched;
+    std::map<int, double> t0;
+    std::vector<double> launch0;
+    if ((rc = measure(t0, &launch0))) return rc;
+    struct Key { int P, Q, prec; };
+    std::vector<Key> keys0;
+    for (const auto &q : c->qclasses) keys0.push_back({q.P, q.Q, q.prec});
+    std::map<int, fk_ctx::ClassSched> cur;
+    for (const auto &kv : t0) {
+        auto it = start.find(kv.first);
+        cur[kv.first] = it == start.end() ? fk_ctx::ClassSched{} : it->second;
+    }
+    std::map<int, double> tbest = t0;
+    // one axis at a time, every class measured under each candidate value
+    for (int axis = 0; axis < 3; ++axis) {
+        std::vector<double> vals;
+        if (axis == 0) vals = {1, 2, 4, 8, 16, 32};
+        else if (axis == 1) vals = {1, 2, 4, 8};   // rounds of kets (team and wave kernels)
+        else vals = {1.0, 0.5, 0.25};
+        for (double v : vals) {
+            std::map<int, fk_ctx::ClassSched> trial = cur;
+            for (auto &kv : trial) {
+                const int P = kv.first / NPC, Q = kv.first % NPC;
+                FkClassInfo info;
+                if (fk_kernels_class_info(P, Q, &info)) continue;
+                if (axis == 0) kv.second.bb = (int)v;
+                else if (axis == 1) {
+                    if (info.wave_per_quartet == 0) continue;
+                    const int qpw = info.wave_per_quartet == 3 ? 1 : 64 / std::max(1, info.team_size);
+                    kv.second.kt = std::min(64, (int)v * qpw);
+                } else kv.second.gf = v;
+            }
+            c->sched = trial;
+            std::map<int, double> t;
+            if ((rc = measure(t, nullptr))) { c->sched = start; fk_build_quartets(c, &opts); return rc; }
+            for (auto &kv : t) {
+                auto b = tbest.find(kv.first);
+                if (b == tbest.end() || kv.second < b->second * 0.98) {  // 2 %: above timing noise
+                    tbest[kv.first] = kv.second;
+                    cur[kv.first] = trial[kv.first];
+                }
+            }
+        }
+    }
+    c->sched = cur;
+    std::map<int, double> t1;
+    std::vector<double> launch1;
+    if ((rc = measure(t1, &launch1))) return rc;
+    if (rep) {
+        rep->nclass = (int)c->qclasses.size();
+        rep->configurations = configs;
+        for (size_t i = 0; i < c->qclasses.size(); ++i) {
+            const auto &q = c->qclasses[i];
+            const auto &sc = c->sched[q.P * NPC + q.Q];
+            rep->la[i] = q.info.la; rep->lb[i] = q.info.lb; rep->lc[i] = q.info.lc; rep->ld[i] = q.info.ld;
+            rep->precision[i] = q.prec ? 32 : 64;
+            rep->bra_block[i] = std::max(1, std::min(sc.bb > 0 ? sc.bb : (opts.bra_block > 0 ? opts.bra_block : 8), q.info.bra_block));
+            rep->kets_per_tile[i] = q.info.wave_per_quartet == 0 ? 64 : (sc.kt > 0 ? sc.kt : 2 * (q.info.wave_per_quartet == 3 ? 1 : 64 / std::max(1, q.info.team_size)));
+            rep->grid_fraction[i] = sc.gf;
+            rep->ms_tuned[i] = launch1[i];
+            for (size_t j = 0; j < keys0.size(); ++j)
+                if (keys0[j].P == q.P && keys0[j].Q == q.Q && keys0[j].prec == q.prec) rep->ms_default[i] = launch0[j];
+            rep->build_ms_tuned += launch1[i];
+        }
+        for (double x : launch0) rep->build_ms_default += x;
     }
     return FK_OK;
 }

@@ -272,3 +272,20 @@ def test_build_in_hip_graph(fk, torch):
         assert torch.max(torch.abs(J - J0)).item() <= 1e-12, rep
         assert torch.max(torch.abs(K - K0)).item() <= 1e-12, rep
         c.build_jk(Dd, sync=True)  # eager work between replays
+
+
+def test_autotune_keeps_results(fk, torch):
+    """The autotuner only reorders work: after tuning, unscreened J/K of
+    C2H6 / 6-31G*-type still equal the oracle within 1e-10, and the report
+    covers every launch with positive times."""
+    s = wl.alkane_sys(2, "6-31gs-type")
+    S, T, V = oracle.oneel(s)
+    D = core_guess(T + V, orthogonalizer(S), s["nelec"] // 2)
+    c = fk.FockJK(0).set_system(s).build_quartets(tau=0.0)
+    rep = c.autotune(torch.tensor(D, device="cuda:0"), reps=1)
+    assert rep["configurations"] == 15 and len(rep["classes"]) == c.info()["nquartet_class"]
+    assert all(r["ms_tuned"] > 0 and r["ms_default"] > 0 for r in rep["classes"])
+    c.check_indices()
+    J, K = c.build_jk(D)
+    Jo, Ko = oracle.jk(s, D)
+    assert np.max(np.abs(J - Jo)) < 1e-10 and np.max(np.abs(K - Ko)) < 1e-10

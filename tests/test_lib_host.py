@@ -282,3 +282,33 @@ def test_guess_errors():
     assert e.value.code == fk.FK_ERR_UNSUPPORTED
     m = fk.mlp_struct([32, 225], [None], [None])
     assert fk._lib.fk_mlp_forward(fk.ctypes.byref(m), None, 1, None, None, None) == fk.FK_ERR_ARG
+
+
+# ------------------------------------------------------------ kernel schedules
+@pytest.mark.parametrize("sched", [(32, 64, 0.25), (1, 1, 1.0), (3, 17, 0.5)])
+def test_class_schedules_keep_the_lists(sched):
+    """Any schedule regroups the same Schwarz quartets into tiles: the quartet
+    count is unchanged and every kernel address stays in bounds."""
+    s = wl.alkane_sys(3, "6-31gs-type")
+    ref = fk.FockJK(device=-1).set_system(s).build_quartets(tau=1e-10).info()
+    c = fk.FockJK(device=-1).set_system(s)
+    for la in range(3):
+        for lb in range(la + 1):
+            for lc in range(3):
+                for ld in range(lc + 1):
+                    c.set_class_schedule(la, lb, lc, ld, *sched)
+    c.build_quartets(tau=1e-10)
+    c.check_indices()
+    assert c.info()["nquartet_schwarz"] == ref["nquartet_schwarz"]
+
+
+def test_class_schedule_errors():
+    c = fk.FockJK(device=-1).set_system(wl.water4_sto3g())
+    for bad in [(0, 1, 0, 0, 0, 0, 1.0), (1, 0, 0, 0, 33, 0, 1.0), (1, 0, 0, 0, 0, 65, 1.0), (1, 0, 0, 0, 0, 0, 0.0)]:
+        with pytest.raises(fk.FockJKError) as e:
+            c.set_class_schedule(*bad)
+        assert e.value.code == fk.FK_ERR_ARG
+    c.build_quartets(tau=0.0)
+    with pytest.raises(fk.FockJKError) as e:
+        c.autotune(np.zeros((28, 28)))
+    assert e.value.code == fk.FK_ERR_STATE
