@@ -199,6 +199,7 @@ typedef struct {
     int    precision[FK_MAX_QCLASS];    /* 64 or 32 */
     int    bra_block[FK_MAX_QCLASS], kets_per_tile[FK_MAX_QCLASS];
     double grid_fraction[FK_MAX_QCLASS];
+    int    changed[FK_MAX_QCLASS];      /* 1 if the schedule differs from the one before tuning */
     double ms_default[FK_MAX_QCLASS];   /* the launch's kernel time before tuning */
     double ms_tuned[FK_MAX_QCLASS];
     double build_ms_default, build_ms_tuned;  /* sums over the class launches */

@@ -64,7 +64,8 @@ class TuneReport(ctypes.Structure):
     _fields_ = [("nclass", ctypes.c_int), ("la", ctypes.c_int * _Q), ("lb", ctypes.c_int * _Q),
                 ("lc", ctypes.c_int * _Q), ("ld", ctypes.c_int * _Q), ("precision", ctypes.c_int * _Q),
                 ("bra_block", ctypes.c_int * _Q), ("kets_per_tile", ctypes.c_int * _Q),
-                ("grid_fraction", ctypes.c_double * _Q), ("ms_default", ctypes.c_double * _Q),
+                ("grid_fraction", ctypes.c_double * _Q), ("changed", ctypes.c_int * _Q),
+                ("ms_default", ctypes.c_double * _Q),
                 ("ms_tuned", ctypes.c_double * _Q), ("build_ms_default", ctypes.c_double),
                 ("build_ms_tuned", ctypes.c_double), ("configurations", ctypes.c_int)]
 
@@ -309,7 +310,7 @@ class FockJK:
             rc = _lib.fk_autotune(self._ctx, _ptr(Dc), 0, int(reps), None, ctypes.byref(r))
         self._check(rc)
         rows = [{k: getattr(r, k)[i] for k in ("la", "lb", "lc", "ld", "precision", "bra_block", "kets_per_tile",
-                                                 "grid_fraction", "ms_default", "ms_tuned")} for i in range(r.nclass)]
+                                                 "grid_fraction", "changed", "ms_default", "ms_tuned")} for i in range(r.nclass)]
         return {"classes": rows, "build_ms_default": r.build_ms_default, "build_ms_tuned": r.build_ms_tuned,
                 "configurations": r.configurations}
 

@@ -1246,6 +1246,9 @@ int fk_autotune(fk_ctx *c, const double *D, unsigned flags, int reps, void *stre
             rep->bra_block[i] = std::max(1, std::min(sc.bb > 0 ? sc.bb : (opts.bra_block > 0 ? opts.bra_block : 8), q.info.bra_block));
             rep->kets_per_tile[i] = q.info.wave_per_quartet == 0 ? 64 : (sc.kt > 0 ? sc.kt : 2 * (q.info.wave_per_quartet == 3 ? 1 : 64 / std::max(1, q.info.team_size)));
             rep->grid_fraction[i] = sc.gf;
+            const auto s0 = start.find(q.P * NPC + q.Q);
+            const fk_ctx::ClassSched sc0 = s0 == start.end() ? fk_ctx::ClassSched{} : s0->second;
+            rep->changed[i] = (sc0.bb != sc.bb || sc0.kt != sc.kt || sc0.gf != sc.gf) ? 1 : 0;
             rep->ms_tuned[i] = launch1[i];
             for (size_t j = 0; j < keys0.size(); ++j)
                 if (keys0[j].P == q.P && keys0[j].Q == q.Q && keys0[j].prec == q.prec) rep->ms_default[i] = launch0[j];
