@@ -1248,7 +1248,15 @@ int fk_autotune(fk_ctx *c, const double *D, unsigned flags, int reps, void *stre
             rep->grid_fraction[i] = sc.gf;
             const auto s0 = start.find(q.P * NPC + q.Q);
             const fk_ctx::ClassSched sc0 = s0 == start.end() ? fk_ctx::ClassSched{} : s0->second;
-            rep->changed[i] = (sc0.bb != sc.bb || sc0.kt != sc.kt || sc0.gf != sc.gf) ? 1 : 0;
+            // compare the schedules in effect (a candidate equal to the default is no change)
+            auto eff_bb = [&](const fk_ctx::ClassSched &x) {
+                return std::max(1, std::min(x.bb > 0 ? x.bb : (opts.bra_block > 0 ? opts.bra_block : 8), q.info.bra_block));
+            };
+            auto eff_kt = [&](const fk_ctx::ClassSched &x) {
+                if (q.info.wave_per_quartet == 0) return 64;
+                return x.kt > 0 ? x.kt : 2 * (q.info.wave_per_quartet == 3 ? 1 : 64 / std::max(1, q.info.team_size));
+            };
+            rep->changed[i] = (eff_bb(sc0) != eff_bb(sc) || eff_kt(sc0) != eff_kt(sc) || sc0.gf != sc.gf) ? 1 : 0;
             rep->ms_tuned[i] = launch1[i];
             for (size_t j = 0; j < keys0.size(); ++j)
                 if (keys0[j].P == q.P && keys0[j].Q == q.Q && keys0[j].prec == q.prec) rep->ms_default[i] = launch0[j];
