@@ -114,13 +114,30 @@ def bench_batch(args, torch, fk):
     from synth import workloads as wl
     b = wl.organic_batch(args.nmol)
     ctx = fk.FockJK(0).set_system(b).set_molecules(b["atom_mol"])
-    ctx.build_quartets(tau=args.tau, tau_prim=args.tau_prim, tau_fp32=args.tau_fp32)
-    info = ctx.info()
     Ds = []
     for m in b["mols"]:
         h = fk.FockJK(-1).set_system(m)
         S, T, V, _ = h.one_electron()
         Ds.append(_core_density(S, T + V, m["nelec"] // 2).ravel())
+    tune = None
+    if args.autotune:
+        # schedules tuned on a two-molecule batch of the same set, applied to all
+        t_tune = time.perf_counter()
+        nsub = min(2, args.nmol)
+        sb = wl.batch(b["mols"][:nsub])
+        sub = fk.FockJK(0).set_system(sb).set_molecules(sb["atom_mol"])
+        sub.build_quartets(tau=args.tau, tau_prim=args.tau_prim, tau_fp32=args.tau_fp32)
+        rep = sub.autotune(np.concatenate(Ds[:nsub]), reps=1)
+        for r in rep["classes"]:
+            ctx.set_class_schedule(r["la"], r["lb"], r["lc"], r["ld"], r["bra_block"], r["kets_per_tile"],
+                                   r["grid_fraction"])
+        tune = {"seconds": time.perf_counter() - t_tune, "tuned_on": f"first {nsub} molecules",
+                "configurations": rep["configurations"], "class_ms_sum_default": rep["build_ms_default"],
+                "class_ms_sum_tuned": rep["build_ms_tuned"],
+                "changed_classes": sum(r["changed"] for r in rep["classes"])}
+        del sub
+    ctx.build_quartets(tau=args.tau, tau_prim=args.tau_prim, tau_fp32=args.tau_fp32)
+    info = ctx.info()
     dev = torch.device("cuda:0")
     Dd = torch.tensor(np.concatenate(Ds), dtype=torch.float64, device=dev)
     J = torch.empty_like(Dd)
@@ -164,6 +181,20 @@ def bench_batch(args, torch, fk):
         "quartets_per_build": st["quartets"], "schwarz_quartets": info["nquartet_schwarz"],
         "tflops_build": st["flops_total"] / (ms * 1e-3) / 1e12,
     }
+    if tune:
+        out["autotune"] = tune
+    if args.batch_scf:
+        # batched SCF of every molecule from SAD (outside the timed region)
+        rs, _ = ctx.run_scf_batch(guess=fk.GUESS_SAD)
+        out["scf_batch"] = {"iterations": rs[0]["iterations"], "converged": int(sum(r["converged"] for r in rs)),
+                            "seconds": rs[0]["total_seconds"], "jk_seconds": rs[0]["jk_seconds"],
+                            "energies": [r["energy"] for r in rs]}
+        if args.tau_fp32 > 0:
+            ref = fk.FockJK(0).set_system(b).set_molecules(b["atom_mol"])
+            ref.build_quartets(tau=args.tau, tau_prim=args.tau_prim)
+            r64, _ = ref.run_scf_batch(guess=fk.GUESS_SAD)
+            out["scf_batch"]["fp64_seconds"] = r64[0]["total_seconds"]
+            out["scf_batch"]["max_abs_energy_diff_vs_fp64"] = max(abs(a["energy"] - c["energy"]) for a, c in zip(rs, r64))
     print(json.dumps(out), flush=True)
     return 0
 
@@ -183,6 +214,7 @@ def main():
     ap.add_argument("--no-autotune", dest="autotune", action="store_false",
                     help="time the default kernel schedules (the autotuner runs by default, before timing)")
     ap.add_argument("--nmol", type=int, default=8, help="molecules of the organic batch (--workload c4)")
+    ap.add_argument("--batch-scf", action="store_true", help="--workload c4: also run the batched SCF")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MB",
                     help="only run a plain device copy of MB megabytes 5 times (calibrates HBM byte counters)")
     ap.add_argument("--tau-fp32", type=float, default=0.0,

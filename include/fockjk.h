@@ -269,6 +269,20 @@ typedef struct {
  * filled) if max_iter is reached, or if the purification finds no gap. */
 int fk_run_scf(fk_ctx *ctx, const fk_scf_opts *opts, fk_scf_result *result, double *D_inout);
 
+/* Batched SCF (several molecules in one context, fk_set_molecules): the SCF
+ * step above for every molecule at once -- one batched fk_build_jk per
+ * iteration, every dense step (orthogonaliser, Fock matrix, energies, DIIS
+ * commutators, purification, D = X D' X) a batched kernel over the
+ * concatenated per-molecule blocks, with each molecule's DIIS system and
+ * purification choices solved on the host.  Molecules must be neutral and
+ * closed shell.  Iterates until every molecule meets the criteria of
+ * fk_run_scf in the same iteration.  results: nmol entries (iterations,
+ * jk_seconds and total_seconds are the batch's); D_inout: host array of the
+ * batch layout (fk_molecule_layout), the guess for guess = 1 and the final
+ * densities on return.  guess = 3 starts from SAD (guess_used = 2): the
+ * learned guess is per molecule.  max_iter = 0 returns the initial densities. */
+int fk_run_scf_batch(fk_ctx *ctx, const fk_scf_opts *opts, fk_scf_result *results, double *D_inout);
+
 /* ---- initial densities (an extension: the paper's SCF starts from a
  * conventional guess and has no learned part) ---------------------------- */
 
@@ -277,8 +291,9 @@ int fk_run_scf(fk_ctx *ctx, const fk_scf_opts *opts, fk_scf_result *result, doub
  * D = sum n_i c_i c_i^T, aufbau over levels of orbitals within 1e-4 hartree,
  * a partly filled level sharing its electrons equally, damped iteration
  * from the core guess until max |dD| < 1e-10); the molecule's density is
- * block diagonal over its atoms.  Host computation; D_out is a host
- * nbf x nbf array.  Works on a context without a device. */
+ * block diagonal over its atoms.  Host computation; D_out is a host array
+ * of nbf x nbf (a batch: of the batch layout, fk_molecule_layout).  Works on
+ * a context without a device. */
 int fk_sad_density(fk_ctx *ctx, double *D_out);
 
 /* Learned guess.  Atom pairs: every atom with itself and every pair closer

@@ -111,6 +111,7 @@ _sig = {
     "fk_set_molecules": ([_P, _I, _P], _I),
     "fk_molecule_layout": ([_P, _P, _P], _I),
     "fk_sad_density": ([_P, _P], _I),
+    "fk_run_scf_batch": ([_P, ctypes.POINTER(ScfOpts), _P, _P], _I),
     "fk_set_class_schedule": ([_P, _I, _I, _I, _I, _I, _I, _D], _I),
     "fk_autotune": ([_P, _P, _U, _I, _P, ctypes.POINTER(TuneReport)], _I),
     "fk_guess_pairs": ([_P, _P, _P, _P], _I),
@@ -314,9 +315,29 @@ class FockJK:
         return {"classes": rows, "build_ms_default": r.build_ms_default, "build_ms_tuned": r.build_ms_tuned,
                 "configurations": r.configurations}
 
+    def run_scf_batch(self, D0=None, max_iter=100, e_tol=1e-10, g_tol=1e-8, diis_n=8, lindep=1e-8, guess=None):
+        """SCF of every molecule of a batch at once; returns (list of per-molecule
+        result dicts, flat density array in the batch layout)."""
+        nmol = self.info()["nmol"]
+        nmat = self.info()["nmat"]
+        D = np.zeros(nmat) if D0 is None else np.ascontiguousarray(D0, dtype=np.float64).reshape(-1).copy()
+        if guess is None:
+            guess = GUESS_CORE if D0 is None else GUESS_GIVEN
+        o = ScfOpts(int(max_iter), float(e_tol), float(g_tol), int(diis_n), int(guess), float(lindep))
+        rs = (ScfResult * nmol)()
+        rc = _lib.fk_run_scf_batch(self._ctx, ctypes.byref(o), rs, _ptr(D))
+        if rc not in (FK_OK, FK_ERR_NOT_CONVERGED):
+            self._check(rc)
+        return [{k: getattr(r, k) for k, _ in ScfResult._fields_} for r in rs], D
+
     # ---- initial guesses ----
     def sad_density(self):
-        D = np.zeros((self.nbf, self.nbf))
+        """SAD density (nbf x nbf; a batch: the flat batch layout)."""
+        info = self.info()
+        if info["nmol"] > 1:
+            D = np.zeros(info["nmat"])
+        else:
+            D = np.zeros((self.nbf, self.nbf))
         self._check(_lib.fk_sad_density(self._ctx, _ptr(D)))
         return D
 

@@ -44,6 +44,7 @@ def build(maxl: int = 3, jobs: int | None = None, verbose: bool = False, extra=(
                   ["-DFK_ONLY_P=-1"]))
     units.append((os.path.join(CSRC, "fk_scf.hip"), os.path.join(BUILD, "fk_scf.o"), []))
     units.append((os.path.join(CSRC, "fk_guess.hip"), os.path.join(BUILD, "fk_guess.o"), []))
+    units.append((os.path.join(CSRC, "fk_scf_batch.hip"), os.path.join(BUILD, "fk_scf_batch.o"), []))
     units.append((os.path.join(CSRC, "fk_host.cpp"), os.path.join(BUILD, "fk_host.o"), ["-x", "hip"]))
     cmds = [[HIPCC] + COMMON + defs + u[2] + ["-c", u[0], "-o", u[1]] for u in units]
     with cf.ThreadPoolExecutor(jobs) as ex:

@@ -18,6 +18,7 @@
 #include "fockjk.h"
 #include "fk_internal.h"
 #include "fk_guess.h"
+#include "fk_scf_batch.h"
 #include "fk_rys.h"
 
 namespace {
@@ -2381,13 +2382,19 @@ int fk_sad_density(fk_ctx *c, double *D_out)
     if (!c) return FK_ERR_ARG;
     if (!D_out) return fail(c, FK_ERR_ARG, "fk_sad_density: null output");
     if (!c->have_basis) return fail(c, FK_ERR_STATE, "fk_sad_density: geometry and basis not set");
-    if (c->nmol > 1) return fail(c, FK_ERR_UNSUPPORTED, "fk_sad_density: one molecule per context");
-    std::vector<int> f0, nf;
+    // each atom's block sits in its molecule's block (one molecule: the whole matrix)
+    std::vector<int> lf0(c->natom, -1), nf(c->natom, 0);
+    for (int s = 0; s < c->nshell; ++s) {
+        const int a = c->sh_atom[s];
+        if (lf0[a] < 0) lf0[a] = c->sh_lbf[s];
+        else if (lf0[a] + nf[a] != c->sh_lbf[s])
+            return fail(c, FK_ERR_UNSUPPORTED, "fk_sad_density: the shells of atom %d are not consecutive", a);
+        nf[a] += ncart(c->sh_l[s]);
+    }
+    std::fill(D_out, D_out + (size_t)c->mol_base[c->nmol], 0.0);
     int rc;
-    if ((rc = atom_ranges(c, f0, nf))) return rc;
-    const int n = c->nbf;
-    std::fill(D_out, D_out + (size_t)n * n, 0.0);
     for (int a = 0; a < c->natom; ++a) {
+        if (nf[a] == 0) continue;
         auto it = c->sad_cache.find(c->Z[a]);
         if (it == c->sad_cache.end()) {
             std::vector<double> Dat;
@@ -2397,8 +2404,10 @@ int fk_sad_density(fk_ctx *c, double *D_out)
         const std::vector<double> &Dat = it->second;
         const int m = nf[a];
         if ((int)Dat.size() != m * m) return fail(c, FK_ERR_ARG, "fk_sad_density: atoms of element %d differ in basis", c->Z[a]);
+        const int mol = c->atom_mol[a], n = c->mol_nbf[mol];
+        double *Dm = D_out + c->mol_base[mol];
         for (int i = 0; i < m; ++i)
-            for (int j = 0; j < m; ++j) D_out[(size_t)(f0[a] + i) * n + f0[a] + j] = Dat[(size_t)i * m + j];
+            for (int j = 0; j < m; ++j) Dm[(size_t)(lf0[a] + i) * n + lf0[a] + j] = Dat[(size_t)i * m + j];
     }
     return FK_OK;
 }
@@ -2631,5 +2640,356 @@ extern "C" int fk_guess_predict(fk_ctx *c, double *D_out)
     if ((rc = dev_upload<double>(c, c->g_D, nullptr, nn))) return rc;
     if ((rc = guess_predict_device(c, c->g_D.p, nullptr))) return rc;
     HIPCHK(c, hipMemcpy(D_out, c->g_D.p, nn * sizeof(double), hipMemcpyDeviceToHost));
+    return FK_OK;
+}
+
+// ============================================================== batched SCF
+// The SCF step for every molecule of a batch at once: one batched J/K build
+// per iteration, and the dense steps as batched kernels over the
+// concatenated per-molecule blocks, with per-molecule scalars (energies,
+// DIIS systems, purification choices) on the host.
+namespace {
+
+// A host context holding molecule m of the batch alone (its atoms and shells).
+int molecule_context(fk_ctx *c, int m, fk_ctx **out)
+{
+    *out = nullptr;
+    int a0 = -1, na = 0;
+    for (int a = 0; a < c->natom; ++a)
+        if (c->atom_mol[a] == m) {
+            if (a0 < 0) a0 = a;
+            ++na;
+        }
+    const int s0 = c->mol_sh0[m], ns = c->mol_nsh[m];
+    std::vector<int> Z(c->Z.begin() + a0, c->Z.begin() + a0 + na), satom(ns), sl(ns), snp(ns);
+    std::vector<double> xyz(c->xyz.begin() + 3 * a0, c->xyz.begin() + 3 * (a0 + na)), ex, cf;
+    for (int k = 0; k < ns; ++k) {
+        const int s = s0 + k;
+        satom[k] = c->sh_atom[s] - a0;
+        sl[k] = c->sh_l[s];
+        snp[k] = c->sh_nprim[s];
+        for (int p = c->sh_poff[s]; p < c->sh_poff[s + 1]; ++p) {
+            ex.push_back(c->exps[p]);
+            cf.push_back(c->coef_in[p]);
+        }
+    }
+    fk_ctx *t = nullptr;
+    if (fk_create(&t, -1) != FK_OK) return fail(c, FK_ERR_OOM, "batched SCF: cannot create a molecule context");
+    if (fk_set_geometry(t, na, Z.data(), xyz.data(), 0) || fk_set_basis(t, ns, satom.data(), sl.data(), snp.data(), ex.data(), cf.data())) {
+        const int rc = fail(c, FK_ERR_ARG, "batched SCF: molecule %d: %s", m, t->err.c_str());
+        fk_destroy(t);
+        return rc;
+    }
+    *out = t;
+    return FK_OK;
+}
+
+struct ScfBatch {
+    fk_ctx *c = nullptr;
+    hipStream_t st = nullptr;
+    int nmol = 0, nmax = 0;
+    size_t nm = 0;
+    DevBuf<double> h, X, Xi, D, Do, J, K, F, Fo, G, E, T1, T2, T3, part, out, coef;
+    std::vector<DevBuf<double>> ringF, ringE;
+    ~ScfBatch()
+    {
+        for (auto *b : {&h, &X, &Xi, &D, &Do, &J, &K, &F, &Fo, &G, &E, &T1, &T2, &T3, &part, &out, &coef}) dev_free(*b);
+        for (auto &b : ringF) dev_free(b);
+        for (auto &b : ringE) dev_free(b);
+    }
+    const int *nbf() const { return c->d_mol_nbf.p; }
+    const long long *off() const { return c->d_mol_base.p; }
+    int gemm(const double *A, const double *B, double *C, double alpha = 1.0, double beta = 0.0)
+    {
+        return fk_scfb_gemm(A, B, C, nmol, nmax, nbf(), off(), alpha, beta, st) ? fail(c, FK_ERR_HIP, "batched SCF: GEMM launch failed") : FK_OK;
+    }
+    // out = a_m x + b_m y + c_m z + d_m I, coefficients [4 nmol] from the host
+    int lincomb(double *o, const double *x, const double *y, const double *z, const std::vector<double> &cf)
+    {
+        HIPCHK(c, hipMemcpy(coef.p, cf.data(), cf.size() * sizeof(double), hipMemcpyHostToDevice));
+        return fk_scfb_lincomb(o, x, y, z, nmol, nmax, nbf(), off(), coef.p, st) ? fail(c, FK_ERR_HIP, "batched SCF: launch failed") : FK_OK;
+    }
+    int lincomb_u(double *o, const double *x, const double *y, const double *z, double a, double b, double cc, double d)
+    {
+        std::vector<double> cf(4 * (size_t)nmol);
+        for (int m = 0; m < nmol; ++m) { cf[4 * m] = a; cf[4 * m + 1] = b; cf[4 * m + 2] = cc; cf[4 * m + 3] = d; }
+        return lincomb(o, x, y, z, cf);
+    }
+    int reduce(const double *x, const double *y, int op, std::vector<double> &r)
+    {
+        if (fk_scfb_reduce(x, y, nmol, nbf(), off(), op, part.p, out.p, st)) return fail(c, FK_ERR_HIP, "batched SCF: reduction launch failed");
+        r.resize((op == 3 ? 2 : 1) * (size_t)nmol);
+        HIPCHK(c, hipMemcpyAsync(r.data(), out.p, r.size() * sizeof(double), hipMemcpyDeviceToHost, st));
+        HIPCHK(c, hipStreamSynchronize(st));
+        return FK_OK;
+    }
+};
+
+int scfb_orthogonaliser(ScfBatch &w, double tol)
+{
+    const int nm = w.nmol;
+    std::vector<double> gb, err, prev(nm, 1e300);
+    int rc;
+    if ((rc = w.reduce(w.T3.p, nullptr, 3, gb))) return rc;  // T3 holds S
+    std::vector<double> cs(nm), cf(4 * (size_t)nm, 0.0);
+    for (int m = 0; m < nm; ++m) {
+        cs[m] = gb[nm + m];
+        if (!(cs[m] > 0)) return fail(w.c, FK_ERR_ARG, "batched SCF: molecule %d: overlap matrix has no positive bound", m);
+        cf[4 * m] = 1.0 / cs[m];
+    }
+    if ((rc = w.lincomb(w.Xi.p, w.T3.p, nullptr, nullptr, cf)) || (rc = w.lincomb_u(w.X.p, w.T3.p, nullptr, nullptr, 0, 0, 0, 1)))
+        return rc;
+    std::vector<char> done(nm, 0);
+    for (int it = 0; it < 200; ++it) {
+        if ((rc = w.gemm(w.X.p, w.Xi.p, w.T1.p)) || (rc = w.lincomb_u(w.T2.p, w.T1.p, nullptr, nullptr, 1, 0, 0, -1)) ||
+            (rc = w.reduce(w.T2.p, nullptr, 1, err)))
+            return rc;
+        bool all = true;
+        for (int m = 0; m < nm; ++m) {
+            if (err[m] < tol * 1e-3 || (err[m] < 1e-9 && err[m] > 0.5 * prev[m])) done[m] = 1;
+            prev[m] = err[m];
+            all = all && done[m];
+        }
+        if (all) break;
+        if ((rc = w.lincomb_u(w.T2.p, w.T1.p, nullptr, nullptr, -0.5, 0, 0, 1.5)) || (rc = w.gemm(w.Xi.p, w.T2.p, w.T1.p)) ||
+            (rc = w.gemm(w.T2.p, w.X.p, w.G.p)))
+            return rc;
+        std::swap(w.Xi, w.T1);
+        std::swap(w.X, w.G);
+    }
+    for (int m = 0; m < nm; ++m)
+        if (!(err[m] < tol))
+            return fail(w.c, FK_ERR_ARG, "batched SCF: molecule %d: S^(-1/2) did not converge (%.3g)", m, err[m]);
+    std::vector<double> c1(4 * (size_t)nm, 0.0), c2(4 * (size_t)nm, 0.0);
+    for (int m = 0; m < nm; ++m) {
+        c1[4 * m] = 1.0 / std::sqrt(cs[m]);
+        c2[4 * m] = std::sqrt(cs[m]);
+    }
+    if ((rc = w.lincomb(w.X.p, w.X.p, nullptr, nullptr, c1)) || (rc = w.lincomb(w.Xi.p, w.Xi.p, nullptr, nullptr, c2))) return rc;
+    return FK_OK;
+}
+
+// Orthonormal densities D'_m = 2 P_m from F'_m in Fo (trace-correcting
+// purification per molecule; molecules that have converged keep P).
+int scfb_purify(ScfBatch &w, const std::vector<int> &nocc)
+{
+    const int nm = w.nmol;
+    std::vector<double> gb, t1, t2, cf(4 * (size_t)nm, 0.0);
+    int rc;
+    if ((rc = w.reduce(w.Fo.p, nullptr, 3, gb))) return rc;
+    for (int m = 0; m < nm; ++m) {
+        const double lo = gb[m], hi = gb[nm + m];
+        if (!(hi > lo)) return fail(w.c, FK_ERR_ARG, "batched SCF: molecule %d: degenerate Fock spectrum bounds", m);
+        cf[4 * m] = -1.0 / (hi - lo);
+        cf[4 * m + 3] = hi / (hi - lo);
+    }
+    if ((rc = w.lincomb(w.T1.p, w.Fo.p, nullptr, nullptr, cf))) return rc;
+    std::vector<int> extra(nm, -1);
+    bool all = false;
+    for (int it = 0; it < 300 && !all; ++it) {
+        if ((rc = w.gemm(w.T1.p, w.T1.p, w.T2.p)) || (rc = w.reduce(w.T1.p, nullptr, 2, t1)) || (rc = w.reduce(w.T2.p, nullptr, 2, t2)))
+            return rc;
+        all = true;
+        for (int m = 0; m < nm; ++m) {
+            double a = 1.0, b = 0.0;  // keep P
+            if (extra[m] != 0) {
+                const double idem = t1[m] - t2[m];
+                if (extra[m] < 0 && std::fabs(idem) < 1e-11) extra[m] = 2;
+                if (extra[m] != 0) {
+                    if (extra[m] > 0) --extra[m];
+                    if (std::fabs(t2[m] - nocc[m]) < std::fabs(2 * t1[m] - t2[m] - nocc[m])) { a = 0.0; b = 1.0; }
+                    else { a = 2.0; b = -1.0; }
+                }
+            }
+            cf[4 * m] = a; cf[4 * m + 1] = b; cf[4 * m + 2] = 0.0; cf[4 * m + 3] = 0.0;
+            all = all && extra[m] == 0;
+        }
+        if (all) break;
+        if ((rc = w.lincomb(w.T1.p, w.T1.p, w.T2.p, nullptr, cf))) return rc;
+    }
+    if (!all) return fail(w.c, FK_ERR_NOT_CONVERGED, "batched SCF: purification did not converge (no gap?)");
+    return w.lincomb_u(w.Do.p, w.T1.p, nullptr, nullptr, 2.0, 0, 0, 0);
+}
+
+}  // namespace
+
+extern "C" int fk_run_scf_batch(fk_ctx *c, const fk_scf_opts *opts, fk_scf_result *results, double *D_inout)
+{
+    if (!c) return FK_ERR_ARG;
+    if (!results || !D_inout) return fail(c, FK_ERR_ARG, "fk_run_scf_batch: null results or density pointer");
+    if (c->device < 0) return fail(c, FK_ERR_STATE, "fk_run_scf_batch: context has no device");
+    if (!c->have_quartets) return fail(c, FK_ERR_STATE, "fk_run_scf_batch: call fk_build_quartets first");
+    const int nmol = c->nmol;
+    std::memset(results, 0, sizeof(fk_scf_result) * (size_t)nmol);
+    fk_scf_opts o = {100, 1e-10, 1e-8, 8, 0, 1e-8};
+    if (opts) o = *opts;
+    if (o.max_iter < 0 || o.diis_n < 0 || o.diis_n > 32 || !(o.e_tol > 0) || !(o.g_tol > 0) || !(o.lindep > 0) ||
+        o.guess < 0 || o.guess > 3)
+        return fail(c, FK_ERR_ARG, "fk_run_scf_batch: invalid options");
+    if (c->charge != 0) return fail(c, FK_ERR_UNSUPPORTED, "fk_run_scf_batch: the molecules of a batch must be neutral");
+    const auto t_start = std::chrono::steady_clock::now();
+    hipSetDevice(c->device);
+    int rc;
+    // one-electron part per molecule (host), electron counts
+    const size_t nmat = (size_t)c->mol_base[nmol];
+    std::vector<double> Sh(nmat), hh(nmat), enuc(nmol);
+    std::vector<int> nocc(nmol);
+    int nmax = 0;
+    for (int m = 0; m < nmol; ++m) {
+        fk_ctx *t = nullptr;
+        if ((rc = molecule_context(c, m, &t))) return rc;
+        const int n = c->mol_nbf[m];
+        nmax = std::max(nmax, n);
+        std::vector<double> S(n * (size_t)n), T(S.size()), V(S.size());
+        rc = fk_one_electron(t, S.data(), T.data(), V.data(), &enuc[m]);
+        const int ne = t->nelec;
+        fk_destroy(t);
+        if (rc) return fail(c, rc, "fk_run_scf_batch: molecule %d: one-electron integrals failed", m);
+        if (ne % 2 || ne <= 0 || ne / 2 > n) return fail(c, FK_ERR_ARG, "fk_run_scf_batch: molecule %d: %d electrons", m, ne);
+        nocc[m] = ne / 2;
+        for (size_t i = 0; i < S.size(); ++i) {
+            Sh[c->mol_base[m] + i] = S[i];
+            hh[c->mol_base[m] + i] = T[i] + V[i];
+        }
+    }
+    ScfBatch w;
+    w.c = c;
+    w.nmol = nmol;
+    w.nmax = nmax;
+    w.nm = nmat;
+    for (auto *b : {&w.h, &w.X, &w.Xi, &w.D, &w.Do, &w.J, &w.K, &w.F, &w.Fo, &w.G, &w.E, &w.T1, &w.T2, &w.T3})
+        if ((rc = dev_upload<double>(c, *b, nullptr, nmat))) return rc;
+    if ((rc = dev_upload<double>(c, w.part, nullptr, (size_t)fk_scfb_reduce_scratch(nmol))) ||
+        (rc = dev_upload<double>(c, w.out, nullptr, 2 * (size_t)nmol)) || (rc = dev_upload<double>(c, w.coef, nullptr, 4 * (size_t)nmol)))
+        return rc;
+    const int dn = std::max(o.diis_n, 1);
+    w.ringF.resize(dn);
+    w.ringE.resize(dn);
+    if (o.diis_n > 1)
+        for (int k = 0; k < dn; ++k)
+            if ((rc = dev_upload<double>(c, w.ringF[k], nullptr, nmat)) || (rc = dev_upload<double>(c, w.ringE[k], nullptr, nmat)))
+                return rc;
+    if ((rc = dev_upload(c, w.h, hh.data(), nmat)) || (rc = dev_upload(c, w.T3, Sh.data(), nmat))) return rc;
+    if ((rc = scfb_orthogonaliser(w, o.lindep))) return rc;
+
+    // initial orthonormal densities: the learned guess is per molecule only,
+    // so a batch starts it from SAD
+    const auto t_guess = std::chrono::steady_clock::now();
+    int gused = o.guess == 3 ? 2 : o.guess;
+    if (gused == 2) {
+        std::vector<double> Dsad(nmat);
+        if (fk_sad_density(c, Dsad.data()) || dev_upload(c, w.D, Dsad.data(), nmat)) {
+            gused = 0;
+            c->err.clear();
+        }
+    } else if (gused == 1) {
+        if ((rc = dev_upload(c, w.D, D_inout, nmat))) return rc;
+    }
+    if (gused == 0) {
+        if ((rc = w.gemm(w.X.p, w.h.p, w.T3.p)) || (rc = w.gemm(w.T3.p, w.X.p, w.Fo.p)) || (rc = scfb_purify(w, nocc))) return rc;
+    } else {
+        if ((rc = w.gemm(w.Xi.p, w.D.p, w.T3.p)) || (rc = w.gemm(w.T3.p, w.Xi.p, w.Do.p))) return rc;
+    }
+    if ((rc = w.gemm(w.X.p, w.Do.p, w.T3.p)) || (rc = w.gemm(w.T3.p, w.X.p, w.D.p))) return rc;
+    HIPCHK(c, hipStreamSynchronize(w.st));
+    const double guess_s = std::chrono::duration<double>(std::chrono::steady_clock::now() - t_guess).count();
+    for (int m = 0; m < nmol; ++m) {
+        results[m].e_nuc = enuc[m];
+        results[m].guess_used = gused;
+        results[m].guess_seconds = guess_s;
+    }
+    if (o.max_iter == 0) {
+        HIPCHK(c, hipMemcpy(D_inout, w.D.p, nmat * sizeof(double), hipMemcpyDeviceToHost));
+        const double tot = std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start).count();
+        for (int m = 0; m < nmol; ++m) results[m].total_seconds = tot;
+        return FK_OK;
+    }
+
+    std::vector<double> e_prev(nmol, 0.0), e_cur(nmol, 0.0), err(nmol, 0.0), dh, df, ev;
+    std::vector<std::vector<double>> Bm(nmol, std::vector<double>((size_t)dn * dn, 0.0));
+    std::vector<int> slot_age;
+    std::vector<char> conv(nmol, 0);
+    double jk_s = 0;
+    bool all_conv = false;
+    int it = 0;
+    for (; it < o.max_iter; ++it) {
+        const auto t0 = std::chrono::steady_clock::now();
+        if ((rc = fk_build_jk(c, w.D.p, w.J.p, w.K.p, FK_DEVICE_PTRS | FK_SYNC, w.st))) return rc;
+        jk_s += std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+        if ((rc = w.lincomb_u(w.F.p, w.h.p, w.J.p, w.K.p, 1.0, 1.0, -0.5, 0)) || (rc = w.reduce(w.D.p, w.h.p, 0, dh)) ||
+            (rc = w.reduce(w.D.p, w.F.p, 0, df)))
+            return rc;
+        for (int m = 0; m < nmol; ++m) {
+            e_prev[m] = e_cur[m];
+            e_cur[m] = 0.5 * (dh[m] + df[m]) + enuc[m];
+        }
+        if ((rc = w.gemm(w.X.p, w.F.p, w.T3.p)) || (rc = w.gemm(w.T3.p, w.X.p, w.Fo.p)) || (rc = w.gemm(w.Fo.p, w.Do.p, w.G.p)))
+            return rc;
+        if (fk_scfb_antisym(w.E.p, w.G.p, nmol, nmax, w.nbf(), w.off(), w.st)) return fail(c, FK_ERR_HIP, "batched SCF: launch failed");
+        if ((rc = w.reduce(w.E.p, nullptr, 1, err))) return rc;
+        all_conv = true;
+        for (int m = 0; m < nmol; ++m) {
+            if (!std::isfinite(e_cur[m]) || !std::isfinite(err[m]))
+                return fail(c, FK_ERR_NOT_CONVERGED, "fk_run_scf_batch: molecule %d: non-finite energy or error at iteration %d", m, it + 1);
+            conv[m] = it > 0 && std::fabs(e_cur[m] - e_prev[m]) < o.e_tol && err[m] < o.g_tol;
+            all_conv = all_conv && conv[m];
+        }
+        if (all_conv) {
+            ++it;
+            break;
+        }
+        if (o.diis_n > 1) {
+            int k;
+            if ((int)slot_age.size() < o.diis_n) {
+                k = (int)slot_age.size();
+            } else {
+                k = slot_age.front();
+                slot_age.erase(slot_age.begin());
+            }
+            slot_age.push_back(k);
+            HIPCHK(c, hipMemcpyAsync(w.ringF[k].p, w.Fo.p, nmat * sizeof(double), hipMemcpyDeviceToDevice, w.st));
+            HIPCHK(c, hipMemcpyAsync(w.ringE[k].p, w.E.p, nmat * sizeof(double), hipMemcpyDeviceToDevice, w.st));
+            for (int j : slot_age) {
+                if ((rc = w.reduce(w.ringE[k].p, w.ringE[j].p, 0, ev))) return rc;
+                for (int m = 0; m < nmol; ++m) Bm[m][(size_t)k * dn + j] = Bm[m][(size_t)j * dn + k] = ev[m];
+            }
+            const int ms = (int)slot_age.size();
+            if (ms >= 2) {
+                // per molecule the Pulay coefficients (the newest F' alone if singular)
+                std::vector<std::vector<double>> coefs(nmol);
+                for (int m = 0; m < nmol; ++m) {
+                    std::vector<double> B((size_t)ms * ms);
+                    for (int i = 0; i < ms; ++i)
+                        for (int j = 0; j < ms; ++j) B[(size_t)i * ms + j] = Bm[m][(size_t)slot_age[i] * dn + slot_age[j]];
+                    if (!diis_solve(B, ms, coefs[m])) {
+                        coefs[m].assign(ms, 0.0);
+                        coefs[m][ms - 1] = 1.0;
+                    }
+                }
+                std::vector<double> cf(4 * (size_t)nmol, 0.0);
+                for (int m = 0; m < nmol; ++m) cf[4 * m] = coefs[m][0];
+                if ((rc = w.lincomb(w.Fo.p, w.ringF[slot_age[0]].p, nullptr, nullptr, cf))) return rc;
+                for (int i = 1; i < ms; ++i) {
+                    for (int m = 0; m < nmol; ++m) { cf[4 * m] = 1.0; cf[4 * m + 1] = coefs[m][i]; }
+                    if ((rc = w.lincomb(w.Fo.p, w.Fo.p, w.ringF[slot_age[i]].p, nullptr, cf))) return rc;
+                }
+            }
+        }
+        if ((rc = scfb_purify(w, nocc))) return rc;
+        if ((rc = w.gemm(w.X.p, w.Do.p, w.T3.p)) || (rc = w.gemm(w.T3.p, w.X.p, w.D.p))) return rc;
+    }
+    HIPCHK(c, hipMemcpy(D_inout, w.D.p, nmat * sizeof(double), hipMemcpyDeviceToHost));
+    const double tot = std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start).count();
+    for (int m = 0; m < nmol; ++m) {
+        fk_scf_result &r = results[m];
+        r.energy = e_cur[m];
+        r.iterations = it;
+        r.converged = conv[m] ? 1 : 0;
+        r.error = err[m];
+        r.delta_e = e_cur[m] - e_prev[m];
+        r.jk_seconds = jk_s;
+        r.total_seconds = tot;
+    }
+    if (!all_conv) return fail(c, FK_ERR_NOT_CONVERGED, "fk_run_scf_batch: not every molecule converged in %d iterations", o.max_iter);
     return FK_OK;
 }

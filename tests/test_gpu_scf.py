@@ -94,3 +94,52 @@ def test_scf_mixed_precision_gate(fk):
     r32 = c.run_scf()
     assert r64["converged"] and r32["converged"]
     assert abs(r32["energy"] - r64["energy"]) <= 1e-6
+
+
+def _neutral_batch():
+    from synth import geometry as geom
+    return [wl.water4_sto3g(), wl.h2_sto3g(), wl.alkane_sys(2, "6-31gs-type"),
+            wl.make_system(geom.water_cluster(2, 8), "6-31gs-type")]
+
+
+@pytest.mark.parametrize("guess", ["core", "sad"])
+def test_batched_scf_equals_single_molecules(fk, guess):
+    """One batched SCF over four molecules of different sizes and bases gives
+    each molecule the energy of its own SCF (1e-8 Eh) and of the oracle where
+    the oracle is cheap (H2, (H2O)4); the density blocks agree."""
+    mols = _neutral_batch()
+    b = wl.batch(mols)
+    c = fk.FockJK(0).set_system(b).set_molecules(b["atom_mol"]).build_quartets(tau=0.0)
+    g = fk.GUESS_CORE if guess == "core" else fk.GUESS_SAD
+    rs, D = c.run_scf_batch(guess=g)
+    nbf, off = c.molecule_layout()
+    assert all(r["converged"] and r["guess_used"] == g for r in rs)
+    for m, s in enumerate(mols):
+        r = fk.FockJK(0).set_system(s).build_quartets(tau=0.0).run_scf()
+        assert abs(rs[m]["energy"] - r["energy"]) <= 1e-8, (m, rs[m]["energy"], r["energy"])
+        assert abs(rs[m]["e_nuc"] - oracle.enuc(s)) <= 1e-10
+        Dm = D[off[m]:off[m + 1]].reshape(nbf[m], nbf[m])
+        assert np.max(np.abs(Dm - r["D"])) <= 1e-5
+    for m in (0, 1):
+        assert abs(rs[m]["energy"] - run_scf(mols[m])["E"]) <= 1e-8
+
+
+def test_batched_scf_initial_density_and_errors(fk):
+    """max_iter = 0 returns the SAD blocks of each molecule; a charged batch
+    is refused."""
+    from oracle import guess as og
+    mols = _neutral_batch()
+    b = wl.batch(mols)
+    c = fk.FockJK(0).set_system(b).set_molecules(b["atom_mol"]).build_quartets(tau=1e-10)
+    rs, D = c.run_scf_batch(max_iter=0, guess=fk.GUESS_SAD)
+    nbf, off = c.molecule_layout()
+    for m, s in enumerate(mols):
+        assert rs[m]["iterations"] == 0
+        assert np.max(np.abs(D[off[m]:off[m + 1]].reshape(nbf[m], nbf[m]) - og.sad_density(s))) < 1e-9
+    b2 = dict(b)
+    b2["charge"] = 2
+    b2["nelec"] = b["nelec"] - 2
+    c2 = fk.FockJK(0).set_system(b2).set_molecules(b2["atom_mol"]).build_quartets(tau=1e-10)
+    with pytest.raises(fk.FockJKError) as e:
+        c2.run_scf_batch()
+    assert e.value.code == fk.FK_ERR_UNSUPPORTED

@@ -312,3 +312,20 @@ def test_class_schedule_errors():
     with pytest.raises(fk.FockJKError) as e:
         c.autotune(np.zeros((28, 28)))
     assert e.value.code == fk.FK_ERR_STATE
+
+
+def test_sad_density_batch_layout():
+    """SAD of a batch: each molecule's block equals the oracle's SAD of that
+    molecule alone, in the batch layout."""
+    from oracle import guess as og
+    from synth import geometry as geom
+    mols = [wl.make_system(geom.water_cluster(2, 8), "6-31gs-type"), wl.alkane_sys(2, "6-31gs-type")]
+    b = wl.batch(mols)
+    c = fk.FockJK(device=-1).set_system(b).set_molecules(b["atom_mol"])
+    D = c.sad_density()
+    nbf, off = c.molecule_layout()
+    for m, s in enumerate(mols):
+        assert np.max(np.abs(D[off[m]:off[m + 1]].reshape(nbf[m], nbf[m]) - og.sad_density(s))) < 1e-9
+    with pytest.raises(fk.FockJKError) as e:
+        c.build_quartets(tau=1e-10).run_scf_batch()
+    assert e.value.code == fk.FK_ERR_STATE
