@@ -117,7 +117,7 @@ struct fk_ctx {
     std::map<int, ClassSched> sched;
     // initial guesses
     std::vector<double> coef_in;                  // contraction coefficients as given
-    std::map<int, std::vector<double>> sad_cache; // atomic density block per element
+    std::map<std::vector<double>, std::vector<double>> sad_cache; // atomic density per (element, shells)
     bool have_model = false;
     fk_mlp g_model{};                             // device copy of the guess network
     DevBuf<float> g_W[FK_MLP_MAX_LAYERS], g_b[FK_MLP_MAX_LAYERS], g_X, g_Y, g_work;
@@ -2395,15 +2395,26 @@ int fk_sad_density(fk_ctx *c, double *D_out)
     int rc;
     for (int a = 0; a < c->natom; ++a) {
         if (nf[a] == 0) continue;
-        auto it = c->sad_cache.find(c->Z[a]);
+        // one atomic calculation per element and shell set (a batch may mix bases)
+        std::vector<double> key{(double)c->Z[a]};
+        for (int sh = 0; sh < c->nshell; ++sh) {
+            if (c->sh_atom[sh] != a) continue;
+            key.push_back(c->sh_l[sh]);
+            key.push_back(c->sh_nprim[sh]);
+            for (int p = c->sh_poff[sh]; p < c->sh_poff[sh + 1]; ++p) {
+                key.push_back(c->exps[p]);
+                key.push_back(c->coef_in[p]);
+            }
+        }
+        auto it = c->sad_cache.find(key);
         if (it == c->sad_cache.end()) {
             std::vector<double> Dat;
             if ((rc = atomic_density(c, a, Dat))) return rc;
-            it = c->sad_cache.emplace(c->Z[a], std::move(Dat)).first;
+            it = c->sad_cache.emplace(std::move(key), std::move(Dat)).first;
         }
         const std::vector<double> &Dat = it->second;
         const int m = nf[a];
-        if ((int)Dat.size() != m * m) return fail(c, FK_ERR_ARG, "fk_sad_density: atoms of element %d differ in basis", c->Z[a]);
+        if ((int)Dat.size() != m * m) return fail(c, FK_ERR_ARG, "fk_sad_density: internal: atomic block size");
         const int mol = c->atom_mol[a], n = c->mol_nbf[mol];
         double *Dm = D_out + c->mol_base[mol];
         for (int i = 0; i < m; ++i)

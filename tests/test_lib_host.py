@@ -329,3 +329,16 @@ def test_sad_density_batch_layout():
     with pytest.raises(fk.FockJKError) as e:
         c.build_quartets(tau=1e-10).run_scf_batch()
     assert e.value.code == fk.FK_ERR_STATE
+
+
+def test_sad_density_mixed_bases():
+    """A batch mixing bases gives each atom the atomic density of its own
+    shells (hydrogen in STO-3G and in 6-31G*-type)."""
+    from oracle import guess as og
+    mols = [wl.h2_sto3g(), wl.alkane_sys(2, "6-31gs-type")]
+    b = wl.batch(mols)
+    c = fk.FockJK(device=-1).set_system(b).set_molecules(b["atom_mol"])
+    D = c.sad_density()
+    nbf, off = c.molecule_layout()
+    for m, s in enumerate(mols):
+        assert np.max(np.abs(D[off[m]:off[m + 1]].reshape(nbf[m], nbf[m]) - og.sad_density(s))) < 1e-9
