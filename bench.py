@@ -106,6 +106,10 @@ def cpu_baseline(sys_, D, target_s=15.0):
             "quartets_per_s": 1.0 / per_q, "est_build_s": est_build_s}
 
 
+def _progress(msg):
+    print(f"bench.py: {msg}", file=sys.stderr, flush=True)
+
+
 def bench_batch(args, torch, fk):
     """Batched builds: the first --nmol molecules of the seeded 256-molecule
     organic set (tzvp-type basis, s to f) in one context, every class launch
@@ -119,6 +123,7 @@ def bench_batch(args, torch, fk):
         h = fk.FockJK(-1).set_system(m)
         S, T, V, _ = h.one_electron()
         Ds.append(_core_density(S, T + V, m["nelec"] // 2).ravel())
+    _progress(f"batch of {args.nmol} molecules set up")
     tune = None
     if args.autotune:
         # schedules tuned on a two-molecule batch of the same set, applied to all
@@ -136,6 +141,7 @@ def bench_batch(args, torch, fk):
                 "class_ms_sum_tuned": rep["build_ms_tuned"],
                 "changed_classes": sum(r["changed"] for r in rep["classes"])}
         del sub
+        _progress(f"schedules tuned in {tune['seconds']:.0f} s")
     ctx.build_quartets(tau=args.tau, tau_prim=args.tau_prim, tau_fp32=args.tau_fp32)
     info = ctx.info()
     dev = torch.device("cuda:0")
@@ -166,6 +172,7 @@ def bench_batch(args, torch, fk):
     e1.record(stream)
     torch.cuda.synchronize()
     ms_graph = e0.elapsed_time(e1) / args.steps
+    _progress(f"builds timed: {ms:.0f} ms eager, {ms_graph:.0f} ms graph")
     nbf = [m["nbf"] for m in b["mols"]]
     out = {
         "metric": METRIC, "value": 1000.0 / ms, "unit": "batch builds/s", "n_gpus": 1, "steps": args.steps,
@@ -186,6 +193,7 @@ def bench_batch(args, torch, fk):
     if args.batch_scf:
         # batched SCF of every molecule from SAD (outside the timed region)
         rs, _ = ctx.run_scf_batch(guess=fk.GUESS_SAD)
+        _progress(f"batched SCF: {rs[0]['iterations']} iterations")
         out["scf_batch"] = {"iterations": rs[0]["iterations"], "converged": int(sum(r["converged"] for r in rs)),
                             "seconds": rs[0]["total_seconds"], "jk_seconds": rs[0]["jk_seconds"],
                             "energies": [r["energy"] for r in rs]}
