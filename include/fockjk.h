@@ -280,7 +280,9 @@ int fk_run_scf(fk_ctx *ctx, const fk_scf_opts *opts, fk_scf_result *result, doub
  * jk_seconds and total_seconds are the batch's); D_inout: host array of the
  * batch layout (fk_molecule_layout), the guess for guess = 1 and the final
  * densities on return.  guess = 3 starts from SAD (guess_used = 2): the
- * learned guess is per molecule.  max_iter = 0 returns the initial densities. */
+ * learned guess is per molecule.  max_iter = 0 returns the initial densities.
+ * With the environment variable FK_SCF_LOG set (not "0") each iteration
+ * prints one progress line to stderr. */
 int fk_run_scf_batch(fk_ctx *ctx, const fk_scf_opts *opts, fk_scf_result *results, double *D_inout);
 
 /* ---- initial densities (an extension: the paper's SCF starts from a

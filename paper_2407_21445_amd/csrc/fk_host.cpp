@@ -9,6 +9,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <numeric>
@@ -2922,6 +2923,9 @@ extern "C" int fk_run_scf_batch(fk_ctx *c, const fk_scf_opts *opts, fk_scf_resul
     std::vector<char> conv(nmol, 0);
     double jk_s = 0;
     bool all_conv = false;
+    // progress lines on stderr when FK_SCF_LOG is set (long batches)
+    const char *lg = std::getenv("FK_SCF_LOG");
+    const bool log = lg && *lg && *lg != '0';
     int it = 0;
     for (; it < o.max_iter; ++it) {
         const auto t0 = std::chrono::steady_clock::now();
@@ -2939,12 +2943,21 @@ extern "C" int fk_run_scf_batch(fk_ctx *c, const fk_scf_opts *opts, fk_scf_resul
         if (fk_scfb_antisym(w.E.p, w.G.p, nmol, nmax, w.nbf(), w.off(), w.st)) return fail(c, FK_ERR_HIP, "batched SCF: launch failed");
         if ((rc = w.reduce(w.E.p, nullptr, 1, err))) return rc;
         all_conv = true;
+        int nconv = 0;
+        double de_max = 0, err_max = 0;
         for (int m = 0; m < nmol; ++m) {
             if (!std::isfinite(e_cur[m]) || !std::isfinite(err[m]))
                 return fail(c, FK_ERR_NOT_CONVERGED, "fk_run_scf_batch: molecule %d: non-finite energy or error at iteration %d", m, it + 1);
             conv[m] = it > 0 && std::fabs(e_cur[m] - e_prev[m]) < o.e_tol && err[m] < o.g_tol;
             all_conv = all_conv && conv[m];
+            nconv += conv[m];
+            de_max = std::max(de_max, std::fabs(e_cur[m] - e_prev[m]));
+            err_max = std::max(err_max, err[m]);
         }
+        if (log)
+            std::fprintf(stderr, "fk_run_scf_batch: iteration %d: %d of %d converged, max |dE| %.3e, max error %.3e, %.1f s\n",
+                         it + 1, nconv, nmol, de_max, err_max,
+                         std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start).count());
         if (all_conv) {
             ++it;
             break;
