@@ -238,7 +238,10 @@ typedef struct {
     double lindep;       /* required accuracy of the orthogonaliser: max |Z S Z - I|
                             with Z = S^(-1/2) from the Newton-Schulz iteration;
                             fails with FK_ERR_ARG for an overlap matrix too
-                            ill-conditioned to reach it.  Default 1e-8 */
+                            ill-conditioned to reach it, or when an entry of
+                            S^(-1/2) exceeds 3e3 (overlap eigenvalues near
+                            1e-7: the basis is nearly linearly dependent and
+                            no direction is dropped).  Default 1e-8 */
 } fk_scf_opts;
 
 typedef struct {

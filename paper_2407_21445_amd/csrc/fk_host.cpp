@@ -1567,6 +1567,10 @@ namespace {
 
 int guess_predict_device(fk_ctx *c, double *D, hipStream_t st);  // learned guess, defined below
 
+// Largest entry of S^(-1/2) the SCF accepts (overlap eigenvalues down to
+// about 1e-7); beyond it the orthonormal-basis steps lose all accuracy.
+constexpr double kMaxOrthoEntry = 3.0e3;
+
 struct ScfWork {
     fk_ctx *c = nullptr;
     hipStream_t st = nullptr;
@@ -1627,6 +1631,12 @@ int scf_orthogonaliser(ScfWork &w, double tol)
     if (!(err < tol)) return fail(w.c, FK_ERR_ARG, "fk_run_scf: S^(-1/2) did not converge (max|ZY - I| = %.3g); overlap too ill-conditioned", err);
     SCFCHK(w, fk_scf_lincomb(w.X.p, w.X.p, nullptr, nullptr, n, 1.0 / std::sqrt(cs), 0, 0, 0, w.st));
     SCFCHK(w, fk_scf_lincomb(w.Xi.p, w.Xi.p, nullptr, nullptr, n, std::sqrt(cs), 0, 0, 0, w.st));
+    // every direction of S is kept: a nearly linearly dependent basis (overlap
+    // eigenvalues about 1e-7 or below) would amplify rounding past use
+    double xmax = 0;
+    if ((rc = scf_reduce(w, w.X.p, nullptr, 1, &xmax))) return rc;
+    if (!(xmax < kMaxOrthoEntry))
+        return fail(w.c, FK_ERR_ARG, "fk_run_scf: max |S^(-1/2)| = %.3g: the basis is nearly linearly dependent", xmax);
     return FK_OK;
 }
 
@@ -2778,6 +2788,11 @@ int scfb_orthogonaliser(ScfBatch &w, double tol)
         c2[4 * m] = std::sqrt(cs[m]);
     }
     if ((rc = w.lincomb(w.X.p, w.X.p, nullptr, nullptr, c1)) || (rc = w.lincomb(w.Xi.p, w.Xi.p, nullptr, nullptr, c2))) return rc;
+    std::vector<double> xmax;
+    if ((rc = w.reduce(w.X.p, nullptr, 1, xmax))) return rc;
+    for (int m = 0; m < nm; ++m)
+        if (!(xmax[m] < kMaxOrthoEntry))
+            return fail(w.c, FK_ERR_ARG, "batched SCF: molecule %d: max |S^(-1/2)| = %.3g: the basis is nearly linearly dependent", m, xmax[m]);
     return FK_OK;
 }
 

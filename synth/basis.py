@@ -158,19 +158,21 @@ def _atom_shells(name: str, Z: int):
         if Z == 1:
             a, c = _scaled(("1s",), 3, 1.6 * z1)
             out.append(_shell(0, a, c["1s"]))
-            out.append(_shell(0, [0.27], [1.0]))
-            out.append(_shell(0, [0.09], [1.0]))
+            out.append(_shell(0, [0.33], [1.0]))
+            out.append(_shell(0, [0.12], [1.0]))
             out.append(_shell(1, [0.8], [1.0]))
         else:
             a, c = _scaled(("1s",), 6, z1)
             out.append(_shell(0, a, c["1s"]))
-            a, c = _scaled(("2s",), 2, 1.5 * z2)
+            a, c = _scaled(("2s",), 2, 2.2 * z2)
             out.append(_shell(0, a, c["2s"]))
-            for e in (0.45, 0.16, 0.06):
+            # a tight contracted 2s and three uncontracted s spread below it, so that
+            # no one-centre combination is nearly redundant
+            for e in (0.40, 0.17, 0.08):
                 out.append(_shell(0, [e * z2 * z2 / 2.96], [1.0]))
             a, c = _scaled(("2p",), 4, 1.1 * z2)
             out.append(_shell(1, a, c["2p"]))
-            for e in (0.17, 0.06):
+            for e in (0.30, 0.12):
                 out.append(_shell(1, [e * z2 * z2 / 2.96], [1.0]))
             out.append(_shell(2, [1.1], [1.0]))
             out.append(_shell(2, [0.32], [1.0]))
