@@ -192,15 +192,18 @@ def bench_batch(args, torch, fk):
         out["autotune"] = tune
     if args.batch_scf:
         # batched SCF of every molecule from SAD (outside the timed region)
-        rs, _ = ctx.run_scf_batch(guess=fk.GUESS_SAD)
+        # criteria of the organic set: its overlap eigenvalues reach ~1e-6, so
+        # the orthonormal-basis commutator has a noise floor near 1e-6
+        tol = dict(e_tol=1e-7, g_tol=1e-5)
+        rs, _ = ctx.run_scf_batch(guess=fk.GUESS_SAD, **tol)
         _progress(f"batched SCF: {rs[0]['iterations']} iterations")
-        out["scf_batch"] = {"iterations": rs[0]["iterations"], "converged": int(sum(r["converged"] for r in rs)),
+        out["scf_batch"] = {"criteria": tol, "iterations": rs[0]["iterations"], "converged": int(sum(r["converged"] for r in rs)),
                             "seconds": rs[0]["total_seconds"], "jk_seconds": rs[0]["jk_seconds"],
                             "energies": [r["energy"] for r in rs]}
         if args.tau_fp32 > 0:
             ref = fk.FockJK(0).set_system(b).set_molecules(b["atom_mol"])
             ref.build_quartets(tau=args.tau, tau_prim=args.tau_prim)
-            r64, _ = ref.run_scf_batch(guess=fk.GUESS_SAD)
+            r64, _ = ref.run_scf_batch(guess=fk.GUESS_SAD, **tol)
             out["scf_batch"]["fp64_seconds"] = r64[0]["total_seconds"]
             out["scf_batch"]["max_abs_energy_diff_vs_fp64"] = max(abs(a["energy"] - c["energy"]) for a, c in zip(rs, r64))
     print(json.dumps(out), flush=True)
