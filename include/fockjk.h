@@ -278,9 +278,11 @@ int fk_run_scf(fk_ctx *ctx, const fk_scf_opts *opts, fk_scf_result *result, doub
  * commutators, purification, D = X D' X) a batched kernel over the
  * concatenated per-molecule blocks, with each molecule's DIIS system and
  * purification choices solved on the host.  Molecules must be neutral and
- * closed shell.  Iterates until every molecule meets the criteria of
- * fk_run_scf in the same iteration.  results: nmol entries (iterations,
- * jk_seconds and total_seconds are the batch's); D_inout: host array of the
+ * closed shell.  A molecule that meets the criteria of fk_run_scf keeps
+ * that density (and those results) while the others iterate on; the run ends
+ * when every molecule has converged.  results: nmol entries (iterations: the
+ * Fock builds until that molecule converged; jk_seconds and total_seconds are
+ * the batch's); D_inout: host array of the
  * batch layout (fk_molecule_layout), the guess for guess = 1 and the final
  * densities on return.  guess = 3 starts from SAD (guess_used = 2): the
  * learned guess is per molecule.  max_iter = 0 returns the initial densities.

@@ -2935,7 +2935,11 @@ extern "C" int fk_run_scf_batch(fk_ctx *c, const fk_scf_opts *opts, fk_scf_resul
     std::vector<double> e_prev(nmol, 0.0), e_cur(nmol, 0.0), err(nmol, 0.0), dh, df, ev;
     std::vector<std::vector<double>> Bm(nmol, std::vector<double>((size_t)dn * dn, 0.0));
     std::vector<int> slot_age;
+    // a molecule that meets the criteria keeps that density (and its results)
+    // while the others iterate on
     std::vector<char> conv(nmol, 0);
+    std::vector<double> e_fin(nmol, 0.0), err_fin(nmol, 0.0), de_fin(nmol, 0.0);
+    std::vector<int> it_fin(nmol, 0);
     double jk_s = 0;
     bool all_conv = false;
     // progress lines on stderr when FK_SCF_LOG is set (long batches)
@@ -2961,11 +2965,21 @@ extern "C" int fk_run_scf_batch(fk_ctx *c, const fk_scf_opts *opts, fk_scf_resul
         int nconv = 0;
         double de_max = 0, err_max = 0;
         for (int m = 0; m < nmol; ++m) {
+            if (conv[m]) {  // frozen at its converged density
+                ++nconv;
+                continue;
+            }
             if (!std::isfinite(e_cur[m]) || !std::isfinite(err[m]))
                 return fail(c, FK_ERR_NOT_CONVERGED, "fk_run_scf_batch: molecule %d: non-finite energy or error at iteration %d", m, it + 1);
             conv[m] = it > 0 && std::fabs(e_cur[m] - e_prev[m]) < o.e_tol && err[m] < o.g_tol;
+            if (conv[m]) {
+                ++nconv;
+                e_fin[m] = e_cur[m];
+                err_fin[m] = err[m];
+                de_fin[m] = e_cur[m] - e_prev[m];
+                it_fin[m] = it + 1;
+            }
             all_conv = all_conv && conv[m];
-            nconv += conv[m];
             de_max = std::max(de_max, std::fabs(e_cur[m] - e_prev[m]));
             err_max = std::max(err_max, err[m]);
         }
@@ -3014,18 +3028,30 @@ extern "C" int fk_run_scf_batch(fk_ctx *c, const fk_scf_opts *opts, fk_scf_resul
                 }
             }
         }
+        // new densities; frozen molecules keep theirs (D' and D: keep = 1)
+        HIPCHK(c, hipMemcpyAsync(w.G.p, w.Do.p, nmat * sizeof(double), hipMemcpyDeviceToDevice, w.st));
+        HIPCHK(c, hipMemcpyAsync(w.E.p, w.D.p, nmat * sizeof(double), hipMemcpyDeviceToDevice, w.st));
         if ((rc = scfb_purify(w, nocc))) return rc;
         if ((rc = w.gemm(w.X.p, w.Do.p, w.T3.p)) || (rc = w.gemm(w.T3.p, w.X.p, w.D.p))) return rc;
+        if (std::find(conv.begin(), conv.end(), 1) != conv.end()) {
+            std::vector<double> cf(4 * (size_t)nmol, 0.0);
+            for (int m = 0; m < nmol; ++m) {
+                cf[4 * m] = conv[m] ? 0.0 : 1.0;
+                cf[4 * m + 1] = conv[m] ? 1.0 : 0.0;
+            }
+            if ((rc = w.lincomb(w.Do.p, w.Do.p, w.G.p, nullptr, cf)) || (rc = w.lincomb(w.D.p, w.D.p, w.E.p, nullptr, cf)))
+                return rc;
+        }
     }
     HIPCHK(c, hipMemcpy(D_inout, w.D.p, nmat * sizeof(double), hipMemcpyDeviceToHost));
     const double tot = std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start).count();
     for (int m = 0; m < nmol; ++m) {
         fk_scf_result &r = results[m];
-        r.energy = e_cur[m];
-        r.iterations = it;
+        r.energy = conv[m] ? e_fin[m] : e_cur[m];
+        r.iterations = conv[m] ? it_fin[m] : it;
         r.converged = conv[m] ? 1 : 0;
-        r.error = err[m];
-        r.delta_e = e_cur[m] - e_prev[m];
+        r.error = conv[m] ? err_fin[m] : err[m];
+        r.delta_e = conv[m] ? de_fin[m] : e_cur[m] - e_prev[m];
         r.jk_seconds = jk_s;
         r.total_seconds = tot;
     }
