@@ -143,3 +143,16 @@ def test_batched_scf_initial_density_and_errors(fk):
     with pytest.raises(fk.FockJKError) as e:
         c2.run_scf_batch()
     assert e.value.code == fk.FK_ERR_UNSUPPORTED
+
+
+def test_batched_scf_mixed_precision_gate(fk):
+    """The batched SCF with the FP32 split (tau_fp32 = 1e-5) gives every
+    molecule its FP64 batched energy within the 1e-6 Eh gate."""
+    mols = _neutral_batch()
+    b = wl.batch(mols)
+    r64, _ = fk.FockJK(0).set_system(b).set_molecules(b["atom_mol"]).build_quartets(tau=1e-10).run_scf_batch()
+    c = fk.FockJK(0).set_system(b).set_molecules(b["atom_mol"]).build_quartets(tau=1e-10, tau_fp32=1e-5)
+    r32, _ = c.run_scf_batch()
+    for a, x in zip(r64, r32):
+        assert a["converged"] and x["converged"]
+        assert abs(a["energy"] - x["energy"]) <= 1e-6
