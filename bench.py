@@ -119,10 +119,11 @@ def bench_batch(args, torch, fk):
     b = wl.organic_batch(args.nmol)
     ctx = fk.FockJK(0).set_system(b).set_molecules(b["atom_mol"])
     Ds = []
-    for m in b["mols"]:
-        h = fk.FockJK(-1).set_system(m)
-        S, T, V, _ = h.one_electron()
-        Ds.append(_core_density(S, T + V, m["nelec"] // 2).ravel())
+    if args.batch_density == "core":
+        for m in b["mols"]:
+            h = fk.FockJK(-1).set_system(m)
+            S, T, V, _ = h.one_electron()
+            Ds.append(_core_density(S, T + V, m["nelec"] // 2).ravel())
     _progress(f"batch of {args.nmol} molecules set up")
     tune = None
     if args.autotune:
@@ -132,7 +133,8 @@ def bench_batch(args, torch, fk):
         sb = wl.batch(b["mols"][:nsub])
         sub = fk.FockJK(0).set_system(sb).set_molecules(sb["atom_mol"])
         sub.build_quartets(tau=args.tau, tau_prim=args.tau_prim, tau_fp32=args.tau_fp32)
-        rep = sub.autotune(np.concatenate(Ds[:nsub]), reps=1)
+        Dsub = np.concatenate(Ds[:nsub]) if Ds else sub.sad_density()
+        rep = sub.autotune(Dsub, reps=1)
         for r in rep["classes"]:
             ctx.set_class_schedule(r["la"], r["lb"], r["lc"], r["ld"], r["bra_block"], r["kets_per_tile"],
                                    r["grid_fraction"])
@@ -144,35 +146,55 @@ def bench_batch(args, torch, fk):
         _progress(f"schedules tuned in {tune['seconds']:.0f} s")
     ctx.build_quartets(tau=args.tau, tau_prim=args.tau_prim, tau_fp32=args.tau_fp32)
     info = ctx.info()
+    _progress(f"lists built: {info['ntile']} tiles, {info['nquartet_schwarz']} Schwarz quartets")
     dev = torch.device("cuda:0")
-    Dd = torch.tensor(np.concatenate(Ds), dtype=torch.float64, device=dev)
+    Dh = np.concatenate(Ds) if Ds else ctx.sad_density()
+    Dd = torch.tensor(Dh, dtype=torch.float64, device=dev)
     J = torch.empty_like(Dd)
     K = torch.empty_like(Dd)
     stream = torch.cuda.current_stream(dev)
+    def build(timed):
+        ctx.build_jk(Dd, J, K, stream=stream, time_classes=args.progress)
+        if args.progress:
+            # long builds report each finished class launch (work-derived progress)
+            last = -1
+            while True:
+                done, total = ctx.build_progress()
+                if done != last:
+                    _progress(f"{'timed' if timed else 'warm-up'} build: {done} of {total} class launches finished")
+                    last = done
+                if done == total:
+                    break
+                time.sleep(2.0)
+
     for _ in range(args.warmup):
-        ctx.build_jk(Dd, J, K, stream=stream)
+        build(False)
     torch.cuda.synchronize()
     st = ctx.stats()
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
     e0.record(stream)
     for _ in range(args.steps):
-        ctx.build_jk(Dd, J, K, stream=stream)
+        build(True)
     e1.record(stream)
     torch.cuda.synchronize()
     ms = e0.elapsed_time(e1) / args.steps
-    # the same build captured once in a HIP graph, replayed
-    g = torch.cuda.CUDAGraph()
-    with torch.cuda.graph(g):
-        ctx.build_jk(Dd, J, K)
-    torch.cuda.synchronize()
-    e0.record(stream)
-    for _ in range(args.steps):
-        g.replay()
-    e1.record(stream)
-    torch.cuda.synchronize()
-    ms_graph = e0.elapsed_time(e1) / args.steps
-    _progress(f"builds timed: {ms:.0f} ms eager, {ms_graph:.0f} ms graph")
+    if args.warmup == 0:
+        st = ctx.stats()
+    ms_graph = None
+    if not args.progress:
+        # the same build captured once in a HIP graph, replayed
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            ctx.build_jk(Dd, J, K)
+        torch.cuda.synchronize()
+        e0.record(stream)
+        for _ in range(args.steps):
+            g.replay()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms_graph = e0.elapsed_time(e1) / args.steps
+    _progress(f"builds timed: {ms:.0f} ms eager" + (f", {ms_graph:.0f} ms graph" if ms_graph else ""))
     nbf = [m["nbf"] for m in b["mols"]]
     out = {
         "metric": METRIC, "value": 1000.0 / ms, "unit": "batch builds/s", "n_gpus": 1, "steps": args.steps,
@@ -181,7 +203,8 @@ def bench_batch(args, torch, fk):
         "config": {"workload": f"organic batch, first {args.nmol} of 256 seeded molecules (3-30 C/N/O + H), "
                                f"tzvp-type basis (s-f), one launch per class for all molecules",
                    "nmol": args.nmol, "nbf_total": int(sum(nbf)), "nbf_min": int(min(nbf)), "nbf_max": int(max(nbf)),
-                   "tau": args.tau, "tau_prim": args.tau_prim, "density": "core-Hamiltonian guess per molecule"},
+                   "tau": args.tau, "tau_prim": args.tau_prim,
+                   "density": "core-Hamiltonian guess per molecule" if args.batch_density == "core" else "SAD"},
         "molecule_builds_per_s": args.nmol * 1000.0 / ms,
         "graph_ms_per_step": ms_graph,
         "quartets_per_s": st["quartets"] / (ms * 1e-3),
@@ -227,6 +250,10 @@ def main():
                     help="time the default kernel schedules (the autotuner runs by default, before timing)")
     ap.add_argument("--nmol", type=int, default=8, help="molecules of the organic batch (--workload c4)")
     ap.add_argument("--batch-scf", action="store_true", help="--workload c4: also run the batched SCF")
+    ap.add_argument("--batch-density", choices=("core", "sad"), default="core",
+                    help="--workload c4: density of the timed builds")
+    ap.add_argument("--progress", action="store_true",
+                    help="--workload c4: report finished class launches during each build (long batches)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MB",
                     help="only run a plain device copy of MB megabytes 5 times (calibrates HBM byte counters)")
     ap.add_argument("--tau-fp32", type=float, default=0.0,

@@ -179,6 +179,11 @@ int fk_build_jk(fk_ctx *ctx, const double *D, double *J, double *K, unsigned fla
 /* Statistics of the last fk_build_jk (waits for it to finish). */
 int fk_stats(fk_ctx *ctx, fk_stats_t *stats);
 
+/* Progress of the last fk_build_jk issued with FK_TIME_CLASSES (and without
+ * FK_SYNC): *done of *total class launches have finished on the device.
+ * Does not block.  FK_ERR_STATE if the last build was not timed. */
+int fk_build_progress(fk_ctx *ctx, int *done, int *total);
+
 /* ---- kernel schedules ---------------------------------------------------
  * Per quartet class (named by its momenta as fk_stats lists them), the
  * schedule of its J/K kernel: bra_block = bras sharing their first shell per

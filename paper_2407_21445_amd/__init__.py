@@ -111,6 +111,7 @@ _sig = {
     "fk_set_molecules": ([_P, _I, _P], _I),
     "fk_molecule_layout": ([_P, _P, _P], _I),
     "fk_sad_density": ([_P, _P], _I),
+    "fk_build_progress": ([_P, _P, _P], _I),
     "fk_run_scf_batch": ([_P, ctypes.POINTER(ScfOpts), _P, _P], _I),
     "fk_set_class_schedule": ([_P, _I, _I, _I, _I, _I, _I, _D], _I),
     "fk_autotune": ([_P, _P, _U, _I, _P, ctypes.POINTER(TuneReport)], _I),
@@ -254,6 +255,12 @@ class FockJK:
         self._check(_lib.fk_build_jk(self._ctx, ctypes.c_void_p(D.data_ptr()), ctypes.c_void_p(J.data_ptr()),
                                      ctypes.c_void_p(K.data_ptr()), flags, ctypes.c_void_p(st.cuda_stream)))
         return J, K
+
+    def build_progress(self):
+        """(finished, total) class launches of the last timed build."""
+        d, t = ctypes.c_int(), ctypes.c_int()
+        self._check(_lib.fk_build_progress(self._ctx, ctypes.byref(d), ctypes.byref(t)))
+        return d.value, t.value
 
     def stats(self):
         s = Stats()

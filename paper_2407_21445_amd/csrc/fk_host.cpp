@@ -1132,6 +1132,21 @@ int fk_stats(fk_ctx *c, fk_stats_t *s)
     return FK_OK;
 }
 
+int fk_build_progress(fk_ctx *c, int *done, int *total)
+{
+    if (!c || !done || !total) return FK_ERR_ARG;
+    *done = 0;
+    *total = (int)c->qclasses.size();
+    if (c->device < 0 || !c->timed) return fail(c, FK_ERR_STATE, "fk_build_progress: last build was not timed (FK_TIME_CLASSES)");
+    hipSetDevice(c->device);
+    for (size_t i = 0; i < c->qclasses.size() && 2 * i + 1 < c->ev.size(); ++i) {
+        const hipError_t e = hipEventQuery(c->ev[2 * i + 1]);
+        if (e == hipSuccess) ++*done;
+        else if (e != hipErrorNotReady) return fail(c, FK_ERR_HIP, "fk_build_progress: %s", hipGetErrorString(e));
+    }
+    return FK_OK;
+}
+
 int fk_set_class_schedule(fk_ctx *c, int la, int lb, int lc, int ld, int bra_block, int kets_per_tile,
                           double grid_fraction)
 {
