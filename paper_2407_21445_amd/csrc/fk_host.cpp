@@ -5,6 +5,7 @@
 
 #include <algorithm>
 #include <array>
+#include <atomic>
 #include <chrono>
 #include <cmath>
 #include <cstdarg>
@@ -14,6 +15,7 @@
 #include <map>
 #include <numeric>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "fockjk.h"
@@ -116,6 +118,7 @@ struct fk_ctx {
     // per quartet class schedule (key P * NPC + Q), from fk_set_class_schedule or fk_autotune
     struct ClassSched { int bb = 0, kt = 0; double gf = 1.0; };
     std::map<int, ClassSched> sched;
+    std::vector<double> oe_S, oe_T, oe_V;          // one-electron matrices of the current geometry and basis
     // initial guesses
     std::vector<double> coef_in;                  // contraction coefficients as given
     std::map<std::vector<double>, std::vector<double>> sad_cache; // atomic density per (element, shells)
@@ -592,6 +595,7 @@ int fk_set_geometry(fk_ctx *c, int natom, const int *Z, const double *xyz, int c
     c->atom_mol.assign(natom, 0);
     c->sad_cache.clear();
     c->sched.clear();
+    c->oe_S.clear(); c->oe_T.clear(); c->oe_V.clear();
     c->have_geom = true;
     c->have_basis = false;
     c->have_quartets = false;
@@ -636,6 +640,7 @@ int fk_set_basis(fk_ctx *c, int nshell, const int *shell_atom, const int *shell_
     c->coef_in.assign(coefs, coefs + np);
     c->sad_cache.clear();
     c->sched.clear();
+    c->oe_S.clear(); c->oe_T.clear(); c->oe_V.clear();
     c->coef.assign(np, 0.0);
     c->bf_scale.assign(c->nbf, 1.0);
     for (int s = 0; s < nshell; ++s) {
@@ -1471,103 +1476,127 @@ int fk_one_electron(fk_ctx *c, double *S, double *T, double *V, double *e_nuc)
         *e_nuc = e;
     }
     if (!S && !T && !V) return FK_OK;
-    constexpr int LM = FK_MAX_L + 3;
-    for (int sa = 0; sa < c->nshell; ++sa)
-        for (int sb = 0; sb < c->nshell; ++sb) {
-            const int la = c->sh_l[sa], lb = c->sh_l[sb];
-            const int na = ncart(la), nb = ncart(lb);
-            const double *A = &c->xyz[3 * c->sh_atom[sa]], *B = &c->xyz[3 * c->sh_atom[sb]];
-            double AB[3], ab2 = 0;
-            for (int k = 0; k < 3; ++k) { AB[k] = A[k] - B[k]; ab2 += AB[k] * AB[k]; }
-            std::vector<double> bs(na * nb, 0.0), bt(na * nb, 0.0), bv(na * nb, 0.0);
-            for (int i = c->sh_poff[sa]; i < c->sh_poff[sa + 1]; ++i)
-                for (int j = c->sh_poff[sb]; j < c->sh_poff[sb + 1]; ++j) {
-                    const double al = c->exps[i], be = c->exps[j], p = al + be;
-                    const double Kab = std::exp(-al * be / p * ab2) * c->coef[i] * c->coef[j];
-                    double P[3], PA[3], PB[3];
-                    for (int k = 0; k < 3; ++k) {
-                        P[k] = (al * A[k] + be * B[k]) / p;
-                        PA[k] = P[k] - A[k];
-                        PB[k] = P[k] - B[k];
-                    }
-                    // 1-D overlaps O[k][i][j], i <= la, j <= lb + 2
-                    double O[3][LM][LM] = {};
-                    for (int k = 0; k < 3; ++k) {
-                        O[k][0][0] = std::sqrt(M_PI / p);
-                        for (int x = 0; x <= la; ++x)
-                            for (int y = 0; y <= lb + 2; ++y) {
-                                if (x == 0 && y == 0) continue;
-                                double v;
-                                if (x > 0) {
-                                    v = PA[k] * O[k][x - 1][y];
-                                    if (x > 1) v += (x - 1) / (2 * p) * O[k][x - 2][y];
-                                    if (y > 0) v += y / (2 * p) * O[k][x - 1][y - 1];
-                                } else {
-                                    v = PB[k] * O[k][x][y - 1];
-                                    if (y > 1) v += (y - 1) / (2 * p) * O[k][x][y - 2];
-                                }
-                                O[k][x][y] = v;
-                            }
-                    }
-                    for (int ia = 0; ia < na; ++ia)
-                        for (int ib = 0; ib < nb; ++ib) {
-                            int a[3], b[3];
-                            cart_exps(la, ia, a[0], a[1], a[2]);
-                            cart_exps(lb, ib, b[0], b[1], b[2]);
-                            double s1[3], t1[3];
+    const size_t nn = (size_t)n * n;
+    if (c->oe_S.size() != nn) {
+        // computed once per geometry and basis: shell pairs sa >= sb, both
+        // triangles written, shared out over host threads
+        std::vector<double> Sv(nn), Tv(nn), Vv(nn);
+        double *Sc = Sv.data(), *Tc = Tv.data(), *Vc = Vv.data();
+        constexpr int LM = FK_MAX_L + 3;
+        std::atomic<int> next{0};
+        auto work = [&]() {
+            for (int sa; (sa = next.fetch_add(1)) < c->nshell;)
+                for (int sb = 0; sb <= sa; ++sb) {
+                    const int la = c->sh_l[sa], lb = c->sh_l[sb];
+                    const int na = ncart(la), nb = ncart(lb);
+                    const double *A = &c->xyz[3 * c->sh_atom[sa]], *B = &c->xyz[3 * c->sh_atom[sb]];
+                    double AB[3], ab2 = 0;
+                    for (int k = 0; k < 3; ++k) { AB[k] = A[k] - B[k]; ab2 += AB[k] * AB[k]; }
+                    std::vector<double> bs(na * nb, 0.0), bt(na * nb, 0.0), bv(na * nb, 0.0);
+                    for (int i = c->sh_poff[sa]; i < c->sh_poff[sa + 1]; ++i)
+                        for (int j = c->sh_poff[sb]; j < c->sh_poff[sb + 1]; ++j) {
+                            const double al = c->exps[i], be = c->exps[j], p = al + be;
+                            const double Kab = std::exp(-al * be / p * ab2) * c->coef[i] * c->coef[j];
+                            double P[3], PA[3], PB[3];
                             for (int k = 0; k < 3; ++k) {
-                                s1[k] = O[k][a[k]][b[k]];
-                                double tk = -2 * be * be * O[k][a[k]][b[k] + 2] + be * (2 * b[k] + 1) * s1[k];
-                                if (b[k] >= 2) tk -= 0.5 * b[k] * (b[k] - 1) * O[k][a[k]][b[k] - 2];
-                                t1[k] = tk;
+                                P[k] = (al * A[k] + be * B[k]) / p;
+                                PA[k] = P[k] - A[k];
+                                PB[k] = P[k] - B[k];
                             }
-                            bs[ia * nb + ib] += Kab * s1[0] * s1[1] * s1[2];
-                            bt[ia * nb + ib] += Kab * (t1[0] * s1[1] * s1[2] + s1[0] * t1[1] * s1[2] + s1[0] * s1[1] * t1[2]);
-                        }
-                    if (!V) continue;
-                    const int nr = (la + lb) / 2 + 1;
-                    for (int C = 0; C < c->natom; ++C) {
-                        if (c->Z[C] == 0) continue;
-                        double PC[3], pc2 = 0;
-                        for (int k = 0; k < 3; ++k) { PC[k] = P[k] - c->xyz[3 * C + k]; pc2 += PC[k] * PC[k]; }
-                        double u[RYS_NMAX], w[RYS_NMAX];
-                        fk_rys_host(nr, p * pc2, u, w);
-                        const double pre = -c->Z[C] * 2 * M_PI / p * Kab;
-                        for (int r = 0; r < nr; ++r) {
-                            double I[3][LM][LM];
+                            // 1-D overlaps O[k][i][j], i <= la, j <= lb + 2
+                            double O[3][LM][LM] = {};
                             for (int k = 0; k < 3; ++k) {
-                                double G[2 * LM];
-                                G[0] = 1.0;
-                                const double c00 = PA[k] - u[r] * PC[k], b10 = (1 - u[r]) / (2 * p);
-                                if (la + lb > 0) G[1] = c00;
-                                for (int e = 1; e < la + lb; ++e) G[e + 1] = c00 * G[e] + e * b10 * G[e - 1];
-                                // transfer to b: H[x][y] with x + y <= la + lb
-                                double H[2 * LM][LM];
-                                for (int e = 0; e <= la + lb; ++e) H[e][0] = G[e];
-                                for (int y = 0; y < lb; ++y)
-                                    for (int x = 0; x < la + lb - y; ++x) H[x][y + 1] = H[x + 1][y] + AB[k] * H[x][y];
+                                O[k][0][0] = std::sqrt(M_PI / p);
                                 for (int x = 0; x <= la; ++x)
-                                    for (int y = 0; y <= lb; ++y) I[k][x][y] = H[x][y];
+                                    for (int y = 0; y <= lb + 2; ++y) {
+                                        if (x == 0 && y == 0) continue;
+                                        double v;
+                                        if (x > 0) {
+                                            v = PA[k] * O[k][x - 1][y];
+                                            if (x > 1) v += (x - 1) / (2 * p) * O[k][x - 2][y];
+                                            if (y > 0) v += y / (2 * p) * O[k][x - 1][y - 1];
+                                        } else {
+                                            v = PB[k] * O[k][x][y - 1];
+                                            if (y > 1) v += (y - 1) / (2 * p) * O[k][x][y - 2];
+                                        }
+                                        O[k][x][y] = v;
+                                    }
                             }
                             for (int ia = 0; ia < na; ++ia)
                                 for (int ib = 0; ib < nb; ++ib) {
                                     int a[3], b[3];
                                     cart_exps(la, ia, a[0], a[1], a[2]);
                                     cart_exps(lb, ib, b[0], b[1], b[2]);
-                                    bv[ia * nb + ib] += pre * w[r] * I[0][a[0]][b[0]] * I[1][a[1]][b[1]] * I[2][a[2]][b[2]];
+                                    double s1[3], t1[3];
+                                    for (int k = 0; k < 3; ++k) {
+                                        s1[k] = O[k][a[k]][b[k]];
+                                        double tk = -2 * be * be * O[k][a[k]][b[k] + 2] + be * (2 * b[k] + 1) * s1[k];
+                                        if (b[k] >= 2) tk -= 0.5 * b[k] * (b[k] - 1) * O[k][a[k]][b[k] - 2];
+                                        t1[k] = tk;
+                                    }
+                                    bs[ia * nb + ib] += Kab * s1[0] * s1[1] * s1[2];
+                                    bt[ia * nb + ib] += Kab * (t1[0] * s1[1] * s1[2] + s1[0] * t1[1] * s1[2] + s1[0] * s1[1] * t1[2]);
                                 }
+                            const int nr = (la + lb) / 2 + 1;
+                            for (int C = 0; C < c->natom; ++C) {
+                                if (c->Z[C] == 0) continue;
+                                double PC[3], pc2 = 0;
+                                for (int k = 0; k < 3; ++k) { PC[k] = P[k] - c->xyz[3 * C + k]; pc2 += PC[k] * PC[k]; }
+                                double u[RYS_NMAX], w[RYS_NMAX];
+                                fk_rys_host(nr, p * pc2, u, w);
+                                const double pre = -c->Z[C] * 2 * M_PI / p * Kab;
+                                for (int r = 0; r < nr; ++r) {
+                                    double I[3][LM][LM];
+                                    for (int k = 0; k < 3; ++k) {
+                                        double G[2 * LM];
+                                        G[0] = 1.0;
+                                        const double c00 = PA[k] - u[r] * PC[k], b10 = (1 - u[r]) / (2 * p);
+                                        if (la + lb > 0) G[1] = c00;
+                                        for (int e = 1; e < la + lb; ++e) G[e + 1] = c00 * G[e] + e * b10 * G[e - 1];
+                                        // transfer to b: H[x][y] with x + y <= la + lb
+                                        double H[2 * LM][LM];
+                                        for (int e = 0; e <= la + lb; ++e) H[e][0] = G[e];
+                                        for (int y = 0; y < lb; ++y)
+                                            for (int x = 0; x < la + lb - y; ++x) H[x][y + 1] = H[x + 1][y] + AB[k] * H[x][y];
+                                        for (int x = 0; x <= la; ++x)
+                                            for (int y = 0; y <= lb; ++y) I[k][x][y] = H[x][y];
+                                    }
+                                    for (int ia = 0; ia < na; ++ia)
+                                        for (int ib = 0; ib < nb; ++ib) {
+                                            int a[3], b[3];
+                                            cart_exps(la, ia, a[0], a[1], a[2]);
+                                            cart_exps(lb, ib, b[0], b[1], b[2]);
+                                            bv[ia * nb + ib] += pre * w[r] * I[0][a[0]][b[0]] * I[1][a[1]][b[1]] * I[2][a[2]][b[2]];
+                                        }
+                                }
+                            }
                         }
-                    }
+                    for (int ia = 0; ia < na; ++ia)
+                        for (int ib = 0; ib < nb; ++ib) {
+                            const int r = c->sh_bf[sa] + ia, col = c->sh_bf[sb] + ib;
+                            const double f = c->bf_scale[r] * c->bf_scale[col];
+                            const size_t e1 = (size_t)r * n + col, e2 = (size_t)col * n + r;
+                            Sc[e1] = Sc[e2] = f * bs[ia * nb + ib];
+                            Tc[e1] = Tc[e2] = f * bt[ia * nb + ib];
+                            Vc[e1] = Vc[e2] = f * bv[ia * nb + ib];
+                        }
+        
                 }
-            for (int ia = 0; ia < na; ++ia)
-                for (int ib = 0; ib < nb; ++ib) {
-                    const int r = c->sh_bf[sa] + ia, col = c->sh_bf[sb] + ib;
-                    const double f = c->bf_scale[r] * c->bf_scale[col];
-                    if (S) S[(size_t)r * n + col] = f * bs[ia * nb + ib];
-                    if (T) T[(size_t)r * n + col] = f * bt[ia * nb + ib];
-                    if (V) V[(size_t)r * n + col] = f * bv[ia * nb + ib];
-                }
-        }
+        };
+        int nth = (int)std::thread::hardware_concurrency();
+        if (const char *e = std::getenv("OMP_NUM_THREADS")) nth = std::min(nth, std::max(1, std::atoi(e)));
+        nth = std::max(1, std::min({nth, 32, c->nshell}));
+        std::vector<std::thread> pool;
+        for (int k = 1; k < nth; ++k) pool.emplace_back(work);
+        work();
+        for (auto &th : pool) th.join();
+        c->oe_S.swap(Sv);
+        c->oe_T.swap(Tv);
+        c->oe_V.swap(Vv);
+    }
+    if (S) std::copy(c->oe_S.begin(), c->oe_S.end(), S);
+    if (T) std::copy(c->oe_T.begin(), c->oe_T.end(), T);
+    if (V) std::copy(c->oe_V.begin(), c->oe_V.end(), V);
     return FK_OK;
 }
 
