@@ -192,8 +192,25 @@ __device__ __forceinline__ int nth_bit(unsigned long long m, int n)
 // Digestion: X_J[a, b_j] is reduced over the wave per bra; X_K[b_j, c],
 // X_K[b_j, d] go to memory per bra; X_K[a, c], X_K[a, d] and X_J[c, d] do not
 // depend on b_j and are summed in registers over the whole block first.
+// Workgroups per CU the compiler must fit in registers.  Two lane-per-quartet
+// classes run faster at two waves per SIMD with a few bytes spilled per lane
+// than at one wave without spills (their register demand is just above half
+// of the file); the others keep the compiler's own choice (measured, C20H42).
+template <int LA, int LB, int LC, int LD>
+struct LpqMinBlocks {
+    static constexpr int value = 1;
+};
+template <>
+struct LpqMinBlocks<1, 0, 1, 0> {
+    static constexpr int value = 2;
+};
+template <>
+struct LpqMinBlocks<2, 0, 1, 0> {
+    static constexpr int value = 2;
+};
+
 template <int LA, int LB, int LC, int LD, typename R = double>
-__global__ void __launch_bounds__(FK_BLOCK) k_jk_lpq(FkJKArgs a)
+__global__ void __launch_bounds__(FK_BLOCK, (LpqMinBlocks<LA, LB, LC, LD>::value)) k_jk_lpq(FkJKArgs a)
 {
     using Q = fk::QClass<LA, LB, LC, LD>;
     constexpr int NA = Q::NA, NB = Q::NB, NC = Q::NC, ND = Q::ND, NOUT = Q::NOUT;
