@@ -289,3 +289,46 @@ def test_autotune_keeps_results(fk, torch):
     J, K = c.build_jk(D)
     Jo, Ko = oracle.jk(s, D)
     assert np.max(np.abs(J - Jo)) < 1e-10 and np.max(np.abs(K - Ko)) < 1e-10
+
+
+@pytest.mark.parametrize("sched", [(32, 64, 0.25), (1, 1, 1.0), (3, 17, 0.5)])
+def test_extreme_schedules_keep_results(fk, torch, sched):
+    """Every class under an extreme schedule (bra blocks of 1 to 32, 1 to 64
+    kets per tile for the team and wave kernels, a quarter of the grid):
+    unscreened J/K of C3H8 / 6-31G*-type equal the oracle within 1e-10."""
+    s = wl.alkane_sys(3, "6-31gs-type")
+    S, T, V = oracle.oneel(s)
+    D = core_guess(T + V, orthogonalizer(S), s["nelec"] // 2)
+    c = fk.FockJK(0).set_system(s)
+    for la in range(3):
+        for lb in range(la + 1):
+            for lc in range(3):
+                for ld in range(lc + 1):
+                    c.set_class_schedule(la, lb, lc, ld, *sched)
+    c.build_quartets(tau=0.0)
+    J, K = c.build_jk(D)
+    Jo, Ko = oracle.jk(s, D)
+    assert np.max(np.abs(J - Jo)) < 1e-10 and np.max(np.abs(K - Ko)) < 1e-10
+
+
+def test_build_progress(fk, torch):
+    """A timed build without synchronisation reports its finished class
+    launches until all are done; the result is the synchronous one's."""
+    import time
+    s = wl.alkane_sys(4, "6-31gs-type")
+    S, T, V = oracle.oneel(s)
+    D = torch.tensor(core_guess(T + V, orthogonalizer(S), s["nelec"] // 2), device="cuda:0")
+    c = fk.FockJK(0).set_system(s).build_quartets(tau=1e-10)
+    J0, K0 = c.build_jk(D, sync=True)
+    J0, K0 = J0.clone(), K0.clone()
+    J, K = c.build_jk(D, time_classes=True)
+    t0 = time.time()
+    while True:
+        done, total = c.build_progress()
+        assert 0 <= done <= total == c.info()["nquartet_class"]
+        if done == total:
+            break
+        assert time.time() - t0 < 60
+        time.sleep(0.001)
+    torch.cuda.synchronize()
+    assert float((J - J0).abs().max()) < 1e-11 and float((K - K0).abs().max()) < 1e-11
