@@ -368,6 +368,8 @@ def main():
     if args.tau_fp32 > 0:
         # the same build in FP64 only: J/K and one-build energy differences
         ref = fk.FockJK(0).set_system(sys_).build_quartets(tau=args.tau, tau_prim=args.tau_prim)
+        if args.autotune:  # the FP64 reference with its own tuned schedules
+            ref.autotune(Dd, reps=2, stream=stream.cuda_stream)
         J64, K64 = ref.build_jk(Dd, sync=True)
         torch.cuda.synchronize()
         for _ in range(2):
