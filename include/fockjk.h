@@ -247,6 +247,12 @@ typedef struct {
                             S^(-1/2) exceeds 3e3 (overlap eigenvalues near
                             1e-7: the basis is nearly linearly dependent and
                             no direction is dropped).  Default 1e-8 */
+    int    graph;        /* 1: from the second iteration on, the Fock stage of an
+                            iteration (J/K build, F, the energy terms, X F X,
+                            the commutator and its norm) is one HIP graph,
+                            captured once and replayed, on a stream of the
+                            run's own; DIIS and purification stay eager.
+                            jk_seconds then times the whole stage.  Default 0 */
 } fk_scf_opts;
 
 typedef struct {

@@ -72,7 +72,8 @@ class TuneReport(ctypes.Structure):
 
 class ScfOpts(ctypes.Structure):
     _fields_ = [("max_iter", ctypes.c_int), ("e_tol", ctypes.c_double), ("g_tol", ctypes.c_double),
-                ("diis_n", ctypes.c_int), ("guess", ctypes.c_int), ("lindep", ctypes.c_double)]
+                ("diis_n", ctypes.c_int), ("guess", ctypes.c_int), ("lindep", ctypes.c_double),
+                ("graph", ctypes.c_int)]
 
 
 class ScfResult(ctypes.Structure):
@@ -283,7 +284,8 @@ class FockJK:
         self._check(_lib.fk_one_electron(self._ctx, _ptr(S), _ptr(T), _ptr(V), ctypes.byref(e)))
         return S, T, V, e.value
 
-    def run_scf(self, D0=None, max_iter=100, e_tol=1e-10, g_tol=1e-8, diis_n=8, lindep=1e-8, guess=None):
+    def run_scf(self, D0=None, max_iter=100, e_tol=1e-10, g_tol=1e-8, diis_n=8, lindep=1e-8, guess=None,
+                graph=False):
         """guess: GUESS_CORE (default without D0), GUESS_GIVEN (default with
         D0), GUESS_SAD or GUESS_LEARNED; max_iter=0 returns the initial
         density only."""
@@ -291,7 +293,7 @@ class FockJK:
         D = np.zeros((n, n)) if D0 is None else np.ascontiguousarray(D0, dtype=np.float64).copy()
         if guess is None:
             guess = GUESS_CORE if D0 is None else GUESS_GIVEN
-        o = ScfOpts(int(max_iter), float(e_tol), float(g_tol), int(diis_n), int(guess), float(lindep))
+        o = ScfOpts(int(max_iter), float(e_tol), float(g_tol), int(diis_n), int(guess), float(lindep), int(bool(graph)))
         r = ScfResult()
         rc = _lib.fk_run_scf(self._ctx, ctypes.byref(o), ctypes.byref(r), _ptr(D))
         if rc not in (FK_OK, FK_ERR_NOT_CONVERGED):

@@ -1766,10 +1766,10 @@ int fk_run_scf(fk_ctx *c, const fk_scf_opts *opts, fk_scf_result *result, double
     if (c->device < 0) return fail(c, FK_ERR_STATE, "fk_run_scf: context has no device");
     if (!c->have_quartets) return fail(c, FK_ERR_STATE, "fk_run_scf: call fk_build_quartets first");
     if (c->nmol > 1) return fail(c, FK_ERR_UNSUPPORTED, "fk_run_scf: one molecule per context (batches: one context each)");
-    fk_scf_opts o = {100, 1e-10, 1e-8, 8, 0, 1e-8};
+    fk_scf_opts o = {100, 1e-10, 1e-8, 8, 0, 1e-8, 0};
     if (opts) o = *opts;
     if (o.max_iter < 0 || o.diis_n < 0 || o.diis_n > 32 || !(o.e_tol > 0) || !(o.g_tol > 0) || !(o.lindep > 0) ||
-        o.guess < 0 || o.guess > 3)
+        o.guess < 0 || o.guess > 3 || (o.graph != 0 && o.graph != 1))
         return fail(c, FK_ERR_ARG, "fk_run_scf: invalid options");
     if (c->nelec % 2 != 0 || c->nelec <= 0) return fail(c, FK_ERR_ARG, "fk_run_scf: closed shell needs an even, positive electron count");
     const int n = c->nbf, nocc = c->nelec / 2;
@@ -1789,6 +1789,23 @@ int fk_run_scf(fk_ctx *c, const fk_scf_opts *opts, fk_scf_result *result, double
     w.c = c;
     w.n = n;
     w.st = nullptr;
+    // graph mode runs on a stream of its own (capture needs one); a blocking
+    // stream keeps the order with the synchronous copies of the set-up
+    struct GraphRes {
+        hipStream_t st = nullptr;
+        hipGraph_t g = nullptr;
+        hipGraphExec_t x = nullptr;
+        ~GraphRes()
+        {
+            if (x) (void)hipGraphExecDestroy(x);
+            if (g) (void)hipGraphDestroy(g);
+            if (st) (void)hipStreamDestroy(st);
+        }
+    } gr;
+    if (o.graph) {
+        HIPCHK(c, hipStreamCreate(&gr.st));
+        w.st = gr.st;
+    }
     for (auto *b : {&w.h, &w.X, &w.Xi, &w.D, &w.Do, &w.J, &w.K, &w.F, &w.Fo, &w.G, &w.E, &w.T1, &w.T2, &w.T3})
         if ((rc = dev_upload<double>(c, *b, nullptr, nn))) return rc;
     if ((rc = dev_upload<double>(c, w.part, nullptr, (size_t)fk_scf_reduce_scratch() + 2))) return rc;
@@ -1861,22 +1878,52 @@ int fk_run_scf(fk_ctx *c, const fk_scf_opts *opts, fk_scf_result *result, double
     double e_prev = 0, e_cur = 0, err = 0, jk_s = 0;
     bool converged = false;
     int it = 0;
-    for (; it < o.max_iter; ++it) {
-        const auto t0 = std::chrono::steady_clock::now();
-        if ((rc = fk_build_jk(c, w.D.p, w.J.p, w.K.p, FK_DEVICE_PTRS | FK_SYNC, w.st))) return rc;
-        jk_s += std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
-        // F = h + J - K/2 and E = (D.h + D.F)/2 + E_nuc
+    // the Fock stage: J, K, F = h + J - K/2, D.h and D.F, F' = X F X, the
+    // commutator F'D' - D'F' and its largest element, into scal[0..2]
+    auto fock_stage = [&](bool eager) -> int {
+        int r;
+        if (eager) {  // the build timed on its own
+            const auto tb = std::chrono::steady_clock::now();
+            if ((r = fk_build_jk(c, w.D.p, w.J.p, w.K.p, FK_DEVICE_PTRS | FK_SYNC, w.st))) return r;
+            jk_s += std::chrono::duration<double>(std::chrono::steady_clock::now() - tb).count();
+        } else if ((r = fk_build_jk(c, w.D.p, w.J.p, w.K.p, FK_DEVICE_PTRS, w.st))) {
+            return r;
+        }
         SCFCHK(w, fk_scf_lincomb(w.F.p, w.h.p, w.J.p, w.K.p, n, 1.0, 1.0, -0.5, 0, w.st));
-        double dh, df;
-        if ((rc = scf_reduce(w, w.D.p, w.h.p, 0, &dh)) || (rc = scf_reduce(w, w.D.p, w.F.p, 0, &df))) return rc;
-        e_prev = e_cur;
-        e_cur = 0.5 * (dh + df) + enuc;
-        // F' = X F X and the commutator e = F'D' - D'F'
+        SCFCHK(w, fk_scf_reduce(w.D.p, w.h.p, n, 0, w.part.p, w.scal.p, 0, w.st));
+        SCFCHK(w, fk_scf_reduce(w.D.p, w.F.p, n, 0, w.part.p, w.scal.p, 1, w.st));
         SCFCHK(w, fk_scf_gemm(w.X.p, w.F.p, w.T3.p, n, 1.0, 0.0, w.st));
         SCFCHK(w, fk_scf_gemm(w.T3.p, w.X.p, w.Fo.p, n, 1.0, 0.0, w.st));
         SCFCHK(w, fk_scf_gemm(w.Fo.p, w.Do.p, w.G.p, n, 1.0, 0.0, w.st));
         SCFCHK(w, fk_scf_antisym(w.E.p, w.G.p, n, w.st));
-        if ((rc = scf_reduce(w, w.E.p, nullptr, 1, &err))) return rc;
+        SCFCHK(w, fk_scf_reduce(w.E.p, nullptr, n, 1, w.part.p, w.scal.p, 2, w.st));
+        return FK_OK;
+    };
+    for (; it < o.max_iter; ++it) {
+        const auto t0 = std::chrono::steady_clock::now();
+        if (o.graph && it > 0) {
+            if (!gr.x) {  // captured once, after an eager stage has set every buffer up
+                HIPCHK(c, hipStreamBeginCapture(w.st, hipStreamCaptureModeThreadLocal));
+                rc = fock_stage(false);
+                hipGraph_t g = nullptr;
+                const hipError_t e = hipStreamEndCapture(w.st, &g);
+                gr.g = g;
+                if (rc) return rc;
+                if (e != hipSuccess) return fail(c, FK_ERR_HIP, "fk_run_scf: graph capture failed: %s", hipGetErrorString(e));
+                HIPCHK(c, hipGraphInstantiate(&gr.x, gr.g, nullptr, nullptr, 0));
+            }
+            HIPCHK(c, hipGraphLaunch(gr.x, w.st));
+        } else if ((rc = fock_stage(true))) {
+            return rc;
+        }
+        double sc[3];
+        HIPCHK(c, hipMemcpyAsync(sc, w.scal.p, 3 * sizeof(double), hipMemcpyDeviceToHost, w.st));
+        HIPCHK(c, hipStreamSynchronize(w.st));
+        if (o.graph && it > 0) jk_s += std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+        const double dh = sc[0], df = sc[1];
+        err = sc[2];
+        e_prev = e_cur;
+        e_cur = 0.5 * (dh + df) + enuc;
         if (!std::isfinite(e_cur) || !std::isfinite(err))
             return fail(c, FK_ERR_NOT_CONVERGED, "fk_run_scf: non-finite energy or error at iteration %d", it + 1);
         if (it > 0 && std::fabs(e_cur - e_prev) < o.e_tol && err < o.g_tol) {
@@ -2892,7 +2939,7 @@ extern "C" int fk_run_scf_batch(fk_ctx *c, const fk_scf_opts *opts, fk_scf_resul
     if (!c->have_quartets) return fail(c, FK_ERR_STATE, "fk_run_scf_batch: call fk_build_quartets first");
     const int nmol = c->nmol;
     std::memset(results, 0, sizeof(fk_scf_result) * (size_t)nmol);
-    fk_scf_opts o = {100, 1e-10, 1e-8, 8, 0, 1e-8};
+    fk_scf_opts o = {100, 1e-10, 1e-8, 8, 0, 1e-8, 0};
     if (opts) o = *opts;
     if (o.max_iter < 0 || o.diis_n < 0 || o.diis_n > 32 || !(o.e_tol > 0) || !(o.g_tol > 0) || !(o.lindep > 0) ||
         o.guess < 0 || o.guess > 3)

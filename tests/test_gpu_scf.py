@@ -156,3 +156,17 @@ def test_batched_scf_mixed_precision_gate(fk):
     for a, x in zip(r64, r32):
         assert a["converged"] and x["converged"]
         assert abs(a["energy"] - x["energy"]) <= 1e-6
+
+
+@pytest.mark.parametrize("name", ["water4_sto3g", "c2h6_631gs"])
+def test_scf_with_graph_replay(fk, name):
+    """The Fock stage captured once as a HIP graph and replayed every
+    iteration gives the eager run's iterations and energy (1e-10 Eh)."""
+    s = wl.water4_sto3g() if name == "water4_sto3g" else wl.alkane_sys(2, "6-31gs-type")
+    c = fk.FockJK(0).set_system(s).build_quartets(tau=1e-10)
+    r0 = c.run_scf()
+    r1 = c.run_scf(graph=True)
+    r2 = c.run_scf(graph=True, guess=fk.GUESS_SAD)
+    assert r0["converged"] and r1["converged"] and r2["converged"]
+    assert r1["iterations"] == r0["iterations"]
+    assert abs(r1["energy"] - r0["energy"]) <= 1e-10 and abs(r2["energy"] - r0["energy"]) <= 1e-9
