@@ -412,6 +412,11 @@ def main():
                 guesses["learned"] = fk.GUESS_LEARNED
             except fk.FockJKError as e:  # weights of another feature layout
                 print(f"bench.py: learned guess skipped: {e}", file=sys.stderr)
+        # the core-guess SCF again with its Fock stage replayed from a HIP graph
+        rgr = ctx.run_scf(graph=True)
+        out["scf"]["graph"] = {"iterations": rgr["iterations"], "converged": bool(rgr["converged"]),
+                               "seconds": rgr["total_seconds"], "stage_seconds": rgr["jk_seconds"],
+                               "energy_minus_eager": rgr["energy"] - r["energy"]}
         for name, g in guesses.items():
             rg = ctx.run_scf(guess=g)
             out["scf"][name] = {"iterations": rg["iterations"], "converged": bool(rg["converged"]),
