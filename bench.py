@@ -400,7 +400,9 @@ def main():
             out["mixed"]["scf_energy_fp64"] = r64["energy"]
             out["mixed"]["scf_energy_diff"] = r["energy"] - r64["energy"]
         out["scf"] = {"iterations": r["iterations"], "converged": bool(r["converged"]), "energy": r["energy"],
-                      "seconds": r["total_seconds"], "jk_seconds": r["jk_seconds"], "guess": "core Hamiltonian"}
+                      "seconds": r["total_seconds"], "jk_seconds": r["jk_seconds"],
+                      "jk_ms_per_iteration": 1000.0 * r["jk_seconds"] / max(1, r["iterations"]),
+                      "guess": "core Hamiltonian"}
         # the same SCF from the SAD guess and from the learned guess (when the
         # trained network for this basis is present)
         guesses = {"sad": fk.GUESS_SAD}
