@@ -414,6 +414,11 @@ def main():
                 guesses["learned"] = fk.GUESS_LEARNED
             except fk.FockJKError as e:  # weights of another feature layout
                 print(f"bench.py: learned guess skipped: {e}", file=sys.stderr)
+        # the core-guess SCF with incremental builds (full build every 8 iterations)
+        rin = ctx.run_scf(incremental=8)
+        out["scf"]["incremental"] = {"iterations": rin["iterations"], "converged": bool(rin["converged"]),
+                                     "seconds": rin["total_seconds"], "jk_seconds": rin["jk_seconds"],
+                                     "energy_minus_full": rin["energy"] - r["energy"]}
         # the core-guess SCF again with its Fock stage replayed from a HIP graph
         rgr = ctx.run_scf(graph=True)
         out["scf"]["graph"] = {"iterations": rgr["iterations"], "converged": bool(rgr["converged"]),

@@ -253,6 +253,11 @@ typedef struct {
                             captured once and replayed, on a stream of the
                             run's own; DIIS and purification stay eager.
                             jk_seconds then times the whole stage.  Default 0 */
+    int    incremental;  /* k > 0: J and K from the density change since the
+                            previous build, added to running sums, with a full
+                            build every k iterations (the density screen then
+                            sees the smaller change); 0 = full builds.  Not
+                            together with graph.  Default 0 */
 } fk_scf_opts;
 
 typedef struct {

@@ -73,7 +73,7 @@ class TuneReport(ctypes.Structure):
 class ScfOpts(ctypes.Structure):
     _fields_ = [("max_iter", ctypes.c_int), ("e_tol", ctypes.c_double), ("g_tol", ctypes.c_double),
                 ("diis_n", ctypes.c_int), ("guess", ctypes.c_int), ("lindep", ctypes.c_double),
-                ("graph", ctypes.c_int)]
+                ("graph", ctypes.c_int), ("incremental", ctypes.c_int)]
 
 
 class ScfResult(ctypes.Structure):
@@ -285,7 +285,7 @@ class FockJK:
         return S, T, V, e.value
 
     def run_scf(self, D0=None, max_iter=100, e_tol=1e-10, g_tol=1e-8, diis_n=8, lindep=1e-8, guess=None,
-                graph=False):
+                graph=False, incremental=0):
         """guess: GUESS_CORE (default without D0), GUESS_GIVEN (default with
         D0), GUESS_SAD or GUESS_LEARNED; max_iter=0 returns the initial
         density only."""
@@ -293,7 +293,8 @@ class FockJK:
         D = np.zeros((n, n)) if D0 is None else np.ascontiguousarray(D0, dtype=np.float64).copy()
         if guess is None:
             guess = GUESS_CORE if D0 is None else GUESS_GIVEN
-        o = ScfOpts(int(max_iter), float(e_tol), float(g_tol), int(diis_n), int(guess), float(lindep), int(bool(graph)))
+        o = ScfOpts(int(max_iter), float(e_tol), float(g_tol), int(diis_n), int(guess), float(lindep), int(bool(graph)),
+                    int(incremental))
         r = ScfResult()
         rc = _lib.fk_run_scf(self._ctx, ctypes.byref(o), ctypes.byref(r), _ptr(D))
         if rc not in (FK_OK, FK_ERR_NOT_CONVERGED):

@@ -1620,10 +1620,12 @@ struct ScfWork {
     hipStream_t st = nullptr;
     int n = 0;
     DevBuf<double> h, X, Xi, D, Do, J, K, F, Fo, G, E, T1, T2, T3, part, scal;
+    DevBuf<double> Dlast, dD, Jacc, Kacc;  // incremental builds
     std::vector<DevBuf<double>> ringF, ringE;
     ~ScfWork()
     {
-        for (auto *b : {&h, &X, &Xi, &D, &Do, &J, &K, &F, &Fo, &G, &E, &T1, &T2, &T3, &part, &scal}) dev_free(*b);
+        for (auto *b : {&h, &X, &Xi, &D, &Do, &J, &K, &F, &Fo, &G, &E, &T1, &T2, &T3, &part, &scal, &Dlast, &dD, &Jacc, &Kacc})
+            dev_free(*b);
         for (auto &b : ringF) dev_free(b);
         for (auto &b : ringE) dev_free(b);
     }
@@ -1766,10 +1768,11 @@ int fk_run_scf(fk_ctx *c, const fk_scf_opts *opts, fk_scf_result *result, double
     if (c->device < 0) return fail(c, FK_ERR_STATE, "fk_run_scf: context has no device");
     if (!c->have_quartets) return fail(c, FK_ERR_STATE, "fk_run_scf: call fk_build_quartets first");
     if (c->nmol > 1) return fail(c, FK_ERR_UNSUPPORTED, "fk_run_scf: one molecule per context (batches: one context each)");
-    fk_scf_opts o = {100, 1e-10, 1e-8, 8, 0, 1e-8, 0};
+    fk_scf_opts o = {100, 1e-10, 1e-8, 8, 0, 1e-8, 0, 0};
     if (opts) o = *opts;
     if (o.max_iter < 0 || o.diis_n < 0 || o.diis_n > 32 || !(o.e_tol > 0) || !(o.g_tol > 0) || !(o.lindep > 0) ||
-        o.guess < 0 || o.guess > 3 || (o.graph != 0 && o.graph != 1))
+        o.guess < 0 || o.guess > 3 || (o.graph != 0 && o.graph != 1) || o.incremental < 0 ||
+        (o.graph && o.incremental))
         return fail(c, FK_ERR_ARG, "fk_run_scf: invalid options");
     if (c->nelec % 2 != 0 || c->nelec <= 0) return fail(c, FK_ERR_ARG, "fk_run_scf: closed shell needs an even, positive electron count");
     const int n = c->nbf, nocc = c->nelec / 2;
@@ -1806,6 +1809,9 @@ int fk_run_scf(fk_ctx *c, const fk_scf_opts *opts, fk_scf_result *result, double
         HIPCHK(c, hipStreamCreate(&gr.st));
         w.st = gr.st;
     }
+    if (o.incremental)
+        for (auto *b : {&w.Dlast, &w.dD, &w.Jacc, &w.Kacc})
+            if ((rc = dev_upload<double>(c, *b, nullptr, nn))) return rc;
     for (auto *b : {&w.h, &w.X, &w.Xi, &w.D, &w.Do, &w.J, &w.K, &w.F, &w.Fo, &w.G, &w.E, &w.T1, &w.T2, &w.T3})
         if ((rc = dev_upload<double>(c, *b, nullptr, nn))) return rc;
     if ((rc = dev_upload<double>(c, w.part, nullptr, (size_t)fk_scf_reduce_scratch() + 2))) return rc;
@@ -1880,16 +1886,37 @@ int fk_run_scf(fk_ctx *c, const fk_scf_opts *opts, fk_scf_result *result, double
     int it = 0;
     // the Fock stage: J, K, F = h + J - K/2, D.h and D.F, F' = X F X, the
     // commutator F'D' - D'F' and its largest element, into scal[0..2]
+    int since_full = 0;
     auto fock_stage = [&](bool eager) -> int {
         int r;
-        if (eager) {  // the build timed on its own
+        if (eager && o.incremental) {
+            // J, K from the density change since the last build (screened by
+            // its own, smaller, density bounds) added to the running sums; a
+            // full build every `incremental` iterations
+            const bool full = since_full == 0;
+            const double *Dsrc = w.D.p;
+            if (!full) {
+                SCFCHK(w, fk_scf_lincomb(w.dD.p, w.D.p, w.Dlast.p, nullptr, n, 1.0, -1.0, 0, 0, w.st));
+                Dsrc = w.dD.p;
+            }
             const auto tb = std::chrono::steady_clock::now();
-            if ((r = fk_build_jk(c, w.D.p, w.J.p, w.K.p, FK_DEVICE_PTRS | FK_SYNC, w.st))) return r;
+            if ((r = fk_build_jk(c, Dsrc, w.J.p, w.K.p, FK_DEVICE_PTRS | FK_SYNC, w.st))) return r;
             jk_s += std::chrono::duration<double>(std::chrono::steady_clock::now() - tb).count();
-        } else if ((r = fk_build_jk(c, w.D.p, w.J.p, w.K.p, FK_DEVICE_PTRS, w.st))) {
-            return r;
+            SCFCHK(w, fk_scf_lincomb(w.Jacc.p, w.J.p, w.Jacc.p, nullptr, n, 1.0, full ? 0.0 : 1.0, 0, 0, w.st));
+            SCFCHK(w, fk_scf_lincomb(w.Kacc.p, w.K.p, w.Kacc.p, nullptr, n, 1.0, full ? 0.0 : 1.0, 0, 0, w.st));
+            HIPCHK(c, hipMemcpyAsync(w.Dlast.p, w.D.p, nn * sizeof(double), hipMemcpyDeviceToDevice, w.st));
+            since_full = (since_full + 1) % o.incremental;
+            SCFCHK(w, fk_scf_lincomb(w.F.p, w.h.p, w.Jacc.p, w.Kacc.p, n, 1.0, 1.0, -0.5, 0, w.st));
+        } else {
+            if (eager) {  // the build timed on its own
+                const auto tb = std::chrono::steady_clock::now();
+                if ((r = fk_build_jk(c, w.D.p, w.J.p, w.K.p, FK_DEVICE_PTRS | FK_SYNC, w.st))) return r;
+                jk_s += std::chrono::duration<double>(std::chrono::steady_clock::now() - tb).count();
+            } else if ((r = fk_build_jk(c, w.D.p, w.J.p, w.K.p, FK_DEVICE_PTRS, w.st))) {
+                return r;
+            }
+            SCFCHK(w, fk_scf_lincomb(w.F.p, w.h.p, w.J.p, w.K.p, n, 1.0, 1.0, -0.5, 0, w.st));
         }
-        SCFCHK(w, fk_scf_lincomb(w.F.p, w.h.p, w.J.p, w.K.p, n, 1.0, 1.0, -0.5, 0, w.st));
         SCFCHK(w, fk_scf_reduce(w.D.p, w.h.p, n, 0, w.part.p, w.scal.p, 0, w.st));
         SCFCHK(w, fk_scf_reduce(w.D.p, w.F.p, n, 0, w.part.p, w.scal.p, 1, w.st));
         SCFCHK(w, fk_scf_gemm(w.X.p, w.F.p, w.T3.p, n, 1.0, 0.0, w.st));
@@ -2939,7 +2966,7 @@ extern "C" int fk_run_scf_batch(fk_ctx *c, const fk_scf_opts *opts, fk_scf_resul
     if (!c->have_quartets) return fail(c, FK_ERR_STATE, "fk_run_scf_batch: call fk_build_quartets first");
     const int nmol = c->nmol;
     std::memset(results, 0, sizeof(fk_scf_result) * (size_t)nmol);
-    fk_scf_opts o = {100, 1e-10, 1e-8, 8, 0, 1e-8, 0};
+    fk_scf_opts o = {100, 1e-10, 1e-8, 8, 0, 1e-8, 0, 0};
     if (opts) o = *opts;
     if (o.max_iter < 0 || o.diis_n < 0 || o.diis_n > 32 || !(o.e_tol > 0) || !(o.g_tol > 0) || !(o.lindep > 0) ||
         o.guess < 0 || o.guess > 3)

@@ -170,3 +170,19 @@ def test_scf_with_graph_replay(fk, name):
     assert r0["converged"] and r1["converged"] and r2["converged"]
     assert r1["iterations"] == r0["iterations"]
     assert abs(r1["energy"] - r0["energy"]) <= 1e-10 and abs(r2["energy"] - r0["energy"]) <= 1e-9
+
+
+@pytest.mark.parametrize("name", ["water4_sto3g", "c2h6_631gs"])
+def test_scf_incremental_builds(fk, name):
+    """J and K from density changes (full build every 8 iterations) converge
+    to the full-build energy within 1e-8 Eh and to the oracle's."""
+    s = wl.water4_sto3g() if name == "water4_sto3g" else wl.alkane_sys(2, "6-31gs-type")
+    c = fk.FockJK(0).set_system(s).build_quartets(tau=1e-10)
+    r0 = c.run_scf()
+    r1 = c.run_scf(incremental=8)
+    assert r0["converged"] and r1["converged"]
+    assert abs(r1["energy"] - r0["energy"]) <= 1e-8
+    assert abs(r1["energy"] - run_scf(s)["E"]) <= 1e-8
+    assert abs(r1["iterations"] - r0["iterations"]) <= 3
+    with pytest.raises(fk.FockJKError):
+        c.run_scf(incremental=8, graph=True)
