@@ -255,9 +255,10 @@ typedef struct {
                             jk_seconds then times the whole stage.  Default 0 */
     int    incremental;  /* k > 0: J and K from the density change since the
                             previous build, added to running sums, with a full
-                            build every k iterations (the density screen then
-                            sees the smaller change); 0 = full builds.  Not
-                            together with graph.  Default 0 */
+                            build every k iterations; the change is screened
+                            with tau / 1000 (its smaller density bounds still
+                            drop most quartets late in the run); 0 = full
+                            builds.  Not together with graph.  Default 0 */
 } fk_scf_opts;
 
 typedef struct {

@@ -119,6 +119,7 @@ struct fk_ctx {
     struct ClassSched { int bb = 0, kt = 0; double gf = 1.0; };
     std::map<int, ClassSched> sched;
     std::vector<double> oe_S, oe_T, oe_V;          // one-electron matrices of the current geometry and basis
+    double dscreen_scale = 1.0;                   // per-quartet threshold = tau * this (builds from density changes)
     // initial guesses
     std::vector<double> coef_in;                  // contraction coefficients as given
     std::map<std::vector<double>, std::vector<double>> sad_cache; // atomic density per (element, shells)
@@ -1074,7 +1075,7 @@ int fk_build_jk(fk_ctx *c, const double *D, double *J, double *K, unsigned flags
         a.XK = c->d_X.p + nn;
         a.xcopy = (long long)(2 * nn);
         a.dscreen = c->opts.density_screen && c->opts.tau > 0;
-        a.tau = c->opts.tau;
+        a.tau = c->opts.tau * c->dscreen_scale;
         a.rys_tab = c->d_rys.p + rys_staged_offset(qc.info.nroot);
         a.counters = c->d_cnt.p + 2 * i;
         a.bra_slot = qc.bra_slot;
@@ -1900,7 +1901,12 @@ int fk_run_scf(fk_ctx *c, const fk_scf_opts *opts, fk_scf_result *result, double
                 Dsrc = w.dD.p;
             }
             const auto tb = std::chrono::steady_clock::now();
-            if ((r = fk_build_jk(c, Dsrc, w.J.p, w.K.p, FK_DEVICE_PTRS | FK_SYNC, w.st))) return r;
+            // a density change is screened 1000 times tighter, so that the
+            // running sums stay as accurate as full builds
+            c->dscreen_scale = full ? 1.0 : 1e-3;
+            r = fk_build_jk(c, Dsrc, w.J.p, w.K.p, FK_DEVICE_PTRS | FK_SYNC, w.st);
+            c->dscreen_scale = 1.0;
+            if (r) return r;
             jk_s += std::chrono::duration<double>(std::chrono::steady_clock::now() - tb).count();
             SCFCHK(w, fk_scf_lincomb(w.Jacc.p, w.J.p, w.Jacc.p, nullptr, n, 1.0, full ? 0.0 : 1.0, 0, 0, w.st));
             SCFCHK(w, fk_scf_lincomb(w.Kacc.p, w.K.p, w.Kacc.p, nullptr, n, 1.0, full ? 0.0 : 1.0, 0, 0, w.st));
