@@ -260,7 +260,7 @@ def main():
                     help="precision split: FP32 recurrences for quartets with G_ab G_cd * 2 below this (0: FP64)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported", file=sys.stderr)
+        print(f"bench.py: the library runs on one GPU; --gpus {args.gpus} is not supported", file=sys.stderr)
         return 2
     import torch
     import paper_2407_21445_amd as fk
