@@ -190,8 +190,9 @@ int fk_build_progress(fk_ctx *ctx, int *done, int *total);
  * work tile (0 = fk_screen_opts.bra_block; capped by the class kernel),
  * kets_per_tile = 1..64 kets per tile for the team and wave-per-quartet
  * kernels (0 = two rounds; lane-per-quartet kernels always take 64),
- * grid_fraction = share (0, 1] of the resident-workgroup grid that is
- * launched (the persistent loop covers every tile either way).  A schedule
+ * grid_fraction = size (0, 4] of the launched grid relative to the
+ * resident-workgroup grid (the persistent loop covers every tile either way;
+ * above 1 the later workgroups start as the first ones finish).  A schedule
  * changes the work order only, never the result beyond rounding order.
  * Takes effect at the next fk_build_quartets; fk_set_geometry, fk_set_basis
  * and fk_set_molecules clear all schedules. */
@@ -215,12 +216,12 @@ typedef struct {
  * screening options (those of the last fk_build_quartets) and density D
  * (as in fk_build_jk: FK_DEVICE_PTRS for a device pointer, else host), it
  * tries one axis at a time for all classes at once -- bra_block 1..32, then
- * 1, 2, 4, 8 rounds of kets per tile, then grid fractions 1, 1/2, 1/4 --
+ * 1, 2, 4, 8 rounds of kets per tile, then grid fractions 1, 1/2, 1/4, 2, 4 --
  * rebuilding the lists and timing each class launch with HIP events (one
  * warm-up and `reps` timed builds, the minimum kept), keeps for each class the
  * candidate more than 2 % faster than its best so far, and leaves the lists
  * built with the chosen schedules.  report may be NULL.  Runs about
- * 14 (reps + 1) builds and 14 list builds; allocates three nbf^2 buffers for
+ * 16 (reps + 1) builds and 16 list builds; allocates three nbf^2 buffers for
  * its duration. */
 int fk_autotune(fk_ctx *ctx, const double *D, unsigned flags, int reps, void *stream, fk_tune_report *report);
 

@@ -1162,8 +1162,8 @@ int fk_set_class_schedule(fk_ctx *c, int la, int lb, int lc, int ld, int bra_blo
     int P = pair_class(la, lb), Q = pair_class(lc, ld);
     if (P < Q) std::swap(P, Q);
     if (bra_block < 0 || bra_block > FK_MAX_BRA_BLOCK || kets_per_tile < 0 || kets_per_tile > 64 ||
-        !(grid_fraction > 0 && grid_fraction <= 1))
-        return fail(c, FK_ERR_ARG, "fk_set_class_schedule: bra_block 0..%d, kets_per_tile 0..64, grid_fraction (0, 1]",
+        !(grid_fraction > 0 && grid_fraction <= 4))
+        return fail(c, FK_ERR_ARG, "fk_set_class_schedule: bra_block 0..%d, kets_per_tile 0..64, grid_fraction (0, 4]",
                     FK_MAX_BRA_BLOCK);
     c->sched[P * NPC + Q] = fk_ctx::ClassSched{bra_block, kets_per_tile, grid_fraction};
     return FK_OK;
@@ -1228,7 +1228,7 @@ int fk_autotune(fk_ctx *c, const double *D, unsigned flags, int reps, void *stre
         std::vector<double> vals;
         if (axis == 0) vals = {1, 2, 4, 8, 16, 32};
         else if (axis == 1) vals = {1, 2, 4, 8};   // rounds of kets (team and wave kernels)
-        else vals = {1.0, 0.5, 0.25};
+        else vals = {1.0, 0.5, 0.25, 2.0, 4.0};
         for (double v : vals) {
             std::map<int, fk_ctx::ClassSched> trial = cur;
             for (auto &kv : trial) {

@@ -304,7 +304,7 @@ def test_class_schedules_keep_the_lists(sched):
 
 def test_class_schedule_errors():
     c = fk.FockJK(device=-1).set_system(wl.water4_sto3g())
-    for bad in [(0, 1, 0, 0, 0, 0, 1.0), (1, 0, 0, 0, 33, 0, 1.0), (1, 0, 0, 0, 0, 65, 1.0), (1, 0, 0, 0, 0, 0, 0.0)]:
+    for bad in [(0, 1, 0, 0, 0, 0, 1.0), (1, 0, 0, 0, 33, 0, 1.0), (1, 0, 0, 0, 0, 65, 1.0), (1, 0, 0, 0, 0, 0, 0.0), (1, 0, 0, 0, 0, 0, 4.5)]:
         with pytest.raises(fk.FockJKError) as e:
             c.set_class_schedule(*bad)
         assert e.value.code == fk.FK_ERR_ARG
