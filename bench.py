@@ -40,10 +40,12 @@ def _kernel_source_hash():
     return h.hexdigest()
 
 
-def _traffic(kernel_name, workload):
+def _traffic(kernel_name, workload, schedule="default"):
     """HBM bytes per launch of the named kernel from profiles/roofline_traffic.json
     (rocprofv3 FETCH_SIZE and WRITE_SIZE, each scaled by the same counter on a
-    plain copy of known size), or None when absent or taken on other kernels."""
+    plain copy of known size), or None when absent, taken on other kernels or
+    under another schedule of the class ("default", or [bra block, kets per
+    tile, grid fraction])."""
     path = os.path.join(HERE, "profiles", "roofline_traffic.json")
     if not os.path.exists(path):
         return None
@@ -52,7 +54,7 @@ def _traffic(kernel_name, workload):
     if t.get("source_sha256") != _kernel_source_hash() or t.get("workload") != workload:
         return None
     for k in t.get("kernels", []):
-        if k["kernel"] == kernel_name:
+        if k["kernel"] == kernel_name and k.get("schedule", "default") == schedule:
             return k["fetch_bytes_per_launch"] * t["copy_scale_fetch"] + k["write_bytes_per_launch"] * t["copy_scale_write"]
     return None
 
@@ -245,6 +247,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--classes", action="store_true", help="print the per-class kernel table to stderr")
+    ap.add_argument("--schedule", action="append", default=[], metavar="LA,LB,LC,LD,BB,KT,GF",
+                    help="fix a class schedule (bra block, kets per tile, grid fraction) before the lists "
+                         "are built; with --no-autotune it is the one timed")
     ap.add_argument("--no-scf", action="store_true", help="skip the SCF run reported beside the build rate")
     ap.add_argument("--no-autotune", dest="autotune", action="store_false",
                     help="time the default kernel schedules (the autotuner runs by default, before timing)")
@@ -276,7 +281,16 @@ def main():
     if args.workload == "c4":
         return bench_batch(args, torch, fk)
     sys_, desc = _workload(args.workload)
-    ctx = fk.FockJK(0).set_system(sys_).build_quartets(tau=args.tau, tau_prim=args.tau_prim, tau_fp32=args.tau_fp32)
+    ctx = fk.FockJK(0).set_system(sys_)
+    pinned = {}
+    for spec in args.schedule:
+        v = spec.split(",")
+        if len(v) != 7:
+            raise SystemExit(f"--schedule {spec}: expected LA,LB,LC,LD,BRA_BLOCK,KETS,GRID_FRACTION")
+        cls, sch = tuple(int(x) for x in v[:4]), (int(v[4]), int(v[5]), float(v[6]))
+        ctx.set_class_schedule(*cls, *sch)
+        pinned[cls] = list(sch)
+    ctx.build_quartets(tau=args.tau, tau_prim=args.tau_prim, tau_fp32=args.tau_fp32)
     info = ctx.info()
     S, T, V, _ = ctx.one_electron()
     D = _core_density(S, T + V, sys_["nelec"] // 2)
@@ -342,10 +356,12 @@ def main():
     peak = PEAK_FP32_VALU if c["precision"] == 32 else PEAK_FP64_VALU
     lname = "spdf"
     cname = "({}{}|{}{})".format(*(lname[x] for x in c["class"]))
-    # the committed counter figures were taken under the default schedules
-    dominant_changed = any(r["changed"] for r in tuned_rows
-                           if (r["la"], r["lb"], r["lc"], r["ld"]) == tuple(c["class"])
-                           and r["precision"] == c["precision"])
+    # the committed counter figures name the schedule they were taken under
+    sched = pinned.get(tuple(c["class"]), "default")
+    for r in tuned_rows:
+        if (r["la"], r["lb"], r["lc"], r["ld"]) == tuple(c["class"]) and r["precision"] == c["precision"] \
+                and r["changed"]:
+            sched = [r["bra_block"], r["kets_per_tile"], r["grid_fraction"]]
     out = {
         "metric": METRIC, "value": 1000.0 / ms, "unit": "builds/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
@@ -360,9 +376,9 @@ def main():
         "flops_per_build": st["flops_total"], "tflops_build": st["flops_total"] / (ms * 1e-3) / 1e12,
         "wall_s_timed": wall,
         "roofline": {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
-                     "frac": achieved / peak, "traffic": None if dominant_changed else _traffic(f"J/K class {cname}", args.workload),
+                     "frac": achieved / peak, "traffic": _traffic(f"J/K class {cname}", args.workload, sched),
                      "kernel": f"J/K class {cname}" + (" (FP32 part)" if c["precision"] == 32 else ""),
-                     "kernel_ms": float(cls_ms[i]),
+                     "kernel_ms": float(cls_ms[i]), "schedule": sched,
                      "class_share": float(cls_ms[i] / cls_ms.sum())},
     }
     if args.tau_fp32 > 0:

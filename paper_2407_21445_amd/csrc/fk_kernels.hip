@@ -25,7 +25,10 @@
 #ifndef FK_BUILD_MAXL
 #define FK_BUILD_MAXL 3
 #endif
-#define FK_LPQ_MAX_NOUT 81
+// lane-per-quartet classes have at most this many integrals per lane; (pp|pp),
+// with 81, runs as a team class (three lanes per quartet): one lane's 81
+// accumulators spilled, and the team kernel took less than half the time
+#define FK_LPQ_MAX_NOUT 80
 // lane-per-quartet classes up to this many integrals sum K[a,c], K[a,d] and
 // J[c,d] over a block of bras in registers; larger ones take one bra per tile
 #define FK_LPQ_BLOCK_NOUT 54
@@ -192,10 +195,12 @@ __device__ __forceinline__ int nth_bit(unsigned long long m, int n)
 // Digestion: X_J[a, b_j] is reduced over the wave per bra; X_K[b_j, c],
 // X_K[b_j, d] go to memory per bra; X_K[a, c], X_K[a, d] and X_J[c, d] do not
 // depend on b_j and are summed in registers over the whole block first.
-// Workgroups per CU the compiler must fit in registers.  Two lane-per-quartet
-// classes run faster at two waves per SIMD with a few bytes spilled per lane
-// than at one wave without spills (their register demand is just above half
-// of the file); the others keep the compiler's own choice (measured, C20H42).
+// Waves per SIMD the compiler must fit in registers (one workgroup of four
+// waves places one per SIMD).  Four lane-per-quartet classes run faster at two
+// waves per SIMD with some bytes spilled per lane than at one wave without
+// spills (their register demand is just above half of the file); the others
+// keep the compiler's own choice (measured, C20H42).  (ps|ss) at three waves
+// spilled 124 bytes per lane, doubled its HBM traffic and gained nothing.
 template <int LA, int LB, int LC, int LD>
 struct LpqMinBlocks {
     static constexpr int value = 1;
@@ -206,6 +211,14 @@ struct LpqMinBlocks<1, 0, 1, 0> {
 };
 template <>
 struct LpqMinBlocks<2, 0, 1, 0> {
+    static constexpr int value = 2;
+};
+template <>
+struct LpqMinBlocks<1, 1, 1, 0> {
+    static constexpr int value = 2;
+};
+template <>
+struct LpqMinBlocks<2, 1, 0, 0> {
     static constexpr int value = 2;
 };
 
@@ -481,8 +494,24 @@ struct TeamShape {
 
 __device__ __forceinline__ void lds_add(double *p, double v) { unsafeAtomicAdd(p, v); }
 
+// Waves per SIMD the compiler must fit in registers (as for the lane-per-quartet
+// kernels): two team classes whose demand is just above half of the file run
+// faster at two waves with some bytes spilled (measured, C20H42).
+template <int LA, int LB, int LC, int LD>
+struct TpqMinBlocks {
+    static constexpr int value = 1;
+};
+template <>
+struct TpqMinBlocks<2, 1, 2, 0> {
+    static constexpr int value = 2;
+};
+template <>
+struct TpqMinBlocks<2, 2, 1, 0> {
+    static constexpr int value = 2;
+};
+
 template <int LA, int LB, int LC, int LD, int MODE, typename R = double>
-__global__ void __launch_bounds__(FK_BLOCK) k_jk_tpq(FkJKArgs a)
+__global__ void __launch_bounds__(FK_BLOCK, (TpqMinBlocks<LA, LB, LC, LD>::value)) k_jk_tpq(FkJKArgs a)
 {
     using Q = fk::QClass<LA, LB, LC, LD>;
     using TSh = TeamShape<LA, LB, LC, LD, MODE>;
