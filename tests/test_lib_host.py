@@ -1,6 +1,7 @@
 """Host-side checks of libfockjk that need no GPU: exported symbols, the Rys
 tables, the per-quartet integral code evaluated on the host, one-electron
 integrals, screening lists and argument validation."""
+import json
 import math
 import os
 import re
@@ -342,3 +343,34 @@ def test_sad_density_mixed_bases():
     nbf, off = c.molecule_layout()
     for m, s in enumerate(mols):
         assert np.max(np.abs(D[off[m]:off[m + 1]].reshape(nbf[m], nbf[m]) - og.sad_density(s))) < 1e-9
+
+
+def test_bench_traffic_follows_the_schedule(tmp_path, monkeypatch):
+    """bench.py reports the committed counter traffic only for the kernel
+    sources and the class schedule it was measured under."""
+    import importlib.util
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    spec = importlib.util.spec_from_file_location("bench_mod", os.path.join(root, "bench.py"))
+    bench = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(bench)
+    t = {"workload": "c20h42", "source_sha256": bench._kernel_source_hash(), "copy_scale_fetch": 2.0,
+         "copy_scale_write": 1.0,
+         "kernels": [{"kernel": "J/K class (ps|ss)", "schedule": "default", "fetch_bytes_per_launch": 10.0,
+                      "write_bytes_per_launch": 100.0},
+                     {"kernel": "J/K class (ps|ss)", "schedule": [8, 64, 4.0], "fetch_bytes_per_launch": 20.0,
+                      "write_bytes_per_launch": 300.0},
+                     {"kernel": "J/K class (ss|ss)", "fetch_bytes_per_launch": 1.0, "write_bytes_per_launch": 1.0}]}
+    os.makedirs(tmp_path / "profiles")
+    with open(tmp_path / "profiles" / "roofline_traffic.json", "w") as f:
+        json.dump(t, f)
+    # the hash is taken from the real sources; only the profile directory moves
+    real_hash = bench._kernel_source_hash()
+    monkeypatch.setattr(bench, "HERE", str(tmp_path))
+    monkeypatch.setattr(bench, "_kernel_source_hash", lambda: real_hash)
+    assert bench._traffic("J/K class (ps|ss)", "c20h42") == 120.0
+    assert bench._traffic("J/K class (ps|ss)", "c20h42", [8, 64, 4.0]) == 340.0
+    assert bench._traffic("J/K class (ps|ss)", "c20h42", [8, 64, 2.0]) is None
+    assert bench._traffic("J/K class (ss|ss)", "c20h42") == 3.0   # no schedule field: default
+    assert bench._traffic("J/K class (ps|ss)", "water64") is None
+    monkeypatch.setattr(bench, "_kernel_source_hash", lambda: "other sources")
+    assert bench._traffic("J/K class (ps|ss)", "c20h42") is None
