@@ -279,6 +279,42 @@ def test_batch_equals_single_molecules(fk, torch, tau):
             assert np.max(np.abs(Jb - Jo)) <= 1e-10 * scale and np.max(np.abs(Kb - Ko)) <= 1e-10 * scale, i
 
 
+def test_jk_organic_batch_sampled_blocks(fk, torch):
+    """The first four molecules of the organic batch (tzvp-type, s-f, 3894
+    functions) in one batched build, in the configuration the benchmark times
+    (tau = 1e-10, primitive pairs pruned at 1e-12): sampled shell blocks of
+    molecules 0 and 2, f-d, s-p, f-f and d-p among them, against the oracle's
+    literal sums on each molecule alone, within 1e-8 relative to
+    max(1, |J|max)."""
+    b = wl.organic_batch(4)
+    Ds = [_rand_D(m["nbf"], 80 + i) * 0.01 for i, m in enumerate(b["mols"])]
+    c = fk.FockJK(0).set_system(b).set_molecules(b["atom_mol"]).build_quartets(tau=1e-10, tau_prim=1e-12)
+    nbf, off = c.molecule_layout()
+    Dd = torch.tensor(np.concatenate([d.ravel() for d in Ds]), dtype=torch.float64, device="cuda")
+    J, K = c.build_jk(Dd, sync=True)
+    J, K = J.cpu().numpy(), K.cpu().numpy()
+    for i in (0, 2):
+        m, n = b["mols"][i], b["mols"][i]["nbf"]
+        Jm, Km = J[off[i]:off[i + 1]].reshape(n, n), K[off[i]:off[i + 1]].reshape(n, n)
+        l = np.asarray(m["sh_l"])
+        f = [int(x) for x in np.where(l == 3)[0]]
+        d = int(np.where(l == 2)[0][0])
+        p = int(np.where(l == 1)[0][0])
+        jp, kp = [(f[0], d), (0, p)], [(f[0], f[-1]), (d, p)]
+        Jb, Kb = oracle.jk_blocks(m, Ds[i], jp, kp)
+        bo = oracle.bf_offsets(m)
+        scale = max(1.0, max(float(np.max(np.abs(x))) for x in Jb))
+        for (x, y), blk in zip(jp, Jb):
+            err = np.max(np.abs(Jm[bo[x]:bo[x + 1], bo[y]:bo[y + 1]] - blk))
+            print(f"organic mol {i} J[{x},{y}] max {np.max(np.abs(blk)):.2e} err {err:.2e}", flush=True)
+            assert err <= 1e-8 * scale, (i, x, y)
+        for (x, y), blk in zip(kp, Kb):
+            err = np.max(np.abs(Km[bo[x]:bo[x + 1], bo[y]:bo[y + 1]] - blk))
+            print(f"organic mol {i} K[{x},{y}] max {np.max(np.abs(blk)):.2e} err {err:.2e}", flush=True)
+            assert err <= 1e-8 * scale, (i, x, y)
+    c.close()
+
+
 def test_build_in_hip_graph(fk, torch):
     """A J/K build captured in a HIP graph (no host synchronisation, no
     memset inside) and replayed several times, with eager work and
