@@ -25,10 +25,15 @@
 #ifndef FK_BUILD_MAXL
 #define FK_BUILD_MAXL 3
 #endif
-// lane-per-quartet classes have at most this many integrals per lane; (pp|pp),
-// with 81, runs as a team class (three lanes per quartet): one lane's 81
-// accumulators spilled, and the team kernel took less than half the time
-#define FK_LPQ_MAX_NOUT 80
+// lane-per-quartet classes have at most this many integrals per lane.  Above
+// it a team of lanes shares a quartet: (pp|pp) with 81 integrals spilled 292
+// bytes per lane as a lane class and runs in less than half the time with
+// three lanes per quartet; (fs|ds) and (fd|ss) with 60 held one wave per SIMD
+// and run 4.4 and 1.4 times faster with ten lanes per quartet (two waves)
+#define FK_LPQ_MAX_NOUT 54
+// team classes keep at most this many integrals per lane (MODE 1: NB NC ND,
+// MODE 2: NC ND); larger ones take a whole wave per quartet
+#define FK_TEAM_MAX_NOUT 80
 // lane-per-quartet classes up to this many integrals sum K[a,c], K[a,d] and
 // J[c,d] over a block of bras in registers; larger ones take one bra per tile
 #define FK_LPQ_BLOCK_NOUT 54
@@ -47,8 +52,8 @@ constexpr int kernel_kind()
 {
     using Q = fk::QClass<LA, LB, LC, LD>;
     if (Q::NOUT <= FK_LPQ_MAX_NOUT) return 0;
-    if (Q::NB * Q::NC * Q::ND <= FK_LPQ_MAX_NOUT) return 1;
-    if (Q::NA * Q::NB <= 64 && Q::NC * Q::ND <= FK_LPQ_MAX_NOUT) return 2;
+    if (Q::NB * Q::NC * Q::ND <= FK_TEAM_MAX_NOUT) return 1;
+    if (Q::NA * Q::NB <= 64 && Q::NC * Q::ND <= FK_TEAM_MAX_NOUT) return 2;
     return 3;
 }
 
