@@ -374,3 +374,30 @@ def test_bench_traffic_follows_the_schedule(tmp_path, monkeypatch):
     assert bench._traffic("J/K class (ps|ss)", "water64") is None
     monkeypatch.setattr(bench, "_kernel_source_hash", lambda: "other sources")
     assert bench._traffic("J/K class (ps|ss)", "c20h42") is None
+
+
+def test_class_kernel_choice():
+    """Lanes per contracted quartet for every class up to f: one lane up to 54
+    integrals; above it a team of NA lanes while a lane keeps at most 80
+    integrals (NB NC ND), else NA NB lanes (NC ND <= 80), else the whole wave.
+    (pp|pp), (fs|ds) and (fd|ss) are team classes (measured faster than as
+    lane classes), (dp|ps) with 54 integrals a lane class."""
+    s = wl.organic_batch(1)
+    c = fk.FockJK(device=-1).set_system(s).build_quartets(tau=1e-10)
+    nc = [1, 3, 6, 10]
+    got = {r["class"]: r["team_size"] for r in c.stats()["classes"]}
+    assert len(got) == 55
+    for (la, lb, lc, ld), ts in got.items():
+        NA, NB, NC, ND = nc[la], nc[lb], nc[lc], nc[ld]
+        if NA * NB * NC * ND <= 54:
+            want = 1
+        elif NB * NC * ND <= 80:
+            want = NA
+        elif NA * NB <= 64 and NC * ND <= 80:
+            want = NA * NB
+        else:
+            want = 64
+        assert ts == want, ((la, lb, lc, ld), ts, want)
+    assert got[(1, 1, 1, 1)] == 3 and got[(3, 0, 2, 0)] == 10 and got[(3, 2, 0, 0)] == 10
+    assert got[(2, 1, 1, 0)] == 1
+    c.close()
