@@ -201,10 +201,11 @@ __device__ __forceinline__ int nth_bit(unsigned long long m, int n)
 // X_K[b_j, d] go to memory per bra; X_K[a, c], X_K[a, d] and X_J[c, d] do not
 // depend on b_j and are summed in registers over the whole block first.
 // Waves per SIMD the compiler must fit in registers (one workgroup of four
-// waves places one per SIMD).  Four lane-per-quartet classes run faster at two
+// waves places one per SIMD).  Five lane-per-quartet classes run faster at two
 // waves per SIMD with some bytes spilled per lane than at one wave without
 // spills (their register demand is just above half of the file); the others
-// keep the compiler's own choice (measured, C20H42).  (ps|ss) at three waves
+// keep the compiler's own choice (measured: C20H42, (fs|ss) on the organic
+// batch).  (ps|ss) at three waves
 // spilled 124 bytes per lane, doubled its HBM traffic and gained nothing.
 template <int LA, int LB, int LC, int LD>
 struct LpqMinBlocks {
@@ -224,6 +225,10 @@ struct LpqMinBlocks<1, 1, 1, 0> {
 };
 template <>
 struct LpqMinBlocks<2, 1, 0, 0> {
+    static constexpr int value = 2;
+};
+template <>
+struct LpqMinBlocks<3, 0, 0, 0> {
     static constexpr int value = 2;
 };
 
@@ -500,8 +505,9 @@ struct TeamShape {
 __device__ __forceinline__ void lds_add(double *p, double v) { unsafeAtomicAdd(p, v); }
 
 // Waves per SIMD the compiler must fit in registers (as for the lane-per-quartet
-// kernels): two team classes whose demand is just above half of the file run
-// faster at two waves with some bytes spilled (measured, C20H42).
+// kernels): team classes whose demand is just above half of the file run
+// faster at two waves with some bytes spilled (measured: the d classes on
+// C20H42, the f classes on the organic batch).
 template <int LA, int LB, int LC, int LD>
 struct TpqMinBlocks {
     static constexpr int value = 1;
@@ -512,6 +518,22 @@ struct TpqMinBlocks<2, 1, 2, 0> {
 };
 template <>
 struct TpqMinBlocks<2, 2, 1, 0> {
+    static constexpr int value = 2;
+};
+template <>
+struct TpqMinBlocks<3, 2, 1, 0> {
+    static constexpr int value = 2;
+};
+template <>
+struct TpqMinBlocks<3, 0, 1, 1> {
+    static constexpr int value = 2;
+};
+template <>
+struct TpqMinBlocks<3, 1, 2, 0> {
+    static constexpr int value = 2;
+};
+template <>
+struct TpqMinBlocks<3, 0, 3, 0> {
     static constexpr int value = 2;
 };
 
