@@ -220,6 +220,73 @@ def test_nuclear_attraction_gaussian_charge():
     assert V[0, 0] == pytest.approx(ref, rel=1e-13)
 
 
+def _v_elem(atoms, Z, la, ea, lb, eb, comp_a, comp_b):
+    """One element of the oracle's V between a single primitive of momentum la
+    on atom 0 and one of momentum lb on atom 1 (Cartesian components by index)."""
+    s = _sys(atoms, [{"atom": 0, "l": la, "exps": [ea], "coefs": [1.0]},
+                     {"atom": 1, "l": lb, "exps": [eb], "coefs": [1.0]}], Z=Z)
+    _, _, V = oracle.oneel(s)
+    na = (la + 1) * (la + 2) // 2
+    return V[comp_a, na + comp_b]
+
+
+def _fd(f, h=1e-3):
+    return (-f(2 * h) + 8 * f(h) - 8 * f(-h) + f(-2 * h)) / (12 * h)
+
+
+def test_nuclear_attraction_p_d_f_are_centre_derivatives():
+    """Nuclear attraction of p, d and f functions (Hermite form with the Boys
+    function) against centre derivatives of lower momenta.  The moving function
+    sits on a ghost centre (Z = 0), so only the function moves, never a nucleus;
+    two real nuclei elsewhere.  For primitives normalised per component:
+        p_x   = a^(-1/2) d/dA_x s,
+        d_xy  = a^(-1/2) d/dA_y p_x,
+        d_xx  = (d/dA_x p_x + 2 a^(1/2) s) / (3a)^(1/2),
+        f_xyz = a^(-1/2) d/dA_z d_xy,
+    each checked by a 4-point central difference of the oracle's own lower
+    element, starting from the s-s element that the Gaussian-charge test
+    pins.  A sign error in the centre reflection, a wrong index of the R
+    tensor or a transposed component fails one of them.  Both sides (bra and
+    ket function) are moved."""
+    rng = np.random.default_rng(17)
+    base = np.vstack([rng.uniform(-1, 1, size=(2, 3)), [[0.3, -1.1, 0.8], [-0.9, 0.6, -0.4]]])
+    Z = [0, 0, 3, 1]
+    ea, eb = 0.85, 0.55
+
+    def moved(atom, axis, h):
+        at = base.copy()
+        at[atom, axis] += h
+        return at
+
+    # bra side: function on atom 0 moves
+    p_x = _v_elem(base, Z, 1, ea, 0, eb, 0, 0)
+    fd = _fd(lambda h: _v_elem(moved(0, 0, h), Z, 0, ea, 0, eb, 0, 0))
+    assert p_x == pytest.approx(fd / math.sqrt(ea), rel=1e-8)
+    p_y = _v_elem(base, Z, 1, ea, 0, eb, 1, 0)
+    fd = _fd(lambda h: _v_elem(moved(0, 1, h), Z, 0, ea, 0, eb, 0, 0))
+    assert p_y == pytest.approx(fd / math.sqrt(ea), rel=1e-8)
+    # d_xy (component 1 of xx, xy, xz, yy, yz, zz) from p_x moved along y
+    d_xy = _v_elem(base, Z, 2, ea, 0, eb, 1, 0)
+    fd = _fd(lambda h: _v_elem(moved(0, 1, h), Z, 1, ea, 0, eb, 0, 0))
+    assert d_xy == pytest.approx(fd / math.sqrt(ea), rel=1e-7)
+    # d_xx from p_x moved along x and the s element
+    d_xx = _v_elem(base, Z, 2, ea, 0, eb, 0, 0)
+    s_s = _v_elem(base, Z, 0, ea, 0, eb, 0, 0)
+    fd = _fd(lambda h: _v_elem(moved(0, 0, h), Z, 1, ea, 0, eb, 0, 0))
+    assert d_xx == pytest.approx((fd + 2 * math.sqrt(ea) * s_s) / math.sqrt(3 * ea), rel=1e-7)
+    # f_xyz (component 4 of xxx, xxy, xxz, xyy, xyz, ...) from d_xy moved along z
+    f_xyz = _v_elem(base, Z, 3, ea, 0, eb, 4, 0)
+    fd = _fd(lambda h: _v_elem(moved(0, 2, h), Z, 2, ea, 0, eb, 1, 0))
+    assert f_xyz == pytest.approx(fd / math.sqrt(ea), rel=1e-7)
+    # ket side: function on atom 1 moves; p on both sides
+    s_pz = _v_elem(base, Z, 0, ea, 1, eb, 0, 2)
+    fd = _fd(lambda h: _v_elem(moved(1, 2, h), Z, 0, ea, 0, eb, 0, 0))
+    assert s_pz == pytest.approx(fd / math.sqrt(eb), rel=1e-8)
+    px_dyz = _v_elem(base, Z, 1, ea, 2, eb, 0, 4)
+    fd = _fd(lambda h: _v_elem(moved(1, 1, h), Z, 1, ea, 1, eb, 0, 2))
+    assert px_dyz == pytest.approx(fd / math.sqrt(eb), rel=1e-7)
+
+
 # ------------------------------------------------------- J/K brute force ---
 @pytest.mark.parametrize("seed", [0, 1])
 def test_jk_matches_brute_force(seed):
