@@ -67,6 +67,12 @@ typedef enum {
 #define FK_DEVICE_PTRS 1u     /* D, J, K are device pointers (else host pointers) */
 #define FK_SYNC 2u            /* synchronise the stream before returning */
 #define FK_TIME_CLASSES 4u    /* record HIP events around each class kernel (read by fk_stats) */
+#define FK_J_ONLY 8u          /* form J only (paper, "Hartree-Fock Energy Formulation": J_uv =
+                                 sum_ls (uv|ls) D_ls); K is not written and may be NULL.  The
+                                 density screen then uses D_ab and D_cd only */
+#define FK_K_ONLY 16u         /* form K only (K_uv = sum_ls (ul|vs) D_ls); J is not written and
+                                 may be NULL; the density screen uses D_ac, D_ad, D_bc, D_bd.
+                                 FK_J_ONLY | FK_K_ONLY is FK_ERR_ARG */
 
 /* Screening options (paper: Cauchy-Schwarz screening, eq. cauchy-schwarz, and
  * the density screen G_ab G_cd D_max < tau of the Brc21 scheme). */
@@ -172,7 +178,10 @@ int fk_info(const fk_ctx *ctx, fk_info_t *info);
 /* J and K for the density D (all nbf x nbf, row-major, symmetric D).
  * flags: FK_DEVICE_PTRS (D, J, K in device memory, used on `stream`);
  * otherwise host arrays, copied in and out synchronously.  FK_SYNC waits for
- * completion.  Asymmetric D gives J, K of its symmetric part only when
+ * completion.  FK_J_ONLY or FK_K_ONLY form one of the two matrices (the
+ * other pointer may be NULL and is not written); a quartet is then skipped
+ * when G_ab G_cd times the largest |D| over only the blocks that matrix
+ * multiplies falls below tau.  Asymmetric D gives J, K of its symmetric part only when
  * density screening is off; callers pass symmetric D. */
 int fk_build_jk(fk_ctx *ctx, const double *D, double *J, double *K, unsigned flags, void *stream);
 

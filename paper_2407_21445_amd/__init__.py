@@ -30,7 +30,7 @@ except ImportError:  # host-only use (tables, validation) without PyTorch
 _lib = ctypes.CDLL(LIB_PATH)
 
 FK_OK, FK_ERR_ARG, FK_ERR_UNSUPPORTED, FK_ERR_HIP, FK_ERR_OOM, FK_ERR_NOT_CONVERGED, FK_ERR_STATE = 0, -1, -2, -3, -4, -5, -6
-FK_DEVICE_PTRS, FK_SYNC, FK_TIME_CLASSES = 1, 2, 4
+FK_DEVICE_PTRS, FK_SYNC, FK_TIME_CLASSES, FK_J_ONLY, FK_K_ONLY = 1, 2, 4, 8, 16
 FK_MAX_QCLASS = 110
 MAX_L, MAX_K = 3, 9
 
@@ -231,30 +231,45 @@ class FockJK:
         return {k: getattr(i, k) for k, _ in Info._fields_}
 
     # ---- hot path ----
-    def build_jk(self, D, J=None, K=None, stream=None, sync=False, time_classes=False):
+    def build_jk(self, D, J=None, K=None, stream=None, sync=False, time_classes=False, only=None):
         """J, K for density D.  torch CUDA tensors (float64, contiguous) stay on
         the device and run on `stream` (default: torch's current stream);
-        numpy arrays go through host copies."""
+        numpy arrays go through host copies.  only="J" or "K" forms one
+        matrix (FK_J_ONLY / FK_K_ONLY); the other is returned as None."""
+        if only not in (None, "J", "K"):
+            raise ValueError("only must be None, 'J' or 'K'")
+        oflag = {None: 0, "J": FK_J_ONLY, "K": FK_K_ONLY}[only]
         nmat = self.info()["nmat"]
         if isinstance(D, np.ndarray):
             Dh = np.ascontiguousarray(D, dtype=np.float64)
             if Dh.size != nmat:
                 raise ValueError(f"D must hold {nmat} elements (nbf x nbf, or the concatenated blocks of a batch)")
-            Jh = np.zeros(Dh.shape)
-            Kh = np.zeros(Dh.shape)
-            self._check(_lib.fk_build_jk(self._ctx, _ptr(Dh), _ptr(Jh), _ptr(Kh), 0, None))
+            Jh = np.zeros(Dh.shape) if only != "K" else None
+            Kh = np.zeros(Dh.shape) if only != "J" else None
+            self._check(_lib.fk_build_jk(self._ctx, _ptr(Dh), _ptr(Jh) if Jh is not None else None,
+                                         _ptr(Kh) if Kh is not None else None, oflag, None))
             return Jh, Kh
         import torch
         if not (D.is_cuda and D.dtype == torch.float64 and D.is_contiguous() and D.numel() == nmat):
             raise ValueError(f"D must be a contiguous float64 CUDA tensor of {nmat} elements")
-        if J is None:
+        if J is None and only != "K":
             J = torch.empty_like(D)
-        if K is None:
+        if K is None and only != "J":
             K = torch.empty_like(D)
+        if only == "J":
+            K = None
+        if only == "K":
+            J = None
+        for M in (J, K):
+            if M is not None and not (M.is_cuda and M.dtype == torch.float64 and M.is_contiguous()
+                                      and M.numel() == nmat):
+                raise ValueError(f"J and K must be contiguous float64 CUDA tensors of {nmat} elements")
         st = stream if stream is not None else torch.cuda.current_stream(D.device)
-        flags = FK_DEVICE_PTRS | (FK_SYNC if sync else 0) | (FK_TIME_CLASSES if time_classes else 0)
-        self._check(_lib.fk_build_jk(self._ctx, ctypes.c_void_p(D.data_ptr()), ctypes.c_void_p(J.data_ptr()),
-                                     ctypes.c_void_p(K.data_ptr()), flags, ctypes.c_void_p(st.cuda_stream)))
+        flags = FK_DEVICE_PTRS | (FK_SYNC if sync else 0) | (FK_TIME_CLASSES if time_classes else 0) | oflag
+        self._check(_lib.fk_build_jk(self._ctx, ctypes.c_void_p(D.data_ptr()),
+                                     ctypes.c_void_p(J.data_ptr() if J is not None else None),
+                                     ctypes.c_void_p(K.data_ptr() if K is not None else None), flags,
+                                     ctypes.c_void_p(st.cuda_stream)))
         return J, K
 
     def build_progress(self):

@@ -68,7 +68,7 @@ struct PrimPair {
     double oo2z;   // 1 / (2 zeta)
     double P[3];   // Gaussian product centre
     double PA[3];  // P - A (A = centre of the pair's first shell)
-    double K;      // c_i c_j (pi/zeta)^(3/2) exp(-a_i a_j/zeta |AB|^2) * (2/sqrt(pi))^(1/2)
+    double K;      // c_i c_j (pi/zeta)^(3/2) exp(-a_i a_j/zeta |AB|^2) (2/sqrt(pi))^(1/2) sqrt(zeta)
 };
 
 // 2-D recurrences of one axis for one root followed by both horizontal
@@ -134,44 +134,35 @@ struct QuartetSetup {
     double PQ[3];
 };
 
-// 1/x and sqrt(x) for x > 0: on the device the hardware approximations refined
-// by two Newton steps each (cheaper than the IEEE sequences, same accuracy
-// class); on the host the library functions.
-FK_HD double fk_rcp(double x)
-{
-#if defined(__HIP_DEVICE_COMPILE__)
-    double r = __builtin_amdgcn_rcp(x);
-    r = fma(fma(-x, r, 1.0), r, r);
-    r = fma(fma(-x, r, 1.0), r, r);
-    return r;
-#else
-    return 1.0 / x;
-#endif
-}
-
-FK_HD double fk_sqrt(double x)
+// 1/sqrt(x) for x > 0: on the device the hardware estimate refined by two
+// Newton steps y <- y + y (1 - x y^2)/2 (each doubles the correct bits); on the
+// host the library functions.
+FK_HD double fk_rsqrt(double x)
 {
 #if defined(__HIP_DEVICE_COMPILE__)
     double y = __builtin_amdgcn_rsq(x);
     y = fma(0.5 * y, fma(-x * y, y, 1.0), y);
     y = fma(0.5 * y, fma(-x * y, y, 1.0), y);
-    return x * y;
+    return y;
 #else
-    return sqrt(x);
+    return 1.0 / sqrt(x);
 #endif
 }
 
+// One reciprocal square root serves the quartet: with r = (zeta + eta)^(-1/2),
+// 1/(zeta + eta) = r^2 and, since each pair's K carries sqrt(zeta),
+// K_P K_Q r = K_P K_Q sqrt(zeta eta / (zeta + eta)) (the sqrt(rho) of the
+// fundamental integral).
 FK_HD QuartetSetup quartet_setup(const PrimPair &p, const PrimPair &q)
 {
     QuartetSetup s;
-    double zpe = p.zeta + q.zeta;
-    s.inv = fk_rcp(zpe);
-    double rho = p.zeta * q.zeta * s.inv;
+    const double r = fk_rsqrt(p.zeta + q.zeta);
+    s.inv = r * r;
     s.PQ[0] = p.P[0] - q.P[0];
     s.PQ[1] = p.P[1] - q.P[1];
     s.PQ[2] = p.P[2] - q.P[2];
-    s.T = rho * (s.PQ[0] * s.PQ[0] + s.PQ[1] * s.PQ[1] + s.PQ[2] * s.PQ[2]);
-    s.pref = p.K * q.K * fk_sqrt(rho);
+    s.T = (p.zeta * q.zeta * s.inv) * (s.PQ[0] * s.PQ[0] + s.PQ[1] * s.PQ[1] + s.PQ[2] * s.PQ[2]);
+    s.pref = p.K * q.K * r;
     s.ez = q.zeta * s.inv;
     s.zz = p.zeta * s.inv;
     return s;
@@ -182,14 +173,14 @@ FK_HD QuartetSetup quartet_setup(const PrimPair &p, const PrimPair &q)
 // The set-up (T, prefactor) and the roots and weights are FP64; the 2-D
 // recurrences, transfers and products run in R (double, or float for the
 // quartets the precision split assigns to FP32).
-template <int LA, int LB, int LC, int LD, typename R = double>
+template <int LA, int LB, int LC, int LD, typename R = double, bool BRANCHLESS = false>
 FK_HD void rys_prim_all(const double *__restrict tab, const PrimPair &p, const PrimPair &q,
                         const double AB[3], const double CD[3], R *__restrict acc)
 {
     using Q = QClass<LA, LB, LC, LD>;
     QuartetSetup s = quartet_setup(p, q);
     double u[Q::NR], w[Q::NR];
-    rys_roots<Q::NR, (Q::L > 0)>(s.T, tab, u, w);
+    rys_roots<Q::NR, (Q::L > 0), BRANCHLESS>(s.T, tab, u, w);
     if constexpr (Q::L == 0) {
         acc[0] += (R)(w[0] * s.pref);
         return;
@@ -457,7 +448,7 @@ constexpr double flops_prim(int LA, int LB, int LC, int LD)
     const int L = LA + LB + LC + LD, NR = L / 2 + 1, LAB = LA + LB, LCD = LC + LD;
     const int NOUT = ncart(LA) * ncart(LB) * ncart(LC) * ncart(LD);
     double f = 0;
-    f += 1 + 1 + 2 + 3 + 6 + 2 + 2 + 2;            // zpe, inv, rho, PQ, T, pref (sqrt), ez, zz
+    f += 1 + 1 + 1 + 3 + 5 + 3 + 2 + 2;            // zpe, rsqrt, inv, PQ, |PQ|^2, T, pref, ez and zz
     const int nfun = (L > 0) ? 2 * NR : NR;
     f += nfun * RYS_DEG * 2.0 + 4;                 // Horner + interval arithmetic
     if (L == 0) return f + 2;

@@ -242,7 +242,7 @@ void make_pair(fk_ctx *c, int sa, int sb)
                 rec[2 + k] = (ai * A[k] + aj * B[k]) / z;
                 rec[5 + k] = rec[2 + k] - A[k];
             }
-            rec[8] = c->coef[i] * c->coef[j] * std::pow(M_PI / z, 1.5) * std::exp(-ai * aj / z * ab2) * kfac;
+            rec[8] = c->coef[i] * c->coef[j] * std::pow(M_PI / z, 1.5) * std::exp(-ai * aj / z * ab2) * kfac * std::sqrt(z);
             rec[9] = 0.0;
             c->pp.insert(c->pp.end(), rec, rec + FK_NPP_REC);
             ++np;
@@ -1008,7 +1008,13 @@ int fk_build_jk(fk_ctx *c, const double *D, double *J, double *K, unsigned flags
     if (!c) return FK_ERR_ARG;
     if (c->device < 0) return fail(c, FK_ERR_STATE, "fk_build_jk: context has no device");
     if (!c->have_quartets) return fail(c, FK_ERR_STATE, "fk_build_jk: call fk_build_quartets first");
-    if (!D || !J || !K) return fail(c, FK_ERR_ARG, "fk_build_jk: null matrix pointer");
+    if ((flags & FK_J_ONLY) && (flags & FK_K_ONLY))
+        return fail(c, FK_ERR_ARG, "fk_build_jk: FK_J_ONLY and FK_K_ONLY together");
+    const int want = (flags & FK_J_ONLY) ? FK_WANT_J : ((flags & FK_K_ONLY) ? FK_WANT_K : FK_WANT_J | FK_WANT_K);
+    if (!D || (!J && (want & FK_WANT_J)) || (!K && (want & FK_WANT_K)))
+        return fail(c, FK_ERR_ARG, "fk_build_jk: null matrix pointer");
+    if (!(want & FK_WANT_J)) J = nullptr;
+    if (!(want & FK_WANT_K)) K = nullptr;
     hipSetDevice(c->device);
     hipStream_t st = (hipStream_t)stream;
     // one nbf_m^2 block per molecule, concatenated
@@ -1027,8 +1033,8 @@ int fk_build_jk(fk_ctx *c, const double *D, double *J, double *K, unsigned flags
         if ((rc = dev_upload<double>(c, c->d_Kout, nullptr, nn))) return rc;
         HIPCHK(c, hipMemcpyAsync(c->d_Din.p, D, nn * sizeof(double), hipMemcpyHostToDevice, st));
         Dd = c->d_Din.p;
-        Jd = c->d_Jout.p;
-        Kd = c->d_Kout.p;
+        Jd = J ? c->d_Jout.p : nullptr;
+        Kd = K ? c->d_Kout.p : nullptr;
     }
     if (fk_kernels_launch_prep(Dd, c->d_bf_scale.p, &ma, c->d_Ds.p, c->d_Dsh.p, st))
         return fail(c, FK_ERR_HIP, "prep kernel launch failed");
@@ -1075,6 +1081,7 @@ int fk_build_jk(fk_ctx *c, const double *D, double *J, double *K, unsigned flags
         a.XK = c->d_X.p + nn;
         a.xcopy = (long long)(2 * nn);
         a.dscreen = c->opts.density_screen && c->opts.tau > 0;
+        a.want = want;
         a.tau = c->opts.tau * c->dscreen_scale;
         a.rys_tab = c->d_rys.p + rys_staged_offset(qc.info.nroot);
         a.counters = c->d_cnt.p + 2 * i;
@@ -1097,8 +1104,8 @@ int fk_build_jk(fk_ctx *c, const double *D, double *J, double *K, unsigned flags
         return fail(c, FK_ERR_HIP, "finalize kernel launch failed");
     c->stats_pending = true;
     if (!devp) {
-        HIPCHK(c, hipMemcpyAsync(J, Jd, nn * sizeof(double), hipMemcpyDeviceToHost, st));
-        HIPCHK(c, hipMemcpyAsync(K, Kd, nn * sizeof(double), hipMemcpyDeviceToHost, st));
+        if (J) HIPCHK(c, hipMemcpyAsync(J, Jd, nn * sizeof(double), hipMemcpyDeviceToHost, st));
+        if (K) HIPCHK(c, hipMemcpyAsync(K, Kd, nn * sizeof(double), hipMemcpyDeviceToHost, st));
         HIPCHK(c, hipStreamSynchronize(st));
     } else if (flags & FK_SYNC) {
         HIPCHK(c, hipStreamSynchronize(st));

@@ -23,6 +23,10 @@ struct FkTile {
 };
 #define FK_TILE_SAME (1 << 30)
 
+// Matrices a build forms (FkJKArgs::want).
+#define FK_WANT_J 1
+#define FK_WANT_K 2
+
 // Bra block: blk_bra[first .. first + count) are shell-pair indices with the
 // same first shell; blk_pos holds their positions in the sorted pair lists.
 struct FkBraBlock {
@@ -81,6 +85,7 @@ struct FkJKArgs {
     double *XK;              // per molecule [nbf_m * nbf_m] unsymmetrised exchange accumulator
     long long xcopy;         // distance between the FK_XCD_COPIES copies of (XJ, XK)
     int dscreen;             // apply the density screen
+    int want;                // FK_WANT_J | FK_WANT_K: the matrices this build forms
     double tau;
     const double *rys_tab;   // staged Rys segment (table + Gauss-Hermite) of this class's root count
     unsigned long long *counters;  // [2]: contracted quartets, primitive quartets

@@ -37,6 +37,9 @@
 // lane-per-quartet classes up to this many integrals sum K[a,c], K[a,d] and
 // J[c,d] over a block of bras in registers; larger ones take one bra per tile
 #define FK_LPQ_BLOCK_NOUT 54
+// lane-per-quartet classes up to this many integrals evaluate two primitive
+// quartets per step of the bra-primitive loop
+#define FK_LPQ_PAIR_NOUT 9
 #define FK_BLOCK 256
 #define FK_WAVES (FK_BLOCK / 64)
 
@@ -95,12 +98,20 @@ __device__ __forceinline__ void load_table(double *s_tab, const double *__restri
     __syncthreads();
 }
 
-__device__ __forceinline__ double dmax6(const double *__restrict Dsh, int ns, int sa, int sb, int sc, int sd)
+// Density factor of the quartet screen: the largest |D| over the shell blocks
+// the quartet's contributions are multiplied by -- ab and cd for J, ac, ad, bc,
+// bd for K, all six when both are built (want: bit 0 J, bit 1 K).
+__device__ __forceinline__ double dmax_want(const double *__restrict Dsh, int ns, int sa, int sb, int sc, int sd,
+                                            int want)
 {
-    double m1 = fmax(Dsh[sa * ns + sb], Dsh[sc * ns + sd]);
-    double m2 = fmax(Dsh[sa * ns + sc], Dsh[sa * ns + sd]);
-    double m3 = fmax(Dsh[sb * ns + sc], Dsh[sb * ns + sd]);
-    return fmax(m1, fmax(m2, m3));
+    double m = 0.0;
+    if (want & FK_WANT_J) m = fmax(Dsh[sa * ns + sb], Dsh[sc * ns + sd]);
+    if (want & FK_WANT_K) {
+        const double m2 = fmax(Dsh[sa * ns + sc], Dsh[sa * ns + sd]);
+        const double m3 = fmax(Dsh[sb * ns + sc], Dsh[sb * ns + sd]);
+        m = fmax(m, fmax(m2, m3));
+    }
+    return m;
 }
 
 // Ket pair data at a list position (consecutive lanes: consecutive positions).
@@ -152,9 +163,6 @@ __device__ __forceinline__ BraInfo load_bra(const FkJKArgs &a, int bra)
     return b;
 }
 
-// The bra's primitive records are staged in a per-wave LDS slot once per tile
-// (wave-uniform data read inside the innermost loop).
-
 __device__ __forceinline__ void wave_sync_lds()
 {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -162,19 +170,14 @@ __device__ __forceinline__ void wave_sync_lds()
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-__device__ __forceinline__ void stage_bra(double *s, const double *__restrict pp, int ppo, int npp, int lane)
+// The bra's primitive records are the same for every lane of the wave: they
+// are read through the constant address space, which the compiler serves with
+// scalar loads into SGPRs (no LDS traffic and no VGPRs for them; the records
+// are not written while the kernels run).  `idx` must be wave-uniform.
+typedef const __attribute__((address_space(4))) double *fk_const_ptr;
+__device__ __forceinline__ fk::PrimPair sload_pp(const double *__restrict pp, int idx)
 {
-    wave_sync_lds();
-    for (int x = lane; x < npp * FK_NFLD; x += 64) {
-        const int i = x / FK_NFLD, f = x - i * FK_NFLD;
-        s[x] = pp[(size_t)(ppo + i) * FK_NPP_REC + f];
-    }
-    wave_sync_lds();
-}
-
-__device__ __forceinline__ fk::PrimPair lds_pp(const double *s, int i)
-{
-    const double *r = s + i * FK_NFLD;
+    const fk_const_ptr r = (fk_const_ptr)(pp + (size_t)idx * FK_NPP_REC);
     fk::PrimPair p;
     p.zeta = r[0];
     p.oo2z = r[1];
@@ -237,16 +240,14 @@ __global__ void __launch_bounds__(FK_BLOCK, (LpqMinBlocks<LA, LB, LC, LD>::value
 {
     using Q = fk::QClass<LA, LB, LC, LD>;
     constexpr int NA = Q::NA, NB = Q::NB, NC = Q::NC, ND = Q::ND, NOUT = Q::NOUT;
-    // block sums in registers (small classes); otherwise tiles hold one bra
-    // and those blocks go to memory per bra
-    constexpr bool BLK = NOUT <= FK_LPQ_BLOCK_NOUT;
+    static_assert(NOUT <= FK_LPQ_BLOCK_NOUT, "lane-per-quartet classes sum their bra blocks in registers");
+    const bool wj = (a.want & FK_WANT_J) != 0, wk = (a.want & FK_WANT_K) != 0;
     FK_DYN_LDS(s_dyn);
     double *s_tab = s_dyn;
     load_table<Q::NR>(s_tab, a.rys_tab);
 
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    double *s_bra = s_dyn + rys_lds_size(Q::NR) + wave * a.bra_slot;
     const int nwt = gridDim.x * FK_WAVES;
     unsigned long long cq = 0, cp = 0;
 
@@ -273,13 +274,11 @@ __global__ void __launch_bounds__(FK_BLOCK, (LpqMinBlocks<LA, LB, LC, LD>::value
         const int sa = a.pair_sa[a.blk_bra[blk.first]];
         const int oa = shbf[sa];
         // D_cd is used with every bra of the block
-        double dcd[BLK ? NC * ND : 1];
-        if constexpr (BLK) {
+        double dcd[NC * ND];
 #pragma unroll
-            for (int ic = 0; ic < NC; ++ic)
+        for (int ic = 0; ic < NC; ++ic)
 #pragma unroll
-                for (int id = 0; id < ND; ++id) dcd[ic * ND + id] = Ds[(size_t)(oc + ic) * n + od + id];
-        }
+            for (int id = 0; id < ND; ++id) dcd[ic * ND + id] = wj ? Ds[(size_t)(oc + ic) * n + od + id] : 0.0;
         // block sums: X_K[a, c], X_K[a, d], X_J[c, d]
         double kac[NA * NC], kad[NA * ND], jcd[NC * ND];
 #pragma unroll
@@ -299,14 +298,15 @@ __global__ void __launch_bounds__(FK_BLOCK, (LpqMinBlocks<LA, LB, LC, LD>::value
             // and density screen for this (bra, ket)
             bool active = inrange && (!same || pos <= bpos) && (a.tau <= 0 || B.G * Kt.G >= a.tau) &&
                           prec_side<R>(B.G * Kt.G, a.tau_hi);
-            if (a.dscreen) active = active && (B.G * Kt.G * dmax6(Dsh, ns, sa, sb, sc, sd) >= a.tau);
+            if (a.dscreen) active = active && (B.G * Kt.G * dmax_want(Dsh, ns, sa, sb, sc, sd, a.want) >= a.tau);
             const unsigned long long mask = __ballot(active);
             if (mask == 0ull) continue;
             const int nact = __popcll(mask);
             cq += nact;
             cp += (unsigned long long)nact * B.npp * g.npp;
 
-            stage_bra(s_bra, a.pp, B.ppo, B.npp, lane);
+            const int ppo = __builtin_amdgcn_readfirstlane(B.ppo);
+            const int bnpp = __builtin_amdgcn_readfirstlane(B.npp);
             R acc[NOUT];
 #pragma unroll
             for (int o = 0; o < NOUT; ++o) acc[o] = (R)0;
@@ -315,9 +315,19 @@ __global__ void __launch_bounds__(FK_BLOCK, (LpqMinBlocks<LA, LB, LC, LD>::value
                 for (int j = 0; j < g.npp; ++j) {
                     const fk::PrimPair q = qn;
                     if (j + 1 < g.npp) qn = load_ket_pp(a.ppT, g, j + 1, r);
-#pragma unroll 2
-                    for (int i = 0; i < B.npp; ++i)
-                        fk::rys_prim_all<LA, LB, LC, LD, R>(s_tab, lds_pp(s_bra, i), q, B.AB, Kt.CD, acc);
+                    // two bra primitives per step for the small classes: their
+                    // quartets are independent straight-line code the compiler
+                    // interleaves (larger classes would spill)
+                    constexpr bool PAIR = NOUT <= FK_LPQ_PAIR_NOUT;
+                    int i = 0;
+                    if constexpr (PAIR)
+                        for (; i + 1 < bnpp; i += 2) {
+                            const fk::PrimPair p0 = sload_pp(a.pp, ppo + i), p1 = sload_pp(a.pp, ppo + i + 1);
+                            fk::rys_prim_all<LA, LB, LC, LD, R, true>(s_tab, p0, q, B.AB, Kt.CD, acc);
+                            fk::rys_prim_all<LA, LB, LC, LD, R, true>(s_tab, p1, q, B.AB, Kt.CD, acc);
+                        }
+                    for (; i < bnpp; ++i)
+                        fk::rys_prim_all<LA, LB, LC, LD, R, PAIR>(s_tab, sload_pp(a.pp, ppo + i), q, B.AB, Kt.CD, acc);
                 }
             }
             const bool diag = same && pos == bpos;
@@ -326,28 +336,35 @@ __global__ void __launch_bounds__(FK_BLOCK, (LpqMinBlocks<LA, LB, LC, LD>::value
             double jab[NA * NB];
 #pragma unroll
             for (int o = 0; o < NA * NB; ++o) jab[o] = 0.0;
-            if (active && BLK) {
+            if (active) {
                 any = true;
 #pragma unroll
                 for (int o = 0; o < NOUT; ++o) acc[o] *= (R)fac;
-                double dab[NA * NB], dbc[NB * NC], dbd[NB * ND];
+            }
+            if (active && wj) {
+                double dab[NA * NB];
 #pragma unroll
-                for (int ib = 0; ib < NB; ++ib) {
+                for (int ia = 0; ia < NA; ++ia)
 #pragma unroll
-                    for (int ia = 0; ia < NA; ++ia) dab[ia * NB + ib] = Ds[(size_t)(oa + ia) * n + ob + ib];
-#pragma unroll
-                    for (int ic = 0; ic < NC; ++ic) dbc[ib * NC + ic] = Ds[(size_t)(ob + ib) * n + oc + ic];
-#pragma unroll
-                    for (int id = 0; id < ND; ++id) dbd[ib * ND + id] = Ds[(size_t)(ob + ib) * n + od + id];
-                }
+                    for (int ib = 0; ib < NB; ++ib) dab[ia * NB + ib] = Ds[(size_t)(oa + ia) * n + ob + ib];
                 // X_J[a, b] partial (reduced over the wave below); X_J[c, d] block sum
 #pragma unroll
                 for (int ab = 0; ab < NA * NB; ++ab)
 #pragma unroll
                     for (int cd = 0; cd < NC * ND; ++cd) {
-                        jab[ab] += acc[ab * NC * ND + cd] * dcd[BLK ? cd : 0];
+                        jab[ab] += acc[ab * NC * ND + cd] * dcd[cd];
                         jcd[cd] += acc[ab * NC * ND + cd] * dab[ab];
                     }
+            }
+            if (active && wk) {
+                double dbc[NB * NC], dbd[NB * ND];
+#pragma unroll
+                for (int ib = 0; ib < NB; ++ib) {
+#pragma unroll
+                    for (int ic = 0; ic < NC; ++ic) dbc[ib * NC + ic] = Ds[(size_t)(ob + ib) * n + oc + ic];
+#pragma unroll
+                    for (int id = 0; id < ND; ++id) dbd[ib * ND + id] = Ds[(size_t)(ob + ib) * n + od + id];
+                }
                 // X_K[a, c] += v D_bd and X_K[a, d] += v D_bc (block sums)
 #pragma unroll
                 for (int ia = 0; ia < NA; ++ia)
@@ -386,79 +403,16 @@ __global__ void __launch_bounds__(FK_BLOCK, (LpqMinBlocks<LA, LB, LC, LD>::value
                     }
                 }
             }
-            if (active && !BLK) {
-                // one bra per tile: the six blocks straight to memory, density
-                // elements loaded where they are used (register pressure)
-#pragma unroll
-                for (int o = 0; o < NOUT; ++o) acc[o] *= (R)fac;
-#pragma unroll
-                for (int ab = 0; ab < NA * NB; ++ab)
-#pragma unroll
-                    for (int cd = 0; cd < NC * ND; ++cd)
-                        jab[ab] += acc[ab * NC * ND + cd] * Ds[(size_t)(oc + cd / ND) * n + od + cd % ND];
-#pragma unroll
-                for (int cd = 0; cd < NC * ND; ++cd) {
-                    double s = 0.0;
-#pragma unroll
-                    for (int ab = 0; ab < NA * NB; ++ab)
-                        s += acc[ab * NC * ND + cd] * Ds[(size_t)(oa + ab / NB) * n + ob + ab % NB];
-                    atomic_add(&XJ[(size_t)(oc + cd / ND) * n + od + cd % ND], 2.0 * s);
-                }
-#pragma unroll
-                for (int ia = 0; ia < NA; ++ia) {
-#pragma unroll
-                    for (int ic = 0; ic < NC; ++ic) {
-                        double s = 0.0;
-#pragma unroll
-                        for (int ib = 0; ib < NB; ++ib)
-#pragma unroll
-                            for (int id = 0; id < ND; ++id)
-                                s += acc[((ia * NB + ib) * NC + ic) * ND + id] * Ds[(size_t)(ob + ib) * n + od + id];
-                        atomic_add(&XK[(size_t)(oa + ia) * n + oc + ic], s);
-                    }
-#pragma unroll
-                    for (int id = 0; id < ND; ++id) {
-                        double s = 0.0;
-#pragma unroll
-                        for (int ib = 0; ib < NB; ++ib)
-#pragma unroll
-                            for (int ic = 0; ic < NC; ++ic)
-                                s += acc[((ia * NB + ib) * NC + ic) * ND + id] * Ds[(size_t)(ob + ib) * n + oc + ic];
-                        atomic_add(&XK[(size_t)(oa + ia) * n + od + id], s);
-                    }
-                }
-#pragma unroll
-                for (int ib = 0; ib < NB; ++ib) {
-#pragma unroll
-                    for (int ic = 0; ic < NC; ++ic) {
-                        double s = 0.0;
-#pragma unroll
-                        for (int ia = 0; ia < NA; ++ia)
-#pragma unroll
-                            for (int id = 0; id < ND; ++id)
-                                s += acc[((ia * NB + ib) * NC + ic) * ND + id] * Ds[(size_t)(oa + ia) * n + od + id];
-                        atomic_add(&XK[(size_t)(ob + ib) * n + oc + ic], s);
-                    }
-#pragma unroll
-                    for (int id = 0; id < ND; ++id) {
-                        double s = 0.0;
-#pragma unroll
-                        for (int ia = 0; ia < NA; ++ia)
-#pragma unroll
-                            for (int ic = 0; ic < NC; ++ic)
-                                s += acc[((ia * NB + ib) * NC + ic) * ND + id] * Ds[(size_t)(oa + ia) * n + oc + ic];
-                        atomic_add(&XK[(size_t)(ob + ib) * n + od + id], s);
-                    }
-                }
-            }
             // all lanes (active or not) take part in the wave reduction of X_J[a, b]
+            if (wj) {
 #pragma unroll
-            for (int ab = 0; ab < NA * NB; ++ab) {
-                const double s = wave_sum(jab[ab]);
-                if (lane == 0) atomic_add(&XJ[(size_t)(oa + ab / NB) * n + ob + ab % NB], 2.0 * s);
+                for (int ab = 0; ab < NA * NB; ++ab) {
+                    const double s = wave_sum(jab[ab]);
+                    if (lane == 0) atomic_add(&XJ[(size_t)(oa + ab / NB) * n + ob + ab % NB], 2.0 * s);
+                }
             }
         }
-        if (BLK && any) {
+        if (any && wk) {
 #pragma unroll
             for (int ia = 0; ia < NA; ++ia) {
 #pragma unroll
@@ -466,6 +420,8 @@ __global__ void __launch_bounds__(FK_BLOCK, (LpqMinBlocks<LA, LB, LC, LD>::value
 #pragma unroll
                 for (int id = 0; id < ND; ++id) atomic_add(&XK[(size_t)(oa + ia) * n + od + id], kad[ia * ND + id]);
             }
+        }
+        if (any && wj) {
 #pragma unroll
             for (int ic = 0; ic < NC; ++ic)
 #pragma unroll
@@ -547,14 +503,14 @@ __global__ void __launch_bounds__(FK_BLOCK, (TpqMinBlocks<LA, LB, LC, LD>::value
     constexpr int NBL = (MODE == 1) ? NB : 1;
     constexpr int NOL = NBL * NC * ND;
     static_assert(QPW >= 1, "team larger than a wave");
+    const bool wj = (a.want & FK_WANT_J) != 0, wk = (a.want & FK_WANT_K) != 0;
     FK_DYN_LDS(s_dyn);
     double *s_tab = s_dyn;
     load_table<Q::NR>(s_tab, a.rys_tab);
 
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    double *s_bra = s_dyn + rys_lds_size(Q::NR) + wave * (a.bra_slot + TSh::RED);
-    double *s_team = s_bra + a.bra_slot;     // [QPW][NV] team sums
+    double *s_team = s_dyn + rys_lds_size(Q::NR) + wave * TSh::RED;  // [QPW][NV] team sums
     double *s_jab = s_team + QPW * NV;       // [block bra][NA * NB] wave sums of X_J[a, b]
     const int nwt = gridDim.x * FK_WAVES;
     const int slot = lane / TS, comp = lane % TS;
@@ -610,13 +566,14 @@ __global__ void __launch_bounds__(FK_BLOCK, (TpqMinBlocks<LA, LB, LC, LD>::value
                 const int sb = B.sb;
                 bool active = tin && (!same || pos <= bpos) && (a.tau <= 0 || B.G * Kt.G >= a.tau) &&
                               prec_side<R>(B.G * Kt.G, a.tau_hi);
-                if (a.dscreen) active = active && (B.G * Kt.G * dmax6(Dsh, ns, sa, sb, sc, sd) >= a.tau);
+                if (a.dscreen) active = active && (B.G * Kt.G * dmax_want(Dsh, ns, sa, sb, sc, sd, a.want) >= a.tau);
                 const unsigned long long mask = __ballot(active);
                 if (mask == 0ull) continue;
                 const int nact = __popcll(mask) / TS;
                 cq += nact;
                 cp += (unsigned long long)nact * B.npp * g.npp;
-                stage_bra(s_bra, a.pp, B.ppo, B.npp, lane);
+                const int ppo = __builtin_amdgcn_readfirstlane(B.ppo);
+                const int bnpp = __builtin_amdgcn_readfirstlane(B.npp);
                 R acc[NOL];
 #pragma unroll
                 for (int o = 0; o < NOL; ++o) acc[o] = (R)0;
@@ -625,8 +582,9 @@ __global__ void __launch_bounds__(FK_BLOCK, (TpqMinBlocks<LA, LB, LC, LD>::value
                     for (int j = 0; j < g.npp; ++j) {
                         const fk::PrimPair q = qn;
                         if (j + 1 < g.npp) qn = load_ket_pp(a.ppT, g, j + 1, r);
-                        for (int i = 0; i < B.npp; ++i)
-                            fk::rys_prim_team<LA, LB, LC, LD, MODE, R>(s_tab, lds_pp(s_bra, i), q, B.AB, Kt.CD, ax, bx, acc);
+                        for (int i = 0; i < bnpp; ++i)
+                            fk::rys_prim_team<LA, LB, LC, LD, MODE, R>(s_tab, sload_pp(a.pp, ppo + i), q, B.AB, Kt.CD,
+                                                                      ax, bx, acc);
                     }
                 }
                 const bool diag = same && pos == bpos;
@@ -642,34 +600,45 @@ __global__ void __launch_bounds__(FK_BLOCK, (TpqMinBlocks<LA, LB, LC, LD>::value
                     for (int jj = 0; jj < NBL; ++jj) {
                         const int ib = (MODE == 1) ? jj : ib0;
                         const size_t rb = (size_t)(ob + ib) * n;
-                        const double dab = Ds[ra + ob + ib];
-                        double sj = 0.0;
+                        if (wj) {
+                            const double dab = Ds[ra + ob + ib];
+                            double sj = 0.0;
 #pragma unroll
-                        for (int ic = 0; ic < NC; ++ic) {
-                            double kbc = 0.0;
+                            for (int ic = 0; ic < NC; ++ic)
+#pragma unroll
+                                for (int id = 0; id < ND; ++id) {
+                                    const double v = fac * acc[(jj * NC + ic) * ND + id];
+                                    sj += v * Ds[(size_t)(oc + ic) * n + od + id];
+                                    jcd[ic * ND + id] += v * dab;
+                                }
+                            lds_add(&s_jab[jb * NA * NB + ia * NB + ib], sj);
+                        }
+                        if (wk) {
+#pragma unroll
+                            for (int ic = 0; ic < NC; ++ic) {
+                                double kbc = 0.0;
+#pragma unroll
+                                for (int id = 0; id < ND; ++id) {
+                                    const double v = fac * acc[(jj * NC + ic) * ND + id];
+                                    kac[ic] += v * Ds[rb + od + id];
+                                    kad[id] += v * Ds[rb + oc + ic];
+                                    kbc += v * Ds[ra + od + id];
+                                }
+                                lds_add(&tsum[ib * NC + ic], kbc);
+                            }
 #pragma unroll
                             for (int id = 0; id < ND; ++id) {
-                                const double v = fac * acc[(jj * NC + ic) * ND + id];
-                                sj += v * Ds[(size_t)(oc + ic) * n + od + id];
-                                jcd[ic * ND + id] += v * dab;
-                                kac[ic] += v * Ds[rb + od + id];
-                                kad[id] += v * Ds[rb + oc + ic];
-                                kbc += v * Ds[ra + od + id];
+                                double kbd = 0.0;
+#pragma unroll
+                                for (int ic = 0; ic < NC; ++ic)
+                                    kbd += fac * acc[(jj * NC + ic) * ND + id] * Ds[ra + oc + ic];
+                                lds_add(&tsum[NB * NC + ib * ND + id], kbd);
                             }
-                            lds_add(&tsum[ib * NC + ic], kbc);
                         }
-#pragma unroll
-                        for (int id = 0; id < ND; ++id) {
-                            double kbd = 0.0;
-#pragma unroll
-                            for (int ic = 0; ic < NC; ++ic) kbd += fac * acc[(jj * NC + ic) * ND + id] * Ds[ra + oc + ic];
-                            lds_add(&tsum[NB * NC + ib * ND + id], kbd);
-                        }
-                        lds_add(&s_jab[jb * NA * NB + ia * NB + ib], sj);
                     }
                 }
                 wave_sync_lds();
-                if (active)
+                if (active && wk)
                     for (int v = comp; v < TSh::NVB; v += TS) {
                         size_t dst;
                         if (v < NB * NC) dst = (size_t)(ob + v / NC) * n + oc + v % NC;
@@ -683,16 +652,18 @@ __global__ void __launch_bounds__(FK_BLOCK, (TpqMinBlocks<LA, LB, LC, LD>::value
             if (lane_ok)
                 for (int v = comp; v < NV; v += TS) tsum[v] = 0.0;
             wave_sync_lds();
-            if (any) {
+            if (any && wk) {
 #pragma unroll
                 for (int ic = 0; ic < NC; ++ic) atomic_add(&XK[ra + oc + ic], kac[ic]);
 #pragma unroll
                 for (int id = 0; id < ND; ++id) atomic_add(&XK[ra + od + id], kad[id]);
+            }
+            if (any && wj) {
 #pragma unroll
                 for (int o = 0; o < NC * ND; ++o) lds_add(&tsum[o], jcd[o]);
             }
             wave_sync_lds();
-            if (any)
+            if (any && wj)
                 for (int v = comp; v < NC * ND; v += TS)
                     atomic_add(&XJ[(size_t)(oc + v / ND) * n + od + v % ND], 2.0 * tsum[v]);
             wave_sync_lds();
@@ -722,13 +693,13 @@ __global__ void __launch_bounds__(FK_BLOCK) k_jk_wpq(FkJKArgs a)
     constexpr int NB = Q::NB, NC = Q::NC, ND = Q::ND;
     constexpr int NAB = Q::NA * Q::NB, NCD = NC * ND;
     constexpr int ITEMS = (NAB + 63) / 64;
+    const bool wj = (a.want & FK_WANT_J) != 0, wk = (a.want & FK_WANT_K) != 0;
     FK_DYN_LDS(s_dyn);
     double *s_tab = s_dyn;
     load_table<Q::NR>(s_tab, a.rys_tab);
 
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    double *s_bra = s_dyn + rys_lds_size(Q::NR) + wave * a.bra_slot;
     const int nwt = gridDim.x * FK_WAVES;
     unsigned long long cq = 0, cp = 0;
 
@@ -768,11 +739,12 @@ __global__ void __launch_bounds__(FK_BLOCK) k_jk_wpq(FkJKArgs a)
             const bool in = lane < tile.ket_count;
             const KetInfo K0 = load_ket(a, tile.ket_begin + (in ? lane : 0));
             bool ok = in;
-            if (a.dscreen) ok = ok && (B.G * K0.G * dmax6(Dsh, ns, sa, sb, K0.sc, K0.sd) >= a.tau);
+            if (a.dscreen) ok = ok && (B.G * K0.G * dmax_want(Dsh, ns, sa, sb, K0.sc, K0.sd, a.want) >= a.tau);
             live = __ballot(ok);
         }
         if (live == 0ull) continue;
-        stage_bra(s_bra, a.pp, B.ppo, B.npp, lane);
+        const int ppo = __builtin_amdgcn_readfirstlane(B.ppo);
+        const int bnpp = __builtin_amdgcn_readfirstlane(B.npp);
         while (live) {
             const int k = __ffsll((long long)live) - 1;
             live &= live - 1;
@@ -789,8 +761,8 @@ __global__ void __launch_bounds__(FK_BLOCK) k_jk_wpq(FkJKArgs a)
                 for (int o = 0; o < NCD; ++o) acc[it][o] = 0.0;
             for (int j = 0; j < g.npp; ++j) {
                 const fk::PrimPair q = load_ket_pp(a.ppT, g, j, r);
-                for (int i = 0; i < B.npp; ++i) {
-                    const fk::PrimPair p = lds_pp(s_bra, i);
+                for (int i = 0; i < bnpp; ++i) {
+                    const fk::PrimPair p = sload_pp(a.pp, ppo + i);
 #pragma unroll
                     for (int it = 0; it < ITEMS; ++it)
                         if (ival[it]) fk::rys_prim_bra_comp<LA, LB, LC, LD>(s_tab, p, q, B.AB, Kt.CD, iax[it], ibx[it], acc[it]);
@@ -809,16 +781,19 @@ __global__ void __launch_bounds__(FK_BLOCK) k_jk_wpq(FkJKArgs a)
                 double *v = acc[it];
 #pragma unroll
                 for (int o = 0; o < NCD; ++o) v[o] *= fac;
-                const double dab = Ds[(size_t)(oa + ia) * n + ob + ib];
-                double sj = 0.0;
+                if (wj) {
+                    const double dab = Ds[(size_t)(oa + ia) * n + ob + ib];
+                    double sj = 0.0;
 #pragma unroll
-                for (int ic = 0; ic < NC; ++ic)
+                    for (int ic = 0; ic < NC; ++ic)
 #pragma unroll
-                    for (int id = 0; id < ND; ++id) {
-                        sj += v[ic * ND + id] * Ds[(size_t)(oc + ic) * n + od + id];
-                        jcd[ic * ND + id] += v[ic * ND + id] * dab;
-                    }
-                atomic_add(&XJ[(size_t)(oa + ia) * n + ob + ib], 2.0 * sj);
+                        for (int id = 0; id < ND; ++id) {
+                            sj += v[ic * ND + id] * Ds[(size_t)(oc + ic) * n + od + id];
+                            jcd[ic * ND + id] += v[ic * ND + id] * dab;
+                        }
+                    atomic_add(&XJ[(size_t)(oa + ia) * n + ob + ib], 2.0 * sj);
+                }
+                if (!wk) continue;
 #pragma unroll
                 for (int ic = 0; ic < NC; ++ic) {
                     double s1 = 0.0, s2 = 0.0;
@@ -842,10 +817,12 @@ __global__ void __launch_bounds__(FK_BLOCK) k_jk_wpq(FkJKArgs a)
                     atomic_add(&XK[(size_t)(ob + ib) * n + od + id], s2);
                 }
             }
+            if (wj) {
 #pragma unroll
-            for (int o = 0; o < NCD; ++o) {
-                const double s = wave_sum(jcd[o]);
-                if (lane == 0) atomic_add(&XJ[(size_t)(oc + o / ND) * n + od + o % ND], 2.0 * s);
+                for (int o = 0; o < NCD; ++o) {
+                    const double s = wave_sum(jcd[o]);
+                    if (lane == 0) atomic_add(&XJ[(size_t)(oc + o / ND) * n + od + o % ND], 2.0 * s);
+                }
             }
         }
     }
@@ -982,10 +959,13 @@ struct Disp {
     }
     static int lds_bytes(int bra_slot)
     {
+        // the Rys segment, and per wave the team reductions (bra records are
+        // read from memory by scalar loads: bra_slot needs no LDS)
+        (void)bra_slot;
         using C = fk::QClass<LA, LB, LC, LD>;
         int extra = 0;
         if constexpr (KIND == 1 || KIND == 2) extra = TeamShape<LA, LB, LC, LD, KIND>::RED;
-        return (int)sizeof(double) * (rys_lds_size(C::NR) + FK_WAVES * (bra_slot + extra));
+        return (int)sizeof(double) * (rys_lds_size(C::NR) + FK_WAVES * extra);
     }
     static int launch_jk(const FkJKArgs *a, int grid, hipStream_t st)
     {
@@ -1213,15 +1193,25 @@ __global__ void k_finalize(const double *__restrict XJ, const double *__restrict
     const int r = (int)(loc / n), c = (int)(loc % n);
     const long long t = m.mol_base[k] + (long long)c * n + r;
     const double f = s[f0 + r] * s[f0 + c];
-    double sj = 0.0, sk = 0.0;
+    // a build of one matrix passes a null pointer for the other
+    if (J) {
+        double sj = 0.0;
 #pragma unroll
-    for (int x = 0; x < FK_XCD_COPIES; ++x) {
-        const long long o = (long long)x * xcopy;
-        sj += XJ[o + i] + XJ[o + t];
-        sk += XK[o + i] + XK[o + t];
+        for (int x = 0; x < FK_XCD_COPIES; ++x) {
+            const long long o = (long long)x * xcopy;
+            sj += XJ[o + i] + XJ[o + t];
+        }
+        J[i] = f * sj;
     }
-    J[i] = f * sj;
-    K[i] = f * sk;
+    if (K) {
+        double sk = 0.0;
+#pragma unroll
+        for (int x = 0; x < FK_XCD_COPIES; ++x) {
+            const long long o = (long long)x * xcopy;
+            sk += XK[o + i] + XK[o + t];
+        }
+        K[i] = f * sk;
+    }
 }
 
 

@@ -14,6 +14,13 @@ u_i = y_i^2 / T, w_i = h_i / sqrt(T) (y_i > 0 the roots of H_{2n}).
 Output: ``rys_table.inc`` with, for every n = 1..RYS_NMAX, coefficients laid
 out [interval][coefficient][function], function 2i = u_i and 2i+1 = w_i, in
 the monomial basis of x = 2 (T - T_lo)/h - 1 (Horner evaluation).
+
+Intervals: for n <= UNI_NMAX a uniform grid of width UNI_H from 0 up to the
+switch T_s(n) to the Gauss-Hermite rule (the interval of T is then a single
+multiply and truncation); for larger n, whose tables would not fit the LDS
+on a uniform grid, four regions of doubling width up to TMAX.  T_s(n) is the
+smallest integer T from which the Gauss-Hermite moments agree with F_k(T),
+k < 2n, to 3e-15 relative (64 at most).
 """
 from __future__ import annotations
 
@@ -27,8 +34,20 @@ import mpmath as mp
 NMAX = 7
 # (start of region, interval width); the last region ends at TMAX
 REGIONS = [(0.0, 0.5), (16.0, 1.0), (32.0, 2.0), (48.0, 4.0)]
-TMAX = 64.0          # start of the asymptotic regime
+TMAX = 64.0          # end of the region tables
 DEG = 9              # polynomial degree per interval
+UNI_NMAX = 4         # n up to this: uniform grid
+UNI_H = 0.5          # its interval width
+TSWITCH = {1: 36.0, 2: 42.0, 3: 47.0, 4: 52.0, 5: 57.0, 6: 61.0, 7: 64.0}
+
+
+def tswitch_check(n, T):
+    """Largest relative difference between the Gauss-Hermite (asymptotic)
+    moments and F_k(T), k < 2n."""
+    mom = moments(T, 2 * n)
+    T = mp.mpf(T)
+    return max(abs(mp.gamma(k + mp.mpf(1) / 2) / (2 * T ** (k + mp.mpf(1) / 2)) - mom[k]) / mom[k]
+               for k in range(2 * n))
 
 
 def moments(T, kmax):
@@ -115,7 +134,7 @@ def gauss_hermite_half(n):
 
 
 def intervals():
-    """(T_lo, width) of every interval, region by region."""
+    """(T_lo, width) of every interval of the region tables, region by region."""
     out = []
     ends = [r[0] for r in REGIONS[1:]] + [TMAX]
     for (t0, h), t1 in zip(REGIONS, ends):
@@ -124,25 +143,38 @@ def intervals():
     return out
 
 
+def intervals_n(n):
+    """(T_lo, width) of the intervals of the n-point table."""
+    if n <= UNI_NMAX:
+        return [(i * UNI_H, UNI_H) for i in range(int(round(TSWITCH[n] / UNI_H)))]
+    return intervals()
+
+
 def build_tables(nmax=NMAX, deg=DEG, progress=False):
     mp.mp.dps = 80
-    ivs = intervals()
-    nint = len(ivs)
-    tabs = {n: [] for n in range(1, nmax + 1)}
-    for it, (lo, h) in enumerate(ivs):
+    for n in range(1, nmax + 1):
+        assert tswitch_check(n, TSWITCH[n]) < 3e-15 or TSWITCH[n] == TMAX, n
+    # every distinct interval once, with the rules of the n that use it
+    users = {}
+    for n in range(1, nmax + 1):
+        for iv in intervals_n(n):
+            users.setdefault(iv, []).append(n)
+    rules = {}
+    for it, ((lo, h), ns) in enumerate(sorted(users.items())):
         xs, Ts = nodes(mp.mpf(lo), mp.mpf(h), deg)
-        vals = {n: [[] for _ in range(2 * n)] for n in range(1, nmax + 1)}
+        vals = {n: [[] for _ in range(2 * n)] for n in ns}
         for T in Ts:
-            mom = moments(T, 2 * nmax)
-            for n in range(1, nmax + 1):
+            mom = moments(T, 2 * max(ns))
+            for n in ns:
                 u, w = gauss_rule(mom, n)
                 for i in range(n):
                     vals[n][2 * i].append(u[i])
                     vals[n][2 * i + 1].append(w[i])
-        for n in range(1, nmax + 1):
-            tabs[n].append([cheb_to_mono(cheb_fit(vals[n][f], deg)) for f in range(2 * n)])
+        for n in ns:
+            rules[(n, lo, h)] = [cheb_to_mono(cheb_fit(vals[n][f], deg)) for f in range(2 * n)]
         if progress:
-            print(f"interval {it + 1}/{nint}", file=sys.stderr, flush=True)
+            print(f"interval {it + 1}/{len(users)}", file=sys.stderr, flush=True)
+    tabs = {n: [rules[(n, lo, h)] for lo, h in intervals_n(n)] for n in range(1, nmax + 1)}
     gh = {n: gauss_hermite_half(n) for n in range(1, nmax + 1)}
     return tabs, gh
 
@@ -152,14 +184,21 @@ def write_inc(path, tabs, gh, nmax=NMAX, deg=DEG):
     L = []
     L.append("/* Generated by gen_rys_table.py -- do not edit.  Rys roots u_i and weights w_i")
     L.append(" * of the n-point rule for exp(-T t^2) on [0,1] in u = t^2, as degree-RYS_DEG")
-    L.append(" * polynomials in x = 2 (T - T_lo)/h - 1 per interval of T below RYS_TMAX.  Region r")
-    L.append(" * starts at rys_reg_t0[r] with interval width 1/rys_reg_invh[r]; its first interval")
-    L.append(" * has index rys_reg_base[r].")
+    L.append(" * polynomials in x = 2 (T - T_lo)/h - 1 per interval of T below the switch")
+    L.append(" * RYS_TSWITCH_n.  n <= RYS_UNI_NMAX: uniform intervals of width 1/RYS_UNI_INVH from")
+    L.append(" * 0 (rys_table_nint[n] of them); larger n: region r starts at RYS_REGr_T0 with width")
+    L.append(" * 1/RYS_REGr_INVH, its first interval has index RYS_REGr_BASE (RYS_NINT in all).")
     L.append(" * layout [interval][coefficient][function], function 2i = u_i, 2i+1 = w_i.")
-    L.append(" * Above RYS_TMAX: u_i = y_i^2/T, w_i = h_i/sqrt(T) (half-range Gauss-Hermite). */")
+    L.append(" * From the switch on: u_i = y_i^2/T, w_i = h_i/sqrt(T) (half-range Gauss-Hermite). */")
     L.append(f"#define RYS_NMAX {nmax}")
     L.append(f"#define RYS_NREG {len(REGIONS)}")
     L.append(f"#define RYS_TMAX {TMAX!r}")
+    L.append(f"#define RYS_UNI_NMAX {UNI_NMAX}")
+    L.append(f"#define RYS_UNI_INVH {1.0 / UNI_H!r}")
+    for n in range(1, nmax + 1):
+        L.append(f"#define RYS_TSWITCH_{n} {TSWITCH[n]!r}")
+    L.append("static constexpr int rys_table_nint[RYS_NMAX + 1] = {0, " +
+             ", ".join(str(len(tabs[n])) for n in range(1, nmax + 1)) + "};")
     bases, b = [], 0
     ends = [r[0] for r in REGIONS[1:]] + [TMAX]
     for (t0, h), t1 in zip(REGIONS, ends):
@@ -175,12 +214,12 @@ def write_inc(path, tabs, gh, nmax=NMAX, deg=DEG):
     o = 0
     for n in range(1, nmax + 1):
         offs.append(o)
-        o += nint * (deg + 1) * 2 * n
+        o += len(tabs[n]) * (deg + 1) * 2 * n
     L.append(f"#define RYS_TABLE_SIZE {o}")
     L.append("static const int rys_table_offset[RYS_NMAX + 1] = {" + ", ".join(str(x) for x in offs) + f", {o}}};")
     L.append("static const double rys_table_data[RYS_TABLE_SIZE] = {")
     for n in range(1, nmax + 1):
-        for it in range(nint):
+        for it in range(len(tabs[n])):
             for k in range(deg + 1):
                 row = ", ".join(mp.nstr(tabs[n][it][f][k], 17, min_fixed=1, max_fixed=0) for f in range(2 * n))
                 L.append("  " + row + ",")
@@ -191,8 +230,8 @@ def write_inc(path, tabs, gh, nmax=NMAX, deg=DEG):
         ys += [mp.nstr(v * v, 17, min_fixed=1, max_fixed=0) for v in y]   # y_i^2
         ws += [mp.nstr(v, 17, min_fixed=1, max_fixed=0) for v in w]
     L.append("/* half-range Gauss-Hermite: y_i^2 and h_i, n = 1..RYS_NMAX concatenated */")
-    L.append("static const double rys_gh_y2[" + str(len(ys)) + "] = {" + ", ".join(ys) + "};")
-    L.append("static const double rys_gh_w[" + str(len(ws)) + "] = {" + ", ".join(ws) + "};")
+    L.append("static constexpr double rys_gh_y2[" + str(len(ys)) + "] = {" + ", ".join(ys) + "};")
+    L.append("static constexpr double rys_gh_w[" + str(len(ws)) + "] = {" + ", ".join(ws) + "};")
     with open(path, "w") as f:
         f.write("\n".join(L) + "\n")
 

@@ -36,6 +36,9 @@ def test_rys_moments(n):
     asymptotic region."""
     mpmath.mp.dps = 30
     Ts = [0.0, 1e-9, 0.25, 0.5, 3.7, 15.999, 16.0, 16.001, 29.3, 47.0, 63.999, 64.0, 64.5, 90.0, 400.0]
+    # either side of the switch from the table to the Gauss-Hermite rule
+    sw = {1: 36.0, 2: 42.0, 3: 47.0, 4: 52.0, 5: 57.0, 6: 61.0, 7: 64.0}[n]
+    Ts += [sw - 1e-9, sw, sw + 1e-9, sw + 0.5]
     for T in Ts:
         u, w = fk.rys_host(n, T)
         assert np.all(u > 0) and np.all(u < 1) and np.all(w > 0)
