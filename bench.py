@@ -4,12 +4,16 @@
 A step is one full pass of the J/K hot path for one density: density
 preprocessing (scaled D, shell-block maxima), every quartet-class Rys ERI +
 digestion kernel, and the symmetrisation into J and K, on resident device
-buffers.  Workload (default): all-trans C20H42 with 0.02 A seeded jitter in the
-6-31G*-type basis (384 Cartesian functions, s/p/d), Schwarz threshold 1e-10
-with the per-quartet density screen, at the core-Hamiltonian guess density.
+buffers.  Workload (default): 64 seeded waters at 1.0 g/cm^3 in the
+cc-pVDZ-type basis (1600 Cartesian functions, s/p/d), Schwarz threshold 1e-10
+with the per-quartet density screen, primitive pairs pruned at 1e-12, at the
+core-Hamiltonian guess density.  `value` is the FP64 build rate; the line
+also carries the same build with the precision split at tau_fp32 = 1e-5
+(`mixed`: rate, speed-up, J/K and energy differences, SCF energies of both),
+SCF iteration counts, the dominant kernel against the FP64 roofline, a
+C20H42 / 6-31G*-type reference rate and the oracle's CPU baseline.
 
-Prints one JSON line (see the fields below).  --gpus above 1 is refused: the
-build runs on one GPU.
+Prints one JSON line.  --gpus above 1 is refused: the build runs on one GPU.
 """
 from __future__ import annotations
 
@@ -81,31 +85,89 @@ def _core_density(S, h, nocc):
     return 2.0 * C @ C.T
 
 
-def cpu_baseline(sys_, D, target_s=15.0):
-    """The oracle (test infrastructure) timed on host cores over a bounded
-    sample of the same workload: whole shell blocks J[A,B] by literal sums
-    (every (AB|CD) over all C, D), scaled to one full unscreened oracle build
-    (one evaluation per unique shell quartet)."""
+def _cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(sys_, gpu_classes, target_s=20.0):
+    """The oracle (test infrastructure: plain MMD, unscreened) timed on the
+    host's cores over a bounded sample of the same workload.  Per quartet
+    class, random shell quartets of that class (uniform over the unscreened
+    unique quartets) are evaluated by the oracle's MMD code, on all cores and
+    on one; their time per primitive quartet, times the primitive quartets the
+    GPU build computes in that class, estimates the oracle doing the GPU's
+    (screened) work; time per shell quartet times the class's unique quartets
+    estimates one unscreened oracle build.  value = 1 / the screened estimate
+    (all cores)."""
     import oracle
-    nthreads = min(16, os.cpu_count() or 1)
-    ns = sys_["nshell"]
-    rng = np.random.default_rng(99)
-    done_q, t_used, nblk = 0, 0.0, 0
-    while t_used < target_s and nblk < 4096:
-        a, b = (int(x) for x in rng.integers(0, ns, size=2))
-        t0 = time.perf_counter()
-        oracle.jk_blocks(sys_, D, [(a, b)], [], nthreads=nthreads)
-        t_used += time.perf_counter() - t0
-        done_q += ns * ns
-        nblk += 1
-    npair = ns * (ns + 1) // 2
-    unique_q = npair * (npair + 1) // 2
-    per_q = t_used / done_q
-    est_build_s = per_q * unique_q
-    return {"value": 1.0 / est_build_s, "unit": "builds/s", "cores": nthreads, "kind": "oracle",
-            "sample": f"{nblk} random J shell blocks ({done_q} shell quartets, {t_used:.1f} s) scaled to one "
-                      f"unscreened build of {unique_q} unique shell quartets",
-            "quartets_per_s": 1.0 / per_q, "est_build_s": est_build_s}
+    ncpu = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
+    ls = np.asarray(sys_["sh_l"])
+    npr = np.asarray(sys_["sh_nprim"])
+    ns = len(ls)
+
+    def pcls(la, lb):
+        return la * (la + 1) // 2 + lb
+    pairs = {}
+    for a in range(ns):
+        for b in range(a + 1):
+            x, y = (a, b) if (ls[a], a) >= (ls[b], b) else (b, a)
+            pairs.setdefault(pcls(ls[x], ls[y]), []).append((x, y))
+    pairs = {k: np.array(v, dtype=np.int32) for k, v in pairs.items()}
+    gpu = {}
+    for c in gpu_classes:
+        key = tuple(c["class"])
+        q, p = gpu.get(key, (0, 0))
+        gpu[key] = (q + c["quartets"], p + c["prim_quartets"])
+    rng = np.random.default_rng(2024)
+    per = max(0.05, target_s / max(1, len(gpu)))
+    rows, est_scr, est_scr1, est_uns, t_used = [], 0.0, 0.0, 0.0, 0.0
+    for (la, lb, lc, ld), (gq, gp) in sorted(gpu.items()):
+        P, Q = pcls(la, lb), pcls(lc, ld)
+        B, K = pairs[P], pairs[Q]
+        n_unique = len(B) * len(K) if P != Q else len(B) * (len(B) + 1) // 2
+
+        def sample(n):
+            qs = np.concatenate([B[rng.integers(len(B), size=n)], K[rng.integers(len(K), size=n)]], axis=1)
+            prims = float(np.sum(npr[qs[:, 0]] * npr[qs[:, 1]] * npr[qs[:, 2]] * npr[qs[:, 3]]))
+            return qs, prims
+
+        def timed(n, threads):
+            qs, prims = sample(n)
+            t0 = time.perf_counter()
+            oracle.eri_list(sys_, qs, nthreads=threads)
+            return time.perf_counter() - t0, n, prims
+        # grow the sample until it takes a fair share of the budget
+        n = 64
+        while True:
+            t_all, n_all, p_all = timed(n, ncpu)
+            if t_all >= 0.3 * per or n >= 2_000_000:
+                break
+            n = int(min(2_000_000, n * min(16.0, max(2.0, 0.7 * per / max(t_all, 1e-4)))))
+        n1 = int(min(n_all, max(16, n_all * 0.3 * per / max(t_all * ncpu, 1e-4))))
+        t_one, n_one, p_one = timed(n1, 1)
+        t_used += t_all + t_one
+        est_scr += t_all / p_all * gp
+        est_scr1 += t_one / p_one * gp
+        est_uns += t_all / n_all * n_unique
+        rows.append({"class": "({}{}|{}{})".format(*("spdf"[x] for x in (la, lb, lc, ld))),
+                     "sampled_quartets": n_all, "sampled_quartets_1core": n_one,
+                     "s_per_prim_quartet": t_all / p_all, "s_per_prim_quartet_1core": t_one / p_one})
+    return {"value": 1.0 / est_scr, "unit": "builds/s", "cores": ncpu, "kind": "oracle",
+            "sample": f"per quartet class, random unscreened shell quartets of this workload evaluated by the "
+                      f"oracle's MMD code ({sum(r['sampled_quartets'] for r in rows)} quartets on {ncpu} threads, "
+                      f"{sum(r['sampled_quartets_1core'] for r in rows)} on 1, {t_used:.1f} s); time per primitive "
+                      f"quartet x the GPU build's primitive quartets per class = one build of the same screened "
+                      f"work",
+            "nproc": ncpu, "cpu_model": _cpu_model(), "value_1core": 1.0 / est_scr1,
+            "est_screened_build_s": est_scr, "est_screened_build_s_1core": est_scr1,
+            "est_unscreened_build_s": est_uns, "classes": rows}
 
 
 def _progress(msg):
@@ -238,21 +300,237 @@ def bench_batch(args, torch, fk):
     return 0
 
 
+def _time_builds(torch, ctx, Dd, J, K, stream, warmup, steps):
+    """Milliseconds per build: `warmup` untimed builds, then `steps` builds
+    between HIP events on the build stream, bracketed by device syncs."""
+    for _ in range(warmup):
+        ctx.build_jk(Dd, J, K, stream=stream)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(steps):
+        ctx.build_jk(Dd, J, K, stream=stream)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / steps
+
+
+def _class_times(ctx, Dd, J, K, stream, reps=3):
+    """Per-launch kernel times (HIP events around each class launch, on the
+    build stream), averaged over `reps` builds; returns (times, stats)."""
+    acc = None
+    for _ in range(reps):
+        ctx.build_jk(Dd, J, K, stream=stream, time_classes=True)
+        st = ctx.stats()
+        t = np.array([c["ms"] for c in st["classes"]])
+        acc = t if acc is None else acc + t
+    return acc / reps, st
+
+
+def _cname(c):
+    return "({}{}|{}{})".format(*("spdf"[x] for x in c["class"]))
+
+
+def _print_classes(cls_ms, st):
+    print(f"{'class':>10} {'prec':>4} {'ms':>8} {'share':>6} {'quartets':>11} {'prims':>13} {'GFLOP':>9} "
+          f"{'TFLOP/s':>8} {'frac':>6}", file=sys.stderr)
+    for k in np.argsort(-cls_ms):
+        cc = st["classes"][k]
+        f = cc["prim_quartets"] * cc["flops_per_prim"] + cc["quartets"] * cc["flops_per_quartet"]
+        tf = f / (cls_ms[k] * 1e-3) / 1e12 if cls_ms[k] > 0 else 0.0
+        peak = PEAK_FP32_VALU if cc["precision"] == 32 else PEAK_FP64_VALU
+        print(f"{_cname(cc):>10} {cc['precision']:>4} {cls_ms[k]:8.3f} {cls_ms[k] / cls_ms.sum():6.3f} "
+              f"{cc['quartets']:11d} {cc['prim_quartets']:13d} {f / 1e9:9.2f} {tf:8.3f} {tf / peak:6.3f}",
+              file=sys.stderr)
+
+
+def _tune(ctx, Dd, stream):
+    t0 = time.perf_counter()
+    rep = ctx.autotune(Dd, reps=2, stream=stream.cuda_stream)
+    return rep, {"seconds": time.perf_counter() - t0, "configurations": rep["configurations"],
+                 "class_ms_sum_default": rep["build_ms_default"], "class_ms_sum_tuned": rep["build_ms_tuned"],
+                 "changed_classes": int(sum(r["changed"] for r in rep["classes"]))}
+
+
+def _sched_of(c, tuned_rows, pinned):
+    sched = pinned.get(tuple(c["class"]), "default")
+    for r in tuned_rows:
+        if (r["la"], r["lb"], r["lc"], r["ld"]) == tuple(c["class"]) and r["precision"] == c["precision"] \
+                and r["changed"]:
+            sched = [r["bra_block"], r["kets_per_tile"], r["grid_fraction"]]
+    return sched
+
+
+def bench_single(args, torch, fk):
+    """One molecule: the FP64 build timed (the line's value), the dominant
+    class kernel against the FP64 roofline, the same build with the precision
+    split (mixed) timed and compared, SCF runs of both, a C20H42 line and the
+    oracle's CPU baseline."""
+    sys_, desc = _workload(args.workload)
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream(dev)
+    pinned = {}
+
+    def make(tau_fp32):
+        c = fk.FockJK(0).set_system(sys_)
+        for spec in args.schedule:
+            v = spec.split(",")
+            if len(v) != 7:
+                raise SystemExit(f"--schedule {spec}: expected LA,LB,LC,LD,BRA_BLOCK,KETS,GRID_FRACTION")
+            cls, sch = tuple(int(x) for x in v[:4]), (int(v[4]), int(v[5]), float(v[6]))
+            c.set_class_schedule(*cls, *sch)
+            pinned[cls] = list(sch)
+        return c.build_quartets(tau=args.tau, tau_prim=args.tau_prim, tau_fp32=tau_fp32)
+
+    ctx = make(0.0)
+    info = ctx.info()
+    S, T, V, _ = ctx.one_electron()
+    D = _core_density(S, T + V, sys_["nelec"] // 2)
+    Dd = torch.tensor(D, dtype=torch.float64, device=dev)
+    J = torch.empty_like(Dd)
+    K = torch.empty_like(Dd)
+    _progress(f"{desc}: lists built ({info['nquartet_schwarz']} Schwarz quartets)")
+    tune, tuned_rows = None, []
+    if args.autotune:
+        rep, tune = _tune(ctx, Dd, stream)
+        tuned_rows = rep["classes"]
+        _progress(f"FP64 schedules tuned in {tune['seconds']:.0f} s")
+    ms = _time_builds(torch, ctx, Dd, J, K, stream, args.warmup, args.steps)
+    st = ctx.stats()
+    _progress(f"FP64 build {ms:.2f} ms")
+    cls_ms, s2 = _class_times(ctx, Dd, J, K, stream)
+    if args.classes:
+        _print_classes(cls_ms, s2)
+    i = int(np.argmax(cls_ms))
+    c = s2["classes"][i]
+    cflops = c["prim_quartets"] * c["flops_per_prim"] + c["quartets"] * c["flops_per_quartet"]
+    achieved = cflops / (cls_ms[i] * 1e-3) / 1e12
+    sched = _sched_of(c, tuned_rows, pinned)
+    out = {
+        "metric": METRIC, "value": 1000.0 / ms, "unit": "builds/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": desc, "nbf": info["nbf"], "nshell": info["nshell"], "tau": args.tau,
+                   "tau_prim": args.tau_prim, "density": "core-Hamiltonian guess", "precision": "fp64",
+                   "mixed_leg_tau_fp32": args.tau_fp32},
+        "quartets_per_s": st["quartets"] / (ms * 1e-3),
+        "prim_quartets_per_s": st["prim_quartets"] / (ms * 1e-3),
+        "quartets_per_build": st["quartets"], "schwarz_quartets": info["nquartet_schwarz"],
+        "flops_per_build": st["flops_total"], "tflops_build": st["flops_total"] / (ms * 1e-3) / 1e12,
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP64_VALU, "unit": "TFLOP/s",
+                     "frac": achieved / PEAK_FP64_VALU,
+                     "traffic": _traffic(f"J/K class {_cname(c)}", args.workload, sched),
+                     "kernel": f"J/K class {_cname(c)}", "kernel_ms": float(cls_ms[i]), "schedule": sched,
+                     "class_share": float(cls_ms[i] / cls_ms.sum()),
+                     "flops_per_launch": cflops, "quartets_per_launch": c["quartets"],
+                     "prim_quartets_per_launch": c["prim_quartets"]},
+    }
+    if tune:
+        out["autotune"] = tune
+    ref = None
+    if args.tau_fp32 > 0:
+        # the same build with the precision split: FP32 recurrences for the
+        # waves whose quartets all have G_ab G_cd D_max below tau_fp32
+        mx = make(args.tau_fp32)
+        if args.autotune:
+            _, tune_mx = _tune(mx, Dd, stream)
+        Jm = torch.empty_like(Dd)
+        Km = torch.empty_like(Dd)
+        ms_mx = _time_builds(torch, mx, Dd, Jm, Km, stream, args.warmup, args.steps)
+        stm = mx.stats()
+        ctx.build_jk(Dd, J, K, stream=stream)
+        torch.cuda.synchronize()
+        dJ = (Jm - J).cpu().numpy()
+        dK = (Km - K).cpu().numpy()
+        n32 = sum(x["quartets"] for x in stm["classes"] if x["precision"] == 32)
+        cms, s3 = _class_times(mx, Dd, Jm, Km, stream)
+        f64 = sum(x["prim_quartets"] * x["flops_per_prim"] + x["quartets"] * x["flops_per_quartet"]
+                  for x in s3["classes"] if x["precision"] == 64)
+        f32 = sum(x["prim_quartets"] * x["flops_per_prim"] + x["quartets"] * x["flops_per_quartet"]
+                  for x in s3["classes"] if x["precision"] == 32)
+        t_ideal = f64 / (PEAK_FP64_VALU * 1e12) + f32 / (PEAK_FP32_VALU * 1e12)
+        out["mixed"] = {"tau_fp32": args.tau_fp32, "builds_per_s": 1000.0 / ms_mx, "ms_per_step": ms_mx,
+                        "speedup_vs_fp64": ms / ms_mx, "fp32_quartet_fraction": n32 / max(1, stm["quartets"]),
+                        "quartets_per_s": stm["quartets"] / (ms_mx * 1e-3),
+                        "max_abs_dJ": float(np.max(np.abs(dJ))), "max_abs_dK": float(np.max(np.abs(dK))),
+                        "dE_one_build": float(0.5 * np.sum(D * dJ) - 0.25 * np.sum(D * dK)),
+                        "roofline_frac_t_ideal": t_ideal / (float(cms.sum()) * 1e-3)}
+        if args.autotune:
+            out["mixed"]["autotune"] = tune_mx
+        _progress(f"mixed build {ms_mx:.2f} ms ({n32 / max(1, stm['quartets']):.2f} FP32 quartets)")
+        ref = mx
+    if not args.no_scf:
+        # SCF from the core-Hamiltonian guess on the same lists (outside the
+        # timed region): |dE| < 1e-10, max |error| < 1e-8
+        r = ctx.run_scf()
+        out["scf"] = {"iterations": r["iterations"], "converged": bool(r["converged"]), "energy": r["energy"],
+                      "seconds": r["total_seconds"], "jk_seconds": r["jk_seconds"],
+                      "jk_ms_per_iteration": 1000.0 * r["jk_seconds"] / max(1, r["iterations"]),
+                      "guess": "core Hamiltonian"}
+        if ref is not None:
+            rm = ref.run_scf()
+            out["mixed"]["scf"] = {"iterations": rm["iterations"], "converged": bool(rm["converged"]),
+                                   "energy": rm["energy"], "seconds": rm["total_seconds"],
+                                   "jk_seconds": rm["jk_seconds"],
+                                   "energy_minus_fp64": rm["energy"] - r["energy"]}
+        guesses = {"sad": fk.GUESS_SAD}
+        model = os.path.join(HERE, "paper_2407_21445_amd", "guess_631gs.npz")
+        if sys_["name"].endswith("/6-31gs-type") and os.path.exists(model):
+            from paper_2407_21445_amd.guess_train import load_model
+            try:
+                ctx.set_guess_model(*load_model(model))
+                guesses["learned"] = fk.GUESS_LEARNED
+            except fk.FockJKError as e:  # weights of another feature layout
+                print(f"bench.py: learned guess skipped: {e}", file=sys.stderr)
+        for name, g in guesses.items():
+            rg = ctx.run_scf(guess=g)
+            out["scf"][name] = {"iterations": rg["iterations"], "converged": bool(rg["converged"]),
+                                "seconds": rg["total_seconds"], "guess_seconds": rg["guess_seconds"],
+                                "energy_minus_core_start": rg["energy"] - r["energy"],
+                                "guess_used": {0: "core", 2: "sad", 3: "learned"}.get(rg["guess_used"], "?")}
+        _progress(f"SCF: {r['iterations']} iterations")
+    if args.workload != "c20h42" and not args.no_extra:
+        # the C20H42 / 6-31G*-type workload, FP64, as a second line of reference
+        from synth import workloads as wl
+        s2y = wl.c20h42_631gs()
+        c2 = fk.FockJK(0).set_system(s2y).build_quartets(tau=args.tau, tau_prim=args.tau_prim)
+        S2, T2, V2, _ = c2.one_electron()
+        D2 = torch.tensor(_core_density(S2, T2 + V2, s2y["nelec"] // 2), dtype=torch.float64, device=dev)
+        J2, K2 = torch.empty_like(D2), torch.empty_like(D2)
+        if args.autotune:
+            _tune(c2, D2, stream)
+        ms2 = _time_builds(torch, c2, D2, J2, K2, stream, 3, 20)
+        st2 = c2.stats()
+        out["c20h42"] = {"workload": "C20H42 all-trans (0.02 A jitter), 6-31G*-type, 384 Cartesian bf, fp64",
+                         "builds_per_s": 1000.0 / ms2, "ms_per_step": ms2,
+                         "quartets_per_s": st2["quartets"] / (ms2 * 1e-3)}
+        _progress(f"C20H42 build {ms2:.2f} ms")
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(sys_, st["classes"], args.cpu_seconds)
+    print(json.dumps(out), flush=True)
+    return 0
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="c20h42")
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="water64", choices=("water64", "c20h42", "water4", "c4"))
     ap.add_argument("--tau", type=float, default=1e-10)
     ap.add_argument("--tau-prim", type=float, default=1e-12, help="primitive-pair pruning threshold")
+    ap.add_argument("--tau-fp32", type=float, default=1e-5,
+                    help="mixed leg: FP32 recurrences for waves whose quartets all have G_ab G_cd D_max below "
+                         "this (0: no mixed leg; for --workload c4 the precision of the timed batch)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--classes", action="store_true", help="print the per-class kernel table to stderr")
     ap.add_argument("--schedule", action="append", default=[], metavar="LA,LB,LC,LD,BB,KT,GF",
                     help="fix a class schedule (bra block, kets per tile, grid fraction) before the lists "
                          "are built; with --no-autotune it is the one timed")
-    ap.add_argument("--no-scf", action="store_true", help="skip the SCF run reported beside the build rate")
+    ap.add_argument("--no-scf", action="store_true", help="skip the SCF runs reported beside the build rate")
+    ap.add_argument("--no-extra", action="store_true", help="skip the C20H42 reference line")
     ap.add_argument("--no-autotune", dest="autotune", action="store_false",
                     help="time the default kernel schedules (the autotuner runs by default, before timing)")
     ap.add_argument("--nmol", type=int, default=8, help="molecules of the organic batch (--workload c4)")
@@ -263,8 +541,6 @@ def main():
                     help="--workload c4: report finished class launches during each build (long batches)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MB",
                     help="only run a plain device copy of MB megabytes 5 times (calibrates HBM byte counters)")
-    ap.add_argument("--tau-fp32", type=float, default=0.0,
-                    help="precision split: FP32 recurrences for quartets with G_ab G_cd * 2 below this (0: FP64)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: the library runs on one GPU; --gpus {args.gpus} is not supported", file=sys.stderr)
@@ -281,177 +557,10 @@ def main():
         print(json.dumps({"copy_probe_bytes": x.numel() * 8}), flush=True)
         return 0
     if args.workload == "c4":
+        if "--tau-fp32" not in " ".join(sys.argv):
+            args.tau_fp32 = 0.0
         return bench_batch(args, torch, fk)
-    sys_, desc = _workload(args.workload)
-    ctx = fk.FockJK(0).set_system(sys_)
-    pinned = {}
-    for spec in args.schedule:
-        v = spec.split(",")
-        if len(v) != 7:
-            raise SystemExit(f"--schedule {spec}: expected LA,LB,LC,LD,BRA_BLOCK,KETS,GRID_FRACTION")
-        cls, sch = tuple(int(x) for x in v[:4]), (int(v[4]), int(v[5]), float(v[6]))
-        ctx.set_class_schedule(*cls, *sch)
-        pinned[cls] = list(sch)
-    ctx.build_quartets(tau=args.tau, tau_prim=args.tau_prim, tau_fp32=args.tau_fp32)
-    info = ctx.info()
-    S, T, V, _ = ctx.one_electron()
-    D = _core_density(S, T + V, sys_["nelec"] // 2)
-    dev = torch.device("cuda:0")
-    Dd = torch.tensor(D, dtype=torch.float64, device=dev)
-    J = torch.empty_like(Dd)
-    K = torch.empty_like(Dd)
-    stream = torch.cuda.current_stream(dev)
-    tune, tuned_rows = None, []
-    if args.autotune:
-        # schedule tuning before the timed region (lists rebuilt with the choice)
-        t_tune = time.perf_counter()
-        rep = ctx.autotune(Dd, reps=2, stream=stream.cuda_stream)
-        tuned_rows = rep["classes"]
-        tune = {"seconds": time.perf_counter() - t_tune, "configurations": rep["configurations"],
-                "class_ms_sum_default": rep["build_ms_default"], "class_ms_sum_tuned": rep["build_ms_tuned"],
-                "classes": {f"({r['la']}{r['lb']}|{r['lc']}{r['ld']})/fp{r['precision']}":
-                            [r["bra_block"], r["kets_per_tile"], r["grid_fraction"], round(r["ms_default"], 4),
-                             round(r["ms_tuned"], 4)]
-                            for r in rep["classes"] if r["ms_default"] > 0.1},
-                "fields": "bra_block, kets_per_tile, grid_fraction, ms_default, ms_tuned (classes above 0.1 ms)"}
-
-    for _ in range(args.warmup):
-        ctx.build_jk(Dd, J, K, stream=stream)
-    torch.cuda.synchronize()
-    st = ctx.stats()
-
-    e0 = torch.cuda.Event(enable_timing=True)
-    e1 = torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    w0 = time.perf_counter()
-    e0.record(stream)
-    for _ in range(args.steps):
-        ctx.build_jk(Dd, J, K, stream=stream)
-    e1.record(stream)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - w0
-    ms = e0.elapsed_time(e1) / args.steps
-
-    # per-class kernel times (HIP events around each class launch on the same stream)
-    reps = 3
-    acc = None
-    for _ in range(reps):
-        ctx.build_jk(Dd, J, K, stream=stream, time_classes=True)
-        s2 = ctx.stats()
-        t = np.array([c["ms"] for c in s2["classes"]])
-        acc = t if acc is None else acc + t
-    cls_ms = acc / reps
-    i = int(np.argmax(cls_ms))
-    c = s2["classes"][i]
-    if args.classes:
-        print(f"{'class':>10} {'ms':>8} {'share':>6} {'quartets':>11} {'prims':>13} {'GFLOP':>9} {'TFLOP/s':>8} {'frac':>6}",
-              file=sys.stderr)
-        for k in np.argsort(-cls_ms):
-            cc = s2["classes"][k]
-            f = cc["prim_quartets"] * cc["flops_per_prim"] + cc["quartets"] * cc["flops_per_quartet"]
-            tf = f / (cls_ms[k] * 1e-3) / 1e12 if cls_ms[k] > 0 else 0.0
-            nm = "({}{}|{}{})".format(*("spdf"[x] for x in cc["class"]))
-            print(f"{nm:>10} {cls_ms[k]:8.3f} {cls_ms[k] / cls_ms.sum():6.3f} {cc['quartets']:11d} "
-                  f"{cc['prim_quartets']:13d} {f / 1e9:9.2f} {tf:8.3f} {tf / PEAK_FP64_VALU:6.3f}", file=sys.stderr)
-    cflops = c["prim_quartets"] * c["flops_per_prim"] + c["quartets"] * c["flops_per_quartet"]
-    achieved = cflops / (cls_ms[i] * 1e-3) / 1e12
-    peak = PEAK_FP32_VALU if c["precision"] == 32 else PEAK_FP64_VALU
-    lname = "spdf"
-    cname = "({}{}|{}{})".format(*(lname[x] for x in c["class"]))
-    # the committed counter figures name the schedule they were taken under
-    sched = pinned.get(tuple(c["class"]), "default")
-    for r in tuned_rows:
-        if (r["la"], r["lb"], r["lc"], r["ld"]) == tuple(c["class"]) and r["precision"] == c["precision"] \
-                and r["changed"]:
-            sched = [r["bra_block"], r["kets_per_tile"], r["grid_fraction"]]
-    out = {
-        "metric": METRIC, "value": 1000.0 / ms, "unit": "builds/s", "n_gpus": 1, "steps": args.steps,
-        "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
-        "vs_baseline": None, "dtype": "f64" if args.tau_fp32 <= 0 else "f64+f32", "data": "synthetic",
-        "config": {"workload": desc, "nbf": info["nbf"], "nshell": info["nshell"], "tau": args.tau,
-                   "tau_prim": args.tau_prim,
-                   "density": "core-Hamiltonian guess",
-                   "precision": "fp64" if args.tau_fp32 <= 0 else f"mixed (FP32 below tau_fp32={args.tau_fp32:g})"},
-        "quartets_per_s": st["quartets"] / (ms * 1e-3),
-        "prim_quartets_per_s": st["prim_quartets"] / (ms * 1e-3),
-        "quartets_per_build": st["quartets"], "schwarz_quartets": info["nquartet_schwarz"],
-        "flops_per_build": st["flops_total"], "tflops_build": st["flops_total"] / (ms * 1e-3) / 1e12,
-        "wall_s_timed": wall,
-        "roofline": {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
-                     "frac": achieved / peak, "traffic": _traffic(f"J/K class {cname}", args.workload, sched),
-                     "kernel": f"J/K class {cname}" + (" (FP32 part)" if c["precision"] == 32 else ""),
-                     "kernel_ms": float(cls_ms[i]), "schedule": sched,
-                     "class_share": float(cls_ms[i] / cls_ms.sum())},
-    }
-    if args.tau_fp32 > 0:
-        # the same build in FP64 only: J/K and one-build energy differences
-        ref = fk.FockJK(0).set_system(sys_).build_quartets(tau=args.tau, tau_prim=args.tau_prim)
-        if args.autotune:  # the FP64 reference with its own tuned schedules
-            ref.autotune(Dd, reps=2, stream=stream.cuda_stream)
-        J64, K64 = ref.build_jk(Dd, sync=True)
-        torch.cuda.synchronize()
-        for _ in range(2):
-            ref.build_jk(Dd, J64, K64, stream=stream)
-        r0 = torch.cuda.Event(enable_timing=True)
-        r1 = torch.cuda.Event(enable_timing=True)
-        r0.record(stream)
-        for _ in range(args.steps):
-            ref.build_jk(Dd, J64, K64, stream=stream)
-        r1.record(stream)
-        torch.cuda.synchronize()
-        ms64 = r0.elapsed_time(r1) / args.steps
-        dJ = (J - J64).cpu().numpy()
-        dK = (K - K64).cpu().numpy()
-        n32 = sum(x["quartets"] for x in st["classes"] if x["precision"] == 32)
-        out["mixed"] = {"tau_fp32": args.tau_fp32, "fp32_quartet_fraction": n32 / max(1, st["quartets"]),
-                        "fp64_builds_per_s": 1000.0 / ms64, "speedup": ms64 / ms,
-                        "max_abs_dJ": float(np.max(np.abs(dJ))), "max_abs_dK": float(np.max(np.abs(dK))),
-                        "dE_one_build": float(0.5 * np.sum(D * dJ) - 0.25 * np.sum(D * dK))}
-    if tune:
-        out["autotune"] = tune
-    if not args.no_scf:
-        # SCF from the core-Hamiltonian guess on the same quartet lists (outside
-        # the timed region): iterations to |dE| < 1e-10, max|error| < 1e-8
-        r = ctx.run_scf()
-        if args.tau_fp32 > 0:
-            r64 = ref.run_scf()
-            out["mixed"]["scf_energy_fp64"] = r64["energy"]
-            out["mixed"]["scf_energy_diff"] = r["energy"] - r64["energy"]
-        out["scf"] = {"iterations": r["iterations"], "converged": bool(r["converged"]), "energy": r["energy"],
-                      "seconds": r["total_seconds"], "jk_seconds": r["jk_seconds"],
-                      "jk_ms_per_iteration": 1000.0 * r["jk_seconds"] / max(1, r["iterations"]),
-                      "guess": "core Hamiltonian"}
-        # the same SCF from the SAD guess and from the learned guess (when the
-        # trained network for this basis is present)
-        guesses = {"sad": fk.GUESS_SAD}
-        model = os.path.join(HERE, "paper_2407_21445_amd", "guess_631gs.npz")
-        if sys_["name"].endswith("/6-31gs-type") and os.path.exists(model):
-            from paper_2407_21445_amd.guess_train import load_model
-            try:
-                ctx.set_guess_model(*load_model(model))
-                guesses["learned"] = fk.GUESS_LEARNED
-            except fk.FockJKError as e:  # weights of another feature layout
-                print(f"bench.py: learned guess skipped: {e}", file=sys.stderr)
-        # the core-guess SCF with incremental builds (full build every 8 iterations)
-        rin = ctx.run_scf(incremental=8)
-        out["scf"]["incremental"] = {"iterations": rin["iterations"], "converged": bool(rin["converged"]),
-                                     "seconds": rin["total_seconds"], "jk_seconds": rin["jk_seconds"],
-                                     "energy_minus_full": rin["energy"] - r["energy"]}
-        # the core-guess SCF again with its Fock stage replayed from a HIP graph
-        rgr = ctx.run_scf(graph=True)
-        out["scf"]["graph"] = {"iterations": rgr["iterations"], "converged": bool(rgr["converged"]),
-                               "seconds": rgr["total_seconds"], "stage_seconds": rgr["jk_seconds"],
-                               "energy_minus_eager": rgr["energy"] - r["energy"]}
-        for name, g in guesses.items():
-            rg = ctx.run_scf(guess=g)
-            out["scf"][name] = {"iterations": rg["iterations"], "converged": bool(rg["converged"]),
-                                "seconds": rg["total_seconds"], "guess_seconds": rg["guess_seconds"],
-                                "energy_minus_core_start": rg["energy"] - r["energy"],
-                                "guess_used": {0: "core", 2: "sad", 3: "learned"}.get(rg["guess_used"], "?")}
-    if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(sys_, D, args.cpu_seconds)
-    print(json.dumps(out), flush=True)
-    return 0
+    return bench_single(args, torch, fk)
 
 
 if __name__ == "__main__":

@@ -85,10 +85,14 @@ typedef struct {
                           pairs with the same kets (1..32; 0 = default 8).
                           Contributions to K[a, c], K[a, d] and J[c, d] are
                           summed over the block before they reach memory */
-    double tau_fp32;   /* precision split: quartets with G_ab G_cd * 2 < tau_fp32
-                          (2 bounds |D| of a closed-shell density) evaluate their
-                          recurrences in FP32; set-up, roots, weights,
-                          digestion and all accumulation stay FP64.  0 = FP64 only */
+    double tau_fp32;   /* precision split (an extension: the paper runs FP64 only):
+                          each class gets a second, FP32 launch over the same work
+                          tiles; per bra and tile, the quartets of a wave run their
+                          recurrences in FP32 when every one has G_ab G_cd D_max <
+                          tau_fp32 (D_max of the build's density, as in the density
+                          screen), in FP64 otherwise.  Set-up, roots, weights,
+                          digestion and all accumulation stay FP64; f-f bras stay
+                          FP64.  0 = FP64 only */
 } fk_screen_opts;
 
 typedef struct {

@@ -43,6 +43,7 @@ def lib():
         L.oracle_nbf.argtypes = ob
         L.oracle_eri_quartet.argtypes = ob + [I, I, I, I, I, P]
         L.oracle_eri_full.argtypes = ob + [P]
+        L.oracle_eri_list.argtypes = ob + [I, P, I, P]
         L.oracle_jk.argtypes = ob + [P, P, P, I]
         L.oracle_jk_blocks.argtypes = ob + [P, I, P, P, I, P, P, I]
         L.oracle_oneel.argtypes = ob + [P, P, P]
@@ -94,6 +95,17 @@ def eri_quartet(sys, a, b, c, d, method="mmd"):
     if rc:
         raise ValueError("oracle: invalid basis")
     return out
+
+
+def eri_list(sys, quartets, nthreads=0):
+    """Evaluates the listed shell quartets (rows a, b, c, d) with the oracle's
+    MMD code, OpenMP over the list; returns the sum of |(ab|cd)| (timing aid)."""
+    A = _Args(sys)
+    q = np.ascontiguousarray(np.asarray(quartets, dtype=np.int32).reshape(-1, 4))
+    sink = ctypes.c_double()
+    if lib().oracle_eri_list(*A.tup(), len(q), _ptr(q), int(nthreads), ctypes.byref(sink)):
+        raise ValueError("oracle: invalid basis")
+    return sink.value
 
 
 def eri_full(sys):

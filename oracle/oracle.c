@@ -496,6 +496,33 @@ int oracle_eri_quartet(OB_ARGS, int sa, int sb, int sc, int sd, int method, doub
     return 0;
 }
 
+/* nq listed shell quartets q[4k..4k+3], each evaluated as oracle_eri_quartet
+ * does (MMD), OpenMP over the list; the sum of |(ab|cd)| over every integral is
+ * returned in *sink.  Used to time the oracle on a sample of a workload's
+ * quartets; adds no arithmetic of its own. */
+int oracle_eri_list(OB_ARGS, int nq, const int *q, int nthreads, double *sink)
+{
+    obasis ob;
+    if (ob_init(&ob, OB_PASS)) return -1;
+    if (nthreads > 0) omp_set_num_threads(nthreads);
+    double total = 0.0;
+#pragma omp parallel reduction(+ : total)
+    {
+        double *buf = malloc(sizeof(double) * 10000);
+#pragma omp for schedule(dynamic, 4)
+        for (int k = 0; k < nq; ++k) {
+            const int *t = q + 4 * k;
+            eri_scaled(&ob, 0, t[0], t[1], t[2], t[3], buf);
+            const int n = ncart(sh_l[t[0]]) * ncart(sh_l[t[1]]) * ncart(sh_l[t[2]]) * ncart(sh_l[t[3]]);
+            for (int i = 0; i < n; ++i) total += fabs(buf[i]);
+        }
+        free(buf);
+    }
+    *sink = total;
+    ob_free(&ob);
+    return 0;
+}
+
 /* full N^4 tensor (tiny systems only) */
 int oracle_eri_full(OB_ARGS, double *out)
 {

@@ -120,6 +120,7 @@ struct fk_ctx {
     std::map<int, ClassSched> sched;
     std::vector<double> oe_S, oe_T, oe_V;          // one-electron matrices of the current geometry and basis
     double dscreen_scale = 1.0;                   // per-quartet threshold = tau * this (builds from density changes)
+    unsigned long long *cnt_last = nullptr;       // counters of the last build
     // initial guesses
     std::vector<double> coef_in;                  // contraction coefficients as given
     std::map<std::vector<double>, std::vector<double>> sad_cache; // atomic density per (element, shells)
@@ -810,8 +811,6 @@ int fk_build_quartets(fk_ctx *c, const fk_screen_opts *o)
     }
     // 4. tiles per quartet class (P >= Q): bra blocks from class P, kets from class Q
     const int bra_block = opts.bra_block > 0 ? std::min(opts.bra_block, FK_MAX_BRA_BLOCK) : 8;
-    // precision split threshold on G_ab G_cd (|D| <= 2 for a closed-shell density)
-    const double tau_hi = opts.tau_fp32 > 0 ? 0.5 * opts.tau_fp32 : 0.0;
     c->tiles.clear();
     c->blocks.clear();
     c->blk_bra.clear();
@@ -828,8 +827,10 @@ int fk_build_quartets(fk_ctx *c, const fk_screen_opts *o)
             qc.P = P; qc.Q = Q;
             if (fk_kernels_class_info(P, Q, &qc.info))
                 return fail(c, FK_ERR_UNSUPPORTED, "quartet class (%d|%d) is not built into this library", P, Q);
-            // precision split (FP32 recurrences below tau_hi), not for f-f bra kernels
-            const bool split = tau_hi > 0 && qc.info.wave_per_quartet != 3;
+            // precision split: the class gets a second, FP32 launch over the same
+            // tiles (not for the f-f bra kernels, which are FP64 only); per bra
+            // and tile the kernels send the work to exactly one of the two
+            const bool split = opts.tau_fp32 > 0 && qc.info.wave_per_quartet != 3;
             // kets per tile: a full wave of kets for lane-per-quartet kernels, two
             // rounds of teams for team kernels, two kets for wave-per-quartet
             const int ts = std::max(1, qc.info.team_size);
@@ -842,12 +843,9 @@ int fk_build_quartets(fk_ctx *c, const fk_screen_opts *o)
             int max_bra_npp = 1;
             for (int p : LP) max_bra_npp = std::max(max_bra_npp, c->pr_npp[p]);
             qc.bra_slot = max_bra_npp * FK_NFLD;
-            QuartetClass qp[2] = {qc, qc};
-            std::vector<FkTile> tl[2];
-            for (int k = 0; k < 2; ++k) {
-                qp[k].prec = k;
-                qp[k].nquartet = 0; qp[k].nprim = 0; qp[k].prim_slots = 0;
-            }
+            qc.prec = 0;
+            qc.nquartet = 0; qc.nprim = 0; qc.prim_slots = 0;
+            std::vector<FkTile> tl;
             // bra blocks: the class's pairs ordered by (first shell, G descending),
             // cut into runs of at most bmax pairs with the same first shell
             const int bmax = std::max(1, std::min(sch.bb > 0 ? std::min(sch.bb, FK_MAX_BRA_BLOCK) : bra_block, qc.info.bra_block));
@@ -885,56 +883,53 @@ int fk_build_quartets(fk_ctx *c, const fk_screen_opts *o)
                     const auto &g = c->cls_groups[Q][gi];
                     if (c->sh_mol[c->pr_sa[LQ[g.first]]] != bmol) continue;  // kets of the bra's molecule only
                     const int gnpp = c->pr_npp[LQ[g.first]];
-                    // ket ranges [lo, hi) of the group for the FP64 and FP32 launches
-                    int hi64 = 0, lo32 = g.second - g.first, hi32 = 0;
+                    // ket range [0, hi) of the group: the union of the bras' prefixes
+                    int hi = 0;
                     for (size_t x = i0; x < i1; ++x) {
                         const int pb = ord[x], bra = LP[pb];
                         const double gb = c->pr_G[bra];
                         int cnt = opts.tau > 0 ? prefix(g.first, g.second, gb, opts.tau) : g.second - g.first;
                         if (P == Q) cnt = std::min(cnt, std::max(0, pb + 1 - g.first));
                         if (cnt <= 0) continue;
-                        const int c64 = split ? std::min(cnt, prefix(g.first, g.second, gb, tau_hi)) : cnt;
-                        hi64 = std::max(hi64, c64);
-                        if (c64 < cnt) {
-                            lo32 = std::min(lo32, c64);
-                            hi32 = std::max(hi32, cnt);
-                        }
-                        qp[0].nquartet += c64;
-                        qp[0].nprim += (int64_t)c64 * c->pr_npp[bra] * gnpp;
-                        qp[1].nquartet += cnt - c64;
-                        qp[1].nprim += (int64_t)(cnt - c64) * c->pr_npp[bra] * gnpp;
+                        hi = std::max(hi, cnt);
+                        qc.nquartet += cnt;
+                        qc.nprim += (int64_t)cnt * c->pr_npp[bra] * gnpp;
                     }
-                    const int rng[2][2] = {{0, hi64}, {lo32, hi32}};
-                    for (int k = 0; k < 2; ++k)
-                        for (int kk = rng[k][0]; kk < rng[k][1]; kk += tile_kets) {
-                            FkTile t;
-                            t.blk = blk;
-                            t.ket_begin = c->ket_off[Q] + g.first + kk;
-                            t.ket_count = std::min(tile_kets, rng[k][1] - kk);
-                            t.grp = (c->cls_group0[Q] + (int)gi) | ((P == Q) ? FK_TILE_SAME : 0);
-                            tl[k].push_back(t);
-                            // lane slots of the tile's primitive loops: rounds of
-                            // (quartets per wave) kets, 64 lanes each, for every bra
-                            const int64_t rounds = (t.ket_count + qpw - 1) / qpw;
-                            qp[k].prim_slots += rounds * 64 * nppsum * gnpp;
-                        }
+                    for (int kk = 0; kk < hi; kk += tile_kets) {
+                        FkTile t;
+                        t.blk = blk;
+                        t.ket_begin = c->ket_off[Q] + g.first + kk;
+                        t.ket_count = std::min(tile_kets, hi - kk);
+                        t.grp = (c->cls_group0[Q] + (int)gi) | ((P == Q) ? FK_TILE_SAME : 0);
+                        tl.push_back(t);
+                        // lane slots of the tile's primitive loops: rounds of
+                        // (quartets per wave) kets, 64 lanes each, for every bra
+                        const int64_t rounds = (t.ket_count + qpw - 1) / qpw;
+                        qc.prim_slots += rounds * 64 * nppsum * gnpp;
+                    }
                 }
                 i0 = i1;
             }
-            for (int k = 0; k < 2; ++k) {
-                if (tl[k].empty()) continue;
-                QuartetClass &q = qp[k];
-                // most expensive tiles first (bra primitives x ket primitives x kets)
-                auto cost = [&](const FkTile &t) {
-                    const FkGroup &gg = c->groups[t.grp & ~FK_TILE_SAME];
-                    return c->blk_nppsum[t.blk] * gg.npp * t.ket_count;
-                };
-                std::stable_sort(tl[k].begin(), tl[k].end(), [&](const FkTile &x, const FkTile &y) { return cost(x) > cost(y); });
-                q.tile_off = (int64_t)c->tiles.size();
-                q.ntile = (int64_t)tl[k].size();
-                c->tiles.insert(c->tiles.end(), tl[k].begin(), tl[k].end());
-                c->flops_schwarz += q.nprim * q.info.flops_prim + q.nquartet * q.info.flops_quartet;
-                c->nq_schwarz += q.nquartet;
+            if (tl.empty()) continue;
+            // most expensive tiles first (bra primitives x ket primitives x kets)
+            auto cost = [&](const FkTile &t) {
+                const FkGroup &gg = c->groups[t.grp & ~FK_TILE_SAME];
+                return c->blk_nppsum[t.blk] * gg.npp * t.ket_count;
+            };
+            std::stable_sort(tl.begin(), tl.end(), [&](const FkTile &x, const FkTile &y) { return cost(x) > cost(y); });
+            qc.tile_off = (int64_t)c->tiles.size();
+            qc.ntile = (int64_t)tl.size();
+            c->tiles.insert(c->tiles.end(), tl.begin(), tl.end());
+            c->flops_schwarz += qc.nprim * qc.info.flops_prim + qc.nquartet * qc.info.flops_quartet;
+            c->nq_schwarz += qc.nquartet;
+            for (int k = 0; k < (split ? 2 : 1); ++k) {
+                QuartetClass q = qc;
+                q.prec = k;
+                if (k == 1) {
+                    // the FP32 launch shares the tiles; the Schwarz counts and the
+                    // lane slots belong to the class once (the FP64 entry)
+                    q.nquartet = 0; q.nprim = 0; q.prim_slots = 0;
+                }
                 q.blocks_per_cu = 1;
                 if (dev) {
                     int nb = 0;
@@ -1003,11 +998,22 @@ int fk_molecule_layout(const fk_ctx *c, int *nbf, int64_t *offset)
     return FK_OK;
 }
 
-int fk_build_jk(fk_ctx *c, const double *D, double *J, double *K, unsigned flags, void *stream)
+}  // extern "C"
+
+namespace {
+
+// Device buffers one J/K build works in: the component-scaled density, the
+// shell-block maxima, ncopy copies of (X_J, X_K) xcopy doubles apart, and the
+// per-launch counters.
+struct JKBufs {
+    double *Ds, *Dsh, *X;
+    long long xcopy;
+    int ncopy;
+    unsigned long long *cnt;
+};
+
+int build_jk_impl(fk_ctx *c, const double *D, double *J, double *K, unsigned flags, void *stream, const JKBufs &b)
 {
-    if (!c) return FK_ERR_ARG;
-    if (c->device < 0) return fail(c, FK_ERR_STATE, "fk_build_jk: context has no device");
-    if (!c->have_quartets) return fail(c, FK_ERR_STATE, "fk_build_jk: call fk_build_quartets first");
     if ((flags & FK_J_ONLY) && (flags & FK_K_ONLY))
         return fail(c, FK_ERR_ARG, "fk_build_jk: FK_J_ONLY and FK_K_ONLY together");
     const int want = (flags & FK_J_ONLY) ? FK_WANT_J : ((flags & FK_K_ONLY) ? FK_WANT_K : FK_WANT_J | FK_WANT_K);
@@ -1036,10 +1042,10 @@ int fk_build_jk(fk_ctx *c, const double *D, double *J, double *K, unsigned flags
         Jd = J ? c->d_Jout.p : nullptr;
         Kd = K ? c->d_Kout.p : nullptr;
     }
-    if (fk_kernels_launch_prep(Dd, c->d_bf_scale.p, &ma, c->d_Ds.p, c->d_Dsh.p, st))
+    if (fk_kernels_launch_prep(Dd, c->d_bf_scale.p, &ma, b.Ds, b.Dsh, st))
         return fail(c, FK_ERR_HIP, "prep kernel launch failed");
-    if (fk_kernels_launch_fill(c->d_X.p, (long long)(2 * nn * FK_XCD_COPIES), st) ||
-        fk_kernels_launch_fill((double *)c->d_cnt.p, 2 * FK_MAX_QCLASS, st))
+    if (fk_kernels_launch_fill(b.X, (long long)(2 * nn * b.ncopy), st) ||
+        fk_kernels_launch_fill((double *)b.cnt, 2 * FK_MAX_QCLASS, st))
         return fail(c, FK_ERR_HIP, "fill kernel launch failed");
     c->timed = (flags & FK_TIME_CLASSES) != 0;
     if (c->timed)
@@ -1075,34 +1081,39 @@ int fk_build_jk(fk_ctx *c, const double *D, double *J, double *K, unsigned flags
         a.ppT = c->d_ppT.p;
         a.tiles = c->d_tiles.p + qc.tile_off;
         a.ntiles = (int)qc.ntile;
-        a.Dsh = c->d_Dsh.p;
-        a.Ds = c->d_Ds.p;
-        a.XJ = c->d_X.p;
-        a.XK = c->d_X.p + nn;
-        a.xcopy = (long long)(2 * nn);
+        a.Dsh = b.Dsh;
+        a.Ds = b.Ds;
+        a.XJ = b.X;
+        a.XK = b.X + nn;
+        // workgroups add into copy blockIdx mod FK_XCD_COPIES; one copy: all alias it
+        a.xcopy = b.ncopy > 1 ? b.xcopy : 0;
         a.dscreen = c->opts.density_screen && c->opts.tau > 0;
         a.want = want;
         a.tau = c->opts.tau * c->dscreen_scale;
         a.rys_tab = c->d_rys.p + rys_staged_offset(qc.info.nroot);
-        a.counters = c->d_cnt.p + 2 * i;
+        a.counters = b.cnt + 2 * i;
         a.bra_slot = qc.bra_slot;
         a.prec = qc.prec;
-        a.tau_hi = c->opts.tau_fp32 > 0 ? 0.5 * c->opts.tau_fp32 : 0.0;
+        // a class with an FP32 twin splits its work by the per-quartet bound
+        bool twin = false;
+        for (const auto &o : c->qclasses) twin = twin || (o.P == qc.P && o.Q == qc.Q && o.prec != qc.prec);
+        a.tau_fp32 = twin ? c->opts.tau_fp32 : 0.0;
         a.blocks = c->d_blocks.p;
         a.blk_bra = c->d_blk_bra.p;
         a.blk_pos = c->d_blk_pos.p;
         // Enough workgroups for the hardware to fill every CU to its register and
         // LDS limit; the persistent loop covers the rest.
-        const int64_t want = (qc.ntile + 3) / 4;
+        const int64_t wgs = (qc.ntile + 3) / 4;
         const int64_t cap = std::max<int64_t>(1, (int64_t)(qc.grid_frac * std::max(8, qc.blocks_per_cu) * std::max(c->ncu, 1)));
-        const int grid = (int)std::max<int64_t>(1, std::min(want, cap));
+        const int grid = (int)std::max<int64_t>(1, std::min(wgs, cap));
         if (fk_kernels_launch_jk(qc.P, qc.Q, &a, grid, st))
             return fail(c, FK_ERR_HIP, "J/K kernel launch failed for class (%d|%d)", qc.P, qc.Q);
         if (c->timed) HIPCHK(c, hipEventRecord(c->ev[2 * i + 1], st));
     }
-    if (fk_kernels_launch_finalize(c->d_X.p, c->d_X.p + nn, (long long)(2 * nn), c->d_bf_scale.p, &ma, Jd, Kd, st))
+    if (fk_kernels_launch_finalize(b.X, b.X + nn, b.xcopy, b.ncopy, c->d_bf_scale.p, &ma, Jd, Kd, st))
         return fail(c, FK_ERR_HIP, "finalize kernel launch failed");
     c->stats_pending = true;
+    c->cnt_last = b.cnt;
     if (!devp) {
         if (J) HIPCHK(c, hipMemcpyAsync(J, Jd, nn * sizeof(double), hipMemcpyDeviceToHost, st));
         if (K) HIPCHK(c, hipMemcpyAsync(K, Kd, nn * sizeof(double), hipMemcpyDeviceToHost, st));
@@ -1111,6 +1122,20 @@ int fk_build_jk(fk_ctx *c, const double *D, double *J, double *K, unsigned flags
         HIPCHK(c, hipStreamSynchronize(st));
     }
     return FK_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int fk_build_jk(fk_ctx *c, const double *D, double *J, double *K, unsigned flags, void *stream)
+{
+    if (!c) return FK_ERR_ARG;
+    if (c->device < 0) return fail(c, FK_ERR_STATE, "fk_build_jk: context has no device");
+    if (!c->have_quartets) return fail(c, FK_ERR_STATE, "fk_build_jk: call fk_build_quartets first");
+    const size_t nn = (size_t)c->mol_base[c->nmol];
+    const JKBufs b{c->d_Ds.p, c->d_Dsh.p, c->d_X.p, (long long)(2 * nn), FK_XCD_COPIES, c->d_cnt.p};
+    return build_jk_impl(c, D, J, K, flags, stream, b);
 }
 
 int fk_stats(fk_ctx *c, fk_stats_t *s)
@@ -1122,7 +1147,7 @@ int fk_stats(fk_ctx *c, fk_stats_t *s)
     if (c->device >= 0 && c->stats_pending) {
         hipSetDevice(c->device);
         HIPCHK(c, hipDeviceSynchronize());
-        HIPCHK(c, hipMemcpy(cnt.data(), c->d_cnt.p, cnt.size() * sizeof(unsigned long long), hipMemcpyDeviceToHost));
+        HIPCHK(c, hipMemcpy(cnt.data(), c->cnt_last, cnt.size() * sizeof(unsigned long long), hipMemcpyDeviceToHost));
     }
     s->nclass = (int)c->qclasses.size();
     for (size_t i = 0; i < c->qclasses.size(); ++i) {

@@ -91,8 +91,9 @@ struct FkJKArgs {
     unsigned long long *counters;  // [2]: contracted quartets, primitive quartets
     int bra_slot;            // doubles per wave for the staged bra primitive records
     int prec;                // 0: FP64 kernel, 1: FP32 kernel of the precision split
-    double tau_hi;           // precision split: the FP64 kernel takes quartets with
-                             // G_ab G_cd >= tau_hi, the FP32 kernel the others (0: no split)
+    double tau_fp32;         // precision split (0: none): per bra and tile, the FP32
+                             // launch takes the work when G_ab G_cd D_max < tau_fp32
+                             // for every quartet of the wave, the FP64 launch otherwise
 };
 
 // The accumulators X_J, X_K exist once per XCD (CDNA3/4 parts have 8 XCDs,
@@ -139,7 +140,7 @@ int fk_kernels_max_blocks(int P, int Q, int dyn_lds_bytes, int *blocks_per_cu);
 int fk_kernels_jk_lds_bytes(int P, int Q, int bra_slot);
 int fk_kernels_launch_prep(const double *D, const double *bf_scale, const FkMolArgs *m, double *Ds, double *Dsh,
                            void *stream);
-int fk_kernels_launch_finalize(const double *XJ, const double *XK, long long xcopy, const double *bf_scale,
+int fk_kernels_launch_finalize(const double *XJ, const double *XK, long long xcopy, int ncopy, const double *bf_scale,
                                const FkMolArgs *m, double *J, double *K, void *stream);
 int fk_kernels_launch_fill(double *p, long long n, void *stream);
 int fk_kernels_debug_host(int P, int Q, const int *pair_ppoff, const int *pair_npp, const double *pair_AB,

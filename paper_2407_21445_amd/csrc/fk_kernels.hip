@@ -72,15 +72,6 @@ __device__ __forceinline__ fk::PrimPair load_pp(const double *__restrict pp, int
     return p;
 }
 
-// Precision split: the FP64 kernel takes quartets with Schwarz product at or
-// above tau_hi (all of them when tau_hi <= 0), the FP32 kernel the rest.
-template <typename R>
-__device__ __forceinline__ bool prec_side(double gg, double tau_hi)
-{
-    if constexpr (sizeof(R) == sizeof(double)) return tau_hi <= 0 || gg >= tau_hi;
-    else return gg < tau_hi;
-}
-
 __device__ __forceinline__ double wave_sum(double v)
 {
 #pragma unroll
@@ -112,6 +103,29 @@ __device__ __forceinline__ double dmax_want(const double *__restrict Dsh, int ns
         m = fmax(m, fmax(m2, m3));
     }
     return m;
+}
+
+// Screening of the (bra, ket) combinations of a wave and the precision split.
+// A lane's quartet survives the Schwarz bound, the same-class triangle and the
+// density screen G_ab G_cd D_max >= tau.  With the split (tau_fp32 > 0) the
+// wave's surviving quartets of this bra go to the FP32 launch when every one
+// has G_ab G_cd D_max < tau_fp32, else to the FP64 launch: both launches reach
+// the same decision, so each quartet is computed once.  Returns the lanes this
+// launch computes.
+template <typename R>
+__device__ __forceinline__ bool screen_lane(const FkJKArgs &a, bool cand, double gg, const double *__restrict Dsh,
+                                            int ns, int sa, int sb, int sc, int sd)
+{
+    bool active = cand && (a.tau <= 0 || gg >= a.tau);
+    double dm = 0.0;
+    if (a.dscreen || a.tau_fp32 > 0) dm = dmax_want(Dsh, ns, sa, sb, sc, sd, a.want);
+    if (a.dscreen) active = active && gg * dm >= a.tau;
+    if (a.tau_fp32 > 0) {
+        const bool need64 = __ballot(active && gg * dm >= a.tau_fp32) != 0ull;
+        const bool mine = (sizeof(R) == sizeof(double)) ? need64 : !need64;
+        active = active && mine;
+    }
+    return active;
 }
 
 // Ket pair data at a list position (consecutive lanes: consecutive positions).
@@ -296,9 +310,7 @@ __global__ void __launch_bounds__(FK_BLOCK, (LpqMinBlocks<LA, LB, LC, LD>::value
             const int sb = B.sb;
             // Schwarz bound, same-class triangle (ket position <= bra position)
             // and density screen for this (bra, ket)
-            bool active = inrange && (!same || pos <= bpos) && (a.tau <= 0 || B.G * Kt.G >= a.tau) &&
-                          prec_side<R>(B.G * Kt.G, a.tau_hi);
-            if (a.dscreen) active = active && (B.G * Kt.G * dmax_want(Dsh, ns, sa, sb, sc, sd, a.want) >= a.tau);
+            const bool active = screen_lane<R>(a, inrange && (!same || pos <= bpos), B.G * Kt.G, Dsh, ns, sa, sb, sc, sd);
             const unsigned long long mask = __ballot(active);
             if (mask == 0ull) continue;
             const int nact = __popcll(mask);
@@ -564,9 +576,7 @@ __global__ void __launch_bounds__(FK_BLOCK, (TpqMinBlocks<LA, LB, LC, LD>::value
                 const int bpos = a.blk_pos[blk.first + jb];
                 const BraInfo B = load_bra(a, bra);
                 const int sb = B.sb;
-                bool active = tin && (!same || pos <= bpos) && (a.tau <= 0 || B.G * Kt.G >= a.tau) &&
-                              prec_side<R>(B.G * Kt.G, a.tau_hi);
-                if (a.dscreen) active = active && (B.G * Kt.G * dmax_want(Dsh, ns, sa, sb, sc, sd, a.want) >= a.tau);
+                const bool active = screen_lane<R>(a, tin && (!same || pos <= bpos), B.G * Kt.G, Dsh, ns, sa, sb, sc, sd);
                 const unsigned long long mask = __ballot(active);
                 if (mask == 0ull) continue;
                 const int nact = __popcll(mask) / TS;
@@ -1182,7 +1192,7 @@ __global__ void k_prep_dsh(const double *__restrict D, FkMolArgs m, double *__re
 }
 
 // J = s_r s_c (X_J + X_J^T), K likewise, within each molecule's block
-__global__ void k_finalize(const double *__restrict XJ, const double *__restrict XK, long long xcopy,
+__global__ void k_finalize(const double *__restrict XJ, const double *__restrict XK, long long xcopy, int ncopy,
                            const double *__restrict s, FkMolArgs m, double *__restrict J, double *__restrict K)
 {
     const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -1197,7 +1207,7 @@ __global__ void k_finalize(const double *__restrict XJ, const double *__restrict
     if (J) {
         double sj = 0.0;
 #pragma unroll
-        for (int x = 0; x < FK_XCD_COPIES; ++x) {
+        for (int x = 0; x < ncopy; ++x) {
             const long long o = (long long)x * xcopy;
             sj += XJ[o + i] + XJ[o + t];
         }
@@ -1206,7 +1216,7 @@ __global__ void k_finalize(const double *__restrict XJ, const double *__restrict
     if (K) {
         double sk = 0.0;
 #pragma unroll
-        for (int x = 0; x < FK_XCD_COPIES; ++x) {
+        for (int x = 0; x < ncopy; ++x) {
             const long long o = (long long)x * xcopy;
             sk += XK[o + i] + XK[o + t];
         }
@@ -1300,12 +1310,12 @@ int fk_kernels_launch_prep(const double *D, const double *bf_scale, const FkMolA
     return hipGetLastError() == hipSuccess ? 0 : -3;
 }
 
-int fk_kernels_launch_finalize(const double *XJ, const double *XK, long long xcopy, const double *bf_scale,
+int fk_kernels_launch_finalize(const double *XJ, const double *XK, long long xcopy, int ncopy, const double *bf_scale,
                                const FkMolArgs *m, double *J, double *K, void *stream)
 {
     if (m->nmat > 0)
         hipLaunchKernelGGL(k_finalize, dim3((unsigned)((m->nmat + 255) / 256)), dim3(256), 0, (hipStream_t)stream, XJ,
-                           XK, xcopy, bf_scale, *m, J, K);
+                           XK, xcopy, ncopy, bf_scale, *m, J, K);
     return hipGetLastError() == hipSuccess ? 0 : -3;
 }
 

@@ -181,6 +181,33 @@ def test_jk_water64_sampled_blocks(fk, torch, c3, tau, tau_prim, tol):
     c.close()
 
 
+def test_precision_split_water64(fk, torch, c3):
+    """(H2O)64 cc-pVDZ-type with the precision split at tau_fp32 = 1e-5 (the
+    mixed-precision configuration, tau = 1e-10, primitive pairs pruned at
+    1e-12): sampled J/K blocks against the oracle's literal sums within 1e-7,
+    and the one-build energy functional 1/2 D.J - 1/4 D.K within 1e-6 Eh of
+    the FP64 build on the same lists (the mixed-precision gate)."""
+    s, D, jp, kp, Jb, Kb = c3
+    J, K, c = _gpu_jk(fk, torch, s, D, tau=1e-10, tau_prim=1e-12, tau_fp32=1e-5)
+    st = c.stats()
+    n32 = sum(x["quartets"] for x in st["classes"] if x["precision"] == 32)
+    assert n32 > 0
+    J64, K64, c64 = _gpu_jk(fk, torch, s, D, tau=1e-10, tau_prim=1e-12)
+    # every quartet computed once: the split launches together compute the FP64 build's quartets
+    assert st["quartets"] == c64.stats()["quartets"]
+    dE = 0.5 * np.sum(D * (J - J64)) - 0.25 * np.sum(D * (K - K64))
+    print(f"water64 mixed: FP32 share {n32 / st['quartets']:.3f}, dE {dE:.2e}, "
+          f"max|dJ| {np.max(np.abs(J - J64)):.2e}, max|dK| {np.max(np.abs(K - K64)):.2e}", flush=True)
+    assert abs(dE) <= 1e-6
+    off = oracle.bf_offsets(s)
+    for (a, b), blk in zip(jp, Jb):
+        assert np.max(np.abs(J[off[a]:off[a + 1], off[b]:off[b + 1]] - blk)) <= 1e-7, (a, b)
+    for (a, cc), blk in zip(kp, Kb):
+        assert np.max(np.abs(K[off[a]:off[a + 1], off[cc]:off[cc + 1]] - blk)) <= 1e-7, (a, cc)
+    c.close()
+    c64.close()
+
+
 def test_edge_cases(fk, torch):
     # one atom, one s shell: a single tile holding a single quartet
     he = wl.flatten({"Z": np.array([2], dtype=np.int32), "xyz": np.zeros((1, 3)), "charge": 0, "name": "He"},

@@ -157,22 +157,33 @@ def test_argument_validation():
     assert e.value.code == fk.FK_ERR_STATE
 
 
-@pytest.mark.parametrize("name,tau,tau_prim", [
-    ("spdf", 0.0, 0.0), ("water4", 1e-10, 1e-12),
-    ("c20h42", 0.0, 0.0), ("c20h42", 1e-10, 0.0), ("c20h42", 1e-10, 1e-12)])
-def test_kernel_indices_in_bounds(name, tau, tau_prim):
+@pytest.mark.parametrize("name,tau,tau_prim,tau_fp32", [
+    ("spdf", 0.0, 0.0, 0.0), ("water4", 1e-10, 1e-12, 0.0),
+    ("c20h42", 0.0, 0.0, 0.0), ("c20h42", 1e-10, 0.0, 0.0), ("c20h42", 1e-10, 1e-12, 0.0),
+    ("water64", 1e-10, 1e-12, 1e-5), ("organic2", 1e-10, 1e-12, 0.0)])
+def test_kernel_indices_in_bounds(name, tau, tau_prim, tau_fp32):
     """Every address the J/K kernels form from the tile, list, group and pair
-    tables (positions, transposed ket records, bra records and their LDS slot,
-    density, shell-block maxima, Fock accumulators) lies inside its array, for
-    the test systems and the full-size benchmark configurations."""
+    tables (positions, transposed ket records, bra records, density,
+    shell-block maxima, Fock accumulators) lies inside its array, for the test
+    systems and the full-size benchmark configurations: C20H42, (H2O)64 with
+    the precision split (its FP64 and FP32 launches walk the same tiles), and
+    the first two molecules of the organic batch (f shells, molecule
+    offsets)."""
     if name == "spdf":
         s = _rand_sys(33, lmax=3, natom=3, kmax=2)
         s["charge"] = 1
     elif name == "water4":
         s = wl.water4_sto3g()
+    elif name == "water64":
+        s = wl.water64_ccpvdz()
+    elif name == "organic2":
+        s = wl.organic_batch(2)
     else:
         s = wl.c20h42_631gs()
-    c = fk.FockJK(device=-1).set_system(s).build_quartets(tau=tau, tau_prim=tau_prim)
+    c = fk.FockJK(device=-1).set_system(s)
+    if name == "organic2":
+        c.set_molecules(s["atom_mol"])
+    c.build_quartets(tau=tau, tau_prim=tau_prim, tau_fp32=tau_fp32)
     c.check_indices()
     assert c.info()["ntile"] > 0
 
@@ -187,9 +198,10 @@ def test_scf_needs_device():
 
 @pytest.mark.parametrize("tau_fp32", [1e-5, 1e-3])
 def test_precision_split_lists(tau_fp32):
-    """The FP64 and FP32 launches partition the Schwarz quartets: the total
-    unique quartet count is unchanged, both precisions get work, and every
-    kernel address stays in bounds."""
+    """The split adds an FP32 launch per class (but f-f bras) over the same
+    tiles: the Schwarz quartet count is unchanged and every kernel address
+    stays in bounds (which launch computes a quartet is decided per build
+    from the density)."""
     s = wl.water4_sto3g()
     ref = fk.FockJK(device=-1).set_system(s).build_quartets(tau=0.0)
     c = fk.FockJK(device=-1).set_system(s).build_quartets(tau=0.0, tau_fp32=tau_fp32)
