@@ -189,6 +189,27 @@ int fk_info(const fk_ctx *ctx, fk_info_t *info);
  * density screening is off; callers pass symmetric D. */
 int fk_build_jk(fk_ctx *ctx, const double *D, double *J, double *K, unsigned flags, void *stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the build of
+ * fk_build_jk that allocates nothing.  Its working buffers (scaled density,
+ * shell-block maxima, one copy of the Coulomb and exchange accumulators,
+ * counters) live in a fixed device array that each GPU the library runs on
+ * holds for the life of the process: 3 FK_NOALLOC_MAX_NMAT + FK_NOALLOC_MAX_NSHMAT
+ * + 2 FK_MAX_QCLASS doubles (about 52 MB).  Limits: the context's matrices
+ * hold at most FK_NOALLOC_MAX_NMAT elements in all (one molecule: nbf <= 1448)
+ * and its shell blocks at most FK_NOALLOC_MAX_NSHMAT (nshell <= 512); larger
+ * contexts get FK_ERR_ARG (use fk_build_jk).  flags must contain
+ * FK_DEVICE_PTRS (D, J, K device arrays of the caller) and may contain
+ * FK_SYNC, FK_J_ONLY or FK_K_ONLY; FK_TIME_CLASSES is FK_ERR_ARG.  The array
+ * is shared by every context on a GPU and keeps the last call's contents (the
+ * call clears what must start at zero): calls that overlap on one GPU, on any
+ * streams, race and must be ordered by the caller.  Results equal
+ * fk_build_jk's up to the order of the accumulation; fk_stats reports this
+ * call when it was the last build. */
+#define FK_NOALLOC_MAX_NMAT (1 << 21)
+#define FK_NOALLOC_MAX_NSHMAT (1 << 18)
+int fk_build_jk_noalloc(fk_ctx *ctx, const double *D, double *J, double *K, unsigned flags, void *stream);
+
 /* Statistics of the last fk_build_jk (waits for it to finish). */
 int fk_stats(fk_ctx *ctx, fk_stats_t *stats);
 

@@ -103,6 +103,7 @@ _sig = {
     "fk_build_quartets": ([_P, ctypes.POINTER(ScreenOpts)], _I),
     "fk_info": ([_P, ctypes.POINTER(Info)], _I),
     "fk_build_jk": ([_P, _P, _P, _P, _U, _P], _I),
+    "fk_build_jk_noalloc": ([_P, _P, _P, _P, _U, _P], _I),
     "fk_stats": ([_P, ctypes.POINTER(Stats)], _I),
     "fk_one_electron": ([_P, _P, _P, _P, _P], _I),
     "fk_run_scf": ([_P, ctypes.POINTER(ScfOpts), ctypes.POINTER(ScfResult), _P], _I),
@@ -270,6 +271,20 @@ class FockJK:
                                      ctypes.c_void_p(J.data_ptr() if J is not None else None),
                                      ctypes.c_void_p(K.data_ptr() if K is not None else None), flags,
                                      ctypes.c_void_p(st.cuda_stream)))
+        return J, K
+
+    def build_jk_noalloc(self, D, J, K, stream=None, sync=False, only=None):
+        """fk_build_jk_noalloc: the build in the library's fixed device scratch
+        array (no allocation).  D, J, K: contiguous float64 CUDA tensors of
+        the caller (J or K may be None with only="K" or "J")."""
+        import torch
+        oflag = {None: 0, "J": FK_J_ONLY, "K": FK_K_ONLY}[only]
+        st = stream if stream is not None else torch.cuda.current_stream(D.device)
+        flags = FK_DEVICE_PTRS | (FK_SYNC if sync else 0) | oflag
+        self._check(_lib.fk_build_jk_noalloc(self._ctx, ctypes.c_void_p(D.data_ptr()),
+                                             ctypes.c_void_p(J.data_ptr() if J is not None else None),
+                                             ctypes.c_void_p(K.data_ptr() if K is not None else None), flags,
+                                             ctypes.c_void_p(st.cuda_stream)))
         return J, K
 
     def build_progress(self):

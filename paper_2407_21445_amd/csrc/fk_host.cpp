@@ -13,6 +13,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <numeric>
 #include <string>
 #include <thread>
@@ -120,7 +121,8 @@ struct fk_ctx {
     std::map<int, ClassSched> sched;
     std::vector<double> oe_S, oe_T, oe_V;          // one-electron matrices of the current geometry and basis
     double dscreen_scale = 1.0;                   // per-quartet threshold = tau * this (builds from density changes)
-    unsigned long long *cnt_last = nullptr;       // counters of the last build
+    unsigned long long *cnt_last = nullptr;       // counters of the last build (context's or scratch)
+    double *scratch = nullptr;                    // device address of this device's scratch array
     // initial guesses
     std::vector<double> coef_in;                  // contraction coefficients as given
     std::map<std::vector<double>, std::vector<double>> sad_cache; // atomic density per (element, shells)
@@ -523,6 +525,40 @@ int upload_pairs(fk_ctx *c)
 
 }  // namespace
 
+// ---------------------------------------------------- build without allocation
+// The working buffers of fk_build_jk_noalloc: one file-scope device array, of
+// which each GPU holds its own copy for the life of the process.  Host code
+// never passes `scratch` itself to a kernel (in host code the name denotes a
+// host-side stand-in); it uses the device address hipGetSymbolAddress returns,
+// taken once per device, with that device current, when the first context on
+// it is created, and kept per device (contexts copy it to fk_ctx::scratch).
+// Layout: D scaled [NMAT], X_J and X_K [2 NMAT], D_sh [NSHMAT], counters
+// [2 FK_MAX_QCLASS] (64-bit, the size of a double).
+#define FK_SCRATCH_DOUBLES (3 * (size_t)FK_NOALLOC_MAX_NMAT + (size_t)FK_NOALLOC_MAX_NSHMAT + 2 * FK_MAX_QCLASS)
+static __device__ __align__(256) double scratch[FK_SCRATCH_DOUBLES];
+
+namespace {
+constexpr int kMaxDevices = 64;
+double *g_scratch[kMaxDevices] = {};
+std::mutex g_scratch_mutex;
+
+// device address of the calling thread's current device's copy of `scratch`
+int scratch_address(fk_ctx *c)
+{
+    if (c->device >= kMaxDevices) return fail(c, FK_ERR_UNSUPPORTED, "device ordinal %d too large", c->device);
+    std::lock_guard<std::mutex> lock(g_scratch_mutex);
+    if (!g_scratch[c->device]) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p)
+            return fail(c, FK_ERR_HIP, "scratch array: hipGetSymbolAddress failed (%s)", hipGetErrorString(e));
+        g_scratch[c->device] = (double *)p;
+    }
+    c->scratch = g_scratch[c->device];
+    return FK_OK;
+}
+}  // namespace
+
 extern "C" {
 
 // failure message of the last fk_create on this thread (there is no context yet)
@@ -557,6 +593,12 @@ int fk_create(fk_ctx **out, int device)
             g_create_err = c->err;
             delete c;
             return FK_ERR_OOM;
+        }
+        if (scratch_address(c)) {
+            g_create_err = c->err;
+            free_device(c);
+            delete c;
+            return FK_ERR_HIP;
         }
     }
     *out = c;
@@ -1135,6 +1177,25 @@ int fk_build_jk(fk_ctx *c, const double *D, double *J, double *K, unsigned flags
     if (!c->have_quartets) return fail(c, FK_ERR_STATE, "fk_build_jk: call fk_build_quartets first");
     const size_t nn = (size_t)c->mol_base[c->nmol];
     const JKBufs b{c->d_Ds.p, c->d_Dsh.p, c->d_X.p, (long long)(2 * nn), FK_XCD_COPIES, c->d_cnt.p};
+    return build_jk_impl(c, D, J, K, flags, stream, b);
+}
+
+int fk_build_jk_noalloc(fk_ctx *c, const double *D, double *J, double *K, unsigned flags, void *stream)
+{
+    if (!c) return FK_ERR_ARG;
+    if (c->device < 0) return fail(c, FK_ERR_STATE, "fk_build_jk_noalloc: context has no device");
+    if (!c->have_quartets) return fail(c, FK_ERR_STATE, "fk_build_jk_noalloc: call fk_build_quartets first");
+    if (!(flags & FK_DEVICE_PTRS) || (flags & FK_TIME_CLASSES))
+        return fail(c, FK_ERR_ARG, "fk_build_jk_noalloc: needs FK_DEVICE_PTRS and takes no FK_TIME_CLASSES");
+    const long long nn = c->mol_base[c->nmol], nsh = c->mol_shbase[c->nmol];
+    if (nn > FK_NOALLOC_MAX_NMAT || nsh > FK_NOALLOC_MAX_NSHMAT)
+        return fail(c, FK_ERR_ARG,
+                    "fk_build_jk_noalloc: %lld matrix elements and %lld shell-block elements exceed the "
+                    "scratch limits (%d and %d); use fk_build_jk", nn, nsh, FK_NOALLOC_MAX_NMAT, FK_NOALLOC_MAX_NSHMAT);
+    if (!c->scratch) return fail(c, FK_ERR_STATE, "fk_build_jk_noalloc: no scratch address for this device");
+    double *base = c->scratch;
+    const JKBufs b{base, base + 3 * (size_t)FK_NOALLOC_MAX_NMAT, base + FK_NOALLOC_MAX_NMAT, 0, 1,
+                   (unsigned long long *)(base + 3 * (size_t)FK_NOALLOC_MAX_NMAT + FK_NOALLOC_MAX_NSHMAT)};
     return build_jk_impl(c, D, J, K, flags, stream, b);
 }
 
