@@ -79,7 +79,74 @@ __device__ __forceinline__ double wave_sum(double v)
     return v;
 }
 
+__device__ __forceinline__ void wave_sync_lds()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 __device__ __forceinline__ void atomic_add(double *p, double v) { unsafeAtomicAdd(p, v); }
+
+// FP64 atomic adds to device memory are served one 32-byte sector request per
+// lane unless lanes of the same instruction address the same sector (measured
+// on MI355X: 2.4e10 scattered adds/s, 9.4e10 when four lanes share a sector).
+// flush_block therefore issues a lane's R x C block of values, which lies in
+// rows row..row+R-1 and the C consecutive columns col..col+C-1 of X (stride n),
+// with G = C rounded up to a power of two consecutive lanes adding the C
+// doubles of one row of one lane: 64/G lanes' rows per instruction instead of
+// one double per lane.  The values pass through the wave's LDS stage
+// ([R C][64] doubles); zeros (inactive lanes, absent contributions) are not
+// added.  All 64 lanes must call it (wave-uniform control flow).
+template <int R, int C>
+__device__ __forceinline__ void flush_block(double *X, int n, int row, int col, const double *v, double *stage,
+                                            int lane)
+{
+    if constexpr (C == 1) {
+#pragma unroll
+        for (int r = 0; r < R; ++r)
+            if (v[r] != 0.0) atomic_add(&X[(size_t)(row + r) * n + col], v[r]);
+    } else {
+        constexpr int G = C <= 2 ? 2 : (C <= 4 ? 4 : (C <= 8 ? 8 : 16));
+        constexpr int OWN = 64 / G;
+        wave_sync_lds();
+#pragma unroll
+        for (int x = 0; x < R * C; ++x) stage[x * 64 + lane] = v[x];
+        wave_sync_lds();
+        const int q = lane % G, sub = lane / G;
+#pragma unroll
+        for (int t = 0; t < G; ++t) {
+            const int k = t * OWN + sub;
+            const int rk = __shfl(row, k, 64), ck = __shfl(col, k, 64);
+            if (q < C) {
+#pragma unroll
+                for (int r = 0; r < R; ++r) {
+                    const double val = stage[(r * C + q) * 64 + k];
+                    if (val != 0.0) atomic_add(&X[(size_t)(rk + r) * n + ck + q], val);
+                }
+            }
+        }
+    }
+}
+
+// Adds the block B[i][j] (i < NI components of shell row_i, j < NJ of shell
+// col_j, per lane) to X[oi + i][oj + j], or -- when the accumulator is later
+// symmetrised and NI > NJ -- to X[oj + j][oi + i], whichever puts the larger
+// component count in the contiguous dimension.
+template <int NI, int NJ>
+__device__ __forceinline__ void flush_sym(double *X, int n, int oi, int oj, const double *B, double *stage, int lane)
+{
+    if constexpr (NJ >= NI) {
+        flush_block<NI, NJ>(X, n, oi, oj, B, stage, lane);
+    } else {
+        double T[NI * NJ];
+#pragma unroll
+        for (int i = 0; i < NI; ++i)
+#pragma unroll
+            for (int j = 0; j < NJ; ++j) T[j * NI + i] = B[i * NJ + j];
+        flush_block<NJ, NI>(X, n, oj, oi, T, stage, lane);
+    }
+}
 
 template <int NR>
 __device__ __forceinline__ void load_table(double *s_tab, const double *__restrict g)
@@ -177,13 +244,6 @@ __device__ __forceinline__ BraInfo load_bra(const FkJKArgs &a, int bra)
     return b;
 }
 
-__device__ __forceinline__ void wave_sync_lds()
-{
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
-
 // The bra's primitive records are the same for every lane of the wave: they
 // are read through the constant address space, which the compiler serves with
 // scalar loads into SGPRs (no LDS traffic and no VGPRs for them; the records
@@ -229,6 +289,14 @@ struct LpqMinBlocks {
     static constexpr int value = 1;
 };
 template <>
+struct LpqMinBlocks<0, 0, 0, 0> {
+    static constexpr int value = 4;
+};
+template <>
+struct LpqMinBlocks<2, 0, 0, 0> {
+    static constexpr int value = 2;
+};
+template <>
 struct LpqMinBlocks<1, 0, 1, 0> {
     static constexpr int value = 2;
 };
@@ -249,6 +317,17 @@ struct LpqMinBlocks<3, 0, 0, 0> {
     static constexpr int value = 2;
 };
 
+// Doubles per wave of the lane kernel's LDS stage for flush_block: the largest
+// block a lane flushes (K[b,c], K[b,d], K[a,c], K[a,d], J[c,d]) times 64.
+template <int LA, int LB, int LC, int LD>
+struct LpqStage {
+    using Q = fk::QClass<LA, LB, LC, LD>;
+    static constexpr int m1 = Q::NB * Q::NC > Q::NB * Q::ND ? Q::NB * Q::NC : Q::NB * Q::ND;
+    static constexpr int m2 = Q::NA * Q::NC > Q::NA * Q::ND ? Q::NA * Q::NC : Q::NA * Q::ND;
+    static constexpr int m3 = m1 > m2 ? m1 : m2;
+    static constexpr int value = 64 * (m3 > Q::NC * Q::ND ? m3 : Q::NC * Q::ND);
+};
+
 template <int LA, int LB, int LC, int LD, typename R = double>
 __global__ void __launch_bounds__(FK_BLOCK, (LpqMinBlocks<LA, LB, LC, LD>::value)) k_jk_lpq(FkJKArgs a)
 {
@@ -262,6 +341,7 @@ __global__ void __launch_bounds__(FK_BLOCK, (LpqMinBlocks<LA, LB, LC, LD>::value
 
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    double *s_stage = s_dyn + rys_lds_size(Q::NR) + wave * LpqStage<LA, LB, LC, LD>::value;
     const int nwt = gridDim.x * FK_WAVES;
     unsigned long long cq = 0, cp = 0;
 
@@ -368,6 +448,11 @@ __global__ void __launch_bounds__(FK_BLOCK, (LpqMinBlocks<LA, LB, LC, LD>::value
                         jcd[cd] += acc[ab * NC * ND + cd] * dab[ab];
                     }
             }
+            double kbc[NB * NC], kbd[NB * ND];
+#pragma unroll
+            for (int o = 0; o < NB * NC; ++o) kbc[o] = 0.0;
+#pragma unroll
+            for (int o = 0; o < NB * ND; ++o) kbd[o] = 0.0;
             if (active && wk) {
                 double dbc[NB * NC], dbd[NB * ND];
 #pragma unroll
@@ -401,7 +486,7 @@ __global__ void __launch_bounds__(FK_BLOCK, (LpqMinBlocks<LA, LB, LC, LD>::value
 #pragma unroll
                             for (int id = 0; id < ND; ++id)
                                 s += acc[((ia * NB + ib) * NC + ic) * ND + id] * Ds[(size_t)(oa + ia) * n + od + id];
-                        atomic_add(&XK[(size_t)(ob + ib) * n + oc + ic], s);
+                        kbc[ib * NC + ic] = s;
                     }
 #pragma unroll
                     for (int id = 0; id < ND; ++id) {
@@ -411,9 +496,13 @@ __global__ void __launch_bounds__(FK_BLOCK, (LpqMinBlocks<LA, LB, LC, LD>::value
 #pragma unroll
                             for (int ic = 0; ic < NC; ++ic)
                                 s += acc[((ia * NB + ib) * NC + ic) * ND + id] * Ds[(size_t)(oa + ia) * n + oc + ic];
-                        atomic_add(&XK[(size_t)(ob + ib) * n + od + id], s);
+                        kbd[ib * ND + id] = s;
                     }
                 }
+            }
+            if (wk) {
+                flush_sym<NB, NC>(XK, n, ob, oc, kbc, s_stage, lane);
+                flush_sym<NB, ND>(XK, n, ob, od, kbd, s_stage, lane);
             }
             // all lanes (active or not) take part in the wave reduction of X_J[a, b]
             if (wj) {
@@ -424,21 +513,17 @@ __global__ void __launch_bounds__(FK_BLOCK, (LpqMinBlocks<LA, LB, LC, LD>::value
                 }
             }
         }
-        if (any && wk) {
-#pragma unroll
-            for (int ia = 0; ia < NA; ++ia) {
-#pragma unroll
-                for (int ic = 0; ic < NC; ++ic) atomic_add(&XK[(size_t)(oa + ia) * n + oc + ic], kac[ia * NC + ic]);
-#pragma unroll
-                for (int id = 0; id < ND; ++id) atomic_add(&XK[(size_t)(oa + ia) * n + od + id], kad[ia * ND + id]);
+        // block sums: a lane without work holds zeros, which are not added
+        if (__ballot(any) != 0ull) {
+            if (wk) {
+                flush_sym<NA, NC>(XK, n, oa, oc, kac, s_stage, lane);
+                flush_sym<NA, ND>(XK, n, oa, od, kad, s_stage, lane);
             }
-        }
-        if (any && wj) {
+            if (wj) {
 #pragma unroll
-            for (int ic = 0; ic < NC; ++ic)
-#pragma unroll
-                for (int id = 0; id < ND; ++id)
-                    atomic_add(&XJ[(size_t)(oc + ic) * n + od + id], 2.0 * jcd[ic * ND + id]);
+                for (int o = 0; o < NC * ND; ++o) jcd[o] *= 2.0;
+                flush_sym<NC, ND>(XJ, n, oc, od, jcd, s_stage, lane);
+            }
         }
     }
     if (lane == 0 && cq) {
@@ -974,6 +1059,7 @@ struct Disp {
         (void)bra_slot;
         using C = fk::QClass<LA, LB, LC, LD>;
         int extra = 0;
+        if constexpr (KIND == 0) extra = LpqStage<LA, LB, LC, LD>::value;
         if constexpr (KIND == 1 || KIND == 2) extra = TeamShape<LA, LB, LC, LD, KIND>::RED;
         return (int)sizeof(double) * (rys_lds_size(C::NR) + FK_WAVES * extra);
     }
