@@ -333,16 +333,30 @@ def _cname(c):
 
 
 def _print_classes(cls_ms, st):
-    print(f"{'class':>10} {'prec':>4} {'ms':>8} {'share':>6} {'quartets':>11} {'prims':>13} {'GFLOP':>9} "
+    print(f"{'class':>10} {'prec':>4} {'eng':>4} {'ms':>8} {'share':>6} {'quartets':>11} {'prims':>13} {'GFLOP':>9} "
           f"{'TFLOP/s':>8} {'frac':>6}", file=sys.stderr)
     for k in np.argsort(-cls_ms):
         cc = st["classes"][k]
         f = cc["prim_quartets"] * cc["flops_per_prim"] + cc["quartets"] * cc["flops_per_quartet"]
         tf = f / (cls_ms[k] * 1e-3) / 1e12 if cls_ms[k] > 0 else 0.0
         peak = PEAK_FP32_VALU if cc["precision"] == 32 else PEAK_FP64_VALU
-        print(f"{_cname(cc):>10} {cc['precision']:>4} {cls_ms[k]:8.3f} {cls_ms[k] / cls_ms.sum():6.3f} "
+        print(f"{_cname(cc):>10} {cc['precision']:>4} {('rys', 'hgp')[cc['engine']]:>4} {cls_ms[k]:8.3f} {cls_ms[k] / cls_ms.sum():6.3f} "
               f"{cc['quartets']:11d} {cc['prim_quartets']:13d} {f / 1e9:9.2f} {tf:8.3f} {tf / peak:6.3f}",
               file=sys.stderr)
+
+
+def _hgp_everywhere(fk, c):
+    """The HGP engine for every class it is built for (the others keep Rys)."""
+    for la in range(4):
+        for lb in range(la + 1):
+            for lc in range(4):
+                for ld in range(lc + 1):
+                    if (la, lb) >= (lc, ld):
+                        try:
+                            c.set_class_engine(la, lb, lc, ld, "hgp")
+                        except fk.FockJKError as e:
+                            if e.code != fk.FK_ERR_UNSUPPORTED:
+                                raise
 
 
 def _tune(ctx, Dd, stream):
@@ -381,6 +395,8 @@ def bench_single(args, torch, fk):
             cls, sch = tuple(int(x) for x in v[:4]), (int(v[4]), int(v[5]), float(v[6]))
             c.set_class_schedule(*cls, *sch)
             pinned[cls] = list(sch)
+        if args.engine == "hgp":
+            _hgp_everywhere(fk, c)
         return c.build_quartets(tau=args.tau, tau_prim=args.tau_prim, tau_fp32=tau_fp32)
 
     ctx = make(0.0)
@@ -417,11 +433,13 @@ def bench_single(args, torch, fk):
         "quartets_per_s": st["quartets"] / (ms * 1e-3),
         "prim_quartets_per_s": st["prim_quartets"] / (ms * 1e-3),
         "quartets_per_build": st["quartets"], "schwarz_quartets": info["nquartet_schwarz"],
+        "hgp_launches": int(sum(1 for x in st["classes"] if x["engine"] == fk.ENGINE_HGP)),
         "flops_per_build": st["flops_total"], "tflops_build": st["flops_total"] / (ms * 1e-3) / 1e12,
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP64_VALU, "unit": "TFLOP/s",
                      "frac": achieved / PEAK_FP64_VALU,
                      "traffic": _traffic(f"J/K class {_cname(c)}", args.workload, sched),
                      "kernel": f"J/K class {_cname(c)}", "kernel_ms": float(cls_ms[i]), "schedule": sched,
+                     "engine": ("rys", "hgp")[c["engine"]],
                      "class_share": float(cls_ms[i] / cls_ms.sum()),
                      "flops_per_launch": cflops, "quartets_per_launch": c["quartets"],
                      "prim_quartets_per_launch": c["prim_quartets"]},
@@ -529,6 +547,9 @@ def main():
     ap.add_argument("--schedule", action="append", default=[], metavar="LA,LB,LC,LD,BB,KT,GF",
                     help="fix a class schedule (bra block, kets per tile, grid fraction) before the lists "
                          "are built; with --no-autotune it is the one timed")
+    ap.add_argument("--engine", choices=("rys", "hgp"), default="rys",
+                    help="integral engine before tuning: hgp selects it for every class it is built for "
+                         "(the autotuner may still switch a class)")
     ap.add_argument("--no-scf", action="store_true", help="skip the SCF runs reported beside the build rate")
     ap.add_argument("--no-extra", action="store_true", help="skip the C20H42 reference line")
     ap.add_argument("--no-autotune", dest="autotune", action="store_false",

@@ -132,6 +132,7 @@ typedef struct {
                                              per tile, rounds x 64 lanes x bra x ket primitive
                                              pairs.  prim_quartets * team_size / prim_slots is
                                              the lane utilisation of the primitive loops */
+    int     engine[FK_MAX_QCLASS];        /* FK_ENGINE_RYS or FK_ENGINE_HGP */
 } fk_stats_t;
 
 /* ---- context ---------------------------------------------------------- */
@@ -233,12 +234,28 @@ int fk_build_progress(fk_ctx *ctx, int *done, int *total);
 int fk_set_class_schedule(fk_ctx *ctx, int la, int lb, int lc, int ld, int bra_block, int kets_per_tile,
                           double grid_fraction);
 
+/* Integral engine of a quartet class (a per-class schedule choice like the
+ * ones above, with the same lifetime).  FK_ENGINE_RYS: Rys quadrature over
+ * the 2D integrals, built for every class.  FK_ENGINE_HGP: the Obara-Saika
+ * vertical recurrences per primitive quartet, contracted, then the
+ * horizontal recurrences on the contracted integrals (paper: "HGP Recursive
+ * Scheme", the vrr and hrr equations; the early contraction its "Optimised
+ * GPU Implementation" builds on), with the Boys function values F_m(T) taken
+ * as moments of the same Rys rule; built for the
+ * lane-per-quartet classes up to L = la+lb+lc+ld = 4 (fk_stats reports the
+ * choice per launch; FK_ERR_UNSUPPORTED for other classes).  Both engines
+ * give the same integrals up to rounding. */
+#define FK_ENGINE_RYS 0
+#define FK_ENGINE_HGP 1
+int fk_set_class_engine(fk_ctx *ctx, int la, int lb, int lc, int ld, int engine);
+
 typedef struct {
     int    nclass;                      /* class launches after tuning (as fk_stats) */
     int    la[FK_MAX_QCLASS], lb[FK_MAX_QCLASS], lc[FK_MAX_QCLASS], ld[FK_MAX_QCLASS];
     int    precision[FK_MAX_QCLASS];    /* 64 or 32 */
     int    bra_block[FK_MAX_QCLASS], kets_per_tile[FK_MAX_QCLASS];
     double grid_fraction[FK_MAX_QCLASS];
+    int    engine[FK_MAX_QCLASS];       /* FK_ENGINE_RYS or FK_ENGINE_HGP */
     int    changed[FK_MAX_QCLASS];      /* 1 if the schedule differs from the one before tuning */
     double ms_default[FK_MAX_QCLASS];   /* the launch's kernel time before tuning */
     double ms_tuned[FK_MAX_QCLASS];
@@ -250,12 +267,13 @@ typedef struct {
  * screening options (those of the last fk_build_quartets) and density D
  * (as in fk_build_jk: FK_DEVICE_PTRS for a device pointer, else host), it
  * tries one axis at a time for all classes at once -- bra_block 1..32, then
- * 1, 2, 4, 8 rounds of kets per tile, then grid fractions 1, 1/2, 1/4, 2, 4 --
+ * 1, 2, 4, 8 rounds of kets per tile, then grid fractions 1, 1/2, 1/4, 2, 4,
+ * then the other integral engine where a class has both --
  * rebuilding the lists and timing each class launch with HIP events (one
  * warm-up and `reps` timed builds, the minimum kept), keeps for each class the
  * candidate more than 2 % faster than its best so far, and leaves the lists
  * built with the chosen schedules.  report may be NULL.  Runs about
- * 16 (reps + 1) builds and 16 list builds; allocates three nbf^2 buffers for
+ * 18 (reps + 1) builds and 18 list builds; allocates three nbf^2 buffers for
  * its duration. */
 int fk_autotune(fk_ctx *ctx, const double *D, unsigned flags, int reps, void *stream, fk_tune_report *report);
 
@@ -453,9 +471,11 @@ int fk_mlp_adam(const fk_mlp *m, const fk_mlp *grad, const fk_mlp *m1, const fk_
 /* Raw contracted integrals (ab|cd) for nq shell quartets (shell indices
  * quartets[4q..4q+3], any order and any angular momenta), written
  * consecutively as [na][nb][nc][nd] blocks into out (host array of
- * sum na*nb*nc*nd doubles).  on_device = 1 evaluates on the GPU with the
- * production per-quartet code, 0 evaluates the same code on the host. */
-int fk_debug_eri(fk_ctx *ctx, int nq, const int *quartets, double *out, int on_device);
+ * sum na*nb*nc*nd doubles).  mode bit 0: 1 evaluates on the GPU with the
+ * production per-quartet code, 0 evaluates the same code on the host; mode
+ * bit 1: 0 = Rys engine, 1 = HGP engine (FK_ERR_UNSUPPORTED if a quartet's
+ * class has no HGP kernel). */
+int fk_debug_eri(fk_ctx *ctx, int nq, const int *quartets, double *out, int mode);
 
 /* Host-side check of every address the J/K kernels will form for the current
  * quartet lists (list positions, primitive records, LDS slots, density and

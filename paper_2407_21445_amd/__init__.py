@@ -57,14 +57,15 @@ class Stats(ctypes.Structure):
                 ("prim_quartets", ctypes.c_int64 * _Q), ("flops_per_prim", ctypes.c_double * _Q),
                 ("flops_per_quartet", ctypes.c_double * _Q), ("flops_total", ctypes.c_double),
                 ("class_ms", ctypes.c_double * _Q), ("tiles", ctypes.c_int64 * _Q),
-                ("team_size", ctypes.c_int * _Q), ("precision", ctypes.c_int * _Q), ("prim_slots", ctypes.c_int64 * _Q)]
+                ("team_size", ctypes.c_int * _Q), ("precision", ctypes.c_int * _Q), ("prim_slots", ctypes.c_int64 * _Q),
+                ("engine", ctypes.c_int * _Q)]
 
 
 class TuneReport(ctypes.Structure):
     _fields_ = [("nclass", ctypes.c_int), ("la", ctypes.c_int * _Q), ("lb", ctypes.c_int * _Q),
                 ("lc", ctypes.c_int * _Q), ("ld", ctypes.c_int * _Q), ("precision", ctypes.c_int * _Q),
                 ("bra_block", ctypes.c_int * _Q), ("kets_per_tile", ctypes.c_int * _Q),
-                ("grid_fraction", ctypes.c_double * _Q), ("changed", ctypes.c_int * _Q),
+                ("grid_fraction", ctypes.c_double * _Q), ("engine", ctypes.c_int * _Q), ("changed", ctypes.c_int * _Q),
                 ("ms_default", ctypes.c_double * _Q),
                 ("ms_tuned", ctypes.c_double * _Q), ("build_ms_default", ctypes.c_double),
                 ("build_ms_tuned", ctypes.c_double), ("configurations", ctypes.c_int)]
@@ -84,6 +85,7 @@ class ScfResult(ctypes.Structure):
 
 
 GUESS_CORE, GUESS_GIVEN, GUESS_SAD, GUESS_LEARNED = 0, 1, 2, 3
+ENGINE_RYS, ENGINE_HGP = 0, 1
 GUESS_NB, GUESS_NOUT, GUESS_NRBF, GUESS_NFEAT, GUESS_RCUT = 15, 225, 24, 192, 8.0
 MLP_MAX_LAYERS = 4
 
@@ -116,6 +118,7 @@ _sig = {
     "fk_build_progress": ([_P, _P, _P], _I),
     "fk_run_scf_batch": ([_P, ctypes.POINTER(ScfOpts), _P, _P], _I),
     "fk_set_class_schedule": ([_P, _I, _I, _I, _I, _I, _I, _D], _I),
+    "fk_set_class_engine": ([_P, _I, _I, _I, _I, _I], _I),
     "fk_autotune": ([_P, _P, _U, _I, _P, ctypes.POINTER(TuneReport)], _I),
     "fk_guess_pairs": ([_P, _P, _P, _P], _I),
     "fk_guess_targets": ([_P, _P, _P], _I),
@@ -302,7 +305,7 @@ class FockJK:
                         "prim_quartets": s.prim_quartets[i], "flops_per_prim": s.flops_per_prim[i],
                         "flops_per_quartet": s.flops_per_quartet[i], "ms": s.class_ms[i],
                         "tiles": s.tiles[i], "team_size": s.team_size[i], "precision": s.precision[i],
-                        "prim_slots": s.prim_slots[i]})
+                        "prim_slots": s.prim_slots[i], "engine": s.engine[i]})
         return {"classes": out, "flops_total": s.flops_total,
                 "quartets": sum(c["quartets"] for c in out), "prim_quartets": sum(c["prim_quartets"] for c in out)}
 
@@ -339,6 +342,12 @@ class FockJK:
                                                int(kets_per_tile), float(grid_fraction)))
         return self
 
+    def set_class_engine(self, la, lb, lc, ld, engine):
+        """engine: "rys" / "hgp" (or ENGINE_RYS / ENGINE_HGP) for the class."""
+        e = {"rys": ENGINE_RYS, "hgp": ENGINE_HGP}.get(engine, engine)
+        self._check(_lib.fk_set_class_engine(self._ctx, int(la), int(lb), int(lc), int(ld), int(e)))
+        return self
+
     def autotune(self, D, reps=2, stream=None):
         """Tunes the class schedules on density D (numpy or device tensor);
         returns the report as a dict with a per-launch list."""
@@ -351,7 +360,7 @@ class FockJK:
             rc = _lib.fk_autotune(self._ctx, _ptr(Dc), 0, int(reps), None, ctypes.byref(r))
         self._check(rc)
         rows = [{k: getattr(r, k)[i] for k in ("la", "lb", "lc", "ld", "precision", "bra_block", "kets_per_tile",
-                                                 "grid_fraction", "changed", "ms_default", "ms_tuned")} for i in range(r.nclass)]
+                                                 "grid_fraction", "engine", "changed", "ms_default", "ms_tuned")} for i in range(r.nclass)]
         return {"classes": rows, "build_ms_default": r.build_ms_default, "build_ms_tuned": r.build_ms_tuned,
                 "configurations": r.configurations}
 
@@ -417,12 +426,13 @@ class FockJK:
     # ---- diagnostics ----
     def check_indices(self):
         self._check(_lib.fk_check_indices(self._ctx))
-    def debug_eri(self, quartets, on_device=True):
+    def debug_eri(self, quartets, on_device=True, engine="rys"):
         q = np.ascontiguousarray(np.asarray(quartets, dtype=np.int32).reshape(-1, 4))
         shapes = [tuple(_ncart(int(self.sh_l[s])) for s in row) for row in q]
         tot = sum(int(np.prod(s)) for s in shapes)
         out = np.zeros(max(tot, 1))
-        self._check(_lib.fk_debug_eri(self._ctx, len(q), _ptr(q), _ptr(out), 1 if on_device else 0))
+        e = {"rys": ENGINE_RYS, "hgp": ENGINE_HGP}.get(engine, engine)
+        self._check(_lib.fk_debug_eri(self._ctx, len(q), _ptr(q), _ptr(out), (1 if on_device else 0) | (2 * int(e))))
         res, o = [], 0
         for s in shapes:
             m = int(np.prod(s))

@@ -55,6 +55,9 @@ struct QuartetClass {
     double grid_frac = 1.0;   // share of the resident-workgroup grid launched
     int bra_slot;             // doubles per wave of staged bra primitive records
     int prec;                 // 0: FP64 launch, 1: FP32 launch of the precision split
+    int engine = 0;           // 0: Rys quadrature, 1: HGP (classes with info.hgp only)
+    double flops_prim() const { return engine ? info.flops_prim_hgp : info.flops_prim; }
+    double flops_quartet() const { return engine ? info.flops_quartet_hgp : info.flops_quartet; }
 };
 
 }  // namespace
@@ -117,7 +120,7 @@ struct fk_ctx {
     bool timed = false;
     std::vector<hipEvent_t> ev;  // 2 per quartet class
     // per quartet class schedule (key P * NPC + Q), from fk_set_class_schedule or fk_autotune
-    struct ClassSched { int bb = 0, kt = 0; double gf = 1.0; };
+    struct ClassSched { int bb = 0, kt = 0; double gf = 1.0; int eng = 0; };
     std::map<int, ClassSched> sched;
     std::vector<double> oe_S, oe_T, oe_V;          // one-electron matrices of the current geometry and basis
     double dscreen_scale = 1.0;                   // per-quartet threshold = tau * this (builds from density changes)
@@ -266,16 +269,18 @@ struct PairTab {
 };
 
 int eval_quartets_tab(fk_ctx *c, const PairTab &t, int P, int Q, const std::vector<int> &qs,
-                      std::vector<double> &out, bool on_device)
+                      std::vector<double> &out, bool on_device, int engine = 0)
 {
     FkClassInfo ci;
     int rc = fk_kernels_class_info(P, Q, &ci);
     if (rc) return fail(c, FK_ERR_UNSUPPORTED, "class (%d,%d) not built", P, Q);
+    if (engine != 0 && !ci.hgp)
+        return fail(c, FK_ERR_UNSUPPORTED, "the HGP engine is not built for class (%d%d|%d%d)", ci.la, ci.lb, ci.lc, ci.ld);
     const int nq = (int)qs.size() / 2;
     out.assign((size_t)nq * ci.nout, 0.0);
     if (nq == 0) return FK_OK;
     if (!on_device) {
-        rc = fk_kernels_debug_host(P, Q, t.ppoff, t.npp, t.AB, c->pp.data(), qs.data(), nq, out.data());
+        rc = fk_kernels_debug_host(P, Q, t.ppoff, t.npp, t.AB, c->pp.data(), qs.data(), nq, out.data(), engine);
         return rc ? fail(c, FK_ERR_UNSUPPORTED, "host evaluation failed") : FK_OK;
     }
     DevBuf<int> dq;
@@ -291,6 +296,7 @@ int eval_quartets_tab(fk_ctx *c, const PairTab &t, int P, int Q, const std::vect
     a.nq = nq;
     a.out = dout.p;
     a.rys_tab = c->d_rys.p + rys_staged_offset(ci.nroot);
+    a.engine = engine;
     rc = fk_kernels_launch_debug(P, Q, &a, nullptr);
     hipError_t e = hipDeviceSynchronize();
     if (rc == 0 && e == hipSuccess) e = hipMemcpy(out.data(), dout.p, out.size() * sizeof(double), hipMemcpyDeviceToHost);
@@ -301,10 +307,11 @@ int eval_quartets_tab(fk_ctx *c, const PairTab &t, int P, int Q, const std::vect
     return FK_OK;
 }
 
-int eval_quartets(fk_ctx *c, int P, int Q, const std::vector<int> &qs, std::vector<double> &out, bool on_device)
+int eval_quartets(fk_ctx *c, int P, int Q, const std::vector<int> &qs, std::vector<double> &out, bool on_device,
+                  int engine = 0)
 {
     PairTab t{c->pr_ppoff.data(), c->pr_npp.data(), c->pr_AB.data(), c->d_pr_ppoff.p, c->d_pr_npp.p, c->d_pr_AB.p};
-    return eval_quartets_tab(c, t, P, Q, qs, out, on_device);
+    return eval_quartets_tab(c, t, P, Q, qs, out, on_device, engine);
 }
 
 // Largest Cartesian diagonal of (ab|ab) over the components, true normalisation.
@@ -881,6 +888,7 @@ int fk_build_quartets(fk_ctx *c, const fk_screen_opts *o)
             int tile_kets = qc.info.wave_per_quartet == 0 ? 64 : std::max(1, 2 * (64 / ts));
             if (qc.info.wave_per_quartet != 0 && sch.kt > 0) tile_kets = std::min(64, sch.kt);
             qc.grid_frac = sch.gf;
+            qc.engine = (sch.eng != 0 && qc.info.hgp) ? sch.eng : 0;
             const int qpw = qc.info.wave_per_quartet == 0 ? 64 : (qc.info.wave_per_quartet == 3 ? 1 : 64 / ts);
             int max_bra_npp = 1;
             for (int p : LP) max_bra_npp = std::max(max_bra_npp, c->pr_npp[p]);
@@ -962,7 +970,7 @@ int fk_build_quartets(fk_ctx *c, const fk_screen_opts *o)
             qc.tile_off = (int64_t)c->tiles.size();
             qc.ntile = (int64_t)tl.size();
             c->tiles.insert(c->tiles.end(), tl.begin(), tl.end());
-            c->flops_schwarz += qc.nprim * qc.info.flops_prim + qc.nquartet * qc.info.flops_quartet;
+            c->flops_schwarz += qc.nprim * qc.flops_prim() + qc.nquartet * qc.flops_quartet();
             c->nq_schwarz += qc.nquartet;
             for (int k = 0; k < (split ? 2 : 1); ++k) {
                 QuartetClass q = qc;
@@ -976,7 +984,7 @@ int fk_build_quartets(fk_ctx *c, const fk_screen_opts *o)
                 if (dev) {
                     int nb = 0;
                     const int lds = fk_kernels_jk_lds_bytes(P, Q, q.bra_slot);
-                    if (fk_kernels_max_blocks(P, Q, lds, &nb) == 0 && nb > 0) q.blocks_per_cu = nb;
+                    if (fk_kernels_max_blocks(P, Q, lds, q.engine, &nb) == 0 && nb > 0) q.blocks_per_cu = nb;
                 }
                 if ((int)c->qclasses.size() >= FK_MAX_QCLASS)
                     return fail(c, FK_ERR_STATE, "internal: more class launches than FK_MAX_QCLASS");
@@ -1140,6 +1148,7 @@ int build_jk_impl(fk_ctx *c, const double *D, double *J, double *K, unsigned fla
         bool twin = false;
         for (const auto &o : c->qclasses) twin = twin || (o.P == qc.P && o.Q == qc.Q && o.prec != qc.prec);
         a.tau_fp32 = twin ? c->opts.tau_fp32 : 0.0;
+        a.engine = qc.engine;
         a.blocks = c->d_blocks.p;
         a.blk_bra = c->d_blk_bra.p;
         a.blk_pos = c->d_blk_pos.p;
@@ -1216,13 +1225,14 @@ int fk_stats(fk_ctx *c, fk_stats_t *s)
         s->la[i] = q.info.la; s->lb[i] = q.info.lb; s->lc[i] = q.info.lc; s->ld[i] = q.info.ld;
         s->quartets[i] = (int64_t)cnt[2 * i];
         s->prim_quartets[i] = (int64_t)cnt[2 * i + 1];
-        s->flops_per_prim[i] = q.info.flops_prim;
-        s->flops_per_quartet[i] = q.info.flops_quartet;
+        s->flops_per_prim[i] = q.flops_prim();
+        s->flops_per_quartet[i] = q.flops_quartet();
+        s->engine[i] = q.engine;
         s->tiles[i] = q.ntile;
         s->team_size[i] = q.info.wave_per_quartet == 3 ? 64 : std::max(1, q.info.team_size);
         s->precision[i] = q.prec ? 32 : 64;
         s->prim_slots[i] = q.prim_slots;
-        s->flops_total += s->prim_quartets[i] * q.info.flops_prim + s->quartets[i] * q.info.flops_quartet;
+        s->flops_total += s->prim_quartets[i] * q.flops_prim() + s->quartets[i] * q.flops_quartet();
         if (c->timed && 2 * i + 1 < c->ev.size()) {
             float ms = 0;
             if (hipEventElapsedTime(&ms, c->ev[2 * i], c->ev[2 * i + 1]) == hipSuccess) s->class_ms[i] = ms;
@@ -1258,7 +1268,27 @@ int fk_set_class_schedule(fk_ctx *c, int la, int lb, int lc, int ld, int bra_blo
         !(grid_fraction > 0 && grid_fraction <= 4))
         return fail(c, FK_ERR_ARG, "fk_set_class_schedule: bra_block 0..%d, kets_per_tile 0..64, grid_fraction (0, 4]",
                     FK_MAX_BRA_BLOCK);
-    c->sched[P * NPC + Q] = fk_ctx::ClassSched{bra_block, kets_per_tile, grid_fraction};
+    const int eng = c->sched.count(P * NPC + Q) ? c->sched[P * NPC + Q].eng : 0;
+    c->sched[P * NPC + Q] = fk_ctx::ClassSched{bra_block, kets_per_tile, grid_fraction, eng};
+    return FK_OK;
+}
+
+int fk_set_class_engine(fk_ctx *c, int la, int lb, int lc, int ld, int engine)
+{
+    if (!c) return FK_ERR_ARG;
+    if (la < lb || lc < ld || la > FK_MAX_L || lc > FK_MAX_L || lb < 0 || ld < 0)
+        return fail(c, FK_ERR_ARG, "fk_set_class_engine: need la >= lb, lc >= ld, l <= %d", FK_MAX_L);
+    if (engine != FK_ENGINE_RYS && engine != FK_ENGINE_HGP)
+        return fail(c, FK_ERR_ARG, "fk_set_class_engine: engine must be FK_ENGINE_RYS or FK_ENGINE_HGP");
+    int P = pair_class(la, lb), Q = pair_class(lc, ld);
+    if (P < Q) std::swap(P, Q);
+    FkClassInfo info;
+    if (fk_kernels_class_info(P, Q, &info))
+        return fail(c, FK_ERR_UNSUPPORTED, "fk_set_class_engine: class (%d%d|%d%d) is not built", la, lb, lc, ld);
+    if (engine == FK_ENGINE_HGP && !info.hgp)
+        return fail(c, FK_ERR_UNSUPPORTED, "fk_set_class_engine: the HGP engine is not built for class (%d%d|%d%d)",
+                    la, lb, lc, ld);
+    c->sched[P * NPC + Q].eng = engine;
     return FK_OK;
 }
 
@@ -1317,11 +1347,21 @@ int fk_autotune(fk_ctx *c, const double *D, unsigned flags, int reps, void *stre
     }
     std::map<int, double> tbest = t0;
     // one axis at a time, every class measured under each candidate value
-    for (int axis = 0; axis < 3; ++axis) {
+    for (int axis = 0; axis < 4; ++axis) {
         std::vector<double> vals;
         if (axis == 0) vals = {1, 2, 4, 8, 16, 32};
         else if (axis == 1) vals = {1, 2, 4, 8};   // rounds of kets (team and wave kernels)
-        else vals = {1.0, 0.5, 0.25, 2.0, 4.0};
+        else if (axis == 2) vals = {1.0, 0.5, 0.25, 2.0, 4.0};
+        else {
+            // the other engine, for the classes that have both
+            bool any = false;
+            for (const auto &kv : cur) {
+                FkClassInfo info;
+                if (!fk_kernels_class_info(kv.first / NPC, kv.first % NPC, &info) && info.hgp) any = true;
+            }
+            if (!any) break;
+            vals = {-1};
+        }
         for (double v : vals) {
             std::map<int, fk_ctx::ClassSched> trial = cur;
             for (auto &kv : trial) {
@@ -1329,7 +1369,9 @@ int fk_autotune(fk_ctx *c, const double *D, unsigned flags, int reps, void *stre
                 FkClassInfo info;
                 if (fk_kernels_class_info(P, Q, &info)) continue;
                 if (axis == 0) kv.second.bb = (int)v;
-                else if (axis == 1) {
+                else if (axis == 3) {
+                    if (info.hgp) kv.second.eng = 1 - kv.second.eng;
+                } else if (axis == 1) {
                     if (info.wave_per_quartet == 0) continue;
                     const int qpw = info.wave_per_quartet == 3 ? 1 : 64 / std::max(1, info.team_size);
                     kv.second.kt = std::min(64, (int)v * qpw);
@@ -1362,6 +1404,7 @@ int fk_autotune(fk_ctx *c, const double *D, unsigned flags, int reps, void *stre
             rep->bra_block[i] = std::max(1, std::min(sc.bb > 0 ? sc.bb : (opts.bra_block > 0 ? opts.bra_block : 8), q.info.bra_block));
             rep->kets_per_tile[i] = q.info.wave_per_quartet == 0 ? 64 : (sc.kt > 0 ? sc.kt : 2 * (q.info.wave_per_quartet == 3 ? 1 : 64 / std::max(1, q.info.team_size)));
             rep->grid_fraction[i] = sc.gf;
+            rep->engine[i] = q.engine;
             const auto s0 = start.find(q.P * NPC + q.Q);
             const fk_ctx::ClassSched sc0 = s0 == start.end() ? fk_ctx::ClassSched{} : s0->second;
             // compare the schedules in effect (a candidate equal to the default is no change)
@@ -1372,7 +1415,8 @@ int fk_autotune(fk_ctx *c, const double *D, unsigned flags, int reps, void *stre
                 if (q.info.wave_per_quartet == 0) return 64;
                 return x.kt > 0 ? x.kt : 2 * (q.info.wave_per_quartet == 3 ? 1 : 64 / std::max(1, q.info.team_size));
             };
-            rep->changed[i] = (eff_bb(sc0) != eff_bb(sc) || eff_kt(sc0) != eff_kt(sc) || sc0.gf != sc.gf) ? 1 : 0;
+            rep->changed[i] =
+                (eff_bb(sc0) != eff_bb(sc) || eff_kt(sc0) != eff_kt(sc) || sc0.gf != sc.gf || sc0.eng != sc.eng) ? 1 : 0;
             rep->ms_tuned[i] = launch1[i];
             for (size_t j = 0; j < keys0.size(); ++j)
                 if (keys0[j].P == q.P && keys0[j].Q == q.Q && keys0[j].prec == q.prec) rep->ms_default[i] = launch0[j];
@@ -1383,9 +1427,11 @@ int fk_autotune(fk_ctx *c, const double *D, unsigned flags, int reps, void *stre
     return FK_OK;
 }
 
-int fk_debug_eri(fk_ctx *c, int nq, const int *quartets, double *out, int on_device)
+int fk_debug_eri(fk_ctx *c, int nq, const int *quartets, double *out, int mode)
 {
     if (!c) return FK_ERR_ARG;
+    if (mode < 0 || mode > 3) return fail(c, FK_ERR_ARG, "fk_debug_eri: mode must be 0..3");
+    const int on_device = mode & 1, engine = mode >> 1;
     if (c->nmol > 1) return fail(c, FK_ERR_UNSUPPORTED, "fk_debug_eri: not available for a batch of molecules");
     if (!c->have_quartets) return fail(c, FK_ERR_STATE, "fk_debug_eri: call fk_build_quartets first");
     if (nq < 0 || (nq > 0 && (!quartets || !out))) return fail(c, FK_ERR_ARG, "fk_debug_eri: bad arguments");
@@ -1424,7 +1470,7 @@ int fk_debug_eri(fk_ctx *c, int nq, const int *quartets, double *out, int on_dev
             std::vector<int> qs;
             for (auto &it : g) { qs.push_back(it.bra); qs.push_back(it.ket); }
             std::vector<double> raw;
-            int rc = eval_quartets(c, P, Q, qs, raw, on_device != 0);
+            int rc = eval_quartets(c, P, Q, qs, raw, on_device != 0, engine);
             if (rc) return rc;
             for (size_t k = 0; k < g.size(); ++k) {
                 const Item &it = g[k];

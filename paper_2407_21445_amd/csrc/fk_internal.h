@@ -91,6 +91,7 @@ struct FkJKArgs {
     unsigned long long *counters;  // [2]: contracted quartets, primitive quartets
     int bra_slot;            // doubles per wave for the staged bra primitive records
     int prec;                // 0: FP64 kernel, 1: FP32 kernel of the precision split
+    int engine;              // 0: Rys quadrature, 1: HGP with early contraction
     double tau_fp32;         // precision split (0: none): per bra and tile, the FP32
                              // launch takes the work when G_ab G_cd D_max < tau_fp32
                              // for every quartet of the wave, the FP64 launch otherwise
@@ -121,6 +122,7 @@ struct FkDebugArgs {
     int nq;
     double *out;             // [nq * NOUT]
     const double *rys_tab;
+    int engine;              // 0: Rys quadrature, 1: HGP
 };
 
 // Per-class launch entry points (defined in fk_kernels.hip).
@@ -130,13 +132,17 @@ struct FkClassInfo {
     int team_size;           // lanes per quartet
     int bra_block;           // largest bra block the class kernel takes per tile
     double flops_prim, flops_quartet;
+    int hgp;                 // 1: the HGP engine is built for the class
+    double flops_prim_hgp, flops_quartet_hgp;
 };
+// HGP kernels are built for lane-per-quartet classes up to this total momentum
+#define FK_HGP_MAX_L 4
 
 extern "C" {
 int fk_kernels_class_info(int P, int Q, FkClassInfo *info);
 int fk_kernels_launch_jk(int P, int Q, const FkJKArgs *args, int grid, void *stream);
 int fk_kernels_launch_debug(int P, int Q, const FkDebugArgs *args, void *stream);
-int fk_kernels_max_blocks(int P, int Q, int dyn_lds_bytes, int *blocks_per_cu);
+int fk_kernels_max_blocks(int P, int Q, int dyn_lds_bytes, int engine, int *blocks_per_cu);
 int fk_kernels_jk_lds_bytes(int P, int Q, int bra_slot);
 int fk_kernels_launch_prep(const double *D, const double *bf_scale, const FkMolArgs *m, double *Ds, double *Dsh,
                            void *stream);
@@ -144,7 +150,7 @@ int fk_kernels_launch_finalize(const double *XJ, const double *XK, long long xco
                                const FkMolArgs *m, double *J, double *K, void *stream);
 int fk_kernels_launch_fill(double *p, long long n, void *stream);
 int fk_kernels_debug_host(int P, int Q, const int *pair_ppoff, const int *pair_npp, const double *pair_AB,
-                          const double *pp, const int *quartets, int nq, double *out);
+                          const double *pp, const int *quartets, int nq, double *out, int engine);
 // dense SCF kernels (fk_scf.hip); n x n row-major FP64 device matrices
 int fk_scf_gemm(const double *A, const double *B, double *C, int n, double alpha, double beta, void *stream);
 int fk_scf_lincomb(double *out, const double *x, const double *y, const double *z, int n, double a, double b,

@@ -21,6 +21,7 @@
 
 #include "fk_internal.h"
 #include "fk_eri.h"
+#include "fk_hgp.h"
 
 #ifndef FK_BUILD_MAXL
 #define FK_BUILD_MAXL 3
@@ -328,7 +329,8 @@ struct LpqStage {
     static constexpr int value = 64 * (m3 > Q::NC * Q::ND ? m3 : Q::NC * Q::ND);
 };
 
-template <int LA, int LB, int LC, int LD, typename R = double>
+// ENG: the integral engine, 0 Rys quadrature, 1 HGP with early contraction
+template <int LA, int LB, int LC, int LD, typename R = double, int ENG = 0>
 __global__ void __launch_bounds__(FK_BLOCK, (LpqMinBlocks<LA, LB, LC, LD>::value)) k_jk_lpq(FkJKArgs a)
 {
     using Q = fk::QClass<LA, LB, LC, LD>;
@@ -402,24 +404,44 @@ __global__ void __launch_bounds__(FK_BLOCK, (LpqMinBlocks<LA, LB, LC, LD>::value
             R acc[NOUT];
 #pragma unroll
             for (int o = 0; o < NOUT; ++o) acc[o] = (R)0;
-            if (active) {
-                fk::PrimPair qn = load_ket_pp(a.ppT, g, 0, r);
-                for (int j = 0; j < g.npp; ++j) {
-                    const fk::PrimPair q = qn;
-                    if (j + 1 < g.npp) qn = load_ket_pp(a.ppT, g, j + 1, r);
-                    // two bra primitives per step for the small classes: their
-                    // quartets are independent straight-line code the compiler
-                    // interleaves (larger classes would spill)
-                    constexpr bool PAIR = NOUT <= FK_LPQ_PAIR_NOUT;
-                    int i = 0;
-                    if constexpr (PAIR)
-                        for (; i + 1 < bnpp; i += 2) {
-                            const fk::PrimPair p0 = sload_pp(a.pp, ppo + i), p1 = sload_pp(a.pp, ppo + i + 1);
-                            fk::rys_prim_all<LA, LB, LC, LD, R, true>(s_tab, p0, q, B.AB, Kt.CD, acc);
-                            fk::rys_prim_all<LA, LB, LC, LD, R, true>(s_tab, p1, q, B.AB, Kt.CD, acc);
-                        }
-                    for (; i < bnpp; ++i)
-                        fk::rys_prim_all<LA, LB, LC, LD, R, PAIR>(s_tab, sload_pp(a.pp, ppo + i), q, B.AB, Kt.CD, acc);
+            if constexpr (ENG == 0) {
+                if (active) {
+                    fk::PrimPair qn = load_ket_pp(a.ppT, g, 0, r);
+                    for (int j = 0; j < g.npp; ++j) {
+                        const fk::PrimPair q = qn;
+                        if (j + 1 < g.npp) qn = load_ket_pp(a.ppT, g, j + 1, r);
+                        // two bra primitives per step for the small classes: their
+                        // quartets are independent straight-line code the compiler
+                        // interleaves (larger classes would spill)
+                        constexpr bool PAIR = NOUT <= FK_LPQ_PAIR_NOUT;
+                        int i = 0;
+                        if constexpr (PAIR)
+                            for (; i + 1 < bnpp; i += 2) {
+                                const fk::PrimPair p0 = sload_pp(a.pp, ppo + i), p1 = sload_pp(a.pp, ppo + i + 1);
+                                fk::rys_prim_all<LA, LB, LC, LD, R, true>(s_tab, p0, q, B.AB, Kt.CD, acc);
+                                fk::rys_prim_all<LA, LB, LC, LD, R, true>(s_tab, p1, q, B.AB, Kt.CD, acc);
+                            }
+                        for (; i < bnpp; ++i)
+                            fk::rys_prim_all<LA, LB, LC, LD, R, PAIR>(s_tab, sload_pp(a.pp, ppo + i), q, B.AB, Kt.CD,
+                                                                      acc);
+                    }
+                }
+            } else {
+                // HGP engine: [e0|f0] summed over the primitives, then the
+                // horizontal recurrences once per contracted quartet
+                using H = fk::HgpClass<LA, LB, LC, LD>;
+                R acce[H::NACC];
+#pragma unroll
+                for (int o = 0; o < H::NACC; ++o) acce[o] = (R)0;
+                if (active) {
+                    fk::PrimPair qn = load_ket_pp(a.ppT, g, 0, r);
+                    for (int j = 0; j < g.npp; ++j) {
+                        const fk::PrimPair q = qn;
+                        if (j + 1 < g.npp) qn = load_ket_pp(a.ppT, g, j + 1, r);
+                        for (int i = 0; i < bnpp; ++i)
+                            fk::hgp_prim<LA, LB, LC, LD, R>(s_tab, sload_pp(a.pp, ppo + i), q, acce);
+                    }
+                    fk::hgp_hrr<LA, LB, LC, LD, R>(acce, B.AB, Kt.CD, acc);
                 }
             }
             const bool diag = same && pos == bpos;
@@ -1022,6 +1044,33 @@ __global__ void __launch_bounds__(FK_BLOCK) k_debug_tpq(FkDebugArgs a)
     }
 }
 
+// Raw contracted integrals by the HGP engine, one lane per quartet.
+template <int LA, int LB, int LC, int LD>
+__global__ void __launch_bounds__(FK_BLOCK) k_debug_hgp(FkDebugArgs a)
+{
+    using Q = fk::QClass<LA, LB, LC, LD>;
+    using H = fk::HgpClass<LA, LB, LC, LD>;
+    __shared__ double s_tab[rys_lds_size(Q::NR)];
+    load_table<Q::NR>(s_tab, a.rys_tab);
+    const int q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= a.nq) return;
+    const int bra = a.quartets[q].x, ket = a.quartets[q].y;
+    const double AB[3] = {a.pair_AB[3 * bra], a.pair_AB[3 * bra + 1], a.pair_AB[3 * bra + 2]};
+    const double CD[3] = {a.pair_AB[3 * ket], a.pair_AB[3 * ket + 1], a.pair_AB[3 * ket + 2]};
+    double acce[H::NACC];
+#pragma unroll
+    for (int o = 0; o < H::NACC; ++o) acce[o] = 0.0;
+    for (int i = 0; i < a.pair_npp[bra]; ++i) {
+        const fk::PrimPair p = load_pp(a.pp, a.pair_ppoff[bra] + i);
+        for (int j = 0; j < a.pair_npp[ket]; ++j)
+            fk::hgp_prim<LA, LB, LC, LD>(s_tab, p, load_pp(a.pp, a.pair_ppoff[ket] + j), acce);
+    }
+    double out[Q::NOUT];
+    fk::hgp_hrr<LA, LB, LC, LD>(acce, AB, CD, out);
+#pragma unroll
+    for (int o = 0; o < Q::NOUT; ++o) a.out[(size_t)q * Q::NOUT + o] = out[o];
+}
+
 // --------------------------------------------------------- dispatch ------
 template <int P, int Q>
 struct Disp {
@@ -1029,6 +1078,8 @@ struct Disp {
     static constexpr bool BUILT = LA <= FK_BUILD_MAXL;
     static constexpr int KIND = kernel_kind<LA, LB, LC, LD>();
     static constexpr bool WPQ = KIND == 3;
+    // classes the HGP engine is built for: lane-per-quartet kernels up to L = 4
+    static constexpr bool HGP = KIND == 0 && LA + LB + LC + LD <= FK_HGP_MAX_L;
     static void info(FkClassInfo *i)
     {
         using C = fk::QClass<LA, LB, LC, LD>;
@@ -1041,11 +1092,19 @@ struct Disp {
         i->team_size = KIND == 0 ? 1 : (KIND == 1 ? C::NA : (KIND == 2 ? C::NA * C::NB : 64));
         i->flops_prim = fk::flops_prim(LA, LB, LC, LD);
         i->flops_quartet = fk::flops_digest(LA, LB, LC, LD);
+        i->hgp = HGP ? 1 : 0;
+        i->flops_prim_hgp = HGP ? fk::hgp_flops_prim(LA, LB, LC, LD) : 0.0;
+        i->flops_quartet_hgp = HGP ? fk::hgp_flops_hrr(LA, LB, LC, LD) + fk::flops_digest(LA, LB, LC, LD) : 0.0;
     }
-    static const void *jk_kernel(bool low = false)
+    static const void *jk_kernel(bool low = false, int eng = 0)
     {
         if constexpr (!BUILT) return nullptr;
-        else if constexpr (KIND == 0)
+        else if constexpr (HGP) {
+            if (eng == 1)
+                return low ? (const void *)&k_jk_lpq<LA, LB, LC, LD, float, 1>
+                           : (const void *)&k_jk_lpq<LA, LB, LC, LD, double, 1>;
+            return low ? (const void *)&k_jk_lpq<LA, LB, LC, LD, float> : (const void *)&k_jk_lpq<LA, LB, LC, LD, double>;
+        } else if constexpr (KIND == 0)
             return low ? (const void *)&k_jk_lpq<LA, LB, LC, LD, float> : (const void *)&k_jk_lpq<LA, LB, LC, LD, double>;
         else if constexpr (KIND == 1 || KIND == 2)
             return low ? (const void *)&k_jk_tpq<LA, LB, LC, LD, KIND, float>
@@ -1069,12 +1128,21 @@ struct Disp {
         else {
             const int lds = lds_bytes(a->bra_slot);
             const bool low = a->prec == 1;
+            const int eng = a->engine;
             if (low && KIND == 3) return -2;  // f-f bras: FP64 only
-            const void *k = jk_kernel(low);
-            static int raised[2] = {0, 0};
-            if (lds > 65536 && lds > raised[low]) {
+            if (eng != 0 && !HGP) return -2;  // HGP only for the classes it is built for
+            const void *k = jk_kernel(low, eng);
+            static int raised[2][2] = {{0, 0}, {0, 0}};
+            if (lds > 65536 && lds > raised[low][eng]) {
                 if (hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, lds) != hipSuccess) return -3;
-                raised[low] = lds;
+                raised[low][eng] = lds;
+            }
+            if constexpr (HGP) {
+                if (eng == 1) {
+                    if (low) hipLaunchKernelGGL((k_jk_lpq<LA, LB, LC, LD, float, 1>), dim3(grid), dim3(FK_BLOCK), lds, st, *a);
+                    else hipLaunchKernelGGL((k_jk_lpq<LA, LB, LC, LD, double, 1>), dim3(grid), dim3(FK_BLOCK), lds, st, *a);
+                    return hipGetLastError() == hipSuccess ? 0 : -3;
+                }
             }
             if constexpr (KIND == 0) {
                 if (low) hipLaunchKernelGGL((k_jk_lpq<LA, LB, LC, LD, float>), dim3(grid), dim3(FK_BLOCK), lds, st, *a);
@@ -1093,6 +1161,15 @@ struct Disp {
         if constexpr (!BUILT) return -2;
         else {
             if (a->nq <= 0) return 0;
+            if (a->engine != 0) {
+                if constexpr (HGP) {
+                    const int grid = (a->nq + FK_BLOCK - 1) / FK_BLOCK;
+                    hipLaunchKernelGGL((k_debug_hgp<LA, LB, LC, LD>), dim3(grid), dim3(FK_BLOCK), 0, st, *a);
+                    return hipGetLastError() == hipSuccess ? 0 : -3;
+                } else {
+                    return -2;
+                }
+            }
             if constexpr (KIND == 3) {
                 const int grid = (a->nq + FK_WAVES - 1) / FK_WAVES;
                 hipLaunchKernelGGL((k_debug_wpq<LA, LB, LC, LD>), dim3(grid), dim3(FK_BLOCK), 0, st, *a);
@@ -1110,7 +1187,7 @@ struct Disp {
         }
     }
     static int debug_host(const int *ppoff, const int *npp, const double *AB, const double *pp, const int *qs,
-                          int nq, double *out)
+                          int nq, double *out, int eng)
     {
         if constexpr (!BUILT) return -2;
         else {
@@ -1124,6 +1201,22 @@ struct Disp {
             p.K = r[8];
             return p;
         };
+        if (eng != 0) {
+            if constexpr (HGP) {
+                using H = fk::HgpClass<LA, LB, LC, LD>;
+                for (int q = 0; q < nq; ++q) {
+                    const int bra = qs[2 * q], ket = qs[2 * q + 1];
+                    double acce[H::NACC] = {};
+                    for (int i = 0; i < npp[bra]; ++i)
+                        for (int j = 0; j < npp[ket]; ++j)
+                            fk::hgp_prim<LA, LB, LC, LD>(tab, ld(ppoff[bra] + i), ld(ppoff[ket] + j), acce);
+                    fk::hgp_hrr<LA, LB, LC, LD>(acce, AB + 3 * bra, AB + 3 * ket, out + (size_t)q * C::NOUT);
+                }
+                return 0;
+            } else {
+                return -2;
+            }
+        }
         for (int q = 0; q < nq; ++q) {
             const int bra = qs[2 * q], ket = qs[2 * q + 1];
             double *o = out + (size_t)q * C::NOUT;
@@ -1191,10 +1284,13 @@ int dbg_q(int q, const FkDebugArgs *a, hipStream_t st)
     else return q == Q ? Disp<P, Q>::launch_debug(a, st) : dbg_q<P, Q + 1>(q, a, st);
 }
 template <int P, int Q = 0>
-int host_q(int q, const int *o, const int *n, const double *ab, const double *pp, const int *qs, int nq, double *out)
+int host_q(int q, const int *o, const int *n, const double *ab, const double *pp, const int *qs, int nq, double *out,
+           int eng)
 {
     if constexpr (Q > P) return -1;
-    else return q == Q ? Disp<P, Q>::debug_host(o, n, ab, pp, qs, nq, out) : host_q<P, Q + 1>(q, o, n, ab, pp, qs, nq, out);
+    else
+        return q == Q ? Disp<P, Q>::debug_host(o, n, ab, pp, qs, nq, out, eng)
+                      : host_q<P, Q + 1>(q, o, n, ab, pp, qs, nq, out, eng);
 }
 template <int P, int Q = 0>
 int lds_q(int q, int slot)
@@ -1203,10 +1299,16 @@ int lds_q(int q, int slot)
     else return q == Q ? Disp<P, Q>::lds_bytes(slot) : lds_q<P, Q + 1>(q, slot);
 }
 template <int P, int Q = 0>
-const void *kern_q(int q)
+const void *kern_q(int q, int eng)
 {
     if constexpr (Q > P) return nullptr;
-    else return q == Q ? Disp<P, Q>::jk_kernel() : kern_q<P, Q + 1>(q);
+    else {
+        if (q == Q) {
+            if (eng != 0 && !Disp<P, Q>::HGP) return nullptr;
+            return Disp<P, Q>::jk_kernel(false, eng);
+        }
+        return kern_q<P, Q + 1>(q, eng);
+    }
 }
 
 }  // namespace
@@ -1221,11 +1323,11 @@ int FK_CAT(fk_kp, FK_ONLY_P, _jk)(int Q, const FkJKArgs *a, int grid, void *st)
 }
 int FK_CAT(fk_kp, FK_ONLY_P, _dbg)(int Q, const FkDebugArgs *a, void *st) { return dbg_q<FK_ONLY_P>(Q, a, (hipStream_t)st); }
 int FK_CAT(fk_kp, FK_ONLY_P, _host)(int Q, const int *o, const int *n, const double *ab, const double *pp,
-                                      const int *qs, int nq, double *out)
+                                      const int *qs, int nq, double *out, int eng)
 {
-    return host_q<FK_ONLY_P>(Q, o, n, ab, pp, qs, nq, out);
+    return host_q<FK_ONLY_P>(Q, o, n, ab, pp, qs, nq, out, eng);
 }
-const void *FK_CAT(fk_kp, FK_ONLY_P, _kern)(int Q) { return kern_q<FK_ONLY_P>(Q); }
+const void *FK_CAT(fk_kp, FK_ONLY_P, _kern)(int Q, int eng) { return kern_q<FK_ONLY_P>(Q, eng); }
 int FK_CAT(fk_kp, FK_ONLY_P, _lds)(int Q, int slot) { return lds_q<FK_ONLY_P>(Q, slot); }
 }
 #else
@@ -1318,8 +1420,8 @@ __global__ void k_finalize(const double *__restrict XJ, const double *__restrict
     int fk_kp##P##_jk(int, const FkJKArgs *, int, void *);                                                   \
     int fk_kp##P##_dbg(int, const FkDebugArgs *, void *);                                                    \
     int fk_kp##P##_host(int, const int *, const int *, const double *, const double *, const int *, int,    \
-                        double *);                                                                           \
-    const void *fk_kp##P##_kern(int);                                                                        \
+                        double *, int);                                                                      \
+    const void *fk_kp##P##_kern(int, int);                                                                   \
     int fk_kp##P##_lds(int, int);
 extern "C" {
 FK_DECL_P(0) FK_DECL_P(1) FK_DECL_P(2) FK_DECL_P(3) FK_DECL_P(4)
@@ -1354,15 +1456,15 @@ int fk_kernels_launch_debug(int P, int Q, const FkDebugArgs *args, void *stream)
 }
 
 int fk_kernels_debug_host(int P, int Q, const int *pair_ppoff, const int *pair_npp, const double *pair_AB,
-                          const double *pp, const int *quartets, int nq, double *out)
+                          const double *pp, const int *quartets, int nq, double *out, int engine)
 {
-    FK_SWITCH_P(P, host(Q, pair_ppoff, pair_npp, pair_AB, pp, quartets, nq, out))
+    FK_SWITCH_P(P, host(Q, pair_ppoff, pair_npp, pair_AB, pp, quartets, nq, out, engine))
     return -1;
 }
 
-static const void *kern_of(int P, int Q)
+static const void *kern_of(int P, int Q, int engine)
 {
-    FK_SWITCH_P(P, kern(Q))
+    FK_SWITCH_P(P, kern(Q, engine))
     return nullptr;
 }
 
@@ -1372,9 +1474,9 @@ int fk_kernels_jk_lds_bytes(int P, int Q, int bra_slot)
     return -1;
 }
 
-int fk_kernels_max_blocks(int P, int Q, int dyn_lds_bytes, int *blocks_per_cu)
+int fk_kernels_max_blocks(int P, int Q, int dyn_lds_bytes, int engine, int *blocks_per_cu)
 {
-    const void *k = kern_of(P, Q);
+    const void *k = kern_of(P, Q, engine);
     if (!k) return -2;
     int nb = 0;
     if (dyn_lds_bytes > 65536 &&

@@ -72,6 +72,98 @@ def test_device_eri_every_class_and_orientation(fk, torch):
         assert np.max(np.abs(a - h)) <= 1e-13 * scale, q
 
 
+def _hgp_everywhere(fk, c):
+    """Selects the HGP engine for every class it is built for; returns their number."""
+    n = 0
+    for la in range(4):
+        for lb in range(la + 1):
+            for lc in range(4):
+                for ld in range(lc + 1):
+                    if (la, lb) < (lc, ld):
+                        continue
+                    try:
+                        c.set_class_engine(la, lb, lc, ld, "hgp")
+                        n += 1
+                    except fk.FockJKError as e:
+                        assert e.code == fk.FK_ERR_UNSUPPORTED
+    return n
+
+
+def test_device_hgp_every_class(fk, torch):
+    """Raw (ab|cd) from the HGP engine's device code for every ordered
+    (la, lb, lc, ld) with L <= 4 it is built for, three primitives per shell:
+    against the oracle within 1e-12 (relative to max(1, |ERI|max)) and the
+    same code on the host within 1e-13."""
+    s = _rand_sys(31, lmax=3, natom=4, kmax=3)
+    c = fk.FockJK(0).set_system(s).build_quartets(tau=0.0)
+    rng = np.random.default_rng(9)
+    qs = []
+    for la in range(4):
+        for lb in range(4):
+            for lc in range(4):
+                for ld in range(4):
+                    n = [(l + 1) * (l + 2) // 2 for l in (la, lb, lc, ld)]
+                    if la + lb + lc + ld <= 4 and n[0] * n[1] * n[2] * n[3] <= 54:
+                        at = rng.integers(0, 4, size=4)
+                        qs.append([4 * at[0] + la, 4 * at[1] + lb, 4 * at[2] + lc, 4 * at[3] + ld])
+    assert len(qs) == 65
+    dev = c.debug_eri(qs, on_device=True, engine="hgp")
+    host = c.debug_eri(qs, on_device=False, engine="hgp")
+    for q, a, h in zip(qs, dev, host):
+        b = oracle.eri_quartet(s, *q)
+        scale = max(1.0, float(np.max(np.abs(b))))
+        assert np.max(np.abs(a - b)) <= 1e-12 * scale, q
+        assert np.max(np.abs(a - h)) <= 1e-13 * scale, q
+
+
+def test_jk_hgp_engine_spdf(fk, torch):
+    """J/K with the HGP engine on every class it is built for (the Rys engine
+    on the rest), unscreened, on the all-class spdf system with a random
+    density: equal to the oracle within 1e-10 (relative to max(1, |J|max));
+    the statistics name the engine of each launch."""
+    s = _rand_sys(33, lmax=3, natom=3, kmax=2)
+    s["charge"] = 1
+    D = _rand_D(s["nbf"], 6)
+    c = fk.FockJK(0).set_system(s)
+    nh = _hgp_everywhere(fk, c)
+    assert nh == 15
+    c.build_quartets(tau=0.0)
+    Dd = torch.tensor(D, dtype=torch.float64, device="cuda")
+    J, K = c.build_jk(Dd, sync=True)
+    Jo, Ko = oracle.jk(s, D)
+    scale = max(1.0, float(np.max(np.abs(Jo))))
+    assert np.max(np.abs(J.cpu().numpy() - Jo)) <= 1e-10 * scale
+    assert np.max(np.abs(K.cpu().numpy() - Ko)) <= 1e-10 * scale
+    st = c.stats()
+    assert sum(1 for x in st["classes"] if x["engine"] == fk.ENGINE_HGP) == nh
+    assert st["quartets"] == c.info()["nquartet_schwarz"]
+
+
+def test_jk_hgp_engine_water64(fk, torch, c3):
+    """(H2O)64 cc-pVDZ-type at the production threshold (tau = 1e-10,
+    primitive pairs pruned at 1e-12) with the HGP engine on every class it is
+    built for: sampled J/K blocks within 1e-8 of the oracle, and the same
+    quartets as the all-Rys build."""
+    s, D, jp, kp, Jb, Kb = c3
+    c = fk.FockJK(0).set_system(s)
+    _hgp_everywhere(fk, c)
+    c.build_quartets(tau=1e-10, tau_prim=1e-12)
+    Dd = torch.tensor(D, dtype=torch.float64, device="cuda")
+    J, K = c.build_jk(Dd, sync=True)
+    J, K = J.cpu().numpy(), K.cpu().numpy()
+    off = oracle.bf_offsets(s)
+    for (a, b), blk in zip(jp, Jb):
+        assert np.max(np.abs(J[off[a]:off[a + 1], off[b]:off[b + 1]] - blk)) <= 1e-8, (a, b)
+    for (a, cc), blk in zip(kp, Kb):
+        assert np.max(np.abs(K[off[a]:off[a + 1], off[cc]:off[cc + 1]] - blk)) <= 1e-8, (a, cc)
+    nq = c.stats()["quartets"]
+    c.close()
+    J2, K2, c2_ = _gpu_jk(fk, torch, s, D, tau=1e-10, tau_prim=1e-12)
+    assert c2_.stats()["quartets"] == nq
+    assert np.max(np.abs(J - J2)) <= 1e-11 and np.max(np.abs(K - K2)) <= 1e-11
+    c2_.close()
+
+
 @pytest.mark.parametrize("dens", ["core", "random"])
 def test_jk_water4_unscreened(fk, torch, dens):
     s = wl.water4_sto3g()
@@ -384,7 +476,7 @@ def test_autotune_keeps_results(fk, torch):
     D = core_guess(T + V, orthogonalizer(S), s["nelec"] // 2)
     c = fk.FockJK(0).set_system(s).build_quartets(tau=0.0)
     rep = c.autotune(torch.tensor(D, device="cuda:0"), reps=1)
-    assert rep["configurations"] == 17 and len(rep["classes"]) == c.info()["nquartet_class"]
+    assert rep["configurations"] == 18 and len(rep["classes"]) == c.info()["nquartet_class"]
     assert all(r["ms_tuned"] > 0 and r["ms_default"] > 0 for r in rep["classes"])
     c.check_indices()
     J, K = c.build_jk(D)

@@ -73,6 +73,64 @@ def test_host_eri_matches_oracle_all_classes():
         assert np.max(np.abs(a - b)) <= 1e-12 * max(1.0, np.max(np.abs(b))), q
 
 
+def _hgp_built(la, lb, lc, ld):
+    """Classes with an HGP kernel: lane-per-quartet classes (at most 54
+    Cartesian integrals) with la+lb+lc+ld <= 4."""
+    n = [(l + 1) * (l + 2) // 2 for l in (la, lb, lc, ld)]
+    return la + lb + lc + ld <= 4 and n[0] * n[1] * n[2] * n[3] <= 54
+
+
+def test_host_hgp_matches_oracle():
+    """The HGP engine's per-quartet code (vertical recurrences per primitive
+    quartet, early contraction, horizontal recurrences), run on the host,
+    against the oracle's McMurchie-Davidson integrals for every ordered
+    (la, lb, lc, ld) with L <= 4 it is built for, three primitives per shell;
+    the other classes are refused with FK_ERR_UNSUPPORTED."""
+    s = _rand_sys(21, lmax=3, natom=4, kmax=3)
+    c = fk.FockJK(device=-1).set_system(s).build_quartets(tau=0.0)
+    rng = np.random.default_rng(5)
+    nb = 0
+    for la in range(4):
+        for lb in range(4):
+            for lc in range(4):
+                for ld in range(4):
+                    if la + lb + lc + ld > 4:
+                        continue
+                    at = rng.integers(0, 4, size=4)
+                    q = [4 * at[0] + la, 4 * at[1] + lb, 4 * at[2] + lc, 4 * at[3] + ld]
+                    cl = sorted([tuple(sorted((la, lb), reverse=True)), tuple(sorted((lc, ld), reverse=True))],
+                                reverse=True)
+                    if not _hgp_built(*cl[0], *cl[1]):
+                        with pytest.raises(fk.FockJKError) as e:
+                            c.debug_eri([q], on_device=False, engine="hgp")
+                        assert e.value.code == fk.FK_ERR_UNSUPPORTED
+                        continue
+                    a = c.debug_eri([q], on_device=False, engine="hgp")[0]
+                    r = c.debug_eri([q], on_device=False)[0]
+                    b = oracle.eri_quartet(s, *q)
+                    scale = max(1.0, float(np.max(np.abs(b))))
+                    assert np.max(np.abs(a - b)) <= 1e-12 * scale, q
+                    assert np.max(np.abs(a - r)) <= 1e-13 * scale, q
+                    nb += 1
+    assert nb == 65
+
+
+def test_class_engine_arguments():
+    s = _rand_sys(21, lmax=3, natom=4, kmax=2)
+    c = fk.FockJK(device=-1).set_system(s)
+    c.set_class_engine(1, 0, 1, 0, "hgp").set_class_engine(0, 0, 2, 2, "hgp").set_class_engine(1, 1, 1, 1, "rys")
+    for bad in [(1, 1, 1, 1, "hgp"), (3, 3, 0, 0, "hgp")]:
+        with pytest.raises(fk.FockJKError) as e:
+            c.set_class_engine(*bad)
+        assert e.value.code == fk.FK_ERR_UNSUPPORTED
+    with pytest.raises(fk.FockJKError) as e:
+        c.set_class_engine(1, 0, 0, 0, 2)
+    assert e.value.code == fk.FK_ERR_ARG
+    with pytest.raises(fk.FockJKError) as e:
+        c.set_class_engine(0, 1, 0, 0, "rys")
+    assert e.value.code == fk.FK_ERR_ARG
+
+
 def test_one_electron_matches_oracle():
     s = _rand_sys(22, lmax=3, natom=3, kmax=3)
     s["charge"] = 1  # three H nuclei: keep the electron count even
