@@ -44,12 +44,12 @@ def _kernel_source_hash():
     return h.hexdigest()
 
 
-def _traffic(kernel_name, workload, schedule="default"):
+def _traffic(kernel_name, workload, schedule, engine="rys"):
     """HBM bytes per launch of the named kernel from profiles/roofline_traffic.json
     (rocprofv3 FETCH_SIZE and WRITE_SIZE, each scaled by the same counter on a
-    plain copy of known size), or None when absent, taken on other kernels or
-    under another schedule of the class ("default", or [bra block, kets per
-    tile, grid fraction])."""
+    plain copy of known size), or None when absent, taken on other kernels,
+    under another schedule of the class ([bra block, kets per tile, grid
+    fraction]) or with the other integral engine."""
     path = os.path.join(HERE, "profiles", "roofline_traffic.json")
     if not os.path.exists(path):
         return None
@@ -58,7 +58,7 @@ def _traffic(kernel_name, workload, schedule="default"):
     if t.get("source_sha256") != _kernel_source_hash() or t.get("workload") != workload:
         return None
     for k in t.get("kernels", []):
-        if k["kernel"] == kernel_name and k.get("schedule", "default") == schedule:
+        if k["kernel"] == kernel_name and k.get("schedule") == list(schedule) and k.get("engine", "rys") == engine:
             return k["fetch_bytes_per_launch"] * t["copy_scale_fetch"] + k["write_bytes_per_launch"] * t["copy_scale_write"]
     return None
 
@@ -359,21 +359,39 @@ def _hgp_everywhere(fk, c):
                                 raise
 
 
+SCHED_DIR = os.path.join(HERE, "paper_2407_21445_amd", "schedules")
+
+
+def _load_cached(ctx, key, arch, args):
+    """Schedule source of a context: 'default' (--no-autotune), 'cache' (the
+    committed schedules of this workload and architecture, loaded here) or
+    'autotune' (no cache, or --retune)."""
+    if not args.autotune:
+        return "default"
+    path = os.path.join(SCHED_DIR, f"{key}.{arch}.txt")
+    if args.retune or not os.path.exists(path):
+        return "autotune"
+    ctx.load_schedules(path)
+    return "cache"
+
+
+def _save_tuned(ctx, key, arch, args):
+    if args.save_schedules:
+        os.makedirs(args.save_schedules, exist_ok=True)
+        ctx.save_schedules(os.path.join(args.save_schedules, f"{key}.{arch}.txt"))
+
+
 def _tune(ctx, Dd, stream):
     t0 = time.perf_counter()
     rep = ctx.autotune(Dd, reps=2, stream=stream.cuda_stream)
-    return rep, {"seconds": time.perf_counter() - t0, "configurations": rep["configurations"],
+    return rep, {"source": "autotune", "seconds": time.perf_counter() - t0, "configurations": rep["configurations"],
                  "class_ms_sum_default": rep["build_ms_default"], "class_ms_sum_tuned": rep["build_ms_tuned"],
                  "changed_classes": int(sum(r["changed"] for r in rep["classes"]))}
 
 
-def _sched_of(c, tuned_rows, pinned):
-    sched = pinned.get(tuple(c["class"]), "default")
-    for r in tuned_rows:
-        if (r["la"], r["lb"], r["lc"], r["ld"]) == tuple(c["class"]) and r["precision"] == c["precision"] \
-                and r["changed"]:
-            sched = [r["bra_block"], r["kets_per_tile"], r["grid_fraction"]]
-    return sched
+def _sched_of(c):
+    """The schedule a class launch ran with: [bra block, kets per tile, grid fraction]."""
+    return [int(c["schedule"][0]), int(c["schedule"][1]), float(c["schedule"][2])]
 
 
 def bench_single(args, torch, fk):
@@ -386,7 +404,9 @@ def bench_single(args, torch, fk):
     stream = torch.cuda.current_stream(dev)
     pinned = {}
 
-    def make(tau_fp32):
+    arch = torch.cuda.get_device_properties(dev).gcnArchName.split(":")[0]
+
+    def make(tau_fp32, key):
         c = fk.FockJK(0).set_system(sys_)
         for spec in args.schedule:
             v = spec.split(",")
@@ -397,9 +417,10 @@ def bench_single(args, torch, fk):
             pinned[cls] = list(sch)
         if args.engine == "hgp":
             _hgp_everywhere(fk, c)
-        return c.build_quartets(tau=args.tau, tau_prim=args.tau_prim, tau_fp32=tau_fp32)
+        src = _load_cached(c, key, arch, args)
+        return c.build_quartets(tau=args.tau, tau_prim=args.tau_prim, tau_fp32=tau_fp32), src
 
-    ctx = make(0.0)
+    ctx, src64 = make(0.0, f"{args.workload}_fp64")
     info = ctx.info()
     S, T, V, _ = ctx.one_electron()
     D = _core_density(S, T + V, sys_["nelec"] // 2)
@@ -407,10 +428,11 @@ def bench_single(args, torch, fk):
     J = torch.empty_like(Dd)
     K = torch.empty_like(Dd)
     _progress(f"{desc}: lists built ({info['nquartet_schwarz']} Schwarz quartets)")
-    tune, tuned_rows = None, []
-    if args.autotune:
+    tune, tuned_rows = {"source": src64}, []
+    if src64 == "autotune":
         rep, tune = _tune(ctx, Dd, stream)
         tuned_rows = rep["classes"]
+        _save_tuned(ctx, f"{args.workload}_fp64", arch, args)
         _progress(f"FP64 schedules tuned in {tune['seconds']:.0f} s")
     ms = _time_builds(torch, ctx, Dd, J, K, stream, args.warmup, args.steps)
     st = ctx.stats()
@@ -422,7 +444,7 @@ def bench_single(args, torch, fk):
     c = s2["classes"][i]
     cflops = c["prim_quartets"] * c["flops_per_prim"] + c["quartets"] * c["flops_per_quartet"]
     achieved = cflops / (cls_ms[i] * 1e-3) / 1e12
-    sched = _sched_of(c, tuned_rows, pinned)
+    sched = _sched_of(c)
     out = {
         "metric": METRIC, "value": 1000.0 / ms, "unit": "builds/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
@@ -437,22 +459,23 @@ def bench_single(args, torch, fk):
         "flops_per_build": st["flops_total"], "tflops_build": st["flops_total"] / (ms * 1e-3) / 1e12,
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP64_VALU, "unit": "TFLOP/s",
                      "frac": achieved / PEAK_FP64_VALU,
-                     "traffic": _traffic(f"J/K class {_cname(c)}", args.workload, sched),
+                     "traffic": _traffic(f"J/K class {_cname(c)}", args.workload, sched, ("rys", "hgp")[c["engine"]]),
                      "kernel": f"J/K class {_cname(c)}", "kernel_ms": float(cls_ms[i]), "schedule": sched,
                      "engine": ("rys", "hgp")[c["engine"]],
                      "class_share": float(cls_ms[i] / cls_ms.sum()),
                      "flops_per_launch": cflops, "quartets_per_launch": c["quartets"],
                      "prim_quartets_per_launch": c["prim_quartets"]},
     }
-    if tune:
-        out["autotune"] = tune
+    out["schedules"] = tune
     ref = None
     if args.tau_fp32 > 0:
         # the same build with the precision split: FP32 recurrences for the
         # waves whose quartets all have G_ab G_cd D_max below tau_fp32
-        mx = make(args.tau_fp32)
-        if args.autotune:
+        mx, src_mx = make(args.tau_fp32, f"{args.workload}_mixed")
+        tune_mx = {"source": src_mx}
+        if src_mx == "autotune":
             _, tune_mx = _tune(mx, Dd, stream)
+            _save_tuned(mx, f"{args.workload}_mixed", arch, args)
         Jm = torch.empty_like(Dd)
         Km = torch.empty_like(Dd)
         ms_mx = _time_builds(torch, mx, Dd, Jm, Km, stream, args.warmup, args.steps)
@@ -474,8 +497,7 @@ def bench_single(args, torch, fk):
                         "max_abs_dJ": float(np.max(np.abs(dJ))), "max_abs_dK": float(np.max(np.abs(dK))),
                         "dE_one_build": float(0.5 * np.sum(D * dJ) - 0.25 * np.sum(D * dK)),
                         "roofline_frac_t_ideal": t_ideal / (float(cms.sum()) * 1e-3)}
-        if args.autotune:
-            out["mixed"]["autotune"] = tune_mx
+        out["mixed"]["schedules"] = tune_mx
         _progress(f"mixed build {ms_mx:.2f} ms ({n32 / max(1, stm['quartets']):.2f} FP32 quartets)")
         ref = mx
     if not args.no_scf:
@@ -512,16 +534,19 @@ def bench_single(args, torch, fk):
         # the C20H42 / 6-31G*-type workload, FP64, as a second line of reference
         from synth import workloads as wl
         s2y = wl.c20h42_631gs()
-        c2 = fk.FockJK(0).set_system(s2y).build_quartets(tau=args.tau, tau_prim=args.tau_prim)
+        c2 = fk.FockJK(0).set_system(s2y)
+        src2 = _load_cached(c2, "c20h42_fp64", arch, args)
+        c2.build_quartets(tau=args.tau, tau_prim=args.tau_prim)
         S2, T2, V2, _ = c2.one_electron()
         D2 = torch.tensor(_core_density(S2, T2 + V2, s2y["nelec"] // 2), dtype=torch.float64, device=dev)
         J2, K2 = torch.empty_like(D2), torch.empty_like(D2)
-        if args.autotune:
+        if src2 == "autotune":
             _tune(c2, D2, stream)
+            _save_tuned(c2, "c20h42_fp64", arch, args)
         ms2 = _time_builds(torch, c2, D2, J2, K2, stream, 3, 20)
         st2 = c2.stats()
         out["c20h42"] = {"workload": "C20H42 all-trans (0.02 A jitter), 6-31G*-type, 384 Cartesian bf, fp64",
-                         "builds_per_s": 1000.0 / ms2, "ms_per_step": ms2,
+                         "builds_per_s": 1000.0 / ms2, "ms_per_step": ms2, "schedules": src2,
                          "quartets_per_s": st2["quartets"] / (ms2 * 1e-3)}
         _progress(f"C20H42 build {ms2:.2f} ms")
     if not args.no_cpu_baseline:
@@ -553,7 +578,11 @@ def main():
     ap.add_argument("--no-scf", action="store_true", help="skip the SCF runs reported beside the build rate")
     ap.add_argument("--no-extra", action="store_true", help="skip the C20H42 reference line")
     ap.add_argument("--no-autotune", dest="autotune", action="store_false",
-                    help="time the default kernel schedules (the autotuner runs by default, before timing)")
+                    help="time the default kernel schedules (by default the committed schedule cache of the "
+                         "workload is loaded, or the autotuner runs before timing if there is none)")
+    ap.add_argument("--retune", action="store_true", help="run the autotuner even where a schedule cache exists")
+    ap.add_argument("--save-schedules", metavar="DIR", default="",
+                    help="write the schedules the autotuner chose to DIR/<workload>_<leg>.<arch>.txt")
     ap.add_argument("--nmol", type=int, default=8, help="molecules of the organic batch (--workload c4)")
     ap.add_argument("--batch-scf", action="store_true", help="--workload c4: also run the batched SCF")
     ap.add_argument("--batch-density", choices=("core", "sad"), default="core",

@@ -133,6 +133,9 @@ typedef struct {
                                              pairs.  prim_quartets * team_size / prim_slots is
                                              the lane utilisation of the primitive loops */
     int     engine[FK_MAX_QCLASS];        /* FK_ENGINE_RYS or FK_ENGINE_HGP */
+    int     bra_block[FK_MAX_QCLASS];     /* the schedule in effect (fk_set_class_schedule) */
+    int     kets_per_tile[FK_MAX_QCLASS];
+    double  grid_fraction[FK_MAX_QCLASS];
 } fk_stats_t;
 
 /* ---- context ---------------------------------------------------------- */
@@ -248,6 +251,22 @@ int fk_set_class_schedule(fk_ctx *ctx, int la, int lb, int lc, int ld, int bra_b
 #define FK_ENGINE_RYS 0
 #define FK_ENGINE_HGP 1
 int fk_set_class_engine(fk_ctx *ctx, int la, int lb, int lc, int ld, int engine);
+
+/* Schedule cache: fk_save_schedules writes every schedule and engine set on
+ * the context (by fk_set_class_schedule, fk_set_class_engine, fk_autotune or
+ * an earlier load) to a text file, one line per class
+ * ("class la lb lc ld bra_block kets_per_tile grid_fraction engine") after a
+ * line naming the device architecture ("arch gfx950"; "host" for a context
+ * without a device).  fk_load_schedules reads such a file into the context,
+ * on top of the schedules already set; FK_ERR_UNSUPPORTED if the file was
+ * written for another architecture or names a class or engine this library
+ * does not build, FK_ERR_ARG for a malformed file (the context is then left
+ * unchanged).  Like fk_set_class_schedule, a load takes effect at the next
+ * fk_build_quartets.  A schedule set tuned on one workload suits workloads
+ * of the same basis family and size; it never changes results beyond rounding
+ * order. */
+int fk_save_schedules(fk_ctx *ctx, const char *path);
+int fk_load_schedules(fk_ctx *ctx, const char *path);
 
 typedef struct {
     int    nclass;                      /* class launches after tuning (as fk_stats) */

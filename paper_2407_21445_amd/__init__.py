@@ -58,7 +58,8 @@ class Stats(ctypes.Structure):
                 ("flops_per_quartet", ctypes.c_double * _Q), ("flops_total", ctypes.c_double),
                 ("class_ms", ctypes.c_double * _Q), ("tiles", ctypes.c_int64 * _Q),
                 ("team_size", ctypes.c_int * _Q), ("precision", ctypes.c_int * _Q), ("prim_slots", ctypes.c_int64 * _Q),
-                ("engine", ctypes.c_int * _Q)]
+                ("engine", ctypes.c_int * _Q), ("bra_block", ctypes.c_int * _Q), ("kets_per_tile", ctypes.c_int * _Q),
+                ("grid_fraction", ctypes.c_double * _Q)]
 
 
 class TuneReport(ctypes.Structure):
@@ -119,6 +120,8 @@ _sig = {
     "fk_run_scf_batch": ([_P, ctypes.POINTER(ScfOpts), _P, _P], _I),
     "fk_set_class_schedule": ([_P, _I, _I, _I, _I, _I, _I, _D], _I),
     "fk_set_class_engine": ([_P, _I, _I, _I, _I, _I], _I),
+    "fk_save_schedules": ([_P, ctypes.c_char_p], _I),
+    "fk_load_schedules": ([_P, ctypes.c_char_p], _I),
     "fk_autotune": ([_P, _P, _U, _I, _P, ctypes.POINTER(TuneReport)], _I),
     "fk_guess_pairs": ([_P, _P, _P, _P], _I),
     "fk_guess_targets": ([_P, _P, _P], _I),
@@ -305,7 +308,8 @@ class FockJK:
                         "prim_quartets": s.prim_quartets[i], "flops_per_prim": s.flops_per_prim[i],
                         "flops_per_quartet": s.flops_per_quartet[i], "ms": s.class_ms[i],
                         "tiles": s.tiles[i], "team_size": s.team_size[i], "precision": s.precision[i],
-                        "prim_slots": s.prim_slots[i], "engine": s.engine[i]})
+                        "prim_slots": s.prim_slots[i], "engine": s.engine[i],
+                        "schedule": [s.bra_block[i], s.kets_per_tile[i], s.grid_fraction[i]]})
         return {"classes": out, "flops_total": s.flops_total,
                 "quartets": sum(c["quartets"] for c in out), "prim_quartets": sum(c["prim_quartets"] for c in out)}
 
@@ -346,6 +350,14 @@ class FockJK:
         """engine: "rys" / "hgp" (or ENGINE_RYS / ENGINE_HGP) for the class."""
         e = {"rys": ENGINE_RYS, "hgp": ENGINE_HGP}.get(engine, engine)
         self._check(_lib.fk_set_class_engine(self._ctx, int(la), int(lb), int(lc), int(ld), int(e)))
+        return self
+
+    def save_schedules(self, path):
+        self._check(_lib.fk_save_schedules(self._ctx, os.fsencode(path)))
+        return self
+
+    def load_schedules(self, path):
+        self._check(_lib.fk_load_schedules(self._ctx, os.fsencode(path)))
         return self
 
     def autotune(self, D, reps=2, stream=None):

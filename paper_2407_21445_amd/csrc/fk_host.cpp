@@ -53,6 +53,7 @@ struct QuartetClass {
     int64_t prim_slots;       // primitive-quartet slots the waves step through
     int blocks_per_cu;
     double grid_frac = 1.0;   // share of the resident-workgroup grid launched
+    int bra_block = 1, kets_per_tile = 64;  // the schedule in effect
     int bra_slot;             // doubles per wave of staged bra primitive records
     int prec;                 // 0: FP64 launch, 1: FP32 launch of the precision split
     int engine = 0;           // 0: Rys quadrature, 1: HGP (classes with info.hgp only)
@@ -66,6 +67,7 @@ struct fk_ctx {
     int device = -1;
     std::string err;
     int ncu = 0;
+    std::string arch = "host";  // device architecture without feature suffixes (e.g. gfx950); "host" without one
     // geometry
     int natom = 0, charge = 0, nelec = 0;
     std::vector<int> Z;
@@ -596,6 +598,8 @@ int fk_create(fk_ctx **out, int device)
             return FK_ERR_HIP;
         }
         c->ncu = prop.multiProcessorCount;
+        c->arch = prop.gcnArchName;
+        c->arch = c->arch.substr(0, c->arch.find(':'));
         if (dev_upload(c, c->d_rys, rys_staged_host(), (size_t)rys_staged_total())) {
             g_create_err = c->err;
             delete c;
@@ -899,6 +903,8 @@ int fk_build_quartets(fk_ctx *c, const fk_screen_opts *o)
             // bra blocks: the class's pairs ordered by (first shell, G descending),
             // cut into runs of at most bmax pairs with the same first shell
             const int bmax = std::max(1, std::min(sch.bb > 0 ? std::min(sch.bb, FK_MAX_BRA_BLOCK) : bra_block, qc.info.bra_block));
+            qc.bra_block = bmax;
+            qc.kets_per_tile = tile_kets;
             std::vector<int> ord(LP.size());
             std::iota(ord.begin(), ord.end(), 0);
             std::stable_sort(ord.begin(), ord.end(), [&](int x, int y) {
@@ -1228,6 +1234,9 @@ int fk_stats(fk_ctx *c, fk_stats_t *s)
         s->flops_per_prim[i] = q.flops_prim();
         s->flops_per_quartet[i] = q.flops_quartet();
         s->engine[i] = q.engine;
+        s->bra_block[i] = q.bra_block;
+        s->kets_per_tile[i] = q.kets_per_tile;
+        s->grid_fraction[i] = q.grid_frac;
         s->tiles[i] = q.ntile;
         s->team_size[i] = q.info.wave_per_quartet == 3 ? 64 : std::max(1, q.info.team_size);
         s->precision[i] = q.prec ? 32 : 64;
@@ -1289,6 +1298,83 @@ int fk_set_class_engine(fk_ctx *c, int la, int lb, int lc, int ld, int engine)
         return fail(c, FK_ERR_UNSUPPORTED, "fk_set_class_engine: the HGP engine is not built for class (%d%d|%d%d)",
                     la, lb, lc, ld);
     c->sched[P * NPC + Q].eng = engine;
+    return FK_OK;
+}
+
+int fk_save_schedules(fk_ctx *c, const char *path)
+{
+    if (!c) return FK_ERR_ARG;
+    if (!path) return fail(c, FK_ERR_ARG, "fk_save_schedules: null path");
+    FILE *f = std::fopen(path, "w");
+    if (!f) return fail(c, FK_ERR_ARG, "fk_save_schedules: cannot write %s", path);
+    std::fprintf(f, "# fockjk class schedules: la lb lc ld bra_block kets_per_tile grid_fraction engine\n");
+    std::fprintf(f, "arch %s\n", c->arch.c_str());
+    for (const auto &kv : c->sched) {
+        int l[4] = {0, 0, 0, 0};
+        for (int k = 0; k < 2; ++k) {
+            const int pc = k == 0 ? kv.first / NPC : kv.first % NPC;
+            int la = 0;
+            while (pair_class(la + 1, 0) <= pc) ++la;
+            l[2 * k] = la;
+            l[2 * k + 1] = pc - pair_class(la, 0);
+        }
+        const auto &x = kv.second;
+        std::fprintf(f, "class %d %d %d %d %d %d %.17g %d\n", l[0], l[1], l[2], l[3], x.bb, x.kt, x.gf, x.eng);
+    }
+    const bool ok = std::ferror(f) == 0;
+    if (std::fclose(f) != 0 || !ok) return fail(c, FK_ERR_ARG, "fk_save_schedules: write error on %s", path);
+    return FK_OK;
+}
+
+int fk_load_schedules(fk_ctx *c, const char *path)
+{
+    if (!c) return FK_ERR_ARG;
+    if (!path) return fail(c, FK_ERR_ARG, "fk_load_schedules: null path");
+    FILE *f = std::fopen(path, "r");
+    if (!f) return fail(c, FK_ERR_ARG, "fk_load_schedules: cannot read %s", path);
+    std::map<int, fk_ctx::ClassSched> sched = c->sched;
+    char line[512];
+    int lineno = 0;
+    bool arch_ok = false;
+    int rc = FK_OK;
+    while (rc == FK_OK && std::fgets(line, sizeof line, f)) {
+        ++lineno;
+        char word[32] = {0};
+        if (std::sscanf(line, "%31s", word) != 1 || word[0] == '#') continue;
+        if (std::strcmp(word, "arch") == 0) {
+            char a[64] = {0};
+            if (std::sscanf(line, "arch %63s", a) != 1) { rc = fail(c, FK_ERR_ARG, "fk_load_schedules: %s:%d: bad arch line", path, lineno); break; }
+            if (c->arch != a) { rc = fail(c, FK_ERR_UNSUPPORTED, "fk_load_schedules: %s is for %s, the device is %s", path, a, c->arch.c_str()); break; }
+            arch_ok = true;
+        } else if (std::strcmp(word, "class") == 0) {
+            int la, lb, lc, ld, bb, kt, eng;
+            double gf;
+            if (std::sscanf(line, "class %d %d %d %d %d %d %lf %d", &la, &lb, &lc, &ld, &bb, &kt, &gf, &eng) != 8) {
+                rc = fail(c, FK_ERR_ARG, "fk_load_schedules: %s:%d: expected 8 fields", path, lineno);
+                break;
+            }
+            if (!arch_ok) { rc = fail(c, FK_ERR_ARG, "fk_load_schedules: %s: class line before the arch line", path); break; }
+            if (la < lb || lc < ld || la > FK_MAX_L || lc > FK_MAX_L || lb < 0 || ld < 0 || bb < 0 ||
+                bb > FK_MAX_BRA_BLOCK || kt < 0 || kt > 64 || !(gf > 0 && gf <= 4) || (eng != 0 && eng != 1)) {
+                rc = fail(c, FK_ERR_ARG, "fk_load_schedules: %s:%d: value out of range", path, lineno);
+                break;
+            }
+            int P = pair_class(la, lb), Q = pair_class(lc, ld);
+            if (P < Q) std::swap(P, Q);
+            FkClassInfo info;
+            if (fk_kernels_class_info(P, Q, &info) || (eng == 1 && !info.hgp)) {
+                rc = fail(c, FK_ERR_UNSUPPORTED, "fk_load_schedules: %s:%d: class or engine not built", path, lineno);
+                break;
+            }
+            sched[P * NPC + Q] = fk_ctx::ClassSched{bb, kt, gf, eng};
+        } else {
+            rc = fail(c, FK_ERR_ARG, "fk_load_schedules: %s:%d: unknown record '%s'", path, lineno, word);
+        }
+    }
+    std::fclose(f);
+    if (rc) return rc;
+    if (!arch_ok) return fail(c, FK_ERR_ARG, "fk_load_schedules: %s has no arch line", path);
+    c->sched = sched;
     return FK_OK;
 }
 

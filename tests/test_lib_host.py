@@ -420,7 +420,8 @@ def test_sad_density_mixed_bases():
 
 def test_bench_traffic_follows_the_schedule(tmp_path, monkeypatch):
     """bench.py reports the committed counter traffic only for the kernel
-    sources and the class schedule it was measured under."""
+    sources, the class schedule and the integral engine it was measured
+    under."""
     import importlib.util
     root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
     spec = importlib.util.spec_from_file_location("bench_mod", os.path.join(root, "bench.py"))
@@ -428,10 +429,12 @@ def test_bench_traffic_follows_the_schedule(tmp_path, monkeypatch):
     spec.loader.exec_module(bench)
     t = {"workload": "c20h42", "source_sha256": bench._kernel_source_hash(), "copy_scale_fetch": 2.0,
          "copy_scale_write": 1.0,
-         "kernels": [{"kernel": "J/K class (ps|ss)", "schedule": "default", "fetch_bytes_per_launch": 10.0,
+         "kernels": [{"kernel": "J/K class (ps|ss)", "schedule": [8, 64, 1.0], "fetch_bytes_per_launch": 10.0,
                       "write_bytes_per_launch": 100.0},
                      {"kernel": "J/K class (ps|ss)", "schedule": [8, 64, 4.0], "fetch_bytes_per_launch": 20.0,
                       "write_bytes_per_launch": 300.0},
+                     {"kernel": "J/K class (ps|ss)", "schedule": [8, 64, 1.0], "engine": "hgp",
+                      "fetch_bytes_per_launch": 30.0, "write_bytes_per_launch": 300.0},
                      {"kernel": "J/K class (ss|ss)", "fetch_bytes_per_launch": 1.0, "write_bytes_per_launch": 1.0}]}
     os.makedirs(tmp_path / "profiles")
     with open(tmp_path / "profiles" / "roofline_traffic.json", "w") as f:
@@ -440,13 +443,47 @@ def test_bench_traffic_follows_the_schedule(tmp_path, monkeypatch):
     real_hash = bench._kernel_source_hash()
     monkeypatch.setattr(bench, "HERE", str(tmp_path))
     monkeypatch.setattr(bench, "_kernel_source_hash", lambda: real_hash)
-    assert bench._traffic("J/K class (ps|ss)", "c20h42") == 120.0
-    assert bench._traffic("J/K class (ps|ss)", "c20h42", [8, 64, 4.0]) == 340.0
+    assert bench._traffic("J/K class (ps|ss)", "c20h42", [8, 64, 1.0]) == 120.0
+    assert bench._traffic("J/K class (ps|ss)", "c20h42", (8, 64, 4.0)) == 340.0
+    assert bench._traffic("J/K class (ps|ss)", "c20h42", [8, 64, 1.0], "hgp") == 360.0
     assert bench._traffic("J/K class (ps|ss)", "c20h42", [8, 64, 2.0]) is None
-    assert bench._traffic("J/K class (ss|ss)", "c20h42") == 3.0   # no schedule field: default
-    assert bench._traffic("J/K class (ps|ss)", "water64") is None
+    assert bench._traffic("J/K class (ss|ss)", "c20h42", [8, 64, 1.0]) is None   # no schedule: never matched
+    assert bench._traffic("J/K class (ps|ss)", "water64", [8, 64, 1.0]) is None
     monkeypatch.setattr(bench, "_kernel_source_hash", lambda: "other sources")
-    assert bench._traffic("J/K class (ps|ss)", "c20h42") is None
+    assert bench._traffic("J/K class (ps|ss)", "c20h42", [8, 64, 1.0]) is None
+
+
+def test_schedule_cache_round_trip(tmp_path):
+    """fk_save_schedules / fk_load_schedules: the schedules and engines set
+    on one context reach another through the file; files for another
+    architecture, malformed lines and engines a class lacks are refused and
+    leave the context unchanged."""
+    s = _rand_sys(21, lmax=2, natom=4, kmax=2)
+    a = fk.FockJK(device=-1).set_system(s)
+    a.set_class_schedule(1, 0, 0, 0, 4, 0, 2.0).set_class_schedule(2, 2, 1, 1, 1, 16, 0.5)
+    a.set_class_engine(1, 0, 0, 0, "hgp")
+    p = str(tmp_path / "sched.txt")
+    a.save_schedules(p)
+    text = open(p).read()
+    assert "arch host" in text
+    assert "class 1 0 0 0 4 0 2 1" in text and "class 2 2 1 1 1 16 0.5 0" in text
+    b = fk.FockJK(device=-1).set_system(s).load_schedules(p)
+    p2 = str(tmp_path / "sched2.txt")
+    b.save_schedules(p2)
+    assert open(p2).read() == text
+    for bad, code in [("arch gfx942\nclass 1 0 0 0 4 0 2 0\n", fk.FK_ERR_UNSUPPORTED),
+                      ("arch host\nclass 1 0 0 0 4 0\n", fk.FK_ERR_ARG),
+                      ("arch host\nclass 1 1 1 1 4 0 1 1\n", fk.FK_ERR_UNSUPPORTED),
+                      ("class 1 0 0 0 4 0 2 0\n", fk.FK_ERR_ARG),
+                      ("arch host\nclass 0 1 0 0 4 0 2 0\n", fk.FK_ERR_ARG)]:
+        q = tmp_path / "bad.txt"
+        q.write_text(bad)
+        c = fk.FockJK(device=-1).set_system(s).load_schedules(p)
+        with pytest.raises(fk.FockJKError) as e:
+            c.load_schedules(str(q))
+        assert e.value.code == code, bad
+        c.save_schedules(p2)
+        assert open(p2).read() == text
 
 
 def test_class_kernel_choice():
