@@ -455,6 +455,9 @@ int validate_lists(fk_ctx *c)
                 T.ket_count < 1 || T.ket_count > 64)
                 return fail(c, FK_ERR_STATE, "internal: tile %lld is inconsistent", (long long)t);
             const FkBraBlock &B = c->blocks[T.blk];
+            if (B.count > qc.info.bra_block)
+                return fail(c, FK_ERR_STATE, "internal: tile %lld has %d bras, its class kernel takes %d",
+                            (long long)t, B.count, qc.info.bra_block);
             for (int j = 0; j < B.count; ++j)
                 if (c->pr_npp[c->blk_bra[B.first + j]] * FK_NFLD > qc.bra_slot || c->pr_cls[c->blk_bra[B.first + j]] != qc.P)
                     return fail(c, FK_ERR_STATE, "internal: tile %lld bra %d does not fit its class", (long long)t, j);

@@ -270,6 +270,111 @@ __device__ __forceinline__ int nth_bit(unsigned long long m, int n)
 }
 
 
+// Digestion of one bra's contracted quartets with the lane's ket (paper,
+// "Optimised GPU Implementation": the six Fock blocks of a quartet): scales the
+// integrals by the coincidence factors, forms X_J[a, b] (reduced over the wave
+// and added here) and the per-bra X_K[b, c], X_K[b, d] (flushed here), and adds
+// to the block sums X_K[a, c], X_K[a, d], X_J[c, d] of the caller.  Every lane
+// of the wave calls it (the flushes and the reduction are wave operations);
+// `active` marks the lanes whose quartet is computed.
+template <int LA, int LB, int LC, int LD, typename R>
+__device__ __forceinline__ void lpq_digest(R *acc, bool active, bool diag, int sa, int sb, int sc, int sd, int oa,
+                                           int ob, int oc, int od, int n, const double *__restrict Ds,
+                                           const double *dcd, double *kac, double *kad, double *jcd, double *XJ,
+                                           double *XK, double *s_stage, int lane, bool wj, bool wk, bool &any)
+{
+    using Q = fk::QClass<LA, LB, LC, LD>;
+    constexpr int NA = Q::NA, NB = Q::NB, NC = Q::NC, ND = Q::ND, NOUT = Q::NOUT;
+    const double fac = (sa == sb ? 0.5 : 1.0) * (sc == sd ? 0.5 : 1.0) * (diag ? 0.5 : 1.0);
+    double jab[NA * NB];
+#pragma unroll
+    for (int o = 0; o < NA * NB; ++o) jab[o] = 0.0;
+    if (active) {
+        any = true;
+#pragma unroll
+        for (int o = 0; o < NOUT; ++o) acc[o] *= (R)fac;
+    }
+    if (active && wj) {
+        double dab[NA * NB];
+#pragma unroll
+        for (int ia = 0; ia < NA; ++ia)
+#pragma unroll
+            for (int ib = 0; ib < NB; ++ib) dab[ia * NB + ib] = Ds[(size_t)(oa + ia) * n + ob + ib];
+        // X_J[a, b] partial (reduced over the wave below); X_J[c, d] block sum
+#pragma unroll
+        for (int ab = 0; ab < NA * NB; ++ab)
+#pragma unroll
+            for (int cd = 0; cd < NC * ND; ++cd) {
+                jab[ab] += acc[ab * NC * ND + cd] * dcd[cd];
+                jcd[cd] += acc[ab * NC * ND + cd] * dab[ab];
+            }
+    }
+    double kbc[NB * NC], kbd[NB * ND];
+#pragma unroll
+    for (int o = 0; o < NB * NC; ++o) kbc[o] = 0.0;
+#pragma unroll
+    for (int o = 0; o < NB * ND; ++o) kbd[o] = 0.0;
+    if (active && wk) {
+        double dbc[NB * NC], dbd[NB * ND];
+#pragma unroll
+        for (int ib = 0; ib < NB; ++ib) {
+#pragma unroll
+            for (int ic = 0; ic < NC; ++ic) dbc[ib * NC + ic] = Ds[(size_t)(ob + ib) * n + oc + ic];
+#pragma unroll
+            for (int id = 0; id < ND; ++id) dbd[ib * ND + id] = Ds[(size_t)(ob + ib) * n + od + id];
+        }
+        // X_K[a, c] += v D_bd and X_K[a, d] += v D_bc (block sums)
+#pragma unroll
+        for (int ia = 0; ia < NA; ++ia)
+#pragma unroll
+            for (int ib = 0; ib < NB; ++ib)
+#pragma unroll
+                for (int ic = 0; ic < NC; ++ic)
+#pragma unroll
+                    for (int id = 0; id < ND; ++id) {
+                        const double v = acc[((ia * NB + ib) * NC + ic) * ND + id];
+                        kac[ia * NC + ic] += v * dbd[ib * ND + id];
+                        kad[ia * ND + id] += v * dbc[ib * NC + ic];
+                    }
+        // X_K[b, c] += v D_ad and X_K[b, d] += v D_ac (per bra)
+#pragma unroll
+        for (int ib = 0; ib < NB; ++ib) {
+#pragma unroll
+            for (int ic = 0; ic < NC; ++ic) {
+                double s = 0.0;
+#pragma unroll
+                for (int ia = 0; ia < NA; ++ia)
+#pragma unroll
+                    for (int id = 0; id < ND; ++id)
+                        s += acc[((ia * NB + ib) * NC + ic) * ND + id] * Ds[(size_t)(oa + ia) * n + od + id];
+                kbc[ib * NC + ic] = s;
+            }
+#pragma unroll
+            for (int id = 0; id < ND; ++id) {
+                double s = 0.0;
+#pragma unroll
+                for (int ia = 0; ia < NA; ++ia)
+#pragma unroll
+                    for (int ic = 0; ic < NC; ++ic)
+                        s += acc[((ia * NB + ib) * NC + ic) * ND + id] * Ds[(size_t)(oa + ia) * n + oc + ic];
+                kbd[ib * ND + id] = s;
+            }
+        }
+    }
+    if (wk) {
+        flush_sym<NB, NC>(XK, n, ob, oc, kbc, s_stage, lane);
+        flush_sym<NB, ND>(XK, n, ob, od, kbd, s_stage, lane);
+    }
+    // all lanes (active or not) take part in the wave reduction of X_J[a, b]
+    if (wj) {
+#pragma unroll
+        for (int ab = 0; ab < NA * NB; ++ab) {
+            const double s = wave_sum(jab[ab]);
+            if (lane == 0) atomic_add(&XJ[(size_t)(oa + ab / NB) * n + ob + ab % NB], 2.0 * s);
+        }
+    }
+}
+
 // ---------------------------------------------------------------- lpq ----
 // One wave per tile: a block of bras (a, b_j) sharing the first shell a, and up
 // to 64 kets.  Lane i holds ket i and computes the contracted quartets
@@ -316,6 +421,29 @@ struct LpqMinBlocks<2, 1, 0, 0> {
 template <>
 struct LpqMinBlocks<3, 0, 0, 0> {
     static constexpr int value = 2;
+};
+
+// Bra block of the ket-outer loop order (0: bra-outer).  With the bras of a
+// tile outer, each bra re-reads the tile's ket primitive records; the 64 kets'
+// records of a wave (up to ~90 KB) do not survive in L2 while hundreds of
+// waves per XCD stream theirs, so every bra fetches them again from memory.
+// Ket-outer, each ket primitive record is read once per tile and applied to
+// every bra of the block, whose contracted integrals stay in registers (NBK x
+// NOUT accumulators per lane).  Measured on (H2O)64 cc-pVDZ-type: (ps|ss)
+// 47.0 -> 41.7 ms with blocks of 8 (its registers also drop to three waves per
+// SIMD); 16 bras cost (ps|ss) a wave per SIMD (51.8 ms); (ps|ps) and (pp|ss)
+// lose with any block (32.8 -> 36.3 ms at 4 bras, 47.4 ms at 2).
+template <int LA, int LB, int LC, int LD>
+struct LpqKetOuter {
+    static constexpr int value = 0;
+};
+template <>
+struct LpqKetOuter<0, 0, 0, 0> {
+    static constexpr int value = 8;
+};
+template <>
+struct LpqKetOuter<1, 0, 0, 0> {
+    static constexpr int value = 8;
 };
 
 // Doubles per wave of the lane kernel's LDS stage for flush_block: the largest
@@ -384,7 +512,95 @@ __global__ void __launch_bounds__(FK_BLOCK, (LpqMinBlocks<LA, LB, LC, LD>::value
 #pragma unroll
         for (int o = 0; o < NC * ND; ++o) jcd[o] = 0.0;
         bool any = false;
+        constexpr int NBK = LpqKetOuter<LA, LB, LC, LD>::value;
 
+        if constexpr (NBK > 0) {
+            // ket-outer: screen every bra of the block first, then one pass over
+            // the ket's primitives for all of them, then the digestion per bra
+            using H = fk::HgpClass<LA, LB, LC, LD>;
+            constexpr int NACC = ENG == 0 ? NOUT : H::NACC;
+            const int nb = blk.count;  // at most NBK: the class reports it as its largest bra block
+            unsigned act = 0u;
+            int ppo[NBK], bnpp[NBK];
+            R acck[NBK][NACC];
+#pragma unroll
+            for (int jb = 0; jb < NBK; ++jb) {
+#pragma unroll
+                for (int o = 0; o < NACC; ++o) acck[jb][o] = (R)0;
+                ppo[jb] = 0;
+                bnpp[jb] = 0;
+                if (jb < nb) {
+                    const int bra = a.blk_bra[blk.first + jb];
+                    const int bpos = a.blk_pos[blk.first + jb];
+                    const bool active = screen_lane<R>(a, inrange && (!same || pos <= bpos), a.pair_G[bra] * Kt.G,
+                                                       Dsh, ns, sa, a.pair_sb[bra], sc, sd);
+                    ppo[jb] = __builtin_amdgcn_readfirstlane(a.pair_ppoff[bra]);
+                    bnpp[jb] = __builtin_amdgcn_readfirstlane(a.pair_npp[bra]);
+                    const int nact = __popcll(__ballot(active));
+                    cq += nact;
+                    cp += (unsigned long long)nact * bnpp[jb] * g.npp;
+                    if (active) act |= 1u << jb;
+                }
+            }
+            if (act) {
+                fk::PrimPair qn = load_ket_pp(a.ppT, g, 0, r);
+                for (int j = 0; j < g.npp; ++j) {
+                    const fk::PrimPair q = qn;
+                    if (j + 1 < g.npp) qn = load_ket_pp(a.ppT, g, j + 1, r);
+#pragma unroll
+                    for (int jb = 0; jb < NBK; ++jb) {
+                        if (jb < nb && ((act >> jb) & 1u)) {
+                            const fk_const_ptr ab = (fk_const_ptr)(a.pair_AB + 3 * a.blk_bra[blk.first + jb]);
+                            const double AB[3] = {ab[0], ab[1], ab[2]};
+                            if constexpr (ENG == 0) {
+                                constexpr bool PAIR = NOUT <= FK_LPQ_PAIR_NOUT;
+                                int i = 0;
+                                if constexpr (PAIR)
+                                    for (; i + 1 < bnpp[jb]; i += 2) {
+                                        const fk::PrimPair p0 = sload_pp(a.pp, ppo[jb] + i);
+                                        const fk::PrimPair p1 = sload_pp(a.pp, ppo[jb] + i + 1);
+                                        fk::rys_prim_all<LA, LB, LC, LD, R, true>(s_tab, p0, q, AB, Kt.CD, acck[jb]);
+                                        fk::rys_prim_all<LA, LB, LC, LD, R, true>(s_tab, p1, q, AB, Kt.CD, acck[jb]);
+                                    }
+                                for (; i < bnpp[jb]; ++i)
+                                    fk::rys_prim_all<LA, LB, LC, LD, R, PAIR>(s_tab, sload_pp(a.pp, ppo[jb] + i), q,
+                                                                              AB, Kt.CD, acck[jb]);
+                            } else {
+                                for (int i = 0; i < bnpp[jb]; ++i)
+                                    fk::hgp_prim<LA, LB, LC, LD, R>(s_tab, sload_pp(a.pp, ppo[jb] + i), q, acck[jb]);
+                            }
+                        }
+                    }
+                }
+            }
+            // digestion, one bra at a time: the block's accumulators move down
+            // one slot per bra, so the loop body reads slot 0 only
+            for (int jb = 0; jb < nb; ++jb) {
+                const int bra = a.blk_bra[blk.first + jb];
+                const int bpos = a.blk_pos[blk.first + jb];
+                const int sb = a.pair_sb[bra];
+                const bool active = ((act >> jb) & 1u) != 0u;
+                R acc[NOUT];
+                if constexpr (ENG == 0) {
+#pragma unroll
+                    for (int o = 0; o < NOUT; ++o) acc[o] = acck[0][o];
+                } else {
+#pragma unroll
+                    for (int o = 0; o < NOUT; ++o) acc[o] = (R)0;
+                    if (active) {
+                        const double AB[3] = {a.pair_AB[3 * bra], a.pair_AB[3 * bra + 1], a.pair_AB[3 * bra + 2]};
+                        fk::hgp_hrr<LA, LB, LC, LD, R>(acck[0], AB, Kt.CD, acc);
+                    }
+                }
+#pragma unroll
+                for (int k = 0; k + 1 < NBK; ++k)
+#pragma unroll
+                    for (int o = 0; o < NACC; ++o) acck[k][o] = acck[k + 1][o];
+                if (__ballot(active) == 0ull) continue;
+                lpq_digest<LA, LB, LC, LD, R>(acc, active, same && pos == bpos, sa, sb, sc, sd, oa, shbf[sb], oc,
+                                              od, n, Ds, dcd, kac, kad, jcd, XJ, XK, s_stage, lane, wj, wk, any);
+            }
+        } else
         for (int jb = 0; jb < blk.count; ++jb) {
             const int bra = a.blk_bra[blk.first + jb];
             const int bpos = a.blk_pos[blk.first + jb];
@@ -445,95 +661,8 @@ __global__ void __launch_bounds__(FK_BLOCK, (LpqMinBlocks<LA, LB, LC, LD>::value
                 }
             }
             const bool diag = same && pos == bpos;
-            const double fac = (sa == sb ? 0.5 : 1.0) * (sc == sd ? 0.5 : 1.0) * (diag ? 0.5 : 1.0);
-            const int ob = shbf[sb];
-            double jab[NA * NB];
-#pragma unroll
-            for (int o = 0; o < NA * NB; ++o) jab[o] = 0.0;
-            if (active) {
-                any = true;
-#pragma unroll
-                for (int o = 0; o < NOUT; ++o) acc[o] *= (R)fac;
-            }
-            if (active && wj) {
-                double dab[NA * NB];
-#pragma unroll
-                for (int ia = 0; ia < NA; ++ia)
-#pragma unroll
-                    for (int ib = 0; ib < NB; ++ib) dab[ia * NB + ib] = Ds[(size_t)(oa + ia) * n + ob + ib];
-                // X_J[a, b] partial (reduced over the wave below); X_J[c, d] block sum
-#pragma unroll
-                for (int ab = 0; ab < NA * NB; ++ab)
-#pragma unroll
-                    for (int cd = 0; cd < NC * ND; ++cd) {
-                        jab[ab] += acc[ab * NC * ND + cd] * dcd[cd];
-                        jcd[cd] += acc[ab * NC * ND + cd] * dab[ab];
-                    }
-            }
-            double kbc[NB * NC], kbd[NB * ND];
-#pragma unroll
-            for (int o = 0; o < NB * NC; ++o) kbc[o] = 0.0;
-#pragma unroll
-            for (int o = 0; o < NB * ND; ++o) kbd[o] = 0.0;
-            if (active && wk) {
-                double dbc[NB * NC], dbd[NB * ND];
-#pragma unroll
-                for (int ib = 0; ib < NB; ++ib) {
-#pragma unroll
-                    for (int ic = 0; ic < NC; ++ic) dbc[ib * NC + ic] = Ds[(size_t)(ob + ib) * n + oc + ic];
-#pragma unroll
-                    for (int id = 0; id < ND; ++id) dbd[ib * ND + id] = Ds[(size_t)(ob + ib) * n + od + id];
-                }
-                // X_K[a, c] += v D_bd and X_K[a, d] += v D_bc (block sums)
-#pragma unroll
-                for (int ia = 0; ia < NA; ++ia)
-#pragma unroll
-                    for (int ib = 0; ib < NB; ++ib)
-#pragma unroll
-                        for (int ic = 0; ic < NC; ++ic)
-#pragma unroll
-                            for (int id = 0; id < ND; ++id) {
-                                const double v = acc[((ia * NB + ib) * NC + ic) * ND + id];
-                                kac[ia * NC + ic] += v * dbd[ib * ND + id];
-                                kad[ia * ND + id] += v * dbc[ib * NC + ic];
-                            }
-                // X_K[b, c] += v D_ad and X_K[b, d] += v D_ac (per bra)
-#pragma unroll
-                for (int ib = 0; ib < NB; ++ib) {
-#pragma unroll
-                    for (int ic = 0; ic < NC; ++ic) {
-                        double s = 0.0;
-#pragma unroll
-                        for (int ia = 0; ia < NA; ++ia)
-#pragma unroll
-                            for (int id = 0; id < ND; ++id)
-                                s += acc[((ia * NB + ib) * NC + ic) * ND + id] * Ds[(size_t)(oa + ia) * n + od + id];
-                        kbc[ib * NC + ic] = s;
-                    }
-#pragma unroll
-                    for (int id = 0; id < ND; ++id) {
-                        double s = 0.0;
-#pragma unroll
-                        for (int ia = 0; ia < NA; ++ia)
-#pragma unroll
-                            for (int ic = 0; ic < NC; ++ic)
-                                s += acc[((ia * NB + ib) * NC + ic) * ND + id] * Ds[(size_t)(oa + ia) * n + oc + ic];
-                        kbd[ib * ND + id] = s;
-                    }
-                }
-            }
-            if (wk) {
-                flush_sym<NB, NC>(XK, n, ob, oc, kbc, s_stage, lane);
-                flush_sym<NB, ND>(XK, n, ob, od, kbd, s_stage, lane);
-            }
-            // all lanes (active or not) take part in the wave reduction of X_J[a, b]
-            if (wj) {
-#pragma unroll
-                for (int ab = 0; ab < NA * NB; ++ab) {
-                    const double s = wave_sum(jab[ab]);
-                    if (lane == 0) atomic_add(&XJ[(size_t)(oa + ab / NB) * n + ob + ab % NB], 2.0 * s);
-                }
-            }
+            lpq_digest<LA, LB, LC, LD, R>(acc, active, diag, sa, sb, sc, sd, oa, shbf[sb], oc, od, n, Ds, dcd, kac,
+                                          kad, jcd, XJ, XK, s_stage, lane, wj, wk, any);
         }
         // block sums: a lane without work holds zeros, which are not added
         if (__ballot(any) != 0ull) {
@@ -1087,7 +1216,9 @@ struct Disp {
         i->nroot = C::NR; i->nout = C::NOUT;
         i->wave_per_quartet = KIND;
         // largest bra block the kernel takes (1: one bra per tile)
-        i->bra_block = (KIND == 0 && C::NOUT <= FK_LPQ_BLOCK_NOUT) ? FK_MAX_BRA_BLOCK
+        constexpr int NBK = KIND == 0 ? LpqKetOuter<LA, LB, LC, LD>::value : 0;
+        i->bra_block = NBK > 0 ? NBK
+                       : (KIND == 0 && C::NOUT <= FK_LPQ_BLOCK_NOUT) ? FK_MAX_BRA_BLOCK
                        : ((KIND == 1 || KIND == 2) ? FK_TEAM_MAX_BLOCK : 1);
         i->team_size = KIND == 0 ? 1 : (KIND == 1 ? C::NA : (KIND == 2 ? C::NA * C::NB : 64));
         i->flops_prim = fk::flops_prim(LA, LB, LC, LD);
