@@ -331,6 +331,16 @@ typedef struct {
                             with tau / 1000 (its smaller density bounds still
                             drop most quartets late in the run); 0 = full
                             builds.  Not together with graph.  Default 0 */
+    double canonical;    /* 0: the orthogonaliser is S^(-1/2) by Newton-Schulz,
+                            every overlap direction kept (lindep applies);
+                            c in (0, 1): canonical orthogonalisation: the
+                            overlap matrix is diagonalised once per geometry
+                            on the device (rocSOLVER), eigenvectors with
+                            eigenvalue <= c are dropped and X = U s^(-1/2) U^T
+                            over the rest; the dropped directions are given
+                            Fock eigenvalue +1 hartree so that they stay
+                            empty.  For nearly linearly dependent bases.
+                            Default 0 */
 } fk_scf_opts;
 
 typedef struct {
@@ -344,6 +354,7 @@ typedef struct {
     double delta_e;      /* energy change of the last iteration */
     int    guess_used;   /* the guess the run started from (see fk_scf_opts.guess) */
     double guess_seconds;/* wall time of the initial density */
+    int    ndropped;     /* overlap directions the canonical orthogonaliser dropped */
 } fk_scf_result;
 
 /* Restricted closed-shell SCF (paper: "Hartree-Fock Energy Formulation"):

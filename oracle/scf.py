@@ -35,13 +35,15 @@ def core_guess(h, X, nocc):
     return density(X @ Cp, nocc)
 
 
-def run_scf(sys, D0=None, max_iter=100, e_tol=1e-10, g_tol=1e-8, diis_n=8, nthreads=0, jk_fn=None):
-    """Returns dict(E, D, iters, converged, energies)."""
+def run_scf(sys, D0=None, max_iter=100, e_tol=1e-10, g_tol=1e-8, diis_n=8, nthreads=0, jk_fn=None,
+            ortho_cutoff=1e-8):
+    """Returns dict(E, D, iters, converged, energies); overlap eigenvectors with
+    eigenvalue at or below ortho_cutoff are left out of the orthogonal basis."""
     S, T, V = oneel(sys)
     h = T + V
     e_nuc = enuc(sys)
     nocc = sys["nelec"] // 2
-    X = orthogonalizer(S)
+    X = orthogonalizer(S, ortho_cutoff)
     D = core_guess(h, X, nocc) if D0 is None else np.array(D0)
     jk_fn = jk_fn or (lambda Dm: jk(sys, Dm, nthreads))
     focks, errs, energies = [], [], []

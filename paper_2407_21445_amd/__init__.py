@@ -75,14 +75,14 @@ class TuneReport(ctypes.Structure):
 class ScfOpts(ctypes.Structure):
     _fields_ = [("max_iter", ctypes.c_int), ("e_tol", ctypes.c_double), ("g_tol", ctypes.c_double),
                 ("diis_n", ctypes.c_int), ("guess", ctypes.c_int), ("lindep", ctypes.c_double),
-                ("graph", ctypes.c_int), ("incremental", ctypes.c_int)]
+                ("graph", ctypes.c_int), ("incremental", ctypes.c_int), ("canonical", ctypes.c_double)]
 
 
 class ScfResult(ctypes.Structure):
     _fields_ = [("energy", ctypes.c_double), ("e_nuc", ctypes.c_double), ("iterations", ctypes.c_int),
                 ("converged", ctypes.c_int), ("jk_seconds", ctypes.c_double), ("total_seconds", ctypes.c_double),
                 ("error", ctypes.c_double), ("delta_e", ctypes.c_double), ("guess_used", ctypes.c_int),
-                ("guess_seconds", ctypes.c_double)]
+                ("guess_seconds", ctypes.c_double), ("ndropped", ctypes.c_int)]
 
 
 GUESS_CORE, GUESS_GIVEN, GUESS_SAD, GUESS_LEARNED = 0, 1, 2, 3
@@ -322,16 +322,17 @@ class FockJK:
         return S, T, V, e.value
 
     def run_scf(self, D0=None, max_iter=100, e_tol=1e-10, g_tol=1e-8, diis_n=8, lindep=1e-8, guess=None,
-                graph=False, incremental=0):
+                graph=False, incremental=0, canonical=0.0):
         """guess: GUESS_CORE (default without D0), GUESS_GIVEN (default with
         D0), GUESS_SAD or GUESS_LEARNED; max_iter=0 returns the initial
-        density only."""
+        density only; canonical > 0: canonical orthogonalisation dropping
+        overlap eigenvalues up to it."""
         n = self.nbf
         D = np.zeros((n, n)) if D0 is None else np.ascontiguousarray(D0, dtype=np.float64).copy()
         if guess is None:
             guess = GUESS_CORE if D0 is None else GUESS_GIVEN
         o = ScfOpts(int(max_iter), float(e_tol), float(g_tol), int(diis_n), int(guess), float(lindep), int(bool(graph)),
-                    int(incremental))
+                    int(incremental), float(canonical))
         r = ScfResult()
         rc = _lib.fk_run_scf(self._ctx, ctypes.byref(o), ctypes.byref(r), _ptr(D))
         if rc not in (FK_OK, FK_ERR_NOT_CONVERGED):
@@ -376,7 +377,8 @@ class FockJK:
         return {"classes": rows, "build_ms_default": r.build_ms_default, "build_ms_tuned": r.build_ms_tuned,
                 "configurations": r.configurations}
 
-    def run_scf_batch(self, D0=None, max_iter=100, e_tol=1e-10, g_tol=1e-8, diis_n=8, lindep=1e-8, guess=None):
+    def run_scf_batch(self, D0=None, max_iter=100, e_tol=1e-10, g_tol=1e-8, diis_n=8, lindep=1e-8, guess=None,
+                      canonical=0.0):
         """SCF of every molecule of a batch at once; returns (list of per-molecule
         result dicts, flat density array in the batch layout)."""
         nmol = self.info()["nmol"]
@@ -384,7 +386,8 @@ class FockJK:
         D = np.zeros(nmat) if D0 is None else np.ascontiguousarray(D0, dtype=np.float64).reshape(-1).copy()
         if guess is None:
             guess = GUESS_CORE if D0 is None else GUESS_GIVEN
-        o = ScfOpts(int(max_iter), float(e_tol), float(g_tol), int(diis_n), int(guess), float(lindep))
+        o = ScfOpts(int(max_iter), float(e_tol), float(g_tol), int(diis_n), int(guess), float(lindep), 0, 0,
+                    float(canonical))
         rs = (ScfResult * nmol)()
         rc = _lib.fk_run_scf_batch(self._ctx, ctypes.byref(o), rs, _ptr(D))
         if rc not in (FK_OK, FK_ERR_NOT_CONVERGED):

@@ -54,7 +54,9 @@ def build(maxl: int = 3, jobs: int | None = None, verbose: bool = False, extra=(
             if o.strip():
                 print(o[-4000:])
     tmp = LIB + f".tmp{os.getpid()}"
-    _run([HIPCC, "-shared", "-fPIC", f"--offload-arch={ARCH}", "-o", tmp] + [u[1] for u in units])
+    # rocSOLVER: the overlap eigen-decomposition of the canonical orthogonaliser
+    _run([HIPCC, "-shared", "-fPIC", f"--offload-arch={ARCH}", "-o", tmp] + [u[1] for u in units] +
+         ["-L/opt/rocm/lib", "-Wl,-rpath,/opt/rocm/lib", "-lrocsolver", "-lrocblas"])
     os.replace(tmp, LIB)
     return LIB
 

@@ -1843,6 +1843,9 @@ int guess_predict_device(fk_ctx *c, double *D, hipStream_t st);  // learned gues
 // Largest entry of S^(-1/2) the SCF accepts (overlap eigenvalues down to
 // about 1e-7); beyond it the orthonormal-basis steps lose all accuracy.
 constexpr double kMaxOrthoEntry = 3.0e3;
+// Fock eigenvalue (hartree) given to the overlap directions the canonical
+// orthogonaliser drops: far above any occupied level, so that they stay empty.
+constexpr double kNullShift = 1.0;
 
 struct ScfWork {
     fk_ctx *c = nullptr;
@@ -1850,11 +1853,16 @@ struct ScfWork {
     int n = 0;
     DevBuf<double> h, X, Xi, D, Do, J, K, F, Fo, G, E, T1, T2, T3, part, scal;
     DevBuf<double> Dlast, dD, Jacc, Kacc;  // incremental builds
+    DevBuf<double> Pn, ev, wk;             // canonical orthogonaliser: projector onto the dropped directions
+    DevBuf<int> info;
+    int ndrop = 0;
     std::vector<DevBuf<double>> ringF, ringE;
     ~ScfWork()
     {
-        for (auto *b : {&h, &X, &Xi, &D, &Do, &J, &K, &F, &Fo, &G, &E, &T1, &T2, &T3, &part, &scal, &Dlast, &dD, &Jacc, &Kacc})
+        for (auto *b : {&h, &X, &Xi, &D, &Do, &J, &K, &F, &Fo, &G, &E, &T1, &T2, &T3, &part, &scal, &Dlast, &dD, &Jacc, &Kacc,
+                        &Pn, &ev, &wk})
             dev_free(*b);
+        dev_free(info);
         for (auto &b : ringF) dev_free(b);
         for (auto &b : ringE) dev_free(b);
     }
@@ -1912,6 +1920,46 @@ int scf_orthogonaliser(ScfWork &w, double tol)
     if ((rc = scf_reduce(w, w.X.p, nullptr, 1, &xmax))) return rc;
     if (!(xmax < kMaxOrthoEntry))
         return fail(w.c, FK_ERR_ARG, "fk_run_scf: max |S^(-1/2)| = %.3g: the basis is nearly linearly dependent", xmax);
+    return FK_OK;
+}
+
+// Canonical orthogonaliser: S = U s U^T (w.T3 holds S), X = U s^(-1/2) U^T and
+// Xi = U s^(1/2) U^T over the eigenvalues above `cutoff`; the dropped
+// directions' projector I - X Xi goes to w.Pn (when any is dropped).
+int scf_orthogonaliser_canonical(ScfWork &w, double cutoff)
+{
+    const int n = w.n;
+    const size_t nn = (size_t)n * n;
+    int rc;
+    if ((rc = dev_upload<double>(w.c, w.ev, nullptr, n)) || (rc = dev_upload<double>(w.c, w.wk, nullptr, n)) ||
+        (rc = dev_upload<int>(w.c, w.info, nullptr, 1)))
+        return rc;
+    HIPCHK(w.c, hipMemcpyAsync(w.T1.p, w.T3.p, nn * sizeof(double), hipMemcpyDeviceToDevice, w.st));
+    SCFCHK(w, fk_scf_eigh(w.T1.p, w.ev.p, w.wk.p, w.info.p, n, w.st));
+    int info = 0;
+    std::vector<double> s(n);
+    HIPCHK(w.c, hipMemcpy(&info, w.info.p, sizeof(int), hipMemcpyDeviceToHost));
+    HIPCHK(w.c, hipMemcpy(s.data(), w.ev.p, n * sizeof(double), hipMemcpyDeviceToHost));
+    if (info != 0) return fail(w.c, FK_ERR_HIP, "fk_run_scf: overlap eigen-decomposition failed (info %d)", info);
+    w.ndrop = 0;
+    for (double v : s) w.ndrop += v > cutoff ? 0 : 1;
+    if (w.ndrop >= n) return fail(w.c, FK_ERR_ARG, "fk_run_scf: every overlap eigenvalue is below the cutoff %.3g", cutoff);
+    SCFCHK(w, fk_scf_eig_scale(w.T1.p, w.ev.p, w.T2.p, n, cutoff, -0.5, w.st));
+    SCFCHK(w, fk_scf_gemm(w.T2.p, w.T1.p, w.X.p, n, 1.0, 0.0, w.st));
+    SCFCHK(w, fk_scf_eig_scale(w.T1.p, w.ev.p, w.T2.p, n, cutoff, 0.5, w.st));
+    SCFCHK(w, fk_scf_gemm(w.T2.p, w.T1.p, w.Xi.p, n, 1.0, 0.0, w.st));
+    if (w.ndrop > 0) {
+        if ((rc = dev_upload<double>(w.c, w.Pn, nullptr, nn))) return rc;
+        SCFCHK(w, fk_scf_gemm(w.X.p, w.Xi.p, w.T2.p, n, 1.0, 0.0, w.st));
+        SCFCHK(w, fk_scf_lincomb(w.Pn.p, w.T2.p, nullptr, nullptr, n, -1.0, 0, 0, 1.0, w.st));
+    }
+    return FK_OK;
+}
+
+// F' (w.Fo) plus the shift of the dropped directions, when there are any.
+int scf_shift_null(ScfWork &w)
+{
+    if (w.ndrop > 0) SCFCHK(w, fk_scf_lincomb(w.Fo.p, w.Fo.p, w.Pn.p, nullptr, w.n, 1.0, kNullShift, 0, 0, w.st));
     return FK_OK;
 }
 
@@ -1997,9 +2045,10 @@ int fk_run_scf(fk_ctx *c, const fk_scf_opts *opts, fk_scf_result *result, double
     if (c->device < 0) return fail(c, FK_ERR_STATE, "fk_run_scf: context has no device");
     if (!c->have_quartets) return fail(c, FK_ERR_STATE, "fk_run_scf: call fk_build_quartets first");
     if (c->nmol > 1) return fail(c, FK_ERR_UNSUPPORTED, "fk_run_scf: one molecule per context (batches: one context each)");
-    fk_scf_opts o = {100, 1e-10, 1e-8, 8, 0, 1e-8, 0, 0};
+    fk_scf_opts o = {100, 1e-10, 1e-8, 8, 0, 1e-8, 0, 0, 0.0};
     if (opts) o = *opts;
     if (o.max_iter < 0 || o.diis_n < 0 || o.diis_n > 32 || !(o.e_tol > 0) || !(o.g_tol > 0) || !(o.lindep > 0) ||
+        !(o.canonical >= 0 && o.canonical < 1) ||
         o.guess < 0 || o.guess > 3 || (o.graph != 0 && o.graph != 1) || o.incremental < 0 ||
         (o.graph && o.incremental))
         return fail(c, FK_ERR_ARG, "fk_run_scf: invalid options");
@@ -2053,7 +2102,8 @@ int fk_run_scf(fk_ctx *c, const fk_scf_opts *opts, fk_scf_result *result, double
                 return rc;
     if ((rc = dev_upload(c, w.h, h.data(), nn))) return rc;
     if ((rc = dev_upload(c, w.T3, S.data(), nn))) return rc;
-    if ((rc = scf_orthogonaliser(w, o.lindep))) return rc;
+    if ((rc = o.canonical > 0 ? scf_orthogonaliser_canonical(w, o.canonical) : scf_orthogonaliser(w, o.lindep))) return rc;
+    result->ndropped = w.ndrop;
 
     // initial orthonormal density D' (w.Do); a learned or SAD guess that
     // cannot be formed falls back to SAD, then to the core Hamiltonian
@@ -2069,7 +2119,8 @@ int fk_run_scf(fk_ctx *c, const fk_scf_opts *opts, fk_scf_result *result, double
             // purification of F' = -P' (its nocc lowest states)
             SCFCHK(w, fk_scf_gemm(w.Xi.p, w.D.p, w.T3.p, n, 1.0, 0.0, w.st));
             SCFCHK(w, fk_scf_gemm(w.T3.p, w.Xi.p, w.Fo.p, n, -0.5, 0.0, w.st));
-            rc = scf_purify(w, nocc, nullptr);
+            rc = scf_shift_null(w);
+            if (!rc) rc = scf_purify(w, nocc, nullptr);
         }
         if (rc) gused = 2;
     }
@@ -2088,7 +2139,7 @@ int fk_run_scf(fk_ctx *c, const fk_scf_opts *opts, fk_scf_result *result, double
     if (gused == 0) {
         SCFCHK(w, fk_scf_gemm(w.X.p, w.h.p, w.T3.p, n, 1.0, 0.0, w.st));
         SCFCHK(w, fk_scf_gemm(w.T3.p, w.X.p, w.Fo.p, n, 1.0, 0.0, w.st));
-        if ((rc = scf_purify(w, nocc, nullptr))) return rc;
+        if ((rc = scf_shift_null(w)) || (rc = scf_purify(w, nocc, nullptr))) return rc;
     } else if (gused == 1) {
         if ((rc = dev_upload(c, w.D, D_inout, nn))) return rc;
         SCFCHK(w, fk_scf_gemm(w.Xi.p, w.D.p, w.T3.p, n, 1.0, 0.0, w.st));
@@ -2155,6 +2206,7 @@ int fk_run_scf(fk_ctx *c, const fk_scf_opts *opts, fk_scf_result *result, double
         SCFCHK(w, fk_scf_reduce(w.D.p, w.F.p, n, 0, w.part.p, w.scal.p, 1, w.st));
         SCFCHK(w, fk_scf_gemm(w.X.p, w.F.p, w.T3.p, n, 1.0, 0.0, w.st));
         SCFCHK(w, fk_scf_gemm(w.T3.p, w.X.p, w.Fo.p, n, 1.0, 0.0, w.st));
+        if ((r = scf_shift_null(w))) return r;
         SCFCHK(w, fk_scf_gemm(w.Fo.p, w.Do.p, w.G.p, n, 1.0, 0.0, w.st));
         SCFCHK(w, fk_scf_antisym(w.E.p, w.G.p, n, w.st));
         SCFCHK(w, fk_scf_reduce(w.E.p, nullptr, n, 1, w.part.p, w.scal.p, 2, w.st));
@@ -3064,10 +3116,15 @@ struct ScfBatch {
     int nmol = 0, nmax = 0;
     size_t nm = 0;
     DevBuf<double> h, X, Xi, D, Do, J, K, F, Fo, G, E, T1, T2, T3, part, out, coef;
+    DevBuf<double> Pn, ev, wk;  // canonical orthogonaliser
+    DevBuf<int> info;
+    std::vector<int> ndrop;     // per molecule
     std::vector<DevBuf<double>> ringF, ringE;
     ~ScfBatch()
     {
-        for (auto *b : {&h, &X, &Xi, &D, &Do, &J, &K, &F, &Fo, &G, &E, &T1, &T2, &T3, &part, &out, &coef}) dev_free(*b);
+        for (auto *b : {&h, &X, &Xi, &D, &Do, &J, &K, &F, &Fo, &G, &E, &T1, &T2, &T3, &part, &out, &coef, &Pn, &ev, &wk})
+            dev_free(*b);
+        dev_free(info);
         for (auto &b : ringF) dev_free(b);
         for (auto &b : ringE) dev_free(b);
     }
@@ -3148,6 +3205,62 @@ int scfb_orthogonaliser(ScfBatch &w, double tol)
     return FK_OK;
 }
 
+// Canonical orthogonalisers of every molecule (w.T3 holds the overlap blocks):
+// per molecule S = U s U^T, X = U s^(-1/2) U^T, Xi = U s^(1/2) U^T over the
+// eigenvalues above `cutoff`, and the dropped directions' projector in w.Pn.
+int scfb_orthogonaliser_canonical(ScfBatch &w, double cutoff)
+{
+    fk_ctx *c = w.c;
+    const int nm = w.nmol;
+    int rc;
+    if ((rc = dev_upload<double>(c, w.ev, nullptr, w.nm)) || (rc = dev_upload<double>(c, w.wk, nullptr, w.nmax)) ||
+        (rc = dev_upload<int>(c, w.info, nullptr, nm)))
+        return rc;
+    HIPCHK(c, hipMemcpyAsync(w.T1.p, w.T3.p, w.nm * sizeof(double), hipMemcpyDeviceToDevice, w.st));
+    for (int m = 0; m < nm; ++m)
+        if (fk_scf_eigh(w.T1.p + c->mol_base[m], w.ev.p + c->mol_base[m], w.wk.p, w.info.p + m, c->mol_nbf[m], w.st))
+            return fail(c, FK_ERR_HIP, "batched SCF: molecule %d: eigen-decomposition launch failed", m);
+    std::vector<int> info(nm);
+    std::vector<double> s(w.nm);
+    HIPCHK(c, hipMemcpy(info.data(), w.info.p, nm * sizeof(int), hipMemcpyDeviceToHost));
+    HIPCHK(c, hipMemcpy(s.data(), w.ev.p, w.nm * sizeof(double), hipMemcpyDeviceToHost));
+    w.ndrop.assign(nm, 0);
+    bool any = false;
+    for (int m = 0; m < nm; ++m) {
+        if (info[m] != 0) return fail(c, FK_ERR_HIP, "batched SCF: molecule %d: overlap eigen-decomposition failed (info %d)", m, info[m]);
+        const int n = c->mol_nbf[m];
+        for (int i = 0; i < n; ++i) w.ndrop[m] += s[c->mol_base[m] + i] > cutoff ? 0 : 1;
+        if (w.ndrop[m] >= n) return fail(c, FK_ERR_ARG, "batched SCF: molecule %d: every overlap eigenvalue is below the cutoff", m);
+        any = any || w.ndrop[m] > 0;
+    }
+    for (int k = 0; k < 2; ++k) {
+        for (int m = 0; m < nm; ++m)
+            if (fk_scf_eig_scale(w.T1.p + c->mol_base[m], w.ev.p + c->mol_base[m], w.T2.p + c->mol_base[m],
+                                 c->mol_nbf[m], cutoff, k == 0 ? -0.5 : 0.5, w.st))
+                return fail(c, FK_ERR_HIP, "batched SCF: launch failed");
+        if ((rc = w.gemm(w.T2.p, w.T1.p, k == 0 ? w.X.p : w.Xi.p))) return rc;
+    }
+    if (any) {
+        if ((rc = dev_upload<double>(c, w.Pn, nullptr, w.nm)) || (rc = w.gemm(w.X.p, w.Xi.p, w.T2.p)) ||
+            (rc = w.lincomb_u(w.Pn.p, w.T2.p, nullptr, nullptr, -1.0, 0, 0, 1.0)))
+            return rc;
+    }
+    return FK_OK;
+}
+
+// F'_m (w.Fo) plus the shift of each molecule's dropped directions.
+int scfb_shift_null(ScfBatch &w)
+{
+    if (w.ndrop.empty() || std::find_if(w.ndrop.begin(), w.ndrop.end(), [](int x) { return x > 0; }) == w.ndrop.end())
+        return FK_OK;
+    std::vector<double> cf(4 * (size_t)w.nmol, 0.0);
+    for (int m = 0; m < w.nmol; ++m) {
+        cf[4 * m] = 1.0;
+        cf[4 * m + 1] = w.ndrop[m] > 0 ? kNullShift : 0.0;
+    }
+    return w.lincomb(w.Fo.p, w.Fo.p, w.Pn.p, nullptr, cf);
+}
+
 // Orthonormal densities D'_m = 2 P_m from F'_m in Fo (trace-correcting
 // purification per molecule; molecules that have converged keep P).
 int scfb_purify(ScfBatch &w, const std::vector<int> &nocc)
@@ -3200,10 +3313,10 @@ extern "C" int fk_run_scf_batch(fk_ctx *c, const fk_scf_opts *opts, fk_scf_resul
     if (!c->have_quartets) return fail(c, FK_ERR_STATE, "fk_run_scf_batch: call fk_build_quartets first");
     const int nmol = c->nmol;
     std::memset(results, 0, sizeof(fk_scf_result) * (size_t)nmol);
-    fk_scf_opts o = {100, 1e-10, 1e-8, 8, 0, 1e-8, 0, 0};
+    fk_scf_opts o = {100, 1e-10, 1e-8, 8, 0, 1e-8, 0, 0, 0.0};
     if (opts) o = *opts;
     if (o.max_iter < 0 || o.diis_n < 0 || o.diis_n > 32 || !(o.e_tol > 0) || !(o.g_tol > 0) || !(o.lindep > 0) ||
-        o.guess < 0 || o.guess > 3)
+        !(o.canonical >= 0 && o.canonical < 1) || o.guess < 0 || o.guess > 3)
         return fail(c, FK_ERR_ARG, "fk_run_scf_batch: invalid options");
     if (c->charge != 0) return fail(c, FK_ERR_UNSUPPORTED, "fk_run_scf_batch: the molecules of a batch must be neutral");
     const auto t_start = std::chrono::steady_clock::now();
@@ -3249,7 +3362,7 @@ extern "C" int fk_run_scf_batch(fk_ctx *c, const fk_scf_opts *opts, fk_scf_resul
             if ((rc = dev_upload<double>(c, w.ringF[k], nullptr, nmat)) || (rc = dev_upload<double>(c, w.ringE[k], nullptr, nmat)))
                 return rc;
     if ((rc = dev_upload(c, w.h, hh.data(), nmat)) || (rc = dev_upload(c, w.T3, Sh.data(), nmat))) return rc;
-    if ((rc = scfb_orthogonaliser(w, o.lindep))) return rc;
+    if ((rc = o.canonical > 0 ? scfb_orthogonaliser_canonical(w, o.canonical) : scfb_orthogonaliser(w, o.lindep))) return rc;
 
     // initial orthonormal densities: the learned guess is per molecule only,
     // so a batch starts it from SAD
@@ -3265,7 +3378,9 @@ extern "C" int fk_run_scf_batch(fk_ctx *c, const fk_scf_opts *opts, fk_scf_resul
         if ((rc = dev_upload(c, w.D, D_inout, nmat))) return rc;
     }
     if (gused == 0) {
-        if ((rc = w.gemm(w.X.p, w.h.p, w.T3.p)) || (rc = w.gemm(w.T3.p, w.X.p, w.Fo.p)) || (rc = scfb_purify(w, nocc))) return rc;
+        if ((rc = w.gemm(w.X.p, w.h.p, w.T3.p)) || (rc = w.gemm(w.T3.p, w.X.p, w.Fo.p)) || (rc = scfb_shift_null(w)) ||
+            (rc = scfb_purify(w, nocc)))
+            return rc;
     } else {
         if ((rc = w.gemm(w.Xi.p, w.D.p, w.T3.p)) || (rc = w.gemm(w.T3.p, w.Xi.p, w.Do.p))) return rc;
     }
@@ -3309,7 +3424,8 @@ extern "C" int fk_run_scf_batch(fk_ctx *c, const fk_scf_opts *opts, fk_scf_resul
             e_prev[m] = e_cur[m];
             e_cur[m] = 0.5 * (dh[m] + df[m]) + enuc[m];
         }
-        if ((rc = w.gemm(w.X.p, w.F.p, w.T3.p)) || (rc = w.gemm(w.T3.p, w.X.p, w.Fo.p)) || (rc = w.gemm(w.Fo.p, w.Do.p, w.G.p)))
+        if ((rc = w.gemm(w.X.p, w.F.p, w.T3.p)) || (rc = w.gemm(w.T3.p, w.X.p, w.Fo.p)) || (rc = scfb_shift_null(w)) ||
+            (rc = w.gemm(w.Fo.p, w.Do.p, w.G.p)))
             return rc;
         if (fk_scfb_antisym(w.E.p, w.G.p, nmol, nmax, w.nbf(), w.off(), w.st)) return fail(c, FK_ERR_HIP, "batched SCF: launch failed");
         if ((rc = w.reduce(w.E.p, nullptr, 1, err))) return rc;
@@ -3406,6 +3522,7 @@ extern "C" int fk_run_scf_batch(fk_ctx *c, const fk_scf_opts *opts, fk_scf_resul
         r.delta_e = conv[m] ? de_fin[m] : e_cur[m] - e_prev[m];
         r.jk_seconds = jk_s;
         r.total_seconds = tot;
+        r.ndropped = w.ndrop.empty() ? 0 : w.ndrop[m];
     }
     if (!all_conv) return fail(c, FK_ERR_NOT_CONVERGED, "fk_run_scf_batch: not every molecule converged in %d iterations", o.max_iter);
     return FK_OK;

@@ -159,4 +159,6 @@ int fk_scf_antisym(double *e, const double *G, int n, void *stream);
 int fk_scf_reduce(const double *x, const double *y, int n, int op, double *part, double *out, int slot,
                   void *stream);
 int fk_scf_reduce_scratch();
+int fk_scf_eig_scale(const double *V, const double *s, double *out, int n, double cutoff, double power, void *stream);
+int fk_scf_eigh(double *A, double *w, double *work, int *info, int n, void *stream);
 }

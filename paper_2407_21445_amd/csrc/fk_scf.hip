@@ -12,7 +12,12 @@
 //     with Gershgorin bounds, then X <- X^2 or X <- 2X - X^2, whichever moves
 //     the trace towards N_occ, until X is idempotent;
 //   * the DIIS error is the commutator F'D' - D'F' in the orthonormal basis.
+// For nearly linearly dependent bases the orthogonaliser can instead be the
+// canonical one: S = U s U^T once per geometry (rocSOLVER), X = U f(s) U^T
+// with f(s) = s^(-1/2) above a cutoff and 0 below it (eigenvectors dropped).
 // All matrices are n x n, row-major, FP64, device resident.
+#include <rocblas/rocblas.h>
+#include <rocsolver/rocsolver.h>
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -183,6 +188,20 @@ __global__ void k_reduce2(const double *__restrict part, int nblk, int op, doubl
     if (op == 3) out[slot + 1] = b;
 }
 
+// Canonical orthogonaliser pieces.  V holds the eigenvectors of S as rows
+// (rocSOLVER's column-major output read row-major), s the eigenvalues:
+// out = V^T diag(f(s)), f(s) = s^power for s > cutoff and 0 otherwise, so
+// that out V = U f(s) U^T over the kept eigenvectors.
+__global__ void k_eig_scale(const double *__restrict V, const double *__restrict s, double *__restrict out, int n,
+                            double cutoff, double power)
+{
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= (long long)n * n) return;
+    const int r = (int)(i / n), c = (int)(i % n);  // out[r][c] = V[c][r] f(s_c)
+    const double sv = s[c];
+    out[i] = sv > cutoff ? V[(size_t)c * n + r] * pow(sv, power) : 0.0;
+}
+
 int ok() { return hipGetLastError() == hipSuccess ? 0 : -3; }
 
 }  // namespace
@@ -230,5 +249,34 @@ int fk_scf_reduce(const double *x, const double *y, int n, int op, double *part,
 }
 
 int fk_scf_reduce_scratch() { return 2 * RBLK; }
+
+int fk_scf_eig_scale(const double *V, const double *s, double *out, int n, double cutoff, double power, void *stream)
+{
+    const long long nn = (long long)n * n;
+    if (nn <= 0) return 0;
+    hipLaunchKernelGGL(k_eig_scale, dim3((unsigned)((nn + 255) / 256)), dim3(256), 0, (hipStream_t)stream, V, s, out,
+                       n, cutoff, power);
+    return ok();
+}
+
+// Eigen-decomposition of the symmetric n x n device matrix A (overwritten by
+// the eigenvectors, rows of the row-major view) with rocSOLVER's divide and
+// conquer solver; eigenvalues ascending into w; work holds n doubles, info one
+// int (0 on success), all on the device.  Returns 0 or -3.
+int fk_scf_eigh(double *A, double *w, double *work, int *info, int n, void *stream)
+{
+    if (n <= 0) return 0;
+    rocblas_handle h = nullptr;
+    if (rocblas_create_handle(&h) != rocblas_status_success) return -3;
+    int rc = 0;
+    if (rocblas_set_stream(h, (hipStream_t)stream) != rocblas_status_success ||
+        rocsolver_dsyevd(h, rocblas_evect_original, rocblas_fill_upper, n, A, n, w, work, info) !=
+            rocblas_status_success)
+        rc = -3;
+    // the handle may own workspace the solver still uses: wait before freeing it
+    if (hipStreamSynchronize((hipStream_t)stream) != hipSuccess) rc = -3;
+    rocblas_destroy_handle(h);
+    return rc;
+}
 
 }  // extern "C"

@@ -187,3 +187,66 @@ def test_scf_incremental_builds(fk, name):
     assert abs(r1["energy"] - run_scf(s)["E"]) <= 1e-8
     with pytest.raises(fk.FockJKError):
         c.run_scf(incremental=8, graph=True)
+
+
+def _near_dependent_water4(delta):
+    """(H2O)4 STO-3G-type with a copy of the first oxygen's 2s shell whose
+    exponents are scaled by 1 + delta: one overlap eigenvalue near 8e-9 at
+    delta = 3e-4 (the rest above 0.3)."""
+    s = wl.water4_sto3g()
+    t = dict(s)
+    k = int(s["sh_nprim"][1])
+    off = int(s["sh_nprim"][0])
+    t["sh_atom"] = np.append(s["sh_atom"], 0)
+    t["sh_l"] = np.append(s["sh_l"], 0)
+    t["sh_nprim"] = np.append(s["sh_nprim"], k)
+    t["exps"] = np.concatenate([s["exps"], s["exps"][off:off + k] * (1 + delta)])
+    t["coefs"] = np.concatenate([s["coefs"], s["coefs"][off:off + k]])
+    t["nshell"] = s["nshell"] + 1
+    t["nbf"] = s["nbf"] + 1
+    t["name"] = s["name"] + "+near-duplicate 2s"
+    return t
+
+
+def test_scf_canonical_orthogonalisation(fk):
+    """Canonical orthogonalisation (fk_scf_opts.canonical): on a basis with
+    one overlap eigenvalue near 8e-9 the symmetric S^(-1/2) is refused, while
+    the canonical one drops that direction and converges to the oracle's SCF
+    energy with the same cutoff (1e-6) within 1e-8 Eh, eagerly and with the
+    graph-replayed Fock stage; on a well-conditioned basis nothing is dropped
+    and the energy equals the symmetric orthogonaliser's."""
+    s = _near_dependent_water4(3e-4)
+    w = np.linalg.eigvalsh(oracle.oneel(s)[0])
+    assert w[0] < 1e-8 and w[1] > 0.1
+    c = fk.FockJK(0).set_system(s).build_quartets(tau=0.0)
+    with pytest.raises(fk.FockJKError) as e:
+        c.run_scf()
+    assert e.value.code == fk.FK_ERR_ARG
+    ref = run_scf(s, ortho_cutoff=1e-6)
+    assert ref["converged"]
+    S = oracle.oneel(s)[0]
+    for graph in (False, True):
+        r = c.run_scf(canonical=1e-6, graph=graph)
+        assert r["converged"] and r["ndropped"] == 1
+        assert abs(r["energy"] - ref["E"]) <= 1e-8, (graph, r["energy"], ref["E"])
+        assert abs(np.trace(r["D"] @ S) - s["nelec"]) <= 1e-8
+    s2 = wl.alkane_sys(2, "6-31gs-type")
+    c2 = fk.FockJK(0).set_system(s2).build_quartets(tau=0.0)
+    r_sym, r_can = c2.run_scf(), c2.run_scf(canonical=1e-8)
+    assert r_can["converged"] and r_can["ndropped"] == 0
+    assert abs(r_can["energy"] - r_sym["energy"]) <= 1e-9
+
+
+def test_batched_scf_canonical(fk):
+    """The batched SCF with canonical orthogonalisation (cutoff 1e-6): each
+    molecule's own dropped count and the energy of its single-molecule
+    canonical SCF within 1e-8 Eh."""
+    mols = [_near_dependent_water4(3e-4), wl.water4_sto3g(), wl.h2_sto3g()]
+    b = wl.batch(mols)
+    c = fk.FockJK(0).set_system(b).set_molecules(b["atom_mol"]).build_quartets(tau=0.0)
+    rs, _ = c.run_scf_batch(canonical=1e-6)
+    assert [r["ndropped"] for r in rs] == [1, 0, 0]
+    for m, s in enumerate(mols):
+        r = fk.FockJK(0).set_system(s).build_quartets(tau=0.0).run_scf(canonical=1e-6)
+        assert rs[m]["converged"] and r["converged"]
+        assert abs(rs[m]["energy"] - r["energy"]) <= 1e-8, (m, rs[m]["energy"], r["energy"])
