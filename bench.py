@@ -182,13 +182,14 @@ def bench_batch(args, torch, fk):
     from synth import workloads as wl
     b = wl.organic_batch(args.nmol)
     ctx = fk.FockJK(0).set_system(b).set_molecules(b["atom_mol"])
-    Ds = []
-    if args.batch_density == "core":
-        for m in b["mols"]:
-            h = fk.FockJK(-1).set_system(m)
-            S, T, V, _ = h.one_electron()
-            Ds.append(_core_density(S, T + V, m["nelec"] // 2).ravel())
     _progress(f"batch of {args.nmol} molecules set up")
+
+    def start_density(c):
+        # core-Hamiltonian densities of every molecule, by the library's own
+        # batched SCF start (device orthogonaliser and purification), or SAD
+        if args.batch_density == "core":
+            return c.run_scf_batch(max_iter=0, guess=fk.GUESS_CORE)[1]
+        return c.sad_density()
     tune = None
     if args.autotune:
         # schedules tuned on a two-molecule batch of the same set, applied to all
@@ -197,7 +198,7 @@ def bench_batch(args, torch, fk):
         sb = wl.batch(b["mols"][:nsub])
         sub = fk.FockJK(0).set_system(sb).set_molecules(sb["atom_mol"])
         sub.build_quartets(tau=args.tau, tau_prim=args.tau_prim, tau_fp32=args.tau_fp32)
-        Dsub = np.concatenate(Ds[:nsub]) if Ds else sub.sad_density()
+        Dsub = start_density(sub)
         rep = sub.autotune(Dsub, reps=1)
         for r in rep["classes"]:
             ctx.set_class_schedule(r["la"], r["lb"], r["lc"], r["ld"], r["bra_block"], r["kets_per_tile"],
@@ -213,7 +214,8 @@ def bench_batch(args, torch, fk):
     info = ctx.info()
     _progress(f"lists built: {info['ntile']} tiles, {info['nquartet_schwarz']} Schwarz quartets")
     dev = torch.device("cuda:0")
-    Dh = np.concatenate(Ds) if Ds else ctx.sad_density()
+    Dh = start_density(ctx)
+    _progress("start densities formed")
     Dd = torch.tensor(Dh, dtype=torch.float64, device=dev)
     J = torch.empty_like(Dd)
     K = torch.empty_like(Dd)

@@ -3322,27 +3322,46 @@ extern "C" int fk_run_scf_batch(fk_ctx *c, const fk_scf_opts *opts, fk_scf_resul
     const auto t_start = std::chrono::steady_clock::now();
     hipSetDevice(c->device);
     int rc;
-    // one-electron part per molecule (host), electron counts
+    // one-electron part per molecule (host threads, molecules round-robin),
+    // electron counts
     const size_t nmat = (size_t)c->mol_base[nmol];
     std::vector<double> Sh(nmat), hh(nmat), enuc(nmol);
-    std::vector<int> nocc(nmol);
+    std::vector<int> nocc(nmol), mrc(nmol, FK_OK), nel(nmol, 0);
     int nmax = 0;
+    for (int m = 0; m < nmol; ++m) nmax = std::max(nmax, c->mol_nbf[m]);
+    {
+        std::vector<fk_ctx *> tc(nmol, nullptr);
+        for (int m = 0; m < nmol; ++m)  // contexts first: their errors go to c
+            if ((rc = molecule_context(c, m, &tc[m]))) {
+                for (fk_ctx *t : tc) fk_destroy(t);
+                return rc;
+            }
+        const int nth = std::max(1, std::min<int>({16, nmol, (int)std::max(1u, std::thread::hardware_concurrency())}));
+        auto work = [&](int tid) {
+            for (int m = tid; m < nmol; m += nth) {
+                const int n = c->mol_nbf[m];
+                std::vector<double> S(n * (size_t)n), T(S.size()), V(S.size());
+                mrc[m] = fk_one_electron(tc[m], S.data(), T.data(), V.data(), &enuc[m]);
+                nel[m] = tc[m]->nelec;
+                if (mrc[m]) continue;
+                for (size_t i = 0; i < S.size(); ++i) {
+                    Sh[c->mol_base[m] + i] = S[i];
+                    hh[c->mol_base[m] + i] = T[i] + V[i];
+                }
+            }
+        };
+        std::vector<std::thread> pool;
+        for (int k = 1; k < nth; ++k) pool.emplace_back(work, k);
+        work(0);
+        for (auto &th : pool) th.join();
+        for (fk_ctx *t : tc) fk_destroy(t);
+    }
     for (int m = 0; m < nmol; ++m) {
-        fk_ctx *t = nullptr;
-        if ((rc = molecule_context(c, m, &t))) return rc;
-        const int n = c->mol_nbf[m];
-        nmax = std::max(nmax, n);
-        std::vector<double> S(n * (size_t)n), T(S.size()), V(S.size());
-        rc = fk_one_electron(t, S.data(), T.data(), V.data(), &enuc[m]);
-        const int ne = t->nelec;
-        fk_destroy(t);
-        if (rc) return fail(c, rc, "fk_run_scf_batch: molecule %d: one-electron integrals failed", m);
-        if (ne % 2 || ne <= 0 || ne / 2 > n) return fail(c, FK_ERR_ARG, "fk_run_scf_batch: molecule %d: %d electrons", m, ne);
+        if (mrc[m]) return fail(c, mrc[m], "fk_run_scf_batch: molecule %d: one-electron integrals failed", m);
+        const int ne = nel[m];
+        if (ne % 2 || ne <= 0 || ne / 2 > c->mol_nbf[m])
+            return fail(c, FK_ERR_ARG, "fk_run_scf_batch: molecule %d: %d electrons", m, ne);
         nocc[m] = ne / 2;
-        for (size_t i = 0; i < S.size(); ++i) {
-            Sh[c->mol_base[m] + i] = S[i];
-            hh[c->mol_base[m] + i] = T[i] + V[i];
-        }
     }
     ScfBatch w;
     w.c = c;
