@@ -73,6 +73,14 @@ typedef enum {
 #define FK_K_ONLY 16u         /* form K only (K_uv = sum_ls (ul|vs) D_ls); J is not written and
                                  may be NULL; the density screen uses D_ac, D_ad, D_bc, D_bd.
                                  FK_J_ONLY | FK_K_ONLY is FK_ERR_ARG */
+#define FK_J_ENGINE 32u       /* J by the McMurchie-Davidson J engine (paper, "J matrix
+                                 implementation": J_ab = sum_p E^ab_p J_p, J_p = sum_q [p|q] D_q,
+                                 D_q = sum_cd E^cd_q D_cd, per primitive pair); K, unless
+                                 FK_J_ONLY, by the Rys kernels with the K-only density screen.
+                                 Every bra takes all its Schwarz- and density-screened kets (no
+                                 bra-ket symmetry).  One molecule with s, p and d shells
+                                 (FK_ERR_UNSUPPORTED otherwise); its lists are built at the first
+                                 such build after fk_build_quartets */
 
 /* Screening options (paper: Cauchy-Schwarz screening, eq. cauchy-schwarz, and
  * the density screen G_ab G_cd D_max < tau of the Brc21 scheme). */
@@ -204,7 +212,8 @@ int fk_build_jk(fk_ctx *ctx, const double *D, double *J, double *K, unsigned fla
  * and its shell blocks at most FK_NOALLOC_MAX_NSHMAT (nshell <= 512); larger
  * contexts get FK_ERR_ARG (use fk_build_jk).  flags must contain
  * FK_DEVICE_PTRS (D, J, K device arrays of the caller) and may contain
- * FK_SYNC, FK_J_ONLY or FK_K_ONLY; FK_TIME_CLASSES is FK_ERR_ARG.  The array
+ * FK_SYNC, FK_J_ONLY or FK_K_ONLY; FK_TIME_CLASSES and FK_J_ENGINE (whose
+ * lists the context allocates) are FK_ERR_ARG.  The array
  * is shared by every context on a GPU and keeps the last call's contents (the
  * call clears what must start at zero): calls that overlap on one GPU, on any
  * streams, race and must be ordered by the caller.  Results equal
@@ -502,9 +511,10 @@ int fk_mlp_adam(const fk_mlp *m, const fk_mlp *grad, const fk_mlp *m1, const fk_
  * quartets[4q..4q+3], any order and any angular momenta), written
  * consecutively as [na][nb][nc][nd] blocks into out (host array of
  * sum na*nb*nc*nd doubles).  mode bit 0: 1 evaluates on the GPU with the
- * production per-quartet code, 0 evaluates the same code on the host; mode
- * bit 1: 0 = Rys engine, 1 = HGP engine (FK_ERR_UNSUPPORTED if a quartet's
- * class has no HGP kernel). */
+ * production per-quartet code, 0 evaluates the same code on the host;
+ * mode >> 1: 0 = Rys engine, 1 = HGP engine (FK_ERR_UNSUPPORTED if a
+ * quartet's class has no HGP kernel), 2 = the Hermite (McMurchie-Davidson)
+ * expansion the J engine's E and R pieces define (host only, L <= 8). */
 int fk_debug_eri(fk_ctx *ctx, int nq, const int *quartets, double *out, int mode);
 
 /* Host-side check of every address the J/K kernels will form for the current

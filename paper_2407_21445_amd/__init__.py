@@ -30,7 +30,7 @@ except ImportError:  # host-only use (tables, validation) without PyTorch
 _lib = ctypes.CDLL(LIB_PATH)
 
 FK_OK, FK_ERR_ARG, FK_ERR_UNSUPPORTED, FK_ERR_HIP, FK_ERR_OOM, FK_ERR_NOT_CONVERGED, FK_ERR_STATE = 0, -1, -2, -3, -4, -5, -6
-FK_DEVICE_PTRS, FK_SYNC, FK_TIME_CLASSES, FK_J_ONLY, FK_K_ONLY = 1, 2, 4, 8, 16
+FK_DEVICE_PTRS, FK_SYNC, FK_TIME_CLASSES, FK_J_ONLY, FK_K_ONLY, FK_J_ENGINE = 1, 2, 4, 8, 16, 32
 FK_MAX_QCLASS = 110
 MAX_L, MAX_K = 3, 9
 
@@ -238,14 +238,15 @@ class FockJK:
         return {k: getattr(i, k) for k, _ in Info._fields_}
 
     # ---- hot path ----
-    def build_jk(self, D, J=None, K=None, stream=None, sync=False, time_classes=False, only=None):
+    def build_jk(self, D, J=None, K=None, stream=None, sync=False, time_classes=False, only=None, j_engine=False):
         """J, K for density D.  torch CUDA tensors (float64, contiguous) stay on
         the device and run on `stream` (default: torch's current stream);
         numpy arrays go through host copies.  only="J" or "K" forms one
-        matrix (FK_J_ONLY / FK_K_ONLY); the other is returned as None."""
+        matrix (FK_J_ONLY / FK_K_ONLY); the other is returned as None.
+        j_engine: J by the McMurchie-Davidson J engine (FK_J_ENGINE)."""
         if only not in (None, "J", "K"):
             raise ValueError("only must be None, 'J' or 'K'")
-        oflag = {None: 0, "J": FK_J_ONLY, "K": FK_K_ONLY}[only]
+        oflag = {None: 0, "J": FK_J_ONLY, "K": FK_K_ONLY}[only] | (FK_J_ENGINE if j_engine else 0)
         nmat = self.info()["nmat"]
         if isinstance(D, np.ndarray):
             Dh = np.ascontiguousarray(D, dtype=np.float64)
@@ -446,7 +447,7 @@ class FockJK:
         shapes = [tuple(_ncart(int(self.sh_l[s])) for s in row) for row in q]
         tot = sum(int(np.prod(s)) for s in shapes)
         out = np.zeros(max(tot, 1))
-        e = {"rys": ENGINE_RYS, "hgp": ENGINE_HGP}.get(engine, engine)
+        e = {"rys": ENGINE_RYS, "hgp": ENGINE_HGP, "mmd": 2}.get(engine, engine)
         self._check(_lib.fk_debug_eri(self._ctx, len(q), _ptr(q), _ptr(out), (1 if on_device else 0) | (2 * int(e))))
         res, o = [], 0
         for s in shapes:

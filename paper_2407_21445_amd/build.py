@@ -42,6 +42,9 @@ def build(maxl: int = 3, jobs: int | None = None, verbose: bool = False, extra=(
                       [f"-DFK_ONLY_P={P}"]))
     units.append((os.path.join(CSRC, "fk_kernels.hip"), os.path.join(BUILD, "fk_kernels_common.o"),
                   ["-DFK_ONLY_P=-1"]))
+    # the McMurchie-Davidson J engine
+    units.append((os.path.join(CSRC, "fk_kernels.hip"), os.path.join(BUILD, "fk_kernels_jeng.o"),
+                  ["-DFK_ONLY_P=-2"]))
     units.append((os.path.join(CSRC, "fk_scf.hip"), os.path.join(BUILD, "fk_scf.o"), []))
     units.append((os.path.join(CSRC, "fk_guess.hip"), os.path.join(BUILD, "fk_guess.o"), []))
     units.append((os.path.join(CSRC, "fk_scf_batch.hip"), os.path.join(BUILD, "fk_scf_batch.o"), []))

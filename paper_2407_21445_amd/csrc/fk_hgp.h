@@ -41,13 +41,13 @@ constexpr int cidx(int x, int y, int z)
 
 // Exponents of the component with global index g (g < ncum(LMAX + 1)).
 struct CompTab {
-    int x[84], y[84], z[84];
+    int x[165], y[165], z[165];  // momenta 0..8
 };
 constexpr CompTab make_comp()
 {
     CompTab t{};
     int g = 0;
-    for (int l = 0; l <= 6; ++l)
+    for (int l = 0; l <= 8; ++l)
         for (int a = l; a >= 0; --a)
             for (int b = l - a; b >= 0; --b) {
                 t.x[g] = a; t.y[g] = b; t.z[g] = l - a - b;

@@ -31,6 +31,8 @@ constexpr int NPC = 10;  // pair classes (la >= lb, la <= 3)
 
 constexpr int ncart(int l) { return (l + 1) * (l + 2) / 2; }
 inline int pair_class(int la, int lb) { return la * (la + 1) / 2 + lb; }
+// Hermite functions of total order up to L
+inline int nherm_host(int L) { return (L + 1) * (L + 2) * (L + 3) / 6; }
 
 double dfact(int n)
 {
@@ -117,6 +119,14 @@ struct fk_ctx {
     DevBuf<FkBraBlock> d_blocks;
     DevBuf<int> d_blk_bra, d_blk_pos;
     DevBuf<unsigned long long> d_cnt;
+    // J engine (built on first use after fk_build_quartets)
+    bool jeng_valid = false;
+    std::vector<int64_t> jeng_toff;               // tiles of bucket LP * (FK_JENG_MAX_LP + 1) + LQ
+    DevBuf<FkJengTile> d_jeng_tiles;
+    DevBuf<long long> d_jp_off, d_dq_base;
+    DevBuf<int> d_pos_grp;
+    DevBuf<double> d_jp, d_dq;
+    size_t jp_n = 0;
     // last build
     bool stats_pending = false;
     bool timed = false;
@@ -217,6 +227,8 @@ void free_device(fk_ctx *c)
     dev_free(c->d_X); dev_free(c->d_Din); dev_free(c->d_Jout); dev_free(c->d_Kout); dev_free(c->d_tiles);
     dev_free(c->d_cnt); dev_free(c->d_blocks); dev_free(c->d_blk_bra); dev_free(c->d_blk_pos); dev_free(c->d_lst_sa); dev_free(c->d_lst_sb); dev_free(c->d_lst_CD);
     dev_free(c->d_lst_G); dev_free(c->d_ppT); dev_free(c->d_groups);
+    dev_free(c->d_jeng_tiles); dev_free(c->d_jp_off); dev_free(c->d_dq_base); dev_free(c->d_pos_grp);
+    dev_free(c->d_jp); dev_free(c->d_dq);
     for (int k = 0; k < FK_MLP_MAX_LAYERS; ++k) { dev_free(c->g_W[k]); dev_free(c->g_b[k]); }
     dev_free(c->g_X); dev_free(c->g_Y); dev_free(c->g_work); dev_free(c->g_pairs); dev_free(c->g_rot); dev_free(c->g_D);
 }
@@ -276,8 +288,10 @@ int eval_quartets_tab(fk_ctx *c, const PairTab &t, int P, int Q, const std::vect
     FkClassInfo ci;
     int rc = fk_kernels_class_info(P, Q, &ci);
     if (rc) return fail(c, FK_ERR_UNSUPPORTED, "class (%d,%d) not built", P, Q);
-    if (engine != 0 && !ci.hgp)
+    if (engine == 1 && !ci.hgp)
         return fail(c, FK_ERR_UNSUPPORTED, "the HGP engine is not built for class (%d%d|%d%d)", ci.la, ci.lb, ci.lc, ci.ld);
+    if (engine == 2 && (on_device || ci.la + ci.lb + ci.lc + ci.ld > 8))
+        return fail(c, FK_ERR_UNSUPPORTED, "McMurchie-Davidson integrals: host only, L <= 8");
     const int nq = (int)qs.size() / 2;
     out.assign((size_t)nq * ci.nout, 0.0);
     if (nq == 0) return FK_OK;
@@ -1021,6 +1035,7 @@ int fk_build_quartets(fk_ctx *c, const fk_screen_opts *o)
         if ((rc = dev_upload(c, c->d_blk_pos, c->blk_pos.data(), c->blk_pos.size()))) return rc;
     }
     c->have_quartets = true;
+    c->jeng_valid = false;
     c->stats_pending = false;
     return FK_OK;
 }
@@ -1071,6 +1086,144 @@ struct JKBufs {
     unsigned long long *cnt;
 };
 
+constexpr int kJengNB = FK_JENG_MAX_LP + 1;
+
+// Lists and buffers of the J engine for the current quartet lists: per pair
+// the offset of its J_p block, per ket group the offset of its D_q block, and
+// the work tiles (bra pair, <= 64 kets of one group) of every bra class
+// against every ket class, bucketed by (la + lb, lc + ld), each bucket
+// ordered by cost (bra x ket primitives x kets), most expensive first.
+int ensure_jeng(fk_ctx *c)
+{
+    if (c->jeng_valid) return FK_OK;
+    if (c->nmol > 1) return fail(c, FK_ERR_UNSUPPORTED, "FK_J_ENGINE: one molecule per context");
+    for (int s = 0; s < c->nshell; ++s)
+        if (c->sh_l[s] > 2) return fail(c, FK_ERR_UNSUPPORTED, "FK_J_ENGINE: built for s, p and d shells");
+    const int npair = (int)c->pr_sa.size();
+    std::vector<long long> jp_off(npair);
+    long long njp = 0;
+    for (int p = 0; p < npair; ++p) {
+        jp_off[p] = njp;
+        njp += (long long)c->pr_npp[p] * nherm_host(c->sh_l[c->pr_sa[p]] + c->sh_l[c->pr_sb[p]]);
+    }
+    const int ng = (int)c->groups.size();
+    std::vector<long long> dq_base(ng, 0);
+    std::vector<int> pos_grp(c->ket_list_all.size(), 0);
+    long long ndq = 0;
+    for (int Q = 0; Q < NPC; ++Q)
+        for (size_t gi = 0; gi < c->cls_groups[Q].size(); ++gi) {
+            const int g = c->cls_group0[Q] + (int)gi;
+            const FkGroup &G = c->groups[g];
+            const int lq = c->sh_l[c->lst_sa[G.begin]] + c->sh_l[c->lst_sb[G.begin]];
+            dq_base[g] = ndq;
+            ndq += (long long)G.npp * nherm_host(lq) * G.len;
+            for (int r = 0; r < G.len; ++r) pos_grp[G.begin + r] = g;
+        }
+    std::vector<std::vector<FkJengTile>> bucket(kJengNB * kJengNB);
+    const double tau = c->opts.tau;
+    for (int P = 0; P < NPC; ++P) {
+        const auto &LP_ = c->cls_list[P];
+        if (LP_.empty()) continue;
+        const int lp = c->sh_l[c->pr_sa[LP_[0]]] + c->sh_l[c->pr_sb[LP_[0]]];
+        for (int Q = 0; Q < NPC; ++Q) {
+            const auto &LQ_ = c->cls_list[Q];
+            if (LQ_.empty()) continue;
+            const int lq = c->sh_l[c->pr_sa[LQ_[0]]] + c->sh_l[c->pr_sb[LQ_[0]]];
+            auto &tl = bucket[lp * kJengNB + lq];
+            for (int bra : LP_) {
+                const double gb = c->pr_G[bra];
+                for (size_t gi = 0; gi < c->cls_groups[Q].size(); ++gi) {
+                    const auto &g = c->cls_groups[Q][gi];
+                    int cnt = g.second - g.first;
+                    if (tau > 0) {  // prefix with G_bra G_ket >= tau (G descending in a group)
+                        int lo = g.first, hi = g.second;
+                        while (lo < hi) {
+                            const int mid = (lo + hi) / 2;
+                            if (gb * c->pr_G[LQ_[mid]] >= tau) lo = mid + 1; else hi = mid;
+                        }
+                        cnt = lo - g.first;
+                    }
+                    for (int kk = 0; kk < cnt; kk += 64)
+                        tl.push_back(FkJengTile{bra, c->ket_off[Q] + g.first + kk, std::min(64, cnt - kk),
+                                                c->cls_group0[Q] + (int)gi});
+                }
+            }
+            (void)lq;
+        }
+    }
+    std::vector<FkJengTile> all;
+    c->jeng_toff.assign(kJengNB * kJengNB + 1, 0);
+    for (int k = 0; k < kJengNB * kJengNB; ++k) {
+        auto &tl = bucket[k];
+        auto cost = [&](const FkJengTile &t) {
+            return (long long)c->pr_npp[t.bra] * c->groups[t.grp].npp * t.ket_count;
+        };
+        std::stable_sort(tl.begin(), tl.end(), [&](const FkJengTile &x, const FkJengTile &y) { return cost(x) > cost(y); });
+        c->jeng_toff[k] = (int64_t)all.size();
+        all.insert(all.end(), tl.begin(), tl.end());
+    }
+    c->jeng_toff[kJengNB * kJengNB] = (int64_t)all.size();
+    int rc;
+    if ((rc = dev_upload(c, c->d_jeng_tiles, all.data(), all.size())) || (rc = dev_upload(c, c->d_jp_off, jp_off.data(), jp_off.size())) ||
+        (rc = dev_upload(c, c->d_dq_base, dq_base.data(), dq_base.size())) ||
+        (rc = dev_upload(c, c->d_pos_grp, pos_grp.data(), pos_grp.size())) ||
+        (rc = dev_upload<double>(c, c->d_jp, nullptr, (size_t)std::max<long long>(njp, 1))) ||
+        (rc = dev_upload<double>(c, c->d_dq, nullptr, (size_t)std::max<long long>(ndq, 1))))
+        return rc;
+    c->jp_n = (size_t)njp;
+    c->jeng_valid = true;
+    return FK_OK;
+}
+
+// J by the J engine into X_J (block per bra pair; see k_jeng_jab).
+int jeng_build(fk_ctx *c, const JKBufs &b, hipStream_t st)
+{
+    if (fk_kernels_launch_fill(c->d_jp.p, (long long)c->jp_n, st)) return fail(c, FK_ERR_HIP, "fill kernel launch failed");
+    const int nlist = (int)c->ket_list_all.size();
+    for (int Q = 0; Q < NPC; ++Q) {
+        if (c->cls_list[Q].empty()) continue;
+        FkJengDqArgs a;
+        a.groups = c->d_groups.p; a.pos_grp = c->d_pos_grp.p;
+        a.pos0 = c->ket_off[Q]; a.npos = (int)c->cls_list[Q].size();
+        a.lst_sa = c->d_lst_sa.p; a.lst_sb = c->d_lst_sb.p; a.lst_CD = c->d_lst_CD.p; a.nlist = nlist;
+        a.ppT = c->d_ppT.p; a.sh_bf = c->d_sh_bf.p; a.Ds = b.Ds; a.n = c->nbf;
+        a.dq_base = c->d_dq_base.p; a.dq = c->d_dq.p;
+        const int p0 = c->cls_list[Q][0];
+        if (fk_jeng_launch_dq(c->sh_l[c->pr_sa[p0]], c->sh_l[c->pr_sb[p0]], &a, st))
+            return fail(c, FK_ERR_HIP, "J engine: D_q kernel launch failed");
+    }
+    FkJengArgs a;
+    a.pair_ppoff = c->d_pr_ppoff.p; a.pair_npp = c->d_pr_npp.p; a.pair_G = c->d_pr_G.p; a.pp = c->d_pp.p;
+    a.jp_off = c->d_jp_off.p; a.jp = c->d_jp.p; a.ppT = c->d_ppT.p; a.groups = c->d_groups.p;
+    a.lst_G = c->d_lst_G.p; a.lst_sa = c->d_lst_sa.p; a.lst_sb = c->d_lst_sb.p;
+    a.dq_base = c->d_dq_base.p; a.dq = c->d_dq.p; a.Dsh = b.Dsh; a.ns = c->nshell;
+    a.dscreen = c->opts.density_screen && c->opts.tau > 0 ? 1 : 0;
+    a.tau = c->opts.tau * c->dscreen_scale;
+    for (int lp = 0; lp < kJengNB; ++lp)
+        for (int lq = 0; lq < kJengNB; ++lq) {
+            const int k = lp * kJengNB + lq;
+            const int64_t nt = c->jeng_toff[k + 1] - c->jeng_toff[k];
+            if (nt <= 0) continue;
+            a.tiles = c->d_jeng_tiles.p + c->jeng_toff[k];
+            a.ntiles = nt;
+            a.rys_tab = c->d_rys.p + rys_staged_offset((lp + lq) / 2 + 1);
+            const int grid = (int)std::max<int64_t>(1, std::min<int64_t>((nt + 3) / 4, 8LL * std::max(c->ncu, 1)));
+            if (fk_jeng_launch_jp(lp, lq, &a, grid, st)) return fail(c, FK_ERR_HIP, "J engine: J_p kernel launch failed");
+        }
+    for (int P = 0; P < NPC; ++P) {
+        if (c->cls_list[P].empty()) continue;
+        FkJengJabArgs j;
+        j.pairs = c->d_ket.p + c->ket_off[P]; j.npairs = (int)c->cls_list[P].size();
+        j.pair_sa = c->d_pr_sa.p; j.pair_sb = c->d_pr_sb.p; j.pair_ppoff = c->d_pr_ppoff.p; j.pair_npp = c->d_pr_npp.p;
+        j.pair_AB = c->d_pr_AB.p; j.pp = c->d_pp.p; j.jp_off = c->d_jp_off.p; j.jp = c->d_jp.p;
+        j.sh_bf = c->d_sh_bf.p; j.XJ = b.X; j.n = c->nbf;
+        const int p0 = c->cls_list[P][0];
+        if (fk_jeng_launch_jab(c->sh_l[c->pr_sa[p0]], c->sh_l[c->pr_sb[p0]], &j, st))
+            return fail(c, FK_ERR_HIP, "J engine: J_ab kernel launch failed");
+    }
+    return FK_OK;
+}
+
 int build_jk_impl(fk_ctx *c, const double *D, double *J, double *K, unsigned flags, void *stream, const JKBufs &b)
 {
     if ((flags & FK_J_ONLY) && (flags & FK_K_ONLY))
@@ -1080,7 +1233,10 @@ int build_jk_impl(fk_ctx *c, const double *D, double *J, double *K, unsigned fla
         return fail(c, FK_ERR_ARG, "fk_build_jk: null matrix pointer");
     if (!(want & FK_WANT_J)) J = nullptr;
     if (!(want & FK_WANT_K)) K = nullptr;
+    const bool jeng = (flags & FK_J_ENGINE) && (want & FK_WANT_J);
     hipSetDevice(c->device);
+    int rcj;
+    if (jeng && (rcj = ensure_jeng(c))) return rcj;
     hipStream_t st = (hipStream_t)stream;
     // one nbf_m^2 block per molecule, concatenated
     const size_t nn = (size_t)c->mol_base[c->nmol];
@@ -1113,9 +1269,15 @@ int build_jk_impl(fk_ctx *c, const double *D, double *J, double *K, unsigned fla
             HIPCHK(c, hipEventCreate(&e));
             c->ev.push_back(e);
         }
+    // with the J engine the Rys kernels form K only (or nothing)
+    const int want_rys = jeng ? (want & FK_WANT_K) : want;
     for (size_t i = 0; i < c->qclasses.size(); ++i) {
         const QuartetClass &qc = c->qclasses[i];
         if (c->timed) HIPCHK(c, hipEventRecord(c->ev[2 * i], st));
+        if (want_rys == 0) {
+            if (c->timed) HIPCHK(c, hipEventRecord(c->ev[2 * i + 1], st));
+            continue;
+        }
         FkJKArgs a;
         a.sh_bf = c->d_sh_bf.p;
         a.mol_sh0 = c->d_mol_sh0.p;
@@ -1147,7 +1309,7 @@ int build_jk_impl(fk_ctx *c, const double *D, double *J, double *K, unsigned fla
         // workgroups add into copy blockIdx mod FK_XCD_COPIES; one copy: all alias it
         a.xcopy = b.ncopy > 1 ? b.xcopy : 0;
         a.dscreen = c->opts.density_screen && c->opts.tau > 0;
-        a.want = want;
+        a.want = want_rys;
         a.tau = c->opts.tau * c->dscreen_scale;
         a.rys_tab = c->d_rys.p + rys_staged_offset(qc.info.nroot);
         a.counters = b.cnt + 2 * i;
@@ -1170,6 +1332,7 @@ int build_jk_impl(fk_ctx *c, const double *D, double *J, double *K, unsigned fla
             return fail(c, FK_ERR_HIP, "J/K kernel launch failed for class (%d|%d)", qc.P, qc.Q);
         if (c->timed) HIPCHK(c, hipEventRecord(c->ev[2 * i + 1], st));
     }
+    if (jeng && (rcj = jeng_build(c, b, st))) return rcj;
     if (fk_kernels_launch_finalize(b.X, b.X + nn, b.xcopy, b.ncopy, c->d_bf_scale.p, &ma, Jd, Kd, st))
         return fail(c, FK_ERR_HIP, "finalize kernel launch failed");
     c->stats_pending = true;
@@ -1203,8 +1366,8 @@ int fk_build_jk_noalloc(fk_ctx *c, const double *D, double *J, double *K, unsign
     if (!c) return FK_ERR_ARG;
     if (c->device < 0) return fail(c, FK_ERR_STATE, "fk_build_jk_noalloc: context has no device");
     if (!c->have_quartets) return fail(c, FK_ERR_STATE, "fk_build_jk_noalloc: call fk_build_quartets first");
-    if (!(flags & FK_DEVICE_PTRS) || (flags & FK_TIME_CLASSES))
-        return fail(c, FK_ERR_ARG, "fk_build_jk_noalloc: needs FK_DEVICE_PTRS and takes no FK_TIME_CLASSES");
+    if (!(flags & FK_DEVICE_PTRS) || (flags & (FK_TIME_CLASSES | FK_J_ENGINE)))
+        return fail(c, FK_ERR_ARG, "fk_build_jk_noalloc: needs FK_DEVICE_PTRS and takes no FK_TIME_CLASSES or FK_J_ENGINE");
     const long long nn = c->mol_base[c->nmol], nsh = c->mol_shbase[c->nmol];
     if (nn > FK_NOALLOC_MAX_NMAT || nsh > FK_NOALLOC_MAX_NSHMAT)
         return fail(c, FK_ERR_ARG,
@@ -1519,7 +1682,7 @@ int fk_autotune(fk_ctx *c, const double *D, unsigned flags, int reps, void *stre
 int fk_debug_eri(fk_ctx *c, int nq, const int *quartets, double *out, int mode)
 {
     if (!c) return FK_ERR_ARG;
-    if (mode < 0 || mode > 3) return fail(c, FK_ERR_ARG, "fk_debug_eri: mode must be 0..3");
+    if (mode < 0 || mode > 5) return fail(c, FK_ERR_ARG, "fk_debug_eri: mode must be 0..5");
     const int on_device = mode & 1, engine = mode >> 1;
     if (c->nmol > 1) return fail(c, FK_ERR_UNSUPPORTED, "fk_debug_eri: not available for a batch of molecules");
     if (!c->have_quartets) return fail(c, FK_ERR_STATE, "fk_debug_eri: call fk_build_quartets first");

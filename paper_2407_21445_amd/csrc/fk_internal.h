@@ -151,7 +151,63 @@ int fk_kernels_launch_finalize(const double *XJ, const double *XK, long long xco
 int fk_kernels_launch_fill(double *p, long long n, void *stream);
 int fk_kernels_debug_host(int P, int Q, const int *pair_ppoff, const int *pair_npp, const double *pair_AB,
                           const double *pp, const int *quartets, int nq, double *out, int engine);
+// ---- J engine (McMurchie-Davidson; paper, "J matrix implementation") ----
+// Work tile of the J_p kernel: one bra pair against up to 64 kets of one
+// primitive-count group (consecutive list positions).
+struct FkJengTile {
+    int bra, ket_begin, ket_count, grp;
+};
+// Hermite-contracted ket density D_q and the J_p accumulation.
+struct FkJengArgs {
+    const int *pair_ppoff, *pair_npp;
+    const double *pair_G, *pp;
+    const long long *jp_off;  // per pair: first element of its J_p block [npp][nherm(la+lb)]
+    double *jp;
+    const double *ppT;        // transposed ket primitive records (see FkGroup)
+    const FkGroup *groups;
+    const double *lst_G;
+    const int *lst_sa, *lst_sb;
+    const long long *dq_base; // per group: first element of its D_q block [npp][nherm(lc+ld)][len]
+    const double *dq;
+    const double *Dsh;
+    int ns, dscreen;
+    double tau;
+    const FkJengTile *tiles;
+    long long ntiles;
+    const double *rys_tab;
+};
+struct FkJengDqArgs {
+    const FkGroup *groups;
+    const int *pos_grp;       // group of each list position
+    int pos0, npos;           // the list positions of one ket class
+    const int *lst_sa, *lst_sb;
+    const double *lst_CD;
+    int nlist;
+    const double *ppT;
+    const int *sh_bf;
+    const double *Ds;
+    int n;
+    const long long *dq_base;
+    double *dq;
+};
+struct FkJengJabArgs {
+    const int *pairs;         // pair indices of one bra class
+    int npairs;
+    const int *pair_sa, *pair_sb, *pair_ppoff, *pair_npp;
+    const double *pair_AB, *pp;
+    const long long *jp_off;
+    const double *jp;
+    const int *sh_bf;
+    double *XJ;
+    int n;
+};
+// the J engine is built for total pair momenta up to this (s, p, d shells)
+#define FK_JENG_MAX_LP 4
+
 // dense SCF kernels (fk_scf.hip); n x n row-major FP64 device matrices
+int fk_jeng_launch_dq(int lc, int ld, const FkJengDqArgs *a, void *stream);
+int fk_jeng_launch_jp(int LP, int LQ, const FkJengArgs *a, int grid, void *stream);
+int fk_jeng_launch_jab(int la, int lb, const FkJengJabArgs *a, void *stream);
 int fk_scf_gemm(const double *A, const double *B, double *C, int n, double alpha, double beta, void *stream);
 int fk_scf_lincomb(double *out, const double *x, const double *y, const double *z, int n, double a, double b,
                    double c, double d, void *stream);

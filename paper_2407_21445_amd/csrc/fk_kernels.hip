@@ -22,6 +22,7 @@
 #include "fk_internal.h"
 #include "fk_eri.h"
 #include "fk_hgp.h"
+#include "fk_mmd.h"
 
 #ifndef FK_BUILD_MAXL
 #define FK_BUILD_MAXL 3
@@ -1332,6 +1333,23 @@ struct Disp {
             p.K = r[8];
             return p;
         };
+        if (eng == 2) {
+            // the McMurchie-Davidson pieces of the J engine (E and R), host only
+            if constexpr (LA + LB + LC + LD <= 8) {
+                for (int q = 0; q < nq; ++q) {
+                    const int bra = qs[2 * q], ket = qs[2 * q + 1];
+                    double *o = out + (size_t)q * C::NOUT;
+                    for (int k = 0; k < C::NOUT; ++k) o[k] = 0.0;
+                    for (int i = 0; i < npp[bra]; ++i)
+                        for (int j = 0; j < npp[ket]; ++j)
+                            fk::mmd_prim_all<LA, LB, LC, LD>(tab, ld(ppoff[bra] + i), ld(ppoff[ket] + j), AB + 3 * bra,
+                                                             AB + 3 * ket, o);
+                }
+                return 0;
+            } else {
+                return -2;
+            }
+        }
         if (eng != 0) {
             if constexpr (HGP) {
                 using H = fk::HgpClass<LA, LB, LC, LD>;
@@ -1444,7 +1462,243 @@ const void *kern_q(int q, int eng)
 
 }  // namespace
 
-#if FK_ONLY_P >= 0
+#if FK_ONLY_P == -2
+// ---- J engine translation unit (paper, "J matrix implementation") ----
+// Per build: D_q = sum_cd E^{cd}_q D_cd per ket primitive pair (k_jeng_dq),
+// J_p = sum_q [p|q] D_q per bra primitive pair over the Schwarz- and
+// density-screened kets (k_jeng_jp), J_ab = sum_p E^{ab}_p J_p contracted over
+// the bra primitives (k_jeng_jab).  Bra-ket symmetry is not used (every bra
+// takes all its kets, as the paper's J kernels do), so no J_cd digestion.
+namespace {
+
+// D_q of every primitive pair of one ket class: one thread per list position.
+template <int LC, int LD>
+__global__ void __launch_bounds__(256) k_jeng_dq(FkJengDqArgs a)
+{
+    constexpr int LQ = LC + LD, NHQ = fk::nherm(LQ), NC = fk::ncart(LC), ND = fk::ncart(LD);
+    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= a.npos) return;
+    const int pos = a.pos0 + idx;
+    const FkGroup g = a.groups[a.pos_grp[pos]];
+    const int r = pos - g.begin;
+    const int sc = a.lst_sa[pos], sd = a.lst_sb[pos];
+    const int oc = a.sh_bf[sc], od = a.sh_bf[sd];
+    const double CD[3] = {a.lst_CD[pos], a.lst_CD[a.nlist + pos], a.lst_CD[2 * a.nlist + pos]};
+    // both orders (c, d) and (d, c) of a pair of distinct shells contribute
+    const double fac = sc == sd ? 1.0 : 2.0;
+    double dcd[NC * ND];
+#pragma unroll
+    for (int ic = 0; ic < NC; ++ic)
+#pragma unroll
+        for (int id = 0; id < ND; ++id) dcd[ic * ND + id] = fac * a.Ds[(size_t)(oc + ic) * a.n + od + id];
+    double *out = a.dq + a.dq_base[a.pos_grp[pos]] + r;
+    for (int j = 0; j < g.npp; ++j) {
+        const fk::PrimPair q = load_ket_pp(a.ppT, g, j, r);
+        double E[3][LC + 1][LD + 1][LQ + 1];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) fk::mmd_e1<LC, LD>(q.oo2z, q.PA[k], q.PA[k] + CD[k], E[k]);
+#pragma unroll
+        for (int h = 0; h < NHQ; ++h) {
+            const int t = fk::kComp.x[h], u = fk::kComp.y[h], v = fk::kComp.z[h];
+            double s = 0.0;
+#pragma unroll
+            for (int ic = 0; ic < NC; ++ic)
+#pragma unroll
+                for (int id = 0; id < ND; ++id) {
+                    const int cx = fk::kCart.x[LC][ic], cy = fk::kCart.y[LC][ic], cz = fk::kCart.z[LC][ic];
+                    const int dx = fk::kCart.x[LD][id], dy = fk::kCart.y[LD][id], dz = fk::kCart.z[LD][id];
+                    if (t > cx + dx || u > cy + dy || v > cz + dz) continue;
+                    s += E[0][cx][dx][t] * E[1][cy][dy][u] * E[2][cz][dz][v] * dcd[ic * ND + id];
+                }
+            out[((size_t)j * NHQ + h) * g.len] = s;
+        }
+    }
+}
+
+// J_p of the bra primitive pairs: one wave per tile (bra, <= 64 kets), lane =
+// ket; per bra primitive the lanes' sums over their kets' primitives are
+// reduced over the wave and added to J_p.
+template <int LP, int LQ>
+__global__ void __launch_bounds__(FK_BLOCK) k_jeng_jp(FkJengArgs a)
+{
+    constexpr int L = LP + LQ, NR = L / 2 + 1;
+    constexpr int NHP = fk::nherm(LP), NHQ = fk::nherm(LQ), NHR = fk::nherm(L);
+    __shared__ double s_tab[rys_lds_size(NR)];
+    load_table<NR>(s_tab, a.rys_tab);
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const long long nwt = (long long)gridDim.x * FK_WAVES;
+    for (long long t = (long long)blockIdx.x * FK_WAVES + wave; t < a.ntiles; t += nwt) {
+        const FkJengTile tile = a.tiles[t];
+        const FkGroup g = a.groups[tile.grp];
+        const bool inrange = lane < tile.ket_count;
+        const int pos = tile.ket_begin + (inrange ? lane : 0);
+        const int r = pos - g.begin;
+        const double gg = a.pair_G[tile.bra] * a.lst_G[pos];
+        bool active = inrange && (a.tau <= 0 || gg >= a.tau);
+        if (a.dscreen) active = active && gg * a.Dsh[a.lst_sa[pos] * a.ns + a.lst_sb[pos]] >= a.tau;
+        if (__ballot(active) == 0ull) continue;
+        const int ppo = __builtin_amdgcn_readfirstlane(a.pair_ppoff[tile.bra]);
+        const int bnpp = __builtin_amdgcn_readfirstlane(a.pair_npp[tile.bra]);
+        const long long jo = a.jp_off[tile.bra];
+        const double *__restrict dqp = a.dq + a.dq_base[tile.grp] + r;
+        for (int i = 0; i < bnpp; ++i) {
+            const fk::PrimPair p = sload_pp(a.pp, ppo + i);
+            double jp[NHP];
+#pragma unroll
+            for (int h = 0; h < NHP; ++h) jp[h] = 0.0;
+            if (active) {
+                for (int j = 0; j < g.npp; ++j) {
+                    const fk::PrimPair q = load_ket_pp(a.ppT, g, j, r);
+                    double dq[NHQ];
+#pragma unroll
+                    for (int h = 0; h < NHQ; ++h) dq[h] = dqp[((size_t)j * NHQ + h) * g.len];
+                    const fk::QuartetSetup s = fk::quartet_setup(p, q);
+                    double R[NHR];
+                    fk::mmd_r<L>(s_tab, s, p.zeta * q.zeta * s.inv, R);
+#pragma unroll
+                    for (int hp = 0; hp < NHP; ++hp)
+#pragma unroll
+                        for (int hq = 0; hq < NHQ; ++hq) {
+                            const int tx = fk::kComp.x[hp] + fk::kComp.x[hq];
+                            const int ty = fk::kComp.y[hp] + fk::kComp.y[hq];
+                            const int tz = fk::kComp.z[hp] + fk::kComp.z[hq];
+                            const double v = R[fk::cidx(tx, ty, tz)] * dq[hq];
+                            // [p|q] = (-1)^{|q|} R_{p+q}
+                            if ((fk::kComp.x[hq] + fk::kComp.y[hq] + fk::kComp.z[hq]) & 1) jp[hp] -= v;
+                            else jp[hp] += v;
+                        }
+                }
+            }
+#pragma unroll
+            for (int h = 0; h < NHP; ++h) {
+                const double sum = wave_sum(jp[h]);
+                if (lane == 0 && sum != 0.0) atomic_add(&a.jp[jo + (long long)i * NHP + h], sum);
+            }
+        }
+    }
+}
+
+// J_ab of every pair of one bra class: one thread per pair, its block of X_J
+// (a full block for two distinct shells, half a block for a shell with itself:
+// J = X_J + X_J^T then restores both).
+template <int LA, int LB>
+__global__ void __launch_bounds__(256) k_jeng_jab(FkJengJabArgs a)
+{
+    constexpr int LP = LA + LB, NHP = fk::nherm(LP), NA = fk::ncart(LA), NB = fk::ncart(LB);
+    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= a.npairs) return;
+    const int pr = a.pairs[idx];
+    const int sa = a.pair_sa[pr], sb = a.pair_sb[pr];
+    const int oa = a.sh_bf[sa], ob = a.sh_bf[sb];
+    const double AB[3] = {a.pair_AB[3 * pr], a.pair_AB[3 * pr + 1], a.pair_AB[3 * pr + 2]};
+    const long long jo = a.jp_off[pr];
+    double acc[NA * NB];
+#pragma unroll
+    for (int o = 0; o < NA * NB; ++o) acc[o] = 0.0;
+    for (int i = 0; i < a.pair_npp[pr]; ++i) {
+        const fk::PrimPair p = load_pp(a.pp, a.pair_ppoff[pr] + i);
+        double E[3][LA + 1][LB + 1][LP + 1];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) fk::mmd_e1<LA, LB>(p.oo2z, p.PA[k], p.PA[k] + AB[k], E[k]);
+        double jv[NHP];
+#pragma unroll
+        for (int h = 0; h < NHP; ++h) jv[h] = a.jp[jo + (long long)i * NHP + h];
+#pragma unroll
+        for (int ia = 0; ia < NA; ++ia)
+#pragma unroll
+            for (int ib = 0; ib < NB; ++ib) {
+                const int ax = fk::kCart.x[LA][ia], ay = fk::kCart.y[LA][ia], az = fk::kCart.z[LA][ia];
+                const int bx = fk::kCart.x[LB][ib], by = fk::kCart.y[LB][ib], bz = fk::kCart.z[LB][ib];
+                double s = 0.0;
+#pragma unroll
+                for (int h = 0; h < NHP; ++h) {
+                    const int t = fk::kComp.x[h], u = fk::kComp.y[h], v = fk::kComp.z[h];
+                    if (t > ax + bx || u > ay + by || v > az + bz) continue;
+                    s += E[0][ax][bx][t] * E[1][ay][by][u] * E[2][az][bz][v] * jv[h];
+                }
+                acc[ia * NB + ib] += s;
+            }
+    }
+    const double fac = sa == sb ? 0.5 : 1.0;
+#pragma unroll
+    for (int ia = 0; ia < NA; ++ia)
+#pragma unroll
+        for (int ib = 0; ib < NB; ++ib) a.XJ[(size_t)(oa + ia) * a.n + ob + ib] = fac * acc[ia * NB + ib];
+}
+
+template <int LC, int LD>
+int launch_dq(const FkJengDqArgs *a, hipStream_t st)
+{
+    if (a->npos <= 0) return 0;
+    hipLaunchKernelGGL((k_jeng_dq<LC, LD>), dim3((a->npos + 255) / 256), dim3(256), 0, st, *a);
+    return hipGetLastError() == hipSuccess ? 0 : -3;
+}
+template <int LP, int LQ>
+int launch_jp(const FkJengArgs *a, int grid, hipStream_t st)
+{
+    if (a->ntiles <= 0) return 0;
+    hipLaunchKernelGGL((k_jeng_jp<LP, LQ>), dim3(grid), dim3(FK_BLOCK), 0, st, *a);
+    return hipGetLastError() == hipSuccess ? 0 : -3;
+}
+template <int LA, int LB>
+int launch_jab(const FkJengJabArgs *a, hipStream_t st)
+{
+    if (a->npairs <= 0) return 0;
+    hipLaunchKernelGGL((k_jeng_jab<LA, LB>), dim3((a->npairs + 255) / 256), dim3(256), 0, st, *a);
+    return hipGetLastError() == hipSuccess ? 0 : -3;
+}
+template <int LP, int LQ = 0>
+int jp_q(int lq, const FkJengArgs *a, int grid, hipStream_t st)
+{
+    if constexpr (LQ > FK_JENG_MAX_LP) return -2;
+    else return lq == LQ ? launch_jp<LP, LQ>(a, grid, st) : jp_q<LP, LQ + 1>(lq, a, grid, st);
+}
+
+}  // namespace
+
+extern "C" {
+// pair classes (l1 >= l2) up to d
+int fk_jeng_launch_dq(int lc, int ld, const FkJengDqArgs *a, void *stream)
+{
+    hipStream_t st = (hipStream_t)stream;
+    switch (lc * 3 + ld) {
+    case 0: return launch_dq<0, 0>(a, st);
+    case 3: return launch_dq<1, 0>(a, st);
+    case 4: return launch_dq<1, 1>(a, st);
+    case 6: return launch_dq<2, 0>(a, st);
+    case 7: return launch_dq<2, 1>(a, st);
+    case 8: return launch_dq<2, 2>(a, st);
+    default: return -2;
+    }
+}
+int fk_jeng_launch_jab(int la, int lb, const FkJengJabArgs *a, void *stream)
+{
+    hipStream_t st = (hipStream_t)stream;
+    switch (la * 3 + lb) {
+    case 0: return launch_jab<0, 0>(a, st);
+    case 3: return launch_jab<1, 0>(a, st);
+    case 4: return launch_jab<1, 1>(a, st);
+    case 6: return launch_jab<2, 0>(a, st);
+    case 7: return launch_jab<2, 1>(a, st);
+    case 8: return launch_jab<2, 2>(a, st);
+    default: return -2;
+    }
+}
+int fk_jeng_launch_jp(int LP, int LQ, const FkJengArgs *a, int grid, void *stream)
+{
+    hipStream_t st = (hipStream_t)stream;
+    switch (LP) {
+    case 0: return jp_q<0>(LQ, a, grid, st);
+    case 1: return jp_q<1>(LQ, a, grid, st);
+    case 2: return jp_q<2>(LQ, a, grid, st);
+    case 3: return jp_q<3>(LQ, a, grid, st);
+    case 4: return jp_q<4>(LQ, a, grid, st);
+    default: return -2;
+    }
+}
+}
+#elif FK_ONLY_P >= 0
 // ---- per bra-class translation unit ----
 extern "C" {
 int FK_CAT(fk_kp, FK_ONLY_P, _info)(int Q, FkClassInfo *i) { return info_q<FK_ONLY_P>(Q, i); }

@@ -567,3 +567,50 @@ def test_j_only_and_k_only(fk, torch, c2, only):
     Jb, Kb = oracle.jk_blocks(s, D, blocks if only == "J" else [], blocks if only == "K" else [])
     for (a, b), blk in zip(blocks, Jb if only == "J" else Kb):
         assert np.max(np.abs(M[off[a]:off[a + 1], off[b]:off[b + 1]] - blk)) <= 1e-8, (a, b)
+
+
+def test_j_engine_spd_unscreened(fk, torch):
+    """The McMurchie-Davidson J engine (FK_J_ENGINE) on a random s, p, d
+    system, unscreened, random density: J equals the oracle within 1e-10
+    (relative to max(1, |J|max)); with K requested, K comes from the Rys
+    kernels and equals the oracle too; J-only leaves K untouched."""
+    s = _rand_sys(35, lmax=2, natom=4, kmax=3)
+    D = _rand_D(s["nbf"], 7)
+    c = fk.FockJK(0).set_system(s).build_quartets(tau=0.0)
+    Dd = torch.tensor(D, dtype=torch.float64, device="cuda")
+    Jo, Ko = oracle.jk(s, D)
+    scale = max(1.0, float(np.max(np.abs(Jo))))
+    J, K = c.build_jk(Dd, sync=True, j_engine=True)
+    assert np.max(np.abs(J.cpu().numpy() - Jo)) <= 1e-10 * scale
+    assert np.max(np.abs(K.cpu().numpy() - Ko)) <= 1e-10 * scale
+    sentinel = torch.full_like(Dd, 7.0)
+    J1, _ = c.build_jk(Dd, K=sentinel, only="J", sync=True, j_engine=True)
+    assert torch.all(sentinel == 7.0).item()
+    assert np.max(np.abs(J1.cpu().numpy() - Jo)) <= 1e-10 * scale
+
+
+def test_j_engine_water64(fk, torch, c3):
+    """(H2O)64 cc-pVDZ-type at the production threshold (tau = 1e-10,
+    primitive pairs pruned at 1e-12): J from the J engine within 1e-8 of the
+    oracle's sampled blocks and within 1e-8 of the Rys J everywhere."""
+    s, D, jp, kp, Jb, Kb = c3
+    c = fk.FockJK(0).set_system(s).build_quartets(tau=1e-10, tau_prim=1e-12)
+    Dd = torch.tensor(D, dtype=torch.float64, device="cuda")
+    Je, _ = c.build_jk(Dd, only="J", sync=True, j_engine=True)
+    Jr, _ = c.build_jk(Dd, only="J", sync=True)
+    Je, Jr = Je.cpu().numpy(), Jr.cpu().numpy()
+    off = oracle.bf_offsets(s)
+    for (a, b), blk in zip(jp, Jb):
+        assert np.max(np.abs(Je[off[a]:off[a + 1], off[b]:off[b + 1]] - blk)) <= 1e-8, (a, b)
+    assert np.max(np.abs(Je - Jr)) <= 1e-8
+    c.close()
+
+
+def test_j_engine_refuses_f_shells_and_batches(fk, torch):
+    s = _rand_sys(33, lmax=3, natom=3, kmax=2)
+    s["charge"] = 1
+    c = fk.FockJK(0).set_system(s).build_quartets(tau=1e-10)
+    Dd = torch.zeros((s["nbf"], s["nbf"]), dtype=torch.float64, device="cuda")
+    with pytest.raises(fk.FockJKError) as e:
+        c.build_jk(Dd, only="J", j_engine=True)
+    assert e.value.code == fk.FK_ERR_UNSUPPORTED
