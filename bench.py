@@ -306,17 +306,17 @@ def bench_batch(args, torch, fk):
     return 0
 
 
-def _time_builds(torch, ctx, Dd, J, K, stream, warmup, steps):
+def _time_builds(torch, ctx, Dd, J, K, stream, warmup, steps, j_engine=False):
     """Milliseconds per build: `warmup` untimed builds, then `steps` builds
     between HIP events on the build stream, bracketed by device syncs."""
     for _ in range(warmup):
-        ctx.build_jk(Dd, J, K, stream=stream)
+        ctx.build_jk(Dd, J, K, stream=stream, j_engine=j_engine)
     torch.cuda.synchronize()
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
     e0.record(stream)
     for _ in range(steps):
-        ctx.build_jk(Dd, J, K, stream=stream)
+        ctx.build_jk(Dd, J, K, stream=stream, j_engine=j_engine)
     e1.record(stream)
     torch.cuda.synchronize()
     return e0.elapsed_time(e1) / steps
@@ -412,7 +412,7 @@ def bench_single(args, torch, fk):
 
     arch = torch.cuda.get_device_properties(dev).gcnArchName.split(":")[0]
 
-    def make(tau_fp32, key):
+    def make(tau_fp32, key, tau_k=0.0):
         c = fk.FockJK(0).set_system(sys_)
         for spec in args.schedule:
             v = spec.split(",")
@@ -424,7 +424,7 @@ def bench_single(args, torch, fk):
         if args.engine == "hgp":
             _hgp_everywhere(fk, c)
         src = _load_cached(c, key, arch, args)
-        return c.build_quartets(tau=args.tau, tau_prim=args.tau_prim, tau_fp32=tau_fp32), src
+        return c.build_quartets(tau=args.tau, tau_prim=args.tau_prim, tau_fp32=tau_fp32, tau_k=tau_k), src
 
     ctx, src64 = make(0.0, f"{args.workload}_fp64")
     info = ctx.info()
@@ -506,6 +506,23 @@ def bench_single(args, torch, fk):
         out["mixed"]["schedules"] = tune_mx
         _progress(f"mixed build {ms_mx:.2f} ms ({n32 / max(1, stm['quartets']):.2f} FP32 quartets)")
         ref = mx
+    split = None
+    if args.split and all(l <= 2 for l in sys_["sh_l"]):
+        # the split build of the paper's opt-UM scheme: J by the McMurchie-
+        # Davidson J engine, K by the Rys kernels at the looser K threshold
+        split, _ = make(0.0, f"{args.workload}_fp64", tau_k=args.tau_k)
+        Js, Ks = torch.empty_like(Dd), torch.empty_like(Dd)
+        split.build_jk(Dd, Js, Ks, stream=stream, j_engine=True, sync=True)  # its lists
+        ms_sp = _time_builds(torch, split, Dd, Js, Ks, stream, args.warmup, args.steps, j_engine=True)
+        ctx.build_jk(Dd, J, K, stream=stream)
+        torch.cuda.synchronize()
+        dJ = (Js - J).cpu().numpy()
+        dK = (Ks - K).cpu().numpy()
+        out["split_jk"] = {"tau_k": args.tau_k, "ms_per_step": ms_sp, "builds_per_s": 1000.0 / ms_sp,
+                           "speedup_vs_fused": ms / ms_sp,
+                           "max_abs_dJ": float(np.max(np.abs(dJ))), "max_abs_dK": float(np.max(np.abs(dK))),
+                           "dE_one_build": float(0.5 * np.sum(D * dJ) - 0.25 * np.sum(D * dK))}
+        _progress(f"split J-engine/K build {ms_sp:.2f} ms")
     if not args.no_scf:
         # SCF from the core-Hamiltonian guess on the same lists (outside the
         # timed region): |dE| < 1e-10, max |error| < 1e-8
@@ -520,6 +537,13 @@ def bench_single(args, torch, fk):
                                    "energy": rm["energy"], "seconds": rm["total_seconds"],
                                    "jk_seconds": rm["jk_seconds"],
                                    "energy_minus_fp64": rm["energy"] - r["energy"]}
+        if split is not None:
+            # the loose K screen follows D from one iteration to the next, so
+            # this SCF stops at |dE| < 1e-7, max |error| < 1e-5
+            rs = split.run_scf(j_engine=True, e_tol=1e-7, g_tol=1e-5)
+            out["split_jk"]["scf"] = {"iterations": rs["iterations"], "converged": bool(rs["converged"]),
+                                      "energy": rs["energy"], "seconds": rs["total_seconds"],
+                                      "jk_seconds": rs["jk_seconds"], "energy_minus_fused": rs["energy"] - r["energy"]}
         guesses = {"sad": fk.GUESS_SAD}
         model = os.path.join(HERE, "paper_2407_21445_amd", "guess_631gs.npz")
         if sys_["name"].endswith("/6-31gs-type") and os.path.exists(model):
@@ -581,6 +605,9 @@ def main():
     ap.add_argument("--engine", choices=("rys", "hgp"), default="rys",
                     help="integral engine before tuning: hgp selects it for every class it is built for "
                          "(the autotuner may still switch a class)")
+    ap.add_argument("--no-split", dest="split", action="store_false",
+                    help="skip the split build (J engine + K at --tau-k) timed beside the fused one")
+    ap.add_argument("--tau-k", type=float, default=5e-6, help="K threshold of the split build")
     ap.add_argument("--no-scf", action="store_true", help="skip the SCF runs reported beside the build rate")
     ap.add_argument("--no-extra", action="store_true", help="skip the C20H42 reference line")
     ap.add_argument("--no-autotune", dest="autotune", action="store_false",

@@ -101,6 +101,11 @@ typedef struct {
                           screen), in FP64 otherwise.  Set-up, roots, weights,
                           digestion and all accumulation stay FP64; f-f bras stay
                           FP64.  0 = FP64 only */
+    double tau_k;      /* K-block threshold of the K launches in a build with
+                          FK_J_ENGINE (paper, "K matrix implementation": blocks
+                          K_xy whose fitted density bound stays below tau_k are
+                          skipped, see fk_density_bound; the paper uses 5e-6).
+                          0 = no block skip */
 } fk_screen_opts;
 
 typedef struct {
@@ -222,6 +227,20 @@ int fk_build_jk(fk_ctx *ctx, const double *D, double *J, double *K, unsigned fla
 #define FK_NOALLOC_MAX_NMAT (1 << 21)
 #define FK_NOALLOC_MAX_NSHMAT (1 << 18)
 int fk_build_jk_noalloc(fk_ctx *ctx, const double *D, double *J, double *K, unsigned flags, void *stream);
+
+/* Density-decay bound (paper, "K matrix implementation", eq. density_bound):
+ * H and Lambda with |D_uv| <= H exp(-Lambda r_uv) for every element whose
+ * functions sit on different atoms r_uv apart: a least-squares line through
+ * the logarithms of the largest |D| in 64 distance bins (same-atom elements
+ * excluded), raised until it lies on or above every bin's maximum at the bin's
+ * far edge (the printed fit alone is not a bound); Lambda >= 0.  D as in
+ * fk_build_jk (FK_DEVICE_PTRS for a device pointer).  One molecule.  The K
+ * launches of an FK_J_ENGINE build with fk_screen_opts.tau_k > 0 compute it
+ * on the device for their density and skip every K block xy with
+ * H exp(-Lambda max(0, |XY| - R_x - R_y)) G_x G_y <= tau_k (R_x: the largest
+ * distance from shell x to the partner of a pair with G >= tau; G_x: its
+ * largest pair factor); the quartets' other K blocks still count. */
+int fk_density_bound(fk_ctx *ctx, const double *D, unsigned flags, double *H, double *Lambda);
 
 /* Statistics of the last fk_build_jk (waits for it to finish). */
 int fk_stats(fk_ctx *ctx, fk_stats_t *stats);
@@ -350,6 +369,9 @@ typedef struct {
                             Fock eigenvalue +1 hartree so that they stay
                             empty.  For nearly linearly dependent bases.
                             Default 0 */
+    int    j_engine;     /* 1: every build of the run uses FK_J_ENGINE (J by the
+                            J engine, K by the Rys kernels at fk_screen_opts
+                            .tau_k).  Default 0 */
 } fk_scf_opts;
 
 typedef struct {

@@ -37,7 +37,8 @@ MAX_L, MAX_K = 3, 9
 
 class ScreenOpts(ctypes.Structure):
     _fields_ = [("tau", ctypes.c_double), ("tau_prim", ctypes.c_double),
-                ("density_screen", ctypes.c_int), ("bra_block", ctypes.c_int), ("tau_fp32", ctypes.c_double)]
+                ("density_screen", ctypes.c_int), ("bra_block", ctypes.c_int), ("tau_fp32", ctypes.c_double),
+                ("tau_k", ctypes.c_double)]
 
 
 class Info(ctypes.Structure):
@@ -75,7 +76,8 @@ class TuneReport(ctypes.Structure):
 class ScfOpts(ctypes.Structure):
     _fields_ = [("max_iter", ctypes.c_int), ("e_tol", ctypes.c_double), ("g_tol", ctypes.c_double),
                 ("diis_n", ctypes.c_int), ("guess", ctypes.c_int), ("lindep", ctypes.c_double),
-                ("graph", ctypes.c_int), ("incremental", ctypes.c_int), ("canonical", ctypes.c_double)]
+                ("graph", ctypes.c_int), ("incremental", ctypes.c_int), ("canonical", ctypes.c_double),
+                ("j_engine", ctypes.c_int)]
 
 
 class ScfResult(ctypes.Structure):
@@ -107,6 +109,7 @@ _sig = {
     "fk_info": ([_P, ctypes.POINTER(Info)], _I),
     "fk_build_jk": ([_P, _P, _P, _P, _U, _P], _I),
     "fk_build_jk_noalloc": ([_P, _P, _P, _P, _U, _P], _I),
+    "fk_density_bound": ([_P, _P, _U, _P, _P], _I),
     "fk_stats": ([_P, ctypes.POINTER(Stats)], _I),
     "fk_one_electron": ([_P, _P, _P, _P, _P], _I),
     "fk_run_scf": ([_P, ctypes.POINTER(ScfOpts), ctypes.POINTER(ScfResult), _P], _I),
@@ -227,8 +230,9 @@ class FockJK:
         self._check(_lib.fk_molecule_layout(self._ctx, _ptr(nbf), _ptr(off)))
         return nbf, off
 
-    def build_quartets(self, tau=1e-10, tau_prim=0.0, density_screen=True, bra_block=0, tau_fp32=0.0):
-        o = ScreenOpts(float(tau), float(tau_prim), 1 if density_screen else 0, int(bra_block), float(tau_fp32))
+    def build_quartets(self, tau=1e-10, tau_prim=0.0, density_screen=True, bra_block=0, tau_fp32=0.0, tau_k=0.0):
+        o = ScreenOpts(float(tau), float(tau_prim), 1 if density_screen else 0, int(bra_block), float(tau_fp32),
+                       float(tau_k))
         self._check(_lib.fk_build_quartets(self._ctx, ctypes.byref(o)))
         return self
 
@@ -280,6 +284,17 @@ class FockJK:
                                      ctypes.c_void_p(st.cuda_stream)))
         return J, K
 
+    def density_bound(self, D):
+        """(H, Lambda) of the density-decay bound |D_uv| <= H exp(-Lambda r_uv)."""
+        H, L = ctypes.c_double(), ctypes.c_double()
+        if _torch is not None and isinstance(D, _torch.Tensor):
+            self._check(_lib.fk_density_bound(self._ctx, ctypes.c_void_p(D.data_ptr()), FK_DEVICE_PTRS,
+                                              ctypes.byref(H), ctypes.byref(L)))
+        else:
+            Dh = np.ascontiguousarray(D, dtype=np.float64)
+            self._check(_lib.fk_density_bound(self._ctx, _ptr(Dh), 0, ctypes.byref(H), ctypes.byref(L)))
+        return H.value, L.value
+
     def build_jk_noalloc(self, D, J, K, stream=None, sync=False, only=None):
         """fk_build_jk_noalloc: the build in the library's fixed device scratch
         array (no allocation).  D, J, K: contiguous float64 CUDA tensors of
@@ -323,7 +338,7 @@ class FockJK:
         return S, T, V, e.value
 
     def run_scf(self, D0=None, max_iter=100, e_tol=1e-10, g_tol=1e-8, diis_n=8, lindep=1e-8, guess=None,
-                graph=False, incremental=0, canonical=0.0):
+                graph=False, incremental=0, canonical=0.0, j_engine=False):
         """guess: GUESS_CORE (default without D0), GUESS_GIVEN (default with
         D0), GUESS_SAD or GUESS_LEARNED; max_iter=0 returns the initial
         density only; canonical > 0: canonical orthogonalisation dropping
@@ -333,7 +348,7 @@ class FockJK:
         if guess is None:
             guess = GUESS_CORE if D0 is None else GUESS_GIVEN
         o = ScfOpts(int(max_iter), float(e_tol), float(g_tol), int(diis_n), int(guess), float(lindep), int(bool(graph)),
-                    int(incremental), float(canonical))
+                    int(incremental), float(canonical), int(bool(j_engine)))
         r = ScfResult()
         rc = _lib.fk_run_scf(self._ctx, ctypes.byref(o), ctypes.byref(r), _ptr(D))
         if rc not in (FK_OK, FK_ERR_NOT_CONVERGED):

@@ -127,6 +127,11 @@ struct fk_ctx {
     DevBuf<int> d_pos_grp;
     DevBuf<double> d_jp, d_dq;
     size_t jp_n = 0;
+    // density-decay fit and K-block skip (per shell: x, y, z, R, G)
+    DevBuf<int> d_bf_atom;
+    DevBuf<double> d_atom_xyz, d_ks_shell, d_dfit;
+    DevBuf<unsigned long long> d_dfit_bins;
+    double dfit_dr = 1.0;
     // last build
     bool stats_pending = false;
     bool timed = false;
@@ -229,6 +234,7 @@ void free_device(fk_ctx *c)
     dev_free(c->d_lst_G); dev_free(c->d_ppT); dev_free(c->d_groups);
     dev_free(c->d_jeng_tiles); dev_free(c->d_jp_off); dev_free(c->d_dq_base); dev_free(c->d_pos_grp);
     dev_free(c->d_jp); dev_free(c->d_dq);
+    dev_free(c->d_bf_atom); dev_free(c->d_atom_xyz); dev_free(c->d_ks_shell); dev_free(c->d_dfit); dev_free(c->d_dfit_bins);
     for (int k = 0; k < FK_MLP_MAX_LAYERS; ++k) { dev_free(c->g_W[k]); dev_free(c->g_b[k]); }
     dev_free(c->g_X); dev_free(c->g_Y); dev_free(c->g_work); dev_free(c->g_pairs); dev_free(c->g_rot); dev_free(c->g_D);
 }
@@ -761,10 +767,11 @@ int fk_build_quartets(fk_ctx *c, const fk_screen_opts *o)
 {
     if (!c) return FK_ERR_ARG;
     if (!c->have_basis) return fail(c, FK_ERR_STATE, "fk_build_quartets: basis not set");
-    fk_screen_opts opts = {1e-10, 0.0, 1, 0, 0.0};
+    fk_screen_opts opts = {1e-10, 0.0, 1, 0, 0.0, 0.0};
     if (o) opts = *o;
     if (!(opts.tau >= 0) || !(opts.tau_prim >= 0)) return fail(c, FK_ERR_ARG, "fk_build_quartets: negative threshold");
     if (!(opts.tau_fp32 >= 0)) return fail(c, FK_ERR_ARG, "fk_build_quartets: negative tau_fp32");
+    if (!(opts.tau_k >= 0)) return fail(c, FK_ERR_ARG, "fk_build_quartets: negative tau_k");
     if (opts.bra_block < 0 || opts.bra_block > FK_MAX_BRA_BLOCK)
         return fail(c, FK_ERR_ARG, "fk_build_quartets: bra_block must be 0..%d", FK_MAX_BRA_BLOCK);
     c->opts = opts;
@@ -1088,6 +1095,8 @@ struct JKBufs {
 
 constexpr int kJengNB = FK_JENG_MAX_LP + 1;
 
+int ensure_dfit(fk_ctx *c);  // density-bound data, below
+
 // Lists and buffers of the J engine for the current quartet lists: per pair
 // the offset of its J_p block, per ket group the offset of its D_q block, and
 // the work tiles (bra pair, <= 64 kets of one group) of every bra class
@@ -1171,7 +1180,48 @@ int ensure_jeng(fk_ctx *c)
         (rc = dev_upload<double>(c, c->d_dq, nullptr, (size_t)std::max<long long>(ndq, 1))))
         return rc;
     c->jp_n = (size_t)njp;
+    if ((rc = ensure_dfit(c))) return rc;
     c->jeng_valid = true;
+    return FK_OK;
+}
+
+// Device data of the density-decay fit for one molecule: the atom of every
+// function, the atoms' positions, the bin width (the largest interatomic
+// distance over FK_DFIT_BINS - 1 bins), and per shell its centre, R (largest
+// distance to the partner shell of a pair with G >= tau) and G (largest pair
+// factor).
+int ensure_dfit(fk_ctx *c)
+{
+    if (c->nmol > 1) return fail(c, FK_ERR_UNSUPPORTED, "density bound: one molecule per context");
+    std::vector<int> bfa(c->nbf);
+    for (int s = 0; s < c->nshell; ++s)
+        for (int k = c->sh_bf[s]; k < c->sh_bf[s] + ncart(c->sh_l[s]); ++k) bfa[k] = c->sh_atom[s];
+    double rmax = 0;
+    for (int a = 0; a < c->natom; ++a)
+        for (int b = 0; b < a; ++b) {
+            double r2 = 0;
+            for (int k = 0; k < 3; ++k) r2 += (c->xyz[3 * a + k] - c->xyz[3 * b + k]) * (c->xyz[3 * a + k] - c->xyz[3 * b + k]);
+            rmax = std::max(rmax, std::sqrt(r2));
+        }
+    c->dfit_dr = std::max(rmax, 1.0) / (FK_DFIT_BINS - 1);
+    std::vector<double> ks(5 * (size_t)c->nshell, 0.0);
+    for (int s = 0; s < c->nshell; ++s)
+        for (int k = 0; k < 3; ++k) ks[5 * s + k] = c->xyz[3 * c->sh_atom[s] + k];
+    for (size_t p = 0; p < c->pr_sa.size(); ++p) {
+        const int x = c->pr_sa[p], y = c->pr_sb[p];
+        const double g = c->pr_G[p];
+        double r2 = 0;
+        for (int k = 0; k < 3; ++k) r2 += (ks[5 * x + k] - ks[5 * y + k]) * (ks[5 * x + k] - ks[5 * y + k]);
+        for (int z : {x, y}) {
+            ks[5 * z + 4] = std::max(ks[5 * z + 4], g);
+            if (g >= c->opts.tau) ks[5 * z + 3] = std::max(ks[5 * z + 3], std::sqrt(r2));
+        }
+    }
+    int rc;
+    if ((rc = dev_upload(c, c->d_bf_atom, bfa.data(), bfa.size())) || (rc = dev_upload(c, c->d_atom_xyz, c->xyz.data(), c->xyz.size())) ||
+        (rc = dev_upload(c, c->d_ks_shell, ks.data(), ks.size())) || (rc = dev_upload<double>(c, c->d_dfit, nullptr, 2)) ||
+        (rc = dev_upload<unsigned long long>(c, c->d_dfit_bins, nullptr, FK_DFIT_BINS)))
+        return rc;
     return FK_OK;
 }
 
@@ -1271,6 +1321,9 @@ int build_jk_impl(fk_ctx *c, const double *D, double *J, double *K, unsigned fla
         }
     // with the J engine the Rys kernels form K only (or nothing)
     const int want_rys = jeng ? (want & FK_WANT_K) : want;
+    if (jeng && (want_rys & FK_WANT_K) && c->opts.tau_k > 0 &&
+        fk_kernels_launch_dfit(Dd, c->nbf, c->d_bf_atom.p, c->d_atom_xyz.p, c->dfit_dr, c->d_dfit_bins.p, c->d_dfit.p, st))
+        return fail(c, FK_ERR_HIP, "density-bound kernel launch failed");
     for (size_t i = 0; i < c->qclasses.size(); ++i) {
         const QuartetClass &qc = c->qclasses[i];
         if (c->timed) HIPCHK(c, hipEventRecord(c->ev[2 * i], st));
@@ -1311,6 +1364,17 @@ int build_jk_impl(fk_ctx *c, const double *D, double *J, double *K, unsigned fla
         a.dscreen = c->opts.density_screen && c->opts.tau > 0;
         a.want = want_rys;
         a.tau = c->opts.tau * c->dscreen_scale;
+        // K beside the J engine: K blocks the fitted density bound proves
+        // below tau_k are skipped (their quartets' other blocks still count)
+        a.ks_shell = nullptr;
+        a.ks_fit = nullptr;
+        a.ks_tau = 0.0;
+        if (jeng && c->opts.tau_k > 0) {
+            a.ks_shell = c->d_ks_shell.p;
+            a.ks_fit = c->d_dfit.p;
+            a.ks_tau = c->opts.tau_k;
+            a.dscreen = 1;
+        }
         a.rys_tab = c->d_rys.p + rys_staged_offset(qc.info.nroot);
         a.counters = b.cnt + 2 * i;
         a.bra_slot = qc.bra_slot;
@@ -1350,6 +1414,30 @@ int build_jk_impl(fk_ctx *c, const double *D, double *J, double *K, unsigned fla
 }  // namespace
 
 extern "C" {
+
+int fk_density_bound(fk_ctx *c, const double *D, unsigned flags, double *H, double *Lambda)
+{
+    if (!c) return FK_ERR_ARG;
+    if (!D || !H || !Lambda) return fail(c, FK_ERR_ARG, "fk_density_bound: null pointer");
+    if (c->device < 0) return fail(c, FK_ERR_STATE, "fk_density_bound: context has no device");
+    if (!c->have_quartets) return fail(c, FK_ERR_STATE, "fk_density_bound: call fk_build_quartets first");
+    hipSetDevice(c->device);
+    int rc;
+    if ((rc = ensure_dfit(c))) return rc;
+    const size_t nn = (size_t)c->nbf * c->nbf;
+    const double *Dd = D;
+    if (!(flags & FK_DEVICE_PTRS)) {
+        if ((rc = dev_upload(c, c->d_Din, D, nn))) return rc;
+        Dd = c->d_Din.p;
+    }
+    if (fk_kernels_launch_dfit(Dd, c->nbf, c->d_bf_atom.p, c->d_atom_xyz.p, c->dfit_dr, c->d_dfit_bins.p, c->d_dfit.p, nullptr))
+        return fail(c, FK_ERR_HIP, "density-bound kernel launch failed");
+    double f[2];
+    HIPCHK(c, hipMemcpy(f, c->d_dfit.p, sizeof f, hipMemcpyDeviceToHost));
+    *H = f[0];
+    *Lambda = f[1];
+    return FK_OK;
+}
 
 int fk_build_jk(fk_ctx *c, const double *D, double *J, double *K, unsigned flags, void *stream)
 {
@@ -2208,10 +2296,10 @@ int fk_run_scf(fk_ctx *c, const fk_scf_opts *opts, fk_scf_result *result, double
     if (c->device < 0) return fail(c, FK_ERR_STATE, "fk_run_scf: context has no device");
     if (!c->have_quartets) return fail(c, FK_ERR_STATE, "fk_run_scf: call fk_build_quartets first");
     if (c->nmol > 1) return fail(c, FK_ERR_UNSUPPORTED, "fk_run_scf: one molecule per context (batches: one context each)");
-    fk_scf_opts o = {100, 1e-10, 1e-8, 8, 0, 1e-8, 0, 0, 0.0};
+    fk_scf_opts o = {100, 1e-10, 1e-8, 8, 0, 1e-8, 0, 0, 0.0, 0};
     if (opts) o = *opts;
     if (o.max_iter < 0 || o.diis_n < 0 || o.diis_n > 32 || !(o.e_tol > 0) || !(o.g_tol > 0) || !(o.lindep > 0) ||
-        !(o.canonical >= 0 && o.canonical < 1) ||
+        !(o.canonical >= 0 && o.canonical < 1) || (o.j_engine != 0 && o.j_engine != 1) ||
         o.guess < 0 || o.guess > 3 || (o.graph != 0 && o.graph != 1) || o.incremental < 0 ||
         (o.graph && o.incremental))
         return fail(c, FK_ERR_ARG, "fk_run_scf: invalid options");
@@ -2330,6 +2418,7 @@ int fk_run_scf(fk_ctx *c, const fk_scf_opts *opts, fk_scf_result *result, double
     // the Fock stage: J, K, F = h + J - K/2, D.h and D.F, F' = X F X, the
     // commutator F'D' - D'F' and its largest element, into scal[0..2]
     int since_full = 0;
+    const unsigned jflag = o.j_engine ? FK_J_ENGINE : 0u;
     auto fock_stage = [&](bool eager) -> int {
         int r;
         if (eager && o.incremental) {
@@ -2346,7 +2435,7 @@ int fk_run_scf(fk_ctx *c, const fk_scf_opts *opts, fk_scf_result *result, double
             // a density change is screened 1000 times tighter, so that the
             // running sums stay as accurate as full builds
             c->dscreen_scale = full ? 1.0 : 1e-3;
-            r = fk_build_jk(c, Dsrc, w.J.p, w.K.p, FK_DEVICE_PTRS | FK_SYNC, w.st);
+            r = fk_build_jk(c, Dsrc, w.J.p, w.K.p, FK_DEVICE_PTRS | FK_SYNC | jflag, w.st);
             c->dscreen_scale = 1.0;
             if (r) return r;
             jk_s += std::chrono::duration<double>(std::chrono::steady_clock::now() - tb).count();
@@ -2358,9 +2447,9 @@ int fk_run_scf(fk_ctx *c, const fk_scf_opts *opts, fk_scf_result *result, double
         } else {
             if (eager) {  // the build timed on its own
                 const auto tb = std::chrono::steady_clock::now();
-                if ((r = fk_build_jk(c, w.D.p, w.J.p, w.K.p, FK_DEVICE_PTRS | FK_SYNC, w.st))) return r;
+                if ((r = fk_build_jk(c, w.D.p, w.J.p, w.K.p, FK_DEVICE_PTRS | FK_SYNC | jflag, w.st))) return r;
                 jk_s += std::chrono::duration<double>(std::chrono::steady_clock::now() - tb).count();
-            } else if ((r = fk_build_jk(c, w.D.p, w.J.p, w.K.p, FK_DEVICE_PTRS, w.st))) {
+            } else if ((r = fk_build_jk(c, w.D.p, w.J.p, w.K.p, FK_DEVICE_PTRS | jflag, w.st))) {
                 return r;
             }
             SCFCHK(w, fk_scf_lincomb(w.F.p, w.h.p, w.J.p, w.K.p, n, 1.0, 1.0, -0.5, 0, w.st));
@@ -3476,10 +3565,10 @@ extern "C" int fk_run_scf_batch(fk_ctx *c, const fk_scf_opts *opts, fk_scf_resul
     if (!c->have_quartets) return fail(c, FK_ERR_STATE, "fk_run_scf_batch: call fk_build_quartets first");
     const int nmol = c->nmol;
     std::memset(results, 0, sizeof(fk_scf_result) * (size_t)nmol);
-    fk_scf_opts o = {100, 1e-10, 1e-8, 8, 0, 1e-8, 0, 0, 0.0};
+    fk_scf_opts o = {100, 1e-10, 1e-8, 8, 0, 1e-8, 0, 0, 0.0, 0};
     if (opts) o = *opts;
     if (o.max_iter < 0 || o.diis_n < 0 || o.diis_n > 32 || !(o.e_tol > 0) || !(o.g_tol > 0) || !(o.lindep > 0) ||
-        !(o.canonical >= 0 && o.canonical < 1) || o.guess < 0 || o.guess > 3)
+        !(o.canonical >= 0 && o.canonical < 1) || o.j_engine != 0 || o.guess < 0 || o.guess > 3)
         return fail(c, FK_ERR_ARG, "fk_run_scf_batch: invalid options");
     if (c->charge != 0) return fail(c, FK_ERR_UNSUPPORTED, "fk_run_scf_batch: the molecules of a batch must be neutral");
     const auto t_start = std::chrono::steady_clock::now();

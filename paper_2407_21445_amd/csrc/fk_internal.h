@@ -94,6 +94,13 @@ struct FkJKArgs {
     int engine;              // 0: Rys quadrature, 1: HGP with early contraction
     double tau_fp32;         // precision split (0: none): per bra and tile, the FP32
                              // launch takes the work when G_ab G_cd D_max < tau_fp32
+    // K-block skip (K launches beside the J engine; null: off): per shell
+    // x, y, z, R_x, G_x, and the fitted density bound |D| <= H exp(-Lambda r)
+    // in ks_fit[0..1]; block K_xy is insignificant when
+    // H exp(-Lambda max(0, |XY| - R_x - R_y)) G_x G_y <= ks_tau
+    const double *ks_shell;
+    const double *ks_fit;
+    double ks_tau;
                              // for every quartet of the wave, the FP64 launch otherwise
 };
 
@@ -203,6 +210,11 @@ struct FkJengJabArgs {
 };
 // the J engine is built for total pair momenta up to this (s, p, d shells)
 #define FK_JENG_MAX_LP 4
+// density-decay fit (paper, "K matrix implementation", eq. density_bound):
+// bins of the centre distance for the binned maxima of |D|
+#define FK_DFIT_BINS 64
+int fk_kernels_launch_dfit(const double *D, int n, const int *bf_atom, const double *atom_xyz, double dr,
+                           unsigned long long *bins, double *fit, void *stream);
 
 // dense SCF kernels (fk_scf.hip); n x n row-major FP64 device matrices
 int fk_jeng_launch_dq(int lc, int ld, const FkJengDqArgs *a, void *stream);

@@ -174,6 +174,40 @@ __device__ __forceinline__ double dmax_want(const double *__restrict Dsh, int ns
     return m;
 }
 
+// K-block skip (paper, "K matrix implementation"): with |D_cd| <= H
+// exp(-Lambda |CD|), R_x the largest distance from shell x to a partner of a
+// Schwarz-significant pair and G_x its largest pair factor, every contribution
+// to block K_xy is at most H exp(-Lambda max(0, |XY| - R_x - R_y)) G_x G_y.
+__device__ __forceinline__ bool kblock_live(const FkJKArgs &a, int x, int y)
+{
+    const double *X = a.ks_shell + 5 * x, *Y = a.ks_shell + 5 * y;
+    const double dx = X[0] - Y[0], dy = X[1] - Y[1], dz = X[2] - Y[2];
+    const double d = fmax(0.0, sqrt(dx * dx + dy * dy + dz * dz) - X[3] - Y[3]);
+    return a.ks_fit[0] * exp(-a.ks_fit[1] * d) * X[4] * Y[4] > a.ks_tau;
+}
+
+// Density factor of a K-only launch with the block skip: the density block of
+// each K target counts only while that target block is live (K_ac takes D_bd,
+// K_ad D_bc, K_bc D_ad, K_bd D_ac).  A quartet none of whose blocks is live
+// gets factor 0.
+__device__ __forceinline__ double dmax_kskip(const FkJKArgs &a, const double *__restrict Dsh, int ns, int sa, int sb,
+                                             int sc, int sd)
+{
+    double m = 0.0;
+    if (kblock_live(a, sa, sc)) m = fmax(m, Dsh[sb * ns + sd]);
+    if (kblock_live(a, sa, sd)) m = fmax(m, Dsh[sb * ns + sc]);
+    if (kblock_live(a, sb, sc)) m = fmax(m, Dsh[sa * ns + sd]);
+    if (kblock_live(a, sb, sd)) m = fmax(m, Dsh[sa * ns + sc]);
+    return m;
+}
+
+__device__ __forceinline__ double dmax_args(const FkJKArgs &a, const double *__restrict Dsh, int ns, int sa, int sb,
+                                            int sc, int sd)
+{
+    if (a.ks_shell && a.want == FK_WANT_K) return dmax_kskip(a, Dsh, ns, sa, sb, sc, sd);
+    return dmax_want(Dsh, ns, sa, sb, sc, sd, a.want);
+}
+
 // Screening of the (bra, ket) combinations of a wave and the precision split.
 // A lane's quartet survives the Schwarz bound, the same-class triangle and the
 // density screen G_ab G_cd D_max >= tau.  With the split (tau_fp32 > 0) the
@@ -187,7 +221,7 @@ __device__ __forceinline__ bool screen_lane(const FkJKArgs &a, bool cand, double
 {
     bool active = cand && (a.tau <= 0 || gg >= a.tau);
     double dm = 0.0;
-    if (a.dscreen || a.tau_fp32 > 0) dm = dmax_want(Dsh, ns, sa, sb, sc, sd, a.want);
+    if (a.dscreen || a.tau_fp32 > 0) dm = dmax_args(a, Dsh, ns, sa, sb, sc, sd);
     if (a.dscreen) active = active && gg * dm >= a.tau;
     if (a.tau_fp32 > 0) {
         const bool need64 = __ballot(active && gg * dm >= a.tau_fp32) != 0ull;
@@ -986,7 +1020,7 @@ __global__ void __launch_bounds__(FK_BLOCK) k_jk_wpq(FkJKArgs a)
             const bool in = lane < tile.ket_count;
             const KetInfo K0 = load_ket(a, tile.ket_begin + (in ? lane : 0));
             bool ok = in;
-            if (a.dscreen) ok = ok && (B.G * K0.G * dmax_want(Dsh, ns, sa, sb, K0.sc, K0.sd, a.want) >= a.tau);
+            if (a.dscreen) ok = ok && (B.G * K0.G * dmax_args(a, Dsh, ns, sa, sb, K0.sc, K0.sd) >= a.tau);
             live = __ballot(ok);
         }
         if (live == 0ull) continue;
@@ -1764,6 +1798,59 @@ __global__ void k_prep_dsh(const double *__restrict D, FkMolArgs m, double *__re
     Dsh[i] = v;
 }
 
+// Density-decay fit (paper, "K matrix implementation"): the largest |D_ij|
+// per bin of the distance between the functions' atoms, atoms differing
+// (same-atom elements are never screened and would skew the decay); bins of
+// width dr, the last one open-ended.  Non-negative doubles order like their
+// bit patterns, so the maximum is an integer atomic.
+__global__ void k_dfit_bins(const double *__restrict D, int n, const int *__restrict bf_atom,
+                            const double *__restrict xyz, double dr, unsigned long long *__restrict bins)
+{
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= (long long)n * n) return;
+    const int r = (int)(i / n), c = (int)(i % n);
+    const int A = bf_atom[r], B = bf_atom[c];
+    if (A == B) return;
+    const double dx = xyz[3 * A] - xyz[3 * B], dy = xyz[3 * A + 1] - xyz[3 * B + 1], dz = xyz[3 * A + 2] - xyz[3 * B + 2];
+    const int b = min(FK_DFIT_BINS - 1, (int)(sqrt(dx * dx + dy * dy + dz * dz) / dr));
+    const double v = fabs(D[i]);
+    if (v > 0) atomicMax(&bins[b], (unsigned long long)__double_as_longlong(v));
+}
+
+// Least-squares line ln max|D| = ln H - Lambda r through the non-empty bins
+// (r at the bin centre), then ln H raised until the line lies on or above
+// every bin's maximum at the bin's far edge (the line's lowest point over the
+// bin), so that it bounds every element.  Lambda >= 0.  One thread.
+__global__ void k_dfit_solve(const unsigned long long *__restrict bins, double dr, double *__restrict fit)
+{
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    double sx = 0, sy = 0, sxx = 0, sxy = 0;
+    int m = 0;
+    for (int b = 0; b < FK_DFIT_BINS; ++b) {
+        const double v = __longlong_as_double((long long)bins[b]);
+        if (!(v > 1e-300)) continue;
+        const double x = (b + 0.5) * dr, y = log(v);
+        sx += x; sy += y; sxx += x * x; sxy += x * y;
+        ++m;
+    }
+    double lam = 0.0, lnh = 0.0;
+    if (m >= 2) {
+        const double den = m * sxx - sx * sx;
+        lam = den > 0 ? -(m * sxy - sx * sy) / den : 0.0;
+        lam = fmax(lam, 0.0);
+    }
+    if (m >= 1) lnh = (sy + lam * sx) / m;
+    double shift = -1e300;
+    for (int b = 0; b < FK_DFIT_BINS; ++b) {
+        const double v = __longlong_as_double((long long)bins[b]);
+        if (!(v > 1e-300)) continue;
+        shift = fmax(shift, log(v) - (lnh - lam * ((b + 1) * dr)));
+    }
+    if (m >= 1) lnh += fmax(shift, 0.0);
+    fit[0] = m >= 1 ? exp(lnh) : 0.0;
+    fit[1] = lam;
+}
+
 // J = s_r s_c (X_J + X_J^T), K likewise, within each molecule's block
 __global__ void k_finalize(const double *__restrict XJ, const double *__restrict XK, long long xcopy, int ncopy,
                            const double *__restrict s, FkMolArgs m, double *__restrict J, double *__restrict K)
@@ -1889,6 +1976,19 @@ int fk_kernels_launch_finalize(const double *XJ, const double *XK, long long xco
     if (m->nmat > 0)
         hipLaunchKernelGGL(k_finalize, dim3((unsigned)((m->nmat + 255) / 256)), dim3(256), 0, (hipStream_t)stream, XJ,
                            XK, xcopy, ncopy, bf_scale, *m, J, K);
+    return hipGetLastError() == hipSuccess ? 0 : -3;
+}
+
+int fk_kernels_launch_dfit(const double *D, int n, const int *bf_atom, const double *atom_xyz, double dr,
+                           unsigned long long *bins, double *fit, void *stream)
+{
+    hipStream_t st = (hipStream_t)stream;
+    hipLaunchKernelGGL(k_fill, dim3(1), dim3(FK_DFIT_BINS), 0, st, (double *)bins, (long long)FK_DFIT_BINS);
+    const long long nn = (long long)n * n;
+    if (nn > 0)
+        hipLaunchKernelGGL(k_dfit_bins, dim3((unsigned)((nn + 255) / 256)), dim3(256), 0, st, D, n, bf_atom, atom_xyz,
+                           dr, bins);
+    hipLaunchKernelGGL(k_dfit_solve, dim3(1), dim3(64), 0, st, bins, dr, fit);
     return hipGetLastError() == hipSuccess ? 0 : -3;
 }
 

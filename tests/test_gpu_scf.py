@@ -250,3 +250,41 @@ def test_batched_scf_canonical(fk):
         r = fk.FockJK(0).set_system(s).build_quartets(tau=0.0).run_scf(canonical=1e-6)
         assert rs[m]["converged"] and r["converged"]
         assert abs(rs[m]["energy"] - r["energy"]) <= 1e-8, (m, rs[m]["energy"], r["energy"])
+
+
+def test_scf_split_j_engine(fk):
+    """SCF with the split build (J by the J engine, K by the Rys kernels):
+    the energy equals the fused build's SCF within 1e-8 Eh, and within 1e-5 Eh
+    with the paper's K-block skip at tau_k = 5e-6 (its finding for that
+    threshold)."""
+    s = wl.alkane_sys(2, "6-31gs-type")
+    r0 = fk.FockJK(0).set_system(s).build_quartets(tau=1e-10).run_scf()
+    r1 = fk.FockJK(0).set_system(s).build_quartets(tau=1e-10).run_scf(j_engine=True)
+    assert r0["converged"] and r1["converged"]
+    assert abs(r1["energy"] - r0["energy"]) <= 1e-8, (r1["energy"], r0["energy"])
+    r2 = fk.FockJK(0).set_system(s).build_quartets(tau=1e-10, tau_k=5e-6).run_scf(j_engine=True)
+    assert r2["converged"]
+    assert abs(r2["energy"] - r0["energy"]) <= 1e-5, (r2["energy"], r0["energy"])
+
+
+def test_density_bound(fk):
+    """fk_density_bound: on a density that is exactly 0.7 exp(-0.9 r) between
+    functions of different atoms the fit bounds every element, recovers Lambda
+    within 1 % and overestimates no element by more than 25 % (the line is
+    raised to each bin's far edge, about 0.1 bohr wide here); on
+    the core-Hamiltonian density of C2H6 the bound holds for every element of
+    two different atoms."""
+    s = wl.alkane_sys(2, "6-31gs-type")
+    c = fk.FockJK(0).set_system(s).build_quartets(tau=1e-10)
+    n = s["nbf"]
+    atom = np.repeat(s["sh_atom"], [(l + 1) * (l + 2) // 2 for l in s["sh_l"]])
+    xyz = np.asarray(s["xyz"]).reshape(-1, 3)
+    r = np.linalg.norm(xyz[atom][:, None, :] - xyz[atom][None, :, :], axis=2)
+    D = 0.7 * np.exp(-0.9 * r)
+    H, L = c.density_bound(D)
+    other = atom[:, None] != atom[None, :]
+    ratio = H * np.exp(-L * r[other]) / D[other]
+    assert abs(L - 0.9) <= 0.009 and np.all(ratio >= 1 - 1e-12) and np.max(ratio) <= 1.25, (H, L, np.max(ratio))
+    Dc = c.run_scf(max_iter=0)["D"]
+    H, L = c.density_bound(Dc)
+    assert L >= 0 and np.all(np.abs(Dc[other]) <= H * np.exp(-L * r[other]) * (1 + 1e-12) + 1e-300)

@@ -511,3 +511,13 @@ def test_class_kernel_choice():
     assert got[(1, 1, 1, 1)] == 3 and got[(3, 0, 2, 0)] == 10 and got[(3, 2, 0, 0)] == 10
     assert got[(2, 1, 1, 0)] == 1
     c.close()
+
+
+def test_screen_option_validation():
+    s = wl.water4_sto3g()
+    c = fk.FockJK(device=-1).set_system(s)
+    for kw in ({"tau": -1.0}, {"tau_fp32": -1e-5}, {"tau_k": -5e-6}):
+        with pytest.raises(fk.FockJKError) as e:
+            c.build_quartets(**kw)
+        assert e.value.code == fk.FK_ERR_ARG
+    c.build_quartets(tau=1e-10, tau_k=5e-6)
