@@ -347,12 +347,20 @@ typedef struct {
                             S^(-1/2) exceeds 3e3 (overlap eigenvalues near
                             1e-7: the basis is nearly linearly dependent and
                             no direction is dropped).  Default 1e-8 */
-    int    graph;        /* 1: from the second iteration on, the Fock stage of an
-                            iteration (J/K build, F, the energy terms, X F X,
-                            the commutator and its norm) is one HIP graph,
-                            captured once and replayed, on a stream of the
-                            run's own; DIIS and purification stay eager.
-                            jk_seconds then times the whole stage.  Default 0 */
+    int    graph;        /* fk_run_scf: 1: from the second iteration on, the
+                            Fock stage of an iteration (J/K build, F, the
+                            energy terms, X F X, the commutator and its norm)
+                            is one HIP graph, captured once and replayed, on a
+                            stream of the run's own; DIIS and purification
+                            stay eager.  fk_run_scf_batch: 1: the whole
+                            iteration is one HIP graph -- the build, the Fock
+                            stage, the convergence flags, the DIIS ring and
+                            Pulay solve, the purification's choices (at most
+                            128 steps) and the kept densities of converged
+                            molecules are all decided by kernels; the host
+                            reads the energies and flags after each replay.
+                            jk_seconds then times the whole stage or
+                            iteration.  Default 0 */
     int    incremental;  /* k > 0: J and K from the density change since the
                             previous build, added to running sums, with a full
                             build every k iterations; the change is screened

@@ -394,7 +394,7 @@ class FockJK:
                 "configurations": r.configurations}
 
     def run_scf_batch(self, D0=None, max_iter=100, e_tol=1e-10, g_tol=1e-8, diis_n=8, lindep=1e-8, guess=None,
-                      canonical=0.0):
+                      canonical=0.0, graph=False):
         """SCF of every molecule of a batch at once; returns (list of per-molecule
         result dicts, flat density array in the batch layout)."""
         nmol = self.info()["nmol"]
@@ -402,8 +402,8 @@ class FockJK:
         D = np.zeros(nmat) if D0 is None else np.ascontiguousarray(D0, dtype=np.float64).reshape(-1).copy()
         if guess is None:
             guess = GUESS_CORE if D0 is None else GUESS_GIVEN
-        o = ScfOpts(int(max_iter), float(e_tol), float(g_tol), int(diis_n), int(guess), float(lindep), 0, 0,
-                    float(canonical))
+        o = ScfOpts(int(max_iter), float(e_tol), float(g_tol), int(diis_n), int(guess), float(lindep), int(bool(graph)),
+                    0, float(canonical))
         rs = (ScfResult * nmol)()
         rc = _lib.fk_run_scf_batch(self._ctx, ctypes.byref(o), rs, _ptr(D))
         if rc not in (FK_OK, FK_ERR_NOT_CONVERGED):

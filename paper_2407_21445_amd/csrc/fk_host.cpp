@@ -3555,6 +3555,191 @@ int scfb_purify(ScfBatch &w, const std::vector<int> &nocc)
     return w.lincomb_u(w.Do.p, w.T1.p, nullptr, nullptr, 2.0, 0, 0, 0);
 }
 
+// The batched SCF with every per-iteration decision on the device (the
+// convergence flags, the DIIS ring slot and Pulay solve, the purification's
+// choices with a fixed budget of steps, the density of converged molecules
+// kept), so that one iteration -- J/K build included -- is captured once as
+// a HIP graph and replayed; the host reads the energies, errors and flags
+// after each replay to stop.  Results equal the eager loop's up to rounding.
+constexpr int kScfbGraphPurSteps = 128;
+
+int scfb_graph_loop(ScfBatch &w, const fk_scf_opts &o, const std::vector<int> &nocc, const std::vector<double> &enuc,
+                    fk_scf_result *results, double *D_inout, std::chrono::steady_clock::time_point t_start)
+{
+    fk_ctx *c = w.c;
+    const int nmol = w.nmol, nmax = w.nmax;
+    const size_t nmat = w.nm;
+    const int dn = std::max(o.diis_n, 1);
+    if (dn > FK_SCFB_MAX_DIIS) return fail(c, FK_ERR_ARG, "batched SCF graph: at most %d DIIS vectors", FK_SCFB_MAX_DIIS);
+    int rc;
+    struct Res {
+        hipStream_t st = nullptr;
+        hipGraph_t g = nullptr;
+        hipGraphExec_t x = nullptr;
+        ~Res()
+        {
+            if (x) (void)hipGraphExecDestroy(x);
+            if (g) (void)hipGraphDestroy(g);
+            if (st) (void)hipStreamDestroy(st);
+        }
+    } gr;
+    HIPCHK(c, hipStreamCreate(&gr.st));
+    hipStream_t st = gr.st;
+    DevBuf<int> ictl, conv, pstate, pdone, dnocc;
+    DevBuf<double> eprev, dh, df, errv, gb, t1, t2, denuc, status, cF, cShift, cP, cDo, cKeep, Bm, dcoef, dpart, ringF, ringE;
+    struct Free {
+        std::vector<DevBuf<int> *> i;
+        std::vector<DevBuf<double> *> d;
+        ~Free() { for (auto *b : i) dev_free(*b); for (auto *b : d) dev_free(*b); }
+    } fr{{&ictl, &conv, &pstate, &pdone, &dnocc},
+         {&eprev, &dh, &df, &errv, &gb, &t1, &t2, &denuc, &status, &cF, &cShift, &cP, &cDo, &cKeep, &Bm, &dcoef, &dpart, &ringF, &ringE}};
+    std::vector<double> k4(4 * (size_t)nmol, 0.0), kS(4 * (size_t)nmol, 0.0), kD(4 * (size_t)nmol, 0.0);
+    for (int m = 0; m < nmol; ++m) {
+        k4[4 * m] = 1.0; k4[4 * m + 1] = 1.0; k4[4 * m + 2] = -0.5;
+        kS[4 * m] = 1.0; kS[4 * m + 1] = (!w.ndrop.empty() && w.ndrop[m] > 0) ? kNullShift : 0.0;
+        kD[4 * m] = 2.0;
+    }
+    const bool shifted = !w.ndrop.empty() && std::find_if(w.ndrop.begin(), w.ndrop.end(), [](int x) { return x > 0; }) != w.ndrop.end();
+    const std::vector<int> zi(std::max(nmol, 4), 0);
+    const std::vector<double> zd(std::max<size_t>((size_t)nmol * dn * dn, 3 * (size_t)nmol), 0.0);
+    if ((rc = dev_upload(c, ictl, zi.data(), 4)) || (rc = dev_upload(c, conv, zi.data(), nmol)) ||
+        (rc = dev_upload<int>(c, pstate, nullptr, nmol)) || (rc = dev_upload<int>(c, pdone, nullptr, nmol)) ||
+        (rc = dev_upload(c, dnocc, nocc.data(), nmol)) || (rc = dev_upload(c, eprev, zd.data(), nmol)) ||
+        (rc = dev_upload<double>(c, dh, nullptr, nmol)) || (rc = dev_upload<double>(c, df, nullptr, nmol)) ||
+        (rc = dev_upload<double>(c, errv, nullptr, nmol)) || (rc = dev_upload<double>(c, gb, nullptr, 2 * (size_t)nmol)) ||
+        (rc = dev_upload<double>(c, t1, nullptr, nmol)) || (rc = dev_upload<double>(c, t2, nullptr, nmol)) ||
+        (rc = dev_upload(c, denuc, enuc.data(), nmol)) || (rc = dev_upload(c, status, zd.data(), 3 * (size_t)nmol)) ||
+        (rc = dev_upload(c, cF, k4.data(), k4.size())) || (rc = dev_upload(c, cShift, kS.data(), kS.size())) ||
+        (rc = dev_upload<double>(c, cP, nullptr, 4 * (size_t)nmol)) || (rc = dev_upload(c, cDo, kD.data(), kD.size())) ||
+        (rc = dev_upload<double>(c, cKeep, nullptr, 4 * (size_t)nmol)) || (rc = dev_upload(c, Bm, zd.data(), (size_t)nmol * dn * dn)) ||
+        (rc = dev_upload<double>(c, dcoef, nullptr, (size_t)nmol * dn)) ||
+        (rc = dev_upload<double>(c, dpart, nullptr, (size_t)nmol * dn * 32)) ||
+        (rc = dev_upload<double>(c, ringF, nullptr, (size_t)dn * nmat)) || (rc = dev_upload<double>(c, ringE, nullptr, (size_t)dn * nmat)))
+        return rc;
+    // empty ring slots read as zeros (their inner products are never used)
+    if (fk_kernels_launch_fill(ringF.p, (long long)(dn * nmat), st) || fk_kernels_launch_fill(ringE.p, (long long)(dn * nmat), st))
+        return fail(c, FK_ERR_HIP, "batched SCF graph: fill launch failed");
+    HIPCHK(c, hipStreamSynchronize(st));
+    const int *nbf = w.nbf();
+    const long long *off = w.off();
+    auto L = [&](double *o_, const double *x, const double *y, const double *z, const double *cf) {
+        return fk_scfb_lincomb(o_, x, y, z, nmol, nmax, nbf, off, cf, st);
+    };
+    auto G = [&](const double *A, const double *B, double *C_) { return fk_scfb_gemm(A, B, C_, nmol, nmax, nbf, off, 1.0, 0.0, st); };
+    auto R = [&](const double *x, const double *y, int op, double *out) {
+        return fk_scfb_reduce(x, y, nmol, nbf, off, op, w.part.p, out, st);
+    };
+    // one iteration, every step a kernel or a device copy
+    auto enqueue = [&]() -> int {
+        int r = 0;
+        r |= fk_scfb_iter_begin(ictl.p, dn, st);
+        if (r) return fail(c, FK_ERR_HIP, "batched SCF graph: launch failed");
+        if ((r = fk_build_jk(c, w.D.p, w.J.p, w.K.p, FK_DEVICE_PTRS, st))) return r;
+        r |= L(w.F.p, w.h.p, w.J.p, w.K.p, cF.p);
+        r |= R(w.D.p, w.h.p, 0, dh.p);
+        r |= R(w.D.p, w.F.p, 0, df.p);
+        r |= G(w.X.p, w.F.p, w.T3.p);
+        r |= G(w.T3.p, w.X.p, w.Fo.p);
+        if (shifted) r |= L(w.Fo.p, w.Fo.p, w.Pn.p, nullptr, cShift.p);
+        r |= G(w.Fo.p, w.Do.p, w.G.p);
+        r |= fk_scfb_antisym(w.E.p, w.G.p, nmol, nmax, nbf, off, st);
+        r |= R(w.E.p, nullptr, 1, errv.p);
+        r |= fk_scfb_conv(dh.p, df.p, errv.p, denuc.p, nmol, o.e_tol, o.g_tol, ictl.p, conv.p, eprev.p, cKeep.p, status.p, st);
+        if (o.diis_n > 1)
+            r |= fk_scfb_diis(ringF.p, ringE.p, w.Fo.p, w.E.p, w.Fo.p, nmol, nmax, nbf, off, (long long)nmat, dn, ictl.p,
+                              dpart.p, Bm.p, dcoef.p, st);
+        if (r) return fail(c, FK_ERR_HIP, "batched SCF graph: launch failed");
+        // the converged molecules' densities, kept below
+        HIPCHK(c, hipMemcpyAsync(w.G.p, w.Do.p, nmat * sizeof(double), hipMemcpyDeviceToDevice, st));
+        HIPCHK(c, hipMemcpyAsync(w.E.p, w.D.p, nmat * sizeof(double), hipMemcpyDeviceToDevice, st));
+        r |= R(w.Fo.p, nullptr, 3, gb.p);
+        r |= fk_scfb_pur_start(gb.p, nmol, cP.p, pstate.p, pdone.p, ictl.p, st);
+        r |= L(w.T1.p, w.Fo.p, nullptr, nullptr, cP.p);
+        for (int k = 0; k < kScfbGraphPurSteps; ++k) {
+            r |= fk_scfb_gemm_skip(w.T1.p, w.T1.p, w.T2.p, nmol, nmax, nbf, off, pdone.p, st);
+            r |= R(w.T1.p, nullptr, 2, t1.p);
+            r |= R(w.T2.p, nullptr, 2, t2.p);
+            r |= fk_scfb_pur_step(t1.p, t2.p, dnocc.p, nmol, cP.p, pstate.p, pdone.p, st);
+            r |= L(w.T1.p, w.T1.p, w.T2.p, nullptr, cP.p);
+        }
+        r |= fk_scfb_pur_check(pstate.p, nmol, ictl.p, st);
+        r |= L(w.Do.p, w.T1.p, nullptr, nullptr, cDo.p);
+        r |= G(w.X.p, w.Do.p, w.T3.p);
+        r |= G(w.T3.p, w.X.p, w.D.p);
+        r |= L(w.Do.p, w.Do.p, w.G.p, nullptr, cKeep.p);
+        r |= L(w.D.p, w.D.p, w.E.p, nullptr, cKeep.p);
+        return r ? fail(c, FK_ERR_HIP, "batched SCF graph: launch failed") : FK_OK;
+    };
+    HIPCHK(c, hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+    rc = enqueue();
+    hipGraph_t g = nullptr;
+    const hipError_t e = hipStreamEndCapture(st, &g);
+    gr.g = g;
+    if (rc) return rc;
+    if (e != hipSuccess) return fail(c, FK_ERR_HIP, "batched SCF graph: capture failed: %s", hipGetErrorString(e));
+    HIPCHK(c, hipGraphInstantiate(&gr.x, gr.g, nullptr, nullptr, 0));
+    std::vector<double> stat(3 * (size_t)nmol);
+    std::vector<int> ic(4);
+    std::vector<char> done(nmol, 0);
+    std::vector<double> e_prev(nmol, 0.0), de_cur(nmol, 0.0), e_fin(nmol, 0.0), err_fin(nmol, 0.0), de_fin(nmol, 0.0);
+    std::vector<int> it_fin(nmol, 0);
+    const char *lg = std::getenv("FK_SCF_LOG");
+    const bool log = lg && *lg && *lg != '0';
+    double jk_s = 0;
+    int it = 0;
+    bool all_conv = false;
+    for (; it < o.max_iter; ++it) {
+        const auto t0 = std::chrono::steady_clock::now();
+        HIPCHK(c, hipGraphLaunch(gr.x, st));
+        HIPCHK(c, hipMemcpyAsync(stat.data(), status.p, stat.size() * sizeof(double), hipMemcpyDeviceToHost, st));
+        HIPCHK(c, hipMemcpyAsync(ic.data(), ictl.p, 4 * sizeof(int), hipMemcpyDeviceToHost, st));
+        HIPCHK(c, hipStreamSynchronize(st));
+        jk_s += std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+        all_conv = true;
+        for (int m = 0; m < nmol; ++m) {
+            const double em = stat[m], er = stat[nmol + m];
+            const bool cm = stat[2 * nmol + m] != 0.0;
+            if (!done[m] && (!std::isfinite(em) || !std::isfinite(er)))
+                return fail(c, FK_ERR_NOT_CONVERGED, "fk_run_scf_batch: molecule %d: non-finite energy or error at iteration %d", m, it + 1);
+            if (cm && !done[m]) {
+                done[m] = 1;
+                e_fin[m] = em;
+                err_fin[m] = er;
+                de_fin[m] = em - e_prev[m];
+                it_fin[m] = it + 1;
+            }
+            de_cur[m] = em - e_prev[m];
+            e_prev[m] = em;
+            all_conv = all_conv && done[m];
+        }
+        if (log)
+            std::fprintf(stderr, "fk_run_scf_batch (graph): iteration %d: %d of %d converged, %.1f s\n", it + 1,
+                         (int)std::count(done.begin(), done.end(), 1), nmol,
+                         std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start).count());
+        if (all_conv) {
+            ++it;
+            break;
+        }
+        if (ic[3] == 1) return fail(c, FK_ERR_ARG, "batched SCF: degenerate Fock spectrum bounds");
+        if (ic[3] == 2) return fail(c, FK_ERR_NOT_CONVERGED, "batched SCF: purification did not converge in %d steps", kScfbGraphPurSteps);
+    }
+    HIPCHK(c, hipMemcpy(D_inout, w.D.p, nmat * sizeof(double), hipMemcpyDeviceToHost));
+    const double tot = std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start).count();
+    for (int m = 0; m < nmol; ++m) {
+        fk_scf_result &r = results[m];
+        r.energy = done[m] ? e_fin[m] : stat[m];
+        r.iterations = done[m] ? it_fin[m] : it;
+        r.converged = done[m] ? 1 : 0;
+        r.error = done[m] ? err_fin[m] : stat[nmol + m];
+        r.delta_e = done[m] ? de_fin[m] : de_cur[m];
+        r.jk_seconds = jk_s;
+        r.total_seconds = tot;
+        r.ndropped = w.ndrop.empty() ? 0 : w.ndrop[m];
+    }
+    if (!all_conv) return fail(c, FK_ERR_NOT_CONVERGED, "fk_run_scf_batch: not every molecule converged in %d iterations", o.max_iter);
+    return FK_OK;
+}
+
 }  // namespace
 
 extern "C" int fk_run_scf_batch(fk_ctx *c, const fk_scf_opts *opts, fk_scf_result *results, double *D_inout)
@@ -3568,7 +3753,8 @@ extern "C" int fk_run_scf_batch(fk_ctx *c, const fk_scf_opts *opts, fk_scf_resul
     fk_scf_opts o = {100, 1e-10, 1e-8, 8, 0, 1e-8, 0, 0, 0.0, 0};
     if (opts) o = *opts;
     if (o.max_iter < 0 || o.diis_n < 0 || o.diis_n > 32 || !(o.e_tol > 0) || !(o.g_tol > 0) || !(o.lindep > 0) ||
-        !(o.canonical >= 0 && o.canonical < 1) || o.j_engine != 0 || o.guess < 0 || o.guess > 3)
+        !(o.canonical >= 0 && o.canonical < 1) || o.j_engine != 0 || o.guess < 0 || o.guess > 3 ||
+        (o.graph != 0 && o.graph != 1) || o.incremental != 0)
         return fail(c, FK_ERR_ARG, "fk_run_scf_batch: invalid options");
     if (c->charge != 0) return fail(c, FK_ERR_UNSUPPORTED, "fk_run_scf_batch: the molecules of a batch must be neutral");
     const auto t_start = std::chrono::steady_clock::now();
@@ -3669,6 +3855,8 @@ extern "C" int fk_run_scf_batch(fk_ctx *c, const fk_scf_opts *opts, fk_scf_resul
         for (int m = 0; m < nmol; ++m) results[m].total_seconds = tot;
         return FK_OK;
     }
+
+    if (o.graph) return scfb_graph_loop(w, o, nocc, enuc, results, D_inout, t_start);
 
     std::vector<double> e_prev(nmol, 0.0), e_cur(nmol, 0.0), err(nmol, 0.0), dh, df, ev;
     std::vector<std::vector<double>> Bm(nmol, std::vector<double>((size_t)dn * dn, 0.0));

@@ -288,3 +288,30 @@ def test_density_bound(fk):
     Dc = c.run_scf(max_iter=0)["D"]
     H, L = c.density_bound(Dc)
     assert L >= 0 and np.all(np.abs(Dc[other]) <= H * np.exp(-L * r[other]) * (1 + 1e-12) + 1e-300)
+
+
+@pytest.mark.parametrize("guess", ["core", "sad"])
+def test_batched_scf_graph(fk, guess):
+    """The batched SCF with every per-iteration decision on the device and the
+    whole iteration replayed from one HIP graph (fk_scf_opts.graph): every
+    molecule converges to its eager batched energy within 1e-8 Eh; with the
+    canonical orthogonaliser on a batch with a near-duplicate shell too."""
+    mols = _neutral_batch()
+    b = wl.batch(mols)
+    c = fk.FockJK(0).set_system(b).set_molecules(b["atom_mol"]).build_quartets(tau=0.0)
+    g = fk.GUESS_CORE if guess == "core" else fk.GUESS_SAD
+    re_, De = c.run_scf_batch(guess=g)
+    rg, Dg = c.run_scf_batch(guess=g, graph=True)
+    for m in range(len(mols)):
+        assert re_[m]["converged"] and rg[m]["converged"]
+        assert abs(rg[m]["energy"] - re_[m]["energy"]) <= 1e-8, (m, rg[m]["energy"], re_[m]["energy"])
+    assert np.max(np.abs(Dg - De)) <= 1e-5
+    if guess == "core":
+        mols2 = [_near_dependent_water4(3e-4), wl.water4_sto3g(), wl.h2_sto3g()]
+        b2 = wl.batch(mols2)
+        c2 = fk.FockJK(0).set_system(b2).set_molecules(b2["atom_mol"]).build_quartets(tau=0.0)
+        r1, _ = c2.run_scf_batch(canonical=1e-6)
+        r2, _ = c2.run_scf_batch(canonical=1e-6, graph=True)
+        for a, x in zip(r1, r2):
+            assert a["converged"] and x["converged"] and abs(a["energy"] - x["energy"]) <= 1e-8
+            assert a["ndropped"] == x["ndropped"]
