@@ -315,3 +315,22 @@ def test_batched_scf_graph(fk, guess):
         for a, x in zip(r1, r2):
             assert a["converged"] and x["converged"] and abs(a["energy"] - x["energy"]) <= 1e-8
             assert a["ndropped"] == x["ndropped"]
+
+
+def test_scf_c20h42_matches_oracle_golden(fk):
+    """C20H42 / 6-31G*-type (384 functions): the GPU SCF from the
+    core-Hamiltonian guess, unscreened like the oracle, converges to the
+    oracle's stored SCF energy (tests/golden/c20h42_631gs_scf.json, written by
+    make_c20h42_scf.py from the oracle's literal J/K) within 1e-8 Eh; with the
+    benchmark's screening (tau = 1e-10, tau_prim = 1e-12) within 1e-7 Eh."""
+    with open(os.path.join(HERE, "golden", "c20h42_631gs_scf.json")) as f:
+        gold = json.load(f)
+    s = wl.c20h42_631gs()
+    assert gold["converged"] and gold["nbf"] == s["nbf"] == 384
+    r, _ = _gpu_scf(fk, s, tau=0.0)
+    assert r["converged"]
+    assert abs(r["energy"] - gold["E_total"]) <= 1e-8, (r["energy"], gold["E_total"])
+    c = fk.FockJK(0).set_system(s).build_quartets(tau=1e-10, tau_prim=1e-12)
+    r2 = c.run_scf()
+    assert r2["converged"]
+    assert abs(r2["energy"] - gold["E_total"]) <= 1e-7, (r2["energy"], gold["E_total"])
