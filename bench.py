@@ -197,7 +197,8 @@ def bench_batch(args, torch, fk):
         nsub = min(2, args.nmol)
         sb = wl.batch(b["mols"][:nsub])
         sub = fk.FockJK(0).set_system(sb).set_molecules(sb["atom_mol"])
-        sub.build_quartets(tau=args.tau, tau_prim=args.tau_prim, tau_fp32=args.tau_fp32)
+        sub.build_quartets(tau=args.tau, tau_prim=args.tau_prim, tau_fp32=args.tau_fp32,
+                            block_tasks=args.block_tasks)
         Dsub = start_density(sub)
         rep = sub.autotune(Dsub, reps=1)
         for r in rep["classes"]:
@@ -210,7 +211,7 @@ def bench_batch(args, torch, fk):
                 "changed_classes": sum(r["changed"] for r in rep["classes"])}
         del sub
         _progress(f"schedules tuned in {tune['seconds']:.0f} s")
-    ctx.build_quartets(tau=args.tau, tau_prim=args.tau_prim, tau_fp32=args.tau_fp32)
+    ctx.build_quartets(tau=args.tau, tau_prim=args.tau_prim, tau_fp32=args.tau_fp32, block_tasks=args.block_tasks)
     info = ctx.info()
     _progress(f"lists built: {info['ntile']} tiles, {info['nquartet_schwarz']} Schwarz quartets")
     dev = torch.device("cuda:0")
@@ -424,7 +425,8 @@ def bench_single(args, torch, fk):
         if args.engine == "hgp":
             _hgp_everywhere(fk, c)
         src = _load_cached(c, key, arch, args)
-        return c.build_quartets(tau=args.tau, tau_prim=args.tau_prim, tau_fp32=tau_fp32, tau_k=tau_k), src
+        return c.build_quartets(tau=args.tau, tau_prim=args.tau_prim, tau_fp32=tau_fp32, tau_k=tau_k,
+                                block_tasks=args.block_tasks), src
 
     ctx, src64 = make(0.0, f"{args.workload}_fp64")
     info = ctx.info()
@@ -566,7 +568,7 @@ def bench_single(args, torch, fk):
         s2y = wl.c20h42_631gs()
         c2 = fk.FockJK(0).set_system(s2y)
         src2 = _load_cached(c2, "c20h42_fp64", arch, args)
-        c2.build_quartets(tau=args.tau, tau_prim=args.tau_prim)
+        c2.build_quartets(tau=args.tau, tau_prim=args.tau_prim, block_tasks=args.block_tasks)
         S2, T2, V2, _ = c2.one_electron()
         D2 = torch.tensor(_core_density(S2, T2 + V2, s2y["nelec"] // 2), dtype=torch.float64, device=dev)
         J2, K2 = torch.empty_like(D2), torch.empty_like(D2)
@@ -608,6 +610,8 @@ def main():
     ap.add_argument("--no-split", dest="split", action="store_false",
                     help="skip the split build (J engine + K at --tau-k) timed beside the fused one")
     ap.add_argument("--tau-k", type=float, default=5e-6, help="K threshold of the split build")
+    ap.add_argument("--no-block-tasks", dest="block_tasks", action="store_false",
+                    help="ket-outer classes take tiles per wave instead of whole bra blocks per workgroup")
     ap.add_argument("--no-scf", action="store_true", help="skip the SCF runs reported beside the build rate")
     ap.add_argument("--no-extra", action="store_true", help="skip the C20H42 reference line")
     ap.add_argument("--no-autotune", dest="autotune", action="store_false",

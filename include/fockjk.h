@@ -106,6 +106,13 @@ typedef struct {
                           K_xy whose fitted density bound stays below tau_k are
                           skipped, see fk_density_bound; the paper uses 5e-6).
                           0 = no block skip */
+    int    block_tasks; /* ket-outer lane classes ((ss|ss), (ps|ss)): 0 = a
+                          workgroup takes all ket tiles of one bra block
+                          (a, b_1..b_m) at a time and sums X_K[b_j, x], X_K[a, x]
+                          and X_J[a, b_j] in LDS, which reaches memory once per
+                          block instead of once per tile and bra (used where the
+                          rows fit 64 KB of LDS with the class's other LDS);
+                          -1 = every wave takes tiles on its own */
 } fk_screen_opts;
 
 typedef struct {
@@ -149,6 +156,8 @@ typedef struct {
     int     bra_block[FK_MAX_QCLASS];     /* the schedule in effect (fk_set_class_schedule) */
     int     kets_per_tile[FK_MAX_QCLASS];
     double  grid_fraction[FK_MAX_QCLASS];
+    int64_t block_tasks[FK_MAX_QCLASS];   /* workgroup tasks of the class (fk_screen_opts
+                                             .block_tasks), 0 if its waves take tiles */
 } fk_stats_t;
 
 /* ---- context ---------------------------------------------------------- */

@@ -38,7 +38,7 @@ MAX_L, MAX_K = 3, 9
 class ScreenOpts(ctypes.Structure):
     _fields_ = [("tau", ctypes.c_double), ("tau_prim", ctypes.c_double),
                 ("density_screen", ctypes.c_int), ("bra_block", ctypes.c_int), ("tau_fp32", ctypes.c_double),
-                ("tau_k", ctypes.c_double)]
+                ("tau_k", ctypes.c_double), ("block_tasks", ctypes.c_int)]
 
 
 class Info(ctypes.Structure):
@@ -60,7 +60,7 @@ class Stats(ctypes.Structure):
                 ("class_ms", ctypes.c_double * _Q), ("tiles", ctypes.c_int64 * _Q),
                 ("team_size", ctypes.c_int * _Q), ("precision", ctypes.c_int * _Q), ("prim_slots", ctypes.c_int64 * _Q),
                 ("engine", ctypes.c_int * _Q), ("bra_block", ctypes.c_int * _Q), ("kets_per_tile", ctypes.c_int * _Q),
-                ("grid_fraction", ctypes.c_double * _Q)]
+                ("grid_fraction", ctypes.c_double * _Q), ("block_tasks", ctypes.c_int64 * _Q)]
 
 
 class TuneReport(ctypes.Structure):
@@ -230,9 +230,10 @@ class FockJK:
         self._check(_lib.fk_molecule_layout(self._ctx, _ptr(nbf), _ptr(off)))
         return nbf, off
 
-    def build_quartets(self, tau=1e-10, tau_prim=0.0, density_screen=True, bra_block=0, tau_fp32=0.0, tau_k=0.0):
+    def build_quartets(self, tau=1e-10, tau_prim=0.0, density_screen=True, bra_block=0, tau_fp32=0.0, tau_k=0.0,
+                       block_tasks=True):
         o = ScreenOpts(float(tau), float(tau_prim), 1 if density_screen else 0, int(bra_block), float(tau_fp32),
-                       float(tau_k))
+                       float(tau_k), 0 if block_tasks else -1)
         self._check(_lib.fk_build_quartets(self._ctx, ctypes.byref(o)))
         return self
 
@@ -325,7 +326,8 @@ class FockJK:
                         "flops_per_quartet": s.flops_per_quartet[i], "ms": s.class_ms[i],
                         "tiles": s.tiles[i], "team_size": s.team_size[i], "precision": s.precision[i],
                         "prim_slots": s.prim_slots[i], "engine": s.engine[i],
-                        "schedule": [s.bra_block[i], s.kets_per_tile[i], s.grid_fraction[i]]})
+                        "schedule": [s.bra_block[i], s.kets_per_tile[i], s.grid_fraction[i]],
+                        "block_tasks": s.block_tasks[i]})
         return {"classes": out, "flops_total": s.flops_total,
                 "quartets": sum(c["quartets"] for c in out), "prim_quartets": sum(c["prim_quartets"] for c in out)}
 

@@ -30,6 +30,9 @@ namespace {
 constexpr int NPC = 10;  // pair classes (la >= lb, la <= 3)
 
 constexpr int ncart(int l) { return (l + 1) * (l + 2) / 2; }
+// block tasks run where the launch needs at most this much dynamic LDS (two
+// workgroups per CU)
+constexpr int kKrowLdsMax = 65536;
 inline int pair_class(int la, int lb) { return la * (la + 1) / 2 + lb; }
 // Hermite functions of total order up to L
 inline int nherm_host(int L) { return (L + 1) * (L + 2) * (L + 3) / 6; }
@@ -59,6 +62,8 @@ struct QuartetClass {
     int bra_slot;             // doubles per wave of staged bra primitive records
     int prec;                 // 0: FP64 launch, 1: FP32 launch of the precision split
     int engine = 0;           // 0: Rys quadrature, 1: HGP (classes with info.hgp only)
+    int64_t task_off = 0, ntask = 0;  // block tasks (ket-outer classes; 0: none)
+    int krow_ncol = 0;        // LDS row length of the block tasks
     double flops_prim() const { return engine ? info.flops_prim_hgp : info.flops_prim; }
     double flops_quartet() const { return engine ? info.flops_quartet_hgp : info.flops_quartet; }
 };
@@ -101,6 +106,11 @@ struct fk_ctx {
     std::vector<FkGroup> groups;
     std::vector<int> cls_group0;                 // first global group of each class
     std::vector<FkTile> tiles;
+    std::vector<int2> tasks;                     // block tasks (first tile, count) per class
+    // columns of the block tasks' LDS rows: per shell its first column among the
+    // shells of its type in its molecule; per (molecule, type) the column count,
+    // the offset of its function list and the functions (local numbering)
+    std::vector<int> krow_col, krow_cnt, krow_off, krow_fn;
     std::vector<FkBraBlock> blocks;
     std::vector<int> blk_bra, blk_pos;
     std::vector<int64_t> blk_nppsum;             // sum of the bras' primitive-pair counts
@@ -116,6 +126,8 @@ struct fk_ctx {
     DevBuf<double> d_lst_CD, d_lst_G, d_ppT;
     DevBuf<FkGroup> d_groups;
     DevBuf<FkTile> d_tiles;
+    DevBuf<int2> d_tasks;
+    DevBuf<int> d_krow_col, d_krow_cnt, d_krow_off, d_krow_fn;
     DevBuf<FkBraBlock> d_blocks;
     DevBuf<int> d_blk_bra, d_blk_pos;
     DevBuf<unsigned long long> d_cnt;
@@ -232,6 +244,7 @@ void free_device(fk_ctx *c)
     dev_free(c->d_X); dev_free(c->d_Din); dev_free(c->d_Jout); dev_free(c->d_Kout); dev_free(c->d_tiles);
     dev_free(c->d_cnt); dev_free(c->d_blocks); dev_free(c->d_blk_bra); dev_free(c->d_blk_pos); dev_free(c->d_lst_sa); dev_free(c->d_lst_sb); dev_free(c->d_lst_CD);
     dev_free(c->d_lst_G); dev_free(c->d_ppT); dev_free(c->d_groups);
+    dev_free(c->d_tasks); dev_free(c->d_krow_col); dev_free(c->d_krow_cnt); dev_free(c->d_krow_off); dev_free(c->d_krow_fn);
     dev_free(c->d_jeng_tiles); dev_free(c->d_jp_off); dev_free(c->d_dq_base); dev_free(c->d_pos_grp);
     dev_free(c->d_jp); dev_free(c->d_dq);
     dev_free(c->d_bf_atom); dev_free(c->d_atom_xyz); dev_free(c->d_ks_shell); dev_free(c->d_dfit); dev_free(c->d_dfit_bins);
@@ -485,6 +498,38 @@ int validate_lists(fk_ctx *c)
             if (T.ket_begin < G.begin || T.ket_begin + T.ket_count > G.begin + G.len)
                 return fail(c, FK_ERR_STATE, "internal: tile %lld leaves its group", (long long)t);
         }
+    }
+    for (const QuartetClass &qc : c->qclasses) {
+        if (qc.ntask == 0) continue;
+        // tasks partition the class's tiles in order; each holds tiles of one
+        // bra block; every ket's columns lie inside the LDS rows
+        if (qc.task_off < 0 || qc.task_off + qc.ntask > (int64_t)c->tasks.size() || qc.krow_ncol < 1)
+            return fail(c, FK_ERR_STATE, "internal: block tasks of class (%d|%d)", qc.P, qc.Q);
+        int64_t next = 0;
+        const int lc = qc.info.lc, ld = qc.info.ld, nc = (lc + 1) * (lc + 2) / 2, nd = (ld + 1) * (ld + 2) / 2;
+        for (int64_t k = qc.task_off; k < qc.task_off + qc.ntask; ++k) {
+            const int2 T = c->tasks[k];
+            if (T.x != next || T.y < 1 || T.x + T.y > qc.ntile)
+                return fail(c, FK_ERR_STATE, "internal: block task %lld is inconsistent", (long long)k);
+            next = T.x + T.y;
+            const int blk = c->tiles[qc.tile_off + T.x].blk;
+            for (int i = T.x; i < T.x + T.y; ++i) {
+                const FkTile &tt = c->tiles[qc.tile_off + i];
+                if (tt.blk != blk) return fail(c, FK_ERR_STATE, "internal: block task %lld mixes bra blocks", (long long)k);
+                const int m = c->groups[tt.grp & ~FK_TILE_SAME].mol;
+                const int cc = c->krow_cnt[4 * m + lc];
+                const int ncm = cc + (lc != ld ? c->krow_cnt[4 * m + ld] : 0);
+                if (ncm > qc.krow_ncol) return fail(c, FK_ERR_STATE, "internal: block task columns exceed the rows");
+                for (int q = tt.ket_begin; q < tt.ket_begin + tt.ket_count; ++q) {
+                    const int sc = c->lst_sa[q], sd = c->lst_sb[q];
+                    const int xc = c->krow_col[sc], xd = c->krow_col[sd] + (lc != ld ? cc : 0);
+                    if (c->sh_l[sc] != lc || c->sh_l[sd] != ld || c->sh_mol[sc] != m || c->sh_mol[sd] != m ||
+                        xc < 0 || xc + nc > cc || xd < (lc != ld ? cc : 0) || xd + nd > ncm)
+                        return fail(c, FK_ERR_STATE, "internal: list position %d has columns outside the rows", q);
+                }
+            }
+        }
+        if (next != qc.ntile) return fail(c, FK_ERR_STATE, "internal: block tasks do not cover class (%d|%d)", qc.P, qc.Q);
     }
     for (int s = 0; s <= c->nshell; ++s)
         if (c->sh_bf[s] < 0 || c->sh_bf[s] > c->nbf) return fail(c, FK_ERR_STATE, "internal: shell offsets");
@@ -772,6 +817,8 @@ int fk_build_quartets(fk_ctx *c, const fk_screen_opts *o)
     if (!(opts.tau >= 0) || !(opts.tau_prim >= 0)) return fail(c, FK_ERR_ARG, "fk_build_quartets: negative threshold");
     if (!(opts.tau_fp32 >= 0)) return fail(c, FK_ERR_ARG, "fk_build_quartets: negative tau_fp32");
     if (!(opts.tau_k >= 0)) return fail(c, FK_ERR_ARG, "fk_build_quartets: negative tau_k");
+    if (opts.block_tasks != 0 && opts.block_tasks != -1)
+        return fail(c, FK_ERR_ARG, "fk_build_quartets: block_tasks must be 0 or -1");
     if (opts.bra_block < 0 || opts.bra_block > FK_MAX_BRA_BLOCK)
         return fail(c, FK_ERR_ARG, "fk_build_quartets: bra_block must be 0..%d", FK_MAX_BRA_BLOCK);
     c->opts = opts;
@@ -886,6 +933,28 @@ int fk_build_quartets(fk_ctx *c, const fk_screen_opts *o)
         }
         c->cls_group0[NPC] = (int)c->groups.size();
     }
+    // columns of the block tasks' K rows: the functions of each shell type,
+    // per molecule in shell order
+    {
+        const int nm = c->nmol;
+        c->krow_col.assign(c->nshell, 0);
+        c->krow_cnt.assign(4 * nm, 0);
+        c->krow_off.assign(4 * nm, 0);
+        for (int s = 0; s < c->nshell; ++s) {
+            const int l = std::min(c->sh_l[s], 3);
+            c->krow_col[s] = c->krow_cnt[4 * c->sh_mol[s] + l];
+            c->krow_cnt[4 * c->sh_mol[s] + l] += c->sh_lend[s] - c->sh_lbf[s];
+        }
+        int tot = 0;
+        for (int k = 0; k < 4 * nm; ++k) { c->krow_off[k] = tot; tot += c->krow_cnt[k]; }
+        c->krow_fn.assign(std::max(tot, 1), 0);
+        std::vector<int> fill(4 * nm, 0);
+        for (int s = 0; s < c->nshell; ++s) {
+            const int k = 4 * c->sh_mol[s] + std::min(c->sh_l[s], 3);
+            for (int f = c->sh_lbf[s]; f < c->sh_lend[s]; ++f) c->krow_fn[c->krow_off[k] + fill[k]++] = f;
+        }
+    }
+    c->tasks.clear();
     // 4. tiles per quartet class (P >= Q): bra blocks from class P, kets from class Q
     const int bra_block = opts.bra_block > 0 ? std::min(opts.bra_block, FK_MAX_BRA_BLOCK) : 8;
     c->tiles.clear();
@@ -997,6 +1066,56 @@ int fk_build_quartets(fk_ctx *c, const fk_screen_opts *o)
                 return c->blk_nppsum[t.blk] * gg.npp * t.ket_count;
             };
             std::stable_sort(tl.begin(), tl.end(), [&](const FkTile &x, const FkTile &y) { return cost(x) > cost(y); });
+            // block tasks: the tiles of one bra block, cut into chunks that share
+            // the block's tiles round-robin (each a similar mix of costs),
+            // largest chunks first; the class's tiles are stored in task order
+            qc.krow_ncol = 0;
+            qc.ntask = 0;
+            if (qc.info.ket_outer > 0 && opts.block_tasks == 0) {
+                int ncol = 0;
+                for (int m = 0; m < c->nmol; ++m)
+                    ncol = std::max(ncol, c->krow_cnt[4 * m + qc.info.lc] +
+                                              (qc.info.lc != qc.info.ld ? c->krow_cnt[4 * m + qc.info.ld] : 0));
+                // only where the rows cost no workgroups per CU (the LDS they take
+                // would otherwise lower the occupancy the registers allow)
+                if (ncol > 0 && fk_kernels_jk_lds_bytes(P, Q, qc.bra_slot, ncol) <= kKrowLdsMax) {
+                    int nb0 = 0, nb1 = 0;
+                    const bool ok = !dev ||
+                        (fk_kernels_max_blocks(P, Q, fk_kernels_jk_lds_bytes(P, Q, qc.bra_slot, 0), qc.engine, &nb0) == 0 &&
+                         fk_kernels_max_blocks(P, Q, fk_kernels_jk_lds_bytes(P, Q, qc.bra_slot, ncol), qc.engine, &nb1) == 0 &&
+                         nb1 >= nb0);
+                    if (ok) qc.krow_ncol = ncol;
+                }
+            }
+            if (qc.krow_ncol > 0) {
+                std::stable_sort(tl.begin(), tl.end(), [](const FkTile &x, const FkTile &y) { return x.blk < y.blk; });
+                const int64_t ch = std::max<int64_t>(16, std::min<int64_t>(256, (int64_t)tl.size() / 4096));
+                std::vector<std::vector<FkTile>> chunks;
+                std::vector<double> ccost;
+                for (size_t i = 0; i < tl.size();) {
+                    size_t j = i;
+                    while (j < tl.size() && tl[j].blk == tl[i].blk) ++j;
+                    const int64_t len = (int64_t)(j - i), nch = (len + ch - 1) / ch;
+                    const size_t c0 = chunks.size();
+                    chunks.resize(c0 + nch);
+                    ccost.resize(c0 + nch, 0.0);
+                    for (int64_t k = 0; k < len; ++k) {
+                        chunks[c0 + k % nch].push_back(tl[i + k]);
+                        ccost[c0 + k % nch] += (double)cost(tl[i + k]);
+                    }
+                    i = j;
+                }
+                std::vector<int> ord_c(chunks.size());
+                std::iota(ord_c.begin(), ord_c.end(), 0);
+                std::stable_sort(ord_c.begin(), ord_c.end(), [&](int x, int y) { return ccost[x] > ccost[y]; });
+                qc.task_off = (int64_t)c->tasks.size();
+                tl.clear();
+                for (int k : ord_c) {
+                    c->tasks.push_back(int2{(int)tl.size(), (int)chunks[k].size()});
+                    tl.insert(tl.end(), chunks[k].begin(), chunks[k].end());
+                }
+                qc.ntask = (int64_t)chunks.size();
+            }
             qc.tile_off = (int64_t)c->tiles.size();
             qc.ntile = (int64_t)tl.size();
             c->tiles.insert(c->tiles.end(), tl.begin(), tl.end());
@@ -1013,7 +1132,7 @@ int fk_build_quartets(fk_ctx *c, const fk_screen_opts *o)
                 q.blocks_per_cu = 1;
                 if (dev) {
                     int nb = 0;
-                    const int lds = fk_kernels_jk_lds_bytes(P, Q, q.bra_slot);
+                    const int lds = fk_kernels_jk_lds_bytes(P, Q, q.bra_slot, q.ntask > 0 ? q.krow_ncol : 0);
                     if (fk_kernels_max_blocks(P, Q, lds, q.engine, &nb) == 0 && nb > 0) q.blocks_per_cu = nb;
                 }
                 if ((int)c->qclasses.size() >= FK_MAX_QCLASS)
@@ -1032,6 +1151,11 @@ int fk_build_quartets(fk_ctx *c, const fk_screen_opts *o)
         if ((rc = dev_upload(c, c->d_ppT, c->ppT.data(), c->ppT.size()))) return rc;
         if ((rc = dev_upload(c, c->d_groups, c->groups.data(), c->groups.size()))) return rc;
         if ((rc = dev_upload(c, c->d_tiles, c->tiles.data(), c->tiles.size()))) return rc;
+        if ((rc = dev_upload(c, c->d_tasks, c->tasks.data(), c->tasks.size()))) return rc;
+        if ((rc = dev_upload(c, c->d_krow_col, c->krow_col.data(), c->krow_col.size()))) return rc;
+        if ((rc = dev_upload(c, c->d_krow_cnt, c->krow_cnt.data(), c->krow_cnt.size()))) return rc;
+        if ((rc = dev_upload(c, c->d_krow_off, c->krow_off.data(), c->krow_off.size()))) return rc;
+        if ((rc = dev_upload(c, c->d_krow_fn, c->krow_fn.data(), c->krow_fn.size()))) return rc;
         const size_t nn = (size_t)c->mol_base[c->nmol];
         if ((rc = dev_upload<double>(c, c->d_Ds, nullptr, nn))) return rc;
         if ((rc = dev_upload<double>(c, c->d_Dsh, nullptr, (size_t)c->mol_shbase[c->nmol]))) return rc;
@@ -1355,6 +1479,13 @@ int build_jk_impl(fk_ctx *c, const double *D, double *J, double *K, unsigned fla
         a.ppT = c->d_ppT.p;
         a.tiles = c->d_tiles.p + qc.tile_off;
         a.ntiles = (int)qc.ntile;
+        a.tasks = qc.ntask > 0 ? c->d_tasks.p + qc.task_off : nullptr;
+        a.ntask = (int)qc.ntask;
+        a.krow_ncol = qc.krow_ncol;
+        a.krow_col = c->d_krow_col.p;
+        a.krow_cnt = c->d_krow_cnt.p;
+        a.krow_off = c->d_krow_off.p;
+        a.krow_fn = c->d_krow_fn.p;
         a.Dsh = b.Dsh;
         a.Ds = b.Ds;
         a.XJ = b.X;
@@ -1389,7 +1520,7 @@ int build_jk_impl(fk_ctx *c, const double *D, double *J, double *K, unsigned fla
         a.blk_pos = c->d_blk_pos.p;
         // Enough workgroups for the hardware to fill every CU to its register and
         // LDS limit; the persistent loop covers the rest.
-        const int64_t wgs = (qc.ntile + 3) / 4;
+        const int64_t wgs = qc.ntask > 0 ? qc.ntask : (qc.ntile + 3) / 4;
         const int64_t cap = std::max<int64_t>(1, (int64_t)(qc.grid_frac * std::max(8, qc.blocks_per_cu) * std::max(c->ncu, 1)));
         const int grid = (int)std::max<int64_t>(1, std::min(wgs, cap));
         if (fk_kernels_launch_jk(qc.P, qc.Q, &a, grid, st))
@@ -1491,6 +1622,7 @@ int fk_stats(fk_ctx *c, fk_stats_t *s)
         s->bra_block[i] = q.bra_block;
         s->kets_per_tile[i] = q.kets_per_tile;
         s->grid_fraction[i] = q.grid_frac;
+        s->block_tasks[i] = q.ntask;
         s->tiles[i] = q.ntile;
         s->team_size[i] = q.info.wave_per_quartet == 3 ? 64 : std::max(1, q.info.team_size);
         s->precision[i] = q.prec ? 32 : 64;

@@ -101,7 +101,19 @@ struct FkJKArgs {
     const double *ks_shell;
     const double *ks_fit;
     double ks_tau;
-                             // for every quartet of the wave, the FP64 launch otherwise
+    // Block tasks of the ket-outer lane classes (ntask 0: each wave takes tiles
+    // on its own).  A workgroup takes task i = tasks[i] = (first tile, tile
+    // count), tiles of one bra block (a, b_j); its waves share those tiles and
+    // sum X_K[b_j, x], X_K[a, x] and X_J[a, b_j] of the block in LDS, which
+    // reaches memory once per task.  The columns x are the functions of the
+    // ket shells' types, numbered per molecule: krow_col[shell] is a shell's
+    // first column among the shells of its type, krow_cnt[4 mol + l] the
+    // columns of type l, and krow_fn[krow_off[4 mol + l] + x] the function of
+    // column x.  The ket's c columns come first, then (types differing) d's.
+    const int2 *tasks;
+    int ntask;
+    int krow_ncol;           // LDS row length: the class's largest column count over the molecules
+    const int *krow_col, *krow_cnt, *krow_off, *krow_fn;
 };
 
 // The accumulators X_J, X_K exist once per XCD (CDNA3/4 parts have 8 XCDs,
@@ -139,6 +151,7 @@ struct FkClassInfo {
     int team_size;           // lanes per quartet
     int bra_block;           // largest bra block the class kernel takes per tile
     double flops_prim, flops_quartet;
+    int ket_outer;           // bra block of the ket-outer loop order (0: bra-outer)
     int hgp;                 // 1: the HGP engine is built for the class
     double flops_prim_hgp, flops_quartet_hgp;
 };
@@ -150,7 +163,8 @@ int fk_kernels_class_info(int P, int Q, FkClassInfo *info);
 int fk_kernels_launch_jk(int P, int Q, const FkJKArgs *args, int grid, void *stream);
 int fk_kernels_launch_debug(int P, int Q, const FkDebugArgs *args, void *stream);
 int fk_kernels_max_blocks(int P, int Q, int dyn_lds_bytes, int engine, int *blocks_per_cu);
-int fk_kernels_jk_lds_bytes(int P, int Q, int bra_slot);
+// dynamic LDS of a class launch; krow_ncol > 0 adds the block-task K rows
+int fk_kernels_jk_lds_bytes(int P, int Q, int bra_slot, int krow_ncol);
 int fk_kernels_launch_prep(const double *D, const double *bf_scale, const FkMolArgs *m, double *Ds, double *Dsh,
                            void *stream);
 int fk_kernels_launch_finalize(const double *XJ, const double *XK, long long xcopy, int ncopy, const double *bf_scale,

@@ -89,6 +89,7 @@ __device__ __forceinline__ void wave_sync_lds()
 }
 
 __device__ __forceinline__ void atomic_add(double *p, double v) { unsafeAtomicAdd(p, v); }
+__device__ __forceinline__ void lds_add(double *p, double v) { unsafeAtomicAdd(p, v); }
 
 // FP64 atomic adds to device memory are served one 32-byte sector request per
 // lane unless lanes of the same instruction address the same sector (measured
@@ -311,12 +312,17 @@ __device__ __forceinline__ int nth_bit(unsigned long long m, int n)
 // and added here) and the per-bra X_K[b, c], X_K[b, d] (flushed here), and adds
 // to the block sums X_K[a, c], X_K[a, d], X_J[c, d] of the caller.  Every lane
 // of the wave calls it (the flushes and the reduction are wave operations);
-// `active` marks the lanes whose quartet is computed.
+// `active` marks the lanes whose quartet is computed.  With kr_b (block
+// tasks) the per-bra sums go to the workgroup's LDS rows instead of memory:
+// X_K[b, x] to kr_b[ib * ncol + x] (x = colc + ic for c, cold + id for d) and
+// the wave's X_J[a, b] to kr_jab.
 template <int LA, int LB, int LC, int LD, typename R>
 __device__ __forceinline__ void lpq_digest(R *acc, bool active, bool diag, int sa, int sb, int sc, int sd, int oa,
                                            int ob, int oc, int od, int n, const double *__restrict Ds,
                                            const double *dcd, double *kac, double *kad, double *jcd, double *XJ,
-                                           double *XK, double *s_stage, int lane, bool wj, bool wk, bool &any)
+                                           double *XK, double *s_stage, int lane, bool wj, bool wk, bool &any,
+                                           double *kr_b = nullptr, int ncol = 0, int colc = 0, int cold = 0,
+                                           double *kr_jab = nullptr)
 {
     using Q = fk::QClass<LA, LB, LC, LD>;
     constexpr int NA = Q::NA, NB = Q::NB, NC = Q::NC, ND = Q::ND, NOUT = Q::NOUT;
@@ -397,15 +403,30 @@ __device__ __forceinline__ void lpq_digest(R *acc, bool active, bool diag, int s
         }
     }
     if (wk) {
-        flush_sym<NB, NC>(XK, n, ob, oc, kbc, s_stage, lane);
-        flush_sym<NB, ND>(XK, n, ob, od, kbd, s_stage, lane);
+        if (kr_b) {
+            if (active) {
+#pragma unroll
+                for (int ib = 0; ib < NB; ++ib) {
+#pragma unroll
+                    for (int ic = 0; ic < NC; ++ic) lds_add(&kr_b[ib * ncol + colc + ic], kbc[ib * NC + ic]);
+#pragma unroll
+                    for (int id = 0; id < ND; ++id) lds_add(&kr_b[ib * ncol + cold + id], kbd[ib * ND + id]);
+                }
+            }
+        } else {
+            flush_sym<NB, NC>(XK, n, ob, oc, kbc, s_stage, lane);
+            flush_sym<NB, ND>(XK, n, ob, od, kbd, s_stage, lane);
+        }
     }
     // all lanes (active or not) take part in the wave reduction of X_J[a, b]
     if (wj) {
 #pragma unroll
         for (int ab = 0; ab < NA * NB; ++ab) {
             const double s = wave_sum(jab[ab]);
-            if (lane == 0) atomic_add(&XJ[(size_t)(oa + ab / NB) * n + ob + ab % NB], 2.0 * s);
+            if (lane == 0) {
+                if (kr_jab) lds_add(&kr_jab[ab], 2.0 * s);
+                else atomic_add(&XJ[(size_t)(oa + ab / NB) * n + ob + ab % NB], 2.0 * s);
+            }
         }
     }
 }
@@ -467,18 +488,23 @@ struct LpqMinBlocks<3, 0, 0, 0> {
 // NOUT accumulators per lane).  Measured on (H2O)64 cc-pVDZ-type: (ps|ss)
 // 47.0 -> 41.7 ms with blocks of 8 (its registers also drop to three waves per
 // SIMD); 16 bras cost (ps|ss) a wave per SIMD (51.8 ms); (ps|ps) and (pp|ss)
-// lose with any block (32.8 -> 36.3 ms at 4 bras, 47.4 ms at 2).
+// lose with any block (32.8 -> 36.3 ms at 4 bras, 47.4 ms at 2).  With block
+// tasks (the K rows of a block summed in LDS) four bras win: (ps|ss) takes
+// 37.4 ms at 4 (163 VGPRs, three waves per SIMD) against 46.6 ms at 8 (188
+// VGPRs, two waves; 49.1 and 45.2 ms without block tasks); (ss|ss) (HGP)
+// 19.7 ms at 4 with block tasks (four workgroups per CU fit their LDS)
+// against 23.2 ms at 8, where the rows would halve the workgroups per CU.
 template <int LA, int LB, int LC, int LD>
 struct LpqKetOuter {
     static constexpr int value = 0;
 };
 template <>
 struct LpqKetOuter<0, 0, 0, 0> {
-    static constexpr int value = 8;
+    static constexpr int value = 4;
 };
 template <>
 struct LpqKetOuter<1, 0, 0, 0> {
-    static constexpr int value = 8;
+    static constexpr int value = 4;
 };
 
 // Doubles per wave of the lane kernel's LDS stage for flush_block: the largest
@@ -507,10 +533,11 @@ __global__ void __launch_bounds__(FK_BLOCK, (LpqMinBlocks<LA, LB, LC, LD>::value
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     double *s_stage = s_dyn + rys_lds_size(Q::NR) + wave * LpqStage<LA, LB, LC, LD>::value;
-    const int nwt = gridDim.x * FK_WAVES;
     unsigned long long cq = 0, cp = 0;
 
-    for (int t = blockIdx.x * FK_WAVES + wave; t < a.ntiles; t += nwt) {
+    constexpr int NBK = LpqKetOuter<LA, LB, LC, LD>::value;
+    // one tile (t) for this wave; kr: the workgroup's K rows of a block task, or null
+    auto do_tile = [&](int t, double *kr) {
         const FkTile tile = a.tiles[t];
         const bool same = (tile.grp & FK_TILE_SAME) != 0;
         const FkGroup g = a.groups[tile.grp & ~FK_TILE_SAME];
@@ -532,6 +559,12 @@ __global__ void __launch_bounds__(FK_BLOCK, (LpqMinBlocks<LA, LB, LC, LD>::value
         const int oc = shbf[sc], od = shbf[sd];
         const int sa = a.pair_sa[a.blk_bra[blk.first]];
         const int oa = shbf[sa];
+        int colc = 0, cold = 0;
+        if (NBK > 0 && kr) {
+            const int *kcol = a.krow_col + a.mol_sh0[mol];
+            colc = kcol[sc];
+            cold = kcol[sd] + (LC != LD ? a.krow_cnt[4 * mol + LC] : 0);
+        }
         // D_cd is used with every bra of the block
         double dcd[NC * ND];
 #pragma unroll
@@ -547,7 +580,6 @@ __global__ void __launch_bounds__(FK_BLOCK, (LpqMinBlocks<LA, LB, LC, LD>::value
 #pragma unroll
         for (int o = 0; o < NC * ND; ++o) jcd[o] = 0.0;
         bool any = false;
-        constexpr int NBK = LpqKetOuter<LA, LB, LC, LD>::value;
 
         if constexpr (NBK > 0) {
             // ket-outer: screen every bra of the block first, then one pass over
@@ -633,7 +665,9 @@ __global__ void __launch_bounds__(FK_BLOCK, (LpqMinBlocks<LA, LB, LC, LD>::value
                     for (int o = 0; o < NACC; ++o) acck[k][o] = acck[k + 1][o];
                 if (__ballot(active) == 0ull) continue;
                 lpq_digest<LA, LB, LC, LD, R>(acc, active, same && pos == bpos, sa, sb, sc, sd, oa, shbf[sb], oc,
-                                              od, n, Ds, dcd, kac, kad, jcd, XJ, XK, s_stage, lane, wj, wk, any);
+                                              od, n, Ds, dcd, kac, kad, jcd, XJ, XK, s_stage, lane, wj, wk, any,
+                                              kr ? kr + jb * NB * a.krow_ncol : nullptr, a.krow_ncol, colc, cold,
+                                              kr ? kr + (NBK * NB + NA) * a.krow_ncol + jb * NA * NB : nullptr);
             }
         } else
         for (int jb = 0; jb < blk.count; ++jb) {
@@ -701,7 +735,16 @@ __global__ void __launch_bounds__(FK_BLOCK, (LpqMinBlocks<LA, LB, LC, LD>::value
         }
         // block sums: a lane without work holds zeros, which are not added
         if (__ballot(any) != 0ull) {
-            if (wk) {
+            if (NBK > 0 && wk && kr) {
+                // X_K[a, c], X_K[a, d] into the block's a rows
+                double *kra = kr + NBK * NB * a.krow_ncol;
+#pragma unroll
+                for (int o = 0; o < NA * NC; ++o)
+                    if (kac[o] != 0.0) lds_add(&kra[(o / NC) * a.krow_ncol + colc + o % NC], kac[o]);
+#pragma unroll
+                for (int o = 0; o < NA * ND; ++o)
+                    if (kad[o] != 0.0) lds_add(&kra[(o / ND) * a.krow_ncol + cold + o % ND], kad[o]);
+            } else if (wk) {
                 flush_sym<NA, NC>(XK, n, oa, oc, kac, s_stage, lane);
                 flush_sym<NA, ND>(XK, n, oa, od, kad, s_stage, lane);
             }
@@ -711,6 +754,61 @@ __global__ void __launch_bounds__(FK_BLOCK, (LpqMinBlocks<LA, LB, LC, LD>::value
                 flush_sym<NC, ND>(XJ, n, oc, od, jcd, s_stage, lane);
             }
         }
+    };
+    if (NBK > 0 && a.ntask > 0) {
+        // block tasks: the K rows follow the table and the waves' stages
+        double *kr = s_dyn + rys_lds_size(Q::NR) + FK_WAVES * LpqStage<LA, LB, LC, LD>::value;
+        const int ncol = a.krow_ncol;
+        const int nkr = (NBK * NB + NA) * ncol + NBK * NA * NB;
+        for (int task = blockIdx.x; task < a.ntask; task += gridDim.x) {
+            const int2 tk = a.tasks[task];
+            for (int i = threadIdx.x; i < nkr; i += FK_BLOCK) kr[i] = 0.0;
+            __syncthreads();
+            for (int t = tk.x + wave; t < tk.x + tk.y; t += FK_WAVES) do_tile(t, kr);
+            __syncthreads();
+            // the block's rows to memory: nonzero entries, consecutive threads
+            // on consecutive columns of a row
+            const FkTile t0 = a.tiles[tk.x];
+            const int mol = a.groups[t0.grp & ~FK_TILE_SAME].mol;
+            const int n = a.mol_nbf[mol];
+            const int *__restrict shbf = a.sh_bf + a.mol_sh0[mol];
+            const long long xoff = (long long)(blockIdx.x % FK_XCD_COPIES) * a.xcopy + a.mol_base[mol];
+            const FkBraBlock blk = a.blocks[t0.blk];
+            const int oa = shbf[a.pair_sa[a.blk_bra[blk.first]]];
+            const int cc = a.krow_cnt[4 * mol + LC];
+            const int ncm = cc + (LC != LD ? a.krow_cnt[4 * mol + LD] : 0);
+            const int *fnc = a.krow_fn + a.krow_off[4 * mol + LC];
+            const int *fnd = a.krow_fn + a.krow_off[4 * mol + LD];
+            if (wk) {
+                double *XK = a.XK + xoff;
+                const int nrow = blk.count * NB + NA;
+                for (int e = threadIdx.x; e < nrow * ncm; e += FK_BLOCK) {
+                    const int r = e / ncm, x = e - r * ncm;
+                    const int rr = r < blk.count * NB ? r : NBK * NB + (r - blk.count * NB);
+                    const double v = kr[rr * ncol + x];
+                    if (v == 0.0) continue;
+                    const int row = r < blk.count * NB ? shbf[a.pair_sb[a.blk_bra[blk.first + r / NB]]] + r % NB
+                                                       : oa + (r - blk.count * NB);
+                    const int fn = x < cc ? fnc[x] : fnd[x - cc];
+                    atomic_add(&XK[(size_t)row * n + fn], v);
+                }
+            }
+            if (wj) {
+                double *XJ = a.XJ + xoff;
+                const double *kj = kr + (NBK * NB + NA) * ncol;
+                for (int e = threadIdx.x; e < blk.count * NA * NB; e += FK_BLOCK) {
+                    const double v = kj[e];
+                    if (v == 0.0) continue;
+                    const int jb = e / (NA * NB), ab = e % (NA * NB);
+                    const int ob = shbf[a.pair_sb[a.blk_bra[blk.first + jb]]];
+                    atomic_add(&XJ[(size_t)(oa + ab / NB) * n + ob + ab % NB], v);
+                }
+            }
+            __syncthreads();
+        }
+    } else {
+        const int nwt = gridDim.x * FK_WAVES;
+        for (int t = blockIdx.x * FK_WAVES + wave; t < a.ntiles; t += nwt) do_tile(t, nullptr);
     }
     if (lane == 0 && cq) {
         atomicAdd(&a.counters[0], cq);
@@ -741,7 +839,6 @@ struct TeamShape {
     static constexpr int RED = QPW * NV + FK_TEAM_MAX_BLOCK * Q::NA * Q::NB;
 };
 
-__device__ __forceinline__ void lds_add(double *p, double v) { unsafeAtomicAdd(p, v); }
 
 // Waves per SIMD the compiler must fit in registers (as for the lane-per-quartet
 // kernels): team classes whose demand is just above half of the file run
@@ -1256,6 +1353,7 @@ struct Disp {
                        : (KIND == 0 && C::NOUT <= FK_LPQ_BLOCK_NOUT) ? FK_MAX_BRA_BLOCK
                        : ((KIND == 1 || KIND == 2) ? FK_TEAM_MAX_BLOCK : 1);
         i->team_size = KIND == 0 ? 1 : (KIND == 1 ? C::NA : (KIND == 2 ? C::NA * C::NB : 64));
+        i->ket_outer = NBK;
         i->flops_prim = fk::flops_prim(LA, LB, LC, LD);
         i->flops_quartet = fk::flops_digest(LA, LB, LC, LD);
         i->hgp = HGP ? 1 : 0;
@@ -1277,22 +1375,27 @@ struct Disp {
                        : (const void *)&k_jk_tpq<LA, LB, LC, LD, KIND, double>;
         else return (const void *)&k_jk_wpq<LA, LB, LC, LD>;
     }
-    static int lds_bytes(int bra_slot)
+    static int lds_bytes(int bra_slot, int krow_ncol)
     {
         // the Rys segment, and per wave the team reductions (bra records are
-        // read from memory by scalar loads: bra_slot needs no LDS)
+        // read from memory by scalar loads: bra_slot needs no LDS); block
+        // tasks add the block's K rows and X_J[a, b_j]
         (void)bra_slot;
         using C = fk::QClass<LA, LB, LC, LD>;
-        int extra = 0;
+        int extra = 0, rows = 0;
         if constexpr (KIND == 0) extra = LpqStage<LA, LB, LC, LD>::value;
         if constexpr (KIND == 1 || KIND == 2) extra = TeamShape<LA, LB, LC, LD, KIND>::RED;
-        return (int)sizeof(double) * (rys_lds_size(C::NR) + FK_WAVES * extra);
+        if constexpr (KIND == 0) {
+            constexpr int NBK = LpqKetOuter<LA, LB, LC, LD>::value;
+            if (NBK > 0 && krow_ncol > 0) rows = (NBK * C::NB + C::NA) * krow_ncol + NBK * C::NA * C::NB;
+        }
+        return (int)sizeof(double) * (rys_lds_size(C::NR) + FK_WAVES * extra + rows);
     }
     static int launch_jk(const FkJKArgs *a, int grid, hipStream_t st)
     {
         if constexpr (!BUILT) return -2;
         else {
-            const int lds = lds_bytes(a->bra_slot);
+            const int lds = lds_bytes(a->bra_slot, a->ntask > 0 ? a->krow_ncol : 0);
             const bool low = a->prec == 1;
             const int eng = a->engine;
             if (low && KIND == 3) return -2;  // f-f bras: FP64 only
@@ -1476,10 +1579,10 @@ int host_q(int q, const int *o, const int *n, const double *ab, const double *pp
                       : host_q<P, Q + 1>(q, o, n, ab, pp, qs, nq, out, eng);
 }
 template <int P, int Q = 0>
-int lds_q(int q, int slot)
+int lds_q(int q, int slot, int ncol)
 {
     if constexpr (Q > P) return -1;
-    else return q == Q ? Disp<P, Q>::lds_bytes(slot) : lds_q<P, Q + 1>(q, slot);
+    else return q == Q ? Disp<P, Q>::lds_bytes(slot, ncol) : lds_q<P, Q + 1>(q, slot, ncol);
 }
 template <int P, int Q = 0>
 const void *kern_q(int q, int eng)
@@ -1747,7 +1850,7 @@ int FK_CAT(fk_kp, FK_ONLY_P, _host)(int Q, const int *o, const int *n, const dou
     return host_q<FK_ONLY_P>(Q, o, n, ab, pp, qs, nq, out, eng);
 }
 const void *FK_CAT(fk_kp, FK_ONLY_P, _kern)(int Q, int eng) { return kern_q<FK_ONLY_P>(Q, eng); }
-int FK_CAT(fk_kp, FK_ONLY_P, _lds)(int Q, int slot) { return lds_q<FK_ONLY_P>(Q, slot); }
+int FK_CAT(fk_kp, FK_ONLY_P, _lds)(int Q, int slot, int ncol) { return lds_q<FK_ONLY_P>(Q, slot, ncol); }
 }
 #else
 // ---- common translation unit: small kernels and the dispatch tables ----
@@ -1894,7 +1997,7 @@ __global__ void k_finalize(const double *__restrict XJ, const double *__restrict
     int fk_kp##P##_host(int, const int *, const int *, const double *, const double *, const int *, int,    \
                         double *, int);                                                                      \
     const void *fk_kp##P##_kern(int, int);                                                                   \
-    int fk_kp##P##_lds(int, int);
+    int fk_kp##P##_lds(int, int, int);
 extern "C" {
 FK_DECL_P(0) FK_DECL_P(1) FK_DECL_P(2) FK_DECL_P(3) FK_DECL_P(4)
 FK_DECL_P(5) FK_DECL_P(6) FK_DECL_P(7) FK_DECL_P(8) FK_DECL_P(9)
@@ -1940,9 +2043,9 @@ static const void *kern_of(int P, int Q, int engine)
     return nullptr;
 }
 
-int fk_kernels_jk_lds_bytes(int P, int Q, int bra_slot)
+int fk_kernels_jk_lds_bytes(int P, int Q, int bra_slot, int krow_ncol)
 {
-    FK_SWITCH_P(P, lds(Q, bra_slot))
+    FK_SWITCH_P(P, lds(Q, bra_slot, krow_ncol))
     return -1;
 }
 

@@ -235,6 +235,29 @@ def test_jk_c20h42_sampled_blocks(fk, torch, c2, tau, tau_prim):
         assert np.max(np.abs(K[off[a]:off[a + 1], off[cc]:off[cc + 1]] - blk)) <= tol, (a, cc)
 
 
+def test_block_tasks_on_and_off(fk, torch, c2):
+    """C20H42 unscreened, with and without block tasks (the (ps|ss) workgroups
+    summing X_K[b_j, x], X_K[a, x] and X_J[a, b_j] of a bra block in LDS):
+    both agree with the oracle's sampled blocks within 1e-10 and with each
+    other (summation order only) within 1e-12."""
+    s, D = c2
+    res = {}
+    for bt in (True, False):
+        J, K, c = _gpu_jk(fk, torch, s, D, tau=0.0, block_tasks=bt)
+        st = {x["class"]: x["block_tasks"] for x in c.stats()["classes"]}
+        assert (st[(1, 0, 0, 0)] > 0) == bt
+        res[bt] = (J, K)
+        off = oracle.bf_offsets(s)
+        jp, kp = _blocks(s, 3), _blocks(s, 4)
+        Jb, Kb = oracle.jk_blocks(s, D, jp, kp)
+        for (a, b), blk in zip(jp, Jb):
+            assert np.max(np.abs(J[off[a]:off[a + 1], off[b]:off[b + 1]] - blk)) <= 1e-10, (bt, a, b)
+        for (a, cc), blk in zip(kp, Kb):
+            assert np.max(np.abs(K[off[a]:off[a + 1], off[cc]:off[cc + 1]] - blk)) <= 1e-10, (bt, a, cc)
+    assert np.max(np.abs(res[True][0] - res[False][0])) <= 1e-12
+    assert np.max(np.abs(res[True][1] - res[False][1])) <= 1e-12
+
+
 @pytest.fixture(scope="module")
 def c3():
     """(H2O)64 cc-pVDZ-type at full size with a seeded dense density of

@@ -513,6 +513,30 @@ def test_class_kernel_choice():
     c.close()
 
 
+def test_block_tasks_partition_the_ket_outer_tiles():
+    """Block tasks (fk_screen_opts.block_tasks = 0): the (ss|ss) and (ps|ss)
+    tiles are regrouped so that each workgroup task holds tiles of one bra
+    block; the same tiles (count, quartets, primitive slots) as without them,
+    and the other classes are untouched.  fk_build_quartets checks the
+    partition and every ket's LDS row columns itself (validate_lists)."""
+    s = wl.c20h42_631gs()
+    on = fk.FockJK(device=-1).set_system(s).build_quartets(tau=1e-10, tau_prim=1e-12).stats()["classes"]
+    off = fk.FockJK(device=-1).set_system(s).build_quartets(tau=1e-10, tau_prim=1e-12,
+                                                             block_tasks=False).stats()["classes"]
+    assert len(on) == len(off)
+    seen = set()
+    for a, b in zip(on, off):
+        assert a["class"] == b["class"]
+        assert (a["tiles"], a["prim_slots"]) == (b["tiles"], b["prim_slots"])
+        assert b["block_tasks"] == 0
+        if a["class"] in ((0, 0, 0, 0), (1, 0, 0, 0)):
+            assert 0 < a["block_tasks"] <= a["tiles"]
+            seen.add(a["class"])
+        else:
+            assert a["block_tasks"] == 0
+    assert seen == {(0, 0, 0, 0), (1, 0, 0, 0)}
+
+
 def test_screen_option_validation():
     s = wl.water4_sto3g()
     c = fk.FockJK(device=-1).set_system(s)
@@ -520,4 +544,6 @@ def test_screen_option_validation():
         with pytest.raises(fk.FockJKError) as e:
             c.build_quartets(**kw)
         assert e.value.code == fk.FK_ERR_ARG
+    o = fk.ScreenOpts(1e-10, 0.0, 1, 0, 0.0, 0.0, 1)
+    assert fk._lib.fk_build_quartets(c._ctx, fk.ctypes.byref(o)) == fk.FK_ERR_ARG
     c.build_quartets(tau=1e-10, tau_k=5e-6)
