@@ -289,10 +289,20 @@ int fk_set_class_schedule(fk_ctx *ctx, int la, int lb, int lc, int ld, int bra_b
 #define FK_ENGINE_HGP 1
 int fk_set_class_engine(fk_ctx *ctx, int la, int lb, int lc, int ld, int engine);
 
+/* Block tasks per class (see fk_screen_opts.block_tasks, which turns them off
+ * for every class): enable = 1 (the default) lets the class's workgroups take
+ * whole bra blocks where the LDS rows fit, 0 keeps its waves on single tiles.
+ * Takes effect at the next fk_build_quartets; FK_ERR_UNSUPPORTED for a class
+ * not built.  Classes other than the ket-outer lane classes never take block
+ * tasks, whatever is set. */
+int fk_set_class_block_tasks(fk_ctx *ctx, int la, int lb, int lc, int ld, int enable);
+
 /* Schedule cache: fk_save_schedules writes every schedule and engine set on
- * the context (by fk_set_class_schedule, fk_set_class_engine, fk_autotune or
+ * the context (by fk_set_class_schedule, fk_set_class_engine,
+ * fk_set_class_block_tasks, fk_autotune or
  * an earlier load) to a text file, one line per class
- * ("class la lb lc ld bra_block kets_per_tile grid_fraction engine") after a
+ * ("class la lb lc ld bra_block kets_per_tile grid_fraction engine
+ * block_tasks"; files without the last field read as block_tasks 1) after a
  * line naming the device architecture ("arch gfx950"; "host" for a context
  * without a device).  fk_load_schedules reads such a file into the context,
  * on top of the schedules already set; FK_ERR_UNSUPPORTED if the file was
@@ -317,6 +327,7 @@ typedef struct {
     double ms_tuned[FK_MAX_QCLASS];
     double build_ms_default, build_ms_tuned;  /* sums over the class launches */
     int    configurations;              /* list configurations built and timed */
+    int    block_tasks[FK_MAX_QCLASS];  /* 1 if the class's schedule allows block tasks */
 } fk_tune_report;
 
 /* Autotuner for the schedules above: on the current geometry, basis and
@@ -324,12 +335,13 @@ typedef struct {
  * (as in fk_build_jk: FK_DEVICE_PTRS for a device pointer, else host), it
  * tries one axis at a time for all classes at once -- bra_block 1..32, then
  * 1, 2, 4, 8 rounds of kets per tile, then grid fractions 1, 1/2, 1/4, 2, 4,
- * then the other integral engine where a class has both --
+ * then the other integral engine where a class has both, then block tasks
+ * switched for the classes that take them (an LDS staging choice) --
  * rebuilding the lists and timing each class launch with HIP events (one
  * warm-up and `reps` timed builds, the minimum kept), keeps for each class the
  * candidate more than 2 % faster than its best so far, and leaves the lists
  * built with the chosen schedules.  report may be NULL.  Runs about
- * 18 (reps + 1) builds and 18 list builds; allocates three nbf^2 buffers for
+ * 19 (reps + 1) builds and 19 list builds; allocates three nbf^2 buffers for
  * its duration. */
 int fk_autotune(fk_ctx *ctx, const double *D, unsigned flags, int reps, void *stream, fk_tune_report *report);
 

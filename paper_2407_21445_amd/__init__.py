@@ -70,7 +70,8 @@ class TuneReport(ctypes.Structure):
                 ("grid_fraction", ctypes.c_double * _Q), ("engine", ctypes.c_int * _Q), ("changed", ctypes.c_int * _Q),
                 ("ms_default", ctypes.c_double * _Q),
                 ("ms_tuned", ctypes.c_double * _Q), ("build_ms_default", ctypes.c_double),
-                ("build_ms_tuned", ctypes.c_double), ("configurations", ctypes.c_int)]
+                ("build_ms_tuned", ctypes.c_double), ("configurations", ctypes.c_int),
+                ("block_tasks", ctypes.c_int * _Q)]
 
 
 class ScfOpts(ctypes.Structure):
@@ -123,6 +124,8 @@ _sig = {
     "fk_run_scf_batch": ([_P, ctypes.POINTER(ScfOpts), _P, _P], _I),
     "fk_set_class_schedule": ([_P, _I, _I, _I, _I, _I, _I, _D], _I),
     "fk_set_class_engine": ([_P, _I, _I, _I, _I, _I], _I),
+
+    "fk_set_class_block_tasks": ([_P, _I, _I, _I, _I, _I], _I),
     "fk_save_schedules": ([_P, ctypes.c_char_p], _I),
     "fk_load_schedules": ([_P, ctypes.c_char_p], _I),
     "fk_autotune": ([_P, _P, _U, _I, _P, ctypes.POINTER(TuneReport)], _I),
@@ -365,6 +368,11 @@ class FockJK:
                                                int(kets_per_tile), float(grid_fraction)))
         return self
 
+    def set_class_block_tasks(self, la, lb, lc, ld, enable=True):
+        """Allow (default) or forbid block tasks for the class."""
+        self._check(_lib.fk_set_class_block_tasks(self._ctx, int(la), int(lb), int(lc), int(ld), 1 if enable else 0))
+        return self
+
     def set_class_engine(self, la, lb, lc, ld, engine):
         """engine: "rys" / "hgp" (or ENGINE_RYS / ENGINE_HGP) for the class."""
         e = {"rys": ENGINE_RYS, "hgp": ENGINE_HGP}.get(engine, engine)
@@ -391,7 +399,8 @@ class FockJK:
             rc = _lib.fk_autotune(self._ctx, _ptr(Dc), 0, int(reps), None, ctypes.byref(r))
         self._check(rc)
         rows = [{k: getattr(r, k)[i] for k in ("la", "lb", "lc", "ld", "precision", "bra_block", "kets_per_tile",
-                                                 "grid_fraction", "engine", "changed", "ms_default", "ms_tuned")} for i in range(r.nclass)]
+                                                 "grid_fraction", "engine", "changed", "ms_default", "ms_tuned",
+                                                 "block_tasks")} for i in range(r.nclass)]
         return {"classes": rows, "build_ms_default": r.build_ms_default, "build_ms_tuned": r.build_ms_tuned,
                 "configurations": r.configurations}
 

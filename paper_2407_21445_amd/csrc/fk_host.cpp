@@ -149,7 +149,7 @@ struct fk_ctx {
     bool timed = false;
     std::vector<hipEvent_t> ev;  // 2 per quartet class
     // per quartet class schedule (key P * NPC + Q), from fk_set_class_schedule or fk_autotune
-    struct ClassSched { int bb = 0, kt = 0; double gf = 1.0; int eng = 0; };
+    struct ClassSched { int bb = 0, kt = 0; double gf = 1.0; int eng = 0; int nobt = 0; };  // nobt: no block tasks
     std::map<int, ClassSched> sched;
     std::vector<double> oe_S, oe_T, oe_V;          // one-electron matrices of the current geometry and basis
     double dscreen_scale = 1.0;                   // per-quartet threshold = tau * this (builds from density changes)
@@ -1071,7 +1071,7 @@ int fk_build_quartets(fk_ctx *c, const fk_screen_opts *o)
             // largest chunks first; the class's tiles are stored in task order
             qc.krow_ncol = 0;
             qc.ntask = 0;
-            if (qc.info.ket_outer > 0 && opts.block_tasks == 0) {
+            if (qc.info.ket_outer > 0 && opts.block_tasks == 0 && !sch.nobt) {
                 int ncol = 0;
                 for (int m = 0; m < c->nmol; ++m)
                     ncol = std::max(ncol, c->krow_cnt[4 * m + qc.info.lc] +
@@ -1663,8 +1663,23 @@ int fk_set_class_schedule(fk_ctx *c, int la, int lb, int lc, int ld, int bra_blo
         !(grid_fraction > 0 && grid_fraction <= 4))
         return fail(c, FK_ERR_ARG, "fk_set_class_schedule: bra_block 0..%d, kets_per_tile 0..64, grid_fraction (0, 4]",
                     FK_MAX_BRA_BLOCK);
-    const int eng = c->sched.count(P * NPC + Q) ? c->sched[P * NPC + Q].eng : 0;
-    c->sched[P * NPC + Q] = fk_ctx::ClassSched{bra_block, kets_per_tile, grid_fraction, eng};
+    const fk_ctx::ClassSched old = c->sched.count(P * NPC + Q) ? c->sched[P * NPC + Q] : fk_ctx::ClassSched{};
+    c->sched[P * NPC + Q] = fk_ctx::ClassSched{bra_block, kets_per_tile, grid_fraction, old.eng, old.nobt};
+    return FK_OK;
+}
+
+int fk_set_class_block_tasks(fk_ctx *c, int la, int lb, int lc, int ld, int enable)
+{
+    if (!c) return FK_ERR_ARG;
+    if (la < lb || lc < ld || la > FK_MAX_L || lc > FK_MAX_L || lb < 0 || ld < 0)
+        return fail(c, FK_ERR_ARG, "fk_set_class_block_tasks: need la >= lb, lc >= ld, l <= %d", FK_MAX_L);
+    if (enable != 0 && enable != 1) return fail(c, FK_ERR_ARG, "fk_set_class_block_tasks: enable must be 0 or 1");
+    int P = pair_class(la, lb), Q = pair_class(lc, ld);
+    if (P < Q) std::swap(P, Q);
+    FkClassInfo info;
+    if (fk_kernels_class_info(P, Q, &info))
+        return fail(c, FK_ERR_UNSUPPORTED, "fk_set_class_block_tasks: class (%d%d|%d%d) is not built", la, lb, lc, ld);
+    c->sched[P * NPC + Q].nobt = enable ? 0 : 1;
     return FK_OK;
 }
 
@@ -1693,7 +1708,7 @@ int fk_save_schedules(fk_ctx *c, const char *path)
     if (!path) return fail(c, FK_ERR_ARG, "fk_save_schedules: null path");
     FILE *f = std::fopen(path, "w");
     if (!f) return fail(c, FK_ERR_ARG, "fk_save_schedules: cannot write %s", path);
-    std::fprintf(f, "# fockjk class schedules: la lb lc ld bra_block kets_per_tile grid_fraction engine\n");
+    std::fprintf(f, "# fockjk class schedules: la lb lc ld bra_block kets_per_tile grid_fraction engine block_tasks\n");
     std::fprintf(f, "arch %s\n", c->arch.c_str());
     for (const auto &kv : c->sched) {
         int l[4] = {0, 0, 0, 0};
@@ -1705,7 +1720,8 @@ int fk_save_schedules(fk_ctx *c, const char *path)
             l[2 * k + 1] = pc - pair_class(la, 0);
         }
         const auto &x = kv.second;
-        std::fprintf(f, "class %d %d %d %d %d %d %.17g %d\n", l[0], l[1], l[2], l[3], x.bb, x.kt, x.gf, x.eng);
+        std::fprintf(f, "class %d %d %d %d %d %d %.17g %d %d\n", l[0], l[1], l[2], l[3], x.bb, x.kt, x.gf, x.eng,
+                     x.nobt ? 0 : 1);
     }
     const bool ok = std::ferror(f) == 0;
     if (std::fclose(f) != 0 || !ok) return fail(c, FK_ERR_ARG, "fk_save_schedules: write error on %s", path);
@@ -1733,15 +1749,17 @@ int fk_load_schedules(fk_ctx *c, const char *path)
             if (c->arch != a) { rc = fail(c, FK_ERR_UNSUPPORTED, "fk_load_schedules: %s is for %s, the device is %s", path, a, c->arch.c_str()); break; }
             arch_ok = true;
         } else if (std::strcmp(word, "class") == 0) {
-            int la, lb, lc, ld, bb, kt, eng;
+            int la, lb, lc, ld, bb, kt, eng, bt = 1;
             double gf;
-            if (std::sscanf(line, "class %d %d %d %d %d %d %lf %d", &la, &lb, &lc, &ld, &bb, &kt, &gf, &eng) != 8) {
-                rc = fail(c, FK_ERR_ARG, "fk_load_schedules: %s:%d: expected 8 fields", path, lineno);
+            const int nf = std::sscanf(line, "class %d %d %d %d %d %d %lf %d %d", &la, &lb, &lc, &ld, &bb, &kt, &gf, &eng, &bt);
+            if (nf != 8 && nf != 9) {
+                rc = fail(c, FK_ERR_ARG, "fk_load_schedules: %s:%d: expected 8 or 9 fields", path, lineno);
                 break;
             }
             if (!arch_ok) { rc = fail(c, FK_ERR_ARG, "fk_load_schedules: %s: class line before the arch line", path); break; }
             if (la < lb || lc < ld || la > FK_MAX_L || lc > FK_MAX_L || lb < 0 || ld < 0 || bb < 0 ||
-                bb > FK_MAX_BRA_BLOCK || kt < 0 || kt > 64 || !(gf > 0 && gf <= 4) || (eng != 0 && eng != 1)) {
+                bb > FK_MAX_BRA_BLOCK || kt < 0 || kt > 64 || !(gf > 0 && gf <= 4) || (eng != 0 && eng != 1) ||
+                (bt != 0 && bt != 1)) {
                 rc = fail(c, FK_ERR_ARG, "fk_load_schedules: %s:%d: value out of range", path, lineno);
                 break;
             }
@@ -1752,7 +1770,7 @@ int fk_load_schedules(fk_ctx *c, const char *path)
                 rc = fail(c, FK_ERR_UNSUPPORTED, "fk_load_schedules: %s:%d: class or engine not built", path, lineno);
                 break;
             }
-            sched[P * NPC + Q] = fk_ctx::ClassSched{bb, kt, gf, eng};
+            sched[P * NPC + Q] = fk_ctx::ClassSched{bb, kt, gf, eng, bt ? 0 : 1};
         } else {
             rc = fail(c, FK_ERR_ARG, "fk_load_schedules: %s:%d: unknown record '%s'", path, lineno, word);
         }
@@ -1819,12 +1837,18 @@ int fk_autotune(fk_ctx *c, const double *D, unsigned flags, int reps, void *stre
     }
     std::map<int, double> tbest = t0;
     // one axis at a time, every class measured under each candidate value
-    for (int axis = 0; axis < 4; ++axis) {
+    for (int axis = 0; axis < 5; ++axis) {
         std::vector<double> vals;
         if (axis == 0) vals = {1, 2, 4, 8, 16, 32};
         else if (axis == 1) vals = {1, 2, 4, 8};   // rounds of kets (team and wave kernels)
         else if (axis == 2) vals = {1.0, 0.5, 0.25, 2.0, 4.0};
-        else {
+        else if (axis == 4) {
+            // block tasks switched, for the classes that take them
+            bool any = false;
+            for (const auto &q : c->qclasses) any = any || q.info.ket_outer > 0;
+            if (!any || opts.block_tasks != 0) break;
+            vals = {-1};
+        } else {
             // the other engine, for the classes that have both
             bool any = false;
             for (const auto &kv : cur) {
@@ -1841,7 +1865,9 @@ int fk_autotune(fk_ctx *c, const double *D, unsigned flags, int reps, void *stre
                 FkClassInfo info;
                 if (fk_kernels_class_info(P, Q, &info)) continue;
                 if (axis == 0) kv.second.bb = (int)v;
-                else if (axis == 3) {
+                else if (axis == 4) {
+                    if (info.ket_outer > 0) kv.second.nobt = 1 - kv.second.nobt;
+                } else if (axis == 3) {
                     if (info.hgp) kv.second.eng = 1 - kv.second.eng;
                 } else if (axis == 1) {
                     if (info.wave_per_quartet == 0) continue;
@@ -1877,6 +1903,7 @@ int fk_autotune(fk_ctx *c, const double *D, unsigned flags, int reps, void *stre
             rep->kets_per_tile[i] = q.info.wave_per_quartet == 0 ? 64 : (sc.kt > 0 ? sc.kt : 2 * (q.info.wave_per_quartet == 3 ? 1 : 64 / std::max(1, q.info.team_size)));
             rep->grid_fraction[i] = sc.gf;
             rep->engine[i] = q.engine;
+            rep->block_tasks[i] = sc.nobt ? 0 : 1;
             const auto s0 = start.find(q.P * NPC + q.Q);
             const fk_ctx::ClassSched sc0 = s0 == start.end() ? fk_ctx::ClassSched{} : s0->second;
             // compare the schedules in effect (a candidate equal to the default is no change)
@@ -1888,7 +1915,8 @@ int fk_autotune(fk_ctx *c, const double *D, unsigned flags, int reps, void *stre
                 return x.kt > 0 ? x.kt : 2 * (q.info.wave_per_quartet == 3 ? 1 : 64 / std::max(1, q.info.team_size));
             };
             rep->changed[i] =
-                (eff_bb(sc0) != eff_bb(sc) || eff_kt(sc0) != eff_kt(sc) || sc0.gf != sc.gf || sc0.eng != sc.eng) ? 1 : 0;
+                (eff_bb(sc0) != eff_bb(sc) || eff_kt(sc0) != eff_kt(sc) || sc0.gf != sc.gf || sc0.eng != sc.eng ||
+                 (q.info.ket_outer > 0 && sc0.nobt != sc.nobt)) ? 1 : 0;
             rep->ms_tuned[i] = launch1[i];
             for (size_t j = 0; j < keys0.size(); ++j)
                 if (keys0[j].P == q.P && keys0[j].Q == q.Q && keys0[j].prec == q.prec) rep->ms_default[i] = launch0[j];

@@ -499,7 +499,7 @@ def test_autotune_keeps_results(fk, torch):
     D = core_guess(T + V, orthogonalizer(S), s["nelec"] // 2)
     c = fk.FockJK(0).set_system(s).build_quartets(tau=0.0)
     rep = c.autotune(torch.tensor(D, device="cuda:0"), reps=1)
-    assert rep["configurations"] == 18 and len(rep["classes"]) == c.info()["nquartet_class"]
+    assert rep["configurations"] == 19 and len(rep["classes"]) == c.info()["nquartet_class"]
     assert all(r["ms_tuned"] > 0 and r["ms_default"] > 0 for r in rep["classes"])
     c.check_indices()
     J, K = c.build_jk(D)

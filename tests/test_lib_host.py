@@ -461,12 +461,12 @@ def test_schedule_cache_round_trip(tmp_path):
     s = _rand_sys(21, lmax=2, natom=4, kmax=2)
     a = fk.FockJK(device=-1).set_system(s)
     a.set_class_schedule(1, 0, 0, 0, 4, 0, 2.0).set_class_schedule(2, 2, 1, 1, 1, 16, 0.5)
-    a.set_class_engine(1, 0, 0, 0, "hgp")
+    a.set_class_engine(1, 0, 0, 0, "hgp").set_class_block_tasks(1, 0, 0, 0, False)
     p = str(tmp_path / "sched.txt")
     a.save_schedules(p)
     text = open(p).read()
     assert "arch host" in text
-    assert "class 1 0 0 0 4 0 2 1" in text and "class 2 2 1 1 1 16 0.5 0" in text
+    assert "class 1 0 0 0 4 0 2 1 0" in text and "class 2 2 1 1 1 16 0.5 0 1" in text
     b = fk.FockJK(device=-1).set_system(s).load_schedules(p)
     p2 = str(tmp_path / "sched2.txt")
     b.save_schedules(p2)
@@ -475,7 +475,8 @@ def test_schedule_cache_round_trip(tmp_path):
                       ("arch host\nclass 1 0 0 0 4 0\n", fk.FK_ERR_ARG),
                       ("arch host\nclass 1 1 1 1 4 0 1 1\n", fk.FK_ERR_UNSUPPORTED),
                       ("class 1 0 0 0 4 0 2 0\n", fk.FK_ERR_ARG),
-                      ("arch host\nclass 0 1 0 0 4 0 2 0\n", fk.FK_ERR_ARG)]:
+                      ("arch host\nclass 0 1 0 0 4 0 2 0\n", fk.FK_ERR_ARG),
+                      ("arch host\nclass 1 0 0 0 4 0 2 0 2\n", fk.FK_ERR_ARG)]:
         q = tmp_path / "bad.txt"
         q.write_text(bad)
         c = fk.FockJK(device=-1).set_system(s).load_schedules(p)
@@ -484,6 +485,12 @@ def test_schedule_cache_round_trip(tmp_path):
         assert e.value.code == code, bad
         c.save_schedules(p2)
         assert open(p2).read() == text
+    # a file without the block-task field (an older cache) allows block tasks
+    q = tmp_path / "old.txt"
+    q.write_text("arch host\nclass 1 0 0 0 4 0 2 0\n")
+    d = fk.FockJK(device=-1).set_system(s).load_schedules(str(q))
+    d.save_schedules(p2)
+    assert "class 1 0 0 0 4 0 2 0 1" in open(p2).read()
 
 
 def test_class_kernel_choice():
@@ -535,6 +542,9 @@ def test_block_tasks_partition_the_ket_outer_tiles():
         else:
             assert a["block_tasks"] == 0
     assert seen == {(0, 0, 0, 0), (1, 0, 0, 0)}
+    one = fk.FockJK(device=-1).set_system(s).set_class_block_tasks(1, 0, 0, 0, False)
+    st = {x["class"]: x["block_tasks"] for x in one.build_quartets(tau=1e-10, tau_prim=1e-12).stats()["classes"]}
+    assert st[(1, 0, 0, 0)] == 0 and st[(0, 0, 0, 0)] > 0
 
 
 def test_screen_option_validation():
