@@ -297,12 +297,26 @@ int fk_set_class_engine(fk_ctx *ctx, int la, int lb, int lc, int ld, int engine)
  * tasks, whatever is set. */
 int fk_set_class_block_tasks(fk_ctx *ctx, int la, int lb, int lc, int ld, int enable);
 
+/* Lanes per quartet of a class's kernel.  Every class has its own kernel
+ * kind (a lane per quartet up to 54 integrals, a team of lanes per quartet,
+ * or a wave per quartet for f-f bras; fk_stats.team_size); the lane classes
+ * with 18 or more integrals and a bra shell of at least three components
+ * ((pp|ps), (ds|ps), (ds|pp), (ds|ds), (dp|ss), (dp|ps), (dd|ss), (fs|ps),
+ * (fp|ss)) also have a team kernel with one lane per component of the first
+ * bra shell.  lanes = 1 selects the lane kernel, lanes = that component
+ * count the team kernel; any other value, or a class without the kernel,
+ * gives FK_ERR_UNSUPPORTED.  Takes effect at the next fk_build_quartets; the
+ * team kernel takes the Rys engine and no block tasks. */
+int fk_set_class_lanes(fk_ctx *ctx, int la, int lb, int lc, int ld, int lanes);
+
 /* Schedule cache: fk_save_schedules writes every schedule and engine set on
  * the context (by fk_set_class_schedule, fk_set_class_engine,
- * fk_set_class_block_tasks, fk_autotune or
+ * fk_set_class_block_tasks, fk_set_class_lanes, fk_autotune or
  * an earlier load) to a text file, one line per class
  * ("class la lb lc ld bra_block kets_per_tile grid_fraction engine
- * block_tasks"; files without the last field read as block_tasks 1) after a
+ * block_tasks alt_lanes", alt_lanes 0 for the class's own kernel, else the
+ * lanes per quartet of its team alternative; files without the last fields
+ * read as block_tasks 1, alt_lanes 0) after a
  * line naming the device architecture ("arch gfx950"; "host" for a context
  * without a device).  fk_load_schedules reads such a file into the context,
  * on top of the schedules already set; FK_ERR_UNSUPPORTED if the file was
@@ -328,6 +342,7 @@ typedef struct {
     double build_ms_default, build_ms_tuned;  /* sums over the class launches */
     int    configurations;              /* list configurations built and timed */
     int    block_tasks[FK_MAX_QCLASS];  /* 1 if the class's schedule allows block tasks */
+    int    lanes_per_quartet[FK_MAX_QCLASS]; /* 1 (lane kernel), a team's lanes, or 64 */
 } fk_tune_report;
 
 /* Autotuner for the schedules above: on the current geometry, basis and
@@ -336,12 +351,13 @@ typedef struct {
  * tries one axis at a time for all classes at once -- bra_block 1..32, then
  * 1, 2, 4, 8 rounds of kets per tile, then grid fractions 1, 1/2, 1/4, 2, 4,
  * then the other integral engine where a class has both, then block tasks
- * switched for the classes that take them (an LDS staging choice) --
+ * switched for the classes that take them (an LDS staging choice), then the
+ * other kernel kind (lanes per quartet) where a class has two --
  * rebuilding the lists and timing each class launch with HIP events (one
  * warm-up and `reps` timed builds, the minimum kept), keeps for each class the
  * candidate more than 2 % faster than its best so far, and leaves the lists
  * built with the chosen schedules.  report may be NULL.  Runs about
- * 19 (reps + 1) builds and 19 list builds; allocates three nbf^2 buffers for
+ * 20 (reps + 1) builds and 20 list builds; allocates three nbf^2 buffers for
  * its duration. */
 int fk_autotune(fk_ctx *ctx, const double *D, unsigned flags, int reps, void *stream, fk_tune_report *report);
 

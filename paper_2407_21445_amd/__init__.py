@@ -71,7 +71,7 @@ class TuneReport(ctypes.Structure):
                 ("ms_default", ctypes.c_double * _Q),
                 ("ms_tuned", ctypes.c_double * _Q), ("build_ms_default", ctypes.c_double),
                 ("build_ms_tuned", ctypes.c_double), ("configurations", ctypes.c_int),
-                ("block_tasks", ctypes.c_int * _Q)]
+                ("block_tasks", ctypes.c_int * _Q), ("lanes_per_quartet", ctypes.c_int * _Q)]
 
 
 class ScfOpts(ctypes.Structure):
@@ -126,6 +126,9 @@ _sig = {
     "fk_set_class_engine": ([_P, _I, _I, _I, _I, _I], _I),
 
     "fk_set_class_block_tasks": ([_P, _I, _I, _I, _I, _I], _I),
+
+
+    "fk_set_class_lanes": ([_P, _I, _I, _I, _I, _I], _I),
     "fk_save_schedules": ([_P, ctypes.c_char_p], _I),
     "fk_load_schedules": ([_P, ctypes.c_char_p], _I),
     "fk_autotune": ([_P, _P, _U, _I, _P, ctypes.POINTER(TuneReport)], _I),
@@ -368,6 +371,12 @@ class FockJK:
                                                int(kets_per_tile), float(grid_fraction)))
         return self
 
+    def set_class_lanes(self, la, lb, lc, ld, lanes):
+        """Lanes per quartet of the class's kernel (1: lane kernel; the team
+        alternative's lane count where the class has one)."""
+        self._check(_lib.fk_set_class_lanes(self._ctx, int(la), int(lb), int(lc), int(ld), int(lanes)))
+        return self
+
     def set_class_block_tasks(self, la, lb, lc, ld, enable=True):
         """Allow (default) or forbid block tasks for the class."""
         self._check(_lib.fk_set_class_block_tasks(self._ctx, int(la), int(lb), int(lc), int(ld), 1 if enable else 0))
@@ -400,7 +409,7 @@ class FockJK:
         self._check(rc)
         rows = [{k: getattr(r, k)[i] for k in ("la", "lb", "lc", "ld", "precision", "bra_block", "kets_per_tile",
                                                  "grid_fraction", "engine", "changed", "ms_default", "ms_tuned",
-                                                 "block_tasks")} for i in range(r.nclass)]
+                                                 "block_tasks", "lanes_per_quartet")} for i in range(r.nclass)]
         return {"classes": rows, "build_ms_default": r.build_ms_default, "build_ms_tuned": r.build_ms_tuned,
                 "configurations": r.configurations}
 

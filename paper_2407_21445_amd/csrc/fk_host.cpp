@@ -149,7 +149,8 @@ struct fk_ctx {
     bool timed = false;
     std::vector<hipEvent_t> ev;  // 2 per quartet class
     // per quartet class schedule (key P * NPC + Q), from fk_set_class_schedule or fk_autotune
-    struct ClassSched { int bb = 0, kt = 0; double gf = 1.0; int eng = 0; int nobt = 0; };  // nobt: no block tasks
+    // nobt: no block tasks; alt: a lane class runs its team-per-quartet kernel
+    struct ClassSched { int bb = 0, kt = 0; double gf = 1.0; int eng = 0; int nobt = 0; int alt = 0; };
     std::map<int, ClassSched> sched;
     std::vector<double> oe_S, oe_T, oe_V;          // one-electron matrices of the current geometry and basis
     double dscreen_scale = 1.0;                   // per-quartet threshold = tau * this (builds from density changes)
@@ -973,6 +974,16 @@ int fk_build_quartets(fk_ctx *c, const fk_screen_opts *o)
             qc.P = P; qc.Q = Q;
             if (fk_kernels_class_info(P, Q, &qc.info))
                 return fail(c, FK_ERR_UNSUPPORTED, "quartet class (%d|%d) is not built into this library", P, Q);
+            const auto sit = c->sched.find(P * NPC + Q);
+            const fk_ctx::ClassSched sch = sit == c->sched.end() ? fk_ctx::ClassSched{} : sit->second;
+            if (sch.alt && qc.info.alt_team > 0) {
+                // the class's team-per-quartet kernel: a lane per component of a
+                qc.info.wave_per_quartet = 1;
+                qc.info.team_size = qc.info.alt_team;
+                qc.info.bra_block = qc.info.alt_bra_block;
+                qc.info.ket_outer = 0;
+                qc.info.hgp = 0;
+            }
             // precision split: the class gets a second, FP32 launch over the same
             // tiles (not for the f-f bra kernels, which are FP64 only); per bra
             // and tile the kernels send the work to exactly one of the two
@@ -980,8 +991,6 @@ int fk_build_quartets(fk_ctx *c, const fk_screen_opts *o)
             // kets per tile: a full wave of kets for lane-per-quartet kernels, two
             // rounds of teams for team kernels, two kets for wave-per-quartet
             const int ts = std::max(1, qc.info.team_size);
-            const auto sit = c->sched.find(P * NPC + Q);
-            const fk_ctx::ClassSched sch = sit == c->sched.end() ? fk_ctx::ClassSched{} : sit->second;
             int tile_kets = qc.info.wave_per_quartet == 0 ? 64 : std::max(1, 2 * (64 / ts));
             if (qc.info.wave_per_quartet != 0 && sch.kt > 0) tile_kets = std::min(64, sch.kt);
             qc.grid_frac = sch.gf;
@@ -1078,11 +1087,12 @@ int fk_build_quartets(fk_ctx *c, const fk_screen_opts *o)
                                               (qc.info.lc != qc.info.ld ? c->krow_cnt[4 * m + qc.info.ld] : 0));
                 // only where the rows cost no workgroups per CU (the LDS they take
                 // would otherwise lower the occupancy the registers allow)
-                if (ncol > 0 && fk_kernels_jk_lds_bytes(P, Q, qc.bra_slot, ncol) <= kKrowLdsMax) {
+                const int kd = qc.info.wave_per_quartet;
+                if (ncol > 0 && fk_kernels_jk_lds_bytes(P, Q, qc.bra_slot, ncol, kd) <= kKrowLdsMax) {
                     int nb0 = 0, nb1 = 0;
                     const bool ok = !dev ||
-                        (fk_kernels_max_blocks(P, Q, fk_kernels_jk_lds_bytes(P, Q, qc.bra_slot, 0), qc.engine, &nb0) == 0 &&
-                         fk_kernels_max_blocks(P, Q, fk_kernels_jk_lds_bytes(P, Q, qc.bra_slot, ncol), qc.engine, &nb1) == 0 &&
+                        (fk_kernels_max_blocks(P, Q, fk_kernels_jk_lds_bytes(P, Q, qc.bra_slot, 0, kd), qc.engine, kd, &nb0) == 0 &&
+                         fk_kernels_max_blocks(P, Q, fk_kernels_jk_lds_bytes(P, Q, qc.bra_slot, ncol, kd), qc.engine, kd, &nb1) == 0 &&
                          nb1 >= nb0);
                     if (ok) qc.krow_ncol = ncol;
                 }
@@ -1132,8 +1142,10 @@ int fk_build_quartets(fk_ctx *c, const fk_screen_opts *o)
                 q.blocks_per_cu = 1;
                 if (dev) {
                     int nb = 0;
-                    const int lds = fk_kernels_jk_lds_bytes(P, Q, q.bra_slot, q.ntask > 0 ? q.krow_ncol : 0);
-                    if (fk_kernels_max_blocks(P, Q, lds, q.engine, &nb) == 0 && nb > 0) q.blocks_per_cu = nb;
+                    const int lds = fk_kernels_jk_lds_bytes(P, Q, q.bra_slot, q.ntask > 0 ? q.krow_ncol : 0,
+                                                            q.info.wave_per_quartet);
+                    if (fk_kernels_max_blocks(P, Q, lds, q.engine, q.info.wave_per_quartet, &nb) == 0 && nb > 0)
+                        q.blocks_per_cu = nb;
                 }
                 if ((int)c->qclasses.size() >= FK_MAX_QCLASS)
                     return fail(c, FK_ERR_STATE, "internal: more class launches than FK_MAX_QCLASS");
@@ -1515,6 +1527,7 @@ int build_jk_impl(fk_ctx *c, const double *D, double *J, double *K, unsigned fla
         for (const auto &o : c->qclasses) twin = twin || (o.P == qc.P && o.Q == qc.Q && o.prec != qc.prec);
         a.tau_fp32 = twin ? c->opts.tau_fp32 : 0.0;
         a.engine = qc.engine;
+        a.kind = qc.info.wave_per_quartet;
         a.blocks = c->d_blocks.p;
         a.blk_bra = c->d_blk_bra.p;
         a.blk_pos = c->d_blk_pos.p;
@@ -1664,7 +1677,25 @@ int fk_set_class_schedule(fk_ctx *c, int la, int lb, int lc, int ld, int bra_blo
         return fail(c, FK_ERR_ARG, "fk_set_class_schedule: bra_block 0..%d, kets_per_tile 0..64, grid_fraction (0, 4]",
                     FK_MAX_BRA_BLOCK);
     const fk_ctx::ClassSched old = c->sched.count(P * NPC + Q) ? c->sched[P * NPC + Q] : fk_ctx::ClassSched{};
-    c->sched[P * NPC + Q] = fk_ctx::ClassSched{bra_block, kets_per_tile, grid_fraction, old.eng, old.nobt};
+    c->sched[P * NPC + Q] = fk_ctx::ClassSched{bra_block, kets_per_tile, grid_fraction, old.eng, old.nobt, old.alt};
+    return FK_OK;
+}
+
+int fk_set_class_lanes(fk_ctx *c, int la, int lb, int lc, int ld, int lanes)
+{
+    if (!c) return FK_ERR_ARG;
+    if (la < lb || lc < ld || la > FK_MAX_L || lc > FK_MAX_L || lb < 0 || ld < 0)
+        return fail(c, FK_ERR_ARG, "fk_set_class_lanes: need la >= lb, lc >= ld, l <= %d", FK_MAX_L);
+    int P = pair_class(la, lb), Q = pair_class(lc, ld);
+    if (P < Q) std::swap(P, Q);
+    FkClassInfo info;
+    if (fk_kernels_class_info(P, Q, &info))
+        return fail(c, FK_ERR_UNSUPPORTED, "fk_set_class_lanes: class (%d%d|%d%d) is not built", la, lb, lc, ld);
+    const int own = info.wave_per_quartet == 0 ? 1 : (info.wave_per_quartet == 3 ? 64 : info.team_size);
+    if (lanes != own && !(info.alt_team > 0 && lanes == info.alt_team))
+        return fail(c, FK_ERR_UNSUPPORTED, "fk_set_class_lanes: class (%d%d|%d%d) has no kernel with %d lanes per quartet",
+                    la, lb, lc, ld, lanes);
+    c->sched[P * NPC + Q].alt = (info.alt_team > 0 && lanes == info.alt_team) ? 1 : 0;
     return FK_OK;
 }
 
@@ -1708,7 +1739,8 @@ int fk_save_schedules(fk_ctx *c, const char *path)
     if (!path) return fail(c, FK_ERR_ARG, "fk_save_schedules: null path");
     FILE *f = std::fopen(path, "w");
     if (!f) return fail(c, FK_ERR_ARG, "fk_save_schedules: cannot write %s", path);
-    std::fprintf(f, "# fockjk class schedules: la lb lc ld bra_block kets_per_tile grid_fraction engine block_tasks\n");
+    std::fprintf(f, "# fockjk class schedules: la lb lc ld bra_block kets_per_tile grid_fraction engine block_tasks "
+                    "alt_lanes\n");
     std::fprintf(f, "arch %s\n", c->arch.c_str());
     for (const auto &kv : c->sched) {
         int l[4] = {0, 0, 0, 0};
@@ -1720,8 +1752,13 @@ int fk_save_schedules(fk_ctx *c, const char *path)
             l[2 * k + 1] = pc - pair_class(la, 0);
         }
         const auto &x = kv.second;
-        std::fprintf(f, "class %d %d %d %d %d %d %.17g %d %d\n", l[0], l[1], l[2], l[3], x.bb, x.kt, x.gf, x.eng,
-                     x.nobt ? 0 : 1);
+        int alt_lanes = 0;
+        if (x.alt) {
+            FkClassInfo info;
+            if (!fk_kernels_class_info(kv.first / NPC, kv.first % NPC, &info)) alt_lanes = info.alt_team;
+        }
+        std::fprintf(f, "class %d %d %d %d %d %d %.17g %d %d %d\n", l[0], l[1], l[2], l[3], x.bb, x.kt, x.gf, x.eng,
+                     x.nobt ? 0 : 1, alt_lanes);
     }
     const bool ok = std::ferror(f) == 0;
     if (std::fclose(f) != 0 || !ok) return fail(c, FK_ERR_ARG, "fk_save_schedules: write error on %s", path);
@@ -1749,11 +1786,12 @@ int fk_load_schedules(fk_ctx *c, const char *path)
             if (c->arch != a) { rc = fail(c, FK_ERR_UNSUPPORTED, "fk_load_schedules: %s is for %s, the device is %s", path, a, c->arch.c_str()); break; }
             arch_ok = true;
         } else if (std::strcmp(word, "class") == 0) {
-            int la, lb, lc, ld, bb, kt, eng, bt = 1;
+            int la, lb, lc, ld, bb, kt, eng, bt = 1, al = 0;
             double gf;
-            const int nf = std::sscanf(line, "class %d %d %d %d %d %d %lf %d %d", &la, &lb, &lc, &ld, &bb, &kt, &gf, &eng, &bt);
-            if (nf != 8 && nf != 9) {
-                rc = fail(c, FK_ERR_ARG, "fk_load_schedules: %s:%d: expected 8 or 9 fields", path, lineno);
+            const int nf = std::sscanf(line, "class %d %d %d %d %d %d %lf %d %d %d", &la, &lb, &lc, &ld, &bb, &kt, &gf, &eng,
+                                       &bt, &al);
+            if (nf < 8 || nf > 10) {
+                rc = fail(c, FK_ERR_ARG, "fk_load_schedules: %s:%d: expected 8 to 10 fields", path, lineno);
                 break;
             }
             if (!arch_ok) { rc = fail(c, FK_ERR_ARG, "fk_load_schedules: %s: class line before the arch line", path); break; }
@@ -1766,11 +1804,11 @@ int fk_load_schedules(fk_ctx *c, const char *path)
             int P = pair_class(la, lb), Q = pair_class(lc, ld);
             if (P < Q) std::swap(P, Q);
             FkClassInfo info;
-            if (fk_kernels_class_info(P, Q, &info) || (eng == 1 && !info.hgp)) {
-                rc = fail(c, FK_ERR_UNSUPPORTED, "fk_load_schedules: %s:%d: class or engine not built", path, lineno);
+            if (fk_kernels_class_info(P, Q, &info) || (eng == 1 && !info.hgp) || (al != 0 && al != info.alt_team)) {
+                rc = fail(c, FK_ERR_UNSUPPORTED, "fk_load_schedules: %s:%d: class, engine or kernel not built", path, lineno);
                 break;
             }
-            sched[P * NPC + Q] = fk_ctx::ClassSched{bb, kt, gf, eng, bt ? 0 : 1};
+            sched[P * NPC + Q] = fk_ctx::ClassSched{bb, kt, gf, eng, bt ? 0 : 1, al ? 1 : 0};
         } else {
             rc = fail(c, FK_ERR_ARG, "fk_load_schedules: %s:%d: unknown record '%s'", path, lineno, word);
         }
@@ -1837,7 +1875,7 @@ int fk_autotune(fk_ctx *c, const double *D, unsigned flags, int reps, void *stre
     }
     std::map<int, double> tbest = t0;
     // one axis at a time, every class measured under each candidate value
-    for (int axis = 0; axis < 5; ++axis) {
+    for (int axis = 0; axis < 6; ++axis) {
         std::vector<double> vals;
         if (axis == 0) vals = {1, 2, 4, 8, 16, 32};
         else if (axis == 1) vals = {1, 2, 4, 8};   // rounds of kets (team and wave kernels)
@@ -1846,7 +1884,16 @@ int fk_autotune(fk_ctx *c, const double *D, unsigned flags, int reps, void *stre
             // block tasks switched, for the classes that take them
             bool any = false;
             for (const auto &q : c->qclasses) any = any || q.info.ket_outer > 0;
-            if (!any || opts.block_tasks != 0) break;
+            if (!any || opts.block_tasks != 0) continue;
+            vals = {-1};
+        } else if (axis == 5) {
+            // lanes per quartet: the other kernel, for the lane classes with a team alternative
+            bool any = false;
+            for (const auto &kv : cur) {
+                FkClassInfo info;
+                if (!fk_kernels_class_info(kv.first / NPC, kv.first % NPC, &info) && info.alt_team > 0) any = true;
+            }
+            if (!any) continue;
             vals = {-1};
         } else {
             // the other engine, for the classes that have both
@@ -1855,7 +1902,7 @@ int fk_autotune(fk_ctx *c, const double *D, unsigned flags, int reps, void *stre
                 FkClassInfo info;
                 if (!fk_kernels_class_info(kv.first / NPC, kv.first % NPC, &info) && info.hgp) any = true;
             }
-            if (!any) break;
+            if (!any) continue;
             vals = {-1};
         }
         for (double v : vals) {
@@ -1867,6 +1914,8 @@ int fk_autotune(fk_ctx *c, const double *D, unsigned flags, int reps, void *stre
                 if (axis == 0) kv.second.bb = (int)v;
                 else if (axis == 4) {
                     if (info.ket_outer > 0) kv.second.nobt = 1 - kv.second.nobt;
+                } else if (axis == 5) {
+                    if (info.alt_team > 0) kv.second.alt = 1 - kv.second.alt;
                 } else if (axis == 3) {
                     if (info.hgp) kv.second.eng = 1 - kv.second.eng;
                 } else if (axis == 1) {
@@ -1904,6 +1953,7 @@ int fk_autotune(fk_ctx *c, const double *D, unsigned flags, int reps, void *stre
             rep->grid_fraction[i] = sc.gf;
             rep->engine[i] = q.engine;
             rep->block_tasks[i] = sc.nobt ? 0 : 1;
+            rep->lanes_per_quartet[i] = q.info.wave_per_quartet == 0 ? 1 : (q.info.wave_per_quartet == 3 ? 64 : q.info.team_size);
             const auto s0 = start.find(q.P * NPC + q.Q);
             const fk_ctx::ClassSched sc0 = s0 == start.end() ? fk_ctx::ClassSched{} : s0->second;
             // compare the schedules in effect (a candidate equal to the default is no change)
@@ -1916,7 +1966,7 @@ int fk_autotune(fk_ctx *c, const double *D, unsigned flags, int reps, void *stre
             };
             rep->changed[i] =
                 (eff_bb(sc0) != eff_bb(sc) || eff_kt(sc0) != eff_kt(sc) || sc0.gf != sc.gf || sc0.eng != sc.eng ||
-                 (q.info.ket_outer > 0 && sc0.nobt != sc.nobt)) ? 1 : 0;
+                 (q.info.ket_outer > 0 && sc0.nobt != sc.nobt) || sc0.alt != sc.alt) ? 1 : 0;
             rep->ms_tuned[i] = launch1[i];
             for (size_t j = 0; j < keys0.size(); ++j)
                 if (keys0[j].P == q.P && keys0[j].Q == q.Q && keys0[j].prec == q.prec) rep->ms_default[i] = launch0[j];

@@ -92,6 +92,7 @@ struct FkJKArgs {
     int bra_slot;            // doubles per wave for the staged bra primitive records
     int prec;                // 0: FP64 kernel, 1: FP32 kernel of the precision split
     int engine;              // 0: Rys quadrature, 1: HGP with early contraction
+    int kind;                // kernel kind of the launch: the class's own, or 1 for a lane class's team alternative
     double tau_fp32;         // precision split (0: none): per bra and tile, the FP32
                              // launch takes the work when G_ab G_cd D_max < tau_fp32
     // K-block skip (K launches beside the J engine; null: off): per shell
@@ -152,6 +153,8 @@ struct FkClassInfo {
     int bra_block;           // largest bra block the class kernel takes per tile
     double flops_prim, flops_quartet;
     int ket_outer;           // bra block of the ket-outer loop order (0: bra-outer)
+    int alt_team;            // lane classes with a team-per-quartet alternative: its lanes per quartet (else 0)
+    int alt_bra_block;       // and the largest bra block of that kernel
     int hgp;                 // 1: the HGP engine is built for the class
     double flops_prim_hgp, flops_quartet_hgp;
 };
@@ -162,9 +165,9 @@ extern "C" {
 int fk_kernels_class_info(int P, int Q, FkClassInfo *info);
 int fk_kernels_launch_jk(int P, int Q, const FkJKArgs *args, int grid, void *stream);
 int fk_kernels_launch_debug(int P, int Q, const FkDebugArgs *args, void *stream);
-int fk_kernels_max_blocks(int P, int Q, int dyn_lds_bytes, int engine, int *blocks_per_cu);
+int fk_kernels_max_blocks(int P, int Q, int dyn_lds_bytes, int engine, int kind, int *blocks_per_cu);
 // dynamic LDS of a class launch; krow_ncol > 0 adds the block-task K rows
-int fk_kernels_jk_lds_bytes(int P, int Q, int bra_slot, int krow_ncol);
+int fk_kernels_jk_lds_bytes(int P, int Q, int bra_slot, int krow_ncol, int kind);
 int fk_kernels_launch_prep(const double *D, const double *bf_scale, const FkMolArgs *m, double *Ds, double *Dsh,
                            void *stream);
 int fk_kernels_launch_finalize(const double *XJ, const double *XK, long long xcopy, int ncopy, const double *bf_scale,

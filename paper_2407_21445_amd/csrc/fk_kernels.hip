@@ -36,6 +36,10 @@
 // team classes keep at most this many integrals per lane (MODE 1: NB NC ND,
 // MODE 2: NC ND); larger ones take a whole wave per quartet
 #define FK_TEAM_MAX_NOUT 80
+// lane-per-quartet classes with at least this many integrals (and a bra shell
+// of three or more components) also have a team-per-quartet kernel, one lane
+// per component of the first bra shell, which the schedule may choose
+#define FK_ALT_MIN_NOUT 18
 // lane-per-quartet classes up to this many integrals sum K[a,c], K[a,d] and
 // J[c,d] over a block of bras in registers; larger ones take one bra per tile
 #define FK_LPQ_BLOCK_NOUT 54
@@ -1341,6 +1345,9 @@ struct Disp {
     static constexpr bool WPQ = KIND == 3;
     // classes the HGP engine is built for: lane-per-quartet kernels up to L = 4
     static constexpr bool HGP = KIND == 0 && LA + LB + LC + LD <= FK_HGP_MAX_L;
+    // lane classes with a team-per-quartet alternative (MODE 1: a lane per a component)
+    static constexpr bool ALT = KIND == 0 && fk::QClass<LA, LB, LC, LD>::NOUT >= FK_ALT_MIN_NOUT &&
+                                fk::QClass<LA, LB, LC, LD>::NA >= 3;
     static void info(FkClassInfo *i)
     {
         using C = fk::QClass<LA, LB, LC, LD>;
@@ -1354,14 +1361,22 @@ struct Disp {
                        : ((KIND == 1 || KIND == 2) ? FK_TEAM_MAX_BLOCK : 1);
         i->team_size = KIND == 0 ? 1 : (KIND == 1 ? C::NA : (KIND == 2 ? C::NA * C::NB : 64));
         i->ket_outer = NBK;
+        i->alt_team = ALT ? C::NA : 0;
+        i->alt_bra_block = ALT ? FK_TEAM_MAX_BLOCK : 0;
         i->flops_prim = fk::flops_prim(LA, LB, LC, LD);
         i->flops_quartet = fk::flops_digest(LA, LB, LC, LD);
         i->hgp = HGP ? 1 : 0;
         i->flops_prim_hgp = HGP ? fk::hgp_flops_prim(LA, LB, LC, LD) : 0.0;
         i->flops_quartet_hgp = HGP ? fk::hgp_flops_hrr(LA, LB, LC, LD) + fk::flops_digest(LA, LB, LC, LD) : 0.0;
     }
-    static const void *jk_kernel(bool low = false, int eng = 0)
+    static const void *jk_kernel(bool low = false, int eng = 0, int kind = KIND)
     {
+        if constexpr (!BUILT) return nullptr;
+        else if constexpr (ALT) {
+            if (kind == 1)
+                return low ? (const void *)&k_jk_tpq<LA, LB, LC, LD, 1, float>
+                           : (const void *)&k_jk_tpq<LA, LB, LC, LD, 1, double>;
+        }
         if constexpr (!BUILT) return nullptr;
         else if constexpr (HGP) {
             if (eng == 1)
@@ -1375,8 +1390,13 @@ struct Disp {
                        : (const void *)&k_jk_tpq<LA, LB, LC, LD, KIND, double>;
         else return (const void *)&k_jk_wpq<LA, LB, LC, LD>;
     }
-    static int lds_bytes(int bra_slot, int krow_ncol)
+    static int lds_bytes(int bra_slot, int krow_ncol, int kind = KIND)
     {
+        if constexpr (ALT) {
+            if (kind == 1)
+                return (int)sizeof(double) *
+                       (rys_lds_size(fk::QClass<LA, LB, LC, LD>::NR) + FK_WAVES * TeamShape<LA, LB, LC, LD, 1>::RED);
+        }
         // the Rys segment, and per wave the team reductions (bra records are
         // read from memory by scalar loads: bra_slot needs no LDS); block
         // tasks add the block's K rows and X_J[a, b_j]
@@ -1395,9 +1415,24 @@ struct Disp {
     {
         if constexpr (!BUILT) return -2;
         else {
-            const int lds = lds_bytes(a->bra_slot, a->ntask > 0 ? a->krow_ncol : 0);
+            const int lds = lds_bytes(a->bra_slot, a->ntask > 0 ? a->krow_ncol : 0, a->kind);
             const bool low = a->prec == 1;
             const int eng = a->engine;
+            if (a->kind != KIND && !(ALT && a->kind == 1)) return -2;
+            if constexpr (ALT) {
+                if (a->kind == 1) {
+                    if (eng != 0) return -2;
+                    const void *kt = jk_kernel(low, 0, 1);
+                    static int raised_t[2] = {0, 0};
+                    if (lds > 65536 && lds > raised_t[low]) {
+                        if (hipFuncSetAttribute(kt, hipFuncAttributeMaxDynamicSharedMemorySize, lds) != hipSuccess) return -3;
+                        raised_t[low] = lds;
+                    }
+                    if (low) hipLaunchKernelGGL((k_jk_tpq<LA, LB, LC, LD, 1, float>), dim3(grid), dim3(FK_BLOCK), lds, st, *a);
+                    else hipLaunchKernelGGL((k_jk_tpq<LA, LB, LC, LD, 1, double>), dim3(grid), dim3(FK_BLOCK), lds, st, *a);
+                    return hipGetLastError() == hipSuccess ? 0 : -3;
+                }
+            }
             if (low && KIND == 3) return -2;  // f-f bras: FP64 only
             if (eng != 0 && !HGP) return -2;  // HGP only for the classes it is built for
             const void *k = jk_kernel(low, eng);
@@ -1579,21 +1614,22 @@ int host_q(int q, const int *o, const int *n, const double *ab, const double *pp
                       : host_q<P, Q + 1>(q, o, n, ab, pp, qs, nq, out, eng);
 }
 template <int P, int Q = 0>
-int lds_q(int q, int slot, int ncol)
+int lds_q(int q, int slot, int ncol, int kind)
 {
     if constexpr (Q > P) return -1;
-    else return q == Q ? Disp<P, Q>::lds_bytes(slot, ncol) : lds_q<P, Q + 1>(q, slot, ncol);
+    else return q == Q ? Disp<P, Q>::lds_bytes(slot, ncol, kind) : lds_q<P, Q + 1>(q, slot, ncol, kind);
 }
 template <int P, int Q = 0>
-const void *kern_q(int q, int eng)
+const void *kern_q(int q, int eng, int kind)
 {
     if constexpr (Q > P) return nullptr;
     else {
         if (q == Q) {
             if (eng != 0 && !Disp<P, Q>::HGP) return nullptr;
-            return Disp<P, Q>::jk_kernel(false, eng);
+            if (kind != Disp<P, Q>::KIND && !(Disp<P, Q>::ALT && kind == 1)) return nullptr;
+            return Disp<P, Q>::jk_kernel(false, eng, kind);
         }
-        return kern_q<P, Q + 1>(q, eng);
+        return kern_q<P, Q + 1>(q, eng, kind);
     }
 }
 
@@ -1849,8 +1885,8 @@ int FK_CAT(fk_kp, FK_ONLY_P, _host)(int Q, const int *o, const int *n, const dou
 {
     return host_q<FK_ONLY_P>(Q, o, n, ab, pp, qs, nq, out, eng);
 }
-const void *FK_CAT(fk_kp, FK_ONLY_P, _kern)(int Q, int eng) { return kern_q<FK_ONLY_P>(Q, eng); }
-int FK_CAT(fk_kp, FK_ONLY_P, _lds)(int Q, int slot, int ncol) { return lds_q<FK_ONLY_P>(Q, slot, ncol); }
+const void *FK_CAT(fk_kp, FK_ONLY_P, _kern)(int Q, int eng, int kind) { return kern_q<FK_ONLY_P>(Q, eng, kind); }
+int FK_CAT(fk_kp, FK_ONLY_P, _lds)(int Q, int slot, int ncol, int kind) { return lds_q<FK_ONLY_P>(Q, slot, ncol, kind); }
 }
 #else
 // ---- common translation unit: small kernels and the dispatch tables ----
@@ -1996,8 +2032,8 @@ __global__ void k_finalize(const double *__restrict XJ, const double *__restrict
     int fk_kp##P##_dbg(int, const FkDebugArgs *, void *);                                                    \
     int fk_kp##P##_host(int, const int *, const int *, const double *, const double *, const int *, int,    \
                         double *, int);                                                                      \
-    const void *fk_kp##P##_kern(int, int);                                                                   \
-    int fk_kp##P##_lds(int, int, int);
+    const void *fk_kp##P##_kern(int, int, int);                                                              \
+    int fk_kp##P##_lds(int, int, int, int);
 extern "C" {
 FK_DECL_P(0) FK_DECL_P(1) FK_DECL_P(2) FK_DECL_P(3) FK_DECL_P(4)
 FK_DECL_P(5) FK_DECL_P(6) FK_DECL_P(7) FK_DECL_P(8) FK_DECL_P(9)
@@ -2037,21 +2073,21 @@ int fk_kernels_debug_host(int P, int Q, const int *pair_ppoff, const int *pair_n
     return -1;
 }
 
-static const void *kern_of(int P, int Q, int engine)
+static const void *kern_of(int P, int Q, int engine, int kind)
 {
-    FK_SWITCH_P(P, kern(Q, engine))
+    FK_SWITCH_P(P, kern(Q, engine, kind))
     return nullptr;
 }
 
-int fk_kernels_jk_lds_bytes(int P, int Q, int bra_slot, int krow_ncol)
+int fk_kernels_jk_lds_bytes(int P, int Q, int bra_slot, int krow_ncol, int kind)
 {
-    FK_SWITCH_P(P, lds(Q, bra_slot, krow_ncol))
+    FK_SWITCH_P(P, lds(Q, bra_slot, krow_ncol, kind))
     return -1;
 }
 
-int fk_kernels_max_blocks(int P, int Q, int dyn_lds_bytes, int engine, int *blocks_per_cu)
+int fk_kernels_max_blocks(int P, int Q, int dyn_lds_bytes, int engine, int kind, int *blocks_per_cu)
 {
-    const void *k = kern_of(P, Q, engine);
+    const void *k = kern_of(P, Q, engine, kind);
     if (!k) return -2;
     int nb = 0;
     if (dyn_lds_bytes > 65536 &&

@@ -258,6 +258,27 @@ def test_block_tasks_on_and_off(fk, torch, c2):
     assert np.max(np.abs(res[True][1] - res[False][1])) <= 1e-12
 
 
+def test_team_alternative_of_lane_classes(fk, torch):
+    """Every lane class with a team alternative ((pp|ps), (ds|ps), (ds|pp),
+    (ds|ds), (dp|ss), (dp|ps), (dd|ss), (fs|ps), (fp|ss)) switched to it:
+    unscreened J and K of an s-f system still equal the oracle within 1e-10."""
+    s = _rand_sys(41, lmax=3, natom=4, kmax=2)
+    D = _rand_D(s["nbf"], 5)
+    alts = [((1, 1, 1, 0), 3), ((2, 0, 1, 0), 6), ((2, 0, 1, 1), 6), ((2, 0, 2, 0), 6), ((2, 1, 0, 0), 6),
+            ((2, 1, 1, 0), 6), ((2, 2, 0, 0), 6), ((3, 0, 1, 0), 10), ((3, 1, 0, 0), 10)]
+    c = fk.FockJK(0).set_system(s)
+    for cls, lanes in alts:
+        c.set_class_lanes(*cls, lanes)
+    c.build_quartets(tau=0.0)
+    st = {x["class"]: x["team_size"] for x in c.stats()["classes"]}
+    assert all(st[cls] == lanes for cls, lanes in alts if cls in st)
+    assert sum(cls in st for cls, _ in alts) >= 8
+    J, K = c.build_jk(torch.tensor(D, device="cuda:0"), sync=True)
+    Jo, Ko = oracle.jk(s, D)
+    assert np.max(np.abs(J.cpu().numpy() - Jo)) <= 1e-10
+    assert np.max(np.abs(K.cpu().numpy() - Ko)) <= 1e-10
+
+
 @pytest.fixture(scope="module")
 def c3():
     """(H2O)64 cc-pVDZ-type at full size with a seeded dense density of
@@ -499,7 +520,7 @@ def test_autotune_keeps_results(fk, torch):
     D = core_guess(T + V, orthogonalizer(S), s["nelec"] // 2)
     c = fk.FockJK(0).set_system(s).build_quartets(tau=0.0)
     rep = c.autotune(torch.tensor(D, device="cuda:0"), reps=1)
-    assert rep["configurations"] == 19 and len(rep["classes"]) == c.info()["nquartet_class"]
+    assert rep["configurations"] == 20 and len(rep["classes"]) == c.info()["nquartet_class"]
     assert all(r["ms_tuned"] > 0 and r["ms_default"] > 0 for r in rep["classes"])
     c.check_indices()
     J, K = c.build_jk(D)

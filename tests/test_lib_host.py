@@ -466,7 +466,7 @@ def test_schedule_cache_round_trip(tmp_path):
     a.save_schedules(p)
     text = open(p).read()
     assert "arch host" in text
-    assert "class 1 0 0 0 4 0 2 1 0" in text and "class 2 2 1 1 1 16 0.5 0 1" in text
+    assert "class 1 0 0 0 4 0 2 1 0 0" in text and "class 2 2 1 1 1 16 0.5 0 1 0" in text
     b = fk.FockJK(device=-1).set_system(s).load_schedules(p)
     p2 = str(tmp_path / "sched2.txt")
     b.save_schedules(p2)
@@ -490,7 +490,18 @@ def test_schedule_cache_round_trip(tmp_path):
     q.write_text("arch host\nclass 1 0 0 0 4 0 2 0\n")
     d = fk.FockJK(device=-1).set_system(s).load_schedules(str(q))
     d.save_schedules(p2)
-    assert "class 1 0 0 0 4 0 2 0 1" in open(p2).read()
+    assert "class 1 0 0 0 4 0 2 0 1 0" in open(p2).read()
+    # the team alternative of a lane class travels as its lanes per quartet
+    e = fk.FockJK(device=-1).set_system(s).set_class_lanes(2, 0, 1, 0, 6)
+    e.save_schedules(p2)
+    assert "class 2 0 1 0 0 0 1 0 1 6" in open(p2).read()
+    f = fk.FockJK(device=-1).set_system(s).load_schedules(p2)
+    f.save_schedules(str(tmp_path / "sched3.txt"))
+    assert open(str(tmp_path / "sched3.txt")).read() == open(p2).read()
+    q.write_text("arch host\nclass 2 0 1 0 0 0 1 0 1 3\n")
+    with pytest.raises(fk.FockJKError) as ex:
+        fk.FockJK(device=-1).set_system(s).load_schedules(str(q))
+    assert ex.value.code == fk.FK_ERR_UNSUPPORTED
 
 
 def test_class_kernel_choice():
@@ -545,6 +556,29 @@ def test_block_tasks_partition_the_ket_outer_tiles():
     one = fk.FockJK(device=-1).set_system(s).set_class_block_tasks(1, 0, 0, 0, False)
     st = {x["class"]: x["block_tasks"] for x in one.build_quartets(tau=1e-10, tau_prim=1e-12).stats()["classes"]}
     assert st[(1, 0, 0, 0)] == 0 and st[(0, 0, 0, 0)] > 0
+
+
+def test_class_lanes_select_the_team_alternative():
+    """fk_set_class_lanes: a lane class with a team alternative runs it with
+    one lane per component of its first bra shell (fk_stats team_size), over
+    the same quartets; lane counts a class has no kernel for are refused."""
+    s = wl.alkane_sys(2, "6-31gs-type")
+    base = {x["class"]: x for x in fk.FockJK(device=-1).set_system(s).build_quartets(tau=1e-10).stats()["classes"]}
+    c = fk.FockJK(device=-1).set_system(s)
+    for cls, lanes in (((2, 0, 1, 0), 6), ((1, 1, 1, 0), 3), ((2, 1, 0, 0), 6)):
+        c.set_class_lanes(*cls, lanes)
+    st = {x["class"]: x for x in c.build_quartets(tau=1e-10).stats()["classes"]}
+    assert st[(2, 0, 1, 0)]["team_size"] == 6 and st[(1, 1, 1, 0)]["team_size"] == 3
+    assert st[(2, 1, 0, 0)]["team_size"] == 6 and st[(1, 0, 0, 0)]["team_size"] == 1
+    for k, x in st.items():
+        assert x["quartets"] == base[k]["quartets"]
+    c.set_class_lanes(2, 0, 1, 0, 1)
+    assert {x["class"]: x for x in c.build_quartets(tau=1e-10).stats()["classes"]}[(2, 0, 1, 0)]["team_size"] == 1
+    for cls, lanes in (((1, 0, 0, 0), 3), ((2, 0, 1, 0), 3), ((1, 1, 1, 1), 1)):
+        with pytest.raises(fk.FockJKError) as e:
+            c.set_class_lanes(*cls, lanes)
+        assert e.value.code == fk.FK_ERR_UNSUPPORTED
+    c.set_class_lanes(1, 1, 1, 1, 3)  # a team class keeps its own kernel
 
 
 def test_screen_option_validation():
