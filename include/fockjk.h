@@ -106,12 +106,18 @@ typedef struct {
                           K_xy whose fitted density bound stays below tau_k are
                           skipped, see fk_density_bound; the paper uses 5e-6).
                           0 = no block skip */
-    int    block_tasks; /* ket-outer lane classes ((ss|ss), (ps|ss)): 0 = a
-                          workgroup takes all ket tiles of one bra block
-                          (a, b_1..b_m) at a time and sums X_K[b_j, x], X_K[a, x]
-                          and X_J[a, b_j] in LDS, which reaches memory once per
-                          block instead of once per tile and bra (used where the
-                          rows fit 64 KB of LDS with the class's other LDS);
+    int    block_tasks; /* lane classes: 0 = a workgroup takes all ket tiles of
+                          one bra block (a, b_1..b_m) at a time and sums
+                          X_K[b_j, x], X_K[a, x] and X_J[a, b_j] in LDS, which
+                          reaches memory once per block instead of once per tile
+                          and bra.  Used where the rows fit without costing
+                          waves per CU: the ket-outer classes ((ss|ss), (ps|ss))
+                          with four-wave workgroups, and, where the schedule
+                          asks for them (fk_set_class_block_tasks, the
+                          autotuner), the bra-outer (ps|ps), (pp|ss), (pp|ps),
+                          (ds|ss), (ds|ps), (dp|ss), (dp|ps) with eight-wave
+                          workgroups, the bra block lowered until the rows fit
+                          (fk_stats reports both);
                           -1 = every wave takes tiles on its own */
 } fk_screen_opts;
 
@@ -158,6 +164,8 @@ typedef struct {
     double  grid_fraction[FK_MAX_QCLASS];
     int64_t block_tasks[FK_MAX_QCLASS];   /* workgroup tasks of the class (fk_screen_opts
                                              .block_tasks), 0 if its waves take tiles */
+    int     waves_per_group[FK_MAX_QCLASS]; /* waves per workgroup of the launch (4, or 8 for
+                                             the bra-outer lane classes with block tasks) */
 } fk_stats_t;
 
 /* ---- context ---------------------------------------------------------- */
@@ -290,11 +298,13 @@ int fk_set_class_schedule(fk_ctx *ctx, int la, int lb, int lc, int ld, int bra_b
 int fk_set_class_engine(fk_ctx *ctx, int la, int lb, int lc, int ld, int engine);
 
 /* Block tasks per class (see fk_screen_opts.block_tasks, which turns them off
- * for every class): enable = 1 (the default) lets the class's workgroups take
- * whole bra blocks where the LDS rows fit, 0 keeps its waves on single tiles.
- * Takes effect at the next fk_build_quartets; FK_ERR_UNSUPPORTED for a class
- * not built.  Classes other than the ket-outer lane classes never take block
- * tasks, whatever is set. */
+ * for every class): enable = 1 lets the class's workgroups take whole bra
+ * blocks where the LDS rows fit, 0 keeps its waves on single tiles.  Without
+ * a call (or a schedule file) the ket-outer lane classes take them and the
+ * bra-outer ones do not.  Takes effect at the next fk_build_quartets;
+ * FK_ERR_UNSUPPORTED for a class not built.  Classes other than the lane
+ * classes listed at fk_screen_opts.block_tasks never take block tasks,
+ * whatever is set. */
 int fk_set_class_block_tasks(fk_ctx *ctx, int la, int lb, int lc, int ld, int enable);
 
 /* Lanes per quartet of a class's kernel.  Every class has its own kernel
@@ -316,7 +326,7 @@ int fk_set_class_lanes(fk_ctx *ctx, int la, int lb, int lc, int ld, int lanes);
  * ("class la lb lc ld bra_block kets_per_tile grid_fraction engine
  * block_tasks alt_lanes", alt_lanes 0 for the class's own kernel, else the
  * lanes per quartet of its team alternative; files without the last fields
- * read as block_tasks 1, alt_lanes 0) after a
+ * read as the class's default block tasks and alt_lanes 0) after a
  * line naming the device architecture ("arch gfx950"; "host" for a context
  * without a device).  fk_load_schedules reads such a file into the context,
  * on top of the schedules already set; FK_ERR_UNSUPPORTED if the file was

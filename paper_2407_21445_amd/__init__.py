@@ -60,7 +60,8 @@ class Stats(ctypes.Structure):
                 ("class_ms", ctypes.c_double * _Q), ("tiles", ctypes.c_int64 * _Q),
                 ("team_size", ctypes.c_int * _Q), ("precision", ctypes.c_int * _Q), ("prim_slots", ctypes.c_int64 * _Q),
                 ("engine", ctypes.c_int * _Q), ("bra_block", ctypes.c_int * _Q), ("kets_per_tile", ctypes.c_int * _Q),
-                ("grid_fraction", ctypes.c_double * _Q), ("block_tasks", ctypes.c_int64 * _Q)]
+                ("grid_fraction", ctypes.c_double * _Q), ("block_tasks", ctypes.c_int64 * _Q),
+                ("waves_per_group", ctypes.c_int * _Q)]
 
 
 class TuneReport(ctypes.Structure):
@@ -333,7 +334,7 @@ class FockJK:
                         "tiles": s.tiles[i], "team_size": s.team_size[i], "precision": s.precision[i],
                         "prim_slots": s.prim_slots[i], "engine": s.engine[i],
                         "schedule": [s.bra_block[i], s.kets_per_tile[i], s.grid_fraction[i]],
-                        "block_tasks": s.block_tasks[i]})
+                        "block_tasks": s.block_tasks[i], "waves_per_group": s.waves_per_group[i]})
         return {"classes": out, "flops_total": s.flops_total,
                 "quartets": sum(c["quartets"] for c in out), "prim_quartets": sum(c["prim_quartets"] for c in out)}
 

@@ -33,6 +33,8 @@ constexpr int ncart(int l) { return (l + 1) * (l + 2) / 2; }
 // block tasks run where the launch needs at most this much dynamic LDS (two
 // workgroups per CU)
 constexpr int kKrowLdsMax = 65536;
+// and with workgroups of eight waves (one workgroup per CU)
+constexpr int kKrowLdsMaxWide = 160 * 1024;
 inline int pair_class(int la, int lb) { return la * (la + 1) / 2 + lb; }
 // Hermite functions of total order up to L
 inline int nherm_host(int L) { return (L + 1) * (L + 2) * (L + 3) / 6; }
@@ -62,8 +64,10 @@ struct QuartetClass {
     int bra_slot;             // doubles per wave of staged bra primitive records
     int prec;                 // 0: FP64 launch, 1: FP32 launch of the precision split
     int engine = 0;           // 0: Rys quadrature, 1: HGP (classes with info.hgp only)
-    int64_t task_off = 0, ntask = 0;  // block tasks (ket-outer classes; 0: none)
+    int64_t task_off = 0, ntask = 0;  // block tasks (0: none)
     int krow_ncol = 0;        // LDS row length of the block tasks
+    int nw = 4;               // waves per workgroup of the launch
+    int krow_nbk = 0;         // bras per block of the block tasks' rows
     double flops_prim() const { return engine ? info.flops_prim_hgp : info.flops_prim; }
     double flops_quartet() const { return engine ? info.flops_quartet_hgp : info.flops_quartet; }
 };
@@ -149,8 +153,9 @@ struct fk_ctx {
     bool timed = false;
     std::vector<hipEvent_t> ev;  // 2 per quartet class
     // per quartet class schedule (key P * NPC + Q), from fk_set_class_schedule or fk_autotune
-    // nobt: no block tasks; alt: a lane class runs its team-per-quartet kernel
-    struct ClassSched { int bb = 0, kt = 0; double gf = 1.0; int eng = 0; int nobt = 0; int alt = 0; };
+    // bt: block tasks 1 on, 0 off, -1 the class's default (on for the ket-outer
+    // classes, off for the others); alt: a lane class runs its team-per-quartet kernel
+    struct ClassSched { int bb = 0, kt = 0; double gf = 1.0; int eng = 0; int bt = -1; int alt = 0; };
     std::map<int, ClassSched> sched;
     std::vector<double> oe_S, oe_T, oe_V;          // one-electron matrices of the current geometry and basis
     double dscreen_scale = 1.0;                   // per-quartet threshold = tau * this (builds from density changes)
@@ -504,7 +509,7 @@ int validate_lists(fk_ctx *c)
         if (qc.ntask == 0) continue;
         // tasks partition the class's tiles in order; each holds tiles of one
         // bra block; every ket's columns lie inside the LDS rows
-        if (qc.task_off < 0 || qc.task_off + qc.ntask > (int64_t)c->tasks.size() || qc.krow_ncol < 1)
+        if (qc.task_off < 0 || qc.task_off + qc.ntask > (int64_t)c->tasks.size() || qc.krow_ncol < 1 || qc.krow_nbk < 1)
             return fail(c, FK_ERR_STATE, "internal: block tasks of class (%d|%d)", qc.P, qc.Q);
         int64_t next = 0;
         const int lc = qc.info.lc, ld = qc.info.ld, nc = (lc + 1) * (lc + 2) / 2, nd = (ld + 1) * (ld + 2) / 2;
@@ -514,6 +519,8 @@ int validate_lists(fk_ctx *c)
                 return fail(c, FK_ERR_STATE, "internal: block task %lld is inconsistent", (long long)k);
             next = T.x + T.y;
             const int blk = c->tiles[qc.tile_off + T.x].blk;
+            if (c->blocks[blk].count > qc.krow_nbk)
+                return fail(c, FK_ERR_STATE, "internal: block task %lld has more bras than its rows", (long long)k);
             for (int i = T.x; i < T.x + T.y; ++i) {
                 const FkTile &tt = c->tiles[qc.tile_off + i];
                 if (tt.blk != blk) return fail(c, FK_ERR_STATE, "internal: block task %lld mixes bra blocks", (long long)k);
@@ -1004,7 +1011,46 @@ int fk_build_quartets(fk_ctx *c, const fk_screen_opts *o)
             std::vector<FkTile> tl;
             // bra blocks: the class's pairs ordered by (first shell, G descending),
             // cut into runs of at most bmax pairs with the same first shell
-            const int bmax = std::max(1, std::min(sch.bb > 0 ? std::min(sch.bb, FK_MAX_BRA_BLOCK) : bra_block, qc.info.bra_block));
+            int bmax = std::max(1, std::min(sch.bb > 0 ? std::min(sch.bb, FK_MAX_BRA_BLOCK) : bra_block, qc.info.bra_block));
+            // block tasks (fk_screen_opts.block_tasks): the lane classes whose K rows
+            // fit the LDS without costing waves per CU -- the ket-outer ones with
+            // their four-wave workgroups, the others with workgroups of eight
+            // waves (one Rys table for eight waves) and as many bras per block as
+            // fit; decided here, since it may lower the bra block
+            qc.krow_ncol = 0;
+            qc.nw = 4;
+            if (qc.info.wave_per_quartet == 0 && (qc.info.ket_outer > 0 || qc.info.wide > 0) &&
+                opts.block_tasks == 0 && (sch.bt < 0 ? qc.info.ket_outer > 0 : sch.bt != 0)) {
+                int ncol = 0;
+                for (int m = 0; m < c->nmol; ++m)
+                    ncol = std::max(ncol, c->krow_cnt[4 * m + qc.info.lc] +
+                                              (qc.info.lc != qc.info.ld ? c->krow_cnt[4 * m + qc.info.ld] : 0));
+                // waves per CU of a launch (0: the LDS does not fit); without a
+                // device the LDS bound alone decides
+                auto waves_cu = [&](int nw, int nbk, int nc) {
+                    const int lds = fk_kernels_jk_lds_bytes(P, Q, qc.bra_slot, nc, 0, nbk, nw);
+                    if (lds < 0 || lds > (nw == 4 ? kKrowLdsMax : kKrowLdsMaxWide)) return 0;
+                    if (!dev) return nw;
+                    int nb = 0;
+                    if (fk_kernels_max_blocks(P, Q, lds, qc.engine, 0, nw, &nb) != 0) return 0;
+                    return nb * nw;
+                };
+                const int w0 = dev ? waves_cu(4, bmax, 0) : 1;
+                if (ncol > 0 && w0 > 0) {
+                    if (qc.info.ket_outer > 0) {
+                        if (waves_cu(4, bmax, ncol) >= w0) qc.krow_ncol = ncol;
+                    } else if (qc.engine == 0) {
+                        for (int b = bmax; b >= 1; b = b / 2)
+                            if (waves_cu(qc.info.wide, b, ncol) >= w0) {
+                                qc.krow_ncol = ncol;
+                                qc.nw = qc.info.wide;
+                                bmax = b;
+                                break;
+                            }
+                    }
+                }
+            }
+            qc.krow_nbk = qc.krow_ncol > 0 ? bmax : 0;
             qc.bra_block = bmax;
             qc.kets_per_tile = tile_kets;
             std::vector<int> ord(LP.size());
@@ -1078,25 +1124,7 @@ int fk_build_quartets(fk_ctx *c, const fk_screen_opts *o)
             // block tasks: the tiles of one bra block, cut into chunks that share
             // the block's tiles round-robin (each a similar mix of costs),
             // largest chunks first; the class's tiles are stored in task order
-            qc.krow_ncol = 0;
             qc.ntask = 0;
-            if (qc.info.ket_outer > 0 && opts.block_tasks == 0 && !sch.nobt) {
-                int ncol = 0;
-                for (int m = 0; m < c->nmol; ++m)
-                    ncol = std::max(ncol, c->krow_cnt[4 * m + qc.info.lc] +
-                                              (qc.info.lc != qc.info.ld ? c->krow_cnt[4 * m + qc.info.ld] : 0));
-                // only where the rows cost no workgroups per CU (the LDS they take
-                // would otherwise lower the occupancy the registers allow)
-                const int kd = qc.info.wave_per_quartet;
-                if (ncol > 0 && fk_kernels_jk_lds_bytes(P, Q, qc.bra_slot, ncol, kd) <= kKrowLdsMax) {
-                    int nb0 = 0, nb1 = 0;
-                    const bool ok = !dev ||
-                        (fk_kernels_max_blocks(P, Q, fk_kernels_jk_lds_bytes(P, Q, qc.bra_slot, 0, kd), qc.engine, kd, &nb0) == 0 &&
-                         fk_kernels_max_blocks(P, Q, fk_kernels_jk_lds_bytes(P, Q, qc.bra_slot, ncol, kd), qc.engine, kd, &nb1) == 0 &&
-                         nb1 >= nb0);
-                    if (ok) qc.krow_ncol = ncol;
-                }
-            }
             if (qc.krow_ncol > 0) {
                 std::stable_sort(tl.begin(), tl.end(), [](const FkTile &x, const FkTile &y) { return x.blk < y.blk; });
                 const int64_t ch = std::max<int64_t>(16, std::min<int64_t>(256, (int64_t)tl.size() / 4096));
@@ -1143,8 +1171,8 @@ int fk_build_quartets(fk_ctx *c, const fk_screen_opts *o)
                 if (dev) {
                     int nb = 0;
                     const int lds = fk_kernels_jk_lds_bytes(P, Q, q.bra_slot, q.ntask > 0 ? q.krow_ncol : 0,
-                                                            q.info.wave_per_quartet);
-                    if (fk_kernels_max_blocks(P, Q, lds, q.engine, q.info.wave_per_quartet, &nb) == 0 && nb > 0)
+                                                            q.info.wave_per_quartet, q.krow_nbk, q.nw);
+                    if (fk_kernels_max_blocks(P, Q, lds, q.engine, q.info.wave_per_quartet, q.nw, &nb) == 0 && nb > 0)
                         q.blocks_per_cu = nb;
                 }
                 if ((int)c->qclasses.size() >= FK_MAX_QCLASS)
@@ -1528,6 +1556,8 @@ int build_jk_impl(fk_ctx *c, const double *D, double *J, double *K, unsigned fla
         a.tau_fp32 = twin ? c->opts.tau_fp32 : 0.0;
         a.engine = qc.engine;
         a.kind = qc.info.wave_per_quartet;
+        a.nw = qc.nw;
+        a.krow_nbk = qc.krow_nbk;
         a.blocks = c->d_blocks.p;
         a.blk_bra = c->d_blk_bra.p;
         a.blk_pos = c->d_blk_pos.p;
@@ -1636,6 +1666,7 @@ int fk_stats(fk_ctx *c, fk_stats_t *s)
         s->kets_per_tile[i] = q.kets_per_tile;
         s->grid_fraction[i] = q.grid_frac;
         s->block_tasks[i] = q.ntask;
+        s->waves_per_group[i] = q.nw;
         s->tiles[i] = q.ntile;
         s->team_size[i] = q.info.wave_per_quartet == 3 ? 64 : std::max(1, q.info.team_size);
         s->precision[i] = q.prec ? 32 : 64;
@@ -1677,7 +1708,7 @@ int fk_set_class_schedule(fk_ctx *c, int la, int lb, int lc, int ld, int bra_blo
         return fail(c, FK_ERR_ARG, "fk_set_class_schedule: bra_block 0..%d, kets_per_tile 0..64, grid_fraction (0, 4]",
                     FK_MAX_BRA_BLOCK);
     const fk_ctx::ClassSched old = c->sched.count(P * NPC + Q) ? c->sched[P * NPC + Q] : fk_ctx::ClassSched{};
-    c->sched[P * NPC + Q] = fk_ctx::ClassSched{bra_block, kets_per_tile, grid_fraction, old.eng, old.nobt, old.alt};
+    c->sched[P * NPC + Q] = fk_ctx::ClassSched{bra_block, kets_per_tile, grid_fraction, old.eng, old.bt, old.alt};
     return FK_OK;
 }
 
@@ -1710,7 +1741,7 @@ int fk_set_class_block_tasks(fk_ctx *c, int la, int lb, int lc, int ld, int enab
     FkClassInfo info;
     if (fk_kernels_class_info(P, Q, &info))
         return fail(c, FK_ERR_UNSUPPORTED, "fk_set_class_block_tasks: class (%d%d|%d%d) is not built", la, lb, lc, ld);
-    c->sched[P * NPC + Q].nobt = enable ? 0 : 1;
+    c->sched[P * NPC + Q].bt = enable ? 1 : 0;
     return FK_OK;
 }
 
@@ -1752,13 +1783,14 @@ int fk_save_schedules(fk_ctx *c, const char *path)
             l[2 * k + 1] = pc - pair_class(la, 0);
         }
         const auto &x = kv.second;
-        int alt_lanes = 0;
-        if (x.alt) {
-            FkClassInfo info;
-            if (!fk_kernels_class_info(kv.first / NPC, kv.first % NPC, &info)) alt_lanes = info.alt_team;
+        int alt_lanes = 0, bt = x.bt;
+        FkClassInfo info;
+        if (!fk_kernels_class_info(kv.first / NPC, kv.first % NPC, &info)) {
+            if (x.alt) alt_lanes = info.alt_team;
+            if (bt < 0) bt = info.ket_outer > 0 ? 1 : 0;
         }
         std::fprintf(f, "class %d %d %d %d %d %d %.17g %d %d %d\n", l[0], l[1], l[2], l[3], x.bb, x.kt, x.gf, x.eng,
-                     x.nobt ? 0 : 1, alt_lanes);
+                     bt < 0 ? 0 : bt, alt_lanes);
     }
     const bool ok = std::ferror(f) == 0;
     if (std::fclose(f) != 0 || !ok) return fail(c, FK_ERR_ARG, "fk_save_schedules: write error on %s", path);
@@ -1786,7 +1818,7 @@ int fk_load_schedules(fk_ctx *c, const char *path)
             if (c->arch != a) { rc = fail(c, FK_ERR_UNSUPPORTED, "fk_load_schedules: %s is for %s, the device is %s", path, a, c->arch.c_str()); break; }
             arch_ok = true;
         } else if (std::strcmp(word, "class") == 0) {
-            int la, lb, lc, ld, bb, kt, eng, bt = 1, al = 0;
+            int la, lb, lc, ld, bb, kt, eng, bt = -1, al = 0;
             double gf;
             const int nf = std::sscanf(line, "class %d %d %d %d %d %d %lf %d %d %d", &la, &lb, &lc, &ld, &bb, &kt, &gf, &eng,
                                        &bt, &al);
@@ -1797,7 +1829,7 @@ int fk_load_schedules(fk_ctx *c, const char *path)
             if (!arch_ok) { rc = fail(c, FK_ERR_ARG, "fk_load_schedules: %s: class line before the arch line", path); break; }
             if (la < lb || lc < ld || la > FK_MAX_L || lc > FK_MAX_L || lb < 0 || ld < 0 || bb < 0 ||
                 bb > FK_MAX_BRA_BLOCK || kt < 0 || kt > 64 || !(gf > 0 && gf <= 4) || (eng != 0 && eng != 1) ||
-                (bt != 0 && bt != 1)) {
+                (nf >= 9 && bt != 0 && bt != 1)) {
                 rc = fail(c, FK_ERR_ARG, "fk_load_schedules: %s:%d: value out of range", path, lineno);
                 break;
             }
@@ -1808,7 +1840,7 @@ int fk_load_schedules(fk_ctx *c, const char *path)
                 rc = fail(c, FK_ERR_UNSUPPORTED, "fk_load_schedules: %s:%d: class, engine or kernel not built", path, lineno);
                 break;
             }
-            sched[P * NPC + Q] = fk_ctx::ClassSched{bb, kt, gf, eng, bt ? 0 : 1, al ? 1 : 0};
+            sched[P * NPC + Q] = fk_ctx::ClassSched{bb, kt, gf, eng, bt, al ? 1 : 0};
         } else {
             rc = fail(c, FK_ERR_ARG, "fk_load_schedules: %s:%d: unknown record '%s'", path, lineno, word);
         }
@@ -1883,7 +1915,7 @@ int fk_autotune(fk_ctx *c, const double *D, unsigned flags, int reps, void *stre
         else if (axis == 4) {
             // block tasks switched, for the classes that take them
             bool any = false;
-            for (const auto &q : c->qclasses) any = any || q.info.ket_outer > 0;
+            for (const auto &q : c->qclasses) any = any || q.info.ket_outer > 0 || q.info.wide > 0;
             if (!any || opts.block_tasks != 0) continue;
             vals = {-1};
         } else if (axis == 5) {
@@ -1913,7 +1945,10 @@ int fk_autotune(fk_ctx *c, const double *D, unsigned flags, int reps, void *stre
                 if (fk_kernels_class_info(P, Q, &info)) continue;
                 if (axis == 0) kv.second.bb = (int)v;
                 else if (axis == 4) {
-                    if (info.ket_outer > 0) kv.second.nobt = 1 - kv.second.nobt;
+                    if (info.wave_per_quartet == 0 && (info.ket_outer > 0 || info.wide > 0)) {
+                        const int on = kv.second.bt < 0 ? (info.ket_outer > 0 ? 1 : 0) : kv.second.bt;
+                        kv.second.bt = 1 - on;
+                    }
                 } else if (axis == 5) {
                     if (info.alt_team > 0) kv.second.alt = 1 - kv.second.alt;
                 } else if (axis == 3) {
@@ -1952,7 +1987,7 @@ int fk_autotune(fk_ctx *c, const double *D, unsigned flags, int reps, void *stre
             rep->kets_per_tile[i] = q.info.wave_per_quartet == 0 ? 64 : (sc.kt > 0 ? sc.kt : 2 * (q.info.wave_per_quartet == 3 ? 1 : 64 / std::max(1, q.info.team_size)));
             rep->grid_fraction[i] = sc.gf;
             rep->engine[i] = q.engine;
-            rep->block_tasks[i] = sc.nobt ? 0 : 1;
+            rep->block_tasks[i] = q.ntask > 0 ? 1 : 0;
             rep->lanes_per_quartet[i] = q.info.wave_per_quartet == 0 ? 1 : (q.info.wave_per_quartet == 3 ? 64 : q.info.team_size);
             const auto s0 = start.find(q.P * NPC + q.Q);
             const fk_ctx::ClassSched sc0 = s0 == start.end() ? fk_ctx::ClassSched{} : s0->second;
@@ -1966,7 +2001,8 @@ int fk_autotune(fk_ctx *c, const double *D, unsigned flags, int reps, void *stre
             };
             rep->changed[i] =
                 (eff_bb(sc0) != eff_bb(sc) || eff_kt(sc0) != eff_kt(sc) || sc0.gf != sc.gf || sc0.eng != sc.eng ||
-                 (q.info.ket_outer > 0 && sc0.nobt != sc.nobt) || sc0.alt != sc.alt) ? 1 : 0;
+                 ((sc0.bt < 0 ? (q.info.ket_outer > 0 ? 1 : 0) : sc0.bt) !=
+                  (sc.bt < 0 ? (q.info.ket_outer > 0 ? 1 : 0) : sc.bt)) || sc0.alt != sc.alt) ? 1 : 0;
             rep->ms_tuned[i] = launch1[i];
             for (size_t j = 0; j < keys0.size(); ++j)
                 if (keys0[j].P == q.P && keys0[j].Q == q.Q && keys0[j].prec == q.prec) rep->ms_default[i] = launch0[j];

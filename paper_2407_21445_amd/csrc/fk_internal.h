@@ -93,6 +93,7 @@ struct FkJKArgs {
     int prec;                // 0: FP64 kernel, 1: FP32 kernel of the precision split
     int engine;              // 0: Rys quadrature, 1: HGP with early contraction
     int kind;                // kernel kind of the launch: the class's own, or 1 for a lane class's team alternative
+    int nw;                  // waves per workgroup of the launch (4; 8 for the wide lane kernels)
     double tau_fp32;         // precision split (0: none): per bra and tile, the FP32
                              // launch takes the work when G_ab G_cd D_max < tau_fp32
     // K-block skip (K launches beside the J engine; null: off): per shell
@@ -114,6 +115,7 @@ struct FkJKArgs {
     const int2 *tasks;
     int ntask;
     int krow_ncol;           // LDS row length: the class's largest column count over the molecules
+    int krow_nbk;            // bras per block the rows are laid out for (the class's bra block)
     const int *krow_col, *krow_cnt, *krow_off, *krow_fn;
 };
 
@@ -155,6 +157,7 @@ struct FkClassInfo {
     int ket_outer;           // bra block of the ket-outer loop order (0: bra-outer)
     int alt_team;            // lane classes with a team-per-quartet alternative: its lanes per quartet (else 0)
     int alt_bra_block;       // and the largest bra block of that kernel
+    int wide;                // waves per workgroup of a wider build of the lane kernel (0: none)
     int hgp;                 // 1: the HGP engine is built for the class
     double flops_prim_hgp, flops_quartet_hgp;
 };
@@ -165,9 +168,9 @@ extern "C" {
 int fk_kernels_class_info(int P, int Q, FkClassInfo *info);
 int fk_kernels_launch_jk(int P, int Q, const FkJKArgs *args, int grid, void *stream);
 int fk_kernels_launch_debug(int P, int Q, const FkDebugArgs *args, void *stream);
-int fk_kernels_max_blocks(int P, int Q, int dyn_lds_bytes, int engine, int kind, int *blocks_per_cu);
+int fk_kernels_max_blocks(int P, int Q, int dyn_lds_bytes, int engine, int kind, int nw, int *blocks_per_cu);
 // dynamic LDS of a class launch; krow_ncol > 0 adds the block-task K rows
-int fk_kernels_jk_lds_bytes(int P, int Q, int bra_slot, int krow_ncol, int kind);
+int fk_kernels_jk_lds_bytes(int P, int Q, int bra_slot, int krow_ncol, int kind, int nbk, int nw);
 int fk_kernels_launch_prep(const double *D, const double *bf_scale, const FkMolArgs *m, double *Ds, double *Dsh,
                            void *stream);
 int fk_kernels_launch_finalize(const double *XJ, const double *XK, long long xcopy, int ncopy, const double *bf_scale,

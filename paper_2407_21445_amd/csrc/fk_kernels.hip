@@ -522,9 +522,42 @@ struct LpqStage {
     static constexpr int value = 64 * (m3 > Q::NC * Q::ND ? m3 : Q::NC * Q::ND);
 };
 
-// ENG: the integral engine, 0 Rys quadrature, 1 HGP with early contraction
-template <int LA, int LB, int LC, int LD, typename R = double, int ENG = 0>
-__global__ void __launch_bounds__(FK_BLOCK, (LpqMinBlocks<LA, LB, LC, LD>::value)) k_jk_lpq(FkJKArgs a)
+// Doubles per wave of the stage with block tasks, where the K sums go to the
+// LDS rows and only X_J[c, d] passes through the stage (flush_sym<NC, ND>
+// uses it for blocks wider than one element)
+template <int LA, int LB, int LC, int LD>
+struct LpqStageTask {
+    using Q = fk::QClass<LA, LB, LC, LD>;
+    static constexpr int value = (Q::NC > 1 || Q::ND > 1) ? 64 * Q::NC * Q::ND : 0;
+};
+
+// Bra-outer lane classes built also with workgroups of eight waves: one Rys
+// table (2 or 3 roots: 34-50 KB of LDS) then serves eight waves, which leaves
+// room for the K rows of block tasks at the occupancy the registers allow
+// (two waves per SIMD: one workgroup of eight waves per CU)
+template <int LA, int LB, int LC, int LD>
+struct LpqWide {
+    static constexpr bool value = false;
+};
+template <> struct LpqWide<1, 0, 1, 0> { static constexpr bool value = true; };
+template <> struct LpqWide<1, 1, 0, 0> { static constexpr bool value = true; };
+template <> struct LpqWide<1, 1, 1, 0> { static constexpr bool value = true; };
+template <> struct LpqWide<2, 0, 0, 0> { static constexpr bool value = true; };
+template <> struct LpqWide<2, 0, 1, 0> { static constexpr bool value = true; };
+template <> struct LpqWide<2, 1, 0, 0> { static constexpr bool value = true; };
+template <> struct LpqWide<2, 1, 1, 0> { static constexpr bool value = true; };
+
+// workgroups per CU the launch bounds ask for with NW waves per workgroup (the
+// same waves per SIMD as LpqMinBlocks workgroups of four waves)
+template <int LA, int LB, int LC, int LD, int NW>
+struct LpqBounds {
+    static constexpr int value = (LpqMinBlocks<LA, LB, LC, LD>::value * FK_WAVES + NW - 1) / NW;
+};
+
+// ENG: the integral engine, 0 Rys quadrature, 1 HGP with early contraction;
+// NW: waves per workgroup
+template <int LA, int LB, int LC, int LD, typename R = double, int ENG = 0, int NW = FK_WAVES>
+__global__ void __launch_bounds__(64 * NW, (LpqBounds<LA, LB, LC, LD, NW>::value)) k_jk_lpq(FkJKArgs a)
 {
     using Q = fk::QClass<LA, LB, LC, LD>;
     constexpr int NA = Q::NA, NB = Q::NB, NC = Q::NC, ND = Q::ND, NOUT = Q::NOUT;
@@ -536,12 +569,19 @@ __global__ void __launch_bounds__(FK_BLOCK, (LpqMinBlocks<LA, LB, LC, LD>::value
 
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    double *s_stage = s_dyn + rys_lds_size(Q::NR) + wave * LpqStage<LA, LB, LC, LD>::value;
+    // the stage of each wave: its full size, or the X_J[c, d] part with block tasks
+    const int stg = a.ntask > 0 ? LpqStageTask<LA, LB, LC, LD>::value : LpqStage<LA, LB, LC, LD>::value;
+    double *s_stage = s_dyn + rys_lds_size(Q::NR) + wave * stg;
     unsigned long long cq = 0, cp = 0;
 
     constexpr int NBK = LpqKetOuter<LA, LB, LC, LD>::value;
+    // instantiations that take block tasks: the ket-outer ones and the wide ones
+    constexpr bool TASKS = NBK > 0 || NW > FK_WAVES;
+    // bras per block of the block tasks' rows (the class's bra block)
+    const int nbk = a.krow_nbk;
     // one tile (t) for this wave; kr: the workgroup's K rows of a block task, or null
     auto do_tile = [&](int t, double *kr) {
+        if constexpr (!TASKS) kr = nullptr;
         const FkTile tile = a.tiles[t];
         const bool same = (tile.grp & FK_TILE_SAME) != 0;
         const FkGroup g = a.groups[tile.grp & ~FK_TILE_SAME];
@@ -564,7 +604,7 @@ __global__ void __launch_bounds__(FK_BLOCK, (LpqMinBlocks<LA, LB, LC, LD>::value
         const int sa = a.pair_sa[a.blk_bra[blk.first]];
         const int oa = shbf[sa];
         int colc = 0, cold = 0;
-        if (NBK > 0 && kr) {
+        if (kr) {
             const int *kcol = a.krow_col + a.mol_sh0[mol];
             colc = kcol[sc];
             cold = kcol[sd] + (LC != LD ? a.krow_cnt[4 * mol + LC] : 0);
@@ -671,7 +711,7 @@ __global__ void __launch_bounds__(FK_BLOCK, (LpqMinBlocks<LA, LB, LC, LD>::value
                 lpq_digest<LA, LB, LC, LD, R>(acc, active, same && pos == bpos, sa, sb, sc, sd, oa, shbf[sb], oc,
                                               od, n, Ds, dcd, kac, kad, jcd, XJ, XK, s_stage, lane, wj, wk, any,
                                               kr ? kr + jb * NB * a.krow_ncol : nullptr, a.krow_ncol, colc, cold,
-                                              kr ? kr + (NBK * NB + NA) * a.krow_ncol + jb * NA * NB : nullptr);
+                                              kr ? kr + (nbk * NB + NA) * a.krow_ncol + jb * NA * NB : nullptr);
             }
         } else
         for (int jb = 0; jb < blk.count; ++jb) {
@@ -735,13 +775,15 @@ __global__ void __launch_bounds__(FK_BLOCK, (LpqMinBlocks<LA, LB, LC, LD>::value
             }
             const bool diag = same && pos == bpos;
             lpq_digest<LA, LB, LC, LD, R>(acc, active, diag, sa, sb, sc, sd, oa, shbf[sb], oc, od, n, Ds, dcd, kac,
-                                          kad, jcd, XJ, XK, s_stage, lane, wj, wk, any);
+                                          kad, jcd, XJ, XK, s_stage, lane, wj, wk, any,
+                                          kr ? kr + jb * NB * a.krow_ncol : nullptr, a.krow_ncol, colc, cold,
+                                          kr ? kr + (nbk * NB + NA) * a.krow_ncol + jb * NA * NB : nullptr);
         }
         // block sums: a lane without work holds zeros, which are not added
         if (__ballot(any) != 0ull) {
-            if (NBK > 0 && wk && kr) {
+            if (wk && kr) {
                 // X_K[a, c], X_K[a, d] into the block's a rows
-                double *kra = kr + NBK * NB * a.krow_ncol;
+                double *kra = kr + nbk * NB * a.krow_ncol;
 #pragma unroll
                 for (int o = 0; o < NA * NC; ++o)
                     if (kac[o] != 0.0) lds_add(&kra[(o / NC) * a.krow_ncol + colc + o % NC], kac[o]);
@@ -759,16 +801,16 @@ __global__ void __launch_bounds__(FK_BLOCK, (LpqMinBlocks<LA, LB, LC, LD>::value
             }
         }
     };
-    if (NBK > 0 && a.ntask > 0) {
+    if (TASKS && a.ntask > 0) {
         // block tasks: the K rows follow the table and the waves' stages
-        double *kr = s_dyn + rys_lds_size(Q::NR) + FK_WAVES * LpqStage<LA, LB, LC, LD>::value;
+        double *kr = s_dyn + rys_lds_size(Q::NR) + NW * stg;
         const int ncol = a.krow_ncol;
-        const int nkr = (NBK * NB + NA) * ncol + NBK * NA * NB;
+        const int nkr = (nbk * NB + NA) * ncol + nbk * NA * NB;
         for (int task = blockIdx.x; task < a.ntask; task += gridDim.x) {
             const int2 tk = a.tasks[task];
-            for (int i = threadIdx.x; i < nkr; i += FK_BLOCK) kr[i] = 0.0;
+            for (int i = threadIdx.x; i < nkr; i += 64 * NW) kr[i] = 0.0;
             __syncthreads();
-            for (int t = tk.x + wave; t < tk.x + tk.y; t += FK_WAVES) do_tile(t, kr);
+            for (int t = tk.x + wave; t < tk.x + tk.y; t += NW) do_tile(t, kr);
             __syncthreads();
             // the block's rows to memory: nonzero entries, consecutive threads
             // on consecutive columns of a row
@@ -786,9 +828,9 @@ __global__ void __launch_bounds__(FK_BLOCK, (LpqMinBlocks<LA, LB, LC, LD>::value
             if (wk) {
                 double *XK = a.XK + xoff;
                 const int nrow = blk.count * NB + NA;
-                for (int e = threadIdx.x; e < nrow * ncm; e += FK_BLOCK) {
+                for (int e = threadIdx.x; e < nrow * ncm; e += 64 * NW) {
                     const int r = e / ncm, x = e - r * ncm;
-                    const int rr = r < blk.count * NB ? r : NBK * NB + (r - blk.count * NB);
+                    const int rr = r < blk.count * NB ? r : nbk * NB + (r - blk.count * NB);
                     const double v = kr[rr * ncol + x];
                     if (v == 0.0) continue;
                     const int row = r < blk.count * NB ? shbf[a.pair_sb[a.blk_bra[blk.first + r / NB]]] + r % NB
@@ -799,8 +841,8 @@ __global__ void __launch_bounds__(FK_BLOCK, (LpqMinBlocks<LA, LB, LC, LD>::value
             }
             if (wj) {
                 double *XJ = a.XJ + xoff;
-                const double *kj = kr + (NBK * NB + NA) * ncol;
-                for (int e = threadIdx.x; e < blk.count * NA * NB; e += FK_BLOCK) {
+                const double *kj = kr + (nbk * NB + NA) * ncol;
+                for (int e = threadIdx.x; e < blk.count * NA * NB; e += 64 * NW) {
                     const double v = kj[e];
                     if (v == 0.0) continue;
                     const int jb = e / (NA * NB), ab = e % (NA * NB);
@@ -811,8 +853,8 @@ __global__ void __launch_bounds__(FK_BLOCK, (LpqMinBlocks<LA, LB, LC, LD>::value
             __syncthreads();
         }
     } else {
-        const int nwt = gridDim.x * FK_WAVES;
-        for (int t = blockIdx.x * FK_WAVES + wave; t < a.ntiles; t += nwt) do_tile(t, nullptr);
+        const int nwt = gridDim.x * NW;
+        for (int t = blockIdx.x * NW + wave; t < a.ntiles; t += nwt) do_tile(t, nullptr);
     }
     if (lane == 0 && cq) {
         atomicAdd(&a.counters[0], cq);
@@ -1348,6 +1390,8 @@ struct Disp {
     // lane classes with a team-per-quartet alternative (MODE 1: a lane per a component)
     static constexpr bool ALT = KIND == 0 && fk::QClass<LA, LB, LC, LD>::NOUT >= FK_ALT_MIN_NOUT &&
                                 fk::QClass<LA, LB, LC, LD>::NA >= 3;
+    // lane classes also built with workgroups of eight waves (Rys engine)
+    static constexpr bool WIDE = KIND == 0 && LpqWide<LA, LB, LC, LD>::value;
     static void info(FkClassInfo *i)
     {
         using C = fk::QClass<LA, LB, LC, LD>;
@@ -1363,14 +1407,21 @@ struct Disp {
         i->ket_outer = NBK;
         i->alt_team = ALT ? C::NA : 0;
         i->alt_bra_block = ALT ? FK_TEAM_MAX_BLOCK : 0;
+        i->wide = WIDE ? 2 * FK_WAVES : 0;
         i->flops_prim = fk::flops_prim(LA, LB, LC, LD);
         i->flops_quartet = fk::flops_digest(LA, LB, LC, LD);
         i->hgp = HGP ? 1 : 0;
         i->flops_prim_hgp = HGP ? fk::hgp_flops_prim(LA, LB, LC, LD) : 0.0;
         i->flops_quartet_hgp = HGP ? fk::hgp_flops_hrr(LA, LB, LC, LD) + fk::flops_digest(LA, LB, LC, LD) : 0.0;
     }
-    static const void *jk_kernel(bool low = false, int eng = 0, int kind = KIND)
+    static const void *jk_kernel(bool low = false, int eng = 0, int kind = KIND, int nw = FK_WAVES)
     {
+        if constexpr (!BUILT) return nullptr;
+        else if constexpr (WIDE) {
+            if (nw == 2 * FK_WAVES && kind == 0 && eng == 0)
+                return low ? (const void *)&k_jk_lpq<LA, LB, LC, LD, float, 0, 2 * FK_WAVES>
+                           : (const void *)&k_jk_lpq<LA, LB, LC, LD, double, 0, 2 * FK_WAVES>;
+        }
         if constexpr (!BUILT) return nullptr;
         else if constexpr (ALT) {
             if (kind == 1)
@@ -1390,7 +1441,7 @@ struct Disp {
                        : (const void *)&k_jk_tpq<LA, LB, LC, LD, KIND, double>;
         else return (const void *)&k_jk_wpq<LA, LB, LC, LD>;
     }
-    static int lds_bytes(int bra_slot, int krow_ncol, int kind = KIND)
+    static int lds_bytes(int bra_slot, int krow_ncol, int kind = KIND, int nbk = 0, int nw = FK_WAVES)
     {
         if constexpr (ALT) {
             if (kind == 1)
@@ -1403,22 +1454,40 @@ struct Disp {
         (void)bra_slot;
         using C = fk::QClass<LA, LB, LC, LD>;
         int extra = 0, rows = 0;
-        if constexpr (KIND == 0) extra = LpqStage<LA, LB, LC, LD>::value;
+        if constexpr (KIND == 0)
+            extra = krow_ncol > 0 ? LpqStageTask<LA, LB, LC, LD>::value : LpqStage<LA, LB, LC, LD>::value;
         if constexpr (KIND == 1 || KIND == 2) extra = TeamShape<LA, LB, LC, LD, KIND>::RED;
         if constexpr (KIND == 0) {
-            constexpr int NBK = LpqKetOuter<LA, LB, LC, LD>::value;
-            if (NBK > 0 && krow_ncol > 0) rows = (NBK * C::NB + C::NA) * krow_ncol + NBK * C::NA * C::NB;
+            if (krow_ncol > 0) rows = (nbk * C::NB + C::NA) * krow_ncol + nbk * C::NA * C::NB;
         }
-        return (int)sizeof(double) * (rys_lds_size(C::NR) + FK_WAVES * extra + rows);
+        return (int)sizeof(double) * (rys_lds_size(C::NR) + nw * extra + rows);
     }
     static int launch_jk(const FkJKArgs *a, int grid, hipStream_t st)
     {
         if constexpr (!BUILT) return -2;
         else {
-            const int lds = lds_bytes(a->bra_slot, a->ntask > 0 ? a->krow_ncol : 0, a->kind);
+            const int lds = lds_bytes(a->bra_slot, a->ntask > 0 ? a->krow_ncol : 0, a->kind, a->krow_nbk, a->nw);
             const bool low = a->prec == 1;
             const int eng = a->engine;
             if (a->kind != KIND && !(ALT && a->kind == 1)) return -2;
+            if (a->nw != FK_WAVES && !(WIDE && a->nw == 2 * FK_WAVES && a->kind == 0 && eng == 0)) return -2;
+            if constexpr (WIDE) {
+                if (a->nw == 2 * FK_WAVES) {
+                    const void *kw = jk_kernel(low, 0, 0, a->nw);
+                    static int raised_w[2] = {0, 0};
+                    if (lds > 65536 && lds > raised_w[low]) {
+                        if (hipFuncSetAttribute(kw, hipFuncAttributeMaxDynamicSharedMemorySize, lds) != hipSuccess) return -3;
+                        raised_w[low] = lds;
+                    }
+                    if (low)
+                        hipLaunchKernelGGL((k_jk_lpq<LA, LB, LC, LD, float, 0, 2 * FK_WAVES>), dim3(grid),
+                                           dim3(128 * FK_WAVES), lds, st, *a);
+                    else
+                        hipLaunchKernelGGL((k_jk_lpq<LA, LB, LC, LD, double, 0, 2 * FK_WAVES>), dim3(grid),
+                                           dim3(128 * FK_WAVES), lds, st, *a);
+                    return hipGetLastError() == hipSuccess ? 0 : -3;
+                }
+            }
             if constexpr (ALT) {
                 if (a->kind == 1) {
                     if (eng != 0) return -2;
@@ -1614,22 +1683,25 @@ int host_q(int q, const int *o, const int *n, const double *ab, const double *pp
                       : host_q<P, Q + 1>(q, o, n, ab, pp, qs, nq, out, eng);
 }
 template <int P, int Q = 0>
-int lds_q(int q, int slot, int ncol, int kind)
+int lds_q(int q, int slot, int ncol, int kind, int nbk, int nw)
 {
     if constexpr (Q > P) return -1;
-    else return q == Q ? Disp<P, Q>::lds_bytes(slot, ncol, kind) : lds_q<P, Q + 1>(q, slot, ncol, kind);
+    else
+        return q == Q ? Disp<P, Q>::lds_bytes(slot, ncol, kind, nbk, nw)
+                      : lds_q<P, Q + 1>(q, slot, ncol, kind, nbk, nw);
 }
 template <int P, int Q = 0>
-const void *kern_q(int q, int eng, int kind)
+const void *kern_q(int q, int eng, int kind, int nw)
 {
     if constexpr (Q > P) return nullptr;
     else {
         if (q == Q) {
             if (eng != 0 && !Disp<P, Q>::HGP) return nullptr;
             if (kind != Disp<P, Q>::KIND && !(Disp<P, Q>::ALT && kind == 1)) return nullptr;
-            return Disp<P, Q>::jk_kernel(false, eng, kind);
+            if (nw != FK_WAVES && !(Disp<P, Q>::WIDE && nw == 2 * FK_WAVES && kind == 0 && eng == 0)) return nullptr;
+            return Disp<P, Q>::jk_kernel(false, eng, kind, nw);
         }
-        return kern_q<P, Q + 1>(q, eng, kind);
+        return kern_q<P, Q + 1>(q, eng, kind, nw);
     }
 }
 
@@ -1885,8 +1957,14 @@ int FK_CAT(fk_kp, FK_ONLY_P, _host)(int Q, const int *o, const int *n, const dou
 {
     return host_q<FK_ONLY_P>(Q, o, n, ab, pp, qs, nq, out, eng);
 }
-const void *FK_CAT(fk_kp, FK_ONLY_P, _kern)(int Q, int eng, int kind) { return kern_q<FK_ONLY_P>(Q, eng, kind); }
-int FK_CAT(fk_kp, FK_ONLY_P, _lds)(int Q, int slot, int ncol, int kind) { return lds_q<FK_ONLY_P>(Q, slot, ncol, kind); }
+const void *FK_CAT(fk_kp, FK_ONLY_P, _kern)(int Q, int eng, int kind, int nw)
+{
+    return kern_q<FK_ONLY_P>(Q, eng, kind, nw);
+}
+int FK_CAT(fk_kp, FK_ONLY_P, _lds)(int Q, int slot, int ncol, int kind, int nbk, int nw)
+{
+    return lds_q<FK_ONLY_P>(Q, slot, ncol, kind, nbk, nw);
+}
 }
 #else
 // ---- common translation unit: small kernels and the dispatch tables ----
@@ -2032,8 +2110,8 @@ __global__ void k_finalize(const double *__restrict XJ, const double *__restrict
     int fk_kp##P##_dbg(int, const FkDebugArgs *, void *);                                                    \
     int fk_kp##P##_host(int, const int *, const int *, const double *, const double *, const int *, int,    \
                         double *, int);                                                                      \
-    const void *fk_kp##P##_kern(int, int, int);                                                              \
-    int fk_kp##P##_lds(int, int, int, int);
+    const void *fk_kp##P##_kern(int, int, int, int);                                                         \
+    int fk_kp##P##_lds(int, int, int, int, int, int);
 extern "C" {
 FK_DECL_P(0) FK_DECL_P(1) FK_DECL_P(2) FK_DECL_P(3) FK_DECL_P(4)
 FK_DECL_P(5) FK_DECL_P(6) FK_DECL_P(7) FK_DECL_P(8) FK_DECL_P(9)
@@ -2073,27 +2151,27 @@ int fk_kernels_debug_host(int P, int Q, const int *pair_ppoff, const int *pair_n
     return -1;
 }
 
-static const void *kern_of(int P, int Q, int engine, int kind)
+static const void *kern_of(int P, int Q, int engine, int kind, int nw)
 {
-    FK_SWITCH_P(P, kern(Q, engine, kind))
+    FK_SWITCH_P(P, kern(Q, engine, kind, nw))
     return nullptr;
 }
 
-int fk_kernels_jk_lds_bytes(int P, int Q, int bra_slot, int krow_ncol, int kind)
+int fk_kernels_jk_lds_bytes(int P, int Q, int bra_slot, int krow_ncol, int kind, int nbk, int nw)
 {
-    FK_SWITCH_P(P, lds(Q, bra_slot, krow_ncol, kind))
+    FK_SWITCH_P(P, lds(Q, bra_slot, krow_ncol, kind, nbk, nw))
     return -1;
 }
 
-int fk_kernels_max_blocks(int P, int Q, int dyn_lds_bytes, int engine, int kind, int *blocks_per_cu)
+int fk_kernels_max_blocks(int P, int Q, int dyn_lds_bytes, int engine, int kind, int nw, int *blocks_per_cu)
 {
-    const void *k = kern_of(P, Q, engine, kind);
+    const void *k = kern_of(P, Q, engine, kind, nw);
     if (!k) return -2;
     int nb = 0;
     if (dyn_lds_bytes > 65536 &&
         hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, dyn_lds_bytes) != hipSuccess)
         return -3;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k, FK_BLOCK, dyn_lds_bytes) != hipSuccess) return -3;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k, 64 * nw, dyn_lds_bytes) != hipSuccess) return -3;
     *blocks_per_cu = nb;
     return 0;
 }

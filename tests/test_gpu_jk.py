@@ -235,6 +235,29 @@ def test_jk_c20h42_sampled_blocks(fk, torch, c2, tau, tau_prim):
         assert np.max(np.abs(K[off[a]:off[a + 1], off[cc]:off[cc + 1]] - blk)) <= tol, (a, cc)
 
 
+def test_block_tasks_of_bra_outer_classes(fk, torch, c2):
+    """C20H42 unscreened with block tasks for every bra-outer lane class that
+    takes them (eight-wave workgroups, the bra block lowered until the K rows
+    fit): sampled blocks of J and K equal the oracle's within 1e-10."""
+    s, D = c2
+    wide = [(1, 0, 1, 0), (1, 1, 0, 0), (1, 1, 1, 0), (2, 0, 0, 0), (2, 0, 1, 0), (2, 1, 0, 0), (2, 1, 1, 0)]
+    c = fk.FockJK(0).set_system(s)
+    for w in wide:
+        c.set_class_block_tasks(*w, True).set_class_engine(*w, "rys")
+    c.build_quartets(tau=0.0)
+    st = {x["class"]: x for x in c.stats()["classes"]}
+    assert sum(st[w]["block_tasks"] > 0 and st[w]["waves_per_group"] == 8 for w in wide if w in st) >= 5
+    J, K = c.build_jk(torch.tensor(D, device="cuda:0"), sync=True)
+    J, K = J.cpu().numpy(), K.cpu().numpy()
+    off = oracle.bf_offsets(s)
+    jp, kp = _blocks(s, 5), _blocks(s, 6)
+    Jb, Kb = oracle.jk_blocks(s, D, jp, kp)
+    for (a, b), blk in zip(jp, Jb):
+        assert np.max(np.abs(J[off[a]:off[a + 1], off[b]:off[b + 1]] - blk)) <= 1e-10, (a, b)
+    for (a, cc), blk in zip(kp, Kb):
+        assert np.max(np.abs(K[off[a]:off[a + 1], off[cc]:off[cc + 1]] - blk)) <= 1e-10, (a, cc)
+
+
 def test_block_tasks_on_and_off(fk, torch, c2):
     """C20H42 unscreened, with and without block tasks (the (ps|ss) workgroups
     summing X_K[b_j, x], X_K[a, x] and X_J[a, b_j] of a bra block in LDS):

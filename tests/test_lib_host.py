@@ -466,7 +466,7 @@ def test_schedule_cache_round_trip(tmp_path):
     a.save_schedules(p)
     text = open(p).read()
     assert "arch host" in text
-    assert "class 1 0 0 0 4 0 2 1 0 0" in text and "class 2 2 1 1 1 16 0.5 0 1 0" in text
+    assert "class 1 0 0 0 4 0 2 1 0 0" in text and "class 2 2 1 1 1 16 0.5 0 0 0" in text
     b = fk.FockJK(device=-1).set_system(s).load_schedules(p)
     p2 = str(tmp_path / "sched2.txt")
     b.save_schedules(p2)
@@ -494,7 +494,7 @@ def test_schedule_cache_round_trip(tmp_path):
     # the team alternative of a lane class travels as its lanes per quartet
     e = fk.FockJK(device=-1).set_system(s).set_class_lanes(2, 0, 1, 0, 6)
     e.save_schedules(p2)
-    assert "class 2 0 1 0 0 0 1 0 1 6" in open(p2).read()
+    assert "class 2 0 1 0 0 0 1 0 0 6" in open(p2).read()
     f = fk.FockJK(device=-1).set_system(s).load_schedules(p2)
     f.save_schedules(str(tmp_path / "sched3.txt"))
     assert open(str(tmp_path / "sched3.txt")).read() == open(p2).read()
@@ -531,28 +531,43 @@ def test_class_kernel_choice():
     c.close()
 
 
-def test_block_tasks_partition_the_ket_outer_tiles():
-    """Block tasks (fk_screen_opts.block_tasks = 0): the (ss|ss) and (ps|ss)
-    tiles are regrouped so that each workgroup task holds tiles of one bra
-    block; the same tiles (count, quartets, primitive slots) as without them,
-    and the other classes are untouched.  fk_build_quartets checks the
-    partition and every ket's LDS row columns itself (validate_lists)."""
+def test_block_tasks_partition_the_tiles():
+    """Block tasks (fk_screen_opts.block_tasks = 0): the tiles of the ket-outer
+    lane classes ((ss|ss), (ps|ss): four-wave workgroups, the same tiles; on by
+    default) and of the bra-outer lane classes built for eight-wave workgroups
+    (on where the schedule asks; their bra block lowered until the K rows fit)
+    are regrouped so that each workgroup task holds tiles of one bra block; the
+    other classes are untouched.  fk_build_quartets checks the partition, the
+    bras per block against the rows and every ket's LDS row columns itself
+    (validate_lists).  Without a device the LDS bound alone decides."""
     s = wl.c20h42_631gs()
-    on = fk.FockJK(device=-1).set_system(s).build_quartets(tau=1e-10, tau_prim=1e-12).stats()["classes"]
+    wide = {(1, 0, 1, 0), (1, 1, 0, 0), (1, 1, 1, 0), (2, 0, 0, 0), (2, 0, 1, 0), (2, 1, 0, 0), (2, 1, 1, 0)}
+    dflt = {x["class"]: x for x in fk.FockJK(device=-1).set_system(s).build_quartets(
+        tau=1e-10, tau_prim=1e-12).stats()["classes"]}
+    assert all(x["block_tasks"] == 0 for k, x in dflt.items() if k in wide)
+    c = fk.FockJK(device=-1).set_system(s)
+    for w in wide:
+        c.set_class_block_tasks(*w, True)
+    on = c.build_quartets(tau=1e-10, tau_prim=1e-12).stats()["classes"]
     off = fk.FockJK(device=-1).set_system(s).build_quartets(tau=1e-10, tau_prim=1e-12,
                                                              block_tasks=False).stats()["classes"]
     assert len(on) == len(off)
+    ko = {(0, 0, 0, 0), (1, 0, 0, 0)}
     seen = set()
     for a, b in zip(on, off):
         assert a["class"] == b["class"]
-        assert (a["tiles"], a["prim_slots"]) == (b["tiles"], b["prim_slots"])
-        assert b["block_tasks"] == 0
-        if a["class"] in ((0, 0, 0, 0), (1, 0, 0, 0)):
-            assert 0 < a["block_tasks"] <= a["tiles"]
+        assert b["block_tasks"] == 0 and b["waves_per_group"] == 4
+        if a["class"] in ko:
+            assert 0 < a["block_tasks"] <= a["tiles"] and a["waves_per_group"] == 4
+            assert (a["tiles"], a["prim_slots"]) == (b["tiles"], b["prim_slots"])
+            seen.add(a["class"])
+        elif a["block_tasks"] > 0:
+            assert a["class"] in wide and a["waves_per_group"] == 8
+            assert a["schedule"][0] <= b["schedule"][0] and a["tiles"] >= b["tiles"]
             seen.add(a["class"])
         else:
-            assert a["block_tasks"] == 0
-    assert seen == {(0, 0, 0, 0), (1, 0, 0, 0)}
+            assert (a["tiles"], a["prim_slots"], a["waves_per_group"]) == (b["tiles"], b["prim_slots"], 4)
+    assert ko <= seen and len(seen & wide) >= 5
     one = fk.FockJK(device=-1).set_system(s).set_class_block_tasks(1, 0, 0, 0, False)
     st = {x["class"]: x["block_tasks"] for x in one.build_quartets(tau=1e-10, tau_prim=1e-12).stats()["classes"]}
     assert st[(1, 0, 0, 0)] == 0 and st[(0, 0, 0, 0)] > 0
