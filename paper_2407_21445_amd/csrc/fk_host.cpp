@@ -1107,9 +1107,11 @@ int fk_build_quartets(fk_ctx *c, const fk_screen_opts *o)
                         t.grp = (c->cls_group0[Q] + (int)gi) | ((P == Q) ? FK_TILE_SAME : 0);
                         tl.push_back(t);
                         // lane slots of the tile's primitive loops: rounds of
-                        // (quartets per wave) kets, 64 lanes each, for every bra
+                        // (quartets per wave) kets, 64 lanes each (a group of
+                        // waves per quartet for the wave kernels), for every bra
                         const int64_t rounds = (t.ket_count + qpw - 1) / qpw;
-                        qc.prim_slots += rounds * 64 * nppsum * gnpp;
+                        const int64_t lanes = qc.info.wave_per_quartet == 3 ? std::max(64, qc.info.team_size) : 64;
+                        qc.prim_slots += rounds * lanes * nppsum * gnpp;
                     }
                 }
                 i0 = i1;
@@ -1668,7 +1670,7 @@ int fk_stats(fk_ctx *c, fk_stats_t *s)
         s->block_tasks[i] = q.ntask;
         s->waves_per_group[i] = q.nw;
         s->tiles[i] = q.ntile;
-        s->team_size[i] = q.info.wave_per_quartet == 3 ? 64 : std::max(1, q.info.team_size);
+        s->team_size[i] = std::max(1, q.info.team_size);
         s->precision[i] = q.prec ? 32 : 64;
         s->prim_slots[i] = q.prim_slots;
         s->flops_total += s->prim_quartets[i] * q.flops_prim() + s->quartets[i] * q.flops_quartet();
@@ -1722,7 +1724,7 @@ int fk_set_class_lanes(fk_ctx *c, int la, int lb, int lc, int ld, int lanes)
     FkClassInfo info;
     if (fk_kernels_class_info(P, Q, &info))
         return fail(c, FK_ERR_UNSUPPORTED, "fk_set_class_lanes: class (%d%d|%d%d) is not built", la, lb, lc, ld);
-    const int own = info.wave_per_quartet == 0 ? 1 : (info.wave_per_quartet == 3 ? 64 : info.team_size);
+    const int own = info.wave_per_quartet == 0 ? 1 : info.team_size;
     if (lanes != own && !(info.alt_team > 0 && lanes == info.alt_team))
         return fail(c, FK_ERR_UNSUPPORTED, "fk_set_class_lanes: class (%d%d|%d%d) has no kernel with %d lanes per quartet",
                     la, lb, lc, ld, lanes);
@@ -1988,7 +1990,7 @@ int fk_autotune(fk_ctx *c, const double *D, unsigned flags, int reps, void *stre
             rep->grid_fraction[i] = sc.gf;
             rep->engine[i] = q.engine;
             rep->block_tasks[i] = q.ntask > 0 ? 1 : 0;
-            rep->lanes_per_quartet[i] = q.info.wave_per_quartet == 0 ? 1 : (q.info.wave_per_quartet == 3 ? 64 : q.info.team_size);
+            rep->lanes_per_quartet[i] = q.info.wave_per_quartet == 0 ? 1 : q.info.team_size;
             const auto s0 = start.find(q.P * NPC + q.Q);
             const fk_ctx::ClassSched sc0 = s0 == start.end() ? fk_ctx::ClassSched{} : s0->second;
             // compare the schedules in effect (a candidate equal to the default is no change)

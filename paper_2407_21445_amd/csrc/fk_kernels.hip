@@ -1107,16 +1107,28 @@ __global__ void __launch_bounds__(FK_BLOCK, (TpqMinBlocks<LA, LB, LC, LD>::value
 }
 
 // ---------------------------------------------------------------- wpq ----
-// One wave per contracted quartet; lane i owns bra component pairs i, i+64,
-// ... (each with every ket component).  Used when a bra component pair block
-// exceeds a wave (f-f bras).
+// SPLIT consecutive waves per contracted quartet (f-f bras, whose bra
+// component pairs exceed a wave): wave h of the group owns the bra component
+// pairs h CPW .. (h + 1) CPW - 1, CPW = ceil(NA NB / SPLIT), lane i of it pairs
+// i, i + 64, ... of that range (each with every ket component).  The waves of a
+// group repeat the quartet's set-up and each adds its own part of every
+// Fock block; two waves of 50 pairs instead of one wave of 64 + 36 hold half
+// the accumulators per lane.
+template <int LA, int LB, int LC, int LD>
+struct WpqSplit {
+    static constexpr int value = fk::QClass<LA, LB, LC, LD>::NA * fk::QClass<LA, LB, LC, LD>::NB > 64 ? 2 : 1;
+};
+
 template <int LA, int LB, int LC, int LD>
 __global__ void __launch_bounds__(FK_BLOCK) k_jk_wpq(FkJKArgs a)
 {
     using Q = fk::QClass<LA, LB, LC, LD>;
     constexpr int NB = Q::NB, NC = Q::NC, ND = Q::ND;
     constexpr int NAB = Q::NA * Q::NB, NCD = NC * ND;
-    constexpr int ITEMS = (NAB + 63) / 64;
+    constexpr int SPLIT = WpqSplit<LA, LB, LC, LD>::value;
+    static_assert(FK_WAVES % SPLIT == 0, "a wave group lies within a workgroup");
+    constexpr int CPW = (NAB + SPLIT - 1) / SPLIT;
+    constexpr int ITEMS = (CPW + 63) / 64;
     const bool wj = (a.want & FK_WANT_J) != 0, wk = (a.want & FK_WANT_K) != 0;
     FK_DYN_LDS(s_dyn);
     double *s_tab = s_dyn;
@@ -1124,22 +1136,23 @@ __global__ void __launch_bounds__(FK_BLOCK) k_jk_wpq(FkJKArgs a)
 
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int nwt = gridDim.x * FK_WAVES;
+    const int half = wave % SPLIT;                  // this wave's part of the group
+    const int nwt = gridDim.x * (FK_WAVES / SPLIT); // wave groups of the grid
     unsigned long long cq = 0, cp = 0;
 
     int iax[ITEMS][3], ibx[ITEMS][3], iab[ITEMS];
     bool ival[ITEMS];
 #pragma unroll
     for (int k = 0; k < ITEMS; ++k) {
-        const int it = lane + 64 * k;
-        ival[k] = it < NAB;
+        const int it = half * CPW + lane + 64 * k;
+        ival[k] = lane + 64 * k < CPW && it < NAB;
         const int ia = ival[k] ? it / NB : 0, ib = ival[k] ? it % NB : 0;
         iab[k] = ia * NB + ib;
         iax[k][0] = fk::kCart.x[LA][ia]; iax[k][1] = fk::kCart.y[LA][ia]; iax[k][2] = fk::kCart.z[LA][ia];
         ibx[k][0] = fk::kCart.x[LB][ib]; ibx[k][1] = fk::kCart.y[LB][ib]; ibx[k][2] = fk::kCart.z[LB][ib];
     }
 
-    for (int t = blockIdx.x * FK_WAVES + wave; t < a.ntiles; t += nwt) {
+    for (int t = blockIdx.x * (FK_WAVES / SPLIT) + wave / SPLIT; t < a.ntiles; t += nwt) {
         const FkTile tile = a.tiles[t];
         // team and wave kernels get blocks of one bra: the tile's kets are
         // exactly that bra's Schwarz prefix (and same-class triangle)
@@ -1176,8 +1189,10 @@ __global__ void __launch_bounds__(FK_BLOCK) k_jk_wpq(FkJKArgs a)
             const KetInfo Kt = load_ket(a, pos);
             const int sc = Kt.sc, sd = Kt.sd;
             const int r = pos - g.begin;
-            cq += 1;
-            cp += (unsigned long long)B.npp * g.npp;
+            if (half == 0) {
+                cq += 1;
+                cp += (unsigned long long)B.npp * g.npp;
+            }
             double acc[ITEMS][NCD];
 #pragma unroll
             for (int it = 0; it < ITEMS; ++it)
@@ -1403,7 +1418,7 @@ struct Disp {
         i->bra_block = NBK > 0 ? NBK
                        : (KIND == 0 && C::NOUT <= FK_LPQ_BLOCK_NOUT) ? FK_MAX_BRA_BLOCK
                        : ((KIND == 1 || KIND == 2) ? FK_TEAM_MAX_BLOCK : 1);
-        i->team_size = KIND == 0 ? 1 : (KIND == 1 ? C::NA : (KIND == 2 ? C::NA * C::NB : 64));
+        i->team_size = KIND == 0 ? 1 : (KIND == 1 ? C::NA : (KIND == 2 ? C::NA * C::NB : 64 * WpqSplit<LA, LB, LC, LD>::value));
         i->ket_outer = NBK;
         i->alt_team = ALT ? C::NA : 0;
         i->alt_bra_block = ALT ? FK_TEAM_MAX_BLOCK : 0;

@@ -509,7 +509,9 @@ def test_class_kernel_choice():
     integrals; above it a team of NA lanes while a lane keeps at most 80
     integrals (NB NC ND), else NA NB lanes (NC ND <= 80), else the whole wave.
     (pp|pp), (fs|ds) and (fd|ss) are team classes (measured faster than as
-    lane classes), (dp|ps) with 54 integrals a lane class."""
+    lane classes), (dp|ps) with 54 integrals a lane class; the wave classes
+    (more than 64 bra component pairs: f-f bras) split each quartet over two
+    waves (128 lanes)."""
     s = wl.organic_batch(1)
     c = fk.FockJK(device=-1).set_system(s).build_quartets(tau=1e-10)
     nc = [1, 3, 6, 10]
@@ -524,7 +526,7 @@ def test_class_kernel_choice():
         elif NA * NB <= 64 and NC * ND <= 80:
             want = NA * NB
         else:
-            want = 64
+            want = 64 if NA * NB <= 64 else 128
         assert ts == want, ((la, lb, lc, ld), ts, want)
     assert got[(1, 1, 1, 1)] == 3 and got[(3, 0, 2, 0)] == 10 and got[(3, 2, 0, 0)] == 10
     assert got[(2, 1, 1, 0)] == 1
