@@ -427,6 +427,15 @@ typedef struct {
     int    j_engine;     /* 1: every build of the run uses FK_J_ENGINE (J by the
                             J engine, K by the Rys kernels at fk_screen_opts
                             .tau_k).  Default 0 */
+    int    density_eig;  /* 1: each density from the eigenvectors of X F X
+                            (rocSOLVER, the nelec/2 lowest states) instead of
+                            purification.  Purification reaches the commutator
+                            criterion only where X F X is well conditioned: in
+                            a basis with overlap eigenvalues near 1e-5 its
+                            relative gap is small and the density's occupied-
+                            virtual mixing stays near 1e-7; the eigensolver
+                            density converges there.  Not with graph for
+                            fk_run_scf_batch.  Default 0 */
 } fk_scf_opts;
 
 typedef struct {
@@ -449,13 +458,15 @@ typedef struct {
  * X (FDS - SDF) X.  Every per-iteration matrix step runs on the device: the
  * orthogonaliser X = S^(-1/2) comes from a Newton-Schulz iteration, and the
  * density D = 2 X P X from trace-correcting purification of X F X (P the
- * projector onto the nelec/2 lowest states), so no eigensolver is used; the
+ * projector onto the nelec/2 lowest states), so no eigensolver is used
+ * (opts->density_eig = 1: P from rocSOLVER eigenvectors instead); the
  * host solves the small DIIS system.  Converged when |dE| < e_tol and the
  * error < g_tol.  D_inout (host, nbf x nbf, row-major) holds the guess when
  * opts->guess == 1 and the final density on return.  opts may be NULL
  * (defaults).  max_iter = 0 returns the initial density in D_inout and
  * performs no Fock build.  Returns FK_ERR_NOT_CONVERGED (with the result
- * filled) if max_iter is reached, or if the purification finds no gap. */
+ * filled) if max_iter is reached, or if the purification (or the
+ * eigensolver density) finds no gap. */
 int fk_run_scf(fk_ctx *ctx, const fk_scf_opts *opts, fk_scf_result *result, double *D_inout);
 
 /* Batched SCF (several molecules in one context, fk_set_molecules): the SCF
@@ -472,6 +483,7 @@ int fk_run_scf(fk_ctx *ctx, const fk_scf_opts *opts, fk_scf_result *result, doub
  * batch layout (fk_molecule_layout), the guess for guess = 1 and the final
  * densities on return.  guess = 3 starts from SAD (guess_used = 2): the
  * learned guess is per molecule.  max_iter = 0 returns the initial densities.
+ * graph = 1 with density_eig = 1: FK_ERR_UNSUPPORTED.
  * With the environment variable FK_SCF_LOG set (not "0") each iteration
  * prints one progress line to stderr. */
 int fk_run_scf_batch(fk_ctx *ctx, const fk_scf_opts *opts, fk_scf_result *results, double *D_inout);

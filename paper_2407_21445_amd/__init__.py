@@ -79,7 +79,7 @@ class ScfOpts(ctypes.Structure):
     _fields_ = [("max_iter", ctypes.c_int), ("e_tol", ctypes.c_double), ("g_tol", ctypes.c_double),
                 ("diis_n", ctypes.c_int), ("guess", ctypes.c_int), ("lindep", ctypes.c_double),
                 ("graph", ctypes.c_int), ("incremental", ctypes.c_int), ("canonical", ctypes.c_double),
-                ("j_engine", ctypes.c_int)]
+                ("j_engine", ctypes.c_int), ("density_eig", ctypes.c_int)]
 
 
 class ScfResult(ctypes.Structure):
@@ -347,7 +347,7 @@ class FockJK:
         return S, T, V, e.value
 
     def run_scf(self, D0=None, max_iter=100, e_tol=1e-10, g_tol=1e-8, diis_n=8, lindep=1e-8, guess=None,
-                graph=False, incremental=0, canonical=0.0, j_engine=False):
+                graph=False, incremental=0, canonical=0.0, j_engine=False, density_eig=False):
         """guess: GUESS_CORE (default without D0), GUESS_GIVEN (default with
         D0), GUESS_SAD or GUESS_LEARNED; max_iter=0 returns the initial
         density only; canonical > 0: canonical orthogonalisation dropping
@@ -357,7 +357,7 @@ class FockJK:
         if guess is None:
             guess = GUESS_CORE if D0 is None else GUESS_GIVEN
         o = ScfOpts(int(max_iter), float(e_tol), float(g_tol), int(diis_n), int(guess), float(lindep), int(bool(graph)),
-                    int(incremental), float(canonical), int(bool(j_engine)))
+                    int(incremental), float(canonical), int(bool(j_engine)), int(bool(density_eig)))
         r = ScfResult()
         rc = _lib.fk_run_scf(self._ctx, ctypes.byref(o), ctypes.byref(r), _ptr(D))
         if rc not in (FK_OK, FK_ERR_NOT_CONVERGED):
@@ -415,7 +415,7 @@ class FockJK:
                 "configurations": r.configurations}
 
     def run_scf_batch(self, D0=None, max_iter=100, e_tol=1e-10, g_tol=1e-8, diis_n=8, lindep=1e-8, guess=None,
-                      canonical=0.0, graph=False):
+                      canonical=0.0, graph=False, density_eig=False):
         """SCF of every molecule of a batch at once; returns (list of per-molecule
         result dicts, flat density array in the batch layout)."""
         nmol = self.info()["nmol"]
@@ -424,7 +424,7 @@ class FockJK:
         if guess is None:
             guess = GUESS_CORE if D0 is None else GUESS_GIVEN
         o = ScfOpts(int(max_iter), float(e_tol), float(g_tol), int(diis_n), int(guess), float(lindep), int(bool(graph)),
-                    0, float(canonical))
+                    0, float(canonical), 0, int(bool(density_eig)))
         rs = (ScfResult * nmol)()
         rc = _lib.fk_run_scf_batch(self._ctx, ctypes.byref(o), rs, _ptr(D))
         if rc not in (FK_OK, FK_ERR_NOT_CONVERGED):

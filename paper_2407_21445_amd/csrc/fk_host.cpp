@@ -2496,6 +2496,30 @@ int scf_purify(ScfWork &w, int nocc, int *steps)
     return FK_OK;
 }
 
+// Orthonormal density D' = 2 C_o C_o^T from the eigenvectors of the nocc
+// lowest states of the symmetric matrix in w.Fo (rocSOLVER); result in w.Do.
+int scf_density_eig(ScfWork &w, int nocc)
+{
+    const int n = w.n;
+    fk_ctx *c = w.c;
+    HIPCHK(c, hipMemcpyAsync(w.T1.p, w.Fo.p, (size_t)n * n * sizeof(double), hipMemcpyDeviceToDevice, w.st));
+    if (fk_scf_eigh(w.T1.p, w.ev.p, w.wk.p, w.info.p, n, w.st))
+        return fail(c, FK_ERR_HIP, "fk_run_scf: eigen-decomposition launch failed");
+    int info = 0;
+    std::vector<double> occ(n);
+    HIPCHK(c, hipMemcpy(&info, w.info.p, sizeof(int), hipMemcpyDeviceToHost));
+    HIPCHK(c, hipMemcpy(occ.data(), w.ev.p, n * sizeof(double), hipMemcpyDeviceToHost));
+    if (info != 0) return fail(c, FK_ERR_HIP, "fk_run_scf: eigen-decomposition of X F X failed (info %d)", info);
+    if (nocc < n && !(occ[nocc] > occ[nocc - 1]))
+        return fail(c, FK_ERR_NOT_CONVERGED, "fk_run_scf: no gap between the occupied and virtual states");
+    for (int k = 0; k < n; ++k) occ[k] = k < nocc ? 2.0 : 0.0;
+    HIPCHK(c, hipMemcpy(w.ev.p, occ.data(), n * sizeof(double), hipMemcpyHostToDevice));
+    // C diag(occ) C^T: rows of the row-major eigenvector matrix are the states
+    SCFCHK(w, fk_scf_eig_scale(w.T1.p, w.ev.p, w.T2.p, n, 1.0, 1.0, w.st));
+    SCFCHK(w, fk_scf_gemm(w.T2.p, w.T1.p, w.Do.p, n, 1.0, 0.0, w.st));
+    return FK_OK;
+}
+
 // Solves the Pulay system [B 1; 1 0] [c; l] = [0; 1] for m vectors (Gaussian
 // elimination with partial pivoting).  Returns false if singular.
 bool diis_solve(const std::vector<double> &B, int m, std::vector<double> &coef)
@@ -2544,10 +2568,11 @@ int fk_run_scf(fk_ctx *c, const fk_scf_opts *opts, fk_scf_result *result, double
     if (c->device < 0) return fail(c, FK_ERR_STATE, "fk_run_scf: context has no device");
     if (!c->have_quartets) return fail(c, FK_ERR_STATE, "fk_run_scf: call fk_build_quartets first");
     if (c->nmol > 1) return fail(c, FK_ERR_UNSUPPORTED, "fk_run_scf: one molecule per context (batches: one context each)");
-    fk_scf_opts o = {100, 1e-10, 1e-8, 8, 0, 1e-8, 0, 0, 0.0, 0};
+    fk_scf_opts o = {100, 1e-10, 1e-8, 8, 0, 1e-8, 0, 0, 0.0, 0, 0};
     if (opts) o = *opts;
     if (o.max_iter < 0 || o.diis_n < 0 || o.diis_n > 32 || !(o.e_tol > 0) || !(o.g_tol > 0) || !(o.lindep > 0) ||
         !(o.canonical >= 0 && o.canonical < 1) || (o.j_engine != 0 && o.j_engine != 1) ||
+        (o.density_eig != 0 && o.density_eig != 1) ||
         o.guess < 0 || o.guess > 3 || (o.graph != 0 && o.graph != 1) || o.incremental < 0 ||
         (o.graph && o.incremental))
         return fail(c, FK_ERR_ARG, "fk_run_scf: invalid options");
@@ -2603,6 +2628,11 @@ int fk_run_scf(fk_ctx *c, const fk_scf_opts *opts, fk_scf_result *result, double
     if ((rc = dev_upload(c, w.T3, S.data(), nn))) return rc;
     if ((rc = o.canonical > 0 ? scf_orthogonaliser_canonical(w, o.canonical) : scf_orthogonaliser(w, o.lindep))) return rc;
     result->ndropped = w.ndrop;
+    if (o.density_eig &&
+        ((rc = dev_upload<double>(c, w.ev, nullptr, n)) || (rc = dev_upload<double>(c, w.wk, nullptr, n)) ||
+         (rc = dev_upload<int>(c, w.info, nullptr, 1))))
+        return rc;
+    auto density = [&]() { return o.density_eig ? scf_density_eig(w, nocc) : scf_purify(w, nocc, nullptr); };
 
     // initial orthonormal density D' (w.Do); a learned or SAD guess that
     // cannot be formed falls back to SAD, then to the core Hamiltonian
@@ -2619,7 +2649,7 @@ int fk_run_scf(fk_ctx *c, const fk_scf_opts *opts, fk_scf_result *result, double
             SCFCHK(w, fk_scf_gemm(w.Xi.p, w.D.p, w.T3.p, n, 1.0, 0.0, w.st));
             SCFCHK(w, fk_scf_gemm(w.T3.p, w.Xi.p, w.Fo.p, n, -0.5, 0.0, w.st));
             rc = scf_shift_null(w);
-            if (!rc) rc = scf_purify(w, nocc, nullptr);
+            if (!rc) rc = density();
         }
         if (rc) gused = 2;
     }
@@ -2638,7 +2668,7 @@ int fk_run_scf(fk_ctx *c, const fk_scf_opts *opts, fk_scf_result *result, double
     if (gused == 0) {
         SCFCHK(w, fk_scf_gemm(w.X.p, w.h.p, w.T3.p, n, 1.0, 0.0, w.st));
         SCFCHK(w, fk_scf_gemm(w.T3.p, w.X.p, w.Fo.p, n, 1.0, 0.0, w.st));
-        if ((rc = scf_shift_null(w)) || (rc = scf_purify(w, nocc, nullptr))) return rc;
+        if ((rc = scf_shift_null(w)) || (rc = density())) return rc;
     } else if (gused == 1) {
         if ((rc = dev_upload(c, w.D, D_inout, nn))) return rc;
         SCFCHK(w, fk_scf_gemm(w.Xi.p, w.D.p, w.T3.p, n, 1.0, 0.0, w.st));
@@ -2774,7 +2804,7 @@ int fk_run_scf(fk_ctx *c, const fk_scf_opts *opts, fk_scf_result *result, double
             }
         }
         // new density: D' from F', D = X D' X
-        if ((rc = scf_purify(w, nocc, nullptr))) return rc;
+        if ((rc = density())) return rc;
         SCFCHK(w, fk_scf_gemm(w.X.p, w.Do.p, w.T3.p, n, 1.0, 0.0, w.st));
         SCFCHK(w, fk_scf_gemm(w.T3.p, w.X.p, w.D.p, n, 1.0, 0.0, w.st));
     }
@@ -3803,6 +3833,40 @@ int scfb_purify(ScfBatch &w, const std::vector<int> &nocc)
     return w.lincomb_u(w.Do.p, w.T1.p, nullptr, nullptr, 2.0, 0, 0, 0);
 }
 
+// Orthonormal densities D'_m = 2 C_o C_o^T from the eigenvectors of each
+// molecule's nocc_m lowest states of F'_m in Fo (rocSOLVER per molecule).
+int scfb_density_eig(ScfBatch &w, const std::vector<int> &nocc)
+{
+    fk_ctx *c = w.c;
+    const int nm = w.nmol;
+    int rc;
+    if ((rc = dev_upload<double>(c, w.ev, nullptr, w.nm)) || (rc = dev_upload<double>(c, w.wk, nullptr, w.nmax)) ||
+        (rc = dev_upload<int>(c, w.info, nullptr, nm)))
+        return rc;
+    HIPCHK(c, hipMemcpyAsync(w.T1.p, w.Fo.p, w.nm * sizeof(double), hipMemcpyDeviceToDevice, w.st));
+    for (int m = 0; m < nm; ++m)
+        if (fk_scf_eigh(w.T1.p + c->mol_base[m], w.ev.p + c->mol_base[m], w.wk.p, w.info.p + m, c->mol_nbf[m], w.st))
+            return fail(c, FK_ERR_HIP, "batched SCF: molecule %d: eigen-decomposition launch failed", m);
+    std::vector<int> info(nm);
+    std::vector<double> occ(w.nm);
+    HIPCHK(c, hipMemcpy(info.data(), w.info.p, nm * sizeof(int), hipMemcpyDeviceToHost));
+    HIPCHK(c, hipMemcpy(occ.data(), w.ev.p, w.nm * sizeof(double), hipMemcpyDeviceToHost));
+    for (int m = 0; m < nm; ++m) {
+        if (info[m] != 0) return fail(c, FK_ERR_HIP, "batched SCF: molecule %d: eigen-decomposition of X F X failed (info %d)", m, info[m]);
+        const int n = c->mol_nbf[m];
+        double *e = occ.data() + c->mol_base[m];
+        if (nocc[m] < n && !(e[nocc[m]] > e[nocc[m] - 1]))
+            return fail(c, FK_ERR_NOT_CONVERGED, "batched SCF: molecule %d: no gap between the occupied and virtual states", m);
+        for (int k = 0; k < n; ++k) e[k] = k < nocc[m] ? 2.0 : 0.0;
+    }
+    HIPCHK(c, hipMemcpy(w.ev.p, occ.data(), w.nm * sizeof(double), hipMemcpyHostToDevice));
+    for (int m = 0; m < nm; ++m)
+        if (fk_scf_eig_scale(w.T1.p + c->mol_base[m], w.ev.p + c->mol_base[m], w.T2.p + c->mol_base[m], c->mol_nbf[m], 1.0,
+                             1.0, w.st))
+            return fail(c, FK_ERR_HIP, "batched SCF: launch failed");
+    return w.gemm(w.T2.p, w.T1.p, w.Do.p);
+}
+
 // The batched SCF with every per-iteration decision on the device (the
 // convergence flags, the DIIS ring slot and Pulay solve, the purification's
 // choices with a fixed budget of steps, the density of converged molecules
@@ -3998,12 +4062,14 @@ extern "C" int fk_run_scf_batch(fk_ctx *c, const fk_scf_opts *opts, fk_scf_resul
     if (!c->have_quartets) return fail(c, FK_ERR_STATE, "fk_run_scf_batch: call fk_build_quartets first");
     const int nmol = c->nmol;
     std::memset(results, 0, sizeof(fk_scf_result) * (size_t)nmol);
-    fk_scf_opts o = {100, 1e-10, 1e-8, 8, 0, 1e-8, 0, 0, 0.0, 0};
+    fk_scf_opts o = {100, 1e-10, 1e-8, 8, 0, 1e-8, 0, 0, 0.0, 0, 0};
     if (opts) o = *opts;
     if (o.max_iter < 0 || o.diis_n < 0 || o.diis_n > 32 || !(o.e_tol > 0) || !(o.g_tol > 0) || !(o.lindep > 0) ||
         !(o.canonical >= 0 && o.canonical < 1) || o.j_engine != 0 || o.guess < 0 || o.guess > 3 ||
-        (o.graph != 0 && o.graph != 1) || o.incremental != 0)
+        (o.graph != 0 && o.graph != 1) || o.incremental != 0 || (o.density_eig != 0 && o.density_eig != 1))
         return fail(c, FK_ERR_ARG, "fk_run_scf_batch: invalid options");
+    if (o.graph && o.density_eig)
+        return fail(c, FK_ERR_UNSUPPORTED, "fk_run_scf_batch: the graph loop forms densities by purification only");
     if (c->charge != 0) return fail(c, FK_ERR_UNSUPPORTED, "fk_run_scf_batch: the molecules of a batch must be neutral");
     const auto t_start = std::chrono::steady_clock::now();
     hipSetDevice(c->device);
@@ -4084,7 +4150,7 @@ extern "C" int fk_run_scf_batch(fk_ctx *c, const fk_scf_opts *opts, fk_scf_resul
     }
     if (gused == 0) {
         if ((rc = w.gemm(w.X.p, w.h.p, w.T3.p)) || (rc = w.gemm(w.T3.p, w.X.p, w.Fo.p)) || (rc = scfb_shift_null(w)) ||
-            (rc = scfb_purify(w, nocc)))
+            (rc = o.density_eig ? scfb_density_eig(w, nocc) : scfb_purify(w, nocc)))
             return rc;
     } else {
         if ((rc = w.gemm(w.Xi.p, w.D.p, w.T3.p)) || (rc = w.gemm(w.T3.p, w.Xi.p, w.Do.p))) return rc;
@@ -4206,7 +4272,7 @@ extern "C" int fk_run_scf_batch(fk_ctx *c, const fk_scf_opts *opts, fk_scf_resul
         // new densities; frozen molecules keep theirs (D' and D: keep = 1)
         HIPCHK(c, hipMemcpyAsync(w.G.p, w.Do.p, nmat * sizeof(double), hipMemcpyDeviceToDevice, w.st));
         HIPCHK(c, hipMemcpyAsync(w.E.p, w.D.p, nmat * sizeof(double), hipMemcpyDeviceToDevice, w.st));
-        if ((rc = scfb_purify(w, nocc))) return rc;
+        if ((rc = o.density_eig ? scfb_density_eig(w, nocc) : scfb_purify(w, nocc))) return rc;
         if ((rc = w.gemm(w.X.p, w.Do.p, w.T3.p)) || (rc = w.gemm(w.T3.p, w.X.p, w.D.p))) return rc;
         if (std::find(conv.begin(), conv.end(), 1) != conv.end()) {
             std::vector<double> cf(4 * (size_t)nmol, 0.0);

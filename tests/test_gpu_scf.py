@@ -334,3 +334,90 @@ def test_scf_c20h42_matches_oracle_golden(fk):
     r2 = c.run_scf()
     assert r2["converged"]
     assert abs(r2["energy"] - gold["E_total"]) <= 1e-7, (r2["energy"], gold["E_total"])
+
+
+@pytest.mark.parametrize("name", ["water4_sto3g", "c2h6_631gs"])
+def test_scf_density_eig_matches_oracle(fk, name):
+    """density_eig = 1 (densities from rocSOLVER eigenvectors of X F X):
+    the oracle's energy within 1e-8 Eh and its density within 1e-5, with the
+    plain and the canonical orthogonaliser."""
+    s = wl.water4_sto3g() if name == "water4_sto3g" else wl.alkane_sys(2, "6-31gs-type")
+    ref = run_scf(s)
+    for canonical in (0.0, 1e-6):
+        r, _ = _gpu_scf(fk, s, density_eig=True, canonical=canonical)
+        assert r["converged"]
+        assert abs(r["energy"] - ref["E"]) <= 1e-8, (canonical, r["energy"], ref["E"])
+        assert np.max(np.abs(r["D"] - ref["D"])) <= 1e-5
+
+
+def test_scf_density_eig_c20h42_golden(fk):
+    """C20H42 / 6-31G*-type with eigensolver densities: the oracle's stored
+    SCF energy within 1e-8 Eh (unscreened, core guess)."""
+    with open(os.path.join(HERE, "golden", "c20h42_631gs_scf.json")) as f:
+        gold = json.load(f)
+    r, _ = _gpu_scf(fk, wl.c20h42_631gs(), tau=0.0, density_eig=True)
+    assert r["converged"]
+    assert abs(r["energy"] - gold["E_total"]) <= 1e-8, (r["energy"], gold["E_total"])
+
+
+def _commutator(D, F, S):
+    w, U = np.linalg.eigh(S)
+    X = U @ np.diag(w ** -0.5) @ U.T
+    return np.max(np.abs(X @ (F @ D @ S - S @ D @ F) @ X))
+
+
+def test_scf_density_eig_ill_conditioned_basis(fk):
+    """The first molecule of the seeded organic set (10 heavy atoms, TZVP-type
+    with f shells, 450 functions, smallest overlap eigenvalue near 1e-5):
+    with eigensolver densities the SCF meets the default criteria
+    (|dE| < 1e-10, commutator < 1e-8) at the benchmark's screening.  No oracle
+    SCF is affordable at this size; the checks are the properties of a
+    converged closed-shell density: electron count, idempotency in the S
+    metric, a commutator of the returned D with F = h + J - K/2 (J, K from a
+    fresh build of D) below the criterion, and the aufbau order (the nelec/2
+    lowest states of X F X are the occupied ones)."""
+    from synth import geometry as geom
+    s = wl.make_system(geom.organic(wl.SEED + 40), "tzvp-type")
+    assert s["nbf"] == 450
+    c = fk.FockJK(0).set_system(s).build_quartets(tau=1e-10, tau_prim=1e-12)
+    r = c.run_scf(guess=fk.GUESS_SAD, density_eig=True)
+    assert r["converged"], (r["iterations"], r["error"])
+    D = r["D"]
+    S, T, V, _ = c.one_electron()
+    assert np.linalg.eigvalsh(S)[0] < 1e-4
+    assert abs(np.trace(D @ S) - s["nelec"]) <= 1e-8
+    DS = D @ S
+    assert np.max(np.abs(DS @ DS - 2 * DS)) <= 1e-7
+    J, K = c.build_jk(D)
+    F = T + V + J - 0.5 * K
+    assert _commutator(D, F, S) <= 2e-8
+    w, U = np.linalg.eigh(S)
+    X = U @ np.diag(w ** -0.5) @ U.T
+    eps, C = np.linalg.eigh(X @ F @ X)
+    no = s["nelec"] // 2
+    assert eps[no] - eps[no - 1] > 0.1
+    Dq = 2 * (X @ C[:, :no]) @ (X @ C[:, :no]).T
+    assert np.max(np.abs(Dq - D)) <= 1e-5
+    E = 0.5 * np.sum(D * (T + V + F)) + r["e_nuc"]
+    assert abs(E - r["energy"]) <= 1e-8
+
+
+def test_batched_scf_density_eig(fk):
+    """Batched SCF with eigensolver densities: each molecule's energy equals
+    its own single-molecule SCF (1e-8 Eh) and the oracle's where cheap; the
+    graph loop refuses the option."""
+    mols = _neutral_batch()
+    b = wl.batch(mols)
+    c = fk.FockJK(0).set_system(b).set_molecules(b["atom_mol"]).build_quartets(tau=0.0)
+    rs, D = c.run_scf_batch(guess=fk.GUESS_SAD, density_eig=True)
+    nbf, off = c.molecule_layout()
+    for m, s in enumerate(mols):
+        r = fk.FockJK(0).set_system(s).build_quartets(tau=0.0).run_scf(guess=fk.GUESS_SAD)
+        assert rs[m]["converged"]
+        assert abs(rs[m]["energy"] - r["energy"]) <= 1e-8, (m, rs[m]["energy"], r["energy"])
+        assert np.max(np.abs(D[off[m]:off[m + 1]].reshape(nbf[m], nbf[m]) - r["D"])) <= 1e-5
+    for m in (0, 1):
+        assert abs(rs[m]["energy"] - run_scf(mols[m])["E"]) <= 1e-8
+    with pytest.raises(fk.FockJKError) as e:
+        c.run_scf_batch(graph=True, density_eig=True)
+    assert e.value.code == fk.FK_ERR_UNSUPPORTED
