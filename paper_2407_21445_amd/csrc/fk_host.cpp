@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <functional>
 #include <array>
 #include <atomic>
 #include <chrono>
@@ -12,6 +13,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <unordered_map>
 #include <map>
 #include <mutex>
 #include <numeric>
@@ -451,6 +453,107 @@ void prune_primitives(fk_ctx *c, double tau_prim)
 // Every index a J/K kernel dereferences, checked on the host before upload:
 // tiles -> pairs, groups and list positions; groups -> transposed records;
 // pairs -> shells and primitive records; shells -> basis-function offsets.
+// XCD-aware order of a lane-per-quartet class's work.  Workgroup g runs on
+// XCD g mod 8, whose L2 (4 MB) serves only that XCD.  The class's bra blocks
+// are cut into eight regions of equal cost by recursive bisection of the
+// first bra shell's position, and the work items (tiles, or block tasks) are
+// placed so that the workgroups of XCD x take region x: the density blocks
+// its digestion reads (D_ac, D_ad, D_bc, D_bd) then come from one region's
+// rows.  The order within a region stays cost-descending.  Used where the
+// density is larger than one L2 (n > 724: n^2 doubles above 4 MB) and the
+// context holds one molecule; smaller systems keep the cost order, which
+// balances better.
+void order_for_xcds(fk_ctx *c, const QuartetClass &q)
+{
+    constexpr int NX = 8;
+    if (c->nmol != 1 || (int64_t)c->nbf * c->nbf * 8 <= (4 << 20) || q.info.wave_per_quartet != 0 ||
+        q.ntile < 64 * NX)
+        return;
+    const bool tasks = q.ntask > 0;
+    const int64_t nitem = tasks ? q.ntask : q.ntile;
+    const int64_t wgs = tasks ? q.ntask : (q.ntile + 3) / 4;
+    const int64_t cap = std::max<int64_t>(1, (int64_t)(q.grid_frac * std::max(8, q.blocks_per_cu) * std::max(c->ncu, 1)));
+    const int64_t G = std::max<int64_t>(1, std::min(wgs, cap));
+    if (G < NX) return;
+    const int NWT = q.nw;  // waves per workgroup of the strided tile loop
+    auto item_blk = [&](int64_t i) {
+        return tasks ? c->tiles[q.tile_off + c->tasks[q.task_off + i].x].blk : c->tiles[q.tile_off + i].blk;
+    };
+    auto item_cost = [&](int64_t i) {
+        auto tc = [&](const FkTile &t) {
+            return (double)c->blk_nppsum[t.blk] * c->groups[t.grp & ~FK_TILE_SAME].npp * t.ket_count;
+        };
+        if (!tasks) return tc(c->tiles[q.tile_off + i]);
+        const int2 tk = c->tasks[q.task_off + i];
+        double s = 0;
+        for (int k = tk.x; k < tk.x + tk.y; ++k) s += tc(c->tiles[q.tile_off + k]);
+        return s;
+    };
+    // cost and position of every bra block of the class
+    std::unordered_map<int, double> bcost;
+    for (int64_t i = 0; i < nitem; ++i) bcost[item_blk(i)] += item_cost(i);
+    std::vector<int> blks;
+    for (const auto &kv : bcost) blks.push_back(kv.first);
+    std::sort(blks.begin(), blks.end());
+    auto centre = [&](int b, int k) {
+        const int sa = c->pr_sa[c->blk_bra[c->blocks[b].first]];
+        return c->xyz[3 * c->sh_atom[sa] + k];
+    };
+    std::unordered_map<int, int> region;
+    std::function<void(std::vector<int> &, int, int)> cut = [&](std::vector<int> &v, int r0, int nr) {
+        if (nr == 1 || v.size() <= 1) {
+            for (int b : v) region[b] = r0;
+            return;
+        }
+        int ax = 0;
+        double best = -1;
+        for (int k = 0; k < 3; ++k) {
+            double lo = 1e300, hi = -1e300;
+            for (int b : v) { lo = std::min(lo, centre(b, k)); hi = std::max(hi, centre(b, k)); }
+            if (hi - lo > best) { best = hi - lo; ax = k; }
+        }
+        std::stable_sort(v.begin(), v.end(), [&](int x, int y) { return centre(x, ax) < centre(y, ax); });
+        double tot = 0, acc = 0;
+        for (int b : v) tot += bcost[b];
+        size_t m = 0;
+        while (m < v.size() && acc + 0.5 * bcost[v[m]] < 0.5 * tot) acc += bcost[v[m++]];
+        std::vector<int> lo(v.begin(), v.begin() + m), hi(v.begin() + m, v.end());
+        cut(lo, r0, nr / 2);
+        cut(hi, r0 + nr / 2, nr - nr / 2);
+    };
+    cut(blks, 0, NX);
+    // queues per region, in the present (cost-descending) order
+    std::vector<std::vector<int64_t>> qu(NX);
+    for (int64_t i = 0; i < nitem; ++i) qu[region[item_blk(i)]].push_back(i);
+    std::vector<size_t> head(NX, 0);
+    std::vector<int64_t> order(nitem);
+    for (int64_t p = 0; p < nitem; ++p) {
+        const int64_t g = tasks ? p % G : (p % (G * NWT)) / NWT;
+        int x = (int)(g % NX);
+        if (head[x] == qu[x].size()) {
+            size_t most = 0;
+            for (int y = 0; y < NX; ++y)
+                if (qu[y].size() - head[y] > most) { most = qu[y].size() - head[y]; x = y; }
+        }
+        order[p] = qu[x][head[x]++];
+    }
+    if (tasks) {
+        // tasks keep partitioning the tiles in order: their tiles move with them
+        std::vector<int2> tk(c->tasks.begin() + q.task_off, c->tasks.begin() + q.task_off + nitem);
+        std::vector<FkTile> tl(c->tiles.begin() + q.tile_off, c->tiles.begin() + q.tile_off + q.ntile);
+        int x = 0;
+        for (int64_t p = 0; p < nitem; ++p) {
+            const int2 t = tk[order[p]];
+            std::copy(tl.begin() + t.x, tl.begin() + t.x + t.y, c->tiles.begin() + q.tile_off + x);
+            c->tasks[q.task_off + p] = int2{x, t.y};
+            x += t.y;
+        }
+    } else {
+        std::vector<FkTile> tl(c->tiles.begin() + q.tile_off, c->tiles.begin() + q.tile_off + nitem);
+        for (int64_t p = 0; p < nitem; ++p) c->tiles[q.tile_off + p] = tl[order[p]];
+    }
+}
+
 int validate_lists(fk_ctx *c)
 {
     const int npair = (int)c->pr_sa.size();
@@ -1181,6 +1284,7 @@ int fk_build_quartets(fk_ctx *c, const fk_screen_opts *o)
                     return fail(c, FK_ERR_STATE, "internal: more class launches than FK_MAX_QCLASS");
                 c->qclasses.push_back(q);
             }
+            order_for_xcds(c, c->qclasses.back());
         }
     if ((rc = validate_lists(c))) return rc;
     if (dev) {
