@@ -608,3 +608,29 @@ def test_screen_option_validation():
     o = fk.ScreenOpts(1e-10, 0.0, 1, 0, 0.0, 0.0, 1)
     assert fk._lib.fk_build_quartets(c._ctx, fk.ctypes.byref(o)) == fk.FK_ERR_ARG
     c.build_quartets(tau=1e-10, tau_k=5e-6)
+
+
+def test_xcd_region_order_keeps_the_lists_valid():
+    """A molecule whose density exceeds one XCD's L2 ((H2O)32, 800 functions)
+    gets its lane classes' tiles, and block tasks with their tiles, placed by
+    XCD region.  The lists stay a valid partition (fk_build_quartets checks
+    tiles, tasks and LDS row columns itself), both builds hold the same
+    Schwarz quartets per class, and every address the kernels would form lies
+    inside its buffer (the host index walk), with block tasks off and on for
+    every class that has them."""
+    from synth import geometry as geom
+    s = wl.make_system(geom.water_sphere(32, wl.SEED + 3), "ccpvdz-type")
+    assert s["nbf"] > 724
+    wide = {(1, 0, 1, 0), (1, 1, 0, 0), (1, 1, 1, 0), (2, 0, 0, 0), (2, 0, 1, 0), (2, 1, 0, 0), (2, 1, 1, 0)}
+    off = fk.FockJK(device=-1).set_system(s)
+    off.build_quartets(tau=1e-10, tau_prim=1e-12, block_tasks=False)
+    off.check_indices()
+    on = fk.FockJK(device=-1).set_system(s)
+    for w in wide:
+        on.set_class_block_tasks(*w, True)
+    on.build_quartets(tau=1e-10, tau_prim=1e-12)
+    on.check_indices()
+    a, b = on.stats()["classes"], off.stats()["classes"]
+    assert any(x["block_tasks"] > 0 for x in a)
+    for x, y in zip(a, b):
+        assert x["class"] == y["class"] and x["quartets"] == y["quartets"]
