@@ -37,6 +37,10 @@ constexpr int ncart(int l) { return (l + 1) * (l + 2) / 2; }
 constexpr int kKrowLdsMax = 65536;
 // and with workgroups of eight waves (one workgroup per CU)
 constexpr int kKrowLdsMaxWide = 160 * 1024;
+// streams besides the caller's for the class launches of fk_build_jk
+// (measured: three streams in all gave C20H42 7.83 ms per build against 9.06 on
+// one, (H2O)64 238.6 against 244.2; four were slower on (H2O)64)
+constexpr int kAuxStreams = 2;
 inline int pair_class(int la, int lb) { return la * (la + 1) / 2 + lb; }
 // Hermite functions of total order up to L
 inline int nherm_host(int L) { return (L + 1) * (L + 2) * (L + 3) / 6; }
@@ -154,6 +158,12 @@ struct fk_ctx {
     bool stats_pending = false;
     bool timed = false;
     std::vector<hipEvent_t> ev;  // 2 per quartet class
+    // more streams for the class launches of fk_build_jk, with the events
+    // that fork them from and join them to the caller's stream (created with
+    // the lists, outside any stream capture)
+    std::vector<hipStream_t> aux;
+    hipEvent_t ev_fork = nullptr;
+    std::vector<hipEvent_t> ev_join;
     // per quartet class schedule (key P * NPC + Q), from fk_set_class_schedule or fk_autotune
     // bt: block tasks 1 on, 0 off, -1 the class's default (on for the ket-outer
     // classes, off for the others); alt: a lane class runs its team-per-quartet kernel
@@ -802,6 +812,9 @@ void fk_destroy(fk_ctx *c)
         hipSetDevice(c->device);
         free_device(c);
         for (auto e : c->ev) (void)hipEventDestroy(e);
+        if (c->ev_fork) (void)hipEventDestroy(c->ev_fork);
+        for (auto e : c->ev_join) (void)hipEventDestroy(e);
+        for (auto x : c->aux) (void)hipStreamDestroy(x);
     }
     delete c;
 }
@@ -1288,6 +1301,15 @@ int fk_build_quartets(fk_ctx *c, const fk_screen_opts *o)
         }
     if ((rc = validate_lists(c))) return rc;
     if (dev) {
+        if (!c->ev_fork) HIPCHK(c, hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming));
+        while ((int)c->aux.size() < kAuxStreams) {
+            hipStream_t x;
+            hipEvent_t e;
+            HIPCHK(c, hipStreamCreateWithFlags(&x, hipStreamNonBlocking));
+            c->aux.push_back(x);
+            HIPCHK(c, hipEventCreateWithFlags(&e, hipEventDisableTiming));
+            c->ev_join.push_back(e);
+        }
         if ((rc = dev_upload(c, c->d_pr_G, c->pr_G.data(), c->pr_G.size()))) return rc;
         if ((rc = dev_upload(c, c->d_ket, c->ket_list_all.data(), c->ket_list_all.size()))) return rc;
         if ((rc = dev_upload(c, c->d_lst_sa, c->lst_sa_loc.data(), c->lst_sa_loc.size()))) return rc;
@@ -1544,7 +1566,12 @@ int jeng_build(fk_ctx *c, const JKBufs &b, hipStream_t st)
     return FK_OK;
 }
 
-int build_jk_impl(fk_ctx *c, const double *D, double *J, double *K, unsigned flags, void *stream, const JKBufs &b)
+// multi: the class launches may be spread over the caller's stream and the
+// context's other streams (never for the entry point without allocation,
+// never while the caller's stream is being captured, never with per-class
+// timing).
+int build_jk_impl(fk_ctx *c, const double *D, double *J, double *K, unsigned flags, void *stream, const JKBufs &b,
+                  bool multi)
 {
     if ((flags & FK_J_ONLY) && (flags & FK_K_ONLY))
         return fail(c, FK_ERR_ARG, "fk_build_jk: FK_J_ONLY and FK_K_ONLY together");
@@ -1591,6 +1618,36 @@ int build_jk_impl(fk_ctx *c, const double *D, double *J, double *K, unsigned fla
         }
     // with the J engine the Rys kernels form K only (or nothing)
     const int want_rys = jeng ? (want & FK_WANT_K) : want;
+    // Several streams: the classes, largest estimated work first, each go to
+    // the stream with the least work so far, so that the long, latency-bound
+    // launches of the small high-L classes run beside the large ones instead
+    // of leaving most of the GPU idle.  The classes only add into X with
+    // atomics; the other streams fork from and join the caller's.
+    std::vector<hipStream_t> cls_st(c->qclasses.size(), st);
+    int nfork = 0;
+    const int nst = 1 + (int)c->aux.size();
+    if (multi && nst > 1 && !c->timed && want_rys && c->qclasses.size() > 1) {
+        hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+        HIPCHK(c, hipStreamIsCapturing(st, &cs));
+        if (cs == hipStreamCaptureStatusNone) {
+            std::vector<size_t> ord(c->qclasses.size());
+            std::iota(ord.begin(), ord.end(), 0);
+            auto work = [&](size_t i) {
+                const QuartetClass &q = c->qclasses[i];
+                return (double)q.prim_slots * q.flops_prim() + (double)q.nquartet * q.flops_quartet();
+            };
+            std::stable_sort(ord.begin(), ord.end(), [&](size_t x, size_t y) { return work(x) > work(y); });
+            std::vector<double> wsum(nst, 0.0);
+            for (size_t i : ord) {
+                const int k = (int)(std::min_element(wsum.begin(), wsum.end()) - wsum.begin());
+                cls_st[i] = k == 0 ? st : c->aux[k - 1];
+                wsum[k] += work(i);
+            }
+            HIPCHK(c, hipEventRecord(c->ev_fork, st));
+            for (int k = 1; k < nst; ++k) HIPCHK(c, hipStreamWaitEvent(c->aux[k - 1], c->ev_fork, 0));
+            nfork = nst - 1;
+        }
+    }
     if (jeng && (want_rys & FK_WANT_K) && c->opts.tau_k > 0 &&
         fk_kernels_launch_dfit(Dd, c->nbf, c->d_bf_atom.p, c->d_atom_xyz.p, c->dfit_dr, c->d_dfit_bins.p, c->d_dfit.p, st))
         return fail(c, FK_ERR_HIP, "density-bound kernel launch failed");
@@ -1672,11 +1729,15 @@ int build_jk_impl(fk_ctx *c, const double *D, double *J, double *K, unsigned fla
         const int64_t wgs = qc.ntask > 0 ? qc.ntask : (qc.ntile + 3) / 4;
         const int64_t cap = std::max<int64_t>(1, (int64_t)(qc.grid_frac * std::max(8, qc.blocks_per_cu) * std::max(c->ncu, 1)));
         const int grid = (int)std::max<int64_t>(1, std::min(wgs, cap));
-        if (fk_kernels_launch_jk(qc.P, qc.Q, &a, grid, st))
+        if (fk_kernels_launch_jk(qc.P, qc.Q, &a, grid, cls_st[i]))
             return fail(c, FK_ERR_HIP, "J/K kernel launch failed for class (%d|%d)", qc.P, qc.Q);
         if (c->timed) HIPCHK(c, hipEventRecord(c->ev[2 * i + 1], st));
     }
     if (jeng && (rcj = jeng_build(c, b, st))) return rcj;
+    for (int k = 0; k < nfork; ++k) {
+        HIPCHK(c, hipEventRecord(c->ev_join[k], c->aux[k]));
+        HIPCHK(c, hipStreamWaitEvent(st, c->ev_join[k], 0));
+    }
     if (fk_kernels_launch_finalize(b.X, b.X + nn, b.xcopy, b.ncopy, c->d_bf_scale.p, &ma, Jd, Kd, st))
         return fail(c, FK_ERR_HIP, "finalize kernel launch failed");
     c->stats_pending = true;
@@ -1726,7 +1787,7 @@ int fk_build_jk(fk_ctx *c, const double *D, double *J, double *K, unsigned flags
     if (!c->have_quartets) return fail(c, FK_ERR_STATE, "fk_build_jk: call fk_build_quartets first");
     const size_t nn = (size_t)c->mol_base[c->nmol];
     const JKBufs b{c->d_Ds.p, c->d_Dsh.p, c->d_X.p, (long long)(2 * nn), FK_XCD_COPIES, c->d_cnt.p};
-    return build_jk_impl(c, D, J, K, flags, stream, b);
+    return build_jk_impl(c, D, J, K, flags, stream, b, true);
 }
 
 int fk_build_jk_noalloc(fk_ctx *c, const double *D, double *J, double *K, unsigned flags, void *stream)
@@ -1745,7 +1806,7 @@ int fk_build_jk_noalloc(fk_ctx *c, const double *D, double *J, double *K, unsign
     double *base = c->scratch;
     const JKBufs b{base, base + 3 * (size_t)FK_NOALLOC_MAX_NMAT, base + FK_NOALLOC_MAX_NMAT, 0, 1,
                    (unsigned long long *)(base + 3 * (size_t)FK_NOALLOC_MAX_NMAT + FK_NOALLOC_MAX_NSHMAT)};
-    return build_jk_impl(c, D, J, K, flags, stream, b);
+    return build_jk_impl(c, D, J, K, flags, stream, b, false);
 }
 
 int fk_stats(fk_ctx *c, fk_stats_t *s)

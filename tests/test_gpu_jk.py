@@ -681,3 +681,30 @@ def test_j_engine_refuses_f_shells_and_batches(fk, torch):
     with pytest.raises(fk.FockJKError) as e:
         c.build_jk(Dd, only="J", j_engine=True)
     assert e.value.code == fk.FK_ERR_UNSUPPORTED
+
+
+def test_class_streams_join_the_callers_stream(fk, torch, c2):
+    """fk_build_jk spreads the class kernels over the context's streams and
+    joins them to the caller's stream: builds issued back to back on a side
+    stream, with the density rescaled on that stream between them and the
+    results copied on it with no synchronisation in between, equal the
+    single-stream build (FK_TIME_CLASSES) of the same densities; the second
+    build sees the rescaled density (J and K scale with it: Schwarz screening
+    only, so the quartets do not depend on the density)."""
+    s, D = c2
+    c = fk.FockJK(0).set_system(s).build_quartets(tau=1e-10, tau_prim=1e-12, density_screen=False)
+    Dd = torch.tensor(D, device="cuda:0")
+    J0, K0 = c.build_jk(Dd.clone(), time_classes=True, sync=True)
+    J0, K0 = J0.cpu().numpy(), K0.cpu().numpy()
+    side = torch.cuda.Stream()
+    with torch.cuda.stream(side):
+        Dx = Dd.clone()
+        J1, K1 = c.build_jk(Dx, stream=side)
+        J1c, K1c = J1.clone(), K1.clone()
+        Dx.mul_(0.5)
+        J2, K2 = c.build_jk(Dx, stream=side)
+        J2c, K2c = J2.clone(), K2.clone()
+    side.synchronize()
+    scale = max(1.0, float(np.abs(J0).max()), float(np.abs(K0).max()))
+    for a, b in ((J1c, J0), (K1c, K0), (J2c, 0.5 * J0), (K2c, 0.5 * K0)):
+        assert np.max(np.abs(a.cpu().numpy() - b)) <= 1e-12 * scale
