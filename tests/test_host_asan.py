@@ -5,8 +5,9 @@ lists, groups, bra blocks, tiles, block tasks and their LDS row columns.  This
 test builds fk_host.cpp with AddressSanitizer on the host side only (the GPU
 code is not instrumented), links it with the library's kernel objects from
 the last build, and in a separate process -- the sanitizer runtime preloaded,
-PyTorch kept out -- builds the lists of C20H42, an s-f system and a batch of
-three molecules under four schedules (defaults, block tasks for every lane
+PyTorch kept out -- builds the lists of C20H42, an s-f system, a batch of
+three molecules and (H2O)32 (800 functions: large enough for the XCD-region
+order of the work items) under four schedules (defaults, block tasks for every lane
 class that can take them, the team alternatives of the lane classes, no
 block tasks), checks every kernel address with fk_check_indices, and
 requires the process to end cleanly.  Contexts without a device, so no GPU
@@ -31,12 +32,14 @@ sys.path.insert(1, sys.argv[2])
 sys.path.insert(2, sys.argv[3])
 import paper_2407_21445_amd as fk
 from synth import workloads as wl
+from synth import geometry as geom
 from test_oracle import _rand_sys
 wide = [(1, 0, 1, 0), (1, 1, 0, 0), (1, 1, 1, 0), (2, 0, 0, 0), (2, 0, 1, 0), (2, 1, 0, 0), (2, 1, 1, 0)]
 alts = [((1, 1, 1, 0), 3), ((2, 0, 1, 0), 6), ((2, 1, 0, 0), 6), ((3, 0, 1, 0), 10), ((3, 1, 0, 0), 10)]
 spdf = _rand_sys(41, lmax=3, natom=4, kmax=2)
 systems = (("c20h42", wl.c20h42_631gs()), ("spdf", spdf),
-           ("batch", wl.batch([wl.water4_sto3g(), wl.alkane_sys(2, "6-31gs-type"), spdf])))
+           ("batch", wl.batch([wl.water4_sto3g(), wl.alkane_sys(2, "6-31gs-type"), spdf])),
+           ("water32", wl.make_system(geom.water_sphere(32, wl.SEED + 3), "ccpvdz-type")))
 for name, s in systems:
     for variant in ("default", "wide", "lanes", "off"):
         c = fk.FockJK(device=-1).set_system(s)
@@ -93,3 +96,4 @@ def test_host_tables_under_address_sanitizer(tmp_path):
     lines = [l.split() for l in r.stdout.splitlines() if len(l.split()) == 3]
     got = {(a, b): int(n) for a, b, n in lines}
     assert got[("c20h42", "wide")] > got[("c20h42", "default")] > got[("c20h42", "off")] == 0
+    assert got[("water32", "wide")] > got[("water32", "default")] > got[("water32", "off")] == 0
