@@ -178,14 +178,15 @@ MODEL = os.path.join(os.path.dirname(HERE), "paper_2407_21445_amd", "guess_631gs
 
 @pytest.mark.skipif(not os.path.exists(MODEL), reason="no trained guess weights in the package")
 def test_trained_guess_beats_sad_on_held_out(fk):
-    """Held-out geometries of the guess set (never trained on): the learned
-    guess needs fewer SCF iterations than SAD on average and never changes
-    the converged energy by more than 1e-8 Eh."""
+    """The first 24 held-out geometries of the guess set (never trained on;
+    alkanes and water clusters, 80-532 functions): the learned guess needs
+    no more SCF iterations than SAD on any of them, fewer on average, and
+    never changes the converged energy by more than 1e-8 Eh."""
     from paper_2407_21445_amd import guess_train as gt
     Ws, bs = gt.load_model(MODEL)
     first = wl.GUESS_SET_SIZE - wl.GUESS_HELD_OUT
     its_sad, its_nn = [], []
-    for i in range(first, first + 6):
+    for i in range(first, first + 24):
         s = wl.guess_system(i)
         c = fk.FockJK(0).set_system(s).build_quartets(tau=1e-10)
         c.set_guess_model(Ws, bs)
@@ -195,4 +196,5 @@ def test_trained_guess_beats_sad_on_held_out(fk):
         assert abs(r1["energy"] - r0["energy"]) <= 1e-8
         its_sad.append(r0["iterations"])
         its_nn.append(r1["iterations"])
+    assert all(x <= y for x, y in zip(its_nn, its_sad)), (its_sad, its_nn)
     assert np.mean(its_nn) < np.mean(its_sad), (its_sad, its_nn)
