@@ -12,6 +12,10 @@
 //     with Gershgorin bounds, then X <- X^2 or X <- 2X - X^2, whichever moves
 //     the trace towards N_occ, until X is idempotent;
 //   * the DIIS error is the commutator F'D' - D'F' in the orthonormal basis.
+// The products are rocBLAS dgemm calls from n = 256 on (the LDS-tiled kernel
+// below for smaller n and under graph capture).  The density can also come
+// from the eigenvectors of F' (rocSOLVER), for bases where purification
+// leaves too much occupied-virtual mixing.
 // For nearly linearly dependent bases the orthogonaliser can instead be the
 // canonical one: S = U s U^T once per geometry (rocSOLVER), X = U f(s) U^T
 // with f(s) = s^(-1/2) above a cutoff and 0 below it (eigenvectors dropped).
@@ -21,10 +25,16 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <mutex>
 
 #include "fk_internal.h"
 
 namespace {
+
+// rocBLAS handles of fk_scf_gemm, one per device
+constexpr int kBlasDevices = 64;
+rocblas_handle g_blas[kBlasDevices] = {};
+std::mutex g_blas_mutex;
 
 constexpr int GT = 64;   // output tile (GT x GT) per workgroup
 constexpr int GK = 16;   // k-slab staged in LDS
@@ -208,9 +218,27 @@ int ok() { return hipGetLastError() == hipSuccess ? 0 : -3; }
 
 extern "C" {
 
+// C = alpha A B + beta C (row-major, n x n).  From n = 256 on, rocBLAS dgemm
+// on the stream (in column-major terms C^T = B^T A^T), with one handle per
+// device created on first use and kept for the life of the process; the
+// kernel above for smaller n, and while the stream is being captured into a
+// graph (the library call may allocate).
 int fk_scf_gemm(const double *A, const double *B, double *C, int n, double alpha, double beta, void *stream)
 {
     if (n <= 0) return 0;
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing((hipStream_t)stream, &cs) != hipSuccess) cs = hipStreamCaptureStatusActive;
+    int dev = -1;
+    if (n >= 256 && cs == hipStreamCaptureStatusNone && hipGetDevice(&dev) == hipSuccess && dev >= 0 &&
+        dev < kBlasDevices) {
+        std::lock_guard<std::mutex> lock(g_blas_mutex);
+        if (!g_blas[dev] && rocblas_create_handle(&g_blas[dev]) != rocblas_status_success) g_blas[dev] = nullptr;
+        rocblas_handle h = g_blas[dev];
+        if (h && rocblas_set_stream(h, (hipStream_t)stream) == rocblas_status_success &&
+            rocblas_dgemm(h, rocblas_operation_none, rocblas_operation_none, n, n, n, &alpha, B, n, A, n, &beta, C,
+                          n) == rocblas_status_success)
+            return 0;
+    }
     const dim3 grid((n + GT - 1) / GT, (n + GT - 1) / GT);
     hipLaunchKernelGGL(k_gemm, grid, dim3(256), 0, (hipStream_t)stream, A, B, C, n, alpha, beta);
     return ok();
