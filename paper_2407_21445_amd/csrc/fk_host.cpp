@@ -158,9 +158,10 @@ struct fk_ctx {
     bool stats_pending = false;
     bool timed = false;
     std::vector<hipEvent_t> ev;  // 2 per quartet class
-    // more streams for the class launches of fk_build_jk, with the events
-    // that fork them from and join them to the caller's stream (created with
-    // the lists, outside any stream capture)
+    // more streams for the class launches of fk_build_jk (the device's, shared
+    // by its contexts), with this context's events that fork them from and
+    // join them to the caller's stream (set up with the lists, outside any
+    // stream capture)
     std::vector<hipStream_t> aux;
     hipEvent_t ev_fork = nullptr;
     std::vector<hipEvent_t> ev_join;
@@ -740,6 +741,29 @@ constexpr int kMaxDevices = 64;
 double *g_scratch[kMaxDevices] = {};
 std::mutex g_scratch_mutex;
 
+// The class-launch streams of fk_build_jk, per device: created once, on the
+// device's first list build, and shared by every context on it for the life
+// of the process (a few streams, not a few per context: the hardware queues
+// they map to are few, and streams of one build that share a queue
+// serialise).
+std::vector<hipStream_t> g_aux[kMaxDevices];
+std::mutex g_aux_mutex;
+
+int aux_streams(fk_ctx *c, std::vector<hipStream_t> &out)
+{
+    if (c->device >= kMaxDevices) return fail(c, FK_ERR_UNSUPPORTED, "device ordinal %d too large", c->device);
+    std::lock_guard<std::mutex> lock(g_aux_mutex);
+    std::vector<hipStream_t> &v = g_aux[c->device];
+    while ((int)v.size() < kAuxStreams) {
+        hipStream_t x;
+        const hipError_t e = hipStreamCreateWithFlags(&x, hipStreamNonBlocking);
+        if (e != hipSuccess) return fail(c, FK_ERR_HIP, "stream creation failed (%s)", hipGetErrorString(e));
+        v.push_back(x);
+    }
+    out = v;
+    return FK_OK;
+}
+
 // device address of the calling thread's current device's copy of `scratch`
 int scratch_address(fk_ctx *c)
 {
@@ -813,8 +837,7 @@ void fk_destroy(fk_ctx *c)
         free_device(c);
         for (auto e : c->ev) (void)hipEventDestroy(e);
         if (c->ev_fork) (void)hipEventDestroy(c->ev_fork);
-        for (auto e : c->ev_join) (void)hipEventDestroy(e);
-        for (auto x : c->aux) (void)hipStreamDestroy(x);
+        for (auto e : c->ev_join) (void)hipEventDestroy(e);  // the streams are the device's, kept
     }
     delete c;
 }
@@ -1302,13 +1325,13 @@ int fk_build_quartets(fk_ctx *c, const fk_screen_opts *o)
     if ((rc = validate_lists(c))) return rc;
     if (dev) {
         if (!c->ev_fork) HIPCHK(c, hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming));
-        while ((int)c->aux.size() < kAuxStreams) {
-            hipStream_t x;
-            hipEvent_t e;
-            HIPCHK(c, hipStreamCreateWithFlags(&x, hipStreamNonBlocking));
-            c->aux.push_back(x);
-            HIPCHK(c, hipEventCreateWithFlags(&e, hipEventDisableTiming));
-            c->ev_join.push_back(e);
+        if (c->aux.empty()) {
+            if ((rc = aux_streams(c, c->aux))) return rc;
+            for (size_t k = 0; k < c->aux.size(); ++k) {
+                hipEvent_t e;
+                HIPCHK(c, hipEventCreateWithFlags(&e, hipEventDisableTiming));
+                c->ev_join.push_back(e);
+            }
         }
         if ((rc = dev_upload(c, c->d_pr_G, c->pr_G.data(), c->pr_G.size()))) return rc;
         if ((rc = dev_upload(c, c->d_ket, c->ket_list_all.data(), c->ket_list_all.size()))) return rc;
