@@ -221,9 +221,10 @@ int fk_info(const fk_ctx *ctx, fk_info_t *info);
  * when G_ab G_cd times the largest |D| over only the blocks that matrix
  * multiplies falls below tau.  Asymmetric D gives J, K of its symmetric part only when
  * density screening is off; callers pass symmetric D.  The call is ordered on
- * `stream`: the class kernels may run on two more streams of the context,
- * which wait for `stream` before the first of them and which `stream` waits
- * for before the final reduction (not while `stream` is being captured into a
+ * `stream`: the class kernels may run on two more streams (the library's,
+ * one pair per device, shared by its contexts), which wait for `stream`
+ * before the first of them and which `stream` waits for before the final
+ * reduction (not while `stream` is being captured into a
  * graph, and not with FK_TIME_CLASSES: then every launch is on `stream`). */
 int fk_build_jk(fk_ctx *ctx, const double *D, double *J, double *K, unsigned flags, void *stream);
 
