@@ -1590,7 +1590,7 @@ int jeng_build(fk_ctx *c, const JKBufs &b, hipStream_t st)
 }
 
 // multi: the class launches may be spread over the caller's stream and the
-// context's other streams (never for the entry point without allocation,
+// device's class-launch streams (never for the entry point without allocation,
 // never while the caller's stream is being captured, never with per-class
 // timing).
 int build_jk_impl(fk_ctx *c, const double *D, double *J, double *K, unsigned flags, void *stream, const JKBufs &b,

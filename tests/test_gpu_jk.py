@@ -684,7 +684,7 @@ def test_j_engine_refuses_f_shells_and_batches(fk, torch):
 
 
 def test_class_streams_join_the_callers_stream(fk, torch, c2):
-    """fk_build_jk spreads the class kernels over the context's streams and
+    """fk_build_jk spreads the class kernels over the device's class-launch streams and
     joins them to the caller's stream: builds issued back to back on a side
     stream, with the density rescaled on that stream between them and the
     results copied on it with no synchronisation in between, equal the
