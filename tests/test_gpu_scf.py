@@ -172,6 +172,23 @@ def test_scf_with_graph_replay(fk, name):
     assert abs(r1["energy"] - r0["energy"]) <= 1e-10 and abs(r2["energy"] - r0["energy"]) <= 1e-9
 
 
+def test_scf_graph_replay_with_library_products(fk):
+    """C20H42 (384 functions): eager iterations form the dense products with
+    rocBLAS, the graph-captured Fock stage with the library's own GEMM kernel;
+    both runs, and the eigensolver-density run, reach the oracle's stored
+    energy (1e-8 Eh) in the same number of iterations (within one)."""
+    with open(os.path.join(HERE, "golden", "c20h42_631gs_scf.json")) as f:
+        gold = json.load(f)
+    c = fk.FockJK(0).set_system(wl.c20h42_631gs()).build_quartets(tau=0.0)
+    r0 = c.run_scf()
+    r1 = c.run_scf(graph=True)
+    r2 = c.run_scf(graph=True, density_eig=True)
+    for r in (r0, r1, r2):
+        assert r["converged"]
+        assert abs(r["energy"] - gold["E_total"]) <= 1e-8, (r["energy"], gold["E_total"])
+    assert abs(r1["iterations"] - r0["iterations"]) <= 1 and abs(r2["iterations"] - r0["iterations"]) <= 1
+
+
 @pytest.mark.parametrize("name", ["water4_sto3g", "c2h6_631gs"])
 def test_scf_incremental_builds(fk, name):
     """J and K from density changes (full build every 8 iterations) converge
