@@ -243,9 +243,10 @@ int fk_build_jk(fk_ctx *ctx, const double *D, double *J, double *K, unsigned fla
  * lists the context allocates) are FK_ERR_ARG.  The array
  * is shared by every context on a GPU and keeps the last call's contents (the
  * call clears what must start at zero): calls that overlap on one GPU, on any
- * streams, race and must be ordered by the caller.  Results equal
- * fk_build_jk's up to the order of the accumulation; fk_stats reports this
- * call when it was the last build. */
+ * streams, race and must be ordered by the caller.  Every launch is on
+ * `stream` (the library's class-launch streams of fk_build_jk are not used).
+ * Results equal fk_build_jk's up to the order of the accumulation; fk_stats
+ * reports this call when it was the last build. */
 #define FK_NOALLOC_MAX_NMAT (1 << 21)
 #define FK_NOALLOC_MAX_NSHMAT (1 << 18)
 int fk_build_jk_noalloc(fk_ctx *ctx, const double *D, double *J, double *K, unsigned flags, void *stream);
