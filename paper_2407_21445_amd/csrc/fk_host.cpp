@@ -1641,6 +1641,10 @@ int build_jk_impl(fk_ctx *c, const double *D, double *J, double *K, unsigned fla
         }
     // with the J engine the Rys kernels form K only (or nothing)
     const int want_rys = jeng ? (want & FK_WANT_K) : want;
+    // the density-bound fit the K classes read, before the other streams fork
+    if (jeng && (want_rys & FK_WANT_K) && c->opts.tau_k > 0 &&
+        fk_kernels_launch_dfit(Dd, c->nbf, c->d_bf_atom.p, c->d_atom_xyz.p, c->dfit_dr, c->d_dfit_bins.p, c->d_dfit.p, st))
+        return fail(c, FK_ERR_HIP, "density-bound kernel launch failed");
     // Several streams: the classes, largest estimated work first, each go to
     // the stream with the least work so far, so that the long, latency-bound
     // launches of the small high-L classes run beside the large ones instead
@@ -1671,9 +1675,6 @@ int build_jk_impl(fk_ctx *c, const double *D, double *J, double *K, unsigned fla
             nfork = nst - 1;
         }
     }
-    if (jeng && (want_rys & FK_WANT_K) && c->opts.tau_k > 0 &&
-        fk_kernels_launch_dfit(Dd, c->nbf, c->d_bf_atom.p, c->d_atom_xyz.p, c->dfit_dr, c->d_dfit_bins.p, c->d_dfit.p, st))
-        return fail(c, FK_ERR_HIP, "density-bound kernel launch failed");
     for (size_t i = 0; i < c->qclasses.size(); ++i) {
         const QuartetClass &qc = c->qclasses[i];
         if (c->timed) HIPCHK(c, hipEventRecord(c->ev[2 * i], st));

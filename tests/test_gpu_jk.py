@@ -708,3 +708,25 @@ def test_class_streams_join_the_callers_stream(fk, torch, c2):
     scale = max(1.0, float(np.abs(J0).max()), float(np.abs(K0).max()))
     for a, b in ((J1c, J0), (K1c, K0), (J2c, 0.5 * J0), (K2c, 0.5 * K0)):
         assert np.max(np.abs(a.cpu().numpy() - b)) <= 1e-12 * scale
+
+
+def test_split_build_reads_its_own_density_bound(fk, torch, c2):
+    """Split builds (J engine, K by the Rys kernels with the fitted-bound
+    K-block skip at tau_k = 5e-6) issued back to back on one stream, the first
+    on the density scaled by 1e-3, the second on the density itself: the
+    second K equals that of a split build of the density alone (the same skip
+    decisions; only the order of the atomics differs).  The K kernels run on
+    several streams and must read the bound fitted to their own density, which
+    a K-block skip with the smaller density's bound would not give."""
+    s, D = c2
+    Dd = torch.tensor(D, device="cuda:0")
+    ca = fk.FockJK(0).set_system(s).build_quartets(tau=1e-10, tau_prim=1e-12, tau_k=5e-6)
+    Ja, Ka = ca.build_jk(Dd.clone(), j_engine=True, sync=True)
+    cb = fk.FockJK(0).set_system(s).build_quartets(tau=1e-10, tau_prim=1e-12, tau_k=5e-6)
+    cb.build_jk((Dd * 1e-3).contiguous(), j_engine=True)
+    Jb, Kb = cb.build_jk(Dd.clone(), j_engine=True)
+    torch.cuda.synchronize()
+    Ka, Kb, Ja, Jb = (x.cpu().numpy() for x in (Ka, Kb, Ja, Jb))
+    scale = max(1.0, float(np.abs(Ka).max()))
+    assert np.max(np.abs(Kb - Ka)) <= 1e-11 * scale
+    assert np.max(np.abs(Jb - Ja)) <= 1e-11 * max(1.0, float(np.abs(Ja).max()))
