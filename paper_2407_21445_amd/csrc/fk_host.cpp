@@ -1659,10 +1659,20 @@ int build_jk_impl(fk_ctx *c, const double *D, double *J, double *K, unsigned fla
         if (cs == hipStreamCaptureStatusNone) {
             std::vector<size_t> ord(c->qclasses.size());
             std::iota(ord.begin(), ord.end(), 0);
-            auto work = [&](size_t i) {
+            // estimated work per launch; an FP32 twin (its counts belong to the
+            // FP64 entry) walks the same tiles and is given its twin's estimate
+            std::vector<double> wk(c->qclasses.size(), 0.0);
+            for (size_t i = 0; i < wk.size(); ++i) {
                 const QuartetClass &q = c->qclasses[i];
-                return (double)q.prim_slots * q.flops_prim() + (double)q.nquartet * q.flops_quartet();
-            };
+                wk[i] = (double)q.prim_slots * q.flops_prim() + (double)q.nquartet * q.flops_quartet();
+            }
+            for (size_t i = 0; i < wk.size(); ++i)
+                if (c->qclasses[i].prec != 0)
+                    for (size_t j = 0; j < wk.size(); ++j)
+                        if (c->qclasses[j].P == c->qclasses[i].P && c->qclasses[j].Q == c->qclasses[i].Q &&
+                            c->qclasses[j].prec == 0)
+                            wk[i] = wk[j];
+            auto work = [&](size_t i) { return wk[i]; };
             std::stable_sort(ord.begin(), ord.end(), [&](size_t x, size_t y) { return work(x) > work(y); });
             std::vector<double> wsum(nst, 0.0);
             for (size_t i : ord) {
